@@ -1,0 +1,344 @@
+"""Pins of the FP64 oracle against facts other than itself.
+
+Each test checks the oracle against something it does not compute the same
+way: a library FFT (the on-grid special case of Eq. 3), closed forms
+(geometric-series energy, the z = 0 Dirichlet kernel, the paraxial limit of
+Eq. 2), invariants (integer shifts, the band condition of Eq. 4, adjoint dot
+products), brute force (direct spatial convolution with the Fresnel impulse
+response of Eq. 5), 50-digit arithmetic, and an independent physical model
+(Rayleigh-Sommerfeld direct integration, Eq. 10).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+
+def _geo(**kw):
+    base = dict(N=16, g=4e-6, lam=633e-9, z=0.01, ox=0.0, oy=0.0, tf="asm", band="full")
+    base.update(kw)
+    return O.Geometry(**base)
+
+
+def _dirichlet(d, Np):
+    """sum_{k=-Np/2}^{Np/2-1} exp(-2 pi i k d / Np), closed form of the
+    geometric series (d in pixels, any real)."""
+    d = np.asarray(d, dtype=np.float64)
+    out = np.empty(d.shape, dtype=np.complex128)
+    near = np.abs(np.sin(np.pi * d / Np)) < 1e-300
+    dn = d[~near]
+    out[~near] = np.exp(1j * np.pi * dn / Np) * np.sin(np.pi * dn) / np.sin(np.pi * dn / Np)
+    out[near] = Np * np.cos(np.pi * d[near])  # d = multiple of Np
+    return out
+
+
+# ----------------------------------------------------------- transfer funcs
+@pytest.mark.parametrize("z", [0.01, 0.5, 1.0])
+def test_asm_transfer_matches_50_digit_arithmetic(z):
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 50
+    geo = _geo(N=1024, g=4e-6, lam=532e-9, z=z, ox=1e-3, oy=-2e-4)
+    H = O.transfer_asm(geo)
+    rng = np.random.default_rng(7)
+    idx = rng.integers(0, geo.Np, size=(300, 2))
+    K = O.freq_index(geo.Np)
+    err = 0.0
+    for a, b in idx:
+        kx, ky = K[b], K[a]
+        fx = mp.mpf(int(kx)) / (geo.Np * mp.mpf(geo.g))
+        fy = mp.mpf(int(ky)) / (geo.Np * mp.mpf(geo.g))
+        ph = 2 * mp.pi * (fx * mp.mpf(geo.ox) + fy * mp.mpf(geo.oy)
+                          + mp.mpf(z) * mp.sqrt(1 / mp.mpf(geo.lam) ** 2 - fx * fx - fy * fy))
+        ref = complex(mp.cos(ph), mp.sin(ph))
+        err = max(err, abs(H[a, b] - ref))
+    # float64 forms z*sqrt(.) ~ z/lambda cycles before reducing them mod 1: a
+    # few roundings of relative size 2^-53 on that many cycles bound the error
+    bound = 2 * np.pi * 16 * 2.0 ** -53 * (abs(z) / geo.lam + 1.0)
+    assert err < bound
+
+
+def test_asm_transfer_paraxial_limit():
+    """Near k = 0, sqrt(1/l^2 - f^2) = 1/l - l f^2/2 - l^3 f^4/8 - ...; the
+    oracle must agree with the paraxial phase up to the quartic remainder."""
+    geo = _geo(N=1024, g=4e-6, lam=633e-9, z=0.3, ox=2e-4, oy=1e-4)
+    H = O.transfer_asm(geo)
+    K = O.freq_index(geo.Np)
+    c = geo.Np // 2
+    for kx in range(-20, 21, 5):
+        for ky in range(-20, 21, 4):
+            fx, fy = kx * geo.df, ky * geo.df
+            f2 = fx * fx + fy * fy
+            par = 2 * np.pi * (fx * geo.ox + fy * geo.oy + geo.z / geo.lam
+                               - geo.lam * geo.z * f2 / 2.0)
+            bound = 2 * np.pi * 1.01 * geo.z * geo.lam ** 3 * f2 * f2 / 8.0 + 1e-9
+            assert K[ky + c] == ky and K[kx + c] == kx
+            assert abs(H[ky + c, kx + c] - np.exp(1j * par)) <= bound
+
+
+@pytest.mark.parametrize("z,ox,oy", [(0.1, 1e-3, 0.0), (0.5, 1e-3, 0.0), (-0.2, 3e-4, -5e-4),
+                                     (0.01, 1e-3, 0.0), (1.0, 0.0, 0.0)])
+def test_band_edges_satisfy_local_frequency_condition(z, ox, oy):
+    """Band of Eq. 4 (reading: |o - z f/s(f)| <= S per axis, S = N g).  The
+    inequality is evaluated directly at the integer bounds and one past them."""
+    geo = _geo(N=1024, g=4e-6, lam=633e-9, z=z, ox=ox, oy=oy, band="limited")
+    S = geo.N * geo.g
+    kmin, kmax = -geo.Np // 2, geo.Np // 2 - 1
+
+    def ok(k, o):
+        f = k * geo.df
+        s = math.sqrt(1.0 / geo.lam ** 2 - f * f)
+        return abs(o - geo.z * f / s) <= S * (1 + 1e-12)
+
+    for (lo, hi), o in zip(O.band_index_bounds(geo), (ox, oy)):
+        assert lo <= hi
+        assert ok(lo, o) and ok(hi, o)
+        if lo > kmin:
+            assert not ok(lo - 1, o)
+        if hi < kmax:
+            assert not ok(hi + 1, o)
+        mid = (lo + hi) // 2
+        assert ok(mid, o)
+
+
+def test_fresnel_separable_equals_direct_2d_dft():
+    geo = _geo(N=8, g=5e-6, lam=500e-9, z=0.002, ox=7e-6, oy=-3e-6, tf="fresnel")
+    H = O.transfer_fresnel(geo)
+    K = O.freq_index(geo.Np)
+    k = 2 * np.pi / geo.lam
+    MX, MY = np.meshgrid(K, K, indexing="xy")
+    h = (geo.g ** 2 * np.exp(1j * k * geo.z) / (1j * geo.lam * geo.z)
+         * np.exp(1j * np.pi * ((MX * geo.g + geo.ox) ** 2 + (MY * geo.g + geo.oy) ** 2)
+                  / (geo.lam * geo.z)))
+    ref = np.zeros_like(H)
+    for a, ky in enumerate(K):
+        for b, kx in enumerate(K):
+            ref[a, b] = np.sum(h * np.exp(-2j * np.pi * (kx * MX + ky * MY) / geo.Np))
+    assert np.max(np.abs(H - ref)) <= 1e-11 * np.max(np.abs(ref))
+
+
+def _fresnel_h(geo, dx, dy):
+    """Fresnel impulse response exp(ikz)/(i l z) exp(i pi |x|^2/(l z)) at (dx, dy)."""
+    k = 2 * np.pi / geo.lam
+    return (np.exp(1j * k * geo.z) / (1j * geo.lam * geo.z)
+            * np.exp(1j * np.pi * (dx * dx + dy * dy) / (geo.lam * geo.z)))
+
+
+def test_nufre2_on_grid_equals_direct_fresnel_convolution():
+    """NU-FRE_2 at destinations on the pixel grid is the linear convolution
+    sum_m u1[m] g^2 h((n - m) g + o) (zero padding to N' = 2N removes the wrap)."""
+    geo = _geo(N=8, g=5e-6, lam=500e-9, z=0.003, ox=6e-6, oy=-4e-6, tf="fresnel")
+    rng = np.random.default_rng(11)
+    u1 = rng.standard_normal((8, 8)) + 1j * rng.standard_normal((8, 8))
+    n = np.arange(-4, 4)
+    NX, NY = np.meshgrid(n, n, indexing="xy")
+    sel = rng.permutation(64)[:40]
+    qx, qy = NX.ravel()[sel], NY.ravel()[sel]
+    got = O.nuasm2(geo, u1, qx * geo.g, qy * geo.g)
+    ref = np.zeros(sel.size, dtype=np.complex128)
+    for j in range(sel.size):
+        for my in range(8):
+            for mx in range(8):
+                dx = (qx[j] - (mx - 4)) * geo.g + geo.ox
+                dy = (qy[j] - (my - 4)) * geo.g + geo.oy
+                ref[j] += u1[my, mx] * geo.g ** 2 * _fresnel_h(geo, dx, dy)
+    # the brute force evaluates exp(i k z) unreduced (k z ~ 4e4 rad), so its own
+    # rounding is ~ 4e4 * 2^-53 per term
+    assert O.rel_l2(got, ref) < 1e-10
+
+
+def test_nufre1_on_grid_equals_direct_fresnel_convolution():
+    geo = _geo(N=8, g=5e-6, lam=500e-9, z=0.004, ox=-5e-6, oy=2e-6, tf="fresnel")
+    rng = np.random.default_rng(12)
+    M = 25
+    mx = rng.integers(-4, 4, size=M)
+    my = rng.integers(-4, 4, size=M)
+    c = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    u2 = O.nuasm1(geo, mx * geo.g, my * geo.g, c)
+    # central N x N of the N' x N' output has no circular wrap
+    ref = np.zeros((8, 8), dtype=np.complex128)
+    for b in range(8):
+        for a in range(8):
+            nx, ny = a - 4, b - 4
+            dx = (nx - mx) * geo.g + geo.ox
+            dy = (ny - my) * geo.g + geo.oy
+            ref[b, a] = np.sum(c * geo.g ** 2 * _fresnel_h(geo, dx, dy))
+    got = u2[4:12, 4:12]
+    assert O.rel_l2(got, ref) < 1e-10
+
+
+# ------------------------------------------- on-grid reduction to Eq. 3
+def _fft_asm_full(H, img):
+    """Eq. 3 with numpy's FFT on a centred N' x N' array."""
+    X = np.fft.fft2(np.fft.ifftshift(img))
+    return np.fft.fftshift(np.fft.ifft2(X * np.fft.ifftshift(H)))
+
+
+@pytest.mark.parametrize("tf,band,z", [("asm", "full", 0.01), ("asm", "limited", 0.02),
+                                       ("fresnel", "full", 0.005)])
+def test_nuasm2_on_grid_equals_fft_asm(tf, band, z):
+    geo = _geo(N=16, g=4e-6, lam=633e-9, z=z, ox=3e-5, oy=-1e-5, tf=tf, band=band)
+    rng = np.random.default_rng(21)
+    u1 = rng.standard_normal((16, 16)) + 1j * rng.standard_normal((16, 16))
+    H = O.transfer(geo)
+    img = np.zeros((geo.Np, geo.Np), dtype=np.complex128)
+    img[8:24, 8:24] = u1
+    ref = _fft_asm_full(H, img)
+    # destinations: a shuffled subset of the N' x N' grid (x != y pattern)
+    nx = rng.integers(-16, 16, size=60)
+    ny = rng.integers(-16, 16, size=60)
+    got = O.nuasm2(geo, u1, nx * geo.g, ny * geo.g, H)
+    assert O.rel_l2(got, ref[ny + 16, nx + 16]) < 1e-13
+
+
+@pytest.mark.parametrize("tf,band,z", [("asm", "full", 0.01), ("asm", "limited", 0.05),
+                                       ("fresnel", "full", 0.01)])
+def test_nuasm1_on_grid_equals_fft_asm(tf, band, z):
+    geo = _geo(N=16, g=4e-6, lam=633e-9, z=z, ox=-2e-5, oy=1e-5, tf=tf, band=band)
+    rng = np.random.default_rng(22)
+    M = 50
+    mx = rng.integers(-8, 8, size=M)
+    my = rng.integers(-8, 8, size=M)
+    c = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    H = O.transfer(geo)
+    img = np.zeros((geo.Np, geo.Np), dtype=np.complex128)
+    np.add.at(img, (my + 16, mx + 16), c)           # duplicate points add
+    ref = _fft_asm_full(H, img)
+    got = O.nuasm1(geo, mx * geo.g, my * geo.g, c, H)
+    assert O.rel_l2(got, ref) < 1e-13
+
+
+# ------------------------------------------------------------ closed forms
+@pytest.mark.parametrize("z,ox", [(0.01, 0.0), (0.3, 2e-4), (-0.05, -1e-4)])
+def test_nuasm1_energy_closed_form(z, ox):
+    """Full band, |H| = 1: sum_n |u2|^2 = N'^-2 sum_{j,l} c_j conj(c_l)
+    D(x_j - x_l) D(y_j - y_l), D the Dirichlet kernel over K."""
+    geo = _geo(N=16, g=4e-6, z=z, ox=ox, oy=1e-5)
+    rng = np.random.default_rng(31)
+    M = 40
+    x, y = synth.uniform_box(rng, M, geo.N * geo.g)
+    c = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    u2 = O.nuasm1(geo, x, y, c)
+    xp, yp = x / geo.g, y / geo.g
+    Dx = _dirichlet(xp[:, None] - xp[None, :], geo.Np)
+    Dy = _dirichlet(yp[:, None] - yp[None, :], geo.Np)
+    ref = np.real(np.sum(c[:, None] * np.conj(c)[None, :] * Dx * Dy)) / geo.Np ** 2
+    assert abs(np.sum(np.abs(u2) ** 2) - ref) <= 1e-12 * ref
+
+
+def test_nuasm1_z0_is_dirichlet_interpolation_at_offset_window():
+    """z = 0, full band: H = exp(2 pi i df k.o) and the output sample n sits at
+    n g + o, so u2[n] = N'^-2 sum_j c_j conj(D)(n + o/g - p_j) per axis."""
+    geo = _geo(N=8, g=4e-6, z=0.0, ox=1.3e-6, oy=-2.9e-6)
+    rng = np.random.default_rng(41)
+    M = 12
+    x, y = synth.uniform_box(rng, M, geo.N * geo.g)
+    c = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    u2 = O.nuasm1(geo, x, y, c)
+    K = O.freq_index(geo.Np)
+    ref = np.zeros_like(u2)
+    for b, ny in enumerate(K):
+        for a, nx in enumerate(K):
+            dx = nx + geo.ox / geo.g - x / geo.g
+            dy = ny + geo.oy / geo.g - y / geo.g
+            ref[b, a] = np.sum(c * np.conj(_dirichlet(dx, geo.Np)) * np.conj(_dirichlet(dy, geo.Np)))
+    ref /= geo.Np ** 2
+    assert O.rel_l2(u2, ref) < 1e-12
+
+
+def test_nuasm1_integer_shift_rolls_output():
+    geo = _geo(N=16, g=4e-6, z=0.02, ox=1e-5, band="limited")
+    rng = np.random.default_rng(51)
+    M = 30
+    x, y = synth.uniform_box(rng, M, 0.5 * geo.N * geo.g)
+    c = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    H = O.transfer(geo)
+    u = O.nuasm1(geo, x, y, c, H)
+    dx, dy = 3, -2
+    v = O.nuasm1(geo, x + dx * geo.g, y + dy * geo.g, c, H)
+    assert O.rel_l2(v, np.roll(u, (dy, dx), axis=(0, 1))) < 1e-12
+
+
+# --------------------------------------- Rayleigh-Sommerfeld (Eq. 10) pin
+def _gauss_src(X, Y, w0=8e-6):
+    return np.exp(-(X ** 2 + Y ** 2) / (2 * w0 ** 2)) * np.exp(2j * np.pi * (2.5e4 * X + 1.0e4 * Y))
+
+
+@pytest.mark.parametrize("z", [50e-6, 100e-6])
+def test_nuasm2_matches_rayleigh_sommerfeld(z):
+    """A resolved Gaussian beam well inside the window: the oracle's NU-ASM_2
+    equals direct RS integration of the same analytic source (sampled 8x finer)
+    at off-grid destinations, and the sign of z matters."""
+    N, g, lam = 32, 2e-6, 633e-9
+    m = np.arange(-N // 2, N // 2) * g
+    u1 = _gauss_src(*np.meshgrid(m, m, indexing="xy"))
+    rng = np.random.default_rng(3)
+    xq = rng.uniform(-N * g / 4, N * g / 4, 48)
+    yq = rng.uniform(-N * g / 4, N * g / 4, 48)
+    gf, n = g / 8, 320
+    mf = np.arange(-n // 2, n // 2) * gf
+    src = _gauss_src(*np.meshgrid(mf, mf, indexing="xy"))
+    ox, oy = 3e-6, -2e-6
+    ref = O.rayleigh_sommerfeld(src, gf, lam, z, xq, yq, ox, oy)
+    got = O.nuasm2(O.Geometry(N=N, g=g, lam=lam, z=z, ox=ox, oy=oy), u1, xq, yq)
+    assert O.rel_l2(got, ref) < 1e-4
+    wrong = O.nuasm2(O.Geometry(N=N, g=g, lam=lam, z=-z, ox=ox, oy=oy), u1, xq, yq)
+    assert O.rel_l2(wrong, ref) > 0.1
+
+
+# -------------------------------------------------------------- adjoints
+@pytest.mark.parametrize("tf,band", [("asm", "limited"), ("asm", "full"), ("fresnel", "full")])
+def test_adjoint_dot_products(tf, band):
+    geo = _geo(N=8, z=0.002, ox=1e-5, oy=-4e-6, tf=tf, band=band)
+    rng = np.random.default_rng(61)
+    M = 37
+    x, y = synth.clustered_box(rng, M, geo.N * geo.g)
+    c = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    v = rng.standard_normal((geo.Np, geo.Np)) + 1j * rng.standard_normal((geo.Np, geo.Np))
+    lhs = np.vdot(v, O.nuasm1(geo, x, y, c))
+    rhs = np.vdot(O.nuasm1_adjoint(geo, v, x, y), c)
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+    u1 = rng.standard_normal((geo.N, geo.N)) + 1j * rng.standard_normal((geo.N, geo.N))
+    w = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    lhs = np.vdot(w, O.nuasm2(geo, u1, x, y))
+    rhs = np.vdot(O.nuasm2_adjoint(geo, w, x, y), u1)
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+def test_cgh_gradient_matches_central_differences():
+    geo = _geo(N=8, g=4e-6, lam=532e-9, z=0.001, band="limited")
+    rng = np.random.default_rng(71)
+    M = 30
+    x, y = synth.three_clusters(rng, M, geo.N * geo.g)
+    phi = rng.uniform(0, 2 * np.pi, size=(8, 8))
+    H = O.transfer(geo)
+    u0 = O.nuasm2(geo, np.exp(1j * phi), x, y, H)
+    T = 0.5 * np.abs(u0) ** 2 + 0.1 * rng.uniform(size=M) * np.mean(np.abs(u0) ** 2)
+    g = O.cgh_grad(geo, phi, x, y, T, H)
+    eps = 1e-6
+    for (a, b) in [(0, 0), (3, 5), (7, 7), (4, 1), (6, 2)]:
+        p = phi.copy()
+        p[a, b] += eps
+        lp = O.cgh_loss(geo, p, x, y, T, H)
+        p[a, b] -= 2 * eps
+        lm = O.cgh_loss(geo, p, x, y, T, H)
+        fd = (lp - lm) / (2 * eps)
+        assert abs(fd - g[a, b]) <= 1e-6 * np.max(np.abs(g))
+
+
+def test_spectrum_at_matches_fft_of_z0_output():
+    """F(k) at single frequencies (used for full-size sampled checks) equals the
+    numpy FFT of the z = 0, o = 0, full-band NU-ASM_1 output (H = 1)."""
+    geo = _geo(N=8, z=0.0)
+    rng = np.random.default_rng(81)
+    M = 20
+    x, y = synth.uniform_box(rng, M, geo.N * geo.g)
+    c = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    u2 = O.nuasm1(geo, x, y, c)
+    F = np.fft.fftshift(np.fft.fft2(np.fft.ifftshift(u2)))
+    kx = rng.integers(-8, 8, size=10)
+    ky = rng.integers(-8, 8, size=10)
+    got = O.spectrum_at(geo, x, y, c, kx, ky)
+    assert O.rel_l2(got, F[ky + 8, kx + 8]) < 1e-12
