@@ -1,0 +1,175 @@
+/*
+ * nuasm.h -- non-uniform sampled angular-spectrum (ASM) and Fresnel
+ * diffraction on one AMD Instinct MI355X (gfx950).
+ *
+ * Operators (Shimobaba et al., arXiv 1308.6644):
+ *
+ *   NU-ASM_1 / NU-FRE_1 (Eq. 6, type-1 sum of Eq. 7): complex samples c_j at
+ *     non-uniform source points p_j -> uniform N' x N' destination plane,
+ *       u2[n] = N'^-2 sum_{k in K^2} H(k) F(k) exp(2 pi i k.n / N'),
+ *       F(k)  = sum_j c_j exp(-2 pi i df k.p_j),   df = 1/(N' g).
+ *   NU-ASM_2 / NU-FRE_2 (Eq. 9, type-2 sum of Eq. 8): uniform N x N source
+ *     u1 -> complex samples at non-uniform destination points q_j,
+ *       u2_j = N'^-2 sum_{k in K^2} H(k) U(k) exp(2 pi i df k.q_j),
+ *       U(k) = sum_m u1[m] exp(-2 pi i k.m / N').
+ *
+ *   N' = 2N (zero padding against circular wrap, the passage after Eq. 5),
+ *   K = {-N'/2, ..., N'/2 - 1}, g is the pitch of the uniform plane
+ *   (Delta_2 for type 1, Delta_1 for type 2, as stated under Eqs. 6 and 9).
+ *   H is the shifted band-limited ASM transfer function (Eq. 4) or the
+ *   Fresnel transfer function (Eq. 5, the DFT of the impulse response
+ *   sampled on the centred N' x N' grid with area element g^2).
+ *
+ * Layouts: complex values are complex64, interleaved (re, im).  Planes are
+ * row-major with x fastest and centred: element [b][a] of an N' x N' plane is
+ * the sample at n = (a - N'/2, b - N'/2), i.e. at global position n g + o;
+ * element [b][a] of an N x N plane is pixel (a - N/2, b - N/2).  Point
+ * coordinates are FP64 metres in the plane's local frame (window centre at
+ * 0); they must satisfy -N g/2 <= x, y <= N g/2 (up to 1e-9 pixel of
+ * rounding slack; such points are clamped onto the edge).
+ *
+ * Threading and streams: a plan is not thread-safe; use one plan per stream.
+ * All device work of a call is enqueued on the plan's HIP stream.  execute()
+ * never synchronises the host.  set_points() synchronises once (a 4-byte
+ * readback) to report out-of-range points, unless the plan was created with
+ * NUASM_DEFER_RANGE_CHECK, in which case nuasm_check_points() reports it.
+ *
+ * Errors: every call returns nuasm_status; nothing throws across the ABI.
+ * nuasm_last_error() gives a thread-local human-readable detail of the most
+ * recent failure on the calling thread.
+ */
+#ifndef NUASM_H
+#define NUASM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NUASM_OK = 0,
+  NUASM_ERR_INVALID_ARG = 1,   /* bad parameter, null pointer, wrong plan type */
+  NUASM_ERR_OUT_OF_RANGE = 2,  /* a point lies outside the N g window */
+  NUASM_ERR_NOT_READY = 3,     /* execute before a successful set_points */
+  NUASM_ERR_UNSUPPORTED = 4,   /* N not a power of two in [16, 4096], ... */
+  NUASM_ERR_NO_DEVICE = 5,     /* no HIP device visible */
+  NUASM_ERR_ALLOC = 6,         /* device or pinned-host allocation failed */
+  NUASM_ERR_HIP = 7            /* a HIP runtime call failed */
+} nuasm_status;
+
+enum { NUASM_TYPE_1 = 1, NUASM_TYPE_2 = 2 };
+enum { NUASM_TF_ASM = 0, NUASM_TF_FRESNEL = 1 };
+/* Rect of Eq. 4: full grid; limited = aliasing-free band of the shifted ASM
+ * (per axis |o - z f / sqrt(1/lambda^2 - f^2)| <= N g, edges inclusive);
+ * explicit = caller's centre band_c and width band_w in frequency-index
+ * units, |k - c| <= w/2.  Fresnel plans ignore the band. */
+enum { NUASM_BAND_FULL = 0, NUASM_BAND_LIMITED = 1, NUASM_BAND_EXPLICIT = 2 };
+
+/* params.flags */
+#define NUASM_OUT_CROP_N        0x1u  /* type 1: write only the central N x N */
+#define NUASM_DEFER_RANGE_CHECK 0x2u  /* set_points does not synchronise */
+
+typedef struct {
+  int32_t type;        /* NUASM_TYPE_1 or NUASM_TYPE_2 */
+  int32_t tf;          /* NUASM_TF_ASM or NUASM_TF_FRESNEL */
+  int32_t band;        /* NUASM_BAND_* (ASM only) */
+  int32_t phase_fp64;  /* 1 (default): ASM phase in float64; 0: float32 */
+  int64_t N;           /* plane side in pixels; N' = 2N; power of two, 16..4096 */
+  double lambda;       /* wavelength, metres (> 0) */
+  double z;            /* propagation distance, metres; < 0 back-propagates;
+                          must be != 0 for Fresnel */
+  double ox, oy;       /* off-axis offset o of Eq. 4, metres */
+  double d1, d2;       /* source / destination pitch, metres; the uniform
+                          plane's pitch is used: d2 for type 1, d1 for type 2 */
+  double band_c[2];    /* NUASM_BAND_EXPLICIT: band centre (c_m, c_n), index units */
+  double band_w[2];    /* NUASM_BAND_EXPLICIT: band width  (w_m, w_n), index units */
+  double tol;          /* spreading-kernel tolerance, 1e-12 .. 1e-2 */
+  uint32_t flags;      /* NUASM_OUT_CROP_N | NUASM_DEFER_RANGE_CHECK */
+  uint32_t reserved;   /* must be 0 */
+} nuasm_params;
+
+typedef struct {
+  int64_t N, Np, nf;          /* plane side, N' = 2N, fine grid sigma N' = 2N' */
+  int64_t L;                  /* side of the stored fine-grid support, N' + 16 */
+  int32_t w;                  /* spreading-kernel width in fine cells */
+  float beta;                 /* exponential-of-semicircle shape parameter */
+  int32_t tile;               /* fine cells per bin side */
+  int32_t tiles;              /* number of bins */
+  int32_t kx_lo, kx_hi;       /* inclusive band of Eq. 4 in index units */
+  int32_t ky_lo, ky_hi;
+  int64_t in_elems, out_elems;/* complex elements of execute()'s in / out
+                                 (for the current point count) */
+  int64_t M;                  /* points of the last set_points (0 if none) */
+  size_t device_bytes;        /* device memory the plan holds */
+} nuasm_plan_info;
+
+typedef struct nuasm_plan_s* nuasm_plan;
+
+/* Fill *p with defaults: type 1, ASM, full band, float64 phase, tol 1e-6. */
+nuasm_status nuasm_params_default(nuasm_params* p);
+
+/* Create a plan on the current HIP device for operator Eq. 6 (type 1) or
+ * Eq. 9 (type 2) with transfer function Eq. 4 or Eq. 5.  hip_stream is a
+ * hipStream_t (NULL = default stream); it is borrowed, not owned.  Builds the
+ * plan tables on the device (twiddles, deconvolution weights, Fresnel axis
+ * transforms).  On failure *out is set to NULL. */
+nuasm_status nuasm_plan_create(const nuasm_params* p, void* hip_stream, nuasm_plan* out);
+
+/* Release every resource of the plan.  NULL-safe.  Synchronises the plan's
+ * stream first. */
+nuasm_status nuasm_plan_destroy(nuasm_plan plan);
+
+/* Change the stream later calls are enqueued on (borrowed). */
+nuasm_status nuasm_plan_set_stream(nuasm_plan plan, void* hip_stream);
+
+nuasm_status nuasm_plan_get_info(nuasm_plan plan, nuasm_plan_info* info);
+
+/* Coordinate normalisation and binning of the non-uniform plane (Fig. 1 and
+ * the text around Eqs. 7-9): M points x_dev[M], y_dev[M] (device FP64
+ * metres) are converted once to fine-grid cells and offsets and sorted into
+ * bins.  The arrays are read on the plan's stream and may be freed once the
+ * stream has passed this call; the plan keeps its own sorted copy.  Returns
+ * NUASM_ERR_OUT_OF_RANGE (and leaves the plan not ready) if any point is
+ * outside the window or not finite.  M = 0 is allowed. */
+nuasm_status nuasm_set_points(nuasm_plan plan, int64_t M, const double* x_dev, const double* y_dev);
+
+/* With NUASM_DEFER_RANGE_CHECK: synchronise and report whether the last
+ * set_points saw out-of-range points (NUASM_ERR_OUT_OF_RANGE) or not. */
+nuasm_status nuasm_check_points(nuasm_plan plan);
+
+/* Apply the operator.  Type 1: in_dev = c[M], out_dev = u2[N'][N'] (or
+ * [N][N] with NUASM_OUT_CROP_N).  Type 2: in_dev = u1[N][N], out_dev = u2[M]
+ * in the caller's point order.  Device pointers, complex64, caller-owned,
+ * non-overlapping. */
+nuasm_status nuasm_execute(nuasm_plan plan, const void* in_dev, void* out_dev);
+
+/* Apply the adjoint (conjugate transpose) of the plan's operator, derived
+ * from Eqs. 6 and 9 by reversing every step and conjugating H.  Type 1:
+ * in_dev = v[N'][N'], out_dev = w[M].  Type 2: in_dev = w[M], out_dev =
+ * u1'[N][N]. */
+nuasm_status nuasm_execute_adjoint(nuasm_plan plan, const void* in_dev, void* out_dev);
+
+/* Write the transfer function exactly as the fused spectral kernel applies
+ * it, H(k) of Eq. 4 or Eq. 5 times its Rect, as complex64 [N'][N'] centred
+ * ([b][a] holds k = (a - N'/2, b - N'/2)), to out_dev.  For testing. */
+nuasm_status nuasm_debug_transfer(nuasm_plan plan, void* out_dev);
+
+/* Plain batched 1-D FFT with the library's Stockham kernels, for testing:
+ * `batch` contiguous rows of length n (power of two, 32..16384), complex64,
+ * forward (sign = -1) or unnormalised inverse (sign = +1), out of place. */
+nuasm_status nuasm_debug_fft(int64_t n, int64_t batch, int32_t sign, const void* in_dev,
+                             void* out_dev, void* hip_stream);
+
+const char* nuasm_status_string(nuasm_status s);
+const char* nuasm_last_error(void);
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int32_t nuasm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NUASM_H */

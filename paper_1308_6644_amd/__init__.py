@@ -1,0 +1,284 @@
+"""Python binding of libnuasm: non-uniform sampled ASM / Fresnel diffraction
+on one MI355X (Shimobaba et al., arXiv 1308.6644, Eqs. 4-9).
+
+Argument marshalling only: every step of the operators runs in the library's
+HIP kernels.  PyTorch supplies device memory and streams.  The library must be
+built first (``python -m paper_1308_6644_amd.build``); importing this module
+raises if it is missing, and there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # loads the HIP runtime the library binds to
+
+__all__ = [
+    "Plan", "NUASM1", "NUASM2", "nuasm1", "nuasm2", "debug_fft", "lib_path", "load",
+    "NuasmError", "TYPE_1", "TYPE_2", "TF_ASM", "TF_FRESNEL",
+]
+
+TYPE_1, TYPE_2 = 1, 2
+TF_ASM, TF_FRESNEL = 0, 1
+BAND = {"full": 0, "limited": 1, "explicit": 2}
+TF = {"asm": TF_ASM, "fresnel": TF_FRESNEL}
+OUT_CROP_N = 0x1
+DEFER_RANGE_CHECK = 0x2
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def lib_path() -> str:
+    return os.path.join(_HERE, "libnuasm.so")
+
+
+class NuasmError(RuntimeError):
+    def __init__(self, status: int, name: str, detail: str):
+        super().__init__(f"{name}: {detail}")
+        self.status = status
+        self.name = name
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("type", ctypes.c_int32), ("tf", ctypes.c_int32), ("band", ctypes.c_int32),
+        ("phase_fp64", ctypes.c_int32), ("N", ctypes.c_int64),
+        ("lam", ctypes.c_double), ("z", ctypes.c_double),
+        ("ox", ctypes.c_double), ("oy", ctypes.c_double),
+        ("d1", ctypes.c_double), ("d2", ctypes.c_double),
+        ("band_c", ctypes.c_double * 2), ("band_w", ctypes.c_double * 2),
+        ("tol", ctypes.c_double), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+    ]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [
+        ("N", ctypes.c_int64), ("Np", ctypes.c_int64), ("nf", ctypes.c_int64), ("L", ctypes.c_int64),
+        ("w", ctypes.c_int32), ("beta", ctypes.c_float), ("tile", ctypes.c_int32),
+        ("tiles", ctypes.c_int32), ("kx_lo", ctypes.c_int32), ("kx_hi", ctypes.c_int32),
+        ("ky_lo", ctypes.c_int32), ("ky_hi", ctypes.c_int32), ("in_elems", ctypes.c_int64),
+        ("out_elems", ctypes.c_int64), ("M", ctypes.c_int64), ("device_bytes", ctypes.c_size_t),
+    ]
+
+
+_SIGS = {
+    "nuasm_version": (ctypes.c_int32, []),
+    "nuasm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "nuasm_last_error": (ctypes.c_char_p, []),
+    "nuasm_params_default": (ctypes.c_int, [ctypes.POINTER(Params)]),
+    "nuasm_plan_create": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "nuasm_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "nuasm_plan_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "nuasm_plan_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(PlanInfo)]),
+    "nuasm_set_points": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
+    "nuasm_check_points": (ctypes.c_int, [ctypes.c_void_p]),
+    "nuasm_execute": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "nuasm_execute_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "nuasm_debug_transfer": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "nuasm_debug_fft": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p]),
+}
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libnuasm.so (built in-tree).  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = lib_path()
+    if not os.path.exists(p):
+        raise ImportError(f"{p} is missing: build it with `python -m paper_1308_6644_amd.build`")
+    lib = ctypes.CDLL(p)
+    for name, (res, args) in _SIGS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != 0:
+        lib = load()
+        name = lib.nuasm_status_string(status).decode()
+        detail = lib.nuasm_last_error().decode()
+        raise NuasmError(status, name, detail)
+
+
+def _stream_ptr(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _dev_ptr(t: torch.Tensor, dtype, what: str) -> int:
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{what} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    return t.data_ptr()
+
+
+class Plan:
+    """One operator instance: NU-ASM_1/NU-FRE_1 (type 1, Eq. 6) or
+    NU-ASM_2/NU-FRE_2 (type 2, Eq. 9) on an N x N plane of pitch g.
+
+    Type 1: ``execute(c[M]) -> u2[N'][N']`` (``[N][N]`` with ``crop=True``).
+    Type 2: ``execute(u1[N][N]) -> u2[M]``.  Points are FP64 metres.
+    """
+
+    def __init__(self, N: int, type: int, lam: float, z: float, g: float, *, tf: str = "asm",
+                 ox: float = 0.0, oy: float = 0.0, band: str = "full", band_c=(0.0, 0.0),
+                 band_w=(0.0, 0.0), tol: float = 1e-6, phase_fp64: bool = True, crop: bool = False,
+                 defer_range_check: bool = False, device=None):
+        lib = load()
+        p = Params()
+        _check(lib.nuasm_params_default(ctypes.byref(p)))
+        p.type = int(type)
+        p.tf = TF[tf]
+        p.band = BAND[band]
+        p.phase_fp64 = 1 if phase_fp64 else 0
+        p.N = int(N)
+        p.lam = float(lam)
+        p.z = float(z)
+        p.ox, p.oy = float(ox), float(oy)
+        p.d1 = p.d2 = float(g)
+        p.band_c[0], p.band_c[1] = float(band_c[0]), float(band_c[1])
+        p.band_w[0], p.band_w[1] = float(band_w[0]), float(band_w[1])
+        p.tol = float(tol)
+        p.flags = (OUT_CROP_N if crop else 0) | (DEFER_RANGE_CHECK if defer_range_check else 0)
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.params = p
+        self.N, self.Np, self.type, self.crop = int(N), 2 * int(N), int(type), bool(crop)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib.nuasm_plan_create(ctypes.byref(p), ctypes.c_void_p(_stream_ptr()), ctypes.byref(h)))
+        self._h = h
+        self.M = 0
+
+    # ------------------------------------------------------------ lifecycle
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load().nuasm_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_stream(self):
+        _check(load().nuasm_plan_set_stream(self._h, ctypes.c_void_p(_stream_ptr())))
+
+    @property
+    def info(self) -> dict:
+        i = PlanInfo()
+        _check(load().nuasm_plan_get_info(self._h, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in PlanInfo._fields_}
+
+    # ------------------------------------------------------------- calls
+    def set_points(self, x: torch.Tensor, y: torch.Tensor):
+        if x.shape != y.shape or x.dim() != 1:
+            raise ValueError("x and y must be 1-D tensors of equal length")
+        self._sync_stream()
+        M = x.numel()
+        xp = _dev_ptr(x, torch.float64, "x") if M else None
+        yp = _dev_ptr(y, torch.float64, "y") if M else None
+        _check(load().nuasm_set_points(self._h, M, ctypes.c_void_p(xp), ctypes.c_void_p(yp)))
+        self.M = M
+        self._points = (x, y)  # keep alive until the stream has read them
+        return self
+
+    def check_points(self):
+        _check(load().nuasm_check_points(self._h))
+
+    def _in_shape(self, adjoint: bool):
+        fwd = (self.M,) if self.type == TYPE_1 else (self.N, self.N)
+        if not adjoint:
+            return fwd
+        return (self.Np, self.Np) if self.type == TYPE_1 else (self.M,)
+
+    def _out_shape(self, adjoint: bool):
+        if self.type == TYPE_1:
+            if adjoint:
+                return (self.M,)
+            return (self.N, self.N) if self.crop else (self.Np, self.Np)
+        return (self.N, self.N) if adjoint else (self.M,)
+
+    def _run(self, fn, inp: torch.Tensor, out, adjoint: bool):
+        want = self._in_shape(adjoint)
+        if tuple(inp.shape) != want:
+            raise ValueError(f"input shape {tuple(inp.shape)} != {want}")
+        oshape = self._out_shape(adjoint)
+        if out is None:
+            out = torch.empty(oshape, dtype=torch.complex64, device=inp.device)
+        elif tuple(out.shape) != oshape:
+            raise ValueError(f"output shape {tuple(out.shape)} != {oshape}")
+        self._sync_stream()
+        ip = _dev_ptr(inp, torch.complex64, "input")
+        op = _dev_ptr(out, torch.complex64, "output")
+        _check(fn(self._h, ctypes.c_void_p(ip), ctypes.c_void_p(op)))
+        return out
+
+    def execute(self, inp: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        return self._run(load().nuasm_execute, inp, out, adjoint=False)
+
+    def adjoint(self, inp: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        return self._run(load().nuasm_execute_adjoint, inp, out, adjoint=True)
+
+    def transfer(self) -> torch.Tensor:
+        """H(k) Rect(k) as the fused spectral kernel applies it, [N'][N']."""
+        out = torch.empty((self.Np, self.Np), dtype=torch.complex64, device=self.device)
+        self._sync_stream()
+        _check(load().nuasm_debug_transfer(self._h, ctypes.c_void_p(out.data_ptr())))
+        return out
+
+
+def debug_fft(x: torch.Tensor, sign: int = -1) -> torch.Tensor:
+    """Batched 1-D FFT along the last axis with the library's Stockham kernels."""
+    n = x.shape[-1]
+    xin = x.contiguous()
+    out = torch.empty_like(xin)
+    _dev_ptr(xin, torch.complex64, "x")
+    _check(load().nuasm_debug_fft(n, xin.numel() // n, int(sign), ctypes.c_void_p(xin.data_ptr()),
+                                  ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(_stream_ptr())))
+    return out
+
+
+# ------------------------------------------------------------- autograd
+class NUASM1(torch.autograd.Function):
+    """u2 = NU-ASM_1(c) with backward = the hand-written adjoint."""
+
+    @staticmethod
+    def forward(ctx, c, plan: Plan):
+        ctx.plan = plan
+        return plan.execute(c.contiguous())
+
+    @staticmethod
+    def backward(ctx, grad):
+        return ctx.plan.adjoint(grad.contiguous()), None
+
+
+class NUASM2(torch.autograd.Function):
+    """u2 = NU-ASM_2(u1) with backward = the hand-written adjoint."""
+
+    @staticmethod
+    def forward(ctx, u1, plan: Plan):
+        ctx.plan = plan
+        return plan.execute(u1.contiguous())
+
+    @staticmethod
+    def backward(ctx, grad):
+        return ctx.plan.adjoint(grad.contiguous()), None
+
+
+def nuasm1(c: torch.Tensor, plan: Plan) -> torch.Tensor:
+    return NUASM1.apply(c, plan)
+
+
+def nuasm2(u1: torch.Tensor, plan: Plan) -> torch.Tensor:
+    return NUASM2.apply(u1, plan)

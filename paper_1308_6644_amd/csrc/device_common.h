@@ -1,0 +1,192 @@
+// Device helpers shared by the gfx950 kernels: complex arithmetic, the
+// register-level DFT butterflies, the LDS Stockham FFT, and the
+// exponential-of-semicircle spreading kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nuasm {
+
+// ------------------------------------------------------------ complex math
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ float2 czero() { return make_float2(0.f, 0.f); }
+
+// cos / sin of 2 pi m / 16 for m = 0..8 (exact decimal expansions)
+__device__ __forceinline__ float cos16(int m) {
+  switch (m) {
+    case 0: return 1.0f;
+    case 1: return 0.92387953251128675613f;
+    case 2: return 0.70710678118654752440f;
+    case 3: return 0.38268343236508977173f;
+    case 4: return 0.0f;
+    case 5: return -0.38268343236508977173f;
+    case 6: return -0.70710678118654752440f;
+    case 7: return -0.92387953251128675613f;
+    default: return -1.0f;
+  }
+}
+__device__ __forceinline__ float sin16(int m) { return cos16(m < 4 ? 4 - m : m - 4) * (m <= 8 ? 1.f : -1.f); }
+
+// v * exp(DIR * 2 pi i m / 16), m compile-time after unrolling.
+template <int DIR>
+__device__ __forceinline__ float2 rot16(int m, float2 v) {
+  if (m == 0) return v;
+  if (m == 4) return DIR < 0 ? make_float2(v.y, -v.x) : make_float2(-v.y, v.x);
+  const float c = cos16(m);
+  const float s = DIR < 0 ? -sin16(m) : sin16(m);
+  return make_float2(c * v.x - s * v.y, c * v.y + s * v.x);
+}
+
+// In-register DFT of length R (R = 1, 2, 4, 8, 16), natural order in and out,
+// kernel exp(DIR * 2 pi i j k / R).  Radix-2 decimation in time.
+template <int R, int DIR>
+struct Dft {
+  static __device__ __forceinline__ void run(float2* x) {
+    float2 e[R / 2], o[R / 2];
+#pragma unroll
+    for (int i = 0; i < R / 2; ++i) {
+      e[i] = x[2 * i];
+      o[i] = x[2 * i + 1];
+    }
+    Dft<R / 2, DIR>::run(e);
+    Dft<R / 2, DIR>::run(o);
+#pragma unroll
+    for (int k = 0; k < R / 2; ++k) {
+      const float2 t = rot16<DIR>(k * (16 / R), o[k]);
+      x[k] = cadd(e[k], t);
+      x[k + R / 2] = csub(e[k], t);
+    }
+  }
+};
+template <int DIR>
+struct Dft<2, DIR> {
+  static __device__ __forceinline__ void run(float2* x) {
+    const float2 a = x[0], b = x[1];
+    x[0] = cadd(a, b);
+    x[1] = csub(a, b);
+  }
+};
+template <int DIR>
+struct Dft<1, DIR> {
+  static __device__ __forceinline__ void run(float2*) {}
+};
+
+// LDS index with one pad slot per 16 complex elements: breaks the stride-16
+// bank pattern of the first Stockham pass.
+__device__ __forceinline__ int pidx(int e) { return e + (e >> 4); }
+__host__ __device__ constexpr int lds_elems(int n) { return n + (n >> 4) + 1; }
+
+// One radix-R Stockham pass over C interleaved transforms of length N held in
+// LDS (element t of transform c at pidx(t * C + c)), NT threads.  P is the
+// product of the radices of the earlier passes.  tw[m] = exp(-2 pi i m / N).
+template <int LOGN, int C, int NT, int DIR, int R, int P>
+__device__ __forceinline__ void stockham_pass(float2* __restrict__ s, const float2* __restrict__ tw) {
+  constexpr int N = 1 << LOGN;
+  constexpr int NR = N / R;
+  constexpr int NB = C * NR;
+  constexpr int PER = (NB + NT - 1) / NT;
+  constexpr int TWS = N / (P * R);
+  const int tid = threadIdx.x;
+  float2 x[PER][R];
+  float2 w[PER][R];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int b = tid + q * NT;
+    if (NB % NT == 0 || b < NB) {
+      const int c = b % C, i = b / C;
+      const int k = i & (P - 1);
+#pragma unroll
+      for (int j = 0; j < R; ++j) x[q][j] = s[pidx((i + j * NR) * C + c)];
+      if (P > 1) {
+#pragma unroll
+        for (int j = 1; j < R; ++j) w[q][j] = tw[j * k * TWS];
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int b = tid + q * NT;
+    if (NB % NT == 0 || b < NB) {
+      const int c = b % C, i = b / C;
+      const int k = i & (P - 1);
+      if (P > 1) {
+#pragma unroll
+        for (int j = 1; j < R; ++j) {
+          float2 t = w[q][j];
+          if (DIR > 0) t.y = -t.y;
+          x[q][j] = cmul(x[q][j], t);
+        }
+      }
+      Dft<R, DIR>::run(x[q]);
+      const int base = (i - k) * R + k;
+#pragma unroll
+      for (int j = 0; j < R; ++j) s[pidx((base + j * P) * C + c)] = x[q][j];
+    }
+  }
+  __syncthreads();
+}
+
+template <int LOGN, int C, int NT, int DIR, int P, int REM>
+struct FftPasses {
+  static __device__ __forceinline__ void run(float2* s, const float2* tw) {
+    constexpr int LR = REM >= 4 ? 4 : REM;
+    constexpr int R = 1 << LR;
+    stockham_pass<LOGN, C, NT, DIR, R, P>(s, tw);
+    FftPasses<LOGN, C, NT, DIR, P * R, REM - LR>::run(s, tw);
+  }
+};
+template <int LOGN, int C, int NT, int DIR, int P>
+struct FftPasses<LOGN, C, NT, DIR, P, 0> {
+  static __device__ __forceinline__ void run(float2*, const float2*) {}
+};
+
+// Unnormalised in-LDS FFT of C interleaved transforms of length 2^LOGN,
+// kernel exp(DIR * 2 pi i t k / N).  Must be entered by all NT threads after
+// the data is in LDS and a barrier; ends with a barrier.
+template <int LOGN, int C, int NT, int DIR>
+__device__ __forceinline__ void fft_lds(float2* s, const float2* tw) {
+  FftPasses<LOGN, C, NT, DIR, 1, LOGN>::run(s, tw);
+}
+
+// ------------------------------------------------- spreading kernel (ES)
+// psi(d) = exp(beta (sqrt(1 - (2d/w)^2) - 1)) for |d| <= w/2, 0 outside
+// (Barnett, Magland and af Klinteberg, SIAM J. Sci. Comput. 2019).
+__device__ __forceinline__ float es_kernel(float d, float two_over_w, float beta) {
+  const float t = d * two_over_w;
+  const float r = 1.0f - t * t;
+  return r > 0.0f ? expf(beta * (sqrtf(r) - 1.0f)) : 0.0f;
+}
+
+// Bin record: one (point, bin) pair.  lx, ly: first tap relative to the bin
+// origin (int8 each), bit 16: the bin holds the point's first tap; dx, dy:
+// offset of the first tap from the point in fine cells; idx: caller's point
+// index.
+struct __align__(16) BinRec {
+  int32_t packed;
+  float dx, dy;
+  int32_t idx;
+};
+
+__device__ __forceinline__ int rec_lx(int32_t p) { return (int)(int8_t)(p & 0xff); }
+__device__ __forceinline__ int rec_ly(int32_t p) { return (int)(int8_t)((p >> 8) & 0xff); }
+__device__ __forceinline__ bool rec_primary(int32_t p) { return (p >> 16) & 1; }
+
+// blockIdx -> work index such that consecutive work items land on the same
+// XCD (the dispatcher deals workgroups round-robin over the 8 XCDs, each with
+// its own L2).  `count` must be the grid size.
+__device__ __forceinline__ int xcd_remap(int bid, int count) {
+  constexpr int XCD = 8;
+  const int per = count / XCD;
+  if (per == 0 || bid >= per * XCD) return bid;
+  return (bid % XCD) * per + bid / XCD;
+}
+
+}  // namespace nuasm

@@ -1,0 +1,546 @@
+// Grid passes of the two pipelines on gfx950: pruned row FFTs, the fused
+// column pass (FFT -> deconvolution x transfer function x Rect -> inverse FFT),
+// and the final row passes.  Every 1-D transform lives in LDS (Stockham,
+// radix 16 with an 8/4/2 tail); HBM is touched once per pass.
+//
+// Index conventions (centred, as in Eqs. 3, 6 and 9): a plane element [b][a]
+// of an N' x N' array holds n = (a - N'/2, b - N'/2); frequency k = a - N'/2.
+// The fine grid of the non-uniform sums has nf = 2 N' cells per axis; the
+// non-uniform window occupies fine cells [N'/2, 3N'/2), and only the support
+// rows/columns [s0, s0 + L), L = N' + 16, are ever stored.
+#include "launch.h"
+
+namespace nuasm {
+
+// Row passes: C rows per workgroup, C * n = 4096 complex values in LDS.
+template <int LOGN>
+struct RowCfg {
+  static constexpr int N = 1 << LOGN;
+  static constexpr int C = N >= 4096 ? 1 : 4096 / N;
+  static constexpr int NB = C * N / 16;
+  static constexpr int NT = NB < 64 ? 64 : (NB > 1024 ? 1024 : NB);
+  static constexpr int LDS = lds_elems(C * N) * 8;
+};
+
+// Column passes: C adjacent columns per workgroup sized so that C columns of
+// the fine length fit in LDS (C * nf <= 16384 complex values, <= 140 KB).
+template <int LOGNF>
+struct ColCfg {
+  static constexpr int NF = 1 << LOGNF;
+  static constexpr int C0 = 16384 / NF;
+  static constexpr int C = C0 < 1 ? 1 : (C0 > 16 ? 16 : C0);
+  static constexpr int NB = C * NF / 16;
+  static constexpr int NT = NB < 64 ? 64 : (NB > 1024 ? 1024 : NB);
+  static constexpr int LDS = lds_elems(C * NF) * 8;
+};
+
+__device__ __forceinline__ bool in_band(int k, int lo, int hi) { return k >= lo && k <= hi; }
+
+// Transfer function of Eq. 4 (ASM) or Eq. 5 (Fresnel) at integer frequency
+// (kx, ky), without the Rect.  The ASM phase is formed in cycles:
+// z sqrt(1/l^2 - q k^2) = z/l - z q k^2 / (1/l + sqrt(.)), which keeps full
+// float64 accuracy at large z, then reduced to [-1/2, 1/2] before the float32
+// sincospi.  Evanescent frequencies give 0.
+__device__ __forceinline__ float2 transfer_at(const Spectral& sp, int Np, int kx, int ky) {
+  float2 h;
+  if (sp.tf == 1) {
+    h = cmul(sp.fre_x[kx + Np / 2], sp.fre_y[ky + Np / 2]);
+  } else if (sp.phase_fp64) {
+    const double k2 = (double)kx * kx + (double)ky * ky;
+    const double r = sp.inv_lam2 - sp.q * k2;
+    if (r < 0.0) return czero();
+    const double s = sqrt(r);
+    double cyc = sp.c0 + sp.ax * kx + sp.ay * ky - sp.zq * k2 / (sp.inv_lam + s);
+    cyc -= rint(cyc);
+    float sn, cs;
+    sincospif(2.0f * (float)cyc, &sn, &cs);
+    h = make_float2(cs, sn);
+  } else {
+    const float k2 = (float)kx * (float)kx + (float)ky * (float)ky;
+    const float r = sp.inv_lam2f - sp.qf * k2;
+    if (r < 0.0f) return czero();
+    float cyc = sp.axf * (float)kx + sp.ayf * (float)ky + sp.zf * sqrtf(r);
+    cyc -= rintf(cyc);
+    float sn, cs;
+    sincospif(2.0f * cyc, &sn, &cs);
+    h = make_float2(cs, sn);
+  }
+  if (sp.conj) h.y = -h.y;
+  return h;
+}
+
+// ----------------------------------------------------------------- type 1
+// Fine support rows -> nf-point FFT along x -> keep k_x in K, times 1/psihat.
+// T[i][a] = sum_l G[i][l] exp(-2 pi i k_x (s0 + l) / nf) / psihat(k_x).
+template <int LOGNP>
+__global__ void __launch_bounds__(RowCfg<LOGNP + 1>::NT)
+k_t1_rows(const float2* __restrict__ fine, float2* __restrict__ T, GridGeom g,
+          const float* __restrict__ dinv, const float2* __restrict__ twall) {
+  constexpr int LOGN = LOGNP + 1, NF = 1 << LOGN, NP = 1 << LOGNP;
+  using Cfg = RowCfg<LOGN>;
+  constexpr int C = Cfg::C, NT = Cfg::NT;
+  extern __shared__ float2 s[];
+  const int r0 = blockIdx.x * C;
+  const int L = g.L, s0 = g.s0;
+  for (int e = threadIdx.x; e < C * NF; e += NT) {
+    const int c = e / NF, t = e % NF;
+    const int row = r0 + c, i = t - s0;
+    float2 v = czero();
+    if (row < L && i >= 0 && i < L) v = fine[(size_t)row * L + i];
+    s[pidx(t * C + c)] = v;
+  }
+  __syncthreads();
+  fft_lds<LOGN, C, NT, -1>(s, tw_for(twall, LOGN));
+  for (int e = threadIdx.x; e < C * NP; e += NT) {
+    const int c = e / NP, a = e % NP;
+    const int row = r0 + c, kx = a - NP / 2;
+    if (row < L && in_band(kx, g.kxlo, g.kxhi))
+      T[(size_t)row * NP + a] = cscale(s[pidx(((kx + NF) & (NF - 1)) * C + c)], dinv[a]);
+  }
+}
+
+// Columns of T -> nf-point FFT along y -> keep k_y in K -> times
+// H(k) Rect(k) / psihat(k_y) / N'^2 -> N'-point inverse FFT along y.
+// The (-1)^k factors of the centred fine grid and of the centred inverse DFT
+// cancel (N'/2 is even); the remaining output sign (-1)^n_y is applied here.
+template <int LOGNP>
+__global__ void __launch_bounds__(ColCfg<LOGNP + 1>::NT)
+k_t1_cols(const float2* __restrict__ T, float2* __restrict__ V, GridGeom g, Spectral sp,
+          const float2* __restrict__ twall) {
+  constexpr int LOGN = LOGNP + 1, NF = 1 << LOGN, NP = 1 << LOGNP;
+  using Cfg = ColCfg<LOGN>;
+  constexpr int C = Cfg::C, NT = Cfg::NT;
+  extern __shared__ float2 s[];
+  const int strip = xcd_remap(blockIdx.x, gridDim.x);
+  const int a0 = strip * C;
+  const int kx0 = a0 - NP / 2;
+  if (kx0 + C - 1 < g.kxlo || kx0 > g.kxhi) return;  // whole strip outside the band
+  const int L = g.L, s0 = g.s0;
+  for (int e = threadIdx.x; e < C * NF; e += NT) {
+    const int t = e / C, c = e % C;
+    const int i = t - s0;
+    float2 v = czero();
+    if (i >= 0 && i < L && in_band(kx0 + c, g.kxlo, g.kxhi)) v = T[(size_t)i * NP + a0 + c];
+    s[pidx(e)] = v;
+  }
+  __syncthreads();
+  fft_lds<LOGN, C, NT, -1>(s, tw_for(twall, LOGN));
+  constexpr int PER = (C * NP + NT - 1) / NT;
+  float2 v[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + q * NT;
+    if (e < C * NP) {
+      const int ay = e / C, c = e % C;
+      const int ky = ay - NP / 2, kx = kx0 + c;
+      float2 x = czero();
+      if (in_band(kx, g.kxlo, g.kxhi) && in_band(ky, g.kylo, g.kyhi)) {
+        const float2 h = transfer_at(sp, NP, kx, ky);
+        x = cmul(s[pidx(((ky + NF) & (NF - 1)) * C + c)], h);
+        x = cscale(x, sp.dinv[ay] * sp.scale);
+      }
+      v[q] = x;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + q * NT;
+    if (e < C * NP) s[pidx(e)] = v[q];
+  }
+  __syncthreads();
+  fft_lds<LOGNP, C, NT, +1>(s, tw_for(twall, LOGNP));
+  for (int e = threadIdx.x; e < C * NP; e += NT) {
+    const int by = e / C, c = e % C;
+    if (in_band(kx0 + c, g.kxlo, g.kxhi)) {
+      float2 x = s[pidx(e)];
+      if (by & 1) x = make_float2(-x.x, -x.y);
+      V[(size_t)by * NP + a0 + c] = x;
+    }
+  }
+}
+
+// Rows of V -> N'-point inverse FFT along x -> times (-1)^n_x -> plane
+// (N' x N', or the central N x N when cropping).
+template <int LOGNP>
+__global__ void __launch_bounds__(RowCfg<LOGNP>::NT)
+k_t1_rows_inv(const float2* __restrict__ V, float2* __restrict__ out, GridGeom g,
+              const float2* __restrict__ twall) {
+  constexpr int NP = 1 << LOGNP;
+  using Cfg = RowCfg<LOGNP>;
+  constexpr int C = Cfg::C, NT = Cfg::NT;
+  extern __shared__ float2 s[];
+  const int nrows = g.crop ? g.N : NP;
+  const int rowoff = g.crop ? g.N / 2 : 0;
+  const int r0 = blockIdx.x * C;
+  for (int e = threadIdx.x; e < C * NP; e += NT) {
+    const int c = e / NP, a = e % NP;
+    const int r = r0 + c, kx = a - NP / 2;
+    float2 v = czero();
+    if (r < nrows && in_band(kx, g.kxlo, g.kxhi)) v = V[(size_t)(r + rowoff) * NP + a];
+    s[pidx(a * C + c)] = v;
+  }
+  __syncthreads();
+  fft_lds<LOGNP, C, NT, +1>(s, tw_for(twall, LOGNP));
+  for (int e = threadIdx.x; e < C * NP; e += NT) {
+    const int c = e / NP, bx = e % NP;
+    const int r = r0 + c;
+    if (r >= nrows) continue;
+    float2 x = s[pidx(bx * C + c)];
+    if (bx & 1) x = make_float2(-x.x, -x.y);
+    if (g.crop) {
+      const int ox = bx - g.N / 2;
+      if (ox >= 0 && ox < g.N) out[(size_t)r * g.N + ox] = x;
+    } else {
+      out[(size_t)r * NP + bx] = x;
+    }
+  }
+}
+
+// ----------------------------------------------------------------- type 2
+// Rows of the Nin x Nin plane, zero-padded circularly to N' -> FFT along x ->
+// times (-1)^k_x / psihat(k_x), centred output T[row][k_x + N'/2].
+template <int LOGNP>
+__global__ void __launch_bounds__(RowCfg<LOGNP>::NT)
+k_t2_rows(const float2* __restrict__ u1, float2* __restrict__ T, GridGeom g,
+          const float* __restrict__ dinv, const float2* __restrict__ twall) {
+  constexpr int NP = 1 << LOGNP;
+  using Cfg = RowCfg<LOGNP>;
+  constexpr int C = Cfg::C, NT = Cfg::NT;
+  extern __shared__ float2 s[];
+  const int Nin = g.Nin;
+  const int r0 = blockIdx.x * C;
+  for (int e = threadIdx.x; e < C * NP; e += NT) {
+    const int c = e / NP, t = e % NP;
+    const int r = r0 + c;
+    const int mx = t < NP / 2 ? t : t - NP;
+    float2 v = czero();
+    if (r < Nin && mx >= -Nin / 2 && mx < Nin / 2) v = u1[(size_t)r * Nin + mx + Nin / 2];
+    s[pidx(t * C + c)] = v;
+  }
+  __syncthreads();
+  fft_lds<LOGNP, C, NT, -1>(s, tw_for(twall, LOGNP));
+  for (int e = threadIdx.x; e < C * NP; e += NT) {
+    const int c = e / NP, a = e % NP;
+    const int r = r0 + c, kx = a - NP / 2;
+    if (r < Nin && in_band(kx, g.kxlo, g.kxhi)) {
+      float2 x = cscale(s[pidx(((kx + NP) & (NP - 1)) * C + c)], dinv[a]);
+      if (kx & 1) x = make_float2(-x.x, -x.y);
+      T[(size_t)r * NP + a] = x;
+    }
+  }
+}
+
+// Columns of T (Nin rows) -> N'-point FFT along y -> times H(k) Rect(k)
+// (-1)^k_y / psihat(k_y) / N'^2 -> embed k_y into the nf-point spectrum ->
+// inverse nf-point FFT along y -> keep the support rows [s0, s0 + L).
+template <int LOGNP>
+__global__ void __launch_bounds__(ColCfg<LOGNP + 1>::NT)
+k_t2_cols(const float2* __restrict__ T, float2* __restrict__ V, GridGeom g, Spectral sp,
+          const float2* __restrict__ twall) {
+  constexpr int LOGN = LOGNP + 1, NF = 1 << LOGN, NP = 1 << LOGNP;
+  using Cfg = ColCfg<LOGN>;
+  constexpr int C = Cfg::C, NT = Cfg::NT;
+  extern __shared__ float2 s[];
+  const int strip = xcd_remap(blockIdx.x, gridDim.x);
+  const int a0 = strip * C;
+  const int kx0 = a0 - NP / 2;
+  if (kx0 + C - 1 < g.kxlo || kx0 > g.kxhi) return;
+  const int Nin = g.Nin;
+  for (int e = threadIdx.x; e < C * NP; e += NT) {
+    const int t = e / C, c = e % C;
+    const int my = t < NP / 2 ? t : t - NP;
+    float2 v = czero();
+    if (my >= -Nin / 2 && my < Nin / 2 && in_band(kx0 + c, g.kxlo, g.kxhi))
+      v = T[(size_t)(my + Nin / 2) * NP + a0 + c];
+    s[pidx(e)] = v;
+  }
+  __syncthreads();
+  fft_lds<LOGNP, C, NT, -1>(s, tw_for(twall, LOGNP));
+  constexpr int PER = (C * NP + NT - 1) / NT;
+  float2 v[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + q * NT;
+    if (e < C * NP) {
+      const int ay = e / C, c = e % C;
+      const int ky = ay - NP / 2, kx = kx0 + c;
+      float2 x = czero();
+      if (in_band(kx, g.kxlo, g.kxhi) && in_band(ky, g.kylo, g.kyhi)) {
+        const float2 h = transfer_at(sp, NP, kx, ky);
+        x = cmul(s[pidx(((ky + NP) & (NP - 1)) * C + c)], h);
+        x = cscale(x, sp.dinv[ay] * sp.scale * ((ky & 1) ? -1.0f : 1.0f));
+      }
+      v[q] = x;
+    }
+  }
+  __syncthreads();
+  // the gap between the two halves of K inside the nf-point spectrum is zero
+  for (int e = threadIdx.x; e < C * (NF - NP); e += NT) {
+    const int t = NP / 2 + e / C, c = e % C;
+    s[pidx(t * C + c)] = czero();
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + q * NT;
+    if (e < C * NP) {
+      const int ay = e / C, c = e % C;
+      const int ky = ay - NP / 2;
+      s[pidx(((ky + NF) & (NF - 1)) * C + c)] = v[q];
+    }
+  }
+  __syncthreads();
+  fft_lds<LOGN, C, NT, +1>(s, tw_for(twall, LOGN));
+  const int L = g.L, s0 = g.s0;
+  for (int e = threadIdx.x; e < C * L; e += NT) {
+    const int i = e / C, c = e % C;
+    if (in_band(kx0 + c, g.kxlo, g.kxhi)) V[(size_t)i * NP + a0 + c] = s[pidx((s0 + i) * C + c)];
+  }
+}
+
+// Support rows of V -> embed k_x into nf -> inverse nf-point FFT along x ->
+// keep support columns: the fine grid the interpolation reads.
+template <int LOGNP>
+__global__ void __launch_bounds__(RowCfg<LOGNP + 1>::NT)
+k_t2_rows_inv(const float2* __restrict__ V, float2* __restrict__ fine, GridGeom g,
+              const float2* __restrict__ twall) {
+  constexpr int LOGN = LOGNP + 1, NF = 1 << LOGN, NP = 1 << LOGNP;
+  using Cfg = RowCfg<LOGN>;
+  constexpr int C = Cfg::C, NT = Cfg::NT;
+  extern __shared__ float2 s[];
+  const int L = g.L, s0 = g.s0;
+  const int r0 = blockIdx.x * C;
+  for (int e = threadIdx.x; e < C * NF; e += NT) {
+    const int c = e / NF, t = e % NF;
+    const int r = r0 + c;
+    int kx = NP;  // marks the zero gap
+    if (t < NP / 2) kx = t;
+    else if (t >= NF - NP / 2) kx = t - NF;
+    float2 v = czero();
+    if (r < L && kx != NP && in_band(kx, g.kxlo, g.kxhi)) v = V[(size_t)r * NP + kx + NP / 2];
+    s[pidx(t * C + c)] = v;
+  }
+  __syncthreads();
+  fft_lds<LOGN, C, NT, +1>(s, tw_for(twall, LOGN));
+  for (int e = threadIdx.x; e < C * L; e += NT) {
+    const int c = e / L, i = e % L;
+    const int r = r0 + c;
+    if (r < L) fine[(size_t)r * L + i] = s[pidx((s0 + i) * C + c)];
+  }
+}
+
+// ----------------------------------------------------------- test kernels
+template <int LOGN, int DIR>
+__global__ void __launch_bounds__(RowCfg<LOGN>::NT)
+k_fft_rows(const float2* __restrict__ in, float2* __restrict__ out, int64_t batch,
+           const float2* __restrict__ twall) {
+  constexpr int N = 1 << LOGN;
+  using Cfg = RowCfg<LOGN>;
+  constexpr int C = Cfg::C, NT = Cfg::NT;
+  extern __shared__ float2 s[];
+  const int64_t r0 = (int64_t)blockIdx.x * C;
+  for (int e = threadIdx.x; e < C * N; e += NT) {
+    const int c = e / N, t = e % N;
+    const int64_t r = r0 + c;
+    s[pidx(t * C + c)] = r < batch ? in[r * N + t] : czero();
+  }
+  __syncthreads();
+  fft_lds<LOGN, C, NT, DIR>(s, tw_for(twall, LOGN));
+  for (int e = threadIdx.x; e < C * N; e += NT) {
+    const int c = e / N, t = e % N;
+    const int64_t r = r0 + c;
+    if (r < batch) out[r * N + t] = s[pidx(t * C + c)];
+  }
+}
+
+__global__ void k_transfer_table(GridGeom g, Spectral sp, float2* __restrict__ out) {
+  const int Np = g.Np;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)Np * Np) return;
+  const int ay = (int)(e / Np), ax = (int)(e % Np);
+  const int kx = ax - Np / 2, ky = ay - Np / 2;
+  float2 h = czero();
+  if (in_band(kx, g.kxlo, g.kxhi) && in_band(ky, g.kylo, g.kyhi)) h = transfer_at(sp, Np, kx, ky);
+  out[e] = h;
+}
+
+// One axis of the Fresnel transfer function (Eq. 5) in float64:
+// out[k + N'/2] = amp * sum_{m in K} exp(i pi (m g + o)^2 / (lambda z)) exp(-2 pi i k m / N').
+// Both phases are reduced to whole cycles exactly (k m mod N' in integers)
+// before the float64 sincospi.
+__global__ void k_fresnel_axis(int Np, double g, double two_lam_z, double o, double2 amp,
+                               float2* __restrict__ out) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= Np) return;
+  const int64_t k = a - Np / 2;
+  double re = 0.0, im = 0.0;
+  for (int m = -Np / 2; m < Np / 2; ++m) {
+    const double xm = m * g + o;
+    double c = xm * xm / two_lam_z;
+    c -= rint(c);
+    const int64_t km = (k * m) % Np;
+    double cyc = c - (double)km / (double)Np;
+    double sn, cs;
+    sincospi(2.0 * cyc, &sn, &cs);
+    re += cs;
+    im += sn;
+  }
+  out[a] = make_float2((float)(re * amp.x - im * amp.y), (float)(re * amp.y + im * amp.x));
+}
+
+// --------------------------------------------------------------- launchers
+template <typename K>
+static hipError_t set_lds(K kernel, int bytes) {
+  if (bytes > 64 * 1024)
+    return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  return hipSuccess;
+}
+
+#define NUASM_DISPATCH_NP(logNp, CALL)                  \
+  switch (logNp) {                                      \
+    case 5: CALL(5); break;                             \
+    case 6: CALL(6); break;                             \
+    case 7: CALL(7); break;                             \
+    case 8: CALL(8); break;                             \
+    case 9: CALL(9); break;                             \
+    case 10: CALL(10); break;                           \
+    case 11: CALL(11); break;                           \
+    case 12: CALL(12); break;                           \
+    case 13: CALL(13); break;                           \
+    default: return hipErrorInvalidValue;               \
+  }
+
+hipError_t launch_t1_rows(int logNp, const float2* fine, float2* T, GridGeom g, const float* dinv,
+                          const float2* tw, hipStream_t st) {
+#define CALL(LP)                                                                         \
+  {                                                                                      \
+    using Cfg = RowCfg<LP + 1>;                                                          \
+    hipError_t e = set_lds(k_t1_rows<LP>, Cfg::LDS);                                     \
+    if (e != hipSuccess) return e;                                                       \
+    const int grid = (g.L + Cfg::C - 1) / Cfg::C;                                        \
+    hipLaunchKernelGGL(k_t1_rows<LP>, dim3(grid), dim3(Cfg::NT), Cfg::LDS, st, fine, T, g, dinv, tw); \
+  }
+  NUASM_DISPATCH_NP(logNp, CALL)
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_t1_cols(int logNp, const float2* T, float2* V, GridGeom g, Spectral sp,
+                          const float2* tw, hipStream_t st) {
+#define CALL(LP)                                                                         \
+  {                                                                                      \
+    using Cfg = ColCfg<LP + 1>;                                                          \
+    hipError_t e = set_lds(k_t1_cols<LP>, Cfg::LDS);                                     \
+    if (e != hipSuccess) return e;                                                       \
+    const int grid = (1 << LP) / Cfg::C;                                                 \
+    hipLaunchKernelGGL(k_t1_cols<LP>, dim3(grid), dim3(Cfg::NT), Cfg::LDS, st, T, V, g, sp, tw); \
+  }
+  NUASM_DISPATCH_NP(logNp, CALL)
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_t1_rows_inv(int logNp, const float2* V, float2* out, GridGeom g, const float2* tw,
+                              hipStream_t st) {
+#define CALL(LP)                                                                         \
+  {                                                                                      \
+    using Cfg = RowCfg<LP>;                                                              \
+    hipError_t e = set_lds(k_t1_rows_inv<LP>, Cfg::LDS);                                 \
+    if (e != hipSuccess) return e;                                                       \
+    const int nrows = g.crop ? g.N : (1 << LP);                                          \
+    const int grid = (nrows + Cfg::C - 1) / Cfg::C;                                      \
+    hipLaunchKernelGGL(k_t1_rows_inv<LP>, dim3(grid), dim3(Cfg::NT), Cfg::LDS, st, V, out, g, tw); \
+  }
+  NUASM_DISPATCH_NP(logNp, CALL)
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_t2_rows(int logNp, const float2* u1, float2* T, GridGeom g, const float* dinv,
+                          const float2* tw, hipStream_t st) {
+#define CALL(LP)                                                                         \
+  {                                                                                      \
+    using Cfg = RowCfg<LP>;                                                              \
+    hipError_t e = set_lds(k_t2_rows<LP>, Cfg::LDS);                                     \
+    if (e != hipSuccess) return e;                                                       \
+    const int grid = (g.Nin + Cfg::C - 1) / Cfg::C;                                      \
+    hipLaunchKernelGGL(k_t2_rows<LP>, dim3(grid), dim3(Cfg::NT), Cfg::LDS, st, u1, T, g, dinv, tw); \
+  }
+  NUASM_DISPATCH_NP(logNp, CALL)
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_t2_cols(int logNp, const float2* T, float2* V, GridGeom g, Spectral sp,
+                          const float2* tw, hipStream_t st) {
+#define CALL(LP)                                                                         \
+  {                                                                                      \
+    using Cfg = ColCfg<LP + 1>;                                                          \
+    hipError_t e = set_lds(k_t2_cols<LP>, Cfg::LDS);                                     \
+    if (e != hipSuccess) return e;                                                       \
+    const int grid = (1 << LP) / Cfg::C;                                                 \
+    hipLaunchKernelGGL(k_t2_cols<LP>, dim3(grid), dim3(Cfg::NT), Cfg::LDS, st, T, V, g, sp, tw); \
+  }
+  NUASM_DISPATCH_NP(logNp, CALL)
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_t2_rows_inv(int logNp, const float2* V, float2* fine, GridGeom g, const float2* tw,
+                              hipStream_t st) {
+#define CALL(LP)                                                                         \
+  {                                                                                      \
+    using Cfg = RowCfg<LP + 1>;                                                          \
+    hipError_t e = set_lds(k_t2_rows_inv<LP>, Cfg::LDS);                                 \
+    if (e != hipSuccess) return e;                                                       \
+    const int grid = (g.L + Cfg::C - 1) / Cfg::C;                                        \
+    hipLaunchKernelGGL(k_t2_rows_inv<LP>, dim3(grid), dim3(Cfg::NT), Cfg::LDS, st, V, fine, g, tw); \
+  }
+  NUASM_DISPATCH_NP(logNp, CALL)
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_fft_rows(int logn, int64_t batch, int sign, const float2* in, float2* out,
+                           const float2* tw, hipStream_t st) {
+#define CALL2(LN, D)                                                                     \
+  {                                                                                      \
+    using Cfg = RowCfg<LN>;                                                              \
+    hipError_t e = set_lds(k_fft_rows<LN, D>, Cfg::LDS);                                 \
+    if (e != hipSuccess) return e;                                                       \
+    const int64_t grid = (batch + Cfg::C - 1) / Cfg::C;                                  \
+    hipLaunchKernelGGL((k_fft_rows<LN, D>), dim3((unsigned)grid), dim3(Cfg::NT), Cfg::LDS, st, in, out, batch, tw); \
+  }
+#define CALL(LN) \
+  if (sign < 0) CALL2(LN, -1) else CALL2(LN, 1)
+  switch (logn) {
+    case 5: CALL(5); break;
+    case 6: CALL(6); break;
+    case 7: CALL(7); break;
+    case 8: CALL(8); break;
+    case 9: CALL(9); break;
+    case 10: CALL(10); break;
+    case 11: CALL(11); break;
+    case 12: CALL(12); break;
+    case 13: CALL(13); break;
+    case 14: CALL(14); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef CALL
+#undef CALL2
+  return hipGetLastError();
+}
+
+hipError_t launch_transfer_table(const GridGeom& g, const Spectral& sp, float2* out, hipStream_t st) {
+  const int64_t n = (int64_t)g.Np * g.Np;
+  hipLaunchKernelGGL(k_transfer_table, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, sp, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fresnel_axis(int Np, double g, double two_lam_z, double o, double2 amp,
+                               float2* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_fresnel_axis, dim3((Np + 127) / 128), dim3(128), 0, st, Np, g, two_lam_z, o, amp, out);
+  return hipGetLastError();
+}
+
+}  // namespace nuasm

@@ -1,0 +1,121 @@
+// Internal interface between the host plan code and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_common.h"
+
+namespace nuasm {
+
+constexpr int kTile = 32;        // fine cells per bin side
+constexpr int kPad = 8;          // support margin: taps reach w/2 <= 8 cells past the window
+constexpr int kChunk = 1024;     // max records per spreading / interpolation workgroup
+constexpr int kMaxW = 16;
+
+// Geometry of the fine-grid support and of the uniform planes.
+struct GridGeom {
+  int N, Np, nf;   // plane side, N' = 2N, fine grid 2N'
+  int L, s0;       // support side N' + 2*kPad, first support row/column in the fine grid
+  int kxlo, kxhi;  // inclusive band of Eq. 4, index units
+  int kylo, kyhi;
+  int Nin;         // side of the uniform input of the type-2 pipeline (N, or N' for the type-1 adjoint)
+  int crop;        // type-1 pipeline writes only the central N x N
+};
+
+// Everything the fused spectral kernels need to form D(kx) D(ky) H(k) R(k).
+struct Spectral {
+  int tf;          // 0 = ASM (Eq. 4), 1 = Fresnel (Eq. 5)
+  int phase_fp64;  // ASM phase in float64 (1) or float32 (0)
+  int conj;        // apply conj(H) (adjoint)
+  float scale;     // N'^-2
+  // ASM: cycles = c0 + ax kx + ay ky - zq k^2 / (inv_lam + sqrt(inv_lam2 - q k^2))
+  double c0, ax, ay, q, zq, inv_lam, inv_lam2;
+  // float32 variant: cycles = axf kx + ayf ky + zf sqrt(inv_lam2f - qf k^2)
+  float axf, ayf, qf, zf, inv_lam2f;
+  const float2* fre_x;  // Fresnel: A * H_x(k), index k + N'/2
+  const float2* fre_y;  // Fresnel: H_y(k), index k + N'/2
+  const float* dinv;    // 1 / psihat(k), index k + N'/2
+};
+
+struct BinGeom {
+  int N;            // plane side
+  double inv_g;     // 1 / pitch
+  double half_n;    // N / 2 (range check, pixels)
+  double tau0;      // support coordinate of pixel 0: N + kPad
+  int w;            // kernel width
+  int L;            // support side
+  int TX;           // bins per axis
+};
+
+struct SpreadArgs {
+  const BinRec* recs;
+  const int4* chunks;     // (bin, first record, count, chunks of the bin)
+  const int* nchunks;     // device count of valid chunks (element 0)
+  float2* scratch;        // per-chunk partial bins of multi-chunk bins
+  const float2* vals;     // point values, caller order
+  float2* grid;           // L x L support
+  int L, TX;
+  float two_over_w, beta;
+};
+
+struct SpreadReduceArgs {
+  const int* multi;       // multi-chunk bins
+  const int* nmulti;      // their count
+  const int* bin_chunk0;  // first chunk of each bin
+  const int* bin_nchunk;  // chunks of each bin
+  const float2* scratch;
+  float2* grid;
+  int L, TX;
+};
+
+struct InterpArgs {
+  const BinRec* recs;
+  const int4* chunks;
+  const int* nchunks;
+  const float2* grid;
+  float2* out;            // caller order
+  int L, TX;
+  float two_over_w, beta;
+};
+
+// ---- launchers (return hipGetLastError() of the launch) -------------------
+hipError_t launch_fill_i32(int* p, int v, int64_t n, hipStream_t st);
+hipError_t launch_bin_count(const double* x, const double* y, int64_t M, BinGeom g, int* counts,
+                            int* bad, hipStream_t st);
+// nch[0] spread chunks, nch[1] interpolation chunks, nch[2] records, nch[3] multi-chunk bins
+hipError_t launch_bin_scan(const int* counts, int T, int* cursor, int4* sp_chunks, int* sp_first,
+                           int* sp_n, int* multi, int4* ip_chunks, int* nch, hipStream_t st);
+hipError_t launch_bin_scatter(const double* x, const double* y, int64_t M, BinGeom g, int* cursor,
+                              BinRec* recs, hipStream_t st);
+hipError_t launch_spread(int w, const SpreadArgs& a, int grid, hipStream_t st);
+hipError_t launch_spread_reduce(const SpreadReduceArgs& a, int grid, hipStream_t st);
+hipError_t launch_interp(int w, const InterpArgs& a, int grid, hipStream_t st);
+
+// type-1 pipeline: fine support (L x L) -> rows -> fused columns -> rows -> plane
+hipError_t launch_t1_rows(int logNp, const float2* fine, float2* T, GridGeom g, const float* dinv,
+                          const float2* tw, hipStream_t st);
+hipError_t launch_t1_cols(int logNp, const float2* T, float2* V, GridGeom g, Spectral sp,
+                          const float2* tw, hipStream_t st);
+hipError_t launch_t1_rows_inv(int logNp, const float2* V, float2* out, GridGeom g, const float2* tw,
+                              hipStream_t st);
+// type-2 pipeline: plane (Nin x Nin) -> rows -> fused columns -> fine rows (L x L)
+hipError_t launch_t2_rows(int logNp, const float2* u1, float2* T, GridGeom g, const float* dinv,
+                          const float2* tw, hipStream_t st);
+hipError_t launch_t2_cols(int logNp, const float2* T, float2* V, GridGeom g, Spectral sp,
+                          const float2* tw, hipStream_t st);
+hipError_t launch_t2_rows_inv(int logNp, const float2* V, float2* fine, GridGeom g, const float2* tw,
+                              hipStream_t st);
+
+hipError_t launch_transfer_table(const GridGeom& g, const Spectral& sp, float2* out, hipStream_t st);
+hipError_t launch_fresnel_axis(int Np, double g, double two_lam_z, double o, double2 amp,
+                               float2* out, hipStream_t st);
+hipError_t launch_fft_rows(int logn, int64_t batch, int sign, const float2* in, float2* out,
+                           const float2* tw, hipStream_t st);
+
+// Twiddle tables: for length n = 2^logn (1 <= logn <= kMaxLogN) the table
+// tw[m] = exp(-2 pi i m / n), m < n, starts at element n of one buffer.
+constexpr int kMaxLogN = 14;
+__host__ __device__ inline const float2* tw_for(const float2* all, int logn) { return all + (1 << logn); }
+
+}  // namespace nuasm

@@ -1,0 +1,692 @@
+// Host side of libnuasm: parameter validation, plan tables, workspace, and
+// the C-ABI entry points declared in include/nuasm.h.  Every step of the
+// operators runs in the gfx950 kernels of k_fft.hip and k_points.hip; the
+// host only derives sizes and constants, builds the small float64 plan tables
+// and enqueues launches on the plan's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "launch.h"
+#include "nuasm.h"
+
+using namespace nuasm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+nuasm_status fail(nuasm_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+nuasm_status hip_fail(hipError_t e, const char* what) {
+  std::string m = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return fail(NUASM_ERR_ALLOC, m);
+  return fail(NUASM_ERR_HIP, m);
+}
+
+#define HIP_TRY(expr, what)                     \
+  do {                                          \
+    hipError_t e_ = (expr);                     \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+// ------------------------------------------------------- twiddle tables
+// One table per device: for n = 2^l, tw[n + m] = exp(-2 pi i m / n).
+std::mutex g_tw_mutex;
+float2* g_tw[64] = {nullptr};
+
+nuasm_status twiddles_for_device(int dev, const float2** out) {
+  std::lock_guard<std::mutex> lk(g_tw_mutex);
+  if (dev < 0 || dev >= 64) return fail(NUASM_ERR_UNSUPPORTED, "device ordinal >= 64");
+  if (!g_tw[dev]) {
+    const int total = 2 << kMaxLogN;
+    std::vector<float2> h(total);
+    h[0] = make_float2(0.f, 0.f);
+    h[1] = make_float2(0.f, 0.f);
+    for (int l = 1; l <= kMaxLogN; ++l) {
+      const int n = 1 << l;
+      for (int m = 0; m < n; ++m) {
+        const double a = -2.0 * kPi * (double)m / (double)n;
+        h[n + m] = make_float2((float)std::cos(a), (float)std::sin(a));
+      }
+    }
+    float2* d = nullptr;
+    HIP_TRY(hipMalloc(&d, sizeof(float2) * total), "hipMalloc(twiddles)");
+    hipError_t e = hipMemcpy(d, h.data(), sizeof(float2) * total, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(d);
+      return hip_fail(e, "hipMemcpy(twiddles)");
+    }
+    g_tw[dev] = d;
+  }
+  *out = g_tw[dev];
+  return NUASM_OK;
+}
+
+// ------------------------------------------------------ kernel transform
+// Gauss-Legendre nodes/weights on [-1, 1] by Newton iteration on P_n.
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.resize(n);
+  w.resize(n);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(kPi * (i + 0.75) / (n + 0.5));
+    double dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= n; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = n * (z * p1 - p0) / (z * z - 1.0);
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+// 1 / psihat(k) for k in K, where psihat(k) = int psi(d) exp(-2 pi i k d / nf) dd
+// over |d| <= w/2 (psi even, so a cosine transform), by Gauss-Legendre.
+std::vector<float> deconvolution_table(int Np, int nf, int w, double beta) {
+  std::vector<double> gx, gw;
+  gauss_legendre(64, gx, gw);
+  const double half = 0.5 * w;
+  std::vector<float> out(Np);
+  for (int a = 0; a < Np; ++a) {
+    const int k = a - Np / 2;
+    double s = 0.0;
+    for (size_t i = 0; i < gx.size(); ++i) {
+      const double d = 0.5 * (gx[i] + 1.0) * half;  // [0, w/2]
+      const double t = d / half;
+      const double psi = std::exp(beta * (std::sqrt(std::max(0.0, 1.0 - t * t)) - 1.0));
+      s += gw[i] * 0.5 * half * psi * std::cos(2.0 * kPi * k * d / nf);
+    }
+    out[a] = (float)(1.0 / (2.0 * s));
+  }
+  return out;
+}
+
+// --------------------------------------------------------------- Eq. 4 band
+// Per axis, frequencies whose transfer-function phase has local spatial
+// frequency within the window: |o - z f / sqrt(1/l^2 - f^2)| <= S, S = N g.
+// Inverting u = z f / s(f): f = sign(z) u / (l sqrt(z^2 + u^2)).
+void band_axis(double lam, double z, double o, double S, double df, int Np, int* lo, int* hi) {
+  const int kmin = -Np / 2, kmax = Np / 2 - 1;
+  if (z == 0.0) {
+    if (std::fabs(o) <= S) {
+      *lo = kmin;
+      *hi = kmax;
+    } else {
+      *lo = 1;
+      *hi = 0;
+    }
+    return;
+  }
+  auto gam = [&](double t) { return t / (lam * std::sqrt(z * z + t * t)); };
+  double flo, fhi;
+  if (z > 0.0) {
+    flo = gam(o - S);
+    fhi = gam(o + S);
+  } else {
+    flo = -gam(o + S);
+    fhi = -gam(o - S);
+  }
+  const double klo = std::ceil(flo / df), khi = std::floor(fhi / df);
+  *lo = (int)std::max<double>(klo, kmin);
+  *hi = (int)std::min<double>(khi, kmax);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------- plan
+struct nuasm_plan_s {
+  nuasm_params p{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int logNp = 0;
+  int w = 0;
+  float beta = 0.f;
+  GridGeom geom{};
+  BinGeom bgeom{};
+  Spectral spec{};
+  int T = 0, TX = 0;
+  const float2* tw = nullptr;
+  // device memory
+  float2* gridA = nullptr;
+  float2* gridB = nullptr;
+  float* dinv = nullptr;
+  float2* fre = nullptr;  // [2][Np]
+  int* counts = nullptr;
+  int* cursor = nullptr;
+  int* sp_first = nullptr;
+  int* sp_n = nullptr;
+  int* multi = nullptr;
+  int* nch = nullptr;     // [4] + bad counter at [4]
+  int4* sp_chunks = nullptr;
+  int4* ip_chunks = nullptr;
+  int64_t chunk_cap = 0;
+  BinRec* recs = nullptr;
+  int64_t rec_cap = 0;    // points the record buffer is sized for
+  float2* scratch = nullptr;
+  int64_t scratch_chunks = 0;
+  int* host_stat = nullptr;  // pinned [5]
+  size_t bytes = 0;
+  // state
+  int64_t M = 0;
+  bool ready = false;
+  bool synced = false;
+  int exact_sp = 0, exact_ip = 0, exact_multi = 0;
+  int64_t grid_elems = 0;
+};
+
+namespace {
+
+template <typename T>
+hipError_t dalloc(nuasm_plan_s* pl, T** p, size_t n) {
+  hipError_t e = hipMalloc((void**)p, sizeof(T) * std::max<size_t>(n, 1));
+  if (e == hipSuccess) pl->bytes += sizeof(T) * std::max<size_t>(n, 1);
+  return e;
+}
+
+void release(nuasm_plan_s* pl) {
+  auto f = [](void* p) {
+    if (p) (void)hipFree(p);
+  };
+  f(pl->gridA);
+  f(pl->gridB);
+  f(pl->dinv);
+  f(pl->fre);
+  f(pl->counts);
+  f(pl->cursor);
+  f(pl->sp_first);
+  f(pl->sp_n);
+  f(pl->multi);
+  f(pl->nch);
+  f(pl->sp_chunks);
+  f(pl->ip_chunks);
+  f(pl->recs);
+  f(pl->scratch);
+  if (pl->host_stat) (void)hipHostFree(pl->host_stat);
+}
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+nuasm_status validate(const nuasm_params* p) {
+  if (!p) return fail(NUASM_ERR_INVALID_ARG, "params is NULL");
+  if (p->type != NUASM_TYPE_1 && p->type != NUASM_TYPE_2) return fail(NUASM_ERR_INVALID_ARG, "type must be 1 or 2");
+  if (p->tf != NUASM_TF_ASM && p->tf != NUASM_TF_FRESNEL) return fail(NUASM_ERR_INVALID_ARG, "tf must be ASM or FRESNEL");
+  if (p->band < NUASM_BAND_FULL || p->band > NUASM_BAND_EXPLICIT) return fail(NUASM_ERR_INVALID_ARG, "bad band mode");
+  if (p->phase_fp64 != 0 && p->phase_fp64 != 1) return fail(NUASM_ERR_INVALID_ARG, "phase_fp64 must be 0 or 1");
+  if (!is_pow2(p->N) || p->N < 16 || p->N > 4096)
+    return fail(NUASM_ERR_UNSUPPORTED, "N must be a power of two in [16, 4096]");
+  if (!(p->lambda > 0.0) || !std::isfinite(p->lambda)) return fail(NUASM_ERR_INVALID_ARG, "lambda must be > 0");
+  if (!std::isfinite(p->z)) return fail(NUASM_ERR_INVALID_ARG, "z must be finite");
+  if (!std::isfinite(p->ox) || !std::isfinite(p->oy)) return fail(NUASM_ERR_INVALID_ARG, "offset must be finite");
+  const double g = p->type == NUASM_TYPE_1 ? p->d2 : p->d1;
+  if (!(g > 0.0) || !std::isfinite(g)) return fail(NUASM_ERR_INVALID_ARG, "pitch of the uniform plane must be > 0");
+  if (p->tf == NUASM_TF_FRESNEL && p->z == 0.0) return fail(NUASM_ERR_INVALID_ARG, "Fresnel needs z != 0");
+  if (!(p->tol >= 1e-12 && p->tol <= 1e-2)) return fail(NUASM_ERR_INVALID_ARG, "tol must be in [1e-12, 1e-2]");
+  if (p->flags & ~(NUASM_OUT_CROP_N | NUASM_DEFER_RANGE_CHECK)) return fail(NUASM_ERR_INVALID_ARG, "unknown flag bits");
+  if (p->reserved != 0) return fail(NUASM_ERR_INVALID_ARG, "reserved must be 0");
+  if (p->band == NUASM_BAND_EXPLICIT) {
+    for (int i = 0; i < 2; ++i)
+      if (!std::isfinite(p->band_c[i]) || !(p->band_w[i] >= 0.0))
+        return fail(NUASM_ERR_INVALID_ARG, "explicit band needs finite centre and width >= 0");
+  }
+  return NUASM_OK;
+}
+
+nuasm_status ensure_points_capacity(nuasm_plan_s* pl, int64_t M) {
+  if (M <= pl->rec_cap && pl->recs) return NUASM_OK;
+  const int64_t cap = std::max<int64_t>(M, 1024);
+  if (cap * 4 > (int64_t)INT32_MAX) return fail(NUASM_ERR_UNSUPPORTED, "too many points (4 M must fit in int32)");
+  HIP_TRY(hipStreamSynchronize(pl->stream), "hipStreamSynchronize");
+  if (pl->recs) {
+    (void)hipFree(pl->recs);
+    pl->bytes -= sizeof(BinRec) * 4 * pl->rec_cap;
+    pl->recs = nullptr;
+  }
+  if (pl->sp_chunks) {
+    (void)hipFree(pl->sp_chunks);
+    (void)hipFree(pl->ip_chunks);
+    pl->bytes -= 2 * sizeof(int4) * pl->chunk_cap;
+    pl->sp_chunks = pl->ip_chunks = nullptr;
+  }
+  if (pl->scratch) {
+    (void)hipFree(pl->scratch);
+    pl->bytes -= sizeof(float2) * kTile * kTile * pl->scratch_chunks;
+    pl->scratch = nullptr;
+    pl->scratch_chunks = 0;
+  }
+  pl->rec_cap = 0;
+  HIP_TRY(dalloc(pl, &pl->recs, (size_t)(4 * cap)), "hipMalloc(records)");
+  pl->chunk_cap = pl->T + (4 * cap) / kChunk + 1;
+  HIP_TRY(dalloc(pl, &pl->sp_chunks, (size_t)pl->chunk_cap), "hipMalloc(chunks)");
+  HIP_TRY(dalloc(pl, &pl->ip_chunks, (size_t)pl->chunk_cap), "hipMalloc(chunks)");
+  pl->rec_cap = cap;
+  return NUASM_OK;
+}
+
+nuasm_status ensure_scratch(nuasm_plan_s* pl) {
+  if (pl->scratch) return NUASM_OK;
+  HIP_TRY(dalloc(pl, &pl->scratch, (size_t)pl->chunk_cap * kTile * kTile), "hipMalloc(spread scratch)");
+  pl->scratch_chunks = pl->chunk_cap;
+  return NUASM_OK;
+}
+
+int sp_grid(const nuasm_plan_s* pl) {
+  return pl->synced ? pl->exact_sp : (int)std::min<int64_t>(pl->chunk_cap, pl->T + (4 * pl->M) / kChunk + 1);
+}
+int ip_grid(const nuasm_plan_s* pl) {
+  return pl->synced ? pl->exact_ip : (int)std::min<int64_t>(pl->chunk_cap, pl->T + (4 * pl->M) / kChunk + 1);
+}
+int multi_grid(const nuasm_plan_s* pl) {
+  return pl->synced ? pl->exact_multi : (int)std::min<int64_t>(pl->T, (4 * pl->M) / kChunk + 1);
+}
+
+// type-1 pipeline: values at the points -> N' x N' (or N x N) plane
+nuasm_status run_type1_pipeline(nuasm_plan_s* pl, const float2* vals, float2* out, bool conj, bool crop) {
+  hipStream_t st = pl->stream;
+  nuasm_status s = ensure_scratch(pl);
+  if (s != NUASM_OK) return s;
+  SpreadArgs sa{};
+  sa.recs = pl->recs;
+  sa.chunks = pl->sp_chunks;
+  sa.nchunks = pl->nch + 0;
+  sa.scratch = pl->scratch;
+  sa.vals = vals;
+  sa.grid = pl->gridA;
+  sa.L = pl->geom.L;
+  sa.TX = pl->TX;
+  sa.two_over_w = 2.0f / (float)pl->w;
+  sa.beta = pl->beta;
+  HIP_TRY(launch_spread(pl->w, sa, sp_grid(pl), st), "launch spread");
+  SpreadReduceArgs ra{};
+  ra.multi = pl->multi;
+  ra.nmulti = pl->nch + 3;
+  ra.bin_chunk0 = pl->sp_first;
+  ra.bin_nchunk = pl->sp_n;
+  ra.scratch = pl->scratch;
+  ra.grid = pl->gridA;
+  ra.L = pl->geom.L;
+  ra.TX = pl->TX;
+  HIP_TRY(launch_spread_reduce(ra, multi_grid(pl), st), "launch spread_reduce");
+  GridGeom g = pl->geom;
+  g.crop = crop ? 1 : 0;
+  Spectral sp = pl->spec;
+  sp.conj = conj ? 1 : 0;
+  HIP_TRY(launch_t1_rows(pl->logNp, pl->gridA, pl->gridB, g, pl->dinv, pl->tw, st), "launch t1_rows");
+  HIP_TRY(launch_t1_cols(pl->logNp, pl->gridB, pl->gridA, g, sp, pl->tw, st), "launch t1_cols");
+  HIP_TRY(launch_t1_rows_inv(pl->logNp, pl->gridA, out, g, pl->tw, st), "launch t1_rows_inv");
+  return NUASM_OK;
+}
+
+// type-2 pipeline: Nin x Nin plane -> values at the points
+nuasm_status run_type2_pipeline(nuasm_plan_s* pl, const float2* plane, int Nin, float2* out, bool conj) {
+  hipStream_t st = pl->stream;
+  GridGeom g = pl->geom;
+  g.Nin = Nin;
+  g.crop = 0;
+  Spectral sp = pl->spec;
+  sp.conj = conj ? 1 : 0;
+  HIP_TRY(launch_t2_rows(pl->logNp, plane, pl->gridB, g, pl->dinv, pl->tw, st), "launch t2_rows");
+  HIP_TRY(launch_t2_cols(pl->logNp, pl->gridB, pl->gridA, g, sp, pl->tw, st), "launch t2_cols");
+  HIP_TRY(launch_t2_rows_inv(pl->logNp, pl->gridA, pl->gridB, g, pl->tw, st), "launch t2_rows_inv");
+  if (pl->M > 0) {
+    InterpArgs ia{};
+    ia.recs = pl->recs;
+    ia.chunks = pl->ip_chunks;
+    ia.nchunks = pl->nch + 1;
+    ia.grid = pl->gridB;
+    ia.out = out;
+    ia.L = pl->geom.L;
+    ia.TX = pl->TX;
+    ia.two_over_w = 2.0f / (float)pl->w;
+    ia.beta = pl->beta;
+    HIP_TRY(launch_interp(pl->w, ia, ip_grid(pl), st), "launch interp");
+  }
+  return NUASM_OK;
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+extern "C" {
+
+int32_t nuasm_version(void) { return 100; }
+
+const char* nuasm_status_string(nuasm_status s) {
+  switch (s) {
+    case NUASM_OK: return "NUASM_OK";
+    case NUASM_ERR_INVALID_ARG: return "NUASM_ERR_INVALID_ARG";
+    case NUASM_ERR_OUT_OF_RANGE: return "NUASM_ERR_OUT_OF_RANGE";
+    case NUASM_ERR_NOT_READY: return "NUASM_ERR_NOT_READY";
+    case NUASM_ERR_UNSUPPORTED: return "NUASM_ERR_UNSUPPORTED";
+    case NUASM_ERR_NO_DEVICE: return "NUASM_ERR_NO_DEVICE";
+    case NUASM_ERR_ALLOC: return "NUASM_ERR_ALLOC";
+    case NUASM_ERR_HIP: return "NUASM_ERR_HIP";
+  }
+  return "NUASM_UNKNOWN_STATUS";
+}
+
+const char* nuasm_last_error(void) { return g_last_error.c_str(); }
+
+nuasm_status nuasm_params_default(nuasm_params* p) {
+  if (!p) return fail(NUASM_ERR_INVALID_ARG, "params is NULL");
+  std::memset(p, 0, sizeof(*p));
+  p->type = NUASM_TYPE_1;
+  p->tf = NUASM_TF_ASM;
+  p->band = NUASM_BAND_FULL;
+  p->phase_fp64 = 1;
+  p->N = 1024;
+  p->lambda = 633e-9;
+  p->z = 0.01;
+  p->d1 = p->d2 = 4e-6;
+  p->tol = 1e-6;
+  return NUASM_OK;
+}
+
+nuasm_status nuasm_plan_create(const nuasm_params* p, void* hip_stream, nuasm_plan* out) {
+  if (!out) return fail(NUASM_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  nuasm_status s = validate(p);
+  if (s != NUASM_OK) return s;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    return fail(NUASM_ERR_NO_DEVICE, "no HIP device visible");
+  }
+  nuasm_plan_s* pl = new (std::nothrow) nuasm_plan_s();
+  if (!pl) return fail(NUASM_ERR_ALLOC, "host allocation failed");
+  pl->p = *p;
+  pl->stream = (hipStream_t)hip_stream;
+  auto bail = [&](nuasm_status st) {
+    release(pl);
+    delete pl;
+    return st;
+  };
+  if (hipGetDevice(&pl->device) != hipSuccess) return bail(fail(NUASM_ERR_HIP, "hipGetDevice failed"));
+  const int N = (int)p->N, Np = 2 * N, nf = 2 * Np;
+  int logNp = 0;
+  while ((1 << logNp) < Np) ++logNp;
+  pl->logNp = logNp;
+  const double g = p->type == NUASM_TYPE_1 ? p->d2 : p->d1;
+  const double df = 1.0 / (Np * g);
+  // kernel width from the tolerance: w = ceil(log10(1/tol)) + 1, beta = 2.30 w
+  int w = (int)std::ceil(-std::log10(p->tol) - 1e-9) + 1;
+  w = std::max(2, std::min(kMaxW, w));
+  pl->w = w;
+  pl->beta = (float)(2.30 * w);
+  const int L = Np + 2 * kPad;
+  pl->TX = (L + kTile - 1) / kTile;
+  pl->T = pl->TX * pl->TX;
+
+  GridGeom& G = pl->geom;
+  G.N = N;
+  G.Np = Np;
+  G.nf = nf;
+  G.L = L;
+  G.s0 = Np / 2 - kPad;
+  G.Nin = N;
+  G.crop = (p->flags & NUASM_OUT_CROP_N) ? 1 : 0;
+  const int kmin = -Np / 2, kmax = Np / 2 - 1;
+  G.kxlo = G.kylo = kmin;
+  G.kxhi = G.kyhi = kmax;
+  if (p->tf == NUASM_TF_ASM && p->band == NUASM_BAND_LIMITED) {
+    band_axis(p->lambda, p->z, p->ox, N * g, df, Np, &G.kxlo, &G.kxhi);
+    band_axis(p->lambda, p->z, p->oy, N * g, df, Np, &G.kylo, &G.kyhi);
+  } else if (p->tf == NUASM_TF_ASM && p->band == NUASM_BAND_EXPLICIT) {
+    int b[4];
+    for (int i = 0; i < 2; ++i) {
+      b[2 * i] = (int)std::max<double>(std::ceil(p->band_c[i] - 0.5 * p->band_w[i]), kmin);
+      b[2 * i + 1] = (int)std::min<double>(std::floor(p->band_c[i] + 0.5 * p->band_w[i]), kmax);
+    }
+    G.kxlo = b[0];
+    G.kxhi = b[1];
+    G.kylo = b[2];
+    G.kyhi = b[3];
+  }
+
+  BinGeom& B = pl->bgeom;
+  B.N = N;
+  B.inv_g = 1.0 / g;
+  B.half_n = 0.5 * N;
+  B.tau0 = (double)(N + kPad);
+  B.w = w;
+  B.L = L;
+  B.TX = pl->TX;
+
+  Spectral& S = pl->spec;
+  S.tf = p->tf == NUASM_TF_FRESNEL ? 1 : 0;
+  S.phase_fp64 = p->phase_fp64;
+  S.conj = 0;
+  S.scale = (float)(1.0 / ((double)Np * (double)Np));
+  {
+    const double zl = p->z / p->lambda;
+    S.c0 = zl - std::nearbyint(zl);
+    S.ax = df * p->ox;
+    S.ay = df * p->oy;
+    S.q = df * df;
+    S.zq = p->z * df * df;
+    S.inv_lam = 1.0 / p->lambda;
+    S.inv_lam2 = 1.0 / (p->lambda * p->lambda);
+    S.axf = (float)S.ax;
+    S.ayf = (float)S.ay;
+    S.qf = (float)S.q;
+    S.zf = (float)p->z;
+    S.inv_lam2f = (float)S.inv_lam2;
+  }
+
+  s = twiddles_for_device(pl->device, &pl->tw);
+  if (s != NUASM_OK) return bail(s);
+  pl->grid_elems = (int64_t)L * L;
+  hipError_t e;
+  if ((e = dalloc(pl, &pl->gridA, (size_t)pl->grid_elems)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(gridA)"));
+  if ((e = dalloc(pl, &pl->gridB, (size_t)pl->grid_elems)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(gridB)"));
+  if ((e = dalloc(pl, &pl->dinv, (size_t)Np)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(dinv)"));
+  if ((e = dalloc(pl, &pl->counts, (size_t)pl->T)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(bins)"));
+  if ((e = dalloc(pl, &pl->cursor, (size_t)pl->T)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(bins)"));
+  if ((e = dalloc(pl, &pl->sp_first, (size_t)pl->T)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(bins)"));
+  if ((e = dalloc(pl, &pl->sp_n, (size_t)pl->T)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(bins)"));
+  if ((e = dalloc(pl, &pl->multi, (size_t)pl->T)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(bins)"));
+  if ((e = dalloc(pl, &pl->nch, (size_t)8)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(counters)"));
+  if ((e = hipHostMalloc((void**)&pl->host_stat, sizeof(int) * 8, hipHostMallocDefault)) != hipSuccess)
+    return bail(hip_fail(e, "hipHostMalloc(status)"));
+  {
+    std::vector<float> dv = deconvolution_table(Np, nf, w, (double)pl->beta);
+    if ((e = hipMemcpyAsync(pl->dinv, dv.data(), sizeof(float) * Np, hipMemcpyHostToDevice, pl->stream)) != hipSuccess)
+      return bail(hip_fail(e, "hipMemcpy(dinv)"));
+    if ((e = hipStreamSynchronize(pl->stream)) != hipSuccess) return bail(hip_fail(e, "hipStreamSynchronize"));
+  }
+  S.dinv = pl->dinv;
+  if (S.tf == 1) {
+    if ((e = dalloc(pl, &pl->fre, (size_t)2 * Np)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(fresnel)"));
+    // A = g^2 exp(2 pi i z/l) / (i l z), folded into the x table
+    const double cyc = S.c0;
+    const double mag = g * g / (p->lambda * p->z);
+    const double cr = std::cos(2.0 * kPi * cyc), ci = std::sin(2.0 * kPi * cyc);
+    const double2 A = make_double2(mag * ci, -mag * cr);  // (cr + i ci) * mag / i
+    const double2 one = make_double2(1.0, 0.0);
+    const double two_lam_z = 2.0 * p->lambda * p->z;
+    if ((e = launch_fresnel_axis(Np, g, two_lam_z, p->ox, A, pl->fre, pl->stream)) != hipSuccess)
+      return bail(hip_fail(e, "launch fresnel_axis"));
+    if ((e = launch_fresnel_axis(Np, g, two_lam_z, p->oy, one, pl->fre + Np, pl->stream)) != hipSuccess)
+      return bail(hip_fail(e, "launch fresnel_axis"));
+    S.fre_x = pl->fre;
+    S.fre_y = pl->fre + Np;
+  }
+  if ((e = launch_fill_i32(pl->nch, 0, 8, pl->stream)) != hipSuccess) return bail(hip_fail(e, "launch fill"));
+  *out = pl;
+  return NUASM_OK;
+}
+
+nuasm_status nuasm_plan_destroy(nuasm_plan pl) {
+  if (!pl) return NUASM_OK;
+  (void)hipStreamSynchronize(pl->stream);
+  release(pl);
+  delete pl;
+  return NUASM_OK;
+}
+
+nuasm_status nuasm_plan_set_stream(nuasm_plan pl, void* hip_stream) {
+  if (!pl) return fail(NUASM_ERR_INVALID_ARG, "plan is NULL");
+  pl->stream = (hipStream_t)hip_stream;
+  return NUASM_OK;
+}
+
+nuasm_status nuasm_plan_get_info(nuasm_plan pl, nuasm_plan_info* info) {
+  if (!pl || !info) return fail(NUASM_ERR_INVALID_ARG, "plan or info is NULL");
+  std::memset(info, 0, sizeof(*info));
+  info->N = pl->geom.N;
+  info->Np = pl->geom.Np;
+  info->nf = pl->geom.nf;
+  info->L = pl->geom.L;
+  info->w = pl->w;
+  info->beta = pl->beta;
+  info->tile = kTile;
+  info->tiles = pl->T;
+  info->kx_lo = pl->geom.kxlo;
+  info->kx_hi = pl->geom.kxhi;
+  info->ky_lo = pl->geom.kylo;
+  info->ky_hi = pl->geom.kyhi;
+  const int64_t plane = pl->geom.crop ? (int64_t)pl->geom.N * pl->geom.N : (int64_t)pl->geom.Np * pl->geom.Np;
+  if (pl->p.type == NUASM_TYPE_1) {
+    info->in_elems = pl->M;
+    info->out_elems = plane;
+  } else {
+    info->in_elems = (int64_t)pl->geom.N * pl->geom.N;
+    info->out_elems = pl->M;
+  }
+  info->M = pl->M;
+  info->device_bytes = pl->bytes;
+  return NUASM_OK;
+}
+
+nuasm_status nuasm_set_points(nuasm_plan pl, int64_t M, const double* x, const double* y) {
+  if (!pl) return fail(NUASM_ERR_INVALID_ARG, "plan is NULL");
+  if (M < 0) return fail(NUASM_ERR_INVALID_ARG, "M < 0");
+  if (M > 0 && (!x || !y)) return fail(NUASM_ERR_INVALID_ARG, "coordinate pointer is NULL");
+  pl->ready = false;
+  nuasm_status s = ensure_points_capacity(pl, M);
+  if (s != NUASM_OK) return s;
+  hipStream_t st = pl->stream;
+  HIP_TRY(launch_fill_i32(pl->counts, 0, pl->T, st), "launch fill");
+  HIP_TRY(launch_fill_i32(pl->nch, 0, 8, st), "launch fill");
+  HIP_TRY(launch_bin_count(x, y, M, pl->bgeom, pl->counts, pl->nch + 4, st), "launch bin_count");
+  HIP_TRY(launch_bin_scan(pl->counts, pl->T, pl->cursor, pl->sp_chunks, pl->sp_first, pl->sp_n, pl->multi,
+                          pl->ip_chunks, pl->nch, st),
+          "launch bin_scan");
+  HIP_TRY(launch_bin_scatter(x, y, M, pl->bgeom, pl->cursor, pl->recs, st), "launch bin_scatter");
+  pl->M = M;
+  pl->synced = false;
+  if (pl->p.flags & NUASM_DEFER_RANGE_CHECK) {
+    pl->ready = true;
+    return NUASM_OK;
+  }
+  HIP_TRY(hipMemcpyAsync(pl->host_stat, pl->nch, sizeof(int) * 5, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+  HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+  if (pl->host_stat[4] != 0) {
+    char buf[128];
+    std::snprintf(buf, sizeof(buf), "%d point(s) outside the window [-N g/2, N g/2]^2 or not finite",
+                  pl->host_stat[4]);
+    return fail(NUASM_ERR_OUT_OF_RANGE, buf);
+  }
+  pl->exact_sp = pl->host_stat[0];
+  pl->exact_ip = pl->host_stat[1];
+  pl->exact_multi = pl->host_stat[3];
+  pl->synced = true;
+  pl->ready = true;
+  return NUASM_OK;
+}
+
+nuasm_status nuasm_check_points(nuasm_plan pl) {
+  if (!pl) return fail(NUASM_ERR_INVALID_ARG, "plan is NULL");
+  HIP_TRY(hipMemcpyAsync(pl->host_stat, pl->nch, sizeof(int) * 5, hipMemcpyDeviceToHost, pl->stream),
+          "hipMemcpyAsync");
+  HIP_TRY(hipStreamSynchronize(pl->stream), "hipStreamSynchronize");
+  if (pl->host_stat[4] != 0) {
+    pl->ready = false;
+    return fail(NUASM_ERR_OUT_OF_RANGE, "points outside the window in the last set_points");
+  }
+  return NUASM_OK;
+}
+
+nuasm_status nuasm_execute(nuasm_plan pl, const void* in, void* out) {
+  if (!pl) return fail(NUASM_ERR_INVALID_ARG, "plan is NULL");
+  if (!pl->ready) return fail(NUASM_ERR_NOT_READY, "execute before a successful set_points");
+  // the point-side array may be NULL only when there are no points
+  const bool t1 = pl->p.type == NUASM_TYPE_1;
+  const void* pts = t1 ? in : out;
+  const void* plane = t1 ? out : in;
+  if (!plane || (!pts && pl->M > 0)) return fail(NUASM_ERR_INVALID_ARG, "in/out pointer is NULL");
+  if (t1) return run_type1_pipeline(pl, (const float2*)in, (float2*)out, false, pl->geom.crop != 0);
+  if (pl->M == 0) return NUASM_OK;
+  return run_type2_pipeline(pl, (const float2*)in, pl->geom.N, (float2*)out, false);
+}
+
+nuasm_status nuasm_execute_adjoint(nuasm_plan pl, const void* in, void* out) {
+  if (!pl) return fail(NUASM_ERR_INVALID_ARG, "plan is NULL");
+  if (!pl->ready) return fail(NUASM_ERR_NOT_READY, "execute before a successful set_points");
+  const bool t1 = pl->p.type == NUASM_TYPE_1;
+  const void* pts = t1 ? out : in;
+  const void* plane = t1 ? in : out;
+  if (!plane || (!pts && pl->M > 0)) return fail(NUASM_ERR_INVALID_ARG, "in/out pointer is NULL");
+  if (t1) {
+    if (pl->geom.crop) return fail(NUASM_ERR_UNSUPPORTED, "adjoint of a cropped type-1 plan");
+    if (pl->M == 0) return NUASM_OK;
+    return run_type2_pipeline(pl, (const float2*)in, pl->geom.Np, (float2*)out, true);
+  }
+  return run_type1_pipeline(pl, (const float2*)in, (float2*)out, true, true);
+}
+
+nuasm_status nuasm_debug_transfer(nuasm_plan pl, void* out) {
+  if (!pl || !out) return fail(NUASM_ERR_INVALID_ARG, "plan or out is NULL");
+  HIP_TRY(launch_transfer_table(pl->geom, pl->spec, (float2*)out, pl->stream), "launch transfer_table");
+  return NUASM_OK;
+}
+
+nuasm_status nuasm_debug_fft(int64_t n, int64_t batch, int32_t sign, const void* in, void* out, void* stream) {
+  if (!is_pow2(n) || n < 32 || n > (1 << kMaxLogN)) return fail(NUASM_ERR_UNSUPPORTED, "n must be 2^5..2^14");
+  if (batch < 0 || (sign != -1 && sign != 1)) return fail(NUASM_ERR_INVALID_ARG, "bad batch or sign");
+  if (batch == 0) return NUASM_OK;
+  if (!in || !out) return fail(NUASM_ERR_INVALID_ARG, "in/out pointer is NULL");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    return fail(NUASM_ERR_NO_DEVICE, "no HIP device visible");
+  }
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  const float2* tw = nullptr;
+  nuasm_status s = twiddles_for_device(dev, &tw);
+  if (s != NUASM_OK) return s;
+  int logn = 0;
+  while ((int64_t(1) << logn) < n) ++logn;
+  HIP_TRY(launch_fft_rows(logn, batch, sign, (const float2*)in, (float2*)out, tw, (hipStream_t)stream),
+          "launch fft_rows");
+  return NUASM_OK;
+}
+
+}  // extern "C"
