@@ -1,0 +1,237 @@
+#!/usr/bin/env python3
+"""Throughput of the non-uniform diffraction hot path on one MI355X.
+
+Workload (N' = 2048, M = 2^20): NU-ASM_1 and NU-ASM_2 on a 1024 x 1024 plane
+of pitch 4 um, wavelength 633 nm, off-axis offset o = (1 mm, 0), kernel
+tolerance 1e-6, clustered point sets (70 % in a Gaussian of sigma = 0.1 W at
+the centre, 30 % uniform), for z in {0.01, 0.1, 0.5} m and both the
+band-limited ASM (Eq. 4) and the Fresnel (Eq. 5) transfer functions: 12 runs.
+One step runs all 12 one-shot (binning of the points + operator) on inputs
+already resident in HBM.  value = 12 M / step time, in non-uniform points/s.
+
+Prints one JSON line.  The per-kernel roofline figure comes from HIP events
+the library records around every launch during a second, separately timed
+pass; the CPU baseline is the FP64 oracle on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "non-uniform pts/sec NUASM_1/2 at N'=2048, M=1M, rel-L2≤1e-5; % HBM roofline"
+HBM_PEAK_GBS = 8000.0
+N, G, LAM, OX, OY, TOL = 1024, 4e-6, 633e-9, 1e-3, 0.0, 1e-6
+ZS = (0.01, 0.1, 0.5)
+TFS = (("asm", "limited"), ("fresnel", "full"))
+M = 1 << 20
+
+
+def stage_bytes(stage: str, info: dict) -> float:
+    """Algorithmic (compulsory) HBM bytes of one launch of a stage: every
+    input the stage needs read once, every output written once.  Nb is the
+    number of in-band x-frequencies (the Rect of Eq. 4 lets the grid passes
+    skip the others)."""
+    n, np_, L, m = info["N"], info["Np"], info["L"], info["M"]
+    nb = max(0, min(info["kx_hi"], np_ // 2 - 1) - max(info["kx_lo"], -np_ // 2) + 1)
+    c = 8.0  # complex64
+    return {
+        "bin": 16.0 * m + 16.0 * m,                  # coordinates in, one record out
+        "spread": 16.0 * m + c * m + c * L * L,      # records + values in, support grid out
+        "t1_rows": c * L * L + c * L * nb,
+        "t1_cols": c * L * nb + c * np_ * nb,
+        "t1_rows_inv": c * np_ * nb + c * np_ * np_,
+        "t2_rows": c * n * n + c * n * nb,
+        "t2_cols": c * n * nb + c * L * nb,
+        "t2_rows_inv": c * L * nb + c * L * L,
+        "interp": c * L * L + 16.0 * m + c * m,      # grid + records in, values out
+    }[stage]
+
+
+def make_inputs(torch, synth):
+    import numpy as np
+    W = N * G
+    r1 = synth.rng_for(2, 0)
+    x1, y1 = synth.clustered_box(r1, M, W)
+    c1 = synth.unit_phase(r1, M)
+    r2 = synth.rng_for(2, 1)
+    x2, y2 = synth.clustered_box(r2, M, W)
+    u1 = synth.unit_phase(r2, (N, N))
+    host = dict(x1=x1, y1=y1, c1=c1, x2=x2, y2=y2, u1=u1)
+    d = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in host.items()}
+    return host, d
+
+
+def cpu_baseline(host, n1=16384, n2=16384):
+    """The FP64 oracle as it stands, timed on this host: NU-ASM_1 on the first
+    n1 source points and NU-ASM_2 on the first n2 destination points of the
+    same workload at z = 0.1 m, band-limited ASM (transfer function included)."""
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    geo = O.Geometry(N=N, g=G, lam=LAM, z=0.1, ox=OX, oy=OY, tf="asm", band="limited")
+    t0 = time.perf_counter()
+    H = O.transfer(geo)
+    O.nuasm1(geo, host["x1"][:n1], host["y1"][:n1], host["c1"][:n1], H)
+    O.nuasm2(geo, host["u1"], host["x2"][:n2], host["y2"][:n2], H)
+    dt = time.perf_counter() - t0
+    return {"value": (n1 + n2) / dt, "unit": "points/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"FP64 direct-sum oracle, z=0.1 m band-limited ASM, N'=2048: NU-ASM_1 on "
+                      f"{n1} source points + NU-ASM_2 on {n2} destination points, {dt:.1f} s wall",
+            "seconds": dt}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--profile-steps", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    a = ap.parse_args(argv)
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {a.gpus}). "
+              "Run with --gpus 1.", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_1308_6644_amd as P
+    import synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    torch.cuda.set_device(0)
+    P.load()
+    print(f"[bench] generating inputs N={N} M={M}", file=sys.stderr, flush=True)
+    host, d = make_inputs(torch, synth)
+
+    runs = []
+    for z in ZS:
+        for tf, band in TFS:
+            for t in (1, 2):
+                plan = P.Plan(N, t, LAM, z, G, tf=tf, band=band, ox=OX, oy=OY, tol=TOL,
+                              defer_range_check=True)
+                if t == 1:
+                    x, y, inp = d["x1"], d["y1"], d["c1"]
+                    out = torch.empty((2 * N, 2 * N), dtype=torch.complex64, device="cuda")
+                else:
+                    x, y, inp = d["x2"], d["y2"], d["u1"]
+                    out = torch.empty((M,), dtype=torch.complex64, device="cuda")
+                runs.append(dict(plan=plan, x=x, y=y, inp=inp, out=out, type=t, z=z, tf=tf))
+
+    def step():
+        for r in runs:
+            r["plan"].set_points(r["x"], r["y"])
+            r["plan"].execute(r["inp"], r["out"])
+
+    print(f"[bench] warmup {a.warmup}", file=sys.stderr, flush=True)
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    for r in runs:
+        r["plan"].check_points()  # every point was inside its window
+
+    print(f"[bench] timing {a.steps} steps", file=sys.stderr, flush=True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record()
+    for _ in range(a.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms_per_step = e0.elapsed_time(e1) / a.steps
+    value = len(runs) * M / (ms_per_step * 1e-3)
+
+    # second pass: per-stage HIP events recorded by the library
+    print(f"[bench] per-stage timing {a.profile_steps} steps", file=sys.stderr, flush=True)
+    for r in runs:
+        r["plan"].set_timing(True)
+    for _ in range(a.profile_steps):
+        step()
+    torch.cuda.synchronize()
+    stages = {}
+    per_type_ms = {1: 0.0, 2: 0.0}
+    for r in runs:
+        info = r["plan"].info
+        for st, (ms, n) in r["plan"].read_timing().items():
+            if n == 0:
+                continue
+            s = stages.setdefault(st, {"ms": 0.0, "launches": 0, "bytes": 0.0})
+            s["ms"] += ms
+            s["launches"] += n
+            s["bytes"] += stage_bytes(st, info) * n
+            per_type_ms[r["type"]] += ms
+        r["plan"].set_timing(False)
+    dom = max(stages, key=lambda k: stages[k]["ms"])
+    ds = stages[dom]
+    avg_ms = ds["ms"] / ds["launches"]
+    achieved = ds["bytes"] / (ds["ms"] * 1e-3) / 1e9
+    stage_report = {k: {"avg_us": 1e3 * v["ms"] / v["launches"], "launches_per_step": v["launches"] // a.profile_steps,
+                        "share": v["ms"] / sum(s["ms"] for s in stages.values()),
+                        "GBps": v["bytes"] / (v["ms"] * 1e-3) / 1e9}
+                    for k, v in sorted(stages.items(), key=lambda kv: -kv[1]["ms"])}
+    # whole-path byte model per type (pass-minimal): 64 M + 56 N'^2 and 56 M + 44 N'^2
+    Np = 2 * N
+    nruns = len(runs) // 2
+    path = {}
+    for t, bpp in ((1, 64.0 * M + 56.0 * Np * Np), (2, 56.0 * M + 44.0 * Np * Np)):
+        t_ms = per_type_ms[t] / (a.profile_steps * nruns)
+        path[f"nuasm{t}"] = {"avg_ms": t_ms, "model_bytes": bpp,
+                             "frac": bpp / (t_ms * 1e-3) / (HBM_PEAK_GBS * 1e9)}
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "NU-ASM_1 + NU-ASM_2 one-shot (bin + execute), N=1024 (N'=2048), M=2^20 clustered "
+                        "points per run, pitch 4 um, 633 nm, o=(1 mm, 0), z in {0.01, 0.1, 0.5} m x "
+                        "{band-limited ASM, Fresnel}, tol 1e-6 (w=7), 12 runs per step",
+            "N": N, "Np": Np, "M": M, "runs_per_step": len(runs), "phase": "f64",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": dom,
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "avg_launch_us": avg_ms * 1e3,
+        },
+        "stages": stage_report,
+        "path_model": path,
+        "wall_s_timed": wall,
+    }
+    if not a.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(host)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -19,6 +19,8 @@ __all__ = [
 ]
 
 TYPE_1, TYPE_2 = 1, 2
+STAGES = ("bin", "spread", "t1_rows", "t1_cols", "t1_rows_inv", "t2_rows", "t2_cols",
+          "t2_rows_inv", "interp")
 TF_ASM, TF_FRESNEL = 0, 1
 BAND = {"full": 0, "limited": 1, "explicit": 2}
 TF = {"asm": TF_ASM, "fresnel": TF_FRESNEL}
@@ -75,6 +77,9 @@ _SIGS = {
     "nuasm_execute": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "nuasm_execute_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "nuasm_debug_transfer": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "nuasm_plan_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "nuasm_plan_read_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                              ctypes.POINTER(ctypes.c_int64)]),
     "nuasm_debug_fft": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_void_p]),
 }
@@ -229,6 +234,16 @@ class Plan:
 
     def adjoint(self, inp: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         return self._run(load().nuasm_execute_adjoint, inp, out, adjoint=True)
+
+    def set_timing(self, enable: bool = True):
+        _check(load().nuasm_plan_set_timing(self._h, 1 if enable else 0))
+
+    def read_timing(self) -> dict:
+        """{stage: (milliseconds, launches)} accumulated since the last read."""
+        ms = (ctypes.c_double * len(STAGES))()
+        n = (ctypes.c_int64 * len(STAGES))()
+        _check(load().nuasm_plan_read_timing(self._h, ms, n))
+        return {st: (ms[i], n[i]) for i, st in enumerate(STAGES)}
 
     def transfer(self) -> torch.Tensor:
         """H(k) Rect(k) as the fused spectral kernel applies it, [N'][N']."""

@@ -45,9 +45,31 @@ __device__ __forceinline__ PointCells point_cells(double x, double y, const BinG
   return pc;
 }
 
-__global__ void k_bin_count(const double* __restrict__ x, const double* __restrict__ y, int64_t M,
-                            BinGeom g, int* __restrict__ counts, int* __restrict__ bad) {
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < M; j += (int64_t)gridDim.x * blockDim.x) {
+// Counting sort of (point, bin) pairs without global atomics on hot bins.
+// The points are cut into G contiguous ranges of at most kBinPoints points,
+// one workgroup each.  Pass 1 counts the range's pairs per bin in LDS (two
+// 16-bit counters per word: a range has fewer than 65536 points, and a point
+// adds at most 1 to a bin) and writes its histogram row hist[g][*].  A column
+// scan turns hist into per-(range, bin) offsets; the bin scan adds the bin
+// bases.  Pass 2 re-derives the pairs and ranks them inside (range, bin) with
+// LDS counters, so every slot is written exactly once.
+constexpr int kBinThreads = 512;
+
+__device__ __forceinline__ unsigned lds_bump16(unsigned* sh, int b) {
+  const int sft = (b & 1) * 16;
+  return (atomicAdd(&sh[b >> 1], 1u << sft) >> sft) & 0xffffu;
+}
+
+__global__ void __launch_bounds__(kBinThreads)
+k_bin_hist(const double* __restrict__ x, const double* __restrict__ y, int64_t M, BinGeom g, int ppw,
+           uint16_t* __restrict__ hist, int* __restrict__ bad) {
+  extern __shared__ unsigned sh[];
+  const int T = g.TX * g.TX, TW = (T + 1) / 2;
+  for (int e = threadIdx.x; e < TW; e += kBinThreads) sh[e] = 0u;
+  __syncthreads();
+  const int64_t j0 = (int64_t)blockIdx.x * ppw;
+  const int64_t j1 = min(M, j0 + ppw);
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += kBinThreads) {
     const PointCells pc = point_cells(x[j], y[j], g);
     if (!pc.ok) {
       atomicAdd(bad, 1);
@@ -56,20 +78,65 @@ __global__ void k_bin_count(const double* __restrict__ x, const double* __restri
     const int bx0 = pc.i0x / kTile, bx1 = (pc.i0x + g.w - 1) / kTile;
     const int by0 = pc.i0y / kTile, by1 = (pc.i0y + g.w - 1) / kTile;
     for (int by = by0; by <= by1; ++by)
-      for (int bx = bx0; bx <= bx1; ++bx) atomicAdd(&counts[by * g.TX + bx], 1);
+      for (int bx = bx0; bx <= bx1; ++bx) lds_bump16(sh, by * g.TX + bx);
+  }
+  __syncthreads();
+  uint16_t* row = hist + (size_t)blockIdx.x * T;
+  for (int b = threadIdx.x; b < T; b += kBinThreads) row[b] = (uint16_t)((sh[b >> 1] >> ((b & 1) * 16)) & 0xffffu);
+}
+
+// Column scan: off[g][b] = sum_{g' < g} hist[g'][b], total[b] = sum_g hist[g][b].
+// A workgroup takes 64 consecutive bins (one per lane) and splits the G
+// ranges over its 16 waves.
+constexpr int kColWaves = 16;
+
+__global__ void __launch_bounds__(64 * kColWaves)
+k_bin_colscan(const uint16_t* __restrict__ hist, int G, int T, int* __restrict__ off, int* __restrict__ total) {
+  __shared__ int part[kColWaves][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int b = blockIdx.x * 64 + lane;
+  const int per = (G + kColWaves - 1) / kColWaves;
+  const int g0 = min(G, wv * per), g1 = min(G, g0 + per);
+  int s = 0;
+  if (b < T) {
+#pragma unroll 8
+    for (int gg = g0; gg < g1; ++gg) s += hist[(size_t)gg * T + b];
+  }
+  part[wv][lane] = s;
+  __syncthreads();
+  int base = 0;
+  for (int q = 0; q < wv; ++q) base += part[q][lane];
+  if (b < T) {
+    int run = base;
+#pragma unroll 8
+    for (int gg = g0; gg < g1; ++gg) {
+      const int h = hist[(size_t)gg * T + b];
+      off[(size_t)gg * T + b] = run;
+      run += h;
+    }
+    if (wv == kColWaves - 1) total[b] = run;
   }
 }
 
-__global__ void k_bin_scatter(const double* __restrict__ x, const double* __restrict__ y, int64_t M,
-                              BinGeom g, int* __restrict__ cursor, BinRec* __restrict__ recs) {
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < M; j += (int64_t)gridDim.x * blockDim.x) {
+__global__ void __launch_bounds__(kBinThreads)
+k_bin_scatter(const double* __restrict__ x, const double* __restrict__ y, int64_t M, BinGeom g, int ppw,
+              const int* __restrict__ off, const int* __restrict__ bin_base, BinRec* __restrict__ recs) {
+  extern __shared__ unsigned sh[];
+  const int T = g.TX * g.TX, TW = (T + 1) / 2;
+  for (int e = threadIdx.x; e < TW; e += kBinThreads) sh[e] = 0u;
+  __syncthreads();
+  const int64_t j0 = (int64_t)blockIdx.x * ppw;
+  const int64_t j1 = min(M, j0 + ppw);
+  const int* myoff = off + (size_t)blockIdx.x * T;
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += kBinThreads) {
     const PointCells pc = point_cells(x[j], y[j], g);
     if (!pc.ok) continue;
     const int bx0 = pc.i0x / kTile, bx1 = (pc.i0x + g.w - 1) / kTile;
     const int by0 = pc.i0y / kTile, by1 = (pc.i0y + g.w - 1) / kTile;
     for (int by = by0; by <= by1; ++by)
       for (int bx = bx0; bx <= bx1; ++bx) {
-        const int slot = atomicAdd(&cursor[by * g.TX + bx], 1);
+        const int b = by * g.TX + bx;
+        const int slot = bin_base[b] + myoff[b] + (int)lds_bump16(sh, b);
         const int lx = pc.i0x - bx * kTile, ly = pc.i0y - by * kTile;
         BinRec r;
         r.packed = (lx & 0xff) | ((ly & 0xff) << 8) | ((bx == bx0 && by == by0) ? (1 << 16) : 0);
@@ -81,8 +148,8 @@ __global__ void k_bin_scatter(const double* __restrict__ x, const double* __rest
   }
 }
 
-// Single-workgroup scan over the bins: record offsets (written to `cursor`,
-// which the scatter then advances), and the chunk tables.  Spreading needs a
+// Single-workgroup scan over the bins: first record of every bin (written to
+// `cursor`, the bin bases the scatter adds), and the chunk tables.  Spreading needs a
 // chunk for every bin (empty bins write zeros); interpolation only for
 // non-empty bins.  A bin with more than kChunk records is split into several
 // chunks; for spreading those bins are listed in `multi` for the reduction.
@@ -143,65 +210,148 @@ k_bin_scan(const int* __restrict__ counts, int T, int* __restrict__ cursor, int4
 }
 
 // ------------------------------------------------------------- spreading
-// One workgroup per chunk of a bin: accumulate c_j psi(.) psi(.) into a 32 x 32
-// LDS tile with LDS float atomics (only the taps that fall inside this bin;
-// the point's other bins hold their own copy of the record), then write the
-// tile.  A bin split into several chunks writes per-chunk partial tiles that
-// k_spread_reduce sums.
+// Gather form, no atomics on the grid.  One workgroup per chunk of a bin.  A
+// sub-batch of the chunk's records is counting-sorted in LDS by first-tap
+// cell (first taps range over [-(w-1), 31]^2 relative to the bin), with the
+// kernel weights of every record staged next to it (zero-padded by one entry
+// on both sides).  Thread t owns a 2 x 2 block of the 32 x 32 bin in
+// registers and walks only the records whose w x w footprint covers it: first
+// taps in a (w+1) x (w+1) window, i.e. w+1 contiguous runs of the sorted
+// order.  Every grid cell is then written once.  A bin split into several
+// chunks writes per-chunk partial tiles that k_spread_reduce sums.
 constexpr int kSpreadThreads = 256;
-constexpr int kTS = kTile + 1;  // padded LDS row
+
+// es_kernel with the hardware exp2 and square root (v_exp_f32, v_sqrt_f32):
+// absolute error below 3e-8 of the kernel's peak value 1.
+__device__ __forceinline__ float es_kernel_fast(float d, float two_over_w, float beta_log2e) {
+  const float t = d * two_over_w;
+  const float r = 1.0f - t * t;
+  return r > 0.0f ? __builtin_amdgcn_exp2f(beta_log2e * (__builtin_amdgcn_sqrtf(r) - 1.0f)) : 0.0f;
+}
+
+template <int W>
+struct SpreadCfg {
+  static constexpr int SB = W <= 8 ? 512 : 256;  // records per LDS sub-batch
+  static constexpr int RS = kTile + W - 1;       // first-tap cells per axis
+  static constexpr int NC = RS * RS;
+  static constexpr int WP = W + 2;               // padded weights, d = -1 .. w
+};
 
 template <int W>
 __global__ void __launch_bounds__(kSpreadThreads) k_spread(SpreadArgs a) {
-  __shared__ float sre[kTile * kTS];
-  __shared__ float sim[kTile * kTS];
+  using Cfg = SpreadCfg<W>;
+  constexpr int SB = Cfg::SB, RS = Cfg::RS, NC = Cfg::NC, WP = Cfg::WP, NT = kSpreadThreads;
+  constexpr int PER = SB / NT;
+  __shared__ float2 sc[SB];
+  __shared__ float swx[SB][WP];
+  __shared__ float swy[SB][WP];
+  __shared__ int slx[SB];
+  __shared__ int soff[NC + 1];
+  __shared__ int srank[SB];
   const int cid = blockIdx.x;
   if (cid >= a.nchunks[0]) return;
   const int4 ch = a.chunks[cid];
   const int bin = ch.x, start = ch.y, n = ch.z, nb = ch.w;
-  for (int e = threadIdx.x; e < kTile * kTS; e += kSpreadThreads) {
-    sre[e] = 0.f;
-    sim[e] = 0.f;
-  }
-  __syncthreads();
-  for (int r = threadIdx.x; r < n; r += kSpreadThreads) {
-    const BinRec rec = a.recs[start + r];
-    const float2 c = a.vals[rec.idx];
-    const int lx = rec_lx(rec.packed), ly = rec_ly(rec.packed);
-    float wx[W], wy[W];
+  const int t = threadIdx.x;
+  const int x0 = 2 * (t & 15), y0 = 2 * (t >> 4);
+  const float blog = a.beta * 1.4426950408889634f;
+  float2 a00 = czero(), a01 = czero(), a10 = czero(), a11 = czero();
+  for (int b0 = 0; b0 < n; b0 += SB) {
+    const int nb_ = min(SB, n - b0);
+    for (int e = t; e <= NC; e += NT) soff[e] = 0;
+    __syncthreads();
+    BinRec rl[PER];
+    int key[PER];
 #pragma unroll
-    for (int m = 0; m < W; ++m) {
-      wx[m] = es_kernel(rec.dx + (float)m, a.two_over_w, a.beta);
-      wy[m] = es_kernel(rec.dy + (float)m, a.two_over_w, a.beta);
-    }
-#pragma unroll
-    for (int my = 0; my < W; ++my) {
-      const int yy = ly + my;
-      if ((unsigned)yy >= (unsigned)kTile) continue;
-      const float cyr = c.x * wy[my], cyi = c.y * wy[my];
-#pragma unroll
-      for (int mx = 0; mx < W; ++mx) {
-        const int xx = lx + mx;
-        if ((unsigned)xx >= (unsigned)kTile) continue;
-        atomicAdd(&sre[yy * kTS + xx], cyr * wx[mx]);
-        atomicAdd(&sim[yy * kTS + xx], cyi * wx[mx]);
+    for (int q = 0; q < PER; ++q) {
+      const int r = t + q * NT;
+      key[q] = 0;
+      if (r < nb_) {
+        rl[q] = a.recs[start + b0 + r];
+        key[q] = (rec_ly(rl[q].packed) + W - 1) * RS + rec_lx(rl[q].packed) + W - 1;
+        srank[r] = atomicAdd(&soff[key[q]], 1);
       }
     }
+    __syncthreads();
+    if (t < 64) {  // exclusive scan of the cell counts by one wave
+      constexpr int per = (NC + 63) / 64;
+      const int s0 = min(NC, t * per), s1 = min(NC, s0 + per);
+      int acc = 0;
+      for (int e = s0; e < s1; ++e) acc += soff[e];
+      int incl = acc;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(incl, o, 64);
+        if (t >= o) incl += v;
+      }
+      int run = incl - acc;
+      for (int e = s0; e < s1; ++e) {
+        const int c = soff[e];
+        soff[e] = run;
+        run += c;
+      }
+      if (t == 63) soff[NC] = run;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int r = t + q * NT;
+      if (r < nb_) {
+        const int slot = soff[key[q]] + srank[r];
+        sc[slot] = a.vals[rl[q].idx];
+        slx[slot] = rec_lx(rl[q].packed);
+        swx[slot][0] = 0.f;
+        swy[slot][0] = 0.f;
+        swx[slot][W + 1] = 0.f;
+        swy[slot][W + 1] = 0.f;
+#pragma unroll
+        for (int m = 0; m < W; ++m) {
+          swx[slot][m + 1] = es_kernel_fast(rl[q].dx + (float)m, a.two_over_w, blog);
+          swy[slot][m + 1] = es_kernel_fast(rl[q].dy + (float)m, a.two_over_w, blog);
+        }
+      }
+    }
+    __syncthreads();
+    for (int ly = y0 - (W - 1); ly <= y0 + 1; ++ly) {
+      const int row = (ly + W - 1) * RS;
+      const int rs = soff[row + x0];                 // first taps from x0 - (w-1)
+      const int re = soff[row + x0 + W + 1];         // ... through x0 + 1
+      const int dy = y0 - ly + 1;
+      for (int r = rs; r < re; ++r) {
+        const int dx = x0 - slx[r] + 1;
+        const float wx0 = swx[r][dx], wx1 = swx[r][dx + 1];
+        const float wy0 = swy[r][dy], wy1 = swy[r][dy + 1];
+        const float2 c = sc[r];
+        const float p0r = c.x * wy0, p0i = c.y * wy0, p1r = c.x * wy1, p1i = c.y * wy1;
+        a00.x += p0r * wx0;
+        a00.y += p0i * wx0;
+        a01.x += p0r * wx1;
+        a01.y += p0i * wx1;
+        a10.x += p1r * wx0;
+        a10.y += p1i * wx0;
+        a11.x += p1r * wx1;
+        a11.y += p1i * wx1;
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
   if (nb == 1) {
     const int bx = bin % a.TX, by = bin / a.TX;
-    for (int e = threadIdx.x; e < kTile * kTile; e += kSpreadThreads) {
-      const int yy = e / kTile, xx = e % kTile;
-      const int gy = by * kTile + yy, gx = bx * kTile + xx;
-      if (gy < a.L && gx < a.L) a.grid[(size_t)gy * a.L + gx] = make_float2(sre[yy * kTS + xx], sim[yy * kTS + xx]);
+    const int gx = bx * kTile + x0, gy = by * kTile + y0;
+    float2* g = a.grid;
+    if (gy < a.L) {
+      if (gx < a.L) g[(size_t)gy * a.L + gx] = a00;
+      if (gx + 1 < a.L) g[(size_t)gy * a.L + gx + 1] = a01;
+    }
+    if (gy + 1 < a.L) {
+      if (gx < a.L) g[(size_t)(gy + 1) * a.L + gx] = a10;
+      if (gx + 1 < a.L) g[(size_t)(gy + 1) * a.L + gx + 1] = a11;
     }
   } else {
     float2* part = a.scratch + (size_t)cid * (kTile * kTile);
-    for (int e = threadIdx.x; e < kTile * kTile; e += kSpreadThreads) {
-      const int yy = e / kTile, xx = e % kTile;
-      part[e] = make_float2(sre[yy * kTS + xx], sim[yy * kTS + xx]);
-    }
+    part[y0 * kTile + x0] = a00;
+    part[y0 * kTile + x0 + 1] = a01;
+    part[(y0 + 1) * kTile + x0] = a10;
+    part[(y0 + 1) * kTile + x0 + 1] = a11;
   }
 }
 
@@ -244,13 +394,14 @@ __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs a) {
     const BinRec rec = a.recs[start + r];
     if (!rec_primary(rec.packed)) continue;
     const int lx = rec_lx(rec.packed), ly = rec_ly(rec.packed);
+    const float blog = a.beta * 1.4426950408889634f;
     float wx[W];
 #pragma unroll
-    for (int m = 0; m < W; ++m) wx[m] = es_kernel(rec.dx + (float)m, a.two_over_w, a.beta);
+    for (int m = 0; m < W; ++m) wx[m] = es_kernel_fast(rec.dx + (float)m, a.two_over_w, blog);
     float accr = 0.f, acci = 0.f;
 #pragma unroll
     for (int my = 0; my < W; ++my) {
-      const float wy = es_kernel(rec.dy + (float)my, a.two_over_w, a.beta);
+      const float wy = es_kernel_fast(rec.dy + (float)my, a.two_over_w, blog);
       const float2* row = sg + (ly + my) * RS + lx;
       float rr = 0.f, ri = 0.f;
 #pragma unroll
@@ -279,10 +430,23 @@ hipError_t launch_fill_i32(int* p, int v, int64_t n, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_bin_count(const double* x, const double* y, int64_t M, BinGeom g, int* counts,
-                            int* bad, hipStream_t st) {
-  if (M <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_bin_count, dim3(grid_for(M, 256)), dim3(256), 0, st, x, y, M, g, counts, bad);
+static hipError_t bin_lds_attr(const void* k, int bytes) {
+  if (bytes > 64 * 1024) return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  return hipSuccess;
+}
+
+hipError_t launch_bin_hist(const double* x, const double* y, int64_t M, BinGeom g, int ppw, int G,
+                           uint16_t* hist, int* bad, hipStream_t st) {
+  if (G <= 0) return hipSuccess;
+  const int T = g.TX * g.TX, bytes = ((T + 1) / 2) * 4;
+  hipError_t e = bin_lds_attr((const void*)k_bin_hist, bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_bin_hist, dim3(G), dim3(kBinThreads), bytes, st, x, y, M, g, ppw, hist, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_colscan(const uint16_t* hist, int G, int T, int* off, int* total, hipStream_t st) {
+  hipLaunchKernelGGL(k_bin_colscan, dim3((T + 63) / 64), dim3(64 * kColWaves), 0, st, hist, G, T, off, total);
   return hipGetLastError();
 }
 
@@ -293,10 +457,13 @@ hipError_t launch_bin_scan(const int* counts, int T, int* cursor, int4* sp_chunk
   return hipGetLastError();
 }
 
-hipError_t launch_bin_scatter(const double* x, const double* y, int64_t M, BinGeom g, int* cursor,
-                              BinRec* recs, hipStream_t st) {
-  if (M <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_bin_scatter, dim3(grid_for(M, 256)), dim3(256), 0, st, x, y, M, g, cursor, recs);
+hipError_t launch_bin_scatter(const double* x, const double* y, int64_t M, BinGeom g, int ppw, int G,
+                              const int* off, const int* bin_base, BinRec* recs, hipStream_t st) {
+  if (G <= 0) return hipSuccess;
+  const int T = g.TX * g.TX, bytes = ((T + 1) / 2) * 4;
+  hipError_t e = bin_lds_attr((const void*)k_bin_scatter, bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_bin_scatter, dim3(G), dim3(kBinThreads), bytes, st, x, y, M, g, ppw, off, bin_base, recs);
   return hipGetLastError();
 }
 

@@ -10,7 +10,7 @@ namespace nuasm {
 
 constexpr int kTile = 32;        // fine cells per bin side
 constexpr int kPad = 8;          // support margin: taps reach w/2 <= 8 cells past the window
-constexpr int kChunk = 1024;     // max records per spreading / interpolation workgroup
+constexpr int kChunk = 2048;     // max records per spreading / interpolation workgroup
 constexpr int kMaxW = 16;
 
 // Geometry of the fine-grid support and of the uniform planes.
@@ -81,13 +81,16 @@ struct InterpArgs {
 
 // ---- launchers (return hipGetLastError() of the launch) -------------------
 hipError_t launch_fill_i32(int* p, int v, int64_t n, hipStream_t st);
-hipError_t launch_bin_count(const double* x, const double* y, int64_t M, BinGeom g, int* counts,
-                            int* bad, hipStream_t st);
+// counting sort of (point, bin) pairs: hist -> colscan -> scan -> scatter
+constexpr int kBinPointsMax = 65535;  // points per binning workgroup (16-bit LDS counters)
+hipError_t launch_bin_hist(const double* x, const double* y, int64_t M, BinGeom g, int ppw, int G,
+                           uint16_t* hist, int* bad, hipStream_t st);
+hipError_t launch_bin_colscan(const uint16_t* hist, int G, int T, int* off, int* total, hipStream_t st);
 // nch[0] spread chunks, nch[1] interpolation chunks, nch[2] records, nch[3] multi-chunk bins
 hipError_t launch_bin_scan(const int* counts, int T, int* cursor, int4* sp_chunks, int* sp_first,
                            int* sp_n, int* multi, int4* ip_chunks, int* nch, hipStream_t st);
-hipError_t launch_bin_scatter(const double* x, const double* y, int64_t M, BinGeom g, int* cursor,
-                              BinRec* recs, hipStream_t st);
+hipError_t launch_bin_scatter(const double* x, const double* y, int64_t M, BinGeom g, int ppw, int G,
+                              const int* off, const int* bin_base, BinRec* recs, hipStream_t st);
 hipError_t launch_spread(int w, const SpreadArgs& a, int grid, hipStream_t st);
 hipError_t launch_spread_reduce(const SpreadReduceArgs& a, int grid, hipStream_t st);
 hipError_t launch_interp(int w, const InterpArgs& a, int grid, hipStream_t st);

@@ -178,8 +178,11 @@ struct nuasm_plan_s {
   float2* gridB = nullptr;
   float* dinv = nullptr;
   float2* fre = nullptr;  // [2][Np]
-  int* counts = nullptr;
-  int* cursor = nullptr;
+  int* counts = nullptr;   // records per bin
+  int* cursor = nullptr;   // first record of each bin
+  uint16_t* hist = nullptr;  // [G][T] per-range bin counts
+  int* hoff = nullptr;       // [G][T] per-range offsets inside each bin
+  int64_t hist_rows = 0;
   int* sp_first = nullptr;
   int* sp_n = nullptr;
   int* multi = nullptr;
@@ -193,6 +196,11 @@ struct nuasm_plan_s {
   int64_t scratch_chunks = 0;
   int* host_stat = nullptr;  // pinned [5]
   size_t bytes = 0;
+  // stage timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<int> ev_stage;          // stage of each recorded (start, end) pair
+  std::vector<hipEvent_t> ev_pairs;   // start0, end0, start1, end1, ...
   // state
   int64_t M = 0;
   bool ready = false;
@@ -228,8 +236,49 @@ void release(nuasm_plan_s* pl) {
   f(pl->ip_chunks);
   f(pl->recs);
   f(pl->scratch);
+  f(pl->hist);
+  f(pl->hoff);
   if (pl->host_stat) (void)hipHostFree(pl->host_stat);
+  for (hipEvent_t e : pl->ev_pool) (void)hipEventDestroy(e);
+  for (hipEvent_t e : pl->ev_pairs) (void)hipEventDestroy(e);
+  pl->ev_pool.clear();
+  pl->ev_pairs.clear();
 }
+
+hipEvent_t take_event(nuasm_plan_s* pl) {
+  if (!pl->ev_pool.empty()) {
+    hipEvent_t e = pl->ev_pool.back();
+    pl->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets the launches of one stage with events when timing is on.
+struct StageScope {
+  nuasm_plan_s* pl;
+  int stage;
+  hipEvent_t start = nullptr;
+  StageScope(nuasm_plan_s* p, int s) : pl(p), stage(s) {
+    if (!pl->timing) return;
+    start = take_event(pl);
+    if (start) (void)hipEventRecord(start, pl->stream);
+  }
+  ~StageScope() {
+    if (!start) return;
+    hipEvent_t end = take_event(pl);
+    if (!end) {
+      pl->ev_pool.push_back(start);
+      return;
+    }
+    (void)hipEventRecord(end, pl->stream);
+    pl->ev_pairs.push_back(start);
+    pl->ev_pairs.push_back(end);
+    pl->ev_stage.push_back(stage);
+  }
+};
 
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
@@ -258,6 +307,15 @@ nuasm_status validate(const nuasm_params* p) {
   return NUASM_OK;
 }
 
+// Binning workgroups: contiguous ranges of ppw points (at least 4096, at most
+// kBinPointsMax, and about 256 ranges for large M).
+void bin_ranges(int64_t M, int* ppw, int* G) {
+  int64_t p = std::max<int64_t>(4096, (M + 255) / 256);
+  p = std::min<int64_t>(p, kBinPointsMax);
+  *ppw = (int)p;
+  *G = (int)((M + p - 1) / p);
+}
+
 nuasm_status ensure_points_capacity(nuasm_plan_s* pl, int64_t M) {
   if (M <= pl->rec_cap && pl->recs) return NUASM_OK;
   const int64_t cap = std::max<int64_t>(M, 1024);
@@ -280,7 +338,21 @@ nuasm_status ensure_points_capacity(nuasm_plan_s* pl, int64_t M) {
     pl->scratch = nullptr;
     pl->scratch_chunks = 0;
   }
+  if (pl->hist) {
+    (void)hipFree(pl->hist);
+    (void)hipFree(pl->hoff);
+    pl->bytes -= (sizeof(uint16_t) + sizeof(int)) * pl->hist_rows * pl->T;
+    pl->hist = nullptr;
+    pl->hoff = nullptr;
+  }
   pl->rec_cap = 0;
+  {
+    int ppw = 0, G = 0;
+    bin_ranges(cap, &ppw, &G);
+    pl->hist_rows = std::max(G, 1);
+    HIP_TRY(dalloc(pl, &pl->hist, (size_t)pl->hist_rows * pl->T), "hipMalloc(bin histograms)");
+    HIP_TRY(dalloc(pl, &pl->hoff, (size_t)pl->hist_rows * pl->T), "hipMalloc(bin offsets)");
+  }
   HIP_TRY(dalloc(pl, &pl->recs, (size_t)(4 * cap)), "hipMalloc(records)");
   pl->chunk_cap = pl->T + (4 * cap) / kChunk + 1;
   HIP_TRY(dalloc(pl, &pl->sp_chunks, (size_t)pl->chunk_cap), "hipMalloc(chunks)");
@@ -311,35 +383,47 @@ nuasm_status run_type1_pipeline(nuasm_plan_s* pl, const float2* vals, float2* ou
   hipStream_t st = pl->stream;
   nuasm_status s = ensure_scratch(pl);
   if (s != NUASM_OK) return s;
-  SpreadArgs sa{};
-  sa.recs = pl->recs;
-  sa.chunks = pl->sp_chunks;
-  sa.nchunks = pl->nch + 0;
-  sa.scratch = pl->scratch;
-  sa.vals = vals;
-  sa.grid = pl->gridA;
-  sa.L = pl->geom.L;
-  sa.TX = pl->TX;
-  sa.two_over_w = 2.0f / (float)pl->w;
-  sa.beta = pl->beta;
-  HIP_TRY(launch_spread(pl->w, sa, sp_grid(pl), st), "launch spread");
-  SpreadReduceArgs ra{};
-  ra.multi = pl->multi;
-  ra.nmulti = pl->nch + 3;
-  ra.bin_chunk0 = pl->sp_first;
-  ra.bin_nchunk = pl->sp_n;
-  ra.scratch = pl->scratch;
-  ra.grid = pl->gridA;
-  ra.L = pl->geom.L;
-  ra.TX = pl->TX;
-  HIP_TRY(launch_spread_reduce(ra, multi_grid(pl), st), "launch spread_reduce");
+  {
+    StageScope sc(pl, NUASM_STAGE_SPREAD);
+    SpreadArgs sa{};
+    sa.recs = pl->recs;
+    sa.chunks = pl->sp_chunks;
+    sa.nchunks = pl->nch + 0;
+    sa.scratch = pl->scratch;
+    sa.vals = vals;
+    sa.grid = pl->gridA;
+    sa.L = pl->geom.L;
+    sa.TX = pl->TX;
+    sa.two_over_w = 2.0f / (float)pl->w;
+    sa.beta = pl->beta;
+    HIP_TRY(launch_spread(pl->w, sa, sp_grid(pl), st), "launch spread");
+    SpreadReduceArgs ra{};
+    ra.multi = pl->multi;
+    ra.nmulti = pl->nch + 3;
+    ra.bin_chunk0 = pl->sp_first;
+    ra.bin_nchunk = pl->sp_n;
+    ra.scratch = pl->scratch;
+    ra.grid = pl->gridA;
+    ra.L = pl->geom.L;
+    ra.TX = pl->TX;
+    HIP_TRY(launch_spread_reduce(ra, multi_grid(pl), st), "launch spread_reduce");
+  }
   GridGeom g = pl->geom;
   g.crop = crop ? 1 : 0;
   Spectral sp = pl->spec;
   sp.conj = conj ? 1 : 0;
-  HIP_TRY(launch_t1_rows(pl->logNp, pl->gridA, pl->gridB, g, pl->dinv, pl->tw, st), "launch t1_rows");
-  HIP_TRY(launch_t1_cols(pl->logNp, pl->gridB, pl->gridA, g, sp, pl->tw, st), "launch t1_cols");
-  HIP_TRY(launch_t1_rows_inv(pl->logNp, pl->gridA, out, g, pl->tw, st), "launch t1_rows_inv");
+  {
+    StageScope sc(pl, NUASM_STAGE_T1_ROWS);
+    HIP_TRY(launch_t1_rows(pl->logNp, pl->gridA, pl->gridB, g, pl->dinv, pl->tw, st), "launch t1_rows");
+  }
+  {
+    StageScope sc(pl, NUASM_STAGE_T1_COLS);
+    HIP_TRY(launch_t1_cols(pl->logNp, pl->gridB, pl->gridA, g, sp, pl->tw, st), "launch t1_cols");
+  }
+  {
+    StageScope sc(pl, NUASM_STAGE_T1_ROWS_INV);
+    HIP_TRY(launch_t1_rows_inv(pl->logNp, pl->gridA, out, g, pl->tw, st), "launch t1_rows_inv");
+  }
   return NUASM_OK;
 }
 
@@ -351,10 +435,20 @@ nuasm_status run_type2_pipeline(nuasm_plan_s* pl, const float2* plane, int Nin, 
   g.crop = 0;
   Spectral sp = pl->spec;
   sp.conj = conj ? 1 : 0;
-  HIP_TRY(launch_t2_rows(pl->logNp, plane, pl->gridB, g, pl->dinv, pl->tw, st), "launch t2_rows");
-  HIP_TRY(launch_t2_cols(pl->logNp, pl->gridB, pl->gridA, g, sp, pl->tw, st), "launch t2_cols");
-  HIP_TRY(launch_t2_rows_inv(pl->logNp, pl->gridA, pl->gridB, g, pl->tw, st), "launch t2_rows_inv");
+  {
+    StageScope sc(pl, NUASM_STAGE_T2_ROWS);
+    HIP_TRY(launch_t2_rows(pl->logNp, plane, pl->gridB, g, pl->dinv, pl->tw, st), "launch t2_rows");
+  }
+  {
+    StageScope sc(pl, NUASM_STAGE_T2_COLS);
+    HIP_TRY(launch_t2_cols(pl->logNp, pl->gridB, pl->gridA, g, sp, pl->tw, st), "launch t2_cols");
+  }
+  {
+    StageScope sc(pl, NUASM_STAGE_T2_ROWS_INV);
+    HIP_TRY(launch_t2_rows_inv(pl->logNp, pl->gridA, pl->gridB, g, pl->tw, st), "launch t2_rows_inv");
+  }
   if (pl->M > 0) {
+    StageScope sc(pl, NUASM_STAGE_INTERP);
     InterpArgs ia{};
     ia.recs = pl->recs;
     ia.chunks = pl->ip_chunks;
@@ -592,13 +686,23 @@ nuasm_status nuasm_set_points(nuasm_plan pl, int64_t M, const double* x, const d
   nuasm_status s = ensure_points_capacity(pl, M);
   if (s != NUASM_OK) return s;
   hipStream_t st = pl->stream;
-  HIP_TRY(launch_fill_i32(pl->counts, 0, pl->T, st), "launch fill");
-  HIP_TRY(launch_fill_i32(pl->nch, 0, 8, st), "launch fill");
-  HIP_TRY(launch_bin_count(x, y, M, pl->bgeom, pl->counts, pl->nch + 4, st), "launch bin_count");
-  HIP_TRY(launch_bin_scan(pl->counts, pl->T, pl->cursor, pl->sp_chunks, pl->sp_first, pl->sp_n, pl->multi,
-                          pl->ip_chunks, pl->nch, st),
-          "launch bin_scan");
-  HIP_TRY(launch_bin_scatter(x, y, M, pl->bgeom, pl->cursor, pl->recs, st), "launch bin_scatter");
+  {
+    StageScope sc(pl, NUASM_STAGE_BIN);
+    int ppw = 0, G = 0;
+    bin_ranges(M, &ppw, &G);
+    HIP_TRY(launch_fill_i32(pl->nch, 0, 8, st), "launch fill");
+    if (M > 0) {
+      HIP_TRY(launch_bin_hist(x, y, M, pl->bgeom, ppw, G, pl->hist, pl->nch + 4, st), "launch bin_hist");
+      HIP_TRY(launch_bin_colscan(pl->hist, G, pl->T, pl->hoff, pl->counts, st), "launch bin_colscan");
+    } else {
+      HIP_TRY(launch_fill_i32(pl->counts, 0, pl->T, st), "launch fill");
+    }
+    HIP_TRY(launch_bin_scan(pl->counts, pl->T, pl->cursor, pl->sp_chunks, pl->sp_first, pl->sp_n, pl->multi,
+                            pl->ip_chunks, pl->nch, st),
+            "launch bin_scan");
+    HIP_TRY(launch_bin_scatter(x, y, M, pl->bgeom, ppw, G, pl->hoff, pl->cursor, pl->recs, st),
+            "launch bin_scatter");
+  }
   pl->M = M;
   pl->synced = false;
   if (pl->p.flags & NUASM_DEFER_RANGE_CHECK) {
@@ -659,6 +763,28 @@ nuasm_status nuasm_execute_adjoint(nuasm_plan pl, const void* in, void* out) {
     return run_type2_pipeline(pl, (const float2*)in, pl->geom.Np, (float2*)out, true);
   }
   return run_type1_pipeline(pl, (const float2*)in, (float2*)out, true, true);
+}
+
+nuasm_status nuasm_plan_set_timing(nuasm_plan pl, int32_t enable) {
+  if (!pl) return fail(NUASM_ERR_INVALID_ARG, "plan is NULL");
+  pl->timing = enable != 0;
+  return NUASM_OK;
+}
+
+nuasm_status nuasm_plan_read_timing(nuasm_plan pl, double* ms, int64_t* launches) {
+  if (!pl || !ms || !launches) return fail(NUASM_ERR_INVALID_ARG, "NULL argument");
+  if (!pl->ev_pairs.empty()) HIP_TRY(hipEventSynchronize(pl->ev_pairs.back()), "hipEventSynchronize");
+  for (size_t i = 0; i < pl->ev_stage.size(); ++i) {
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, pl->ev_pairs[2 * i], pl->ev_pairs[2 * i + 1]), "hipEventElapsedTime");
+    const int s = pl->ev_stage[i];
+    ms[s] += t;
+    launches[s] += 1;
+  }
+  for (hipEvent_t e : pl->ev_pairs) pl->ev_pool.push_back(e);
+  pl->ev_pairs.clear();
+  pl->ev_stage.clear();
+  return NUASM_OK;
 }
 
 nuasm_status nuasm_debug_transfer(nuasm_plan pl, void* out) {

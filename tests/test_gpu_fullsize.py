@@ -1,0 +1,103 @@
+"""Full-size parity in the benchmark's launch configuration: N = 1024
+(N' = 2048), M = 2^20 clustered points, o = (1 mm, 0), tolerance 1e-6, z in
+{0.01, 0.1, 0.5} m, band-limited ASM and Fresnel, deferred range check.
+
+The oracle cannot produce whole outputs at this size in seconds, so it is
+evaluated one sample at a time:
+* NU-ASM_2: the destination values at 512 seeded points (each is an
+  independent sum over K^2, exact per point);
+* NU-ASM_1: the spectrum of the GPU's N' x N' output at 512 seeded
+  frequencies, which must equal H(k) F(k) (the inverse FFT's N'^-2 and the
+  forward DFT cancel); F(k) is the O(M) sum of Eq. 7 at that k.  By
+  Parseval the sampled relative error estimates the whole-plane rel-L2.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from gpu_util import dev, host, rel_l2, type1_spectral_samples
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+N, G, LAM, OX, M = 1024, 4e-6, 633e-9, 1e-3, 1 << 20
+SETTINGS = [(z, tf) for z in (0.01, 0.1, 0.5) for tf in ("asm", "fresnel")]
+
+
+@pytest.fixture(scope="module")
+def data():
+    import paper_1308_6644_amd as P
+    P.load()
+    W = N * G
+    r1 = synth.rng_for(2, 0)
+    x1, y1 = synth.clustered_box(r1, M, W)
+    c1 = synth.unit_phase(r1, M)
+    r2 = synth.rng_for(2, 1)
+    x2, y2 = synth.clustered_box(r2, M, W)
+    u1 = synth.unit_phase(r2, (N, N))
+    geo0 = O.Geometry(N=N, g=G, lam=LAM, z=0.1, ox=OX)
+    D = O.nuasm_oracle._source_dft(N, 2 * N)
+    U = D @ u1.astype(np.complex128) @ D.T          # uniform spectrum of Eq. 9
+    rs = np.random.default_rng(2024)
+    sel = rs.choice(M, size=512, replace=False)
+    return dict(P=P, x1=x1, y1=y1, c1=c1, x2=x2, y2=y2, u1=u1, U=U, sel=sel, rs=rs,
+                d=dict(x1=dev(torch, x1), y1=dev(torch, y1), c1=dev(torch, c1),
+                       x2=dev(torch, x2), y2=dev(torch, y2), u1=dev(torch, u1)))
+
+
+def _geo(z, tf):
+    return O.Geometry(N=N, g=G, lam=LAM, z=z, ox=OX, oy=0.0, tf=tf,
+                      band="limited" if tf == "asm" else "full")
+
+
+def _plan(P, z, tf, t):
+    return P.Plan(N, t, LAM, z, G, tf=tf, band="limited" if tf == "asm" else "full", ox=OX,
+                  tol=1e-6, defer_range_check=True)
+
+
+@pytest.mark.parametrize("z,tf", SETTINGS)
+def test_fullsize_nuasm2_sampled_points(data, z, tf):
+    print(f"fullsize nuasm2 z={z} tf={tf} N={N} M={M}", flush=True)
+    P, d = data["P"], data["d"]
+    plan = _plan(P, z, tf, 2)
+    plan.set_points(d["x2"], d["y2"])
+    out = plan.execute(d["u1"])
+    plan.check_points()
+    got = host(out)[data["sel"]]
+    geo = _geo(z, tf)
+    H = O.transfer(geo)
+    G2 = H * data["U"] / float(geo.Np) ** 2
+    ref = O.nuasm_oracle._type2_eval(geo, G2, data["x2"][data["sel"]], data["y2"][data["sel"]])
+    err = rel_l2(got, ref)
+    print(f"  rel-L2 on 512 sampled points = {err:.3e}", flush=True)
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("z,tf", SETTINGS)
+def test_fullsize_nuasm1_spectral_samples(data, z, tf):
+    print(f"fullsize nuasm1 z={z} tf={tf} N={N} M={M}", flush=True)
+    P, d = data["P"], data["d"]
+    plan = _plan(P, z, tf, 1)
+    plan.set_points(d["x1"], d["y1"])
+    out = plan.execute(d["c1"])
+    plan.check_points()
+    u2 = host(out)
+    geo = _geo(z, tf)
+    (xlo, xhi), (ylo, yhi) = O.band_index_bounds(geo)
+    rs = np.random.default_rng(int(1000 * z) + (0 if tf == "asm" else 7))
+    kx = rs.integers(xlo, xhi + 1, size=448)
+    ky = rs.integers(ylo, yhi + 1, size=448)
+    # plus samples anywhere in K^2 (out of band for the ASM: must be ~0)
+    kx = np.concatenate([kx, rs.integers(-N, N, size=64)])
+    ky = np.concatenate([ky, rs.integers(-N, N, size=64)])
+    H = O.transfer(geo)
+    Hk = H[ky + N, kx + N]
+    F = O.spectrum_at(geo, data["x1"], data["y1"], data["c1"], kx, ky)
+    ref = Hk * F
+    got = type1_spectral_samples(u2, kx, ky)
+    err = rel_l2(got, ref)
+    print(f"  rel-L2 on 512 spectral samples = {err:.3e}", flush=True)
+    assert err <= 1e-5
