@@ -32,25 +32,36 @@ ZS = (0.01, 0.1, 0.5)
 TFS = (("asm", "limited"), ("fresnel", "full"))
 M = 1 << 20
 
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes over this
+# workload (scaled by a plain-copy calibration), for kernels whose code has not
+# changed since the counters were taken; see profiles/bench_N2048_M1M_kernels.md.
+COUNTER_TRAFFIC = {"spread": (143.4 + 35.6) * 1e6}
+
 
 def stage_bytes(stage: str, info: dict) -> float:
-    """Algorithmic (compulsory) HBM bytes of one launch of a stage: every
-    input the stage needs read once, every output written once.  Nb is the
-    number of in-band x-frequencies (the Rect of Eq. 4 lets the grid passes
-    skip the others)."""
-    n, np_, L, m = info["N"], info["Np"], info["L"], info["M"]
+    """Algorithmic (compulsory) HBM bytes of one launch of a kernel: every
+    input the kernel's job needs read once, every output written once.  M is
+    the point count, L the fine-grid support side, T the number of bins, G the
+    number of binning ranges, Nb the number of in-band x-frequencies (the Rect
+    of Eq. 4 lets the grid passes skip the others)."""
+    n, np_, L, m, T = info["N"], info["Np"], info["L"], info["M"], info["tiles"]
     nb = max(0, min(info["kx_hi"], np_ // 2 - 1) - max(info["kx_lo"], -np_ // 2) + 1)
+    G = max(1, -(-m // max(4096, min(65535, -(-m // 256)))))
     c = 8.0  # complex64
     return {
-        "bin": 16.0 * m + 16.0 * m,                  # coordinates in, one record out
-        "spread": 16.0 * m + c * m + c * L * L,      # records + values in, support grid out
+        "bin_hist": 16.0 * m + 2.0 * G * T,            # coordinates in, 16-bit histograms out
+        "bin_colscan": 2.0 * G * T + 4.0 * G * T + 4.0 * T,
+        "bin_scan": 4.0 * T + 4.0 * T + 16.0 * T,      # totals in, bases + chunk table out
+        "bin_scatter": 16.0 * m + 4.0 * G * T + 16.0 * m,  # coordinates + offsets in, records out
+        "spread": 16.0 * m + c * m + c * L * L,        # records + values in, support grid out
+        "spread_reduce": 0.0,
         "t1_rows": c * L * L + c * L * nb,
         "t1_cols": c * L * nb + c * np_ * nb,
         "t1_rows_inv": c * np_ * nb + c * np_ * np_,
         "t2_rows": c * n * n + c * n * nb,
         "t2_cols": c * n * nb + c * L * nb,
         "t2_rows_inv": c * L * nb + c * L * L,
-        "interp": c * L * L + 16.0 * m + c * m,      # grid + records in, values out
+        "interp": c * L * L + 16.0 * m + c * m,        # grid + records in, values out
     }[stage]
 
 
@@ -97,6 +108,9 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--profile-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES bytes (3 times), the "
+                         "reference for the FETCH_SIZE / WRITE_SIZE counters, and exit")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {a.gpus}). "
@@ -112,6 +126,15 @@ def main(argv=None):
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     torch.cuda.set_device(0)
+    if a.copy_calibration:
+        n = a.copy_calibration // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n * 4, "copies": 3}), flush=True)
+        return 0
     P.load()
     print(f"[bench] generating inputs N={N} M={M}", file=sys.stderr, flush=True)
     host, d = make_inputs(torch, synth)
@@ -156,6 +179,31 @@ def main(argv=None):
     ms_per_step = e0.elapsed_time(e1) / a.steps
     value = len(runs) * M / (ms_per_step * 1e-3)
 
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "NU-ASM_1 + NU-ASM_2 one-shot (bin + execute), N=1024 (N'=2048), M=2^20 clustered "
+                        "points per run, pitch 4 um, 633 nm, o=(1 mm, 0), z in {0.01, 0.1, 0.5} m x "
+                        "{band-limited ASM, Fresnel}, tol 1e-6 (w=7), 12 runs per step",
+            "N": N, "Np": 2 * N, "M": M, "runs_per_step": len(runs), "phase": "f64",
+        },
+        "wall_s_timed": wall,
+    }
+    if a.profile_steps <= 0:
+        print(json.dumps(line), flush=True)
+        return 0
+
     # second pass: per-stage HIP events recorded by the library
     print(f"[bench] per-stage timing {a.profile_steps} steps", file=sys.stderr, flush=True)
     for r in runs:
@@ -182,7 +230,7 @@ def main(argv=None):
     achieved = ds["bytes"] / (ds["ms"] * 1e-3) / 1e9
     stage_report = {k: {"avg_us": 1e3 * v["ms"] / v["launches"], "launches_per_step": v["launches"] // a.profile_steps,
                         "share": v["ms"] / sum(s["ms"] for s in stages.values()),
-                        "GBps": v["bytes"] / (v["ms"] * 1e-3) / 1e9}
+                        "GBps": v["bytes"] / max(v["ms"] * 1e-3, 1e-12) / 1e9}
                     for k, v in sorted(stages.items(), key=lambda kv: -kv[1]["ms"])}
     # whole-path byte model per type (pass-minimal): 64 M + 56 N'^2 and 56 M + 44 N'^2
     Np = 2 * N
@@ -193,25 +241,7 @@ def main(argv=None):
         path[f"nuasm{t}"] = {"avg_ms": t_ms, "model_bytes": bpp,
                              "frac": bpp / (t_ms * 1e-3) / (HBM_PEAK_GBS * 1e9)}
 
-    line = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "points/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {
-            "workload": "NU-ASM_1 + NU-ASM_2 one-shot (bin + execute), N=1024 (N'=2048), M=2^20 clustered "
-                        "points per run, pitch 4 um, 633 nm, o=(1 mm, 0), z in {0.01, 0.1, 0.5} m x "
-                        "{band-limited ASM, Fresnel}, tol 1e-6 (w=7), 12 runs per step",
-            "N": N, "Np": Np, "M": M, "runs_per_step": len(runs), "phase": "f64",
-        },
+    line.update({
         "roofline": {
             "bound": "hbm",
             "kernel": dom,
@@ -219,13 +249,12 @@ def main(argv=None):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": COUNTER_TRAFFIC.get(dom),
             "avg_launch_us": avg_ms * 1e3,
         },
         "stages": stage_report,
         "path_model": path,
-        "wall_s_timed": wall,
-    }
+    })
     if not a.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(host)

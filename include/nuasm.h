@@ -162,18 +162,22 @@ nuasm_status nuasm_debug_transfer(nuasm_plan plan, void* out_dev);
 nuasm_status nuasm_debug_fft(int64_t n, int64_t batch, int32_t sign, const void* in_dev,
                              void* out_dev, void* hip_stream);
 
-/* Per-stage device timing with HIP events recorded on the plan's stream
- * around each kernel launch (off by default).  Stages: */
-#define NUASM_STAGE_BIN 0          /* set_points: count + scan + scatter */
-#define NUASM_STAGE_SPREAD 1       /* spreading (+ reduction of split bins) */
-#define NUASM_STAGE_T1_ROWS 2      /* type-1 pipeline: fine rows, FFT */
-#define NUASM_STAGE_T1_COLS 3      /* type-1 pipeline: fused column pass */
-#define NUASM_STAGE_T1_ROWS_INV 4  /* type-1 pipeline: inverse row FFT */
-#define NUASM_STAGE_T2_ROWS 5      /* type-2 pipeline: plane rows, FFT */
-#define NUASM_STAGE_T2_COLS 6      /* type-2 pipeline: fused column pass */
-#define NUASM_STAGE_T2_ROWS_INV 7  /* type-2 pipeline: fine rows, inverse FFT */
-#define NUASM_STAGE_INTERP 8       /* interpolation */
-#define NUASM_NUM_STAGES 9
+/* Per-kernel device timing with HIP events recorded on the plan's stream
+ * around each kernel launch (off by default).  Stages, one kernel each: */
+#define NUASM_STAGE_BIN_HIST 0     /* set_points: per-range bin histograms */
+#define NUASM_STAGE_BIN_COLSCAN 1  /* set_points: offsets across ranges */
+#define NUASM_STAGE_BIN_SCAN 2     /* set_points: bin bases and chunk tables */
+#define NUASM_STAGE_BIN_SCATTER 3  /* set_points: records into bin order */
+#define NUASM_STAGE_SPREAD 4       /* spreading */
+#define NUASM_STAGE_SPREAD_REDUCE 5 /* sum of split bins' partial tiles */
+#define NUASM_STAGE_T1_ROWS 6      /* type-1 pipeline: fine rows, FFT */
+#define NUASM_STAGE_T1_COLS 7      /* type-1 pipeline: fused column pass */
+#define NUASM_STAGE_T1_ROWS_INV 8  /* type-1 pipeline: inverse row FFT */
+#define NUASM_STAGE_T2_ROWS 9      /* type-2 pipeline: plane rows, FFT */
+#define NUASM_STAGE_T2_COLS 10     /* type-2 pipeline: fused column pass */
+#define NUASM_STAGE_T2_ROWS_INV 11 /* type-2 pipeline: fine rows, inverse FFT */
+#define NUASM_STAGE_INTERP 12      /* interpolation */
+#define NUASM_NUM_STAGES 13
 nuasm_status nuasm_plan_set_timing(nuasm_plan plan, int32_t enable);
 /* Synchronise on the recorded events, add each stage's elapsed milliseconds
  * and launch count into ms[NUASM_NUM_STAGES] / launches[NUASM_NUM_STAGES]

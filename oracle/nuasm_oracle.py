@@ -54,7 +54,8 @@ __all__ = [
     "Geometry", "freq_index", "cis_cycles", "band_index_bounds", "band_mask",
     "transfer_asm", "transfer_fresnel", "transfer", "nuasm1", "nuasm2",
     "nuasm1_adjoint", "nuasm2_adjoint", "type1_spectrum", "spectrum_at",
-    "cgh_loss", "cgh_grad", "rayleigh_sommerfeld", "rel_l2", "snr_db",
+    "cgh_loss", "cgh_grad", "rayleigh_sommerfeld", "rel_l2", "snr_db", "uniform_spectrum",
+    "nuasm2_from_spectrum",
 ]
 
 
@@ -259,6 +260,28 @@ def _source_dft(N: int, Np: int) -> np.ndarray:
     K = freq_index(Np)
     m = np.arange(-N // 2, N // 2, dtype=np.float64)
     return cis_cycles(-np.outer(K, m) / Np)
+
+
+def uniform_spectrum(u1: np.ndarray, Np: int, method: str = "dense") -> np.ndarray:
+    """U(k) = sum_m u1[m] exp(-2 pi i k.m / N') of Eq. 9 for a centred N x N
+    source, k in K^2, [ky][kx].  'dense' uses DFT matrices; 'fft' uses numpy's
+    float64 FFT (a library primitive, for sizes where the dense form is slow)."""
+    u1 = np.asarray(u1).astype(np.complex128)
+    n = u1.shape[0]
+    if method == "dense":
+        D = _source_dft(n, Np)
+        return D @ u1 @ D.T
+    pad = np.zeros((Np, Np), dtype=np.complex128)
+    pad[Np // 2 - n // 2:Np // 2 + n // 2, Np // 2 - n // 2:Np // 2 + n // 2] = u1
+    return np.fft.fftshift(np.fft.fft2(np.fft.ifftshift(pad)))
+
+
+def nuasm2_from_spectrum(geo: Geometry, U: np.ndarray, x, y, H: np.ndarray | None = None) -> np.ndarray:
+    """NU-ASM_2 (Eq. 9) at the given destination points from a precomputed
+    uniform spectrum U (see uniform_spectrum): each output is its own sum."""
+    if H is None:
+        H = transfer(geo)
+    return _type2_eval(geo, H * U / float(geo.Np) ** 2, x, y)
 
 
 def nuasm1(geo: Geometry, x, y, c, H: np.ndarray | None = None) -> np.ndarray:

@@ -19,8 +19,8 @@ __all__ = [
 ]
 
 TYPE_1, TYPE_2 = 1, 2
-STAGES = ("bin", "spread", "t1_rows", "t1_cols", "t1_rows_inv", "t2_rows", "t2_cols",
-          "t2_rows_inv", "interp")
+STAGES = ("bin_hist", "bin_colscan", "bin_scan", "bin_scatter", "spread", "spread_reduce",
+          "t1_rows", "t1_cols", "t1_rows_inv", "t2_rows", "t2_cols", "t2_rows_inv", "interp")
 TF_ASM, TF_FRESNEL = 0, 1
 BAND = {"full": 0, "limited": 1, "explicit": 2}
 TF = {"asm": TF_ASM, "fresnel": TF_FRESNEL}

@@ -397,6 +397,9 @@ nuasm_status run_type1_pipeline(nuasm_plan_s* pl, const float2* vals, float2* ou
     sa.two_over_w = 2.0f / (float)pl->w;
     sa.beta = pl->beta;
     HIP_TRY(launch_spread(pl->w, sa, sp_grid(pl), st), "launch spread");
+  }
+  {
+    StageScope sc(pl, NUASM_STAGE_SPREAD_REDUCE);
     SpreadReduceArgs ra{};
     ra.multi = pl->multi;
     ra.nmulti = pl->nch + 3;
@@ -687,19 +690,26 @@ nuasm_status nuasm_set_points(nuasm_plan pl, int64_t M, const double* x, const d
   if (s != NUASM_OK) return s;
   hipStream_t st = pl->stream;
   {
-    StageScope sc(pl, NUASM_STAGE_BIN);
     int ppw = 0, G = 0;
     bin_ranges(M, &ppw, &G);
     HIP_TRY(launch_fill_i32(pl->nch, 0, 8, st), "launch fill");
     if (M > 0) {
-      HIP_TRY(launch_bin_hist(x, y, M, pl->bgeom, ppw, G, pl->hist, pl->nch + 4, st), "launch bin_hist");
+      {
+        StageScope sc(pl, NUASM_STAGE_BIN_HIST);
+        HIP_TRY(launch_bin_hist(x, y, M, pl->bgeom, ppw, G, pl->hist, pl->nch + 4, st), "launch bin_hist");
+      }
+      StageScope sc(pl, NUASM_STAGE_BIN_COLSCAN);
       HIP_TRY(launch_bin_colscan(pl->hist, G, pl->T, pl->hoff, pl->counts, st), "launch bin_colscan");
     } else {
       HIP_TRY(launch_fill_i32(pl->counts, 0, pl->T, st), "launch fill");
     }
-    HIP_TRY(launch_bin_scan(pl->counts, pl->T, pl->cursor, pl->sp_chunks, pl->sp_first, pl->sp_n, pl->multi,
-                            pl->ip_chunks, pl->nch, st),
-            "launch bin_scan");
+    {
+      StageScope sc(pl, NUASM_STAGE_BIN_SCAN);
+      HIP_TRY(launch_bin_scan(pl->counts, pl->T, pl->cursor, pl->sp_chunks, pl->sp_first, pl->sp_n, pl->multi,
+                              pl->ip_chunks, pl->nch, st),
+              "launch bin_scan");
+    }
+    StageScope sc(pl, NUASM_STAGE_BIN_SCATTER);
     HIP_TRY(launch_bin_scatter(x, y, M, pl->bgeom, ppw, G, pl->hoff, pl->cursor, pl->recs, st),
             "launch bin_scatter");
   }

@@ -1,0 +1,139 @@
+"""Differentiation through the hand-written adjoint: autograd gradients of the
+hologram loss L(phi) = sum_j (|NU-ASM_2(exp(i phi))_j|^2 - T_j)^2 against the
+FP64 oracle gradient and against central finite differences, the type-1
+autograd rule, and a short phase optimisation."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from gpu_util import dev, geometry, host, make_plan, rel_l2
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1308_6644_amd as P
+    P.load()
+    return P
+
+
+def _cgh_setup(N, M, seed, z=0.02, lam=532e-9, g=4e-6):
+    geo = geometry(N=N, g=g, lam=lam, z=z, tf="asm", band="limited")
+    rng = synth.rng_for(5, seed)
+    x, y = synth.three_clusters(rng, M, N * g)
+    phi = rng.uniform(0.0, 2 * np.pi, size=(N, N)).astype(np.float32)
+    T = synth.gaussian_blobs(rng, x, y, N * g)
+    return geo, x, y, phi, T
+
+
+def _torch_loss(P, plan, phi_t, T_t):
+    u1 = torch.polar(torch.ones_like(phi_t), phi_t)
+    u = P.nuasm2(u1, plan)
+    r = (u.real.double() ** 2 + u.imag.double() ** 2) - T_t
+    return torch.sum(r * r)
+
+
+def test_cgh_gradient_matches_oracle(P):
+    N, M = 64, 4096
+    print(f"cgh grad vs oracle N={N} M={M}", flush=True)
+    geo, x, y, phi, T = _cgh_setup(N, M, 0)
+    H = O.transfer(geo)
+    u0 = O.nuasm2(geo, np.exp(1j * phi.astype(np.float64)), x, y, H)
+    T = T * (np.sum(np.abs(u0) ** 2) / np.sum(T))          # sum T = sum |u(phi0)|^2
+    plan = make_plan(P, geo, 2)
+    plan.set_points(dev(torch, x), dev(torch, y))
+    phi_t = dev(torch, phi).requires_grad_(True)
+    loss = _torch_loss(P, plan, phi_t, dev(torch, T))
+    loss.backward()
+    g_gpu = phi_t.grad.detach().cpu().numpy().astype(np.float64)
+    g_ref = O.cgh_grad(geo, phi.astype(np.float64), x, y, T, H)
+    err = rel_l2(g_gpu, g_ref)
+    cos = float(np.dot(g_gpu.ravel(), g_ref.ravel()) / np.linalg.norm(g_gpu) / np.linalg.norm(g_ref))
+    print(f"  rel-L2 {err:.3e} cosine {cos:.8f}", flush=True)
+    assert err <= 1e-4 and cos >= 0.99999
+
+
+def test_cgh_gradient_central_differences_full_size(P):
+    """N = 2048 (N' = 4096), M = 4,194,304 points in three clusters, z = 0.2 m,
+    532 nm; central differences (eps = 1e-3, loss summed in FP64) on 64
+    seeded phase entries against the autograd gradient."""
+    N, M = 2048, 1 << 22
+    print(f"cgh FD N={N} M={M}", flush=True)
+    geo, x, y, phi, T = _cgh_setup(N, M, 1, z=0.2)
+    plan = make_plan(P, geo, 2)
+    plan.set_points(dev(torch, x), dev(torch, y))
+    phi_t = dev(torch, phi)
+    with torch.no_grad():
+        u1 = torch.polar(torch.ones_like(phi_t), phi_t)
+        u0 = plan.execute(u1)
+        s0 = float((u0.real.double() ** 2 + u0.imag.double() ** 2).sum())
+    T_t = dev(torch, T * (s0 / np.sum(T)))
+    p = phi_t.clone().requires_grad_(True)
+    loss = _torch_loss(P, plan, p, T_t)
+    loss.backward()
+    g = p.grad.detach()
+    rng = np.random.default_rng(55)
+    idx = rng.choice(N * N, size=64, replace=False)
+    eps = 1e-3
+    fd = np.empty(64)
+    flat = phi_t.view(-1)
+    with torch.no_grad():
+        for i, k in enumerate(idx):
+            q = flat.clone()
+            q[k] = flat[k] + eps
+            hi = float(q[k])
+            lp = float(_torch_loss(P, plan, q.view(N, N), T_t))
+            q[k] = flat[k] - eps
+            lo = float(q[k])
+            lm = float(_torch_loss(P, plan, q.view(N, N), T_t))
+            fd[i] = (lp - lm) / (hi - lo)   # the float32 step actually taken
+    ga = g.view(-1)[torch.from_numpy(idx).cuda()].double().cpu().numpy()
+    cos = float(np.dot(ga, fd) / np.linalg.norm(ga) / np.linalg.norm(fd))
+    rms = float(np.sqrt(np.mean(ga ** 2)))
+    worst = float(np.max(np.abs(fd - ga) / (np.abs(ga) + 1e-3 * rms)))
+    print(f"  cosine {cos:.6f} worst per-entry rel {worst:.3e}", flush=True)
+    assert cos >= 0.999
+    assert worst <= 1e-2
+
+
+def test_type1_autograd_is_adjoint(P):
+    N, M = 32, 700
+    geo = geometry(N=N, g=4e-6, lam=633e-9, z=0.01, tf="fresnel", ox=2e-5)
+    rng = np.random.default_rng(3)
+    x, y = synth.clustered_box(rng, M, N * geo.g)
+    c = synth.unit_phase(rng, M)
+    v = synth.unit_phase(rng, (2 * N, 2 * N))
+    plan = make_plan(P, geo, 1)
+    plan.set_points(dev(torch, x), dev(torch, y))
+    ct = dev(torch, c).requires_grad_(True)
+    u = P.nuasm1(ct, plan)
+    loss = torch.sum(torch.abs(u - dev(torch, v)) ** 2)
+    loss.backward()
+    # torch's gradient of a real loss w.r.t. complex c is 2 dL/d(conj c) = 2 A^H (A c - v)
+    ref = 2.0 * O.nuasm1_adjoint(geo, O.nuasm1(geo, x, y, c) - v, x, y)
+    assert rel_l2(host(ct.grad), ref) <= 1e-5
+
+
+def test_phase_optimisation_reduces_loss(P):
+    N, M = 256, 1 << 16
+    geo, x, y, phi, T = _cgh_setup(N, M, 2, z=0.05)
+    plan = make_plan(P, geo, 2)
+    plan.set_points(dev(torch, x), dev(torch, y))
+    p = dev(torch, phi).requires_grad_(True)
+    with torch.no_grad():
+        u0 = plan.execute(torch.polar(torch.ones_like(p), p))
+        s0 = float((u0.abs().double() ** 2).sum())
+    T_t = dev(torch, T * (s0 / np.sum(T)))
+    opt = torch.optim.Adam([p], lr=0.05)
+    losses = []
+    for _ in range(30):
+        opt.zero_grad()
+        loss = _torch_loss(P, plan, p, T_t)
+        loss.backward()
+        opt.step()
+        losses.append(float(loss))
+    print(f"  loss {losses[0]:.4e} -> {losses[-1]:.4e}", flush=True)
+    assert losses[-1] < 0.5 * losses[0]

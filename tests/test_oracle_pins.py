@@ -342,3 +342,14 @@ def test_spectrum_at_matches_fft_of_z0_output():
     ky = rng.integers(-8, 8, size=10)
     got = O.spectrum_at(geo, x, y, c, kx, ky)
     assert O.rel_l2(got, F[ky + 8, kx + 8]) < 1e-12
+
+
+def test_uniform_spectrum_fft_path_equals_dense_dft():
+    rng = np.random.default_rng(91)
+    u1 = rng.standard_normal((16, 16)) + 1j * rng.standard_normal((16, 16))
+    a = O.uniform_spectrum(u1, 32, "dense")
+    b = O.uniform_spectrum(u1, 32, "fft")
+    assert O.rel_l2(b, a) < 1e-13
+    geo = _geo(N=16, z=0.02, band="limited", ox=1e-5)
+    x, y = synth.uniform_box(rng, 20, geo.N * geo.g)
+    assert O.rel_l2(O.nuasm2_from_spectrum(geo, b, x, y), O.nuasm2(geo, u1, x, y)) < 1e-12
