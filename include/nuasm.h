@@ -185,6 +185,31 @@ nuasm_status nuasm_plan_set_timing(nuasm_plan plan, int32_t enable);
  * the recorded events. */
 nuasm_status nuasm_plan_read_timing(nuasm_plan plan, double* ms, int64_t* launches);
 
+/* ------------------------------------------------------------ batches
+ * Many independent planes (each its own N, type, transfer function, z, point
+ * count) run as one HIP graph: the binning and the operator of every plane
+ * are captured once, on parallel branches, and replayed by each run.  For
+ * callers that propagate many planes per step (a batch of holograms, a
+ * focal stack).  Plans inside a batch always defer their range checks. */
+typedef struct nuasm_batch_s* nuasm_batch;
+
+/* params[P]; hip_stream is borrowed.  On failure *out is NULL. */
+nuasm_status nuasm_batch_create(int32_t P, const nuasm_params* params, void* hip_stream, nuasm_batch* out);
+nuasm_status nuasm_batch_destroy(nuasm_batch batch);  /* NULL-safe */
+/* One-shot run of every plane p: bin M[p] points x[p], y[p] (device FP64
+ * metres) and apply the operator to in[p] -> out[p] (device complex64, shapes
+ * as for nuasm_execute).  The first call with a given set of pointers and
+ * counts records the graph (and runs it); later calls with the same arguments
+ * only launch it.  Never synchronises the host. */
+nuasm_status nuasm_batch_run(nuasm_batch batch, const int64_t* M, const double* const* x,
+                             const double* const* y, const void* const* in, void* const* out);
+/* Synchronise; *bad_plane = index of the first plane with out-of-range
+ * points in the last run, or -1. */
+nuasm_status nuasm_batch_check_points(nuasm_batch batch, int32_t* bad_plane);
+/* Synchronise; ms[p] = device wall-clock time from the start of the last run
+ * to the completion of plane p (caller-owned host array of P floats). */
+nuasm_status nuasm_batch_plane_times(nuasm_batch batch, float* ms);
+
 const char* nuasm_status_string(nuasm_status s);
 const char* nuasm_last_error(void);
 

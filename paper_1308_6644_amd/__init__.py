@@ -14,7 +14,7 @@ import os
 import torch  # loads the HIP runtime the library binds to
 
 __all__ = [
-    "Plan", "NUASM1", "NUASM2", "nuasm1", "nuasm2", "debug_fft", "lib_path", "load",
+    "Plan", "Batch", "make_params", "NUASM1", "NUASM2", "nuasm1", "nuasm2", "debug_fft", "lib_path", "load",
     "NuasmError", "TYPE_1", "TYPE_2", "TF_ASM", "TF_FRESNEL",
 ]
 
@@ -82,6 +82,14 @@ _SIGS = {
                                               ctypes.POINTER(ctypes.c_int64)]),
     "nuasm_debug_fft": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_void_p]),
+    "nuasm_batch_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(Params), ctypes.c_void_p,
+                                          ctypes.POINTER(ctypes.c_void_p)]),
+    "nuasm_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "nuasm_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                       ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p)]),
+    "nuasm_batch_check_points": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
+    "nuasm_batch_plane_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float)]),
 }
 
 _lib = None
@@ -127,6 +135,29 @@ def _dev_ptr(t: torch.Tensor, dtype, what: str) -> int:
     return t.data_ptr()
 
 
+def make_params(N: int, type: int, lam: float, z: float, g: float, *, tf: str = "asm",
+                ox: float = 0.0, oy: float = 0.0, band: str = "full", band_c=(0.0, 0.0),
+                band_w=(0.0, 0.0), tol: float = 1e-6, phase_fp64: bool = True, crop: bool = False,
+                defer_range_check: bool = False) -> Params:
+    lib = load()
+    p = Params()
+    _check(lib.nuasm_params_default(ctypes.byref(p)))
+    p.type = int(type)
+    p.tf = TF[tf]
+    p.band = BAND[band]
+    p.phase_fp64 = 1 if phase_fp64 else 0
+    p.N = int(N)
+    p.lam = float(lam)
+    p.z = float(z)
+    p.ox, p.oy = float(ox), float(oy)
+    p.d1 = p.d2 = float(g)
+    p.band_c[0], p.band_c[1] = float(band_c[0]), float(band_c[1])
+    p.band_w[0], p.band_w[1] = float(band_w[0]), float(band_w[1])
+    p.tol = float(tol)
+    p.flags = (OUT_CROP_N if crop else 0) | (DEFER_RANGE_CHECK if defer_range_check else 0)
+    return p
+
+
 class Plan:
     """One operator instance: NU-ASM_1/NU-FRE_1 (type 1, Eq. 6) or
     NU-ASM_2/NU-FRE_2 (type 2, Eq. 9) on an N x N plane of pitch g.
@@ -140,21 +171,8 @@ class Plan:
                  band_w=(0.0, 0.0), tol: float = 1e-6, phase_fp64: bool = True, crop: bool = False,
                  defer_range_check: bool = False, device=None):
         lib = load()
-        p = Params()
-        _check(lib.nuasm_params_default(ctypes.byref(p)))
-        p.type = int(type)
-        p.tf = TF[tf]
-        p.band = BAND[band]
-        p.phase_fp64 = 1 if phase_fp64 else 0
-        p.N = int(N)
-        p.lam = float(lam)
-        p.z = float(z)
-        p.ox, p.oy = float(ox), float(oy)
-        p.d1 = p.d2 = float(g)
-        p.band_c[0], p.band_c[1] = float(band_c[0]), float(band_c[1])
-        p.band_w[0], p.band_w[1] = float(band_w[0]), float(band_w[1])
-        p.tol = float(tol)
-        p.flags = (OUT_CROP_N if crop else 0) | (DEFER_RANGE_CHECK if defer_range_check else 0)
+        p = make_params(N, type, lam, z, g, tf=tf, ox=ox, oy=oy, band=band, band_c=band_c, band_w=band_w,
+                        tol=tol, phase_fp64=phase_fp64, crop=crop, defer_range_check=defer_range_check)
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self.params = p
         self.N, self.Np, self.type, self.crop = int(N), 2 * int(N), int(type), bool(crop)
@@ -251,6 +269,61 @@ class Plan:
         self._sync_stream()
         _check(load().nuasm_debug_transfer(self._h, ctypes.c_void_p(out.data_ptr())))
         return out
+
+
+class Batch:
+    """Many independent planes run as one recorded HIP graph (binning and the
+    operator of every plane on parallel branches).  ``specs`` is a list of
+    keyword dicts for make_params (N, type, lam, z, g, tf, band, ox, oy, tol)."""
+
+    def __init__(self, specs):
+        lib = load()
+        self.specs = [dict(s) for s in specs]
+        arr = (Params * len(specs))(*[make_params(**s) for s in specs])
+        h = ctypes.c_void_p()
+        _check(lib.nuasm_batch_create(len(specs), arr, ctypes.c_void_p(_stream_ptr()), ctypes.byref(h)))
+        self._h = h
+        self.P = len(specs)
+        self._keep = None
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load().nuasm_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, xs, ys, ins, outs):
+        """One-shot run of every plane: bin xs[p], ys[p] and apply the operator
+        to ins[p] -> outs[p] (device tensors, shapes as for Plan.execute)."""
+        P = self.P
+        if not (len(xs) == len(ys) == len(ins) == len(outs) == P):
+            raise ValueError("need one x, y, in and out per plane")
+        M = (ctypes.c_int64 * P)(*[int(x.numel()) for x in xs])
+        vp = ctypes.c_void_p * P
+
+        def ptrs(ts, dtype, what):
+            return vp(*[(_dev_ptr(t, dtype, what) if t.numel() else None) for t in ts])
+        px, py = ptrs(xs, torch.float64, "x"), ptrs(ys, torch.float64, "y")
+        pi, po = ptrs(ins, torch.complex64, "in"), ptrs(outs, torch.complex64, "out")
+        _check(load().nuasm_batch_run(self._h, M, px, py, pi, po))
+        self._keep = (xs, ys, ins, outs)
+        return outs
+
+    def check_points(self) -> int:
+        bad = ctypes.c_int32(-1)
+        _check(load().nuasm_batch_check_points(self._h, ctypes.byref(bad)))
+        return bad.value
+
+    def plane_times(self):
+        """Milliseconds from the start of the last run to each plane's completion."""
+        ms = (ctypes.c_float * self.P)()
+        _check(load().nuasm_batch_plane_times(self._h, ms))
+        return [ms[i] for i in range(self.P)]
 
 
 def debug_fft(x: torch.Tensor, sign: int = -1) -> torch.Tensor:

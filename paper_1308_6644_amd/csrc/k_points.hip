@@ -417,7 +417,17 @@ __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs a) {
   }
 }
 
+// Device wall-clock stamp (constant-rate counter), for per-plane latency.
+__global__ void k_stamp(long long* __restrict__ out) {
+  if (threadIdx.x == 0) *out = wall_clock64();
+}
+
 // --------------------------------------------------------------- launchers
+hipError_t launch_stamp(long long* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_stamp, dim3(1), dim3(64), 0, st, out);
+  return hipGetLastError();
+}
+
 static int grid_for(int64_t n, int threads) {
   int64_t b = (n + threads - 1) / threads;
   if (b > 65535 * 4) b = 65535 * 4;

@@ -110,6 +110,7 @@ hipError_t launch_t2_cols(int logNp, const float2* T, float2* V, GridGeom g, Spe
 hipError_t launch_t2_rows_inv(int logNp, const float2* V, float2* fine, GridGeom g, const float2* tw,
                               hipStream_t st);
 
+hipError_t launch_stamp(long long* out, hipStream_t st);
 hipError_t launch_transfer_table(const GridGeom& g, const Spectral& sp, float2* out, hipStream_t st);
 hipError_t launch_fresnel_axis(int Np, double g, double two_lam_z, double o, double2 amp,
                                float2* out, hipStream_t st);

@@ -825,4 +825,235 @@ nuasm_status nuasm_debug_fft(int64_t n, int64_t batch, int32_t sign, const void*
   return NUASM_OK;
 }
 
+
+// ================================================================ batches
+}  // extern "C"
+
+struct nuasm_batch_s {
+  std::vector<nuasm_plan_s*> plans;
+  hipStream_t stream = nullptr;  // caller's stream
+  hipStream_t cap = nullptr;     // internal stream the graph is recorded and launched on
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  std::vector<hipStream_t> branch;
+  std::vector<int> branch_of;  // plane -> branch
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
+  hipGraphExec_t exec = nullptr;
+  std::vector<const void*> key;
+  long long* ts = nullptr;     // [P + 1] device wall-clock stamps
+  int clock_khz = 0;
+};
+
+namespace {
+
+constexpr int kBranches = 4;
+
+void batch_release(nuasm_batch_s* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  for (nuasm_plan_s* pl : b->plans) {
+    if (!pl) continue;
+    release(pl);
+    delete pl;
+  }
+  for (hipStream_t s : b->branch) (void)hipStreamDestroy(s);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
+  if (b->ts) (void)hipFree(b->ts);
+}
+
+// enqueue the one-shot work of plane p on the plan's current stream
+nuasm_status batch_plane(nuasm_plan_s* pl, int64_t M, const double* x, const double* y, const void* in,
+                         void* out) {
+  nuasm_status s = nuasm_set_points(pl, M, x, y);
+  if (s != NUASM_OK) return s;
+  return nuasm_execute(pl, in, out);
+}
+
+}  // namespace
+
+extern "C" {
+
+nuasm_status nuasm_batch_create(int32_t P, const nuasm_params* params, void* hip_stream, nuasm_batch* out) {
+  if (!out) return fail(NUASM_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (P <= 0 || !params) return fail(NUASM_ERR_INVALID_ARG, "need P > 0 plane parameters");
+  nuasm_batch_s* b = new (std::nothrow) nuasm_batch_s();
+  if (!b) return fail(NUASM_ERR_ALLOC, "host allocation failed");
+  b->stream = (hipStream_t)hip_stream;
+  auto bail = [&](nuasm_status st) {
+    batch_release(b);
+    delete b;
+    return st;
+  };
+  std::vector<double> work(P);
+  for (int p = 0; p < P; ++p) {
+    nuasm_params q = params[p];
+    q.flags |= NUASM_DEFER_RANGE_CHECK;
+    nuasm_plan pl = nullptr;
+    nuasm_status s = nuasm_plan_create(&q, hip_stream, &pl);
+    if (s != NUASM_OK) {
+      std::string m = "plane " + std::to_string(p) + ": " + g_last_error;
+      b->plans.push_back(nullptr);
+      batch_release(b);
+      delete b;
+      return fail(s, m);
+    }
+    b->plans.push_back(pl);
+    work[p] = (double)pl->geom.L * pl->geom.L;
+  }
+  // longest-processing-time assignment of planes to the capture branches
+  std::vector<int> order(P);
+  for (int p = 0; p < P; ++p) order[p] = p;
+  std::sort(order.begin(), order.end(), [&](int a, int c) { return work[a] > work[c]; });
+  const int K = std::min(kBranches, (int)P);
+  std::vector<double> load(K, 0.0);
+  b->branch_of.assign(P, 0);
+  for (int p : order) {
+    const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    b->branch_of[p] = k;
+    load[k] += work[p];
+  }
+  hipError_t e;
+  for (int k = 0; k < K; ++k) {
+    hipStream_t st = nullptr;
+    if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess)
+      return bail(hip_fail(e, "hipStreamCreate"));
+    b->branch.push_back(st);
+    hipEvent_t ev = nullptr;
+    if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
+      return bail(hip_fail(e, "hipEventCreate"));
+    b->join.push_back(ev);
+  }
+  if ((e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming)) != hipSuccess)
+    return bail(hip_fail(e, "hipEventCreate"));
+  if ((e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming)) != hipSuccess)
+    return bail(hip_fail(e, "hipEventCreate"));
+  if ((e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming)) != hipSuccess)
+    return bail(hip_fail(e, "hipEventCreate"));
+  if ((e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking)) != hipSuccess)
+    return bail(hip_fail(e, "hipStreamCreate"));
+  if ((e = hipMalloc(&b->ts, sizeof(long long) * (P + 1))) != hipSuccess) return bail(hip_fail(e, "hipMalloc(stamps)"));
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  if ((e = hipDeviceGetAttribute(&b->clock_khz, hipDeviceAttributeWallClockRate, dev)) != hipSuccess)
+    return bail(hip_fail(e, "hipDeviceGetAttribute(wall clock)"));
+  *out = b;
+  return NUASM_OK;
+}
+
+nuasm_status nuasm_batch_destroy(nuasm_batch b) {
+  if (!b) return NUASM_OK;
+  (void)hipStreamSynchronize(b->stream);
+  if (b->cap) (void)hipStreamSynchronize(b->cap);
+  for (hipStream_t s : b->branch) (void)hipStreamSynchronize(s);
+  batch_release(b);
+  delete b;
+  return NUASM_OK;
+}
+
+nuasm_status nuasm_batch_run(nuasm_batch b, const int64_t* M, const double* const* x, const double* const* y,
+                             const void* const* in, void* const* out) {
+  if (!b || !M || !x || !y || !in || !out) return fail(NUASM_ERR_INVALID_ARG, "NULL argument");
+  const int P = (int)b->plans.size();
+  std::vector<const void*> key;
+  key.reserve(5 * P);
+  for (int p = 0; p < P; ++p) {
+    if (M[p] < 0) return fail(NUASM_ERR_INVALID_ARG, "M < 0");
+    key.push_back((const void*)(intptr_t)M[p]);
+    key.push_back(x[p]);
+    key.push_back(y[p]);
+    key.push_back(in[p]);
+    key.push_back(out[p]);
+  }
+  // the graph runs on the internal stream, ordered after the caller's stream
+  // and before the caller's later work
+  auto launch = [&]() -> nuasm_status {
+    HIP_TRY(hipEventRecord(b->ev_in, b->stream), "hipEventRecord");
+    HIP_TRY(hipStreamWaitEvent(b->cap, b->ev_in, 0), "hipStreamWaitEvent");
+    HIP_TRY(hipGraphLaunch(b->exec, b->cap), "hipGraphLaunch");
+    HIP_TRY(hipEventRecord(b->ev_out, b->cap), "hipEventRecord");
+    HIP_TRY(hipStreamWaitEvent(b->stream, b->ev_out, 0), "hipStreamWaitEvent");
+    return NUASM_OK;
+  };
+  if (b->exec && key == b->key) return launch();
+  if (b->exec) {
+    HIP_TRY(hipStreamSynchronize(b->cap), "hipStreamSynchronize");
+    (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+    b->key.clear();
+  }
+  // eager pass: sizes every workspace and sets kernel attributes, so the
+  // capture below enqueues launches only
+  for (int p = 0; p < P; ++p) {
+    nuasm_plan_s* pl = b->plans[p];
+    pl->stream = b->stream;
+    pl->timing = false;
+    nuasm_status s = batch_plane(pl, M[p], x[p], y[p], in[p], out[p]);
+    if (s != NUASM_OK) return fail(s, "plane " + std::to_string(p) + ": " + g_last_error);
+  }
+  HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+  // capture on the internal stream: stamp, fork onto the branches, every
+  // plane on its branch followed by its completion stamp, join
+  HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+  nuasm_status st = NUASM_OK;
+  hipError_t e = launch_stamp(b->ts, b->cap);
+  if (e == hipSuccess) e = hipEventRecord(b->fork, b->cap);
+  for (size_t k = 0; e == hipSuccess && k < b->branch.size(); ++k) e = hipStreamWaitEvent(b->branch[k], b->fork, 0);
+  for (int p = 0; e == hipSuccess && st == NUASM_OK && p < P; ++p) {
+    nuasm_plan_s* pl = b->plans[p];
+    pl->stream = b->branch[b->branch_of[p]];
+    st = batch_plane(pl, M[p], x[p], y[p], in[p], out[p]);
+    if (st == NUASM_OK) e = launch_stamp(b->ts + 1 + p, pl->stream);
+  }
+  for (size_t k = 0; e == hipSuccess && k < b->branch.size(); ++k) {
+    e = hipEventRecord(b->join[k], b->branch[k]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->cap, b->join[k], 0);
+  }
+  hipGraph_t graph = nullptr;
+  hipError_t e2 = hipStreamEndCapture(b->cap, &graph);
+  for (nuasm_plan_s* pl : b->plans) pl->stream = b->stream;
+  if (st != NUASM_OK || e != hipSuccess || e2 != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    if (st != NUASM_OK) return st;
+    return hip_fail(e != hipSuccess ? e : e2, "graph capture");
+  }
+  e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    b->exec = nullptr;
+    return hip_fail(e, "hipGraphInstantiate");
+  }
+  b->key = key;
+  return launch();
+}
+
+nuasm_status nuasm_batch_check_points(nuasm_batch b, int32_t* bad_plane) {
+  if (!b || !bad_plane) return fail(NUASM_ERR_INVALID_ARG, "NULL argument");
+  HIP_TRY(hipStreamSynchronize(b->cap), "hipStreamSynchronize");
+  HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+  *bad_plane = -1;
+  for (size_t p = 0; p < b->plans.size(); ++p) {
+    nuasm_plan_s* pl = b->plans[p];
+    HIP_TRY(hipMemcpy(pl->host_stat, pl->nch, sizeof(int) * 5, hipMemcpyDeviceToHost), "hipMemcpy");
+    if (pl->host_stat[4] != 0) {
+      *bad_plane = (int32_t)p;
+      return fail(NUASM_ERR_OUT_OF_RANGE, "plane " + std::to_string(p) + " has points outside its window");
+    }
+  }
+  return NUASM_OK;
+}
+
+nuasm_status nuasm_batch_plane_times(nuasm_batch b, float* ms) {
+  if (!b || !ms) return fail(NUASM_ERR_INVALID_ARG, "NULL argument");
+  HIP_TRY(hipStreamSynchronize(b->cap), "hipStreamSynchronize");
+  const size_t P = b->plans.size();
+  std::vector<long long> h(P + 1);
+  HIP_TRY(hipMemcpy(h.data(), b->ts, sizeof(long long) * (P + 1), hipMemcpyDeviceToHost), "hipMemcpy");
+  for (size_t p = 0; p < P; ++p) ms[p] = (float)((double)(h[p + 1] - h[0]) / (double)b->clock_khz);
+  return NUASM_OK;
+}
+
 }  // extern "C"

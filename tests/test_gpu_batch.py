@@ -1,0 +1,61 @@
+"""Batched execution: planes of different size, type, transfer function,
+distance and point count recorded into one HIP graph must give, plane by
+plane, what the plain single-plane path gives; graph replays (with the
+program's own eager work between them) must keep giving it."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import dev, host, rel_l2
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _planes(seed, P):
+    rng = np.random.default_rng(seed)
+    specs, data = [], []
+    for p in range(P):
+        N = int(rng.choice([32, 64, 128, 256]))
+        t = int(rng.integers(1, 3))
+        tf = "asm" if rng.uniform() < 0.5 else "fresnel"
+        z = float(rng.uniform(0.005, 0.5)) * (1e-1 if N <= 64 else 1.0)
+        g = 4e-6
+        M = int(np.exp(rng.uniform(np.log(100), np.log(40000))))
+        x, y = synth.clustered_box(rng, M, N * g)
+        inp = synth.unit_phase(rng, M if t == 1 else (N, N))
+        specs.append(dict(N=N, type=t, lam=633e-9, z=z, g=g, tf=tf,
+                          band="limited" if tf == "asm" else "full", tol=1e-6))
+        data.append((x, y, inp))
+    return specs, data
+
+
+def test_batch_matches_plain_plans_and_replays(capfd):
+    import paper_1308_6644_amd as P
+    P.load()
+    specs, data = _planes(11, 12)
+    print(f"batch of {len(specs)} planes", flush=True)
+    xs = [dev(torch, d[0]) for d in data]
+    ys = [dev(torch, d[1]) for d in data]
+    ins = [dev(torch, d[2]) for d in data]
+    outs = []
+    refs = []
+    for s, x, y, i in zip(specs, xs, ys, ins):
+        plan = P.Plan(**{k: v for k, v in s.items()})
+        plan.set_points(x, y)
+        refs.append(host(plan.execute(i)))
+        N = s["N"]
+        outs.append(torch.empty((2 * N, 2 * N) if s["type"] == 1 else (x.numel(),),
+                                dtype=torch.complex64, device="cuda"))
+    b = P.Batch(specs)
+    for rep in range(3):
+        for o in outs:
+            o.zero_()               # eager work between graph replays
+        torch.cuda.synchronize()
+        b.run(xs, ys, ins, outs)
+        assert b.check_points() == -1
+        for p, (o, r) in enumerate(zip(outs, refs)):
+            err = rel_l2(host(o), r)
+            assert err <= 1e-6, (rep, p, specs[p], err)
+    t = b.plane_times()
+    assert len(t) == len(specs) and all(v > 0 for v in t)
