@@ -185,6 +185,9 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--profile-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", choices=("graph", "sequential"), default="graph",
+                    help="graph: the 12 runs of a step recorded as one HIP graph on parallel branches; "
+                         "sequential: plain plans one after another on one stream")
     ap.add_argument("--workload", choices=("n2048", "batched"), default="n2048",
                     help="n2048: the 12-run N'=2048 headline workload; batched: 64 mixed planes")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -224,27 +227,44 @@ def main(argv=None):
     for z in ZS:
         for tf, band in TFS:
             for t in (1, 2):
-                plan = P.Plan(N, t, LAM, z, G, tf=tf, band=band, ox=OX, oy=OY, tol=TOL,
-                              defer_range_check=True)
+                spec = dict(N=N, type=t, lam=LAM, z=z, g=G, tf=tf, band=band, ox=OX, oy=OY, tol=TOL)
+                plan = P.Plan(defer_range_check=True, **spec)
                 if t == 1:
                     x, y, inp = d["x1"], d["y1"], d["c1"]
                     out = torch.empty((2 * N, 2 * N), dtype=torch.complex64, device="cuda")
                 else:
                     x, y, inp = d["x2"], d["y2"], d["u1"]
                     out = torch.empty((M,), dtype=torch.complex64, device="cuda")
-                runs.append(dict(plan=plan, x=x, y=y, inp=inp, out=out, type=t, z=z, tf=tf))
+                runs.append(dict(plan=plan, x=x, y=y, inp=inp, out=out, type=t, z=z, tf=tf, spec=spec))
 
-    def step():
+    def seq_step():
         for r in runs:
             r["plan"].set_points(r["x"], r["y"])
             r["plan"].execute(r["inp"], r["out"])
+
+    batch = None
+    if a.mode == "graph":
+        batch = P.Batch([r["spec"] for r in runs])
+        bx = [r["x"] for r in runs]
+        by = [r["y"] for r in runs]
+        bi = [r["inp"] for r in runs]
+        bo = [r["out"] for r in runs]
+
+        def step():
+            batch.run(bx, by, bi, bo)
+    else:
+        step = seq_step
 
     print(f"[bench] warmup {a.warmup}", file=sys.stderr, flush=True)
     for _ in range(a.warmup):
         step()
     torch.cuda.synchronize()
-    for r in runs:
-        r["plan"].check_points()  # every point was inside its window
+    if batch is not None:
+        if batch.check_points() != -1:
+            raise RuntimeError("points outside their window")
+    else:
+        for r in runs:
+            r["plan"].check_points()  # every point was inside its window
 
     print(f"[bench] timing {a.steps} steps", file=sys.stderr, flush=True)
     e0 = torch.cuda.Event(enable_timing=True)
@@ -278,6 +298,7 @@ def main(argv=None):
                         "points per run, pitch 4 um, 633 nm, o=(1 mm, 0), z in {0.01, 0.1, 0.5} m x "
                         "{band-limited ASM, Fresnel}, tol 1e-6 (w=7), 12 runs per step",
             "N": N, "Np": 2 * N, "M": M, "runs_per_step": len(runs), "phase": "f64",
+            "mode": a.mode,
         },
         "wall_s_timed": wall,
     }
@@ -290,7 +311,7 @@ def main(argv=None):
     for r in runs:
         r["plan"].set_timing(True)
     for _ in range(a.profile_steps):
-        step()
+        seq_step()
     torch.cuda.synchronize()
     stages = {}
     per_type_ms = {1: 0.0, 2: 0.0}

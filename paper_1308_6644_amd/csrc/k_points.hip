@@ -60,11 +60,13 @@ __device__ __forceinline__ unsigned lds_bump16(unsigned* sh, int b) {
   return (atomicAdd(&sh[b >> 1], 1u << sft) >> sft) & 0xffffu;
 }
 
+// Histogram rows have T + 1 entries: entry T counts the range's points that
+// are outside the window (they get no record).
 __global__ void __launch_bounds__(kBinThreads)
 k_bin_hist(const double* __restrict__ x, const double* __restrict__ y, int64_t M, BinGeom g, int ppw,
-           uint16_t* __restrict__ hist, int* __restrict__ bad) {
+           uint16_t* __restrict__ hist) {
   extern __shared__ unsigned sh[];
-  const int T = g.TX * g.TX, TW = (T + 1) / 2;
+  const int T = g.TX * g.TX, TW = (T + 2) / 2;
   for (int e = threadIdx.x; e < TW; e += kBinThreads) sh[e] = 0u;
   __syncthreads();
   const int64_t j0 = (int64_t)blockIdx.x * ppw;
@@ -72,7 +74,7 @@ k_bin_hist(const double* __restrict__ x, const double* __restrict__ y, int64_t M
   for (int64_t j = j0 + threadIdx.x; j < j1; j += kBinThreads) {
     const PointCells pc = point_cells(x[j], y[j], g);
     if (!pc.ok) {
-      atomicAdd(bad, 1);
+      lds_bump16(sh, T);
       continue;
     }
     const int bx0 = pc.i0x / kTile, bx1 = (pc.i0x + g.w - 1) / kTile;
@@ -81,8 +83,8 @@ k_bin_hist(const double* __restrict__ x, const double* __restrict__ y, int64_t M
       for (int bx = bx0; bx <= bx1; ++bx) lds_bump16(sh, by * g.TX + bx);
   }
   __syncthreads();
-  uint16_t* row = hist + (size_t)blockIdx.x * T;
-  for (int b = threadIdx.x; b < T; b += kBinThreads) row[b] = (uint16_t)((sh[b >> 1] >> ((b & 1) * 16)) & 0xffffu);
+  uint16_t* row = hist + (size_t)blockIdx.x * (T + 1);
+  for (int b = threadIdx.x; b <= T; b += kBinThreads) row[b] = (uint16_t)((sh[b >> 1] >> ((b & 1) * 16)) & 0xffffu);
 }
 
 // Column scan: off[g][b] = sum_{g' < g} hist[g'][b], total[b] = sum_g hist[g][b].
@@ -92,6 +94,7 @@ constexpr int kColWaves = 16;
 
 __global__ void __launch_bounds__(64 * kColWaves)
 k_bin_colscan(const uint16_t* __restrict__ hist, int G, int T, int* __restrict__ off, int* __restrict__ total) {
+  // T here is the row length (bins + 1)
   __shared__ int part[kColWaves][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int b = blockIdx.x * 64 + lane;
@@ -127,7 +130,7 @@ k_bin_scatter(const double* __restrict__ x, const double* __restrict__ y, int64_
   __syncthreads();
   const int64_t j0 = (int64_t)blockIdx.x * ppw;
   const int64_t j1 = min(M, j0 + ppw);
-  const int* myoff = off + (size_t)blockIdx.x * T;
+  const int* myoff = off + (size_t)blockIdx.x * (T + 1);
   for (int64_t j = j0 + threadIdx.x; j < j1; j += kBinThreads) {
     const PointCells pc = point_cells(x[j], y[j], g);
     if (!pc.ok) continue;
@@ -149,52 +152,86 @@ k_bin_scatter(const double* __restrict__ x, const double* __restrict__ y, int64_
 }
 
 // Single-workgroup scan over the bins: first record of every bin (written to
-// `cursor`, the bin bases the scatter adds), and the chunk tables.  Spreading needs a
-// chunk for every bin (empty bins write zeros); interpolation only for
+// `cursor`, the bin bases the scatter adds), and the chunk tables.  Spreading
+// needs a chunk for every bin (empty bins write zeros); interpolation only for
 // non-empty bins.  A bin with more than kChunk records is split into several
 // chunks; for spreading those bins are listed in `multi` for the reduction.
+// counts[T] (one past the bins) is the number of points outside the window;
+// it is copied to nch[4].  Each thread owns a contiguous run of bins; the
+// block-wide exclusive scan is two wave-shuffle scans around one LDS step.
 constexpr int kScanThreads = 1024;
+constexpr int kScanRegs = 8;  // bins per thread kept in registers
+
+__device__ __forceinline__ int wave_incl_scan(int v, int lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
 
 __global__ void __launch_bounds__(kScanThreads)
 k_bin_scan(const int* __restrict__ counts, int T, int* __restrict__ cursor, int4* __restrict__ sp_chunks,
            int* __restrict__ sp_first, int* __restrict__ sp_n, int* __restrict__ multi,
            int4* __restrict__ ip_chunks, int* __restrict__ nch) {
-  __shared__ int sh[4][kScanThreads];
-  const int tid = threadIdx.x;
+  constexpr int NW = kScanThreads / 64;
+  __shared__ int wsum[4][NW];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int per = (T + kScanThreads - 1) / kScanThreads;
   const int b0 = min(T, tid * per), b1 = min(T, b0 + per);
+  int cr[kScanRegs];
+#pragma unroll
+  for (int q = 0; q < kScanRegs; ++q) cr[q] = (b0 + q < b1) ? counts[b0 + q] : 0;
   int acc[4] = {0, 0, 0, 0};  // records, spread chunks, interp chunks, multi bins
   for (int b = b0; b < b1; ++b) {
-    const int c = counts[b];
+    const int q = b - b0;
+    int c = 0;
+#pragma unroll
+    for (int r = 0; r < kScanRegs; ++r)
+      if (r == q) c = cr[r];
+    if (q >= kScanRegs) c = counts[b];
     const int nsp = c > kChunk ? (c + kChunk - 1) / kChunk : 1;
     acc[0] += c;
     acc[1] += nsp;
     acc[2] += (c + kChunk - 1) / kChunk;
     acc[3] += nsp > 1 ? 1 : 0;
   }
-  for (int q = 0; q < 4; ++q) sh[q][tid] = acc[q];
-  __syncthreads();
-  // inclusive Hillis-Steele scan of the four per-thread sums
-  for (int off = 1; off < kScanThreads; off <<= 1) {
-    int v[4];
-    for (int q = 0; q < 4; ++q) v[q] = tid >= off ? sh[q][tid - off] : 0;
-    __syncthreads();
-    for (int q = 0; q < 4; ++q) sh[q][tid] += v[q];
-    __syncthreads();
+  int incl[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    incl[k] = wave_incl_scan(acc[k], lane);
+    if (lane == 63) wsum[k][wv] = incl[k];
   }
+  __syncthreads();
+  if (wv == 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int v = lane < NW ? wsum[k][lane] : 0;
+      const int w = wave_incl_scan(v, lane);
+      if (lane < NW) wsum[k][lane] = w - v;  // exclusive wave bases
+    }
+  }
+  __syncthreads();
   int run[4];
-  for (int q = 0; q < 4; ++q) run[q] = sh[q][tid] - acc[q];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) run[k] = wsum[k][wv] + incl[k] - acc[k];
   for (int b = b0; b < b1; ++b) {
-    const int c = counts[b];
+    const int q = b - b0;
+    int c = 0;
+#pragma unroll
+    for (int r = 0; r < kScanRegs; ++r)
+      if (r == q) c = cr[r];
+    if (q >= kScanRegs) c = counts[b];
     const int nsp = c > kChunk ? (c + kChunk - 1) / kChunk : 1;
     const int nip = (c + kChunk - 1) / kChunk;
     cursor[b] = run[0];
     sp_first[b] = run[1];
     sp_n[b] = nsp;
-    for (int q = 0; q < nsp; ++q)
-      sp_chunks[run[1] + q] = make_int4(b, run[0] + q * kChunk, min(kChunk, c - q * kChunk), nsp);
-    for (int q = 0; q < nip; ++q)
-      ip_chunks[run[2] + q] = make_int4(b, run[0] + q * kChunk, min(kChunk, c - q * kChunk), nip);
+    for (int r = 0; r < nsp; ++r)
+      sp_chunks[run[1] + r] = make_int4(b, run[0] + r * kChunk, min(kChunk, c - r * kChunk), nsp);
+    for (int r = 0; r < nip; ++r)
+      ip_chunks[run[2] + r] = make_int4(b, run[0] + r * kChunk, min(kChunk, c - r * kChunk), nip);
     if (nsp > 1) multi[run[3]] = b;
     run[0] += c;
     run[1] += nsp;
@@ -202,10 +239,11 @@ k_bin_scan(const int* __restrict__ counts, int T, int* __restrict__ cursor, int4
     run[3] += nsp > 1 ? 1 : 0;
   }
   if (tid == kScanThreads - 1) {
-    nch[0] = sh[1][tid];
-    nch[1] = sh[2][tid];
-    nch[2] = sh[0][tid];
-    nch[3] = sh[3][tid];
+    nch[0] = run[1];
+    nch[1] = run[2];
+    nch[2] = run[0];
+    nch[3] = run[3];
+    nch[4] = counts[T];
   }
 }
 
@@ -241,7 +279,8 @@ template <int W>
 __global__ void __launch_bounds__(kSpreadThreads) k_spread(SpreadArgs a) {
   using Cfg = SpreadCfg<W>;
   constexpr int SB = Cfg::SB, RS = Cfg::RS, NC = Cfg::NC, WP = Cfg::WP, NT = kSpreadThreads;
-  constexpr int PER = SB / NT;
+  constexpr int PER = SB / NT;        // records per thread per sub-batch
+  constexpr int NSUB = kChunk / SB;   // sub-batches per chunk
   __shared__ float2 sc[SB];
   __shared__ float swx[SB][WP];
   __shared__ float swy[SB][WP];
@@ -255,20 +294,38 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(SpreadArgs a) {
   const int t = threadIdx.x;
   const int x0 = 2 * (t & 15), y0 = 2 * (t >> 4);
   const float blog = a.beta * 1.4426950408889634f;
+  // every record of the chunk and its value, loaded up front
+  BinRec rl[NSUB][PER];
+  float2 cv[NSUB][PER];
+#pragma unroll
+  for (int sb = 0; sb < NSUB; ++sb)
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int r = sb * SB + t + q * NT;
+      if (r < n) rl[sb][q] = a.recs[start + r];
+    }
+#pragma unroll
+  for (int sb = 0; sb < NSUB; ++sb)
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int r = sb * SB + t + q * NT;
+      cv[sb][q] = r < n ? a.vals[rl[sb][q].idx] : czero();
+    }
   float2 a00 = czero(), a01 = czero(), a10 = czero(), a11 = czero();
-  for (int b0 = 0; b0 < n; b0 += SB) {
-    const int nb_ = min(SB, n - b0);
+#pragma unroll
+  for (int sb = 0; sb < NSUB; ++sb) {
+    const int b0 = sb * SB;
+    if (b0 >= n) break;
+    const int nsb = min(SB, n - b0);
     for (int e = t; e <= NC; e += NT) soff[e] = 0;
     __syncthreads();
-    BinRec rl[PER];
     int key[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int r = t + q * NT;
       key[q] = 0;
-      if (r < nb_) {
-        rl[q] = a.recs[start + b0 + r];
-        key[q] = (rec_ly(rl[q].packed) + W - 1) * RS + rec_lx(rl[q].packed) + W - 1;
+      if (r < nsb) {
+        key[q] = (rec_ly(rl[sb][q].packed) + W - 1) * RS + rec_lx(rl[sb][q].packed) + W - 1;
         srank[r] = atomicAdd(&soff[key[q]], 1);
       }
     }
@@ -295,42 +352,52 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(SpreadArgs a) {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int r = t + q * NT;
-      if (r < nb_) {
+      if (r < nsb) {
+        const BinRec& rc = rl[sb][q];
         const int slot = soff[key[q]] + srank[r];
-        sc[slot] = a.vals[rl[q].idx];
-        slx[slot] = rec_lx(rl[q].packed);
+        sc[slot] = cv[sb][q];
+        slx[slot] = rec_lx(rc.packed);
         swx[slot][0] = 0.f;
         swy[slot][0] = 0.f;
         swx[slot][W + 1] = 0.f;
         swy[slot][W + 1] = 0.f;
 #pragma unroll
         for (int m = 0; m < W; ++m) {
-          swx[slot][m + 1] = es_kernel_fast(rl[q].dx + (float)m, a.two_over_w, blog);
-          swy[slot][m + 1] = es_kernel_fast(rl[q].dy + (float)m, a.two_over_w, blog);
+          swx[slot][m + 1] = es_kernel_fast(rc.dx + (float)m, a.two_over_w, blog);
+          swy[slot][m + 1] = es_kernel_fast(rc.dy + (float)m, a.two_over_w, blog);
         }
       }
     }
     __syncthreads();
-    for (int ly = y0 - (W - 1); ly <= y0 + 1; ++ly) {
-      const int row = (ly + W - 1) * RS;
-      const int rs = soff[row + x0];                 // first taps from x0 - (w-1)
-      const int re = soff[row + x0 + W + 1];         // ... through x0 + 1
-      const int dy = y0 - ly + 1;
-      for (int r = rs; r < re; ++r) {
-        const int dx = x0 - slx[r] + 1;
-        const float wx0 = swx[r][dx], wx1 = swx[r][dx + 1];
-        const float wy0 = swy[r][dy], wy1 = swy[r][dy + 1];
-        const float2 c = sc[r];
-        const float p0r = c.x * wy0, p0i = c.y * wy0, p1r = c.x * wy1, p1i = c.y * wy1;
-        a00.x += p0r * wx0;
-        a00.y += p0i * wx0;
-        a01.x += p0r * wx1;
-        a01.y += p0i * wx1;
-        a10.x += p1r * wx0;
-        a10.y += p1i * wx0;
-        a11.x += p1r * wx1;
-        a11.y += p1i * wx1;
+    // candidates: first taps in rows y0-(w-1) .. y0+1 and columns x0-(w-1) ..
+    // x0+1, i.e. w+1 contiguous runs of the sorted order, walked as one loop
+    int k = 0;
+    int row = x0;                      // soff index of run k: (ly + w - 1) * RS + x0, ly = y0 - (w-1) + k
+    row += y0 * RS;
+    int r = soff[row], re = soff[row + W + 1];
+    for (;;) {
+      if (r >= re) {
+        if (++k > W) break;
+        row += RS;
+        r = soff[row];
+        re = soff[row + W + 1];
+        continue;
       }
+      const int dy = W - k;            // index of wy for output row y0
+      const int dx = x0 - slx[r] + 1;
+      const float wx0 = swx[r][dx], wx1 = swx[r][dx + 1];
+      const float wy0 = swy[r][dy], wy1 = swy[r][dy + 1];
+      const float2 c = sc[r];
+      const float p0r = c.x * wy0, p0i = c.y * wy0, p1r = c.x * wy1, p1i = c.y * wy1;
+      a00.x += p0r * wx0;
+      a00.y += p0i * wx0;
+      a01.x += p0r * wx1;
+      a01.y += p0i * wx1;
+      a10.x += p1r * wx0;
+      a10.y += p1i * wx0;
+      a11.x += p1r * wx1;
+      a11.y += p1i * wx1;
+      ++r;
     }
     __syncthreads();
   }
@@ -372,48 +439,114 @@ __global__ void __launch_bounds__(256) k_spread_reduce(SpreadReduceArgs a) {
 
 // --------------------------------------------------------- interpolation
 // One workgroup per chunk of a bin: stage the bin plus its (w - 1)-cell halo
-// of the fine grid in LDS, then every primary record gathers its w x w taps.
+// of the fine grid in LDS.  The chunk's primary records (first tap inside the
+// bin) are counting-sorted in LDS by first-tap cell, a sub-batch at a time, so
+// that the lanes of a wave gather their w x w taps from neighbouring cells
+// (distinct banks or broadcasts) instead of random ones; each record then
+// writes its caller-order slot.
 constexpr int kInterpThreads = 256;
+constexpr int kInterpSB = 512;  // records per LDS sub-batch
 
 template <int W>
 __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs a) {
   constexpr int RS = kTile + W - 1;
+  constexpr int NT = kInterpThreads, SB = kInterpSB, PER = SB / NT;
+  constexpr int NC = kTile * kTile;
   __shared__ float2 sg[RS * RS];
+  __shared__ int soff[NC + 1];
+  __shared__ float2 sd[SB];
+  __shared__ int spos[SB];
+  __shared__ int sidx[SB];
+  __shared__ int srank[SB];
   const int cid = blockIdx.x;
   if (cid >= a.nchunks[0]) return;
   const int4 ch = a.chunks[cid];
   const int bin = ch.x, start = ch.y, n = ch.z;
   const int bx = bin % a.TX, by = bin / a.TX;
-  for (int e = threadIdx.x; e < RS * RS; e += kInterpThreads) {
+  const int t = threadIdx.x;
+  for (int e = t; e < RS * RS; e += NT) {
     const int yy = e / RS, xx = e % RS;
     const int gy = by * kTile + yy, gx = bx * kTile + xx;
     sg[e] = (gy < a.L && gx < a.L) ? a.grid[(size_t)gy * a.L + gx] : czero();
   }
-  __syncthreads();
-  for (int r = threadIdx.x; r < n; r += kInterpThreads) {
-    const BinRec rec = a.recs[start + r];
-    if (!rec_primary(rec.packed)) continue;
-    const int lx = rec_lx(rec.packed), ly = rec_ly(rec.packed);
-    const float blog = a.beta * 1.4426950408889634f;
-    float wx[W];
+  const float blog = a.beta * 1.4426950408889634f;
+  for (int b0 = 0; b0 < n; b0 += SB) {
+    const int nb = min(SB, n - b0);
+    for (int e = t; e <= NC; e += NT) soff[e] = 0;
+    __syncthreads();
+    BinRec rl[PER];
+    int key[PER];
 #pragma unroll
-    for (int m = 0; m < W; ++m) wx[m] = es_kernel_fast(rec.dx + (float)m, a.two_over_w, blog);
-    float accr = 0.f, acci = 0.f;
-#pragma unroll
-    for (int my = 0; my < W; ++my) {
-      const float wy = es_kernel_fast(rec.dy + (float)my, a.two_over_w, blog);
-      const float2* row = sg + (ly + my) * RS + lx;
-      float rr = 0.f, ri = 0.f;
-#pragma unroll
-      for (int mx = 0; mx < W; ++mx) {
-        const float2 v = row[mx];
-        rr += v.x * wx[mx];
-        ri += v.y * wx[mx];
+    for (int q = 0; q < PER; ++q) {
+      const int r = t + q * NT;
+      key[q] = -1;
+      if (r < nb) {
+        rl[q] = a.recs[start + b0 + r];
+        if (rec_primary(rl[q].packed)) {
+          key[q] = rec_ly(rl[q].packed) * kTile + rec_lx(rl[q].packed);
+          srank[r] = atomicAdd(&soff[key[q]], 1);
+        }
       }
-      accr += wy * rr;
-      acci += wy * ri;
     }
-    a.out[rec.idx] = make_float2(accr, acci);
+    __syncthreads();
+    if (t < 64) {
+      constexpr int per = NC / 64;
+      const int s0 = t * per;
+      int acc = 0;
+#pragma unroll
+      for (int e = 0; e < per; ++e) acc += soff[s0 + e];
+      int incl = acc;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(incl, o, 64);
+        if (t >= o) incl += v;
+      }
+      int run = incl - acc;
+#pragma unroll
+      for (int e = 0; e < per; ++e) {
+        const int c = soff[s0 + e];
+        soff[s0 + e] = run;
+        run += c;
+      }
+      if (t == 63) soff[NC] = run;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int r = t + q * NT;
+      if (key[q] >= 0) {
+        const int slot = soff[key[q]] + srank[r];
+        sd[slot] = make_float2(rl[q].dx, rl[q].dy);
+        spos[slot] = key[q];
+        sidx[slot] = rl[q].idx;
+      }
+    }
+    __syncthreads();
+    const int np = soff[NC];
+    for (int sidx_ = t; sidx_ < np; sidx_ += NT) {
+      const float2 d = sd[sidx_];
+      const int key_ = spos[sidx_];
+      const int lx = key_ % kTile, ly = key_ / kTile;
+      float wx[W];
+#pragma unroll
+      for (int m = 0; m < W; ++m) wx[m] = es_kernel_fast(d.x + (float)m, a.two_over_w, blog);
+      float accr = 0.f, acci = 0.f;
+#pragma unroll
+      for (int my = 0; my < W; ++my) {
+        const float wy = es_kernel_fast(d.y + (float)my, a.two_over_w, blog);
+        const float2* row = sg + (ly + my) * RS + lx;
+        float rr = 0.f, ri = 0.f;
+#pragma unroll
+        for (int mx = 0; mx < W; ++mx) {
+          const float2 v = row[mx];
+          rr += v.x * wx[mx];
+          ri += v.y * wx[mx];
+        }
+        accr += wy * rr;
+        acci += wy * ri;
+      }
+      a.out[sidx[sidx_]] = make_float2(accr, acci);
+    }
+    __syncthreads();
   }
 }
 
@@ -446,17 +579,19 @@ static hipError_t bin_lds_attr(const void* k, int bytes) {
 }
 
 hipError_t launch_bin_hist(const double* x, const double* y, int64_t M, BinGeom g, int ppw, int G,
-                           uint16_t* hist, int* bad, hipStream_t st) {
+                           uint16_t* hist, hipStream_t st) {
   if (G <= 0) return hipSuccess;
-  const int T = g.TX * g.TX, bytes = ((T + 1) / 2) * 4;
+  const int T = g.TX * g.TX, bytes = ((T + 2) / 2) * 4;
   hipError_t e = bin_lds_attr((const void*)k_bin_hist, bytes);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_bin_hist, dim3(G), dim3(kBinThreads), bytes, st, x, y, M, g, ppw, hist, bad);
+  hipLaunchKernelGGL(k_bin_hist, dim3(G), dim3(kBinThreads), bytes, st, x, y, M, g, ppw, hist);
   return hipGetLastError();
 }
 
 hipError_t launch_bin_colscan(const uint16_t* hist, int G, int T, int* off, int* total, hipStream_t st) {
-  hipLaunchKernelGGL(k_bin_colscan, dim3((T + 63) / 64), dim3(64 * kColWaves), 0, st, hist, G, T, off, total);
+  const int cols = T + 1;
+  hipLaunchKernelGGL(k_bin_colscan, dim3((cols + 63) / 64), dim3(64 * kColWaves), 0, st, hist, G, cols, off,
+                     total);
   return hipGetLastError();
 }
 

@@ -83,10 +83,12 @@ struct InterpArgs {
 hipError_t launch_fill_i32(int* p, int v, int64_t n, hipStream_t st);
 // counting sort of (point, bin) pairs: hist -> colscan -> scan -> scatter
 constexpr int kBinPointsMax = 65535;  // points per binning workgroup (16-bit LDS counters)
+// hist rows and offset rows have T + 1 entries (entry T: points outside the window)
 hipError_t launch_bin_hist(const double* x, const double* y, int64_t M, BinGeom g, int ppw, int G,
-                           uint16_t* hist, int* bad, hipStream_t st);
+                           uint16_t* hist, hipStream_t st);
 hipError_t launch_bin_colscan(const uint16_t* hist, int G, int T, int* off, int* total, hipStream_t st);
-// nch[0] spread chunks, nch[1] interpolation chunks, nch[2] records, nch[3] multi-chunk bins
+// nch[0] spread chunks, nch[1] interpolation chunks, nch[2] records, nch[3] multi-chunk bins,
+// nch[4] points outside the window (counts[T])
 hipError_t launch_bin_scan(const int* counts, int T, int* cursor, int4* sp_chunks, int* sp_first,
                            int* sp_n, int* multi, int4* ip_chunks, int* nch, hipStream_t st);
 hipError_t launch_bin_scatter(const double* x, const double* y, int64_t M, BinGeom g, int ppw, int G,

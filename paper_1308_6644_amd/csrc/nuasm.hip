@@ -341,7 +341,7 @@ nuasm_status ensure_points_capacity(nuasm_plan_s* pl, int64_t M) {
   if (pl->hist) {
     (void)hipFree(pl->hist);
     (void)hipFree(pl->hoff);
-    pl->bytes -= (sizeof(uint16_t) + sizeof(int)) * pl->hist_rows * pl->T;
+    pl->bytes -= (sizeof(uint16_t) + sizeof(int)) * pl->hist_rows * (pl->T + 1);
     pl->hist = nullptr;
     pl->hoff = nullptr;
   }
@@ -350,8 +350,8 @@ nuasm_status ensure_points_capacity(nuasm_plan_s* pl, int64_t M) {
     int ppw = 0, G = 0;
     bin_ranges(cap, &ppw, &G);
     pl->hist_rows = std::max(G, 1);
-    HIP_TRY(dalloc(pl, &pl->hist, (size_t)pl->hist_rows * pl->T), "hipMalloc(bin histograms)");
-    HIP_TRY(dalloc(pl, &pl->hoff, (size_t)pl->hist_rows * pl->T), "hipMalloc(bin offsets)");
+    HIP_TRY(dalloc(pl, &pl->hist, (size_t)pl->hist_rows * (pl->T + 1)), "hipMalloc(bin histograms)");
+    HIP_TRY(dalloc(pl, &pl->hoff, (size_t)pl->hist_rows * (pl->T + 1)), "hipMalloc(bin offsets)");
   }
   HIP_TRY(dalloc(pl, &pl->recs, (size_t)(4 * cap)), "hipMalloc(records)");
   pl->chunk_cap = pl->T + (4 * cap) / kChunk + 1;
@@ -603,7 +603,7 @@ nuasm_status nuasm_plan_create(const nuasm_params* p, void* hip_stream, nuasm_pl
   if ((e = dalloc(pl, &pl->gridA, (size_t)pl->grid_elems)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(gridA)"));
   if ((e = dalloc(pl, &pl->gridB, (size_t)pl->grid_elems)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(gridB)"));
   if ((e = dalloc(pl, &pl->dinv, (size_t)Np)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(dinv)"));
-  if ((e = dalloc(pl, &pl->counts, (size_t)pl->T)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(bins)"));
+  if ((e = dalloc(pl, &pl->counts, (size_t)pl->T + 1)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(bins)"));
   if ((e = dalloc(pl, &pl->cursor, (size_t)pl->T)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(bins)"));
   if ((e = dalloc(pl, &pl->sp_first, (size_t)pl->T)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(bins)"));
   if ((e = dalloc(pl, &pl->sp_n, (size_t)pl->T)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(bins)"));
@@ -692,16 +692,15 @@ nuasm_status nuasm_set_points(nuasm_plan pl, int64_t M, const double* x, const d
   {
     int ppw = 0, G = 0;
     bin_ranges(M, &ppw, &G);
-    HIP_TRY(launch_fill_i32(pl->nch, 0, 8, st), "launch fill");
     if (M > 0) {
       {
         StageScope sc(pl, NUASM_STAGE_BIN_HIST);
-        HIP_TRY(launch_bin_hist(x, y, M, pl->bgeom, ppw, G, pl->hist, pl->nch + 4, st), "launch bin_hist");
+        HIP_TRY(launch_bin_hist(x, y, M, pl->bgeom, ppw, G, pl->hist, st), "launch bin_hist");
       }
       StageScope sc(pl, NUASM_STAGE_BIN_COLSCAN);
       HIP_TRY(launch_bin_colscan(pl->hist, G, pl->T, pl->hoff, pl->counts, st), "launch bin_colscan");
     } else {
-      HIP_TRY(launch_fill_i32(pl->counts, 0, pl->T, st), "launch fill");
+      HIP_TRY(launch_fill_i32(pl->counts, 0, pl->T + 1, st), "launch fill");
     }
     {
       StageScope sc(pl, NUASM_STAGE_BIN_SCAN);
