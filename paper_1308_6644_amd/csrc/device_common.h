@@ -83,9 +83,35 @@ struct Dft<1, DIR> {
 __device__ __forceinline__ int pidx(int e) { return e + (e >> 4); }
 __host__ __device__ constexpr int lds_elems(int n) { return n + (n >> 4) + 1; }
 
+// Two-level twiddle table for length N = 2^LOGN, held in LDS:
+// hi[i] = exp(-2 pi i 64 i / N) for i < HI, lo[j] = exp(-2 pi i j / N) for
+// j < 64, so exp(-2 pi i m / N) = hi[m >> 6] * lo[m & 63] for every m < N
+// (one complex product, about one float32 ulp).  Staging it costs SIZE
+// entries instead of N and keeps twiddles out of global memory.
+template <int LOGN>
+struct Tw2 {
+  static constexpr int N = 1 << LOGN;
+  static constexpr int HI = N >= 64 ? N / 64 : 1;
+  static constexpr int SIZE = HI + 64;
+};
+
+// Fill dst[0 .. Tw2::SIZE) from the global table tw[m] = exp(-2 pi i m / N).
+template <int LOGN, int NT>
+__device__ __forceinline__ void load_tw2(float2* __restrict__ dst, const float2* __restrict__ tw) {
+  using T = Tw2<LOGN>;
+  for (int e = threadIdx.x; e < T::SIZE; e += NT)
+    dst[e] = e < T::HI ? tw[(e * 64) & (T::N - 1)] : tw[(e - T::HI) & (T::N - 1)];
+}
+
+template <int LOGN>
+__device__ __forceinline__ float2 tw2_get(const float2* __restrict__ t, int m) {
+  return cmul(t[m >> 6], t[Tw2<LOGN>::HI + (m & 63)]);
+}
+
 // One radix-R Stockham pass over C interleaved transforms of length N held in
 // LDS (element t of transform c at pidx(t * C + c)), NT threads.  P is the
-// product of the radices of the earlier passes.  tw[m] = exp(-2 pi i m / N).
+// product of the radices of the earlier passes.  tw is the LDS two-level
+// twiddle table of length N (see Tw2).
 template <int LOGN, int C, int NT, int DIR, int R, int P>
 __device__ __forceinline__ void stockham_pass(float2* __restrict__ s, const float2* __restrict__ tw) {
   constexpr int N = 1 << LOGN;
@@ -106,7 +132,7 @@ __device__ __forceinline__ void stockham_pass(float2* __restrict__ s, const floa
       for (int j = 0; j < R; ++j) x[q][j] = s[pidx((i + j * NR) * C + c)];
       if (P > 1) {
 #pragma unroll
-        for (int j = 1; j < R; ++j) w[q][j] = tw[j * k * TWS];
+        for (int j = 1; j < R; ++j) w[q][j] = tw2_get<LOGN>(tw, j * k * TWS);
       }
     }
   }
@@ -149,8 +175,9 @@ struct FftPasses<LOGN, C, NT, DIR, P, 0> {
 };
 
 // Unnormalised in-LDS FFT of C interleaved transforms of length 2^LOGN,
-// kernel exp(DIR * 2 pi i t k / N).  Must be entered by all NT threads after
-// the data is in LDS and a barrier; ends with a barrier.
+// kernel exp(DIR * 2 pi i t k / N).  tw is the LDS two-level twiddle table of
+// that length.  Must be entered by all NT threads after the data and the
+// table are in LDS and a barrier; ends with a barrier.
 template <int LOGN, int C, int NT, int DIR>
 __device__ __forceinline__ void fft_lds(float2* s, const float2* tw) {
   FftPasses<LOGN, C, NT, DIR, 1, LOGN>::run(s, tw);

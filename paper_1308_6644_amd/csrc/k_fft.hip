@@ -19,7 +19,8 @@ struct RowCfg {
   static constexpr int C = N >= 4096 ? 1 : 4096 / N;
   static constexpr int NB = C * N / 16;
   static constexpr int NT = NB < 64 ? 64 : (NB > 1024 ? 1024 : NB);
-  static constexpr int LDS = lds_elems(C * N) * 8;
+  static constexpr int DATA = lds_elems(C * N);  // complex elements of data
+  static constexpr int LDS = (DATA + Tw2<LOGN>::SIZE) * 8;
 };
 
 // Column passes: C adjacent columns per workgroup sized so that C columns of
@@ -31,7 +32,9 @@ struct ColCfg {
   static constexpr int C = C0 < 1 ? 1 : (C0 > 16 ? 16 : C0);
   static constexpr int NB = C * NF / 16;
   static constexpr int NT = NB < 64 ? 64 : (NB > 1024 ? 1024 : NB);
-  static constexpr int LDS = lds_elems(C * NF) * 8;
+  static constexpr int DATA = lds_elems(C * NF);
+  // twiddle tables for the fine length and for N' = NF / 2
+  static constexpr int LDS = (DATA + Tw2<LOGNF>::SIZE + Tw2<LOGNF - 1>::SIZE) * 8;
 };
 
 __device__ __forceinline__ bool in_band(int k, int lo, int hi) { return k >= lo && k <= hi; }
@@ -80,6 +83,8 @@ k_t1_rows(const float2* __restrict__ fine, float2* __restrict__ T, GridGeom g,
   using Cfg = RowCfg<LOGN>;
   constexpr int C = Cfg::C, NT = Cfg::NT;
   extern __shared__ float2 s[];
+  float2* tw = s + Cfg::DATA;
+  load_tw2<LOGN, NT>(tw, tw_for(twall, LOGN));
   const int r0 = blockIdx.x * C;
   const int L = g.L, s0 = g.s0;
   for (int e = threadIdx.x; e < C * NF; e += NT) {
@@ -90,7 +95,7 @@ k_t1_rows(const float2* __restrict__ fine, float2* __restrict__ T, GridGeom g,
     s[pidx(t * C + c)] = v;
   }
   __syncthreads();
-  fft_lds<LOGN, C, NT, -1>(s, tw_for(twall, LOGN));
+  fft_lds<LOGN, C, NT, -1>(s, tw);
   for (int e = threadIdx.x; e < C * NP; e += NT) {
     const int c = e / NP, a = e % NP;
     const int row = r0 + c, kx = a - NP / 2;
@@ -115,6 +120,10 @@ k_t1_cols(const float2* __restrict__ T, float2* __restrict__ V, GridGeom g, Spec
   const int a0 = strip * C;
   const int kx0 = a0 - NP / 2;
   if (kx0 + C - 1 < g.kxlo || kx0 > g.kxhi) return;  // whole strip outside the band
+  float2* twf = s + Cfg::DATA;
+  float2* twp = twf + Tw2<LOGN>::SIZE;
+  load_tw2<LOGN, NT>(twf, tw_for(twall, LOGN));
+  load_tw2<LOGNP, NT>(twp, tw_for(twall, LOGNP));
   const int L = g.L, s0 = g.s0;
   for (int e = threadIdx.x; e < C * NF; e += NT) {
     const int t = e / C, c = e % C;
@@ -124,7 +133,7 @@ k_t1_cols(const float2* __restrict__ T, float2* __restrict__ V, GridGeom g, Spec
     s[pidx(e)] = v;
   }
   __syncthreads();
-  fft_lds<LOGN, C, NT, -1>(s, tw_for(twall, LOGN));
+  fft_lds<LOGN, C, NT, -1>(s, twf);
   constexpr int PER = (C * NP + NT - 1) / NT;
   float2 v[PER];
 #pragma unroll
@@ -149,7 +158,7 @@ k_t1_cols(const float2* __restrict__ T, float2* __restrict__ V, GridGeom g, Spec
     if (e < C * NP) s[pidx(e)] = v[q];
   }
   __syncthreads();
-  fft_lds<LOGNP, C, NT, +1>(s, tw_for(twall, LOGNP));
+  fft_lds<LOGNP, C, NT, +1>(s, twp);
   for (int e = threadIdx.x; e < C * NP; e += NT) {
     const int by = e / C, c = e % C;
     if (in_band(kx0 + c, g.kxlo, g.kxhi)) {
@@ -170,6 +179,8 @@ k_t1_rows_inv(const float2* __restrict__ V, float2* __restrict__ out, GridGeom g
   using Cfg = RowCfg<LOGNP>;
   constexpr int C = Cfg::C, NT = Cfg::NT;
   extern __shared__ float2 s[];
+  float2* tw = s + Cfg::DATA;
+  load_tw2<LOGNP, NT>(tw, tw_for(twall, LOGNP));
   const int nrows = g.crop ? g.N : NP;
   const int rowoff = g.crop ? g.N / 2 : 0;
   const int r0 = blockIdx.x * C;
@@ -181,7 +192,7 @@ k_t1_rows_inv(const float2* __restrict__ V, float2* __restrict__ out, GridGeom g
     s[pidx(a * C + c)] = v;
   }
   __syncthreads();
-  fft_lds<LOGNP, C, NT, +1>(s, tw_for(twall, LOGNP));
+  fft_lds<LOGNP, C, NT, +1>(s, tw);
   for (int e = threadIdx.x; e < C * NP; e += NT) {
     const int c = e / NP, bx = e % NP;
     const int r = r0 + c;
@@ -208,6 +219,8 @@ k_t2_rows(const float2* __restrict__ u1, float2* __restrict__ T, GridGeom g,
   using Cfg = RowCfg<LOGNP>;
   constexpr int C = Cfg::C, NT = Cfg::NT;
   extern __shared__ float2 s[];
+  float2* tw = s + Cfg::DATA;
+  load_tw2<LOGNP, NT>(tw, tw_for(twall, LOGNP));
   const int Nin = g.Nin;
   const int r0 = blockIdx.x * C;
   for (int e = threadIdx.x; e < C * NP; e += NT) {
@@ -219,7 +232,7 @@ k_t2_rows(const float2* __restrict__ u1, float2* __restrict__ T, GridGeom g,
     s[pidx(t * C + c)] = v;
   }
   __syncthreads();
-  fft_lds<LOGNP, C, NT, -1>(s, tw_for(twall, LOGNP));
+  fft_lds<LOGNP, C, NT, -1>(s, tw);
   for (int e = threadIdx.x; e < C * NP; e += NT) {
     const int c = e / NP, a = e % NP;
     const int r = r0 + c, kx = a - NP / 2;
@@ -246,6 +259,10 @@ k_t2_cols(const float2* __restrict__ T, float2* __restrict__ V, GridGeom g, Spec
   const int a0 = strip * C;
   const int kx0 = a0 - NP / 2;
   if (kx0 + C - 1 < g.kxlo || kx0 > g.kxhi) return;
+  float2* twf = s + Cfg::DATA;
+  float2* twp = twf + Tw2<LOGN>::SIZE;
+  load_tw2<LOGN, NT>(twf, tw_for(twall, LOGN));
+  load_tw2<LOGNP, NT>(twp, tw_for(twall, LOGNP));
   const int Nin = g.Nin;
   for (int e = threadIdx.x; e < C * NP; e += NT) {
     const int t = e / C, c = e % C;
@@ -256,7 +273,7 @@ k_t2_cols(const float2* __restrict__ T, float2* __restrict__ V, GridGeom g, Spec
     s[pidx(e)] = v;
   }
   __syncthreads();
-  fft_lds<LOGNP, C, NT, -1>(s, tw_for(twall, LOGNP));
+  fft_lds<LOGNP, C, NT, -1>(s, twp);
   constexpr int PER = (C * NP + NT - 1) / NT;
   float2 v[PER];
 #pragma unroll
@@ -290,7 +307,7 @@ k_t2_cols(const float2* __restrict__ T, float2* __restrict__ V, GridGeom g, Spec
     }
   }
   __syncthreads();
-  fft_lds<LOGN, C, NT, +1>(s, tw_for(twall, LOGN));
+  fft_lds<LOGN, C, NT, +1>(s, twf);
   const int L = g.L, s0 = g.s0;
   for (int e = threadIdx.x; e < C * L; e += NT) {
     const int i = e / C, c = e % C;
@@ -308,6 +325,8 @@ k_t2_rows_inv(const float2* __restrict__ V, float2* __restrict__ fine, GridGeom 
   using Cfg = RowCfg<LOGN>;
   constexpr int C = Cfg::C, NT = Cfg::NT;
   extern __shared__ float2 s[];
+  float2* tw = s + Cfg::DATA;
+  load_tw2<LOGN, NT>(tw, tw_for(twall, LOGN));
   const int L = g.L, s0 = g.s0;
   const int r0 = blockIdx.x * C;
   for (int e = threadIdx.x; e < C * NF; e += NT) {
@@ -321,7 +340,7 @@ k_t2_rows_inv(const float2* __restrict__ V, float2* __restrict__ fine, GridGeom 
     s[pidx(t * C + c)] = v;
   }
   __syncthreads();
-  fft_lds<LOGN, C, NT, +1>(s, tw_for(twall, LOGN));
+  fft_lds<LOGN, C, NT, +1>(s, tw);
   for (int e = threadIdx.x; e < C * L; e += NT) {
     const int c = e / L, i = e % L;
     const int r = r0 + c;
@@ -338,6 +357,8 @@ k_fft_rows(const float2* __restrict__ in, float2* __restrict__ out, int64_t batc
   using Cfg = RowCfg<LOGN>;
   constexpr int C = Cfg::C, NT = Cfg::NT;
   extern __shared__ float2 s[];
+  float2* tw = s + Cfg::DATA;
+  load_tw2<LOGN, NT>(tw, tw_for(twall, LOGN));
   const int64_t r0 = (int64_t)blockIdx.x * C;
   for (int e = threadIdx.x; e < C * N; e += NT) {
     const int c = e / N, t = e % N;
@@ -345,7 +366,7 @@ k_fft_rows(const float2* __restrict__ in, float2* __restrict__ out, int64_t batc
     s[pidx(t * C + c)] = r < batch ? in[r * N + t] : czero();
   }
   __syncthreads();
-  fft_lds<LOGN, C, NT, DIR>(s, tw_for(twall, LOGN));
+  fft_lds<LOGN, C, NT, DIR>(s, tw);
   for (int e = threadIdx.x; e < C * N; e += NT) {
     const int c = e / N, t = e % N;
     const int64_t r = r0 + c;
