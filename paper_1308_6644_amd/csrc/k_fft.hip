@@ -23,12 +23,14 @@ struct RowCfg {
   static constexpr int LDS = (DATA + Tw2<LOGN>::SIZE) * 8;
 };
 
-// Column passes: C adjacent columns per workgroup sized so that C columns of
-// the fine length fit in LDS (C * nf <= 16384 complex values, <= 140 KB).
+// Column passes: C adjacent columns per workgroup, C * nf = kColElems complex
+// values in LDS (one column when nf exceeds it), two workgroups per CU.
+constexpr int kColElems = 8192;  // complex values of fine length held per column workgroup
+
 template <int LOGNF>
 struct ColCfg {
   static constexpr int NF = 1 << LOGNF;
-  static constexpr int C0 = 16384 / NF;
+  static constexpr int C0 = kColElems / NF;
   static constexpr int C = C0 < 1 ? 1 : (C0 > 16 ? 16 : C0);
   static constexpr int NB = C * NF / 16;
   static constexpr int NT = NB < 64 ? 64 : (NB > 1024 ? 1024 : NB);
@@ -38,6 +40,24 @@ struct ColCfg {
 };
 
 __device__ __forceinline__ bool in_band(int k, int lo, int hi) { return k >= lo && k <= hi; }
+
+// float64 square root and reciprocal from the hardware seeds (v_rsq_f64,
+// v_rcp_f64) refined by Newton steps: each step squares the relative error,
+// so two steps from the ~2^-23 seeds are far below 2^-53; a final
+// residual correction gives sqrt to about one ulp.
+__device__ __forceinline__ double sqrt_nr(double r) {
+  double y = __builtin_amdgcn_rsq(r);
+  y = y * (1.5 - 0.5 * r * y * y);
+  y = y * (1.5 - 0.5 * r * y * y);
+  const double s = r * y;
+  return s + 0.5 * y * (r - s * s);
+}
+__device__ __forceinline__ double rcp_nr(double d) {
+  double x = __builtin_amdgcn_rcp(d);
+  x = x * (2.0 - d * x);
+  x = x * (2.0 - d * x);
+  return x + x * (1.0 - d * x);
+}
 
 // Transfer function of Eq. 4 (ASM) or Eq. 5 (Fresnel) at integer frequency
 // (kx, ky), without the Rect.  The ASM phase is formed in cycles:
@@ -52,8 +72,8 @@ __device__ __forceinline__ float2 transfer_at(const Spectral& sp, int Np, int kx
     const double k2 = (double)kx * kx + (double)ky * ky;
     const double r = sp.inv_lam2 - sp.q * k2;
     if (r < 0.0) return czero();
-    const double s = sqrt(r);
-    double cyc = sp.c0 + sp.ax * kx + sp.ay * ky - sp.zq * k2 / (sp.inv_lam + s);
+    const double s = r > 0.0 ? sqrt_nr(r) : 0.0;
+    double cyc = sp.c0 + sp.ax * kx + sp.ay * ky - sp.zq * k2 * rcp_nr(sp.inv_lam + s);
     cyc -= rint(cyc);
     float sn, cs;
     sincospif(2.0f * (float)cyc, &sn, &cs);

@@ -54,6 +54,7 @@ __device__ __forceinline__ PointCells point_cells(double x, double y, const BinG
 // bases.  Pass 2 re-derives the pairs and ranks them inside (range, bin) with
 // LDS counters, so every slot is written exactly once.
 constexpr int kBinThreads = 512;
+constexpr int kBinBatch = 8;  // points per thread whose coordinates are loaded together
 
 __device__ __forceinline__ unsigned lds_bump16(unsigned* sh, int b) {
   const int sft = (b & 1) * 16;
@@ -71,16 +72,28 @@ k_bin_hist(const double* __restrict__ x, const double* __restrict__ y, int64_t M
   __syncthreads();
   const int64_t j0 = (int64_t)blockIdx.x * ppw;
   const int64_t j1 = min(M, j0 + ppw);
-  for (int64_t j = j0 + threadIdx.x; j < j1; j += kBinThreads) {
-    const PointCells pc = point_cells(x[j], y[j], g);
-    if (!pc.ok) {
-      lds_bump16(sh, T);
-      continue;
+  for (int64_t jb = j0; jb < j1; jb += kBinThreads * kBinBatch) {
+    double xv[kBinBatch], yv[kBinBatch];  // all loads of a batch in flight together
+#pragma unroll
+    for (int q = 0; q < kBinBatch; ++q) {
+      const int64_t j = jb + threadIdx.x + q * kBinThreads;
+      xv[q] = j < j1 ? x[j] : 0.0;
+      yv[q] = j < j1 ? y[j] : 0.0;
     }
-    const int bx0 = pc.i0x / kTile, bx1 = (pc.i0x + g.w - 1) / kTile;
-    const int by0 = pc.i0y / kTile, by1 = (pc.i0y + g.w - 1) / kTile;
-    for (int by = by0; by <= by1; ++by)
-      for (int bx = bx0; bx <= bx1; ++bx) lds_bump16(sh, by * g.TX + bx);
+#pragma unroll
+    for (int q = 0; q < kBinBatch; ++q) {
+      const int64_t j = jb + threadIdx.x + q * kBinThreads;
+      if (j >= j1) continue;
+      const PointCells pc = point_cells(xv[q], yv[q], g);
+      if (!pc.ok) {
+        lds_bump16(sh, T);
+        continue;
+      }
+      const int bx0 = pc.i0x / kTile, bx1 = (pc.i0x + g.w - 1) / kTile;
+      const int by0 = pc.i0y / kTile, by1 = (pc.i0y + g.w - 1) / kTile;
+      for (int by = by0; by <= by1; ++by)
+        for (int bx = bx0; bx <= bx1; ++bx) lds_bump16(sh, by * g.TX + bx);
+    }
   }
   __syncthreads();
   uint16_t* row = hist + (size_t)blockIdx.x * (T + 1);
@@ -131,8 +144,19 @@ k_bin_scatter(const double* __restrict__ x, const double* __restrict__ y, int64_
   const int64_t j0 = (int64_t)blockIdx.x * ppw;
   const int64_t j1 = min(M, j0 + ppw);
   const int* myoff = off + (size_t)blockIdx.x * (T + 1);
-  for (int64_t j = j0 + threadIdx.x; j < j1; j += kBinThreads) {
-    const PointCells pc = point_cells(x[j], y[j], g);
+  for (int64_t jb = j0; jb < j1; jb += kBinThreads * kBinBatch) {
+   double xv[kBinBatch], yv[kBinBatch];
+#pragma unroll
+   for (int q = 0; q < kBinBatch; ++q) {
+     const int64_t j = jb + threadIdx.x + q * kBinThreads;
+     xv[q] = j < j1 ? x[j] : 0.0;
+     yv[q] = j < j1 ? y[j] : 0.0;
+   }
+#pragma unroll
+   for (int q = 0; q < kBinBatch; ++q) {
+    const int64_t j = jb + threadIdx.x + q * kBinThreads;
+    if (j >= j1) continue;
+    const PointCells pc = point_cells(xv[q], yv[q], g);
     if (!pc.ok) continue;
     const int bx0 = pc.i0x / kTile, bx1 = (pc.i0x + g.w - 1) / kTile;
     const int by0 = pc.i0y / kTile, by1 = (pc.i0y + g.w - 1) / kTile;
@@ -148,6 +172,7 @@ k_bin_scatter(const double* __restrict__ x, const double* __restrict__ y, int64_
         r.idx = (int32_t)j;
         recs[slot] = r;
       }
+   }
   }
 }
 
@@ -383,21 +408,42 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(SpreadArgs a) {
         re = soff[row + W + 1];
         continue;
       }
+      // two candidates of the run per iteration when it has them, so their
+      // LDS reads are in flight together; the second is masked by a zero value
       const int dy = W - k;            // index of wy for output row y0
-      const int dx = x0 - slx[r] + 1;
-      const float wx0 = swx[r][dx], wx1 = swx[r][dx + 1];
-      const float wy0 = swy[r][dy], wy1 = swy[r][dy + 1];
-      const float2 c = sc[r];
-      const float p0r = c.x * wy0, p0i = c.y * wy0, p1r = c.x * wy1, p1i = c.y * wy1;
-      a00.x += p0r * wx0;
-      a00.y += p0i * wx0;
-      a01.x += p0r * wx1;
-      a01.y += p0i * wx1;
-      a10.x += p1r * wx0;
-      a10.y += p1i * wx0;
-      a11.x += p1r * wx1;
-      a11.y += p1i * wx1;
-      ++r;
+      const bool two = r + 1 < re;
+      const int r2 = two ? r + 1 : r;
+      const int dxa = x0 - slx[r] + 1, dxb = x0 - slx[r2] + 1;
+      const float wa0 = swx[r][dxa], wa1 = swx[r][dxa + 1];
+      const float wb0 = swx[r2][dxb], wb1 = swx[r2][dxb + 1];
+      const float ya0 = swy[r][dy], ya1 = swy[r][dy + 1];
+      const float yb0 = swy[r2][dy], yb1 = swy[r2][dy + 1];
+      const float2 ca = sc[r];
+      float2 cb = sc[r2];
+      if (!two) cb = czero();
+      {
+        const float p0r = ca.x * ya0, p0i = ca.y * ya0, p1r = ca.x * ya1, p1i = ca.y * ya1;
+        a00.x += p0r * wa0;
+        a00.y += p0i * wa0;
+        a01.x += p0r * wa1;
+        a01.y += p0i * wa1;
+        a10.x += p1r * wa0;
+        a10.y += p1i * wa0;
+        a11.x += p1r * wa1;
+        a11.y += p1i * wa1;
+      }
+      {
+        const float p0r = cb.x * yb0, p0i = cb.y * yb0, p1r = cb.x * yb1, p1i = cb.y * yb1;
+        a00.x += p0r * wb0;
+        a00.y += p0i * wb0;
+        a01.x += p0r * wb1;
+        a01.y += p0i * wb1;
+        a10.x += p1r * wb0;
+        a10.y += p1i * wb0;
+        a11.x += p1r * wb1;
+        a11.y += p1i * wb1;
+      }
+      r += 2;
     }
     __syncthreads();
   }
