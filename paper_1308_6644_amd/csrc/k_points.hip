@@ -179,13 +179,23 @@ k_bin_scatter(const double* __restrict__ x, const double* __restrict__ y, int64_
 // Single-workgroup scan over the bins: first record of every bin (written to
 // `cursor`, the bin bases the scatter adds), and the chunk tables.  Spreading
 // needs a chunk for every bin (empty bins write zeros); interpolation only for
-// non-empty bins.  A bin with more than kChunk records is split into several
-// chunks; for spreading those bins are listed in `multi` for the reduction.
+// non-empty bins.  A bin with more than kSpreadChunk (kChunk) records is split
+// into several spreading (interpolation) chunks; for spreading those bins are
+// listed in `multi` for the reduction.  Spreading chunks are ordered by the
+// size of their bin, largest first (17 size classes, a bin's chunks kept
+// together), so that the dispatcher starts the longest workgroups first.
 // counts[T] (one past the bins) is the number of points outside the window;
 // it is copied to nch[4].  Each thread owns a contiguous run of bins; the
 // block-wide exclusive scan is two wave-shuffle scans around one LDS step.
 constexpr int kScanThreads = 1024;
 constexpr int kScanRegs = 8;  // bins per thread kept in registers
+constexpr int kSizeClasses = 17;
+
+// size class of a bin's spreading chunks: 16 for bins of at least one full
+// chunk, else 16 c / kSpreadChunk
+__device__ __forceinline__ int size_class(int c) {
+  return c >= kSpreadChunk ? kSizeClasses - 1 : (c * (kSizeClasses - 1)) / kSpreadChunk;
+}
 
 __device__ __forceinline__ int wave_incl_scan(int v, int lane) {
 #pragma unroll
@@ -202,12 +212,15 @@ k_bin_scan(const int* __restrict__ counts, int T, int* __restrict__ cursor, int4
            int4* __restrict__ ip_chunks, int* __restrict__ nch) {
   constexpr int NW = kScanThreads / 64;
   __shared__ int wsum[4][NW];
+  __shared__ int cls_n[kSizeClasses], cls_base[kSizeClasses];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (tid < kSizeClasses) cls_n[tid] = 0;
   const int per = (T + kScanThreads - 1) / kScanThreads;
   const int b0 = min(T, tid * per), b1 = min(T, b0 + per);
   int cr[kScanRegs];
 #pragma unroll
   for (int q = 0; q < kScanRegs; ++q) cr[q] = (b0 + q < b1) ? counts[b0 + q] : 0;
+  __syncthreads();  // cls_n cleared
   int acc[4] = {0, 0, 0, 0};  // records, spread chunks, interp chunks, multi bins
   for (int b = b0; b < b1; ++b) {
     const int q = b - b0;
@@ -216,11 +229,12 @@ k_bin_scan(const int* __restrict__ counts, int T, int* __restrict__ cursor, int4
     for (int r = 0; r < kScanRegs; ++r)
       if (r == q) c = cr[r];
     if (q >= kScanRegs) c = counts[b];
-    const int nsp = c > kChunk ? (c + kChunk - 1) / kChunk : 1;
+    const int nsp = c > kSpreadChunk ? (c + kSpreadChunk - 1) / kSpreadChunk : 1;
     acc[0] += c;
     acc[1] += nsp;
     acc[2] += (c + kChunk - 1) / kChunk;
     acc[3] += nsp > 1 ? 1 : 0;
+    atomicAdd(&cls_n[size_class(c)], nsp);
   }
   int incl[4];
 #pragma unroll
@@ -237,6 +251,13 @@ k_bin_scan(const int* __restrict__ counts, int T, int* __restrict__ cursor, int4
       if (lane < NW) wsum[k][lane] = w - v;  // exclusive wave bases
     }
   }
+  if (tid == 0) {  // chunk bases of the size classes, largest class first
+    int run = 0;
+    for (int k = kSizeClasses - 1; k >= 0; --k) {
+      cls_base[k] = run;
+      run += cls_n[k];
+    }
+  }
   __syncthreads();
   int run[4];
 #pragma unroll
@@ -248,13 +269,15 @@ k_bin_scan(const int* __restrict__ counts, int T, int* __restrict__ cursor, int4
     for (int r = 0; r < kScanRegs; ++r)
       if (r == q) c = cr[r];
     if (q >= kScanRegs) c = counts[b];
-    const int nsp = c > kChunk ? (c + kChunk - 1) / kChunk : 1;
+    const int nsp = c > kSpreadChunk ? (c + kSpreadChunk - 1) / kSpreadChunk : 1;
     const int nip = (c + kChunk - 1) / kChunk;
+    const int first = atomicAdd(&cls_base[size_class(c)], nsp);
     cursor[b] = run[0];
-    sp_first[b] = run[1];
+    sp_first[b] = first;
     sp_n[b] = nsp;
     for (int r = 0; r < nsp; ++r)
-      sp_chunks[run[1] + r] = make_int4(b, run[0] + r * kChunk, min(kChunk, c - r * kChunk), nsp);
+      sp_chunks[first + r] =
+          make_int4(b, run[0] + r * kSpreadChunk, min(kSpreadChunk, c - r * kSpreadChunk), nsp);
     for (int r = 0; r < nip; ++r)
       ip_chunks[run[2] + r] = make_int4(b, run[0] + r * kChunk, min(kChunk, c - r * kChunk), nip);
     if (nsp > 1) multi[run[3]] = b;
@@ -294,24 +317,31 @@ __device__ __forceinline__ float es_kernel_fast(float d, float two_over_w, float
 
 template <int W>
 struct SpreadCfg {
-  static constexpr int SB = W <= 8 ? 512 : 256;  // records per LDS sub-batch
+  static constexpr int SB = W <= 8 ? 448 : 256;  // records per LDS sub-batch (4 workgroups per CU at w = 7)
   static constexpr int RS = kTile + W - 1;       // first-tap cells per axis
   static constexpr int NC = RS * RS;
   static constexpr int WP = W + 2;               // padded weights, d = -1 .. w
+  static_assert(kSpreadChunk % SB == 0, "a spreading chunk is a whole number of sub-batches");
 };
+
+// 16-bit counters packed two per LDS word (a sub-batch has at most 448
+// records): returns the count before the increment.
+__device__ __forceinline__ int lds_bump16s(unsigned short* cnt, int k) {
+  const int sft = (k & 1) * 16;
+  return (int)((atomicAdd(reinterpret_cast<unsigned*>(cnt) + (k >> 1), 1u << sft) >> sft) & 0xffffu);
+}
 
 template <int W>
 __global__ void __launch_bounds__(kSpreadThreads) k_spread(SpreadArgs a) {
   using Cfg = SpreadCfg<W>;
   constexpr int SB = Cfg::SB, RS = Cfg::RS, NC = Cfg::NC, WP = Cfg::WP, NT = kSpreadThreads;
-  constexpr int PER = SB / NT;        // records per thread per sub-batch
-  constexpr int NSUB = kChunk / SB;   // sub-batches per chunk
+  constexpr int PER = (SB + NT - 1) / NT;  // records per thread per sub-batch
+  constexpr int NSUB = kSpreadChunk / SB;  // sub-batches per chunk
   __shared__ float2 sc[SB];
   __shared__ float swx[SB][WP];
   __shared__ float swy[SB][WP];
   __shared__ int slx[SB];
-  __shared__ int soff[NC + 1];
-  __shared__ int srank[SB];
+  __shared__ __align__(4) unsigned short soff[(NC + 2) & ~1];  // cell counts, then offsets
   const int cid = blockIdx.x;
   if (cid >= a.nchunks[0]) return;
   const int4 ch = a.chunks[cid];
@@ -327,14 +357,14 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(SpreadArgs a) {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int r = sb * SB + t + q * NT;
-      if (r < n) rl[sb][q] = a.recs[start + r];
+      if (t + q * NT < SB && r < n) rl[sb][q] = a.recs[start + r];
     }
 #pragma unroll
   for (int sb = 0; sb < NSUB; ++sb)
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int r = sb * SB + t + q * NT;
-      cv[sb][q] = r < n ? a.vals[rl[sb][q].idx] : czero();
+      cv[sb][q] = (t + q * NT < SB && r < n) ? a.vals[rl[sb][q].idx] : czero();
     }
   float2 a00 = czero(), a01 = czero(), a10 = czero(), a11 = czero();
 #pragma unroll
@@ -344,14 +374,15 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(SpreadArgs a) {
     const int nsb = min(SB, n - b0);
     for (int e = t; e <= NC; e += NT) soff[e] = 0;
     __syncthreads();
-    int key[PER];
+    int key[PER], rank[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int r = t + q * NT;
       key[q] = 0;
+      rank[q] = 0;
       if (r < nsb) {
         key[q] = (rec_ly(rl[sb][q].packed) + W - 1) * RS + rec_lx(rl[sb][q].packed) + W - 1;
-        srank[r] = atomicAdd(&soff[key[q]], 1);
+        rank[q] = lds_bump16s(soff, key[q]);
       }
     }
     __syncthreads();
@@ -379,7 +410,7 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(SpreadArgs a) {
       const int r = t + q * NT;
       if (r < nsb) {
         const BinRec& rc = rl[sb][q];
-        const int slot = soff[key[q]] + srank[r];
+        const int slot = soff[key[q]] + rank[q];
         sc[slot] = cv[sb][q];
         slx[slot] = rec_lx(rc.packed);
         swx[slot][0] = 0.f;

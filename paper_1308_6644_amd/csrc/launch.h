@@ -10,7 +10,8 @@ namespace nuasm {
 
 constexpr int kTile = 32;        // fine cells per bin side
 constexpr int kPad = 8;          // support margin: taps reach w/2 <= 8 cells past the window
-constexpr int kChunk = 2048;     // max records per spreading / interpolation workgroup
+constexpr int kChunk = 2048;       // max records per interpolation workgroup
+constexpr int kSpreadChunk = 1792; // max records per spreading workgroup
 constexpr int kMaxW = 16;
 
 // Geometry of the fine-grid support and of the uniform planes.

@@ -354,7 +354,7 @@ nuasm_status ensure_points_capacity(nuasm_plan_s* pl, int64_t M) {
     HIP_TRY(dalloc(pl, &pl->hoff, (size_t)pl->hist_rows * (pl->T + 1)), "hipMalloc(bin offsets)");
   }
   HIP_TRY(dalloc(pl, &pl->recs, (size_t)(4 * cap)), "hipMalloc(records)");
-  pl->chunk_cap = pl->T + (4 * cap) / kChunk + 1;
+  pl->chunk_cap = pl->T + (4 * cap) / kSpreadChunk + 1;  // covers both chunk tables
   HIP_TRY(dalloc(pl, &pl->sp_chunks, (size_t)pl->chunk_cap), "hipMalloc(chunks)");
   HIP_TRY(dalloc(pl, &pl->ip_chunks, (size_t)pl->chunk_cap), "hipMalloc(chunks)");
   pl->rec_cap = cap;
@@ -369,13 +369,13 @@ nuasm_status ensure_scratch(nuasm_plan_s* pl) {
 }
 
 int sp_grid(const nuasm_plan_s* pl) {
-  return pl->synced ? pl->exact_sp : (int)std::min<int64_t>(pl->chunk_cap, pl->T + (4 * pl->M) / kChunk + 1);
+  return pl->synced ? pl->exact_sp : (int)std::min<int64_t>(pl->chunk_cap, pl->T + (4 * pl->M) / kSpreadChunk + 1);
 }
 int ip_grid(const nuasm_plan_s* pl) {
   return pl->synced ? pl->exact_ip : (int)std::min<int64_t>(pl->chunk_cap, pl->T + (4 * pl->M) / kChunk + 1);
 }
 int multi_grid(const nuasm_plan_s* pl) {
-  return pl->synced ? pl->exact_multi : (int)std::min<int64_t>(pl->T, (4 * pl->M) / kChunk + 1);
+  return pl->synced ? pl->exact_multi : (int)std::min<int64_t>(pl->T, (4 * pl->M) / kSpreadChunk + 1);
 }
 
 // type-1 pipeline: values at the points -> N' x N' (or N x N) plane
