@@ -181,7 +181,7 @@ k_bin_scatter(const double* __restrict__ x, const double* __restrict__ y, int64_
 // needs a chunk for every bin (empty bins write zeros); interpolation only for
 // non-empty bins.  A bin with more than kSpreadChunk (kChunk) records is split
 // into several spreading (interpolation) chunks; for spreading those bins are
-// listed in `multi` for the reduction.  Spreading chunks are ordered by the
+// listed in `multi` for the reduction.  Both chunk tables are ordered by the
 // size of their bin, largest first (17 size classes, a bin's chunks kept
 // together), so that the dispatcher starts the longest workgroups first.
 // counts[T] (one past the bins) is the number of points outside the window;
@@ -191,10 +191,10 @@ constexpr int kScanThreads = 1024;
 constexpr int kScanRegs = 8;  // bins per thread kept in registers
 constexpr int kSizeClasses = 17;
 
-// size class of a bin's spreading chunks: 16 for bins of at least one full
-// chunk, else 16 c / kSpreadChunk
-__device__ __forceinline__ int size_class(int c) {
-  return c >= kSpreadChunk ? kSizeClasses - 1 : (c * (kSizeClasses - 1)) / kSpreadChunk;
+// size class of a bin's chunks of at most `chunk` records: 16 for bins of at
+// least one full chunk, else 16 c / chunk
+__device__ __forceinline__ int size_class(int c, int chunk) {
+  return c >= chunk ? kSizeClasses - 1 : (c * (kSizeClasses - 1)) / chunk;
 }
 
 __device__ __forceinline__ int wave_incl_scan(int v, int lane) {
@@ -212,9 +212,9 @@ k_bin_scan(const int* __restrict__ counts, int T, int* __restrict__ cursor, int4
            int4* __restrict__ ip_chunks, int* __restrict__ nch) {
   constexpr int NW = kScanThreads / 64;
   __shared__ int wsum[4][NW];
-  __shared__ int cls_n[kSizeClasses], cls_base[kSizeClasses];
+  __shared__ int cls_n[2][kSizeClasses], cls_base[2][kSizeClasses];  // spreading, interpolation
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  if (tid < kSizeClasses) cls_n[tid] = 0;
+  if (tid < 2 * kSizeClasses) cls_n[tid / kSizeClasses][tid % kSizeClasses] = 0;
   const int per = (T + kScanThreads - 1) / kScanThreads;
   const int b0 = min(T, tid * per), b1 = min(T, b0 + per);
   int cr[kScanRegs];
@@ -232,9 +232,11 @@ k_bin_scan(const int* __restrict__ counts, int T, int* __restrict__ cursor, int4
     const int nsp = c > kSpreadChunk ? (c + kSpreadChunk - 1) / kSpreadChunk : 1;
     acc[0] += c;
     acc[1] += nsp;
-    acc[2] += (c + kChunk - 1) / kChunk;
+    const int nip = (c + kChunk - 1) / kChunk;
+    acc[2] += nip;
     acc[3] += nsp > 1 ? 1 : 0;
-    atomicAdd(&cls_n[size_class(c)], nsp);
+    atomicAdd(&cls_n[0][size_class(c, kSpreadChunk)], nsp);
+    if (nip > 0) atomicAdd(&cls_n[1][size_class(c, kChunk)], nip);
   }
   int incl[4];
 #pragma unroll
@@ -251,11 +253,11 @@ k_bin_scan(const int* __restrict__ counts, int T, int* __restrict__ cursor, int4
       if (lane < NW) wsum[k][lane] = w - v;  // exclusive wave bases
     }
   }
-  if (tid == 0) {  // chunk bases of the size classes, largest class first
+  if (tid < 2) {  // chunk bases of the size classes, largest class first
     int run = 0;
     for (int k = kSizeClasses - 1; k >= 0; --k) {
-      cls_base[k] = run;
-      run += cls_n[k];
+      cls_base[tid][k] = run;
+      run += cls_n[tid][k];
     }
   }
   __syncthreads();
@@ -271,7 +273,8 @@ k_bin_scan(const int* __restrict__ counts, int T, int* __restrict__ cursor, int4
     if (q >= kScanRegs) c = counts[b];
     const int nsp = c > kSpreadChunk ? (c + kSpreadChunk - 1) / kSpreadChunk : 1;
     const int nip = (c + kChunk - 1) / kChunk;
-    const int first = atomicAdd(&cls_base[size_class(c)], nsp);
+    const int first = atomicAdd(&cls_base[0][size_class(c, kSpreadChunk)], nsp);
+    const int ifirst = nip > 0 ? atomicAdd(&cls_base[1][size_class(c, kChunk)], nip) : 0;
     cursor[b] = run[0];
     sp_first[b] = first;
     sp_n[b] = nsp;
@@ -279,7 +282,7 @@ k_bin_scan(const int* __restrict__ counts, int T, int* __restrict__ cursor, int4
       sp_chunks[first + r] =
           make_int4(b, run[0] + r * kSpreadChunk, min(kSpreadChunk, c - r * kSpreadChunk), nsp);
     for (int r = 0; r < nip; ++r)
-      ip_chunks[run[2] + r] = make_int4(b, run[0] + r * kChunk, min(kChunk, c - r * kChunk), nip);
+      ip_chunks[ifirst + r] = make_int4(b, run[0] + r * kChunk, min(kChunk, c - r * kChunk), nip);
     if (nsp > 1) multi[run[3]] = b;
     run[0] += c;
     run[1] += nsp;
@@ -523,9 +526,11 @@ __global__ void __launch_bounds__(256) k_spread_reduce(SpreadReduceArgs a) {
 // writes its caller-order slot.
 constexpr int kInterpThreads = 256;
 constexpr int kInterpSB = 512;  // records per LDS sub-batch
+// (launch bound: at least 5 waves per SIMD, i.e. at most 96 VGPRs, so that six
+// 26 KB workgroups share a CU)
 
 template <int W>
-__global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs a) {
+__global__ void __launch_bounds__(kInterpThreads, 5) k_interp(InterpArgs a) {
   constexpr int RS = kTile + W - 1;
   constexpr int NT = kInterpThreads, SB = kInterpSB, PER = SB / NT;
   constexpr int NC = kTile * kTile;
