@@ -50,8 +50,8 @@ def stage_bytes(stage: str, info: dict) -> float:
     c = 8.0  # complex64
     return {
         "bin_hist": 16.0 * m + 2.0 * G * T,            # coordinates in, 16-bit histograms out
-        "bin_colscan": 2.0 * G * T + 4.0 * G * T + 4.0 * T,
-        "bin_scan": 4.0 * T + 4.0 * T + 16.0 * T,      # totals in, bases + chunk table out
+        # histograms in, offsets + totals out; then the bin scan: totals in, bases + chunk tables out
+        "bin_colscan": 2.0 * G * T + 4.0 * G * T + 4.0 * T + 4.0 * T + 4.0 * T + 32.0 * T,
         "bin_scatter": 16.0 * m + 4.0 * G * T + 16.0 * m,  # coordinates + offsets in, records out
         "spread": 16.0 * m + c * m + c * L * L,        # records + values in, support grid out
         "spread_reduce": 0.0,

@@ -53,8 +53,8 @@ __device__ __forceinline__ PointCells point_cells(double x, double y, const BinG
 // scan turns hist into per-(range, bin) offsets; the bin scan adds the bin
 // bases.  Pass 2 re-derives the pairs and ranks them inside (range, bin) with
 // LDS counters, so every slot is written exactly once.
-constexpr int kBinThreads = 512;
-constexpr int kBinBatch = 8;  // points per thread whose coordinates are loaded together
+constexpr int kBinThreads = 1024;
+constexpr int kBinBatch = 4;  // points per thread whose coordinates are loaded together
 
 __device__ __forceinline__ unsigned lds_bump16(unsigned* sh, int b) {
   const int sft = (b & 1) * 16;
@@ -100,13 +100,150 @@ k_bin_hist(const double* __restrict__ x, const double* __restrict__ y, int64_t M
   for (int b = threadIdx.x; b <= T; b += kBinThreads) row[b] = (uint16_t)((sh[b >> 1] >> ((b & 1) * 16)) & 0xffffu);
 }
 
+// Scan over the bins, run by one workgroup: first record of every bin (written to
+// `cursor`, the bin bases the scatter adds), and the chunk tables.  Spreading
+// needs a chunk for every bin (empty bins write zeros); interpolation only for
+// non-empty bins.  A bin with more than kSpreadChunk (kChunk) records is split
+// into several spreading (interpolation) chunks; for spreading those bins are
+// listed in `multi` for the reduction.  Both chunk tables are ordered by the
+// size of their bin, largest first (17 size classes, a bin's chunks kept
+// together), so that the dispatcher starts the longest workgroups first.
+// counts[T] (one past the bins) is the number of points outside the window;
+// it is copied to nch[4].  Each thread owns a contiguous run of bins; the
+// block-wide exclusive scan is two wave-shuffle scans around one LDS step.
+constexpr int kScanThreads = 1024;
+constexpr int kScanRegs = 8;  // bins per thread kept in registers
+constexpr int kSizeClasses = 17;
+
+// size class of a bin's chunks of at most `chunk` records: 16 for bins of at
+// least one full chunk, else 16 c / chunk
+__device__ __forceinline__ int size_class(int c, int chunk) {
+  return c >= chunk ? kSizeClasses - 1 : (c * (kSizeClasses - 1)) / chunk;
+}
+
+__device__ __forceinline__ int wave_incl_scan(int v, int lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// `counts` is written by other workgroups of the same launch (see
+// k_bin_colscan), so it is read through a plain pointer.
+__device__ __forceinline__ void bin_scan_body(const int* counts, int T, const BinScanOut& so) {
+  int* __restrict__ cursor = so.cursor;
+  int4* __restrict__ sp_chunks = so.sp_chunks;
+  int* __restrict__ sp_first = so.sp_first;
+  int* __restrict__ sp_n = so.sp_n;
+  int* __restrict__ multi = so.multi;
+  int4* __restrict__ ip_chunks = so.ip_chunks;
+  int* __restrict__ nch = so.nch;
+  constexpr int NW = kScanThreads / 64;
+  __shared__ int wsum[4][NW];
+  __shared__ int cls_n[2][kSizeClasses], cls_base[2][kSizeClasses];  // spreading, interpolation
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (tid < 2 * kSizeClasses) cls_n[tid / kSizeClasses][tid % kSizeClasses] = 0;
+  const int per = (T + kScanThreads - 1) / kScanThreads;
+  const int b0 = min(T, tid * per), b1 = min(T, b0 + per);
+  int cr[kScanRegs];
+#pragma unroll
+  for (int q = 0; q < kScanRegs; ++q) cr[q] = (b0 + q < b1) ? counts[b0 + q] : 0;
+  __syncthreads();  // cls_n cleared
+  int acc[4] = {0, 0, 0, 0};  // records, spread chunks, interp chunks, multi bins
+  for (int q = 0; q < per; ++q) {
+    const int b = b0 + q;
+    const bool valid = b < b1;
+    int c = 0;
+#pragma unroll
+    for (int r = 0; r < kScanRegs; ++r)
+      if (r == q) c = cr[r];
+    if (q >= kScanRegs && valid) c = counts[b];
+    const int nsp = !valid ? 0 : c > kSpreadChunk ? (c + kSpreadChunk - 1) / kSpreadChunk : 1;
+    const int nip = (c + kChunk - 1) / kChunk;
+    acc[0] += c;
+    acc[1] += nsp;
+    acc[2] += nip;
+    acc[3] += nsp > 1 ? 1 : 0;
+    if (nsp > 0) atomicAdd(&cls_n[0][size_class(c, kSpreadChunk)], nsp);
+    if (nip > 0) atomicAdd(&cls_n[1][size_class(c, kChunk)], nip);
+  }
+  int incl[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    incl[k] = wave_incl_scan(acc[k], lane);
+    if (lane == 63) wsum[k][wv] = incl[k];
+  }
+  __syncthreads();
+  if (wv == 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int v = lane < NW ? wsum[k][lane] : 0;
+      const int w = wave_incl_scan(v, lane);
+      if (lane < NW) wsum[k][lane] = w - v;  // exclusive wave bases
+    }
+  }
+  if (tid < 2) {  // chunk bases of the size classes, largest class first
+    int run = 0;
+    for (int k = kSizeClasses - 1; k >= 0; --k) {
+      cls_base[tid][k] = run;
+      run += cls_n[tid][k];
+    }
+  }
+  __syncthreads();
+  int run[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) run[k] = wsum[k][wv] + incl[k] - acc[k];
+  for (int q = 0; q < per; ++q) {
+    const int b = b0 + q;
+    const bool valid = b < b1;
+    int c = 0;
+#pragma unroll
+    for (int r = 0; r < kScanRegs; ++r)
+      if (r == q) c = cr[r];
+    if (q >= kScanRegs && valid) c = counts[b];
+    const int nsp = !valid ? 0 : c > kSpreadChunk ? (c + kSpreadChunk - 1) / kSpreadChunk : 1;
+    const int nip = (c + kChunk - 1) / kChunk;
+    if (!valid) continue;
+    const int first = atomicAdd(&cls_base[0][size_class(c, kSpreadChunk)], nsp);
+    const int ifirst = nip > 0 ? atomicAdd(&cls_base[1][size_class(c, kChunk)], nip) : 0;
+    cursor[b] = run[0];
+    sp_first[b] = first;
+    sp_n[b] = nsp;
+    for (int r = 0; r < nsp; ++r)
+      sp_chunks[first + r] =
+          make_int4(b, run[0] + r * kSpreadChunk, min(kSpreadChunk, c - r * kSpreadChunk), nsp);
+    for (int r = 0; r < nip; ++r)
+      ip_chunks[ifirst + r] = make_int4(b, run[0] + r * kChunk, min(kChunk, c - r * kChunk), nip);
+    if (nsp > 1) multi[run[3]] = b;
+    run[0] += c;
+    run[1] += nsp;
+    run[2] += nip;
+    run[3] += nsp > 1 ? 1 : 0;
+  }
+  if (tid == kScanThreads - 1) {
+    nch[0] = run[1];
+    nch[1] = run[2];
+    nch[2] = run[0];
+    nch[3] = run[3];
+    nch[4] = counts[T];
+  }
+}
+
 // Column scan: off[g][b] = sum_{g' < g} hist[g'][b], total[b] = sum_g hist[g][b].
 // A workgroup takes 64 consecutive bins (one per lane) and splits the G
-// ranges over its 16 waves.
+// ranges over its 16 waves.  The last workgroup to finish (counted in `done`,
+// which it resets to zero) then runs the bin scan over the totals; the
+// counter is bumped after a release fence and read back before an acquire
+// fence, so every workgroup's totals are visible to it.  No workgroup waits
+// for another.
 constexpr int kColWaves = 16;
+static_assert(64 * kColWaves == kScanThreads, "the last column-scan workgroup runs the bin scan");
 
 __global__ void __launch_bounds__(64 * kColWaves)
-k_bin_colscan(const uint16_t* __restrict__ hist, int G, int T, int* __restrict__ off, int* __restrict__ total) {
+k_bin_colscan(const uint16_t* __restrict__ hist, int G, int T, int* __restrict__ off, int* total,
+              BinScanOut so, int* __restrict__ done) {
   // T here is the row length (bins + 1)
   __shared__ int part[kColWaves][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -132,6 +269,23 @@ k_bin_colscan(const uint16_t* __restrict__ hist, int G, int T, int* __restrict__
     }
     if (wv == kColWaves - 1) total[b] = run;
   }
+  // the totals come from the last wave only: it releases them and bumps the
+  // counter; in the last workgroup it also acquires the others' totals for
+  // the whole workgroup (one CU, one L2), which the barrier then orders
+  // before every wave's reads
+  __shared__ int last;
+  if (wv == kColWaves - 1) {
+    __threadfence();
+    if (lane == 0) {
+      const bool l = atomicAdd(done, 1) == (int)gridDim.x - 1;
+      if (l) __threadfence();
+      last = l;
+    }
+  }
+  __syncthreads();
+  if (!last) return;
+  bin_scan_body(total, T - 1, so);
+  if (threadIdx.x == 0) *done = 0;
 }
 
 __global__ void __launch_bounds__(kBinThreads)
@@ -173,128 +327,6 @@ k_bin_scatter(const double* __restrict__ x, const double* __restrict__ y, int64_
         recs[slot] = r;
       }
    }
-  }
-}
-
-// Single-workgroup scan over the bins: first record of every bin (written to
-// `cursor`, the bin bases the scatter adds), and the chunk tables.  Spreading
-// needs a chunk for every bin (empty bins write zeros); interpolation only for
-// non-empty bins.  A bin with more than kSpreadChunk (kChunk) records is split
-// into several spreading (interpolation) chunks; for spreading those bins are
-// listed in `multi` for the reduction.  Both chunk tables are ordered by the
-// size of their bin, largest first (17 size classes, a bin's chunks kept
-// together), so that the dispatcher starts the longest workgroups first.
-// counts[T] (one past the bins) is the number of points outside the window;
-// it is copied to nch[4].  Each thread owns a contiguous run of bins; the
-// block-wide exclusive scan is two wave-shuffle scans around one LDS step.
-constexpr int kScanThreads = 1024;
-constexpr int kScanRegs = 8;  // bins per thread kept in registers
-constexpr int kSizeClasses = 17;
-
-// size class of a bin's chunks of at most `chunk` records: 16 for bins of at
-// least one full chunk, else 16 c / chunk
-__device__ __forceinline__ int size_class(int c, int chunk) {
-  return c >= chunk ? kSizeClasses - 1 : (c * (kSizeClasses - 1)) / chunk;
-}
-
-__device__ __forceinline__ int wave_incl_scan(int v, int lane) {
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int t = __shfl_up(v, o, 64);
-    if (lane >= o) v += t;
-  }
-  return v;
-}
-
-__global__ void __launch_bounds__(kScanThreads)
-k_bin_scan(const int* __restrict__ counts, int T, int* __restrict__ cursor, int4* __restrict__ sp_chunks,
-           int* __restrict__ sp_first, int* __restrict__ sp_n, int* __restrict__ multi,
-           int4* __restrict__ ip_chunks, int* __restrict__ nch) {
-  constexpr int NW = kScanThreads / 64;
-  __shared__ int wsum[4][NW];
-  __shared__ int cls_n[2][kSizeClasses], cls_base[2][kSizeClasses];  // spreading, interpolation
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  if (tid < 2 * kSizeClasses) cls_n[tid / kSizeClasses][tid % kSizeClasses] = 0;
-  const int per = (T + kScanThreads - 1) / kScanThreads;
-  const int b0 = min(T, tid * per), b1 = min(T, b0 + per);
-  int cr[kScanRegs];
-#pragma unroll
-  for (int q = 0; q < kScanRegs; ++q) cr[q] = (b0 + q < b1) ? counts[b0 + q] : 0;
-  __syncthreads();  // cls_n cleared
-  int acc[4] = {0, 0, 0, 0};  // records, spread chunks, interp chunks, multi bins
-  for (int b = b0; b < b1; ++b) {
-    const int q = b - b0;
-    int c = 0;
-#pragma unroll
-    for (int r = 0; r < kScanRegs; ++r)
-      if (r == q) c = cr[r];
-    if (q >= kScanRegs) c = counts[b];
-    const int nsp = c > kSpreadChunk ? (c + kSpreadChunk - 1) / kSpreadChunk : 1;
-    acc[0] += c;
-    acc[1] += nsp;
-    const int nip = (c + kChunk - 1) / kChunk;
-    acc[2] += nip;
-    acc[3] += nsp > 1 ? 1 : 0;
-    atomicAdd(&cls_n[0][size_class(c, kSpreadChunk)], nsp);
-    if (nip > 0) atomicAdd(&cls_n[1][size_class(c, kChunk)], nip);
-  }
-  int incl[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    incl[k] = wave_incl_scan(acc[k], lane);
-    if (lane == 63) wsum[k][wv] = incl[k];
-  }
-  __syncthreads();
-  if (wv == 0) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int v = lane < NW ? wsum[k][lane] : 0;
-      const int w = wave_incl_scan(v, lane);
-      if (lane < NW) wsum[k][lane] = w - v;  // exclusive wave bases
-    }
-  }
-  if (tid < 2) {  // chunk bases of the size classes, largest class first
-    int run = 0;
-    for (int k = kSizeClasses - 1; k >= 0; --k) {
-      cls_base[tid][k] = run;
-      run += cls_n[tid][k];
-    }
-  }
-  __syncthreads();
-  int run[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) run[k] = wsum[k][wv] + incl[k] - acc[k];
-  for (int b = b0; b < b1; ++b) {
-    const int q = b - b0;
-    int c = 0;
-#pragma unroll
-    for (int r = 0; r < kScanRegs; ++r)
-      if (r == q) c = cr[r];
-    if (q >= kScanRegs) c = counts[b];
-    const int nsp = c > kSpreadChunk ? (c + kSpreadChunk - 1) / kSpreadChunk : 1;
-    const int nip = (c + kChunk - 1) / kChunk;
-    const int first = atomicAdd(&cls_base[0][size_class(c, kSpreadChunk)], nsp);
-    const int ifirst = nip > 0 ? atomicAdd(&cls_base[1][size_class(c, kChunk)], nip) : 0;
-    cursor[b] = run[0];
-    sp_first[b] = first;
-    sp_n[b] = nsp;
-    for (int r = 0; r < nsp; ++r)
-      sp_chunks[first + r] =
-          make_int4(b, run[0] + r * kSpreadChunk, min(kSpreadChunk, c - r * kSpreadChunk), nsp);
-    for (int r = 0; r < nip; ++r)
-      ip_chunks[ifirst + r] = make_int4(b, run[0] + r * kChunk, min(kChunk, c - r * kChunk), nip);
-    if (nsp > 1) multi[run[3]] = b;
-    run[0] += c;
-    run[1] += nsp;
-    run[2] += nip;
-    run[3] += nsp > 1 ? 1 : 0;
-  }
-  if (tid == kScanThreads - 1) {
-    nch[0] = run[1];
-    nch[1] = run[2];
-    nch[2] = run[0];
-    nch[3] = run[3];
-    nch[4] = counts[T];
   }
 }
 
@@ -670,17 +702,11 @@ hipError_t launch_bin_hist(const double* x, const double* y, int64_t M, BinGeom 
   return hipGetLastError();
 }
 
-hipError_t launch_bin_colscan(const uint16_t* hist, int G, int T, int* off, int* total, hipStream_t st) {
+hipError_t launch_bin_colscan(const uint16_t* hist, int G, int T, int* off, int* total, const BinScanOut& so,
+                              int* done, hipStream_t st) {
   const int cols = T + 1;
   hipLaunchKernelGGL(k_bin_colscan, dim3((cols + 63) / 64), dim3(64 * kColWaves), 0, st, hist, G, cols, off,
-                     total);
-  return hipGetLastError();
-}
-
-hipError_t launch_bin_scan(const int* counts, int T, int* cursor, int4* sp_chunks, int* sp_first,
-                           int* sp_n, int* multi, int4* ip_chunks, int* nch, hipStream_t st) {
-  hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(kScanThreads), 0, st, counts, T, cursor, sp_chunks,
-                     sp_first, sp_n, multi, ip_chunks, nch);
+                     total, so, done);
   return hipGetLastError();
 }
 

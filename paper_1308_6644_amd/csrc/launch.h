@@ -49,6 +49,18 @@ struct BinGeom {
   int TX;           // bins per axis
 };
 
+// Outputs of the bin scan (bin bases, chunk tables and their counts).
+struct BinScanOut {
+  int* cursor;       // first record of each bin
+  int4* sp_chunks;   // spreading chunks (bin, first record, count, chunks of the bin)
+  int* sp_first;     // first spreading chunk of each bin
+  int* sp_n;         // spreading chunks of each bin
+  int* multi;        // bins with several spreading chunks
+  int4* ip_chunks;   // interpolation chunks
+  int* nch;          // spread chunks, interp chunks, records, multi bins, points out of range
+};
+constexpr int kScanDone = 7;  // element of nch counting finished column-scan workgroups
+
 struct SpreadArgs {
   const BinRec* recs;
   const int4* chunks;     // (bin, first record, count, chunks of the bin)
@@ -87,11 +99,8 @@ constexpr int kBinPointsMax = 65535;  // points per binning workgroup (16-bit LD
 // hist rows and offset rows have T + 1 entries (entry T: points outside the window)
 hipError_t launch_bin_hist(const double* x, const double* y, int64_t M, BinGeom g, int ppw, int G,
                            uint16_t* hist, hipStream_t st);
-hipError_t launch_bin_colscan(const uint16_t* hist, int G, int T, int* off, int* total, hipStream_t st);
-// nch[0] spread chunks, nch[1] interpolation chunks, nch[2] records, nch[3] multi-chunk bins,
-// nch[4] points outside the window (counts[T])
-hipError_t launch_bin_scan(const int* counts, int T, int* cursor, int4* sp_chunks, int* sp_first,
-                           int* sp_n, int* multi, int4* ip_chunks, int* nch, hipStream_t st);
+hipError_t launch_bin_colscan(const uint16_t* hist, int G, int T, int* off, int* total, const BinScanOut& so,
+                              int* done, hipStream_t st);
 hipError_t launch_bin_scatter(const double* x, const double* y, int64_t M, BinGeom g, int ppw, int G,
                               const int* off, const int* bin_base, BinRec* recs, hipStream_t st);
 hipError_t launch_spread(int w, const SpreadArgs& a, int grid, hipStream_t st);

@@ -186,7 +186,7 @@ struct nuasm_plan_s {
   int* sp_first = nullptr;
   int* sp_n = nullptr;
   int* multi = nullptr;
-  int* nch = nullptr;     // [4] + bad counter at [4]
+  int* nch = nullptr;     // [8]: chunk and record counts [0..3], points out of range [4], scan hand-off counter [7]
   int4* sp_chunks = nullptr;
   int4* ip_chunks = nullptr;
   int64_t chunk_cap = 0;
@@ -693,20 +693,16 @@ nuasm_status nuasm_set_points(nuasm_plan pl, int64_t M, const double* x, const d
     int ppw = 0, G = 0;
     bin_ranges(M, &ppw, &G);
     if (M > 0) {
-      {
-        StageScope sc(pl, NUASM_STAGE_BIN_HIST);
-        HIP_TRY(launch_bin_hist(x, y, M, pl->bgeom, ppw, G, pl->hist, st), "launch bin_hist");
-      }
-      StageScope sc(pl, NUASM_STAGE_BIN_COLSCAN);
-      HIP_TRY(launch_bin_colscan(pl->hist, G, pl->T, pl->hoff, pl->counts, st), "launch bin_colscan");
-    } else {
-      HIP_TRY(launch_fill_i32(pl->counts, 0, pl->T + 1, st), "launch fill");
+      StageScope sc(pl, NUASM_STAGE_BIN_HIST);
+      HIP_TRY(launch_bin_hist(x, y, M, pl->bgeom, ppw, G, pl->hist, st), "launch bin_hist");
     }
     {
-      StageScope sc(pl, NUASM_STAGE_BIN_SCAN);
-      HIP_TRY(launch_bin_scan(pl->counts, pl->T, pl->cursor, pl->sp_chunks, pl->sp_first, pl->sp_n, pl->multi,
-                              pl->ip_chunks, pl->nch, st),
-              "launch bin_scan");
+      // column scan and bin scan in one launch; with no points (G = 0) it
+      // writes zero totals and empty-bin chunk tables
+      const BinScanOut so{pl->cursor, pl->sp_chunks, pl->sp_first, pl->sp_n, pl->multi, pl->ip_chunks, pl->nch};
+      StageScope sc(pl, NUASM_STAGE_BIN_COLSCAN);
+      HIP_TRY(launch_bin_colscan(pl->hist, M > 0 ? G : 0, pl->T, pl->hoff, pl->counts, so, pl->nch + kScanDone, st),
+              "launch bin_colscan");
     }
     StageScope sc(pl, NUASM_STAGE_BIN_SCATTER);
     HIP_TRY(launch_bin_scatter(x, y, M, pl->bgeom, ppw, G, pl->hoff, pl->cursor, pl->recs, st),
