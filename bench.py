@@ -79,7 +79,7 @@ def make_inputs(torch, synth):
     return host, d
 
 
-def cpu_baseline(host, n1=16384, n2=16384):
+def cpu_baseline(host, n1=40960, n2=40960):
     """The FP64 oracle as it stands, timed on this host: NU-ASM_1 on the first
     n1 source points and NU-ASM_2 on the first n2 destination points of the
     same workload at z = 0.1 m, band-limited ASM (transfer function included)."""
