@@ -131,8 +131,14 @@ __device__ __forceinline__ void stockham_pass(float2* __restrict__ s, const floa
 #pragma unroll
       for (int j = 0; j < R; ++j) x[q][j] = s[pidx((i + j * NR) * C + c)];
       if (P > 1) {
+        // w^j, w = exp(-2 pi i k TWS / N): one table lookup, then a power
+        // tree (each w^j a few products away from the table value)
+        w[q][1] = tw2_get<LOGN>(tw, k * TWS);
 #pragma unroll
-        for (int j = 1; j < R; ++j) w[q][j] = tw2_get<LOGN>(tw, j * k * TWS);
+        for (int j = 2; j < R; ++j) {
+          const int hb = 1 << (31 - __builtin_clz(j));
+          w[q][j] = hb == j ? cmul(w[q][j / 2], w[q][j / 2]) : cmul(w[q][hb], w[q][j - hb]);
+        }
       }
     }
   }
@@ -163,7 +169,7 @@ __device__ __forceinline__ void stockham_pass(float2* __restrict__ s, const floa
 template <int LOGN, int C, int NT, int DIR, int P, int REM>
 struct FftPasses {
   static __device__ __forceinline__ void run(float2* s, const float2* tw) {
-    constexpr int LR = REM >= 4 ? 4 : REM;
+    constexpr int LR = REM >= 3 ? 3 : REM;
     constexpr int R = 1 << LR;
     stockham_pass<LOGN, C, NT, DIR, R, P>(s, tw);
     FftPasses<LOGN, C, NT, DIR, P * R, REM - LR>::run(s, tw);

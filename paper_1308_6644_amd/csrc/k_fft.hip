@@ -1,7 +1,7 @@
 // Grid passes of the two pipelines on gfx950: pruned row FFTs, the fused
 // column pass (FFT -> deconvolution x transfer function x Rect -> inverse FFT),
 // and the final row passes.  Every 1-D transform lives in LDS (Stockham,
-// radix 16 with an 8/4/2 tail); HBM is touched once per pass.
+// radix 8 with a 4/2 tail); HBM is touched once per pass.
 //
 // Index conventions (centred, as in Eqs. 3, 6 and 9): a plane element [b][a]
 // of an N' x N' array holds n = (a - N'/2, b - N'/2); frequency k = a - N'/2.
@@ -17,7 +17,7 @@ template <int LOGN>
 struct RowCfg {
   static constexpr int N = 1 << LOGN;
   static constexpr int C = N >= 4096 ? 1 : 4096 / N;
-  static constexpr int NB = C * N / 16;
+  static constexpr int NB = C * N / 8;   // radix-8 butterflies per pass
   static constexpr int NT = NB < 64 ? 64 : (NB > 1024 ? 1024 : NB);
   static constexpr int DATA = lds_elems(C * N);  // complex elements of data
   static constexpr int LDS = (DATA + Tw2<LOGN>::SIZE) * 8;
@@ -32,7 +32,7 @@ struct ColCfg {
   static constexpr int NF = 1 << LOGNF;
   static constexpr int C0 = kColElems / NF;
   static constexpr int C = C0 < 1 ? 1 : (C0 > 16 ? 16 : C0);
-  static constexpr int NB = C * NF / 16;
+  static constexpr int NB = C * NF / 8;
   static constexpr int NT = NB < 64 ? 64 : (NB > 1024 ? 1024 : NB);
   static constexpr int DATA = lds_elems(C * NF);
   // twiddle tables for the fine length and for N' = NF / 2
@@ -41,10 +41,10 @@ struct ColCfg {
 
 __device__ __forceinline__ bool in_band(int k, int lo, int hi) { return k >= lo && k <= hi; }
 
-// float64 square root and reciprocal from the hardware seeds (v_rsq_f64,
-// v_rcp_f64) refined by Newton steps: each step squares the relative error,
-// so two steps from the ~2^-23 seeds are far below 2^-53; a final
-// residual correction gives sqrt to about one ulp.
+// float64 square root from the hardware seed (v_rsq_f64) refined by Newton
+// steps: each step squares the relative error, so two steps from the ~2^-23
+// seed are far below 2^-53; a final residual correction gives sqrt to about
+// one ulp.
 __device__ __forceinline__ double sqrt_nr(double r) {
   double y = __builtin_amdgcn_rsq(r);
   y = y * (1.5 - 0.5 * r * y * y);
@@ -52,28 +52,25 @@ __device__ __forceinline__ double sqrt_nr(double r) {
   const double s = r * y;
   return s + 0.5 * y * (r - s * s);
 }
-__device__ __forceinline__ double rcp_nr(double d) {
-  double x = __builtin_amdgcn_rcp(d);
-  x = x * (2.0 - d * x);
-  x = x * (2.0 - d * x);
-  return x + x * (1.0 - d * x);
-}
 
 // Transfer function of Eq. 4 (ASM) or Eq. 5 (Fresnel) at integer frequency
 // (kx, ky), without the Rect.  The ASM phase is formed in cycles:
-// z sqrt(1/l^2 - q k^2) = z/l - z q k^2 / (1/l + sqrt(.)), which keeps full
-// float64 accuracy at large z, then reduced to [-1/2, 1/2] before the float32
-// sincospi.  Evanescent frequencies give 0.
+// z sqrt(1/l^2 - df^2 k^2) = z/l - (z/l)(1 - sqrt(1 - t)), t = (l df)^2 k^2.
+// sqrt(1 - t) is accurate to about one ulp of 1, so the subtracted term is
+// off by about (z/l) 2^-53 cycles however large z/l is (1e-10 cycles at
+// z/l = 2e6); z/l itself enters only as its fraction c0.  The phase is then
+// reduced to [-1/2, 1/2] before the float32 sincospi.  Evanescent
+// frequencies (t > 1) give 0.
 __device__ __forceinline__ float2 transfer_at(const Spectral& sp, int Np, int kx, int ky) {
   float2 h;
   if (sp.tf == 1) {
     h = cmul(sp.fre_x[kx + Np / 2], sp.fre_y[ky + Np / 2]);
   } else if (sp.phase_fp64) {
     const double k2 = (double)kx * kx + (double)ky * ky;
-    const double r = sp.inv_lam2 - sp.q * k2;
-    if (r < 0.0) return czero();
-    const double s = r > 0.0 ? sqrt_nr(r) : 0.0;
-    double cyc = sp.c0 + sp.ax * kx + sp.ay * ky - sp.zq * k2 * rcp_nr(sp.inv_lam + s);
+    const double u = 1.0 - sp.ql2 * k2;
+    if (u < 0.0) return czero();
+    const double s = u > 0.0 ? sqrt_nr(u) : 0.0;
+    double cyc = sp.c0 + sp.ax * kx + sp.ay * ky - sp.zl * (1.0 - s);
     cyc -= rint(cyc);
     float sn, cs;
     sincospif(2.0f * (float)cyc, &sn, &cs);

@@ -30,8 +30,9 @@ struct Spectral {
   int phase_fp64;  // ASM phase in float64 (1) or float32 (0)
   int conj;        // apply conj(H) (adjoint)
   float scale;     // N'^-2
-  // ASM: cycles = c0 + ax kx + ay ky - zq k^2 / (inv_lam + sqrt(inv_lam2 - q k^2))
-  double c0, ax, ay, q, zq, inv_lam, inv_lam2;
+  // ASM: cycles = c0 + ax kx + ay ky - zl (1 - sqrt(1 - t)), t = ql2 k^2,
+  // with zl = z / l, ql2 = (l df)^2 and c0 = z / l reduced mod 1
+  double c0, ax, ay, zl, ql2;
   // float32 variant: cycles = axf kx + ayf ky + zf sqrt(inv_lam2f - qf k^2)
   float axf, ayf, qf, zf, inv_lam2f;
   const float2* fre_x;  // Fresnel: A * H_x(k), index k + N'/2

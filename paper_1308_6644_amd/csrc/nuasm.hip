@@ -585,15 +585,13 @@ nuasm_status nuasm_plan_create(const nuasm_params* p, void* hip_stream, nuasm_pl
     S.c0 = zl - std::nearbyint(zl);
     S.ax = df * p->ox;
     S.ay = df * p->oy;
-    S.q = df * df;
-    S.zq = p->z * df * df;
-    S.inv_lam = 1.0 / p->lambda;
-    S.inv_lam2 = 1.0 / (p->lambda * p->lambda);
+    S.zl = zl;
+    S.ql2 = (p->lambda * df) * (p->lambda * df);
     S.axf = (float)S.ax;
     S.ayf = (float)S.ay;
-    S.qf = (float)S.q;
+    S.qf = (float)(df * df);
     S.zf = (float)p->z;
-    S.inv_lam2f = (float)S.inv_lam2;
+    S.inv_lam2f = (float)(1.0 / (p->lambda * p->lambda));
   }
 
   s = twiddles_for_device(pl->device, &pl->tw);
