@@ -53,13 +53,20 @@ __device__ __forceinline__ double sqrt_nr(double r) {
   return s + 0.5 * y * (r - s * s);
 }
 
+// exp(2 pi i x) for x in [-1/2, 1/2] cycles from the hardware sine and cosine,
+// which take their argument in revolutions (v_sin_f32 / v_cos_f32; measured
+// error below 1.3e-7 over that range, against 5.5e-8 for sincospif).
+__device__ __forceinline__ float2 cis_rev(float x) {
+  return make_float2(__builtin_amdgcn_cosf(x), __builtin_amdgcn_sinf(x));
+}
+
 // Transfer function of Eq. 4 (ASM) or Eq. 5 (Fresnel) at integer frequency
 // (kx, ky), without the Rect.  The ASM phase is formed in cycles:
 // z sqrt(1/l^2 - df^2 k^2) = z/l - (z/l)(1 - sqrt(1 - t)), t = (l df)^2 k^2.
 // sqrt(1 - t) is accurate to about one ulp of 1, so the subtracted term is
 // off by about (z/l) 2^-53 cycles however large z/l is (1e-10 cycles at
 // z/l = 2e6); z/l itself enters only as its fraction c0.  The phase is then
-// reduced to [-1/2, 1/2] before the float32 sincospi.  Evanescent
+// reduced to [-1/2, 1/2] before the float32 sine and cosine.  Evanescent
 // frequencies (t > 1) give 0.
 __device__ __forceinline__ float2 transfer_at(const Spectral& sp, int Np, int kx, int ky) {
   float2 h;
@@ -72,18 +79,14 @@ __device__ __forceinline__ float2 transfer_at(const Spectral& sp, int Np, int kx
     const double s = u > 0.0 ? sqrt_nr(u) : 0.0;
     double cyc = sp.c0 + sp.ax * kx + sp.ay * ky - sp.zl * (1.0 - s);
     cyc -= rint(cyc);
-    float sn, cs;
-    sincospif(2.0f * (float)cyc, &sn, &cs);
-    h = make_float2(cs, sn);
+    h = cis_rev((float)cyc);
   } else {
     const float k2 = (float)kx * (float)kx + (float)ky * (float)ky;
     const float r = sp.inv_lam2f - sp.qf * k2;
     if (r < 0.0f) return czero();
     float cyc = sp.axf * (float)kx + sp.ayf * (float)ky + sp.zf * sqrtf(r);
     cyc -= rintf(cyc);
-    float sn, cs;
-    sincospif(2.0f * cyc, &sn, &cs);
-    h = make_float2(cs, sn);
+    h = cis_rev(cyc);
   }
   if (sp.conj) h.y = -h.y;
   return h;
