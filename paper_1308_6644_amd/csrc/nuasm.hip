@@ -867,6 +867,36 @@ nuasm_status batch_plane(nuasm_plan_s* pl, int64_t M, const double* x, const dou
 
 }  // namespace
 
+// Modelled GPU time of one plane (one-shot: binning + operator), in
+// microseconds, from per-kernel timings of the N' = 2048, M = 2^20 workload on
+// MI355X: the grid passes scale with the stored support L^2 (about 2.1e-5 us
+// per cell for either type), binning with the points (5.2e-5 us each), and
+// the point kernels with the points too: spreading with its reduction
+// 7.4e-5 us per point, interpolation 3.8e-5.  Only the ratios matter.
+static double plane_cost(const nuasm_plan_s* pl, int64_t M) {
+  const double grid = 2.1e-5 * (double)pl->geom.L * (double)pl->geom.L;
+  const double pts = (5.2e-5 + (pl->p.type == NUASM_TYPE_1 ? 7.4e-5 : 3.8e-5)) * (double)M;
+  return 20.0 + grid + pts;
+}
+
+// Longest-processing-time assignment of the planes to the capture branches.
+static void assign_branches(nuasm_batch_s* b, const int64_t* M) {
+  const int P = (int)b->plans.size(), K = (int)b->branch.size();
+  std::vector<double> work(P);
+  std::vector<int> order(P);
+  for (int p = 0; p < P; ++p) {
+    work[p] = plane_cost(b->plans[p], M[p]);
+    order[p] = p;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return work[a] > work[c]; });
+  std::vector<double> load(K, 0.0);
+  for (int p : order) {
+    const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    b->branch_of[p] = k;
+    load[k] += work[p];
+  }
+}
+
 extern "C" {
 
 nuasm_status nuasm_batch_create(int32_t P, const nuasm_params* params, void* hip_stream, nuasm_batch* out) {
@@ -881,7 +911,6 @@ nuasm_status nuasm_batch_create(int32_t P, const nuasm_params* params, void* hip
     delete b;
     return st;
   };
-  std::vector<double> work(P);
   for (int p = 0; p < P; ++p) {
     nuasm_params q = params[p];
     q.flags |= NUASM_DEFER_RANGE_CHECK;
@@ -895,20 +924,9 @@ nuasm_status nuasm_batch_create(int32_t P, const nuasm_params* params, void* hip
       return fail(s, m);
     }
     b->plans.push_back(pl);
-    work[p] = (double)pl->geom.L * pl->geom.L;
   }
-  // longest-processing-time assignment of planes to the capture branches
-  std::vector<int> order(P);
-  for (int p = 0; p < P; ++p) order[p] = p;
-  std::sort(order.begin(), order.end(), [&](int a, int c) { return work[a] > work[c]; });
   const int K = std::min(kBranches, (int)P);
-  std::vector<double> load(K, 0.0);
   b->branch_of.assign(P, 0);
-  for (int p : order) {
-    const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-    b->branch_of[p] = k;
-    load[k] += work[p];
-  }
   hipError_t e;
   for (int k = 0; k < K; ++k) {
     hipStream_t st = nullptr;
@@ -988,6 +1006,7 @@ nuasm_status nuasm_batch_run(nuasm_batch b, const int64_t* M, const double* cons
     if (s != NUASM_OK) return fail(s, "plane " + std::to_string(p) + ": " + g_last_error);
   }
   HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+  assign_branches(b, M);
   // capture on the internal stream: stamp, fork onto the branches, every
   // plane on its branch followed by its completion stamp, join
   HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
