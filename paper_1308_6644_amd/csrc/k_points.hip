@@ -54,6 +54,7 @@ __device__ __forceinline__ PointCells point_cells(double x, double y, const BinG
 // bases.  Pass 2 re-derives the pairs and ranks them inside (range, bin) with
 // LDS counters, so every slot is written exactly once.
 constexpr int kBinThreads = 1024;
+constexpr int kScatterCursorBytes = 64 * 1024;  // LDS for 32-bit scatter cursors (up to 16384 bins)
 constexpr int kBinBatch = 4;  // points per thread whose coordinates are loaded together
 
 __device__ __forceinline__ unsigned lds_bump16(unsigned* sh, int b) {
@@ -288,45 +289,55 @@ k_bin_colscan(const uint16_t* __restrict__ hist, int G, int T, int* __restrict__
   if (threadIdx.x == 0) *done = 0;
 }
 
+// CURSORS: the workgroup's write cursors bin_base[b] + off[g][b] are staged in
+// LDS once and bumped there (one LDS atomic per record, no global loads);
+// otherwise 16-bit LDS ranks are added to the two global tables per record
+// (for supports with too many bins to stage 32-bit cursors).
+template <bool CURSORS>
 __global__ void __launch_bounds__(kBinThreads)
 k_bin_scatter(const double* __restrict__ x, const double* __restrict__ y, int64_t M, BinGeom g, int ppw,
               const int* __restrict__ off, const int* __restrict__ bin_base, BinRec* __restrict__ recs) {
   extern __shared__ unsigned sh[];
   const int T = g.TX * g.TX, TW = (T + 1) / 2;
-  for (int e = threadIdx.x; e < TW; e += kBinThreads) sh[e] = 0u;
+  const int* myoff = off + (size_t)blockIdx.x * (T + 1);
+  if (CURSORS) {
+    for (int b = threadIdx.x; b < T; b += kBinThreads) sh[b] = (unsigned)(bin_base[b] + myoff[b]);
+  } else {
+    for (int e = threadIdx.x; e < TW; e += kBinThreads) sh[e] = 0u;
+  }
   __syncthreads();
   const int64_t j0 = (int64_t)blockIdx.x * ppw;
   const int64_t j1 = min(M, j0 + ppw);
-  const int* myoff = off + (size_t)blockIdx.x * (T + 1);
   for (int64_t jb = j0; jb < j1; jb += kBinThreads * kBinBatch) {
-   double xv[kBinBatch], yv[kBinBatch];
+    double xv[kBinBatch], yv[kBinBatch];
 #pragma unroll
-   for (int q = 0; q < kBinBatch; ++q) {
-     const int64_t j = jb + threadIdx.x + q * kBinThreads;
-     xv[q] = j < j1 ? x[j] : 0.0;
-     yv[q] = j < j1 ? y[j] : 0.0;
-   }
+    for (int q = 0; q < kBinBatch; ++q) {
+      const int64_t j = jb + threadIdx.x + q * kBinThreads;
+      xv[q] = j < j1 ? x[j] : 0.0;
+      yv[q] = j < j1 ? y[j] : 0.0;
+    }
 #pragma unroll
-   for (int q = 0; q < kBinBatch; ++q) {
-    const int64_t j = jb + threadIdx.x + q * kBinThreads;
-    if (j >= j1) continue;
-    const PointCells pc = point_cells(xv[q], yv[q], g);
-    if (!pc.ok) continue;
-    const int bx0 = pc.i0x / kTile, bx1 = (pc.i0x + g.w - 1) / kTile;
-    const int by0 = pc.i0y / kTile, by1 = (pc.i0y + g.w - 1) / kTile;
-    for (int by = by0; by <= by1; ++by)
-      for (int bx = bx0; bx <= bx1; ++bx) {
-        const int b = by * g.TX + bx;
-        const int slot = bin_base[b] + myoff[b] + (int)lds_bump16(sh, b);
-        const int lx = pc.i0x - bx * kTile, ly = pc.i0y - by * kTile;
-        BinRec r;
-        r.packed = (lx & 0xff) | ((ly & 0xff) << 8) | ((bx == bx0 && by == by0) ? (1 << 16) : 0);
-        r.dx = pc.dx;
-        r.dy = pc.dy;
-        r.idx = (int32_t)j;
-        recs[slot] = r;
-      }
-   }
+    for (int q = 0; q < kBinBatch; ++q) {
+      const int64_t j = jb + threadIdx.x + q * kBinThreads;
+      if (j >= j1) continue;
+      const PointCells pc = point_cells(xv[q], yv[q], g);
+      if (!pc.ok) continue;
+      const int bx0 = pc.i0x / kTile, bx1 = (pc.i0x + g.w - 1) / kTile;
+      const int by0 = pc.i0y / kTile, by1 = (pc.i0y + g.w - 1) / kTile;
+      for (int by = by0; by <= by1; ++by)
+        for (int bx = bx0; bx <= bx1; ++bx) {
+          const int b = by * g.TX + bx;
+          const int slot = CURSORS ? (int)atomicAdd(&sh[b], 1u)
+                                   : bin_base[b] + myoff[b] + (int)lds_bump16(sh, b);
+          const int lx = pc.i0x - bx * kTile, ly = pc.i0y - by * kTile;
+          BinRec r;
+          r.packed = (lx & 0xff) | ((ly & 0xff) << 8) | ((bx == bx0 && by == by0) ? (1 << 16) : 0);
+          r.dx = pc.dx;
+          r.dy = pc.dy;
+          r.idx = (int32_t)j;
+          recs[slot] = r;
+        }
+    }
   }
 }
 
@@ -713,10 +724,17 @@ hipError_t launch_bin_colscan(const uint16_t* hist, int G, int T, int* off, int*
 hipError_t launch_bin_scatter(const double* x, const double* y, int64_t M, BinGeom g, int ppw, int G,
                               const int* off, const int* bin_base, BinRec* recs, hipStream_t st) {
   if (G <= 0) return hipSuccess;
-  const int T = g.TX * g.TX, bytes = ((T + 1) / 2) * 4;
-  hipError_t e = bin_lds_attr((const void*)k_bin_scatter, bytes);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_bin_scatter, dim3(G), dim3(kBinThreads), bytes, st, x, y, M, g, ppw, off, bin_base, recs);
+  const int T = g.TX * g.TX;
+  if (T * 4 <= kScatterCursorBytes) {
+    hipLaunchKernelGGL(k_bin_scatter<true>, dim3(G), dim3(kBinThreads), T * 4, st, x, y, M, g, ppw, off, bin_base,
+                       recs);
+  } else {
+    const int bytes = ((T + 1) / 2) * 4;
+    hipError_t e = bin_lds_attr((const void*)k_bin_scatter<false>, bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bin_scatter<false>, dim3(G), dim3(kBinThreads), bytes, st, x, y, M, g, ppw, off, bin_base,
+                       recs);
+  }
   return hipGetLastError();
 }
 
