@@ -562,27 +562,19 @@ __global__ void __launch_bounds__(256) k_spread_reduce(SpreadReduceArgs a) {
 
 // --------------------------------------------------------- interpolation
 // One workgroup per chunk of a bin: stage the bin plus its (w - 1)-cell halo
-// of the fine grid in LDS.  The chunk's primary records (first tap inside the
-// bin) are counting-sorted in LDS by first-tap cell, a sub-batch at a time, so
-// that the lanes of a wave gather their w x w taps from neighbouring cells
-// (distinct banks or broadcasts) instead of random ones; each record then
-// writes its caller-order slot.
+// of the fine grid in LDS; each primary record of the chunk (first tap inside
+// the bin) gathers its w x w taps from it and writes its caller-order slot.
+// Records are taken kInterpBatch per thread at a time so that their loads are
+// in flight together.
 constexpr int kInterpThreads = 256;
-constexpr int kInterpSB = 512;  // records per LDS sub-batch
-// (launch bound: at least 5 waves per SIMD, i.e. at most 96 VGPRs, so that six
-// 26 KB workgroups share a CU)
+constexpr int kInterpBatch = 2;
+// (launch bound: at least 5 waves per SIMD, i.e. at most 96 VGPRs)
 
 template <int W>
 __global__ void __launch_bounds__(kInterpThreads, 5) k_interp(InterpArgs a) {
   constexpr int RS = kTile + W - 1;
-  constexpr int NT = kInterpThreads, SB = kInterpSB, PER = SB / NT;
-  constexpr int NC = kTile * kTile;
+  constexpr int NT = kInterpThreads, B = kInterpBatch;
   __shared__ float2 sg[RS * RS];
-  __shared__ int soff[NC + 1];
-  __shared__ float2 sd[SB];
-  __shared__ int spos[SB];
-  __shared__ int sidx[SB];
-  __shared__ int srank[SB];
   const int cid = blockIdx.x;
   if (cid >= a.nchunks[0]) return;
   const int4 ch = a.chunks[cid];
@@ -594,70 +586,27 @@ __global__ void __launch_bounds__(kInterpThreads, 5) k_interp(InterpArgs a) {
     const int gy = by * kTile + yy, gx = bx * kTile + xx;
     sg[e] = (gy < a.L && gx < a.L) ? a.grid[(size_t)gy * a.L + gx] : czero();
   }
+  __syncthreads();
   const float blog = a.beta * 1.4426950408889634f;
-  for (int b0 = 0; b0 < n; b0 += SB) {
-    const int nb = min(SB, n - b0);
-    for (int e = t; e <= NC; e += NT) soff[e] = 0;
-    __syncthreads();
-    BinRec rl[PER];
-    int key[PER];
+  for (int r0 = 0; r0 < n; r0 += NT * B) {
+    BinRec rl[B];
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int r = t + q * NT;
-      key[q] = -1;
-      if (r < nb) {
-        rl[q] = a.recs[start + b0 + r];
-        if (rec_primary(rl[q].packed)) {
-          key[q] = rec_ly(rl[q].packed) * kTile + rec_lx(rl[q].packed);
-          srank[r] = atomicAdd(&soff[key[q]], 1);
-        }
-      }
+    for (int q = 0; q < B; ++q) {
+      const int r = r0 + t + q * NT;
+      rl[q].packed = 0;  // not primary
+      if (r < n) rl[q] = a.recs[start + r];
     }
-    __syncthreads();
-    if (t < 64) {
-      constexpr int per = NC / 64;
-      const int s0 = t * per;
-      int acc = 0;
 #pragma unroll
-      for (int e = 0; e < per; ++e) acc += soff[s0 + e];
-      int incl = acc;
-      for (int o = 1; o < 64; o <<= 1) {
-        const int v = __shfl_up(incl, o, 64);
-        if (t >= o) incl += v;
-      }
-      int run = incl - acc;
-#pragma unroll
-      for (int e = 0; e < per; ++e) {
-        const int c = soff[s0 + e];
-        soff[s0 + e] = run;
-        run += c;
-      }
-      if (t == 63) soff[NC] = run;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int r = t + q * NT;
-      if (key[q] >= 0) {
-        const int slot = soff[key[q]] + srank[r];
-        sd[slot] = make_float2(rl[q].dx, rl[q].dy);
-        spos[slot] = key[q];
-        sidx[slot] = rl[q].idx;
-      }
-    }
-    __syncthreads();
-    const int np = soff[NC];
-    for (int sidx_ = t; sidx_ < np; sidx_ += NT) {
-      const float2 d = sd[sidx_];
-      const int key_ = spos[sidx_];
-      const int lx = key_ % kTile, ly = key_ / kTile;
+    for (int q = 0; q < B; ++q) {
+      if (!rec_primary(rl[q].packed)) continue;
+      const int lx = rec_lx(rl[q].packed), ly = rec_ly(rl[q].packed);
       float wx[W];
 #pragma unroll
-      for (int m = 0; m < W; ++m) wx[m] = es_kernel_fast(d.x + (float)m, a.two_over_w, blog);
+      for (int m = 0; m < W; ++m) wx[m] = es_kernel_fast(rl[q].dx + (float)m, a.two_over_w, blog);
       float accr = 0.f, acci = 0.f;
 #pragma unroll
       for (int my = 0; my < W; ++my) {
-        const float wy = es_kernel_fast(d.y + (float)my, a.two_over_w, blog);
+        const float wy = es_kernel_fast(rl[q].dy + (float)my, a.two_over_w, blog);
         const float2* row = sg + (ly + my) * RS + lx;
         float rr = 0.f, ri = 0.f;
 #pragma unroll
@@ -669,9 +618,8 @@ __global__ void __launch_bounds__(kInterpThreads, 5) k_interp(InterpArgs a) {
         accr += wy * rr;
         acci += wy * ri;
       }
-      a.out[sidx[sidx_]] = make_float2(accr, acci);
+      a.out[rl[q].idx] = make_float2(accr, acci);
     }
-    __syncthreads();
   }
 }
 
