@@ -567,7 +567,7 @@ __global__ void __launch_bounds__(256) k_spread_reduce(SpreadReduceArgs a) {
 // Records are taken kInterpBatch per thread at a time so that their loads are
 // in flight together.
 constexpr int kInterpThreads = 256;
-constexpr int kInterpBatch = 2;
+constexpr int kInterpBatch = 4;
 // (launch bound: at least 5 waves per SIMD, i.e. at most 96 VGPRs)
 
 template <int W>
