@@ -16,6 +16,10 @@ What is computed (every function cites the passage it follows):
   samples to a uniform N' x N' destination plane.
 * NU-ASM_2 / NU-FRE_2 (Eq. 9 with the type-2 sum of Eq. 8): uniform N x N source
   to non-uniform destination samples.
+* NU-ASM_3 / NU-FRE_3 (the third operator type, stated after Eq. 9 as the
+  combination of the first two): non-uniform source samples to non-uniform
+  destination samples, the type-1 sum of Eq. 7 times H fed to the type-2 sum
+  of Eq. 8.
 * Their adjoints, the hologram loss gradient, and Rayleigh-Sommerfeld direct
   integration (Eq. 10) used as an independent physical cross-check.
 
@@ -42,6 +46,8 @@ Readings of the paper (where it is silent or its printed form is garbled):
 * Both types carry the factor N'^-2 of the inverse FFT, so points that lie on
   the pixel grid reproduce the uniform FFT-ASM of Eq. 3 exactly.
 * Non-uniform source samples carry no quadrature weights: raw sums.
+* NU-ASM_3: the paper gives no intermediate grid; N' and g are those of the
+  destination window, and both point sets lie in the same N g window.
 """
 from __future__ import annotations
 
@@ -55,7 +61,7 @@ __all__ = [
     "transfer_asm", "transfer_fresnel", "transfer", "nuasm1", "nuasm2",
     "nuasm1_adjoint", "nuasm2_adjoint", "type1_spectrum", "spectrum_at",
     "cgh_loss", "cgh_grad", "rayleigh_sommerfeld", "rel_l2", "snr_db", "uniform_spectrum",
-    "nuasm2_from_spectrum",
+    "nuasm2_from_spectrum", "nuasm3", "nuasm3_adjoint",
 ]
 
 
@@ -327,6 +333,26 @@ def nuasm2_adjoint(geo: Geometry, w: np.ndarray, x, y, H: np.ndarray | None = No
     D = _source_dft(geo.N, geo.Np)
     Em = D.conj().T                                   # [m, k] = exp(+2 pi i m k/N')
     return (Em @ (np.conj(H) * W) @ Em.T) / float(geo.Np) ** 2
+
+
+def nuasm3(geo: Geometry, x1, y1, c, x2, y2, H: np.ndarray | None = None) -> np.ndarray:
+    """NU-ASM_3 / NU-FRE_3 (the combination of Eqs. 6 and 9 stated after
+    Eq. 9): u2_j = N'^-2 sum_{k in K^2} H(k) F(k) exp(+2 pi i df k.q_j) with
+    F the type-1 sum of Eq. 7 over the source points p_i = (x1, y1) and
+    q_j = (x2, y2) the destination points.  complex128[M2]."""
+    if H is None:
+        H = transfer(geo)
+    F = type1_spectrum(geo, x1, y1, c)
+    return _type2_eval(geo, H * F / float(geo.Np) ** 2, x2, y2)
+
+
+def nuasm3_adjoint(geo: Geometry, w: np.ndarray, x1, y1, x2, y2, H: np.ndarray | None = None) -> np.ndarray:
+    """Adjoint of NU-ASM_3: the same operator from the destination points to
+    the source points with conj(H).  complex128[M1]."""
+    if H is None:
+        H = transfer(geo)
+    W = type1_spectrum(geo, x2, y2, w)
+    return _type2_eval(geo, np.conj(H) * W / float(geo.Np) ** 2, x1, y1)
 
 
 # ------------------------------------------------------------ hologram loss

@@ -382,3 +382,93 @@ def test_paper_experiment_nuasm2_reaches_reported_snr():
     # the same comparison with z -> -z (wrong propagation direction) fails
     geo_m = O.Geometry(N=N, g=d, lam=lam, z=-z, tf="asm", band="limited")
     assert O.snr_db(O.nuasm2(geo_m, u1, x, y, O.transfer(geo_m)), ref) < 10.0
+
+
+# ------------------------------------------------- NU-ASM_3 / NU-FRE_3 pins
+@pytest.mark.parametrize("tf,band,z", [("asm", "full", 0.01), ("asm", "limited", 0.04),
+                                       ("fresnel", "full", 0.006)])
+def test_nuasm3_on_grid_equals_fft_asm(tf, band, z):
+    """Sources on the N x N pixel grid and destinations on the N' x N' grid:
+    the composition is Eq. 3 with numpy's FFT, sampled at the destinations."""
+    geo = _geo(N=16, g=4e-6, lam=633e-9, z=z, ox=1.5e-5, oy=-2.5e-5, tf=tf, band=band)
+    rng = np.random.default_rng(71)
+    M1, M2 = 45, 55
+    mx = rng.integers(-8, 8, size=M1)
+    my = rng.integers(-8, 8, size=M1)
+    c = rng.standard_normal(M1) + 1j * rng.standard_normal(M1)
+    H = O.transfer(geo)
+    img = np.zeros((geo.Np, geo.Np), dtype=np.complex128)
+    np.add.at(img, (my + 16, mx + 16), c)
+    ref = _fft_asm_full(H, img)
+    nx = rng.integers(-16, 16, size=M2)
+    ny = rng.integers(-16, 16, size=M2)
+    got = O.nuasm3(geo, mx * geo.g, my * geo.g, c, nx * geo.g, ny * geo.g, H)
+    assert O.rel_l2(got, ref[ny + 16, nx + 16]) < 1e-13
+
+
+def test_nuasm3_z0_is_dirichlet_kernel_between_point_sets():
+    """z = 0, full band: H = exp(2 pi i df k.o), so per axis
+    u2_j = N'^-2 sum_i c_i conj(D)(q_j + o/g - p_i) with D the closed-form
+    Dirichlet kernel over K; both point sets off the grid."""
+    geo = _geo(N=8, g=4e-6, z=0.0, ox=2.3e-6, oy=-1.1e-6)
+    rng = np.random.default_rng(72)
+    x1, y1 = synth.uniform_box(rng, 14, geo.N * geo.g)
+    x2, y2 = synth.clustered_box(rng, 17, geo.N * geo.g)
+    c = rng.standard_normal(14) + 1j * rng.standard_normal(14)
+    got = O.nuasm3(geo, x1, y1, c, x2, y2)
+    ref = np.empty(17, dtype=np.complex128)
+    for j in range(17):
+        dx = (x2[j] + geo.ox - x1) / geo.g
+        dy = (y2[j] + geo.oy - y1) / geo.g
+        ref[j] = np.sum(c * np.conj(_dirichlet(dx, geo.Np)) * np.conj(_dirichlet(dy, geo.Np)))
+    ref /= geo.Np ** 2
+    assert O.rel_l2(got, ref) < 1e-12
+
+
+def test_nuasm3_common_shift_leaves_output_unchanged():
+    """Only q_j - p_i enters: moving both point sets by the same non-integer
+    amount changes nothing (a sign slip in either sum breaks this)."""
+    geo = _geo(N=16, g=4e-6, z=0.03, ox=1e-5, band="limited")
+    rng = np.random.default_rng(73)
+    half = 0.35 * geo.N * geo.g
+    x1, y1 = synth.uniform_box(rng, 30, half)
+    x2, y2 = synth.uniform_box(rng, 25, half)
+    c = rng.standard_normal(30) + 1j * rng.standard_normal(30)
+    H = O.transfer(geo)
+    u = O.nuasm3(geo, x1, y1, c, x2, y2, H)
+    dx, dy = 2.37 * geo.g, -1.61 * geo.g
+    v = O.nuasm3(geo, x1 + dx, y1 + dy, c, x2 + dx, y2 + dy, H)
+    assert O.rel_l2(v, u) < 1e-12
+
+
+def test_nuasm3_reduces_to_types_1_and_2():
+    """Destinations on the N' grid give NU-ASM_1's samples; sources on the
+    N x N grid give NU-ASM_2 of the corresponding image."""
+    geo = _geo(N=8, g=5e-6, lam=500e-9, z=0.004, ox=-3e-6, oy=7e-6, tf="fresnel")
+    rng = np.random.default_rng(74)
+    x1, y1 = synth.clustered_box(rng, 21, geo.N * geo.g)
+    c = rng.standard_normal(21) + 1j * rng.standard_normal(21)
+    H = O.transfer(geo)
+    nx = rng.integers(-8, 8, size=30)
+    ny = rng.integers(-8, 8, size=30)
+    u1 = O.nuasm1(geo, x1, y1, c, H)
+    got = O.nuasm3(geo, x1, y1, c, nx * geo.g, ny * geo.g, H)
+    assert O.rel_l2(got, u1[ny + 8, nx + 8]) < 1e-13
+    img = rng.standard_normal((8, 8)) + 1j * rng.standard_normal((8, 8))
+    px, py = np.meshgrid(np.arange(-4, 4), np.arange(-4, 4), indexing="xy")
+    x2, y2 = synth.uniform_box(rng, 19, geo.N * geo.g)
+    got = O.nuasm3(geo, px.ravel() * geo.g, py.ravel() * geo.g, img.ravel(), x2, y2, H)
+    assert O.rel_l2(got, O.nuasm2(geo, img, x2, y2, H)) < 1e-13
+
+
+@pytest.mark.parametrize("tf,band", [("asm", "limited"), ("fresnel", "full")])
+def test_nuasm3_adjoint_dot_product(tf, band):
+    geo = _geo(N=8, z=0.002, ox=1e-5, oy=-4e-6, tf=tf, band=band)
+    rng = np.random.default_rng(75)
+    x1, y1 = synth.clustered_box(rng, 29, geo.N * geo.g)
+    x2, y2 = synth.uniform_box(rng, 33, geo.N * geo.g)
+    c = rng.standard_normal(29) + 1j * rng.standard_normal(29)
+    w = rng.standard_normal(33) + 1j * rng.standard_normal(33)
+    lhs = np.vdot(w, O.nuasm3(geo, x1, y1, c, x2, y2))
+    rhs = np.vdot(O.nuasm3_adjoint(geo, w, x1, y1, x2, y2), c)
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
