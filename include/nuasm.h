@@ -12,10 +12,18 @@
  *     u1 -> complex samples at non-uniform destination points q_j,
  *       u2_j = N'^-2 sum_{k in K^2} H(k) U(k) exp(2 pi i df k.q_j),
  *       U(k) = sum_m u1[m] exp(-2 pi i k.m / N').
+ *   NU-ASM_3 / NU-FRE_3 (the third type, stated after Eq. 9 as the
+ *     combination of the first two): complex samples c_i at non-uniform
+ *     source points p_i -> complex samples at non-uniform destination points
+ *     q_j, both in the same N g window,
+ *       u2_j = N'^-2 sum_{k in K^2} H(k) F(k) exp(2 pi i df k.q_j),
+ *     with F the type-1 sum above; N' and g are the destination's (the paper
+ *     names no intermediate grid).
  *
  *   N' = 2N (zero padding against circular wrap, the passage after Eq. 5),
  *   K = {-N'/2, ..., N'/2 - 1}, g is the pitch of the uniform plane
- *   (Delta_2 for type 1, Delta_1 for type 2, as stated under Eqs. 6 and 9).
+ *   (Delta_2 for type 1, Delta_1 for type 2, as stated under Eqs. 6 and 9;
+ *   Delta_2 for type 3).
  *   H is the shifted band-limited ASM transfer function (Eq. 4) or the
  *   Fresnel transfer function (Eq. 5, the DFT of the impulse response
  *   sampled on the centred N' x N' grid with area element g^2).
@@ -59,7 +67,7 @@ typedef enum {
   NUASM_ERR_HIP = 7            /* a HIP runtime call failed */
 } nuasm_status;
 
-enum { NUASM_TYPE_1 = 1, NUASM_TYPE_2 = 2 };
+enum { NUASM_TYPE_1 = 1, NUASM_TYPE_2 = 2, NUASM_TYPE_3 = 3 };
 enum { NUASM_TF_ASM = 0, NUASM_TF_FRESNEL = 1 };
 /* Rect of Eq. 4: full grid; limited = aliasing-free band of the shifted ASM
  * (per axis |o - z f / sqrt(1/lambda^2 - f^2)| <= N g, edges inclusive);
@@ -72,7 +80,7 @@ enum { NUASM_BAND_FULL = 0, NUASM_BAND_LIMITED = 1, NUASM_BAND_EXPLICIT = 2 };
 #define NUASM_DEFER_RANGE_CHECK 0x2u  /* set_points does not synchronise */
 
 typedef struct {
-  int32_t type;        /* NUASM_TYPE_1 or NUASM_TYPE_2 */
+  int32_t type;        /* NUASM_TYPE_1, NUASM_TYPE_2 or NUASM_TYPE_3 */
   int32_t tf;          /* NUASM_TF_ASM or NUASM_TF_FRESNEL */
   int32_t band;        /* NUASM_BAND_* (ASM only) */
   int32_t phase_fp64;  /* 1 (default): ASM phase in float64; 0: float32 */
@@ -82,11 +90,12 @@ typedef struct {
                           must be != 0 for Fresnel */
   double ox, oy;       /* off-axis offset o of Eq. 4, metres */
   double d1, d2;       /* source / destination pitch, metres; the uniform
-                          plane's pitch is used: d2 for type 1, d1 for type 2 */
+                          plane's pitch is used: d2 for type 1, d1 for type 2;
+                          type 3 uses d2 */
   double band_c[2];    /* NUASM_BAND_EXPLICIT: band centre (c_m, c_n), index units */
   double band_w[2];    /* NUASM_BAND_EXPLICIT: band width  (w_m, w_n), index units */
   double tol;          /* spreading-kernel tolerance, 1e-12 .. 1e-2 */
-  uint32_t flags;      /* NUASM_OUT_CROP_N | NUASM_DEFER_RANGE_CHECK */
+  uint32_t flags;      /* NUASM_OUT_CROP_N (type 1 only) | NUASM_DEFER_RANGE_CHECK */
   uint32_t reserved;   /* must be 0 */
 } nuasm_params;
 
@@ -103,6 +112,7 @@ typedef struct {
                                  (for the current point count) */
   int64_t M;                  /* points of the last set_points (0 if none) */
   size_t device_bytes;        /* device memory the plan holds */
+  int64_t M_dest;             /* type 3: points of the last set_dest_points */
 } nuasm_plan_info;
 
 typedef struct nuasm_plan_s* nuasm_plan;
@@ -110,11 +120,12 @@ typedef struct nuasm_plan_s* nuasm_plan;
 /* Fill *p with defaults: type 1, ASM, full band, float64 phase, tol 1e-6. */
 nuasm_status nuasm_params_default(nuasm_params* p);
 
-/* Create a plan on the current HIP device for operator Eq. 6 (type 1) or
- * Eq. 9 (type 2) with transfer function Eq. 4 or Eq. 5.  hip_stream is a
- * hipStream_t (NULL = default stream); it is borrowed, not owned.  Builds the
- * plan tables on the device (twiddles, deconvolution weights, Fresnel axis
- * transforms).  On failure *out is set to NULL. */
+/* Create a plan on the current HIP device for operator Eq. 6 (type 1),
+ * Eq. 9 (type 2) or their combination (type 3) with transfer function Eq. 4
+ * or Eq. 5.  hip_stream is a hipStream_t (NULL = default stream); it is
+ * borrowed, not owned.  Builds the plan tables on the device (twiddles,
+ * deconvolution weights, Fresnel axis transforms).  On failure *out is set
+ * to NULL. */
 nuasm_status nuasm_plan_create(const nuasm_params* p, void* hip_stream, nuasm_plan* out);
 
 /* Release every resource of the plan.  NULL-safe.  Synchronises the plan's
@@ -132,23 +143,33 @@ nuasm_status nuasm_plan_get_info(nuasm_plan plan, nuasm_plan_info* info);
  * bins.  The arrays are read on the plan's stream and may be freed once the
  * stream has passed this call; the plan keeps its own sorted copy.  Returns
  * NUASM_ERR_OUT_OF_RANGE (and leaves the plan not ready) if any point is
- * outside the window or not finite.  M = 0 is allowed. */
+ * outside the window or not finite.  M = 0 is allowed.  For a type-3 plan
+ * these are the source points p_i. */
 nuasm_status nuasm_set_points(nuasm_plan plan, int64_t M, const double* x_dev, const double* y_dev);
 
+/* Type 3 only: bind the destination points q_j, with the same conventions,
+ * range check and synchronisation as nuasm_set_points (NUASM_ERR_INVALID_ARG
+ * for other plan types).  Each point set keeps its own buffers, so either
+ * can be rebound without touching the other. */
+nuasm_status nuasm_set_dest_points(nuasm_plan plan, int64_t M, const double* x_dev, const double* y_dev);
+
 /* With NUASM_DEFER_RANGE_CHECK: synchronise and report whether the last
- * set_points saw out-of-range points (NUASM_ERR_OUT_OF_RANGE) or not. */
+ * set_points (and, for type 3, set_dest_points) saw out-of-range points
+ * (NUASM_ERR_OUT_OF_RANGE) or not. */
 nuasm_status nuasm_check_points(nuasm_plan plan);
 
 /* Apply the operator.  Type 1: in_dev = c[M], out_dev = u2[N'][N'] (or
  * [N][N] with NUASM_OUT_CROP_N).  Type 2: in_dev = u1[N][N], out_dev = u2[M]
- * in the caller's point order.  Device pointers, complex64, caller-owned,
- * non-overlapping. */
+ * in the caller's point order.  Type 3: in_dev = c[M] (source order),
+ * out_dev = u2[M_dest] (destination order).  Device pointers, complex64,
+ * caller-owned, non-overlapping. */
 nuasm_status nuasm_execute(nuasm_plan plan, const void* in_dev, void* out_dev);
 
 /* Apply the adjoint (conjugate transpose) of the plan's operator, derived
  * from Eqs. 6 and 9 by reversing every step and conjugating H.  Type 1:
  * in_dev = v[N'][N'], out_dev = w[M].  Type 2: in_dev = w[M], out_dev =
- * u1'[N][N]. */
+ * u1'[N][N].  Type 3: in_dev = w[M_dest], out_dev = c'[M] (the type-3
+ * operator from the destination to the source points with conj H). */
 nuasm_status nuasm_execute_adjoint(nuasm_plan plan, const void* in_dev, void* out_dev);
 
 /* Write the transfer function exactly as the fused spectral kernel applies
@@ -177,7 +198,9 @@ nuasm_status nuasm_debug_fft(int64_t n, int64_t batch, int32_t sign, const void*
 #define NUASM_STAGE_T2_COLS 10     /* type-2 pipeline: fused column pass */
 #define NUASM_STAGE_T2_ROWS_INV 11 /* type-2 pipeline: fine rows, inverse FFT */
 #define NUASM_STAGE_INTERP 12      /* interpolation */
-#define NUASM_NUM_STAGES 13
+#define NUASM_STAGE_T3_COLS 13     /* type-3 pipeline: fused column pass (between
+                                      T1_ROWS and T2_ROWS_INV) */
+#define NUASM_NUM_STAGES 14
 nuasm_status nuasm_plan_set_timing(nuasm_plan plan, int32_t enable);
 /* Synchronise on the recorded events, add each stage's elapsed milliseconds
  * and launch count into ms[NUASM_NUM_STAGES] / launches[NUASM_NUM_STAGES]
@@ -190,7 +213,9 @@ nuasm_status nuasm_plan_read_timing(nuasm_plan plan, double* ms, int64_t* launch
  * count) run as one HIP graph: the binning and the operator of every plane
  * are captured once, on parallel branches, and replayed by each run.  For
  * callers that propagate many planes per step (a batch of holograms, a
- * focal stack).  Plans inside a batch always defer their range checks. */
+ * focal stack).  Plans inside a batch always defer their range checks.
+ * Type-3 planes are not batched (nuasm_batch_create returns
+ * NUASM_ERR_UNSUPPORTED). */
 typedef struct nuasm_batch_s* nuasm_batch;
 
 /* params[P]; hip_stream is borrowed.  On failure *out is NULL. */

@@ -14,13 +14,13 @@ import os
 import torch  # loads the HIP runtime the library binds to
 
 __all__ = [
-    "Plan", "Batch", "make_params", "NUASM1", "NUASM2", "nuasm1", "nuasm2", "debug_fft", "lib_path", "load",
-    "NuasmError", "TYPE_1", "TYPE_2", "TF_ASM", "TF_FRESNEL",
+    "Plan", "Batch", "make_params", "NUASM1", "NUASM2", "NUASM3", "nuasm1", "nuasm2", "nuasm3", "debug_fft",
+    "lib_path", "load", "NuasmError", "TYPE_1", "TYPE_2", "TYPE_3", "TF_ASM", "TF_FRESNEL",
 ]
 
-TYPE_1, TYPE_2 = 1, 2
+TYPE_1, TYPE_2, TYPE_3 = 1, 2, 3
 STAGES = ("bin_hist", "bin_colscan", "bin_scan", "bin_scatter", "spread", "spread_reduce",
-          "t1_rows", "t1_cols", "t1_rows_inv", "t2_rows", "t2_cols", "t2_rows_inv", "interp")
+          "t1_rows", "t1_cols", "t1_rows_inv", "t2_rows", "t2_cols", "t2_rows_inv", "interp", "t3_cols")
 TF_ASM, TF_FRESNEL = 0, 1
 BAND = {"full": 0, "limited": 1, "explicit": 2}
 TF = {"asm": TF_ASM, "fresnel": TF_FRESNEL}
@@ -60,6 +60,7 @@ class PlanInfo(ctypes.Structure):
         ("tiles", ctypes.c_int32), ("kx_lo", ctypes.c_int32), ("kx_hi", ctypes.c_int32),
         ("ky_lo", ctypes.c_int32), ("ky_hi", ctypes.c_int32), ("in_elems", ctypes.c_int64),
         ("out_elems", ctypes.c_int64), ("M", ctypes.c_int64), ("device_bytes", ctypes.c_size_t),
+        ("M_dest", ctypes.c_int64),
     ]
 
 
@@ -73,6 +74,7 @@ _SIGS = {
     "nuasm_plan_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "nuasm_plan_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(PlanInfo)]),
     "nuasm_set_points": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
+    "nuasm_set_dest_points": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
     "nuasm_check_points": (ctypes.c_int, [ctypes.c_void_p]),
     "nuasm_execute": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "nuasm_execute_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -159,11 +161,14 @@ def make_params(N: int, type: int, lam: float, z: float, g: float, *, tf: str = 
 
 
 class Plan:
-    """One operator instance: NU-ASM_1/NU-FRE_1 (type 1, Eq. 6) or
-    NU-ASM_2/NU-FRE_2 (type 2, Eq. 9) on an N x N plane of pitch g.
+    """One operator instance: NU-ASM_1/NU-FRE_1 (type 1, Eq. 6),
+    NU-ASM_2/NU-FRE_2 (type 2, Eq. 9) or NU-ASM_3/NU-FRE_3 (type 3, their
+    combination) on an N x N window of pitch g.
 
     Type 1: ``execute(c[M]) -> u2[N'][N']`` (``[N][N]`` with ``crop=True``).
-    Type 2: ``execute(u1[N][N]) -> u2[M]``.  Points are FP64 metres.
+    Type 2: ``execute(u1[N][N]) -> u2[M]``.
+    Type 3: ``set_points`` binds the sources, ``set_dest_points`` the
+    destinations; ``execute(c[M]) -> u2[M_dest]``.  Points are FP64 metres.
     """
 
     def __init__(self, N: int, type: int, lam: float, z: float, g: float, *, tf: str = "asm",
@@ -181,6 +186,7 @@ class Plan:
             _check(lib.nuasm_plan_create(ctypes.byref(p), ctypes.c_void_p(_stream_ptr()), ctypes.byref(h)))
         self._h = h
         self.M = 0
+        self.M_dest = 0
 
     # ------------------------------------------------------------ lifecycle
     def close(self):
@@ -204,28 +210,42 @@ class Plan:
         return {f: getattr(i, f) for f, _ in PlanInfo._fields_}
 
     # ------------------------------------------------------------- calls
-    def set_points(self, x: torch.Tensor, y: torch.Tensor):
+    def _bind(self, fn, x: torch.Tensor, y: torch.Tensor) -> int:
         if x.shape != y.shape or x.dim() != 1:
             raise ValueError("x and y must be 1-D tensors of equal length")
         self._sync_stream()
         M = x.numel()
         xp = _dev_ptr(x, torch.float64, "x") if M else None
         yp = _dev_ptr(y, torch.float64, "y") if M else None
-        _check(load().nuasm_set_points(self._h, M, ctypes.c_void_p(xp), ctypes.c_void_p(yp)))
-        self.M = M
+        _check(fn(self._h, M, ctypes.c_void_p(xp), ctypes.c_void_p(yp)))
+        return M
+
+    def set_points(self, x: torch.Tensor, y: torch.Tensor):
+        """Bind the non-uniform points (type 3: the source points)."""
+        self.M = self._bind(load().nuasm_set_points, x, y)
         self._points = (x, y)  # keep alive until the stream has read them
+        return self
+
+    def set_dest_points(self, x: torch.Tensor, y: torch.Tensor):
+        """Type 3: bind the destination points."""
+        self.M_dest = self._bind(load().nuasm_set_dest_points, x, y)
+        self._dest_points = (x, y)
         return self
 
     def check_points(self):
         _check(load().nuasm_check_points(self._h))
 
     def _in_shape(self, adjoint: bool):
+        if self.type == TYPE_3:
+            return (self.M_dest,) if adjoint else (self.M,)
         fwd = (self.M,) if self.type == TYPE_1 else (self.N, self.N)
         if not adjoint:
             return fwd
         return (self.Np, self.Np) if self.type == TYPE_1 else (self.M,)
 
     def _out_shape(self, adjoint: bool):
+        if self.type == TYPE_3:
+            return (self.M,) if adjoint else (self.M_dest,)
         if self.type == TYPE_1:
             if adjoint:
                 return (self.M,)
@@ -364,9 +384,26 @@ class NUASM2(torch.autograd.Function):
         return ctx.plan.adjoint(grad.contiguous()), None
 
 
+class NUASM3(torch.autograd.Function):
+    """u2 = NU-ASM_3(c) with backward = the hand-written adjoint."""
+
+    @staticmethod
+    def forward(ctx, c, plan: Plan):
+        ctx.plan = plan
+        return plan.execute(c.contiguous())
+
+    @staticmethod
+    def backward(ctx, grad):
+        return ctx.plan.adjoint(grad.contiguous()), None
+
+
 def nuasm1(c: torch.Tensor, plan: Plan) -> torch.Tensor:
     return NUASM1.apply(c, plan)
 
 
 def nuasm2(u1: torch.Tensor, plan: Plan) -> torch.Tensor:
     return NUASM2.apply(u1, plan)
+
+
+def nuasm3(c: torch.Tensor, plan: Plan) -> torch.Tensor:
+    return NUASM3.apply(c, plan)

@@ -368,6 +368,69 @@ k_t2_rows_inv(const float2* __restrict__ V, float2* __restrict__ fine, GridGeom 
   }
 }
 
+// ----------------------------------------------------------------- type 3
+// Column pass of NU-ASM_3 / NU-FRE_3 (non-uniform source and destination),
+// between the type-1 row pass over the source's fine support and the type-2
+// inverse row pass over the destination's: columns of T -> nf-point FFT along
+// y -> keep k_y in K (the gap outside K zeroed) -> times H(k) Rect(k) N'^-2
+// and the three deconvolutions not applied elsewhere, 1/psihat(k_y) of the
+// spreading, 1/psihat(k_y) and 1/psihat(k_x) of the interpolation -> inverse
+// nf-point FFT along y -> the support rows [s0, s0 + L).  Both grids are fine
+// grids, so the (-1)^k factors of the window offset cancel between the
+// forward and the inverse transform on each axis.  Every element is scaled
+// in place by its own thread: one LDS buffer, no register staging.
+template <int LOGNF>
+struct T3Cfg {
+  using Col = ColCfg<LOGNF>;
+  static constexpr int C = Col::C, NT = Col::NT, DATA = Col::DATA;
+  static constexpr int LDS = (DATA + Tw2<LOGNF>::SIZE) * 8;
+};
+
+template <int LOGNP>
+__global__ void __launch_bounds__(T3Cfg<LOGNP + 1>::NT)
+k_t3_cols(const float2* __restrict__ T, float2* __restrict__ V, GridGeom g, Spectral sp,
+          const float2* __restrict__ twall) {
+  constexpr int LOGN = LOGNP + 1, NF = 1 << LOGN, NP = 1 << LOGNP;
+  using Cfg = T3Cfg<LOGN>;
+  constexpr int C = Cfg::C, NT = Cfg::NT;
+  extern __shared__ float2 s[];
+  const int strip = xcd_remap(blockIdx.x, gridDim.x);
+  const int a0 = strip * C;
+  const int kx0 = a0 - NP / 2;
+  if (kx0 + C - 1 < g.kxlo || kx0 > g.kxhi) return;  // whole strip outside the band
+  float2* twf = s + Cfg::DATA;
+  load_tw2<LOGN, NT>(twf, tw_for(twall, LOGN));
+  const int L = g.L, s0 = g.s0;
+  for (int e = threadIdx.x; e < C * NF; e += NT) {
+    const int t = e / C, c = e % C;
+    const int i = t - s0;
+    float2 v = czero();
+    if (i >= 0 && i < L && in_band(kx0 + c, g.kxlo, g.kxhi)) v = T[(size_t)i * NP + a0 + c];
+    s[pidx(e)] = v;
+  }
+  __syncthreads();
+  fft_lds<LOGN, C, NT, -1>(s, twf);
+  for (int e = threadIdx.x; e < C * NF; e += NT) {
+    const int t = e / C, c = e % C;
+    const int ky = t < NF / 2 ? t : t - NF;
+    const int kx = kx0 + c;
+    float2 x = czero();
+    if (ky >= -NP / 2 && ky < NP / 2 && in_band(kx, g.kxlo, g.kxhi) && in_band(ky, g.kylo, g.kyhi)) {
+      const float2 h = transfer_at(sp, NP, kx, ky);
+      const float dy = sp.dinv[ky + NP / 2];
+      x = cmul(s[pidx(e)], h);
+      x = cscale(x, dy * dy * sp.dinv[kx + NP / 2] * sp.scale);
+    }
+    s[pidx(e)] = x;
+  }
+  __syncthreads();
+  fft_lds<LOGN, C, NT, +1>(s, twf);
+  for (int e = threadIdx.x; e < C * L; e += NT) {
+    const int i = e / C, c = e % C;
+    if (in_band(kx0 + c, g.kxlo, g.kxhi)) V[(size_t)i * NP + a0 + c] = s[pidx((s0 + i) * C + c)];
+  }
+}
+
 // ----------------------------------------------------------- test kernels
 template <int LOGN, int DIR>
 __global__ void __launch_bounds__(RowCfg<LOGN>::NT)
@@ -536,6 +599,21 @@ hipError_t launch_t2_rows_inv(int logNp, const float2* V, float2* fine, GridGeom
     if (e != hipSuccess) return e;                                                       \
     const int grid = (g.L + Cfg::C - 1) / Cfg::C;                                        \
     hipLaunchKernelGGL(k_t2_rows_inv<LP>, dim3(grid), dim3(Cfg::NT), Cfg::LDS, st, V, fine, g, tw); \
+  }
+  NUASM_DISPATCH_NP(logNp, CALL)
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_t3_cols(int logNp, const float2* T, float2* V, GridGeom g, Spectral sp,
+                          const float2* tw, hipStream_t st) {
+#define CALL(LP)                                                                         \
+  {                                                                                      \
+    using Cfg = T3Cfg<LP + 1>;                                                           \
+    hipError_t e = set_lds(k_t3_cols<LP>, Cfg::LDS);                                     \
+    if (e != hipSuccess) return e;                                                       \
+    const int grid = (1 << LP) / Cfg::C;                                                 \
+    hipLaunchKernelGGL(k_t3_cols<LP>, dim3(grid), dim3(Cfg::NT), Cfg::LDS, st, T, V, g, sp, tw); \
   }
   NUASM_DISPATCH_NP(logNp, CALL)
 #undef CALL

@@ -122,6 +122,11 @@ hipError_t launch_t2_cols(int logNp, const float2* T, float2* V, GridGeom g, Spe
                           const float2* tw, hipStream_t st);
 hipError_t launch_t2_rows_inv(int logNp, const float2* V, float2* fine, GridGeom g, const float2* tw,
                               hipStream_t st);
+// type-3 column pass: source support rows (after launch_t1_rows) -> FFT ->
+// transfer function and deconvolutions -> inverse FFT -> destination support
+// rows (for launch_t2_rows_inv)
+hipError_t launch_t3_cols(int logNp, const float2* T, float2* V, GridGeom g, Spectral sp,
+                          const float2* tw, hipStream_t st);
 
 hipError_t launch_stamp(long long* out, hipStream_t st);
 hipError_t launch_transfer_table(const GridGeom& g, const Spectral& sp, float2* out, hipStream_t st);

@@ -161,6 +161,32 @@ void band_axis(double lam, double z, double o, double S, double df, int Np, int*
 }  // namespace
 
 // ------------------------------------------------------------------- plan
+// One bound point set: its records in bin order, the counting-sort state and
+// the chunk tables of the spreading and interpolation kernels.
+struct PointSet {
+  int* counts = nullptr;     // records per bin
+  int* cursor = nullptr;     // first record of each bin
+  uint16_t* hist = nullptr;  // [G][T] per-range bin counts
+  int* hoff = nullptr;       // [G][T] per-range offsets inside each bin
+  int64_t hist_rows = 0;
+  int* sp_first = nullptr;
+  int* sp_n = nullptr;
+  int* multi = nullptr;
+  int* nch = nullptr;  // [8]: chunk and record counts [0..3], points out of range [4], scan hand-off counter [7]
+  int4* sp_chunks = nullptr;
+  int4* ip_chunks = nullptr;
+  int64_t chunk_cap = 0;
+  BinRec* recs = nullptr;
+  int64_t rec_cap = 0;  // points the record buffer is sized for
+  float2* scratch = nullptr;
+  int64_t scratch_chunks = 0;
+  int* host_stat = nullptr;  // pinned [8]
+  int64_t M = 0;
+  bool ready = false;
+  bool synced = false;
+  int exact_sp = 0, exact_ip = 0, exact_multi = 0;
+};
+
 struct nuasm_plan_s {
   nuasm_params p{};
   hipStream_t stream = nullptr;
@@ -178,35 +204,21 @@ struct nuasm_plan_s {
   float2* gridB = nullptr;
   float* dinv = nullptr;
   float2* fre = nullptr;  // [2][Np]
-  int* counts = nullptr;   // records per bin
-  int* cursor = nullptr;   // first record of each bin
-  uint16_t* hist = nullptr;  // [G][T] per-range bin counts
-  int* hoff = nullptr;       // [G][T] per-range offsets inside each bin
-  int64_t hist_rows = 0;
-  int* sp_first = nullptr;
-  int* sp_n = nullptr;
-  int* multi = nullptr;
-  int* nch = nullptr;     // [8]: chunk and record counts [0..3], points out of range [4], scan hand-off counter [7]
-  int4* sp_chunks = nullptr;
-  int4* ip_chunks = nullptr;
-  int64_t chunk_cap = 0;
-  BinRec* recs = nullptr;
-  int64_t rec_cap = 0;    // points the record buffer is sized for
-  float2* scratch = nullptr;
-  int64_t scratch_chunks = 0;
-  int* host_stat = nullptr;  // pinned [5]
+  // point sets: [0] the plan's points (type 3: the source), [1] type 3's destination
+  PointSet ps[2];
+  int nsets = 1;
   size_t bytes = 0;
   // stage timing
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
   std::vector<int> ev_stage;          // stage of each recorded (start, end) pair
   std::vector<hipEvent_t> ev_pairs;   // start0, end0, start1, end1, ...
-  // state
-  int64_t M = 0;
-  bool ready = false;
-  bool synced = false;
-  int exact_sp = 0, exact_ip = 0, exact_multi = 0;
   int64_t grid_elems = 0;
+  bool ready() const {
+    for (int i = 0; i < nsets; ++i)
+      if (!ps[i].ready) return false;
+    return true;
+  }
 };
 
 namespace {
@@ -226,19 +238,22 @@ void release(nuasm_plan_s* pl) {
   f(pl->gridB);
   f(pl->dinv);
   f(pl->fre);
-  f(pl->counts);
-  f(pl->cursor);
-  f(pl->sp_first);
-  f(pl->sp_n);
-  f(pl->multi);
-  f(pl->nch);
-  f(pl->sp_chunks);
-  f(pl->ip_chunks);
-  f(pl->recs);
-  f(pl->scratch);
-  f(pl->hist);
-  f(pl->hoff);
-  if (pl->host_stat) (void)hipHostFree(pl->host_stat);
+  for (PointSet& q : pl->ps) {
+    f(q.counts);
+    f(q.cursor);
+    f(q.sp_first);
+    f(q.sp_n);
+    f(q.multi);
+    f(q.nch);
+    f(q.sp_chunks);
+    f(q.ip_chunks);
+    f(q.recs);
+    f(q.scratch);
+    f(q.hist);
+    f(q.hoff);
+    if (q.host_stat) (void)hipHostFree(q.host_stat);
+    q = PointSet{};
+  }
   for (hipEvent_t e : pl->ev_pool) (void)hipEventDestroy(e);
   for (hipEvent_t e : pl->ev_pairs) (void)hipEventDestroy(e);
   pl->ev_pool.clear();
@@ -282,9 +297,14 @@ struct StageScope {
 
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
+// Pitch of the plan's grid: the uniform plane's (d2 for type 1, d1 for type
+// 2); type 3 takes the destination's, d2.
+double plane_pitch(const nuasm_params* p) { return p->type == NUASM_TYPE_2 ? p->d1 : p->d2; }
+
 nuasm_status validate(const nuasm_params* p) {
   if (!p) return fail(NUASM_ERR_INVALID_ARG, "params is NULL");
-  if (p->type != NUASM_TYPE_1 && p->type != NUASM_TYPE_2) return fail(NUASM_ERR_INVALID_ARG, "type must be 1 or 2");
+  if (p->type != NUASM_TYPE_1 && p->type != NUASM_TYPE_2 && p->type != NUASM_TYPE_3)
+    return fail(NUASM_ERR_INVALID_ARG, "type must be 1, 2 or 3");
   if (p->tf != NUASM_TF_ASM && p->tf != NUASM_TF_FRESNEL) return fail(NUASM_ERR_INVALID_ARG, "tf must be ASM or FRESNEL");
   if (p->band < NUASM_BAND_FULL || p->band > NUASM_BAND_EXPLICIT) return fail(NUASM_ERR_INVALID_ARG, "bad band mode");
   if (p->phase_fp64 != 0 && p->phase_fp64 != 1) return fail(NUASM_ERR_INVALID_ARG, "phase_fp64 must be 0 or 1");
@@ -293,8 +313,10 @@ nuasm_status validate(const nuasm_params* p) {
   if (!(p->lambda > 0.0) || !std::isfinite(p->lambda)) return fail(NUASM_ERR_INVALID_ARG, "lambda must be > 0");
   if (!std::isfinite(p->z)) return fail(NUASM_ERR_INVALID_ARG, "z must be finite");
   if (!std::isfinite(p->ox) || !std::isfinite(p->oy)) return fail(NUASM_ERR_INVALID_ARG, "offset must be finite");
-  const double g = p->type == NUASM_TYPE_1 ? p->d2 : p->d1;
+  const double g = plane_pitch(p);
   if (!(g > 0.0) || !std::isfinite(g)) return fail(NUASM_ERR_INVALID_ARG, "pitch of the uniform plane must be > 0");
+  if (p->type == NUASM_TYPE_3 && (p->flags & NUASM_OUT_CROP_N))
+    return fail(NUASM_ERR_INVALID_ARG, "NUASM_OUT_CROP_N applies to type 1 only");
   if (p->tf == NUASM_TF_FRESNEL && p->z == 0.0) return fail(NUASM_ERR_INVALID_ARG, "Fresnel needs z != 0");
   if (!(p->tol >= 1e-12 && p->tol <= 1e-2)) return fail(NUASM_ERR_INVALID_ARG, "tol must be in [1e-12, 1e-2]");
   if (p->flags & ~(NUASM_OUT_CROP_N | NUASM_DEFER_RANGE_CHECK)) return fail(NUASM_ERR_INVALID_ARG, "unknown flag bits");
@@ -316,101 +338,191 @@ void bin_ranges(int64_t M, int* ppw, int* G) {
   *G = (int)((M + p - 1) / p);
 }
 
-nuasm_status ensure_points_capacity(nuasm_plan_s* pl, int64_t M) {
-  if (M <= pl->rec_cap && pl->recs) return NUASM_OK;
+// T-sized bin arrays and counters of one point set (at plan creation).
+nuasm_status alloc_point_set(nuasm_plan_s* pl, PointSet& q) {
+  HIP_TRY(dalloc(pl, &q.counts, (size_t)pl->T + 1), "hipMalloc(bins)");
+  HIP_TRY(dalloc(pl, &q.cursor, (size_t)pl->T), "hipMalloc(bins)");
+  HIP_TRY(dalloc(pl, &q.sp_first, (size_t)pl->T), "hipMalloc(bins)");
+  HIP_TRY(dalloc(pl, &q.sp_n, (size_t)pl->T), "hipMalloc(bins)");
+  HIP_TRY(dalloc(pl, &q.multi, (size_t)pl->T), "hipMalloc(bins)");
+  HIP_TRY(dalloc(pl, &q.nch, (size_t)8), "hipMalloc(counters)");
+  HIP_TRY(hipHostMalloc((void**)&q.host_stat, sizeof(int) * 8, hipHostMallocDefault), "hipHostMalloc(status)");
+  HIP_TRY(launch_fill_i32(q.nch, 0, 8, pl->stream), "launch fill");
+  return NUASM_OK;
+}
+
+nuasm_status ensure_points_capacity(nuasm_plan_s* pl, PointSet& q, int64_t M) {
+  if (M <= q.rec_cap && q.recs) return NUASM_OK;
   const int64_t cap = std::max<int64_t>(M, 1024);
   if (cap * 4 > (int64_t)INT32_MAX) return fail(NUASM_ERR_UNSUPPORTED, "too many points (4 M must fit in int32)");
   HIP_TRY(hipStreamSynchronize(pl->stream), "hipStreamSynchronize");
-  if (pl->recs) {
-    (void)hipFree(pl->recs);
-    pl->bytes -= sizeof(BinRec) * 4 * pl->rec_cap;
-    pl->recs = nullptr;
+  if (q.recs) {
+    (void)hipFree(q.recs);
+    pl->bytes -= sizeof(BinRec) * 4 * q.rec_cap;
+    q.recs = nullptr;
   }
-  if (pl->sp_chunks) {
-    (void)hipFree(pl->sp_chunks);
-    (void)hipFree(pl->ip_chunks);
-    pl->bytes -= 2 * sizeof(int4) * pl->chunk_cap;
-    pl->sp_chunks = pl->ip_chunks = nullptr;
+  if (q.sp_chunks) {
+    (void)hipFree(q.sp_chunks);
+    (void)hipFree(q.ip_chunks);
+    pl->bytes -= 2 * sizeof(int4) * q.chunk_cap;
+    q.sp_chunks = q.ip_chunks = nullptr;
   }
-  if (pl->scratch) {
-    (void)hipFree(pl->scratch);
-    pl->bytes -= sizeof(float2) * kTile * kTile * pl->scratch_chunks;
-    pl->scratch = nullptr;
-    pl->scratch_chunks = 0;
+  if (q.scratch) {
+    (void)hipFree(q.scratch);
+    pl->bytes -= sizeof(float2) * kTile * kTile * q.scratch_chunks;
+    q.scratch = nullptr;
+    q.scratch_chunks = 0;
   }
-  if (pl->hist) {
-    (void)hipFree(pl->hist);
-    (void)hipFree(pl->hoff);
-    pl->bytes -= (sizeof(uint16_t) + sizeof(int)) * pl->hist_rows * (pl->T + 1);
-    pl->hist = nullptr;
-    pl->hoff = nullptr;
+  if (q.hist) {
+    (void)hipFree(q.hist);
+    (void)hipFree(q.hoff);
+    pl->bytes -= (sizeof(uint16_t) + sizeof(int)) * q.hist_rows * (pl->T + 1);
+    q.hist = nullptr;
+    q.hoff = nullptr;
   }
-  pl->rec_cap = 0;
+  q.rec_cap = 0;
   {
     int ppw = 0, G = 0;
     bin_ranges(cap, &ppw, &G);
-    pl->hist_rows = std::max(G, 1);
-    HIP_TRY(dalloc(pl, &pl->hist, (size_t)pl->hist_rows * (pl->T + 1)), "hipMalloc(bin histograms)");
-    HIP_TRY(dalloc(pl, &pl->hoff, (size_t)pl->hist_rows * (pl->T + 1)), "hipMalloc(bin offsets)");
+    q.hist_rows = std::max(G, 1);
+    HIP_TRY(dalloc(pl, &q.hist, (size_t)q.hist_rows * (pl->T + 1)), "hipMalloc(bin histograms)");
+    HIP_TRY(dalloc(pl, &q.hoff, (size_t)q.hist_rows * (pl->T + 1)), "hipMalloc(bin offsets)");
   }
-  HIP_TRY(dalloc(pl, &pl->recs, (size_t)(4 * cap)), "hipMalloc(records)");
-  pl->chunk_cap = pl->T + (4 * cap) / kSpreadChunk + 1;  // covers both chunk tables
-  HIP_TRY(dalloc(pl, &pl->sp_chunks, (size_t)pl->chunk_cap), "hipMalloc(chunks)");
-  HIP_TRY(dalloc(pl, &pl->ip_chunks, (size_t)pl->chunk_cap), "hipMalloc(chunks)");
-  pl->rec_cap = cap;
+  HIP_TRY(dalloc(pl, &q.recs, (size_t)(4 * cap)), "hipMalloc(records)");
+  q.chunk_cap = pl->T + (4 * cap) / kSpreadChunk + 1;  // covers both chunk tables
+  HIP_TRY(dalloc(pl, &q.sp_chunks, (size_t)q.chunk_cap), "hipMalloc(chunks)");
+  HIP_TRY(dalloc(pl, &q.ip_chunks, (size_t)q.chunk_cap), "hipMalloc(chunks)");
+  q.rec_cap = cap;
   return NUASM_OK;
 }
 
-nuasm_status ensure_scratch(nuasm_plan_s* pl) {
-  if (pl->scratch) return NUASM_OK;
-  HIP_TRY(dalloc(pl, &pl->scratch, (size_t)pl->chunk_cap * kTile * kTile), "hipMalloc(spread scratch)");
-  pl->scratch_chunks = pl->chunk_cap;
+nuasm_status ensure_scratch(nuasm_plan_s* pl, PointSet& q) {
+  if (q.scratch) return NUASM_OK;
+  HIP_TRY(dalloc(pl, &q.scratch, (size_t)q.chunk_cap * kTile * kTile), "hipMalloc(spread scratch)");
+  q.scratch_chunks = q.chunk_cap;
   return NUASM_OK;
 }
 
-int sp_grid(const nuasm_plan_s* pl) {
-  return pl->synced ? pl->exact_sp : (int)std::min<int64_t>(pl->chunk_cap, pl->T + (4 * pl->M) / kSpreadChunk + 1);
+// Grid sizes of the point kernels: the exact chunk counts once a set_points
+// has synchronised, else upper bounds (surplus workgroups exit at once).
+int sp_grid(const nuasm_plan_s* pl, const PointSet& q) {
+  return q.synced ? q.exact_sp : (int)std::min<int64_t>(q.chunk_cap, pl->T + (4 * q.M) / kSpreadChunk + 1);
 }
-int ip_grid(const nuasm_plan_s* pl) {
-  return pl->synced ? pl->exact_ip : (int)std::min<int64_t>(pl->chunk_cap, pl->T + (4 * pl->M) / kChunk + 1);
+int ip_grid(const nuasm_plan_s* pl, const PointSet& q) {
+  return q.synced ? q.exact_ip : (int)std::min<int64_t>(q.chunk_cap, pl->T + (4 * q.M) / kChunk + 1);
 }
-int multi_grid(const nuasm_plan_s* pl) {
-  return pl->synced ? pl->exact_multi : (int)std::min<int64_t>(pl->T, (4 * pl->M) / kSpreadChunk + 1);
+int multi_grid(const nuasm_plan_s* pl, const PointSet& q) {
+  return q.synced ? q.exact_multi : (int)std::min<int64_t>(pl->T, (4 * q.M) / kSpreadChunk + 1);
 }
 
-// type-1 pipeline: values at the points -> N' x N' (or N x N) plane
-nuasm_status run_type1_pipeline(nuasm_plan_s* pl, const float2* vals, float2* out, bool conj, bool crop) {
+// Coordinate normalisation and binning of one point set (three launches).
+nuasm_status bind_points(nuasm_plan_s* pl, PointSet& q, int64_t M, const double* x, const double* y) {
+  if (M < 0) return fail(NUASM_ERR_INVALID_ARG, "M < 0");
+  if (M > 0 && (!x || !y)) return fail(NUASM_ERR_INVALID_ARG, "coordinate pointer is NULL");
+  q.ready = false;
+  nuasm_status s = ensure_points_capacity(pl, q, M);
+  if (s != NUASM_OK) return s;
   hipStream_t st = pl->stream;
-  nuasm_status s = ensure_scratch(pl);
+  {
+    int ppw = 0, G = 0;
+    bin_ranges(M, &ppw, &G);
+    if (M > 0) {
+      StageScope sc(pl, NUASM_STAGE_BIN_HIST);
+      HIP_TRY(launch_bin_hist(x, y, M, pl->bgeom, ppw, G, q.hist, st), "launch bin_hist");
+    }
+    {
+      // column scan and bin scan in one launch; with no points (G = 0) it
+      // writes zero totals and empty-bin chunk tables
+      const BinScanOut so{q.cursor, q.sp_chunks, q.sp_first, q.sp_n, q.multi, q.ip_chunks, q.nch};
+      StageScope sc(pl, NUASM_STAGE_BIN_COLSCAN);
+      HIP_TRY(launch_bin_colscan(q.hist, M > 0 ? G : 0, pl->T, q.hoff, q.counts, so, q.nch + kScanDone, st),
+              "launch bin_colscan");
+    }
+    StageScope sc(pl, NUASM_STAGE_BIN_SCATTER);
+    HIP_TRY(launch_bin_scatter(x, y, M, pl->bgeom, ppw, G, q.hoff, q.cursor, q.recs, st), "launch bin_scatter");
+  }
+  q.M = M;
+  q.synced = false;
+  if (pl->p.flags & NUASM_DEFER_RANGE_CHECK) {
+    q.ready = true;
+    return NUASM_OK;
+  }
+  HIP_TRY(hipMemcpyAsync(q.host_stat, q.nch, sizeof(int) * 5, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+  HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+  if (q.host_stat[4] != 0) {
+    char buf[128];
+    std::snprintf(buf, sizeof(buf), "%d point(s) outside the window [-N g/2, N g/2]^2 or not finite",
+                  q.host_stat[4]);
+    return fail(NUASM_ERR_OUT_OF_RANGE, buf);
+  }
+  q.exact_sp = q.host_stat[0];
+  q.exact_ip = q.host_stat[1];
+  q.exact_multi = q.host_stat[3];
+  q.synced = true;
+  q.ready = true;
+  return NUASM_OK;
+}
+
+// Spreading of one point set's values onto the fine support (gridA).
+nuasm_status run_spread(nuasm_plan_s* pl, PointSet& q, const float2* vals) {
+  hipStream_t st = pl->stream;
+  nuasm_status s = ensure_scratch(pl, q);
   if (s != NUASM_OK) return s;
   {
     StageScope sc(pl, NUASM_STAGE_SPREAD);
     SpreadArgs sa{};
-    sa.recs = pl->recs;
-    sa.chunks = pl->sp_chunks;
-    sa.nchunks = pl->nch + 0;
-    sa.scratch = pl->scratch;
+    sa.recs = q.recs;
+    sa.chunks = q.sp_chunks;
+    sa.nchunks = q.nch + 0;
+    sa.scratch = q.scratch;
     sa.vals = vals;
     sa.grid = pl->gridA;
     sa.L = pl->geom.L;
     sa.TX = pl->TX;
     sa.two_over_w = 2.0f / (float)pl->w;
     sa.beta = pl->beta;
-    HIP_TRY(launch_spread(pl->w, sa, sp_grid(pl), st), "launch spread");
+    HIP_TRY(launch_spread(pl->w, sa, sp_grid(pl, q), st), "launch spread");
   }
   {
     StageScope sc(pl, NUASM_STAGE_SPREAD_REDUCE);
     SpreadReduceArgs ra{};
-    ra.multi = pl->multi;
-    ra.nmulti = pl->nch + 3;
-    ra.bin_chunk0 = pl->sp_first;
-    ra.bin_nchunk = pl->sp_n;
-    ra.scratch = pl->scratch;
+    ra.multi = q.multi;
+    ra.nmulti = q.nch + 3;
+    ra.bin_chunk0 = q.sp_first;
+    ra.bin_nchunk = q.sp_n;
+    ra.scratch = q.scratch;
     ra.grid = pl->gridA;
     ra.L = pl->geom.L;
     ra.TX = pl->TX;
-    HIP_TRY(launch_spread_reduce(ra, multi_grid(pl), st), "launch spread_reduce");
+    HIP_TRY(launch_spread_reduce(ra, multi_grid(pl, q), st), "launch spread_reduce");
   }
+  return NUASM_OK;
+}
+
+// Interpolation of the fine support `grid` at one point set's points.
+nuasm_status run_interp(nuasm_plan_s* pl, PointSet& q, const float2* grid, float2* out) {
+  if (q.M == 0) return NUASM_OK;
+  StageScope sc(pl, NUASM_STAGE_INTERP);
+  InterpArgs ia{};
+  ia.recs = q.recs;
+  ia.chunks = q.ip_chunks;
+  ia.nchunks = q.nch + 1;
+  ia.grid = grid;
+  ia.out = out;
+  ia.L = pl->geom.L;
+  ia.TX = pl->TX;
+  ia.two_over_w = 2.0f / (float)pl->w;
+  ia.beta = pl->beta;
+  HIP_TRY(launch_interp(pl->w, ia, ip_grid(pl, q), pl->stream), "launch interp");
+  return NUASM_OK;
+}
+
+// type-1 pipeline: values at the points -> N' x N' (or N x N) plane
+nuasm_status run_type1_pipeline(nuasm_plan_s* pl, PointSet& q, const float2* vals, float2* out, bool conj,
+                                bool crop) {
+  hipStream_t st = pl->stream;
+  nuasm_status s = run_spread(pl, q, vals);
+  if (s != NUASM_OK) return s;
   GridGeom g = pl->geom;
   g.crop = crop ? 1 : 0;
   Spectral sp = pl->spec;
@@ -431,7 +543,8 @@ nuasm_status run_type1_pipeline(nuasm_plan_s* pl, const float2* vals, float2* ou
 }
 
 // type-2 pipeline: Nin x Nin plane -> values at the points
-nuasm_status run_type2_pipeline(nuasm_plan_s* pl, const float2* plane, int Nin, float2* out, bool conj) {
+nuasm_status run_type2_pipeline(nuasm_plan_s* pl, PointSet& q, const float2* plane, int Nin, float2* out,
+                                bool conj) {
   hipStream_t st = pl->stream;
   GridGeom g = pl->geom;
   g.Nin = Nin;
@@ -450,21 +563,35 @@ nuasm_status run_type2_pipeline(nuasm_plan_s* pl, const float2* plane, int Nin, 
     StageScope sc(pl, NUASM_STAGE_T2_ROWS_INV);
     HIP_TRY(launch_t2_rows_inv(pl->logNp, pl->gridA, pl->gridB, g, pl->tw, st), "launch t2_rows_inv");
   }
-  if (pl->M > 0) {
-    StageScope sc(pl, NUASM_STAGE_INTERP);
-    InterpArgs ia{};
-    ia.recs = pl->recs;
-    ia.chunks = pl->ip_chunks;
-    ia.nchunks = pl->nch + 1;
-    ia.grid = pl->gridB;
-    ia.out = out;
-    ia.L = pl->geom.L;
-    ia.TX = pl->TX;
-    ia.two_over_w = 2.0f / (float)pl->w;
-    ia.beta = pl->beta;
-    HIP_TRY(launch_interp(pl->w, ia, ip_grid(pl), st), "launch interp");
+  return run_interp(pl, q, pl->gridB, out);
+}
+
+// type-3 pipeline: values at the points of `src` -> values at the points of
+// `dst`: spreading, the type-1 row pass, the fused type-3 column pass, the
+// type-2 inverse row pass, interpolation.
+nuasm_status run_type3_pipeline(nuasm_plan_s* pl, PointSet& src, PointSet& dst, const float2* vals,
+                                float2* out, bool conj) {
+  if (dst.M == 0) return NUASM_OK;
+  hipStream_t st = pl->stream;
+  nuasm_status s = run_spread(pl, src, vals);
+  if (s != NUASM_OK) return s;
+  GridGeom g = pl->geom;
+  g.crop = 0;
+  Spectral sp = pl->spec;
+  sp.conj = conj ? 1 : 0;
+  {
+    StageScope sc(pl, NUASM_STAGE_T1_ROWS);
+    HIP_TRY(launch_t1_rows(pl->logNp, pl->gridA, pl->gridB, g, pl->dinv, pl->tw, st), "launch t1_rows");
   }
-  return NUASM_OK;
+  {
+    StageScope sc(pl, NUASM_STAGE_T3_COLS);
+    HIP_TRY(launch_t3_cols(pl->logNp, pl->gridB, pl->gridA, g, sp, pl->tw, st), "launch t3_cols");
+  }
+  {
+    StageScope sc(pl, NUASM_STAGE_T2_ROWS_INV);
+    HIP_TRY(launch_t2_rows_inv(pl->logNp, pl->gridA, pl->gridB, g, pl->tw, st), "launch t2_rows_inv");
+  }
+  return run_interp(pl, dst, pl->gridB, out);
 }
 
 }  // namespace
@@ -472,7 +599,7 @@ nuasm_status run_type2_pipeline(nuasm_plan_s* pl, const float2* plane, int Nin, 
 // ================================================================== C ABI
 extern "C" {
 
-int32_t nuasm_version(void) { return 100; }
+int32_t nuasm_version(void) { return 10100; }
 
 const char* nuasm_status_string(nuasm_status s) {
   switch (s) {
@@ -529,7 +656,7 @@ nuasm_status nuasm_plan_create(const nuasm_params* p, void* hip_stream, nuasm_pl
   int logNp = 0;
   while ((1 << logNp) < Np) ++logNp;
   pl->logNp = logNp;
-  const double g = p->type == NUASM_TYPE_1 ? p->d2 : p->d1;
+  const double g = plane_pitch(p);
   const double df = 1.0 / (Np * g);
   // kernel width from the tolerance: w = ceil(log10(1/tol)) + 1, beta = 2.30 w
   int w = (int)std::ceil(-std::log10(p->tol) - 1e-9) + 1;
@@ -601,14 +728,11 @@ nuasm_status nuasm_plan_create(const nuasm_params* p, void* hip_stream, nuasm_pl
   if ((e = dalloc(pl, &pl->gridA, (size_t)pl->grid_elems)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(gridA)"));
   if ((e = dalloc(pl, &pl->gridB, (size_t)pl->grid_elems)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(gridB)"));
   if ((e = dalloc(pl, &pl->dinv, (size_t)Np)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(dinv)"));
-  if ((e = dalloc(pl, &pl->counts, (size_t)pl->T + 1)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(bins)"));
-  if ((e = dalloc(pl, &pl->cursor, (size_t)pl->T)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(bins)"));
-  if ((e = dalloc(pl, &pl->sp_first, (size_t)pl->T)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(bins)"));
-  if ((e = dalloc(pl, &pl->sp_n, (size_t)pl->T)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(bins)"));
-  if ((e = dalloc(pl, &pl->multi, (size_t)pl->T)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(bins)"));
-  if ((e = dalloc(pl, &pl->nch, (size_t)8)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(counters)"));
-  if ((e = hipHostMalloc((void**)&pl->host_stat, sizeof(int) * 8, hipHostMallocDefault)) != hipSuccess)
-    return bail(hip_fail(e, "hipHostMalloc(status)"));
+  pl->nsets = p->type == NUASM_TYPE_3 ? 2 : 1;
+  for (int i = 0; i < pl->nsets; ++i) {
+    s = alloc_point_set(pl, pl->ps[i]);
+    if (s != NUASM_OK) return bail(s);
+  }
   {
     std::vector<float> dv = deconvolution_table(Np, nf, w, (double)pl->beta);
     if ((e = hipMemcpyAsync(pl->dinv, dv.data(), sizeof(float) * Np, hipMemcpyHostToDevice, pl->stream)) != hipSuccess)
@@ -632,7 +756,6 @@ nuasm_status nuasm_plan_create(const nuasm_params* p, void* hip_stream, nuasm_pl
     S.fre_x = pl->fre;
     S.fre_y = pl->fre + Np;
   }
-  if ((e = launch_fill_i32(pl->nch, 0, 8, pl->stream)) != hipSuccess) return bail(hip_fail(e, "launch fill"));
   *out = pl;
   return NUASM_OK;
 }
@@ -667,105 +790,98 @@ nuasm_status nuasm_plan_get_info(nuasm_plan pl, nuasm_plan_info* info) {
   info->ky_lo = pl->geom.kylo;
   info->ky_hi = pl->geom.kyhi;
   const int64_t plane = pl->geom.crop ? (int64_t)pl->geom.N * pl->geom.N : (int64_t)pl->geom.Np * pl->geom.Np;
+  const int64_t M = pl->ps[0].M, M2 = pl->nsets > 1 ? pl->ps[1].M : 0;
   if (pl->p.type == NUASM_TYPE_1) {
-    info->in_elems = pl->M;
+    info->in_elems = M;
     info->out_elems = plane;
-  } else {
+  } else if (pl->p.type == NUASM_TYPE_2) {
     info->in_elems = (int64_t)pl->geom.N * pl->geom.N;
-    info->out_elems = pl->M;
+    info->out_elems = M;
+  } else {
+    info->in_elems = M;
+    info->out_elems = M2;
   }
-  info->M = pl->M;
+  info->M = M;
   info->device_bytes = pl->bytes;
+  info->M_dest = M2;
   return NUASM_OK;
 }
 
 nuasm_status nuasm_set_points(nuasm_plan pl, int64_t M, const double* x, const double* y) {
   if (!pl) return fail(NUASM_ERR_INVALID_ARG, "plan is NULL");
-  if (M < 0) return fail(NUASM_ERR_INVALID_ARG, "M < 0");
-  if (M > 0 && (!x || !y)) return fail(NUASM_ERR_INVALID_ARG, "coordinate pointer is NULL");
-  pl->ready = false;
-  nuasm_status s = ensure_points_capacity(pl, M);
-  if (s != NUASM_OK) return s;
-  hipStream_t st = pl->stream;
-  {
-    int ppw = 0, G = 0;
-    bin_ranges(M, &ppw, &G);
-    if (M > 0) {
-      StageScope sc(pl, NUASM_STAGE_BIN_HIST);
-      HIP_TRY(launch_bin_hist(x, y, M, pl->bgeom, ppw, G, pl->hist, st), "launch bin_hist");
-    }
-    {
-      // column scan and bin scan in one launch; with no points (G = 0) it
-      // writes zero totals and empty-bin chunk tables
-      const BinScanOut so{pl->cursor, pl->sp_chunks, pl->sp_first, pl->sp_n, pl->multi, pl->ip_chunks, pl->nch};
-      StageScope sc(pl, NUASM_STAGE_BIN_COLSCAN);
-      HIP_TRY(launch_bin_colscan(pl->hist, M > 0 ? G : 0, pl->T, pl->hoff, pl->counts, so, pl->nch + kScanDone, st),
-              "launch bin_colscan");
-    }
-    StageScope sc(pl, NUASM_STAGE_BIN_SCATTER);
-    HIP_TRY(launch_bin_scatter(x, y, M, pl->bgeom, ppw, G, pl->hoff, pl->cursor, pl->recs, st),
-            "launch bin_scatter");
-  }
-  pl->M = M;
-  pl->synced = false;
-  if (pl->p.flags & NUASM_DEFER_RANGE_CHECK) {
-    pl->ready = true;
-    return NUASM_OK;
-  }
-  HIP_TRY(hipMemcpyAsync(pl->host_stat, pl->nch, sizeof(int) * 5, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
-  HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
-  if (pl->host_stat[4] != 0) {
-    char buf[128];
-    std::snprintf(buf, sizeof(buf), "%d point(s) outside the window [-N g/2, N g/2]^2 or not finite",
-                  pl->host_stat[4]);
-    return fail(NUASM_ERR_OUT_OF_RANGE, buf);
-  }
-  pl->exact_sp = pl->host_stat[0];
-  pl->exact_ip = pl->host_stat[1];
-  pl->exact_multi = pl->host_stat[3];
-  pl->synced = true;
-  pl->ready = true;
-  return NUASM_OK;
+  return bind_points(pl, pl->ps[0], M, x, y);
+}
+
+nuasm_status nuasm_set_dest_points(nuasm_plan pl, int64_t M, const double* x, const double* y) {
+  if (!pl) return fail(NUASM_ERR_INVALID_ARG, "plan is NULL");
+  if (pl->p.type != NUASM_TYPE_3) return fail(NUASM_ERR_INVALID_ARG, "destination points belong to type-3 plans");
+  return bind_points(pl, pl->ps[1], M, x, y);
 }
 
 nuasm_status nuasm_check_points(nuasm_plan pl) {
   if (!pl) return fail(NUASM_ERR_INVALID_ARG, "plan is NULL");
-  HIP_TRY(hipMemcpyAsync(pl->host_stat, pl->nch, sizeof(int) * 5, hipMemcpyDeviceToHost, pl->stream),
-          "hipMemcpyAsync");
+  for (int i = 0; i < pl->nsets; ++i) {
+    PointSet& q = pl->ps[i];
+    HIP_TRY(hipMemcpyAsync(q.host_stat, q.nch, sizeof(int) * 5, hipMemcpyDeviceToHost, pl->stream),
+            "hipMemcpyAsync");
+  }
   HIP_TRY(hipStreamSynchronize(pl->stream), "hipStreamSynchronize");
-  if (pl->host_stat[4] != 0) {
-    pl->ready = false;
-    return fail(NUASM_ERR_OUT_OF_RANGE, "points outside the window in the last set_points");
+  for (int i = 0; i < pl->nsets; ++i) {
+    PointSet& q = pl->ps[i];
+    if (q.host_stat[4] != 0) {
+      q.ready = false;
+      return fail(NUASM_ERR_OUT_OF_RANGE, i == 0 ? "points outside the window in the last set_points"
+                                                 : "points outside the window in the last set_dest_points");
+    }
   }
   return NUASM_OK;
 }
 
+namespace {
+const char* not_ready_msg(const nuasm_plan_s* pl) {
+  return pl->nsets > 1 ? "execute before successful set_points and set_dest_points"
+                       : "execute before a successful set_points";
+}
+}  // namespace
+
 nuasm_status nuasm_execute(nuasm_plan pl, const void* in, void* out) {
   if (!pl) return fail(NUASM_ERR_INVALID_ARG, "plan is NULL");
-  if (!pl->ready) return fail(NUASM_ERR_NOT_READY, "execute before a successful set_points");
+  if (!pl->ready()) return fail(NUASM_ERR_NOT_READY, not_ready_msg(pl));
+  PointSet& q = pl->ps[0];
+  if (pl->p.type == NUASM_TYPE_3) {
+    PointSet& d = pl->ps[1];
+    if ((!in && q.M > 0) || (!out && d.M > 0)) return fail(NUASM_ERR_INVALID_ARG, "in/out pointer is NULL");
+    return run_type3_pipeline(pl, q, d, (const float2*)in, (float2*)out, false);
+  }
   // the point-side array may be NULL only when there are no points
   const bool t1 = pl->p.type == NUASM_TYPE_1;
   const void* pts = t1 ? in : out;
   const void* plane = t1 ? out : in;
-  if (!plane || (!pts && pl->M > 0)) return fail(NUASM_ERR_INVALID_ARG, "in/out pointer is NULL");
-  if (t1) return run_type1_pipeline(pl, (const float2*)in, (float2*)out, false, pl->geom.crop != 0);
-  if (pl->M == 0) return NUASM_OK;
-  return run_type2_pipeline(pl, (const float2*)in, pl->geom.N, (float2*)out, false);
+  if (!plane || (!pts && q.M > 0)) return fail(NUASM_ERR_INVALID_ARG, "in/out pointer is NULL");
+  if (t1) return run_type1_pipeline(pl, q, (const float2*)in, (float2*)out, false, pl->geom.crop != 0);
+  if (q.M == 0) return NUASM_OK;
+  return run_type2_pipeline(pl, q, (const float2*)in, pl->geom.N, (float2*)out, false);
 }
 
 nuasm_status nuasm_execute_adjoint(nuasm_plan pl, const void* in, void* out) {
   if (!pl) return fail(NUASM_ERR_INVALID_ARG, "plan is NULL");
-  if (!pl->ready) return fail(NUASM_ERR_NOT_READY, "execute before a successful set_points");
+  if (!pl->ready()) return fail(NUASM_ERR_NOT_READY, not_ready_msg(pl));
+  PointSet& q = pl->ps[0];
+  if (pl->p.type == NUASM_TYPE_3) {
+    PointSet& d = pl->ps[1];
+    if ((!in && d.M > 0) || (!out && q.M > 0)) return fail(NUASM_ERR_INVALID_ARG, "in/out pointer is NULL");
+    return run_type3_pipeline(pl, d, q, (const float2*)in, (float2*)out, true);
+  }
   const bool t1 = pl->p.type == NUASM_TYPE_1;
   const void* pts = t1 ? out : in;
   const void* plane = t1 ? in : out;
-  if (!plane || (!pts && pl->M > 0)) return fail(NUASM_ERR_INVALID_ARG, "in/out pointer is NULL");
+  if (!plane || (!pts && q.M > 0)) return fail(NUASM_ERR_INVALID_ARG, "in/out pointer is NULL");
   if (t1) {
     if (pl->geom.crop) return fail(NUASM_ERR_UNSUPPORTED, "adjoint of a cropped type-1 plan");
-    if (pl->M == 0) return NUASM_OK;
-    return run_type2_pipeline(pl, (const float2*)in, pl->geom.Np, (float2*)out, true);
+    if (q.M == 0) return NUASM_OK;
+    return run_type2_pipeline(pl, q, (const float2*)in, pl->geom.Np, (float2*)out, true);
   }
-  return run_type1_pipeline(pl, (const float2*)in, (float2*)out, true, true);
+  return run_type1_pipeline(pl, q, (const float2*)in, (float2*)out, true, true);
 }
 
 nuasm_status nuasm_plan_set_timing(nuasm_plan pl, int32_t enable) {
@@ -913,6 +1029,11 @@ nuasm_status nuasm_batch_create(int32_t P, const nuasm_params* params, void* hip
   };
   for (int p = 0; p < P; ++p) {
     nuasm_params q = params[p];
+    if (q.type == NUASM_TYPE_3) {
+      batch_release(b);
+      delete b;
+      return fail(NUASM_ERR_UNSUPPORTED, "plane " + std::to_string(p) + ": type-3 plans are not batched");
+    }
     q.flags |= NUASM_DEFER_RANGE_CHECK;
     nuasm_plan pl = nullptr;
     nuasm_status s = nuasm_plan_create(&q, hip_stream, &pl);
@@ -1049,8 +1170,9 @@ nuasm_status nuasm_batch_check_points(nuasm_batch b, int32_t* bad_plane) {
   *bad_plane = -1;
   for (size_t p = 0; p < b->plans.size(); ++p) {
     nuasm_plan_s* pl = b->plans[p];
-    HIP_TRY(hipMemcpy(pl->host_stat, pl->nch, sizeof(int) * 5, hipMemcpyDeviceToHost), "hipMemcpy");
-    if (pl->host_stat[4] != 0) {
+    PointSet& q = pl->ps[0];
+    HIP_TRY(hipMemcpy(q.host_stat, q.nch, sizeof(int) * 5, hipMemcpyDeviceToHost), "hipMemcpy");
+    if (q.host_stat[4] != 0) {
       *bad_plane = (int32_t)p;
       return fail(NUASM_ERR_OUT_OF_RANGE, "plane " + std::to_string(p) + " has points outside its window");
     }

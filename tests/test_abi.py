@@ -67,7 +67,8 @@ def _create(P, p):
     ("N", 100, "NUASM_ERR_UNSUPPORTED"),
     ("N", 8, "NUASM_ERR_UNSUPPORTED"),
     ("N", 8192, "NUASM_ERR_UNSUPPORTED"),
-    ("type", 3, "NUASM_ERR_INVALID_ARG"),
+    ("type", 4, "NUASM_ERR_INVALID_ARG"),
+    ("type", 0, "NUASM_ERR_INVALID_ARG"),
     ("tf", 7, "NUASM_ERR_INVALID_ARG"),
     ("band", 9, "NUASM_ERR_INVALID_ARG"),
     ("lam", 0.0, "NUASM_ERR_INVALID_ARG"),
@@ -87,6 +88,27 @@ def test_invalid_params_rejected_before_device_use(P, field, value, expect):
     assert lib.nuasm_last_error().decode()
 
 
+def test_type3_rejects_the_crop_flag(P):
+    p = _params(P, type=3, flags=0x1)
+    st, h = _create(P, p)
+    assert P.load().nuasm_status_string(st).decode() == "NUASM_ERR_INVALID_ARG"
+    assert h.value is None
+
+
+def test_plan_info_struct_layout_matches_header(P):
+    # 4 x int64, 8 x int32/float, 3 x int64, size_t, int64
+    assert ctypes.sizeof(P.PlanInfo) == 4 * 8 + 8 * 4 + 3 * 8 + 8 + 8
+    assert [f for f, _ in P.PlanInfo._fields_][-1] == "M_dest"
+
+
+def test_stage_names_match_header_count(P):
+    src = open(HEADER).read()
+    n = int(re.search(r"#define NUASM_NUM_STAGES (\d+)", src).group(1))
+    assert len(P.STAGES) == n
+    for name, idx in re.findall(r"#define NUASM_STAGE_([A-Z0-9_]+) (\d+)", src):
+        assert P.STAGES[int(idx)] == name.lower()
+
+
 def test_fresnel_needs_nonzero_z(P):
     p = _params(P, tf=1, z=0.0)
     st, h = _create(P, p)
@@ -103,6 +125,7 @@ def test_null_arguments(P):
     assert lib.nuasm_plan_destroy(None) == 0
     assert lib.nuasm_execute(None, None, None) != 0
     assert lib.nuasm_set_points(None, 0, None, None) != 0
+    assert lib.nuasm_set_dest_points(None, 0, None, None) != 0
     assert lib.nuasm_plan_set_timing(None, 1) != 0
 
 
