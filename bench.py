@@ -45,6 +45,13 @@ def stage_bytes(stage: str, info: dict) -> float:
     number of binning ranges, Nb the number of in-band x-frequencies (the Rect
     of Eq. 4 lets the grid passes skip the others)."""
     n, np_, L, m, T = info["N"], info["Np"], info["L"], info["M"], info["tiles"]
+    m_dest = info.get("M_dest", 0)
+    if m_dest:
+        # type 3: interpolation at the destination points; the binning
+        # stages run once per point set (the average of the two is charged)
+        m_interp, m = m_dest, 0.5 * (m + m_dest)
+    else:
+        m_interp = m
     nb = max(0, min(info["kx_hi"], np_ // 2 - 1) - max(info["kx_lo"], -np_ // 2) + 1)
     G = max(1, -(-m // max(4096, min(65535, -(-m // 256)))))
     c = 8.0  # complex64
@@ -61,7 +68,8 @@ def stage_bytes(stage: str, info: dict) -> float:
         "t2_rows": c * n * n + c * n * nb,
         "t2_cols": c * n * nb + c * L * nb,
         "t2_rows_inv": c * L * nb + c * L * L,
-        "interp": c * L * L + 16.0 * m + c * m,        # grid + records in, values out
+        "t3_cols": c * L * nb + c * L * nb,
+        "interp": c * L * L + 16.0 * m_interp + c * m_interp,  # grid + records in, values out
     }[stage]
 
 
@@ -178,6 +186,100 @@ def batched_workload(a, torch, P, synth):
     return 0
 
 
+def stage_pass(runs, seq_step, steps, torch):
+    """Run `steps` sequential steps with the library's per-launch HIP events
+    on and total time, launches and algorithmic bytes per stage."""
+    for r in runs:
+        r["plan"].set_timing(True)
+    for _ in range(steps):
+        seq_step()
+    torch.cuda.synchronize()
+    stages = {}
+    per_type_ms = {1: 0.0, 2: 0.0, 3: 0.0}
+    for r in runs:
+        info = r["plan"].info
+        for st, (ms, n) in r["plan"].read_timing().items():
+            if n == 0:
+                continue
+            s = stages.setdefault(st, {"ms": 0.0, "launches": 0, "bytes": 0.0})
+            s["ms"] += ms
+            s["launches"] += n
+            s["bytes"] += stage_bytes(st, info) * n
+            per_type_ms[r["type"]] += ms
+        r["plan"].set_timing(False)
+    return stages, per_type_ms
+
+
+def roofline(stages, steps):
+    """Roofline object of the dominant kernel and the per-stage report."""
+    dom = max(stages, key=lambda k: stages[k]["ms"])
+    ds = stages[dom]
+    avg_ms = ds["ms"] / ds["launches"]
+    achieved = ds["bytes"] / (ds["ms"] * 1e-3) / 1e9
+    total = sum(s["ms"] for s in stages.values())
+    report = {k: {"avg_us": 1e3 * v["ms"] / v["launches"], "launches_per_step": v["launches"] // steps,
+                  "share": v["ms"] / total, "GBps": v["bytes"] / max(v["ms"] * 1e-3, 1e-12) / 1e9}
+              for k, v in sorted(stages.items(), key=lambda kv: -kv[1]["ms"])}
+    roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": COUNTER_TRAFFIC.get(dom),
+            "avg_launch_us": avg_ms * 1e3}
+    return roof, report
+
+
+def nuasm3_workload(a, torch, P, d):
+    """NU-ASM_3 / NU-FRE_3 at the headline geometry: 2^20 clustered source
+    points and 2^20 clustered destination points (the two point sets of the
+    headline workload), z in {0.01, 0.1, 0.5} m x {band-limited ASM,
+    Fresnel}: 6 runs per step, each one-shot (both point sets binned, then
+    the operator), plain plans one after another on one stream.
+    value = 6 (M_source + M_destination) / step time."""
+    runs = []
+    for z in ZS:
+        for tf, band in TFS:
+            spec = dict(N=N, type=3, lam=LAM, z=z, g=G, tf=tf, band=band, ox=OX, oy=OY, tol=TOL)
+            plan = P.Plan(defer_range_check=True, **spec)
+            out = torch.empty((M,), dtype=torch.complex64, device="cuda")
+            runs.append(dict(plan=plan, out=out, type=3, z=z, tf=tf))
+
+    def step():
+        for r in runs:
+            r["plan"].set_points(d["x1"], d["y1"])
+            r["plan"].set_dest_points(d["x2"], d["y2"])
+            r["plan"].execute(d["c1"], r["out"])
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    for r in runs:
+        r["plan"].check_points()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(a.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_per_step = e0.elapsed_time(e1) / a.steps
+    line = {
+        "metric": "non-uniform pts/sec NU-ASM_3 (source + destination points) at N'=2048, M=1M per side",
+        "value": len(runs) * 2 * M / (ms_per_step * 1e-3), "unit": "points/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "NU-ASM_3 one-shot (bin both point sets + execute), N=1024 (N'=2048), "
+                               "2^20 clustered source and 2^20 clustered destination points, pitch 4 um, "
+                               "633 nm, o=(1 mm, 0), z in {0.01, 0.1, 0.5} m x {band-limited ASM, Fresnel}, "
+                               "tol 1e-6 (w=7), 6 runs per step",
+                   "N": N, "Np": 2 * N, "M_source": M, "M_dest": M, "runs_per_step": len(runs)},
+    }
+    if a.profile_steps > 0:
+        stages, per_type_ms = stage_pass(runs, step, a.profile_steps, torch)
+        roof, report = roofline(stages, a.profile_steps)
+        line.update({"roofline": roof, "stages": report,
+                     "avg_run_ms": per_type_ms[3] / (a.profile_steps * len(runs))})
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,8 +290,9 @@ def main(argv=None):
     ap.add_argument("--mode", choices=("graph", "sequential"), default="graph",
                     help="graph: the 12 runs of a step recorded as one HIP graph on parallel branches; "
                          "sequential: plain plans one after another on one stream")
-    ap.add_argument("--workload", choices=("n2048", "batched"), default="n2048",
-                    help="n2048: the 12-run N'=2048 headline workload; batched: 64 mixed planes")
+    ap.add_argument("--workload", choices=("n2048", "batched", "nuasm3"), default="n2048",
+                    help="n2048: the 12-run N'=2048 headline workload; batched: 64 mixed planes; "
+                         "nuasm3: NU-ASM_3 with 2^20 source and 2^20 destination points, 6 runs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (3 times), the "
                          "reference for the FETCH_SIZE / WRITE_SIZE counters, and exit")
@@ -222,6 +325,8 @@ def main(argv=None):
         return batched_workload(a, torch, P, synth)
     print(f"[bench] generating inputs N={N} M={M}", file=sys.stderr, flush=True)
     host, d = make_inputs(torch, synth)
+    if a.workload == "nuasm3":
+        return nuasm3_workload(a, torch, P, d)
 
     runs = []
     for z in ZS:
@@ -308,32 +413,8 @@ def main(argv=None):
 
     # second pass: per-stage HIP events recorded by the library
     print(f"[bench] per-stage timing {a.profile_steps} steps", file=sys.stderr, flush=True)
-    for r in runs:
-        r["plan"].set_timing(True)
-    for _ in range(a.profile_steps):
-        seq_step()
-    torch.cuda.synchronize()
-    stages = {}
-    per_type_ms = {1: 0.0, 2: 0.0}
-    for r in runs:
-        info = r["plan"].info
-        for st, (ms, n) in r["plan"].read_timing().items():
-            if n == 0:
-                continue
-            s = stages.setdefault(st, {"ms": 0.0, "launches": 0, "bytes": 0.0})
-            s["ms"] += ms
-            s["launches"] += n
-            s["bytes"] += stage_bytes(st, info) * n
-            per_type_ms[r["type"]] += ms
-        r["plan"].set_timing(False)
-    dom = max(stages, key=lambda k: stages[k]["ms"])
-    ds = stages[dom]
-    avg_ms = ds["ms"] / ds["launches"]
-    achieved = ds["bytes"] / (ds["ms"] * 1e-3) / 1e9
-    stage_report = {k: {"avg_us": 1e3 * v["ms"] / v["launches"], "launches_per_step": v["launches"] // a.profile_steps,
-                        "share": v["ms"] / sum(s["ms"] for s in stages.values()),
-                        "GBps": v["bytes"] / max(v["ms"] * 1e-3, 1e-12) / 1e9}
-                    for k, v in sorted(stages.items(), key=lambda kv: -kv[1]["ms"])}
+    stages, per_type_ms = stage_pass(runs, seq_step, a.profile_steps, torch)
+    roof, stage_report = roofline(stages, a.profile_steps)
     # whole-path byte model per type (pass-minimal): 64 M + 56 N'^2 and 56 M + 44 N'^2
     Np = 2 * N
     nruns = len(runs) // 2
@@ -343,20 +424,7 @@ def main(argv=None):
         path[f"nuasm{t}"] = {"avg_ms": t_ms, "model_bytes": bpp,
                              "frac": bpp / (t_ms * 1e-3) / (HBM_PEAK_GBS * 1e9)}
 
-    line.update({
-        "roofline": {
-            "bound": "hbm",
-            "kernel": dom,
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": COUNTER_TRAFFIC.get(dom),
-            "avg_launch_us": avg_ms * 1e3,
-        },
-        "stages": stage_report,
-        "path_model": path,
-    })
+    line.update({"roofline": roof, "stages": stage_report, "path_model": path})
     if not a.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(host)

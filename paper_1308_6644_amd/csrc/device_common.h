@@ -113,13 +113,12 @@ __device__ __forceinline__ float2 tw2_get(const float2* __restrict__ t, int m) {
 // product of the radices of the earlier passes.  tw is the LDS two-level
 // twiddle table of length N (see Tw2).
 template <int LOGN, int C, int NT, int DIR, int R, int P>
-__device__ __forceinline__ void stockham_pass(float2* __restrict__ s, const float2* __restrict__ tw) {
+__device__ __forceinline__ void stockham_pass(float2* __restrict__ s, const float2* __restrict__ tw, int tid) {
   constexpr int N = 1 << LOGN;
   constexpr int NR = N / R;
   constexpr int NB = C * NR;
   constexpr int PER = (NB + NT - 1) / NT;
   constexpr int TWS = N / (P * R);
-  const int tid = threadIdx.x;
   float2 x[PER][R];
   float2 w[PER][R];
 #pragma unroll
@@ -168,16 +167,16 @@ __device__ __forceinline__ void stockham_pass(float2* __restrict__ s, const floa
 
 template <int LOGN, int C, int NT, int DIR, int P, int REM>
 struct FftPasses {
-  static __device__ __forceinline__ void run(float2* s, const float2* tw) {
+  static __device__ __forceinline__ void run(float2* s, const float2* tw, int tid) {
     constexpr int LR = REM >= 3 ? 3 : REM;
     constexpr int R = 1 << LR;
-    stockham_pass<LOGN, C, NT, DIR, R, P>(s, tw);
-    FftPasses<LOGN, C, NT, DIR, P * R, REM - LR>::run(s, tw);
+    stockham_pass<LOGN, C, NT, DIR, R, P>(s, tw, tid);
+    FftPasses<LOGN, C, NT, DIR, P * R, REM - LR>::run(s, tw, tid);
   }
 };
 template <int LOGN, int C, int NT, int DIR, int P>
 struct FftPasses<LOGN, C, NT, DIR, P, 0> {
-  static __device__ __forceinline__ void run(float2*, const float2*) {}
+  static __device__ __forceinline__ void run(float2*, const float2*, int) {}
 };
 
 // Unnormalised in-LDS FFT of C interleaved transforms of length 2^LOGN,
@@ -186,7 +185,22 @@ struct FftPasses<LOGN, C, NT, DIR, P, 0> {
 // table are in LDS and a barrier; ends with a barrier.
 template <int LOGN, int C, int NT, int DIR>
 __device__ __forceinline__ void fft_lds(float2* s, const float2* tw) {
-  FftPasses<LOGN, C, NT, DIR, 1, LOGN>::run(s, tw);
+  FftPasses<LOGN, C, NT, DIR, 1, LOGN>::run(s, tw, (int)threadIdx.x);
+}
+
+// The same transform with the thread index passed in.  A kernel that runs
+// two transforms of one length passes an opaque copy (opaque_tid) to the
+// second, so that the compiler recomputes its LDS addresses instead of
+// keeping the first transform's live across the code in between.
+template <int LOGN, int C, int NT, int DIR>
+__device__ __forceinline__ void fft_lds(float2* s, const float2* tw, int tid) {
+  FftPasses<LOGN, C, NT, DIR, 1, LOGN>::run(s, tw, tid);
+}
+
+__device__ __forceinline__ int opaque_tid() {
+  int t = (int)threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
 }
 
 // ------------------------------------------------- spreading kernel (ES)

@@ -384,10 +384,14 @@ struct T3Cfg {
   using Col = ColCfg<LOGNF>;
   static constexpr int C = Col::C, NT = Col::NT, DATA = Col::DATA;
   static constexpr int LDS = (DATA + Tw2<LOGNF>::SIZE) * 8;
+  // waves per SIMD when two workgroups share a CU (LDS permitting): the
+  // register budget is held to what that occupancy allows
+  static constexpr int WAVES = LDS <= 80 * 1024 ? 2 * NT / 256 : NT / 256;
 };
 
 template <int LOGNP>
 __global__ void __launch_bounds__(T3Cfg<LOGNP + 1>::NT)
+__attribute__((amdgpu_waves_per_eu(T3Cfg<LOGNP + 1>::WAVES)))
 k_t3_cols(const float2* __restrict__ T, float2* __restrict__ V, GridGeom g, Spectral sp,
           const float2* __restrict__ twall) {
   constexpr int LOGN = LOGNP + 1, NF = 1 << LOGN, NP = 1 << LOGNP;
@@ -424,7 +428,7 @@ k_t3_cols(const float2* __restrict__ T, float2* __restrict__ V, GridGeom g, Spec
     s[pidx(e)] = x;
   }
   __syncthreads();
-  fft_lds<LOGN, C, NT, +1>(s, twf);
+  fft_lds<LOGN, C, NT, +1>(s, twf, opaque_tid());
   for (int e = threadIdx.x; e < C * L; e += NT) {
     const int i = e / C, c = e % C;
     if (in_band(kx0 + c, g.kxlo, g.kxhi)) V[(size_t)i * NP + a0 + c] = s[pidx((s0 + i) * C + c)];
