@@ -61,7 +61,7 @@ __all__ = [
     "transfer_asm", "transfer_fresnel", "transfer", "nuasm1", "nuasm2",
     "nuasm1_adjoint", "nuasm2_adjoint", "type1_spectrum", "spectrum_at",
     "cgh_loss", "cgh_grad", "rayleigh_sommerfeld", "rel_l2", "snr_db", "uniform_spectrum",
-    "nuasm2_from_spectrum", "nuasm3", "nuasm3_adjoint",
+    "nuasm2_from_spectrum", "nuasm3", "nuasm3_adjoint", "rayleigh_sommerfeld_points",
 ]
 
 
@@ -396,6 +396,32 @@ def rayleigh_sommerfeld(u1: np.ndarray, g: float, lam: float, z: float, x2, y2,
         r = np.sqrt((X1 - x2[j]) ** 2 + (Y1 - y2[j]) ** 2 + z * z)
         ph = cis_cycles(r / lam)
         out[j] = np.sum(a * (z / r) * (1.0 - 1j * k * r) * ph / (r * r)) * g * g / (2.0 * np.pi)
+    return out
+
+
+def rayleigh_sommerfeld_points(x1, y1, c, x2, y2, lam: float, z: float,
+                               ox: float = 0.0, oy: float = 0.0) -> np.ndarray:
+    """Rayleigh-Sommerfeld diffraction by direct summation over source samples
+    at arbitrary points (Eq. 10 with the integral replaced by a sum):
+    u2_j = 1/(2 pi) sum_i c_i (z/r)(1 - i k r) exp(i k r)/r^2,
+    r = sqrt(|q_j + o - p_i|^2 + z^2), k = 2 pi / lambda.  The weights c_i
+    carry each sample's area element (g^2 for a uniform grid of pitch g), so a
+    uniform grid reproduces rayleigh_sommerfeld.  The phase k r is formed in
+    cycles as z/lambda + (r - |z|)/lambda with r - |z| = rho^2/(r + |z|),
+    which keeps the large z/lambda out of the rounding of the small part."""
+    x1 = np.asarray(x1, dtype=np.float64)
+    y1 = np.asarray(y1, dtype=np.float64)
+    c = np.asarray(c).astype(np.complex128)
+    x2 = np.asarray(x2, dtype=np.float64) + ox
+    y2 = np.asarray(y2, dtype=np.float64) + oy
+    k = 2.0 * np.pi / lam
+    az = abs(z)
+    out = np.empty(x2.size, dtype=np.complex128)
+    for j in range(x2.size):
+        rho2 = (x2[j] - x1) ** 2 + (y2[j] - y1) ** 2
+        r = np.sqrt(rho2 + z * z)
+        ph = cis_cycles(az / lam + rho2 / (r + az) / lam)
+        out[j] = np.sum(c * (z / r) * (1.0 - 1j * k * r) * ph / (r * r)) / (2.0 * np.pi)
     return out
 
 
