@@ -280,6 +280,143 @@ def nuasm3_workload(a, torch, P, d):
     return 0
 
 
+# Rayleigh-Sommerfeld direct summation: floating-point operations per source
+# / destination pair as the kernel evaluates Eq. 10 (an FMA counts two):
+# float64 23 (differences, rho^2, 1 + rho^2/z^2, one Newton step for
+# 1/sqrt, 1 + r/|z|, one Newton step for the reciprocal, the phase and its
+# reduction), float32 16 (amplitude, complex products, accumulation), and
+# the four hardware estimates (rsq, rcp, sin, cos) one each.
+RS_FLOPS_PER_PAIR = 23 + 16 + 4
+# Vector ALU ceiling for that mix: float64 FMA and non-packed float32 FMA
+# issue at the same rate, 256 CUs x 64 lanes x 2 flops x 2.4 GHz.
+ALU_PEAK_TFLOPS = 78.6
+PAPER_RS_S, PAPER_NUASM1_MS = 76.0, 46.0  # the paper's CPU times at N = 256 (context only)
+# wave64 VALU instructions per pair of the current k_rs_direct (rocprofv3
+# SQ_INSTS_VALU / (pairs / 64), profiles/rs_direct_paper_N256.md), and the
+# issue ceiling: 256 CUs x 4 SIMDs, one wave64 VALU instruction per SIMD every
+# 4 cycles at 2.4 GHz
+RS_VALU_PER_PAIR = 38.3
+VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4
+
+
+def paper_workload(a, torch, P, synth):
+    """The paper's experiment set-up (Figs. 2-5) with synthetic fields:
+    256 x 256 samples, 500 nm, 5 um uniform pitch, the non-uniform plane
+    sampled quadrant-wise at 0.9/0.8/0.7/1.0 x 5 um.  NU-ASM_1 (band-limited
+    ASM) and NU-FRE_1 from the quadrant-sampled source to the uniform 256 x 256
+    destination, against Rayleigh-Sommerfeld direct summation (Eq. 10, every
+    source sample weighted by (5 um)^2) over a range of z; NU-ASM_2 from the
+    uniform source to the quadrant-sampled destination at z = 8 mm.  The line's
+    value is the RS kernel's pair throughput."""
+    import numpy as np
+    Np_, d, lam = 256, 5e-6, 500e-9
+    zs = (0.008, 0.016, 0.032, 0.064, 0.128, 0.256)
+    xq, yq = synth.quadrant_grid(Np_, d)
+    rng = synth.rng_for(6)
+    fq = synth.experiment_field(rng, xq, yq, Np_ * d)
+    n = (np.arange(Np_) - Np_ // 2) * d
+    X, Y = np.meshgrid(n, n, indexing="xy")
+    xu, yu = X.ravel(), Y.ravel()
+    fu = synth.experiment_field(synth.rng_for(6, 1), xu, yu, Np_ * d)
+    t = lambda v, dt=None: torch.from_numpy(np.ascontiguousarray(v if dt is None else v.astype(dt))).cuda()
+    dxq, dyq, dxu, dyu = t(xq), t(yq), t(xu), t(yu)
+    cq = t(fq, np.complex64)
+    cq_w = t(fq * d * d, np.complex64)
+    u1 = t(fu.reshape(Np_, Np_), np.complex64)
+    cu_w = t(fu * d * d, np.complex64)
+    M = xq.size
+
+    def snr(test, ref):
+        ref = ref.to(torch.complex128)
+        err = test.to(torch.complex128) - ref
+        return float(10.0 * torch.log10(torch.sum(ref.abs() ** 2) / torch.sum(err.abs() ** 2)))
+
+    def timed(fn, reps):
+        for _ in range(max(1, a.warmup)):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    table = {}
+    times = {}
+    for z in zs:
+        ref = P.rs_direct(dxq, dyq, cq_w, dxu, dyu, lam, z)
+        row = {}
+        for tf, band in (("asm", "limited"), ("fresnel", "full")):
+            plan = P.Plan(Np_, 1, lam, z, d, tf=tf, band=band, tol=1e-6, crop=True)
+            plan.set_points(dxq, dyq)
+            out = plan.execute(cq).reshape(-1)
+            row["nuasm1" if tf == "asm" else "nufre1"] = snr(out, ref)
+            if z == zs[0]:
+                def one_shot(plan=plan):
+                    plan.set_points(dxq, dyq)
+                    plan.execute(cq, out.view(Np_, Np_))
+                times[f"{'nuasm1' if tf == 'asm' else 'nufre1'}_ms"] = timed(one_shot, a.steps)
+        table[f"{z * 1e3:g}mm"] = row
+        print(f"[bench] z = {z * 1e3:g} mm: " + ", ".join(f"{k} {v:.2f} dB" for k, v in row.items()),
+              file=sys.stderr, flush=True)
+    z = zs[0]
+    rs_ms = timed(lambda: P.rs_direct(dxq, dyq, cq_w, dxu, dyu, lam, z), max(3, a.steps // 4))
+    # NU-ASM_2 (uniform source -> quadrant-sampled destination) against two
+    # Rayleigh-Sommerfeld references: the sum over the 256 x 256 source samples
+    # as point sources, and the sum over the band-limited interpolant of the
+    # zero-padded samples (the field the FFT methods assume) on a 4x finer grid
+    U = 4
+    pad = np.zeros((2 * Np_, 2 * Np_), dtype=np.complex128)
+    pad[Np_ // 2:3 * Np_ // 2, Np_ // 2:3 * Np_ // 2] = fu.reshape(Np_, Np_)
+    S = np.fft.fftshift(np.fft.fft2(np.fft.ifftshift(pad)))
+    Sf = np.zeros((2 * U * Np_, 2 * U * Np_), dtype=np.complex128)
+    o = (U - 1) * Np_
+    Sf[o:o + 2 * Np_, o:o + 2 * Np_] = S
+    fine = np.fft.fftshift(np.fft.ifft2(np.fft.ifftshift(Sf))) * U * U
+    nf_ = (np.arange(2 * U * Np_) - U * Np_) * (d / U)
+    XF, YF = np.meshgrid(nf_, nf_, indexing="xy")
+    dxf, dyf = t(XF.ravel()), t(YF.ravel())
+    cf_w = t(fine.ravel() * (d / U) ** 2, np.complex64)
+    del pad, S, Sf, fine, XF, YF
+    nuasm2_rows = {}
+    for z2 in zs[:3]:
+        plan2 = P.Plan(Np_, 2, lam, z2, d, tf="asm", band="limited", tol=1e-6)
+        plan2.set_points(dxq, dyq)
+        u2 = plan2.execute(u1)
+        nuasm2_rows[f"{z2 * 1e3:g}mm"] = {
+            "point_rs": snr(u2, P.rs_direct(dxu, dyu, cu_w, dxq, dyq, lam, z2)),
+            "fine_rs": snr(u2, P.rs_direct(dxf, dyf, cf_w, dxq, dyq, lam, z2))}
+        print(f"[bench] NU-ASM_2 z = {z2 * 1e3:g} mm: " + ", ".join(
+            f"{k} {v:.2f} dB" for k, v in nuasm2_rows[f"{z2 * 1e3:g}mm"].items()), file=sys.stderr, flush=True)
+    pairs = float(M) * float(xu.size)
+    rate = pairs / (rs_ms * 1e-3)
+    achieved = rate * RS_FLOPS_PER_PAIR / 1e12
+    line = {
+        "metric": "Rayleigh-Sommerfeld direct summation pairs/sec, paper experiment 256x256 -> 256x256",
+        "value": rate, "unit": "pairs/s", "n_gpus": 1, "steps": max(3, a.steps // 4), "warmup": a.warmup,
+        "ms_per_step": rs_ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 phase / f32", "data": "synthetic",
+        "config": {"workload": "256 x 256 quadrant-sampled source (0.9/0.8/0.7/1.0 x 5 um) -> 256 x 256 "
+                               "uniform destination (5 um), 500 nm, z = 8 mm; synthetic blob fields "
+                               "standing in for the paper's photographs",
+                   "pairs": pairs},
+        "roofline": {"bound": "alu", "kernel": "rs_direct", "achieved": achieved, "peak": ALU_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / ALU_PEAK_TFLOPS, "traffic": None,
+                     "flops_per_pair": RS_FLOPS_PER_PAIR, "avg_launch_us": rs_ms * 1e3,
+                     "valu_issue_frac": rate * RS_VALU_PER_PAIR / 64.0 / VALU_ISSUE_PER_S},
+        "experiment": {"snr_db_vs_rs": table, "nuasm2_snr_db_vs_rs": nuasm2_rows,
+                       "nuasm2_fine_rs_source": f"band-limited interpolant of the zero-padded 256 x 256 samples "
+                                                f"on a {2 * U * Np_} x {2 * U * Np_} grid of pitch d/{U}",
+                       "nuasm1_one_shot_ms": times.get("nuasm1_ms"), "nufre1_one_shot_ms": times.get("nufre1_ms"),
+                       "rs_ms": rs_ms,
+                       "paper_cpu_context": {"nuasm1_ms": PAPER_NUASM1_MS, "rs_s": PAPER_RS_S}},
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -290,9 +427,10 @@ def main(argv=None):
     ap.add_argument("--mode", choices=("graph", "sequential"), default="graph",
                     help="graph: the 12 runs of a step recorded as one HIP graph on parallel branches; "
                          "sequential: plain plans one after another on one stream")
-    ap.add_argument("--workload", choices=("n2048", "batched", "nuasm3"), default="n2048",
+    ap.add_argument("--workload", choices=("n2048", "batched", "nuasm3", "paper"), default="n2048",
                     help="n2048: the 12-run N'=2048 headline workload; batched: 64 mixed planes; "
-                         "nuasm3: NU-ASM_3 with 2^20 source and 2^20 destination points, 6 runs")
+                         "nuasm3: NU-ASM_3 with 2^20 source and 2^20 destination points, 6 runs; "
+                         "paper: the paper's 256 x 256 experiment against Rayleigh-Sommerfeld")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (3 times), the "
                          "reference for the FETCH_SIZE / WRITE_SIZE counters, and exit")
@@ -323,6 +461,8 @@ def main(argv=None):
     P.load()
     if a.workload == "batched":
         return batched_workload(a, torch, P, synth)
+    if a.workload == "paper":
+        return paper_workload(a, torch, P, synth)
     print(f"[bench] generating inputs N={N} M={M}", file=sys.stderr, flush=True)
     host, d = make_inputs(torch, synth)
     if a.workload == "nuasm3":

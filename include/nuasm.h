@@ -183,6 +183,23 @@ nuasm_status nuasm_debug_transfer(nuasm_plan plan, void* out_dev);
 nuasm_status nuasm_debug_fft(int64_t n, int64_t batch, int32_t sign, const void* in_dev,
                              void* out_dev, void* hip_stream);
 
+/* Rayleigh-Sommerfeld diffraction by direct summation (Eq. 10, the paper's
+ * accuracy reference), O(M1 M2):
+ *   u2_j = 1/(2 pi) sum_i c_i (z/r)(1 - i k r) exp(i k r) / r^2,
+ *   r = sqrt(|q_j + o - p_i|^2 + z^2),  k = 2 pi / lambda,
+ * for M1 source points p_i = (x1, y1) with complex weights c_i that carry
+ * each sample's area element (u1 g^2 for a uniform grid of pitch g) and M2
+ * destination points q_j = (x2, y2).  Coordinates are device FP64 metres,
+ * c and out device complex64 (caller-owned; out[M2] in destination order).
+ * The phase is formed in FP64 (error ~1e-11 cycles), amplitudes and the
+ * sums in FP32 with FP64 accumulation every 64 sources.  z != 0 (its sign
+ * enters as the z/r factor of Eq. 10; r depends on z^2).  Plan-less:
+ * enqueued on hip_stream (NULL = default stream), allocates nothing,
+ * never synchronises.  M1 = 0 writes zeros; M2 = 0 does nothing. */
+nuasm_status nuasm_rs_direct(int64_t M1, const double* x1_dev, const double* y1_dev, const void* c_dev,
+                             int64_t M2, const double* x2_dev, const double* y2_dev, double lambda, double z,
+                             double ox, double oy, void* out_dev, void* hip_stream);
+
 /* Per-kernel device timing with HIP events recorded on the plan's stream
  * around each kernel launch (off by default).  Stages, one kernel each: */
 #define NUASM_STAGE_BIN_HIST 0     /* set_points: per-range bin histograms */

@@ -15,6 +15,7 @@ import torch  # loads the HIP runtime the library binds to
 
 __all__ = [
     "Plan", "Batch", "make_params", "NUASM1", "NUASM2", "NUASM3", "nuasm1", "nuasm2", "nuasm3", "debug_fft",
+    "rs_direct",
     "lib_path", "load", "NuasmError", "TYPE_1", "TYPE_2", "TYPE_3", "TF_ASM", "TF_FRESNEL",
 ]
 
@@ -92,6 +93,10 @@ _SIGS = {
                                        ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p)]),
     "nuasm_batch_check_points": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     "nuasm_batch_plane_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float)]),
+    "nuasm_rs_direct": (ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
+                                       ctypes.c_void_p]),
 }
 
 _lib = None
@@ -354,6 +359,27 @@ def debug_fft(x: torch.Tensor, sign: int = -1) -> torch.Tensor:
     _dev_ptr(xin, torch.complex64, "x")
     _check(load().nuasm_debug_fft(n, xin.numel() // n, int(sign), ctypes.c_void_p(xin.data_ptr()),
                                   ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(_stream_ptr())))
+    return out
+
+
+def rs_direct(x1: torch.Tensor, y1: torch.Tensor, c: torch.Tensor, x2: torch.Tensor, y2: torch.Tensor,
+              lam: float, z: float, ox: float = 0.0, oy: float = 0.0,
+              out: torch.Tensor | None = None) -> torch.Tensor:
+    """Rayleigh-Sommerfeld direct summation (Eq. 10) from weighted source
+    points (x1, y1, c: c carries each sample's area element) to destination
+    points (x2, y2) offset by (ox, oy); complex64 [M2]."""
+    M1, M2 = x1.numel(), x2.numel()
+    if x1.shape != y1.shape or c.shape != x1.shape or x2.shape != y2.shape or x1.dim() != 1 or x2.dim() != 1:
+        raise ValueError("x1, y1, c and x2, y2 must be 1-D with matching lengths")
+    if out is None:
+        out = torch.empty((M2,), dtype=torch.complex64, device=x2.device if M2 else c.device)
+    elif tuple(out.shape) != (M2,):
+        raise ValueError(f"output shape {tuple(out.shape)} != {(M2,)}")
+    p = [(_dev_ptr(t, dt, w) if t.numel() else None) for t, dt, w in
+         ((x1, torch.float64, "x1"), (y1, torch.float64, "y1"), (c, torch.complex64, "c"),
+          (x2, torch.float64, "x2"), (y2, torch.float64, "y2"), (out, torch.complex64, "out"))]
+    _check(load().nuasm_rs_direct(M1, p[0], p[1], p[2], M2, p[3], p[4], float(lam), float(z), float(ox),
+                                  float(oy), p[5], ctypes.c_void_p(_stream_ptr())))
     return out
 
 

@@ -18,6 +18,13 @@ __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2
 __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
 __device__ __forceinline__ float2 czero() { return make_float2(0.f, 0.f); }
 
+// exp(2 pi i x) for x in [-1/2, 1/2] cycles from the hardware sine and cosine,
+// which take their argument in revolutions (v_sin_f32 / v_cos_f32; measured
+// error below 1.3e-7 over that range, against 5.5e-8 for sincospif).
+__device__ __forceinline__ float2 cis_rev(float x) {
+  return make_float2(__builtin_amdgcn_cosf(x), __builtin_amdgcn_sinf(x));
+}
+
 // cos / sin of 2 pi m / 16 for m = 0..8 (exact decimal expansions)
 __device__ __forceinline__ float cos16(int m) {
   switch (m) {

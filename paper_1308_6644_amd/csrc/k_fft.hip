@@ -53,13 +53,6 @@ __device__ __forceinline__ double sqrt_nr(double r) {
   return s + 0.5 * y * (r - s * s);
 }
 
-// exp(2 pi i x) for x in [-1/2, 1/2] cycles from the hardware sine and cosine,
-// which take their argument in revolutions (v_sin_f32 / v_cos_f32; measured
-// error below 1.3e-7 over that range, against 5.5e-8 for sincospif).
-__device__ __forceinline__ float2 cis_rev(float x) {
-  return make_float2(__builtin_amdgcn_cosf(x), __builtin_amdgcn_sinf(x));
-}
-
 // Transfer function of Eq. 4 (ASM) or Eq. 5 (Fresnel) at integer frequency
 // (kx, ky), without the Rect.  The ASM phase is formed in cycles:
 // z sqrt(1/l^2 - df^2 k^2) = z/l - (z/l)(1 - sqrt(1 - t)), t = (l df)^2 k^2.

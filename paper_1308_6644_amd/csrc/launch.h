@@ -128,6 +128,19 @@ hipError_t launch_t2_rows_inv(int logNp, const float2* V, float2* fine, GridGeom
 hipError_t launch_t3_cols(int logNp, const float2* T, float2* V, GridGeom g, Spectral sp,
                           const float2* tw, hipStream_t st);
 
+// Rayleigh-Sommerfeld direct summation (Eq. 10): constants of one propagation
+struct RsConst {
+  double ox, oy;     // offset o added to the destination points, metres
+  double inv_z2;     // 1 / z^2
+  double inv_lz;     // 1 / (l |z|)
+  double c0;         // |z| / l reduced to [-1/2, 1/2]
+  double inv_2pi;    // 1 / (2 pi)
+  float a3;          // z / |z|^3
+  float ak;          // k z / z^2, k = 2 pi / l
+};
+hipError_t launch_rs_direct(const double* x1, const double* y1, const float2* c, int64_t M1, const double* x2,
+                            const double* y2, int64_t M2, const RsConst& k, float2* out, hipStream_t st);
+
 hipError_t launch_stamp(long long* out, hipStream_t st);
 hipError_t launch_transfer_table(const GridGeom& g, const Spectral& sp, float2* out, hipStream_t st);
 hipError_t launch_fresnel_axis(int Np, double g, double two_lam_z, double o, double2 amp,

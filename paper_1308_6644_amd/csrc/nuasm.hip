@@ -935,6 +935,39 @@ nuasm_status nuasm_debug_fft(int64_t n, int64_t batch, int32_t sign, const void*
 }
 
 
+nuasm_status nuasm_rs_direct(int64_t M1, const double* x1, const double* y1, const void* c, int64_t M2,
+                             const double* x2, const double* y2, double lambda, double z, double ox, double oy,
+                             void* out, void* stream) {
+  if (M1 < 0 || M2 < 0) return fail(NUASM_ERR_INVALID_ARG, "point counts must be >= 0");
+  if (M1 > 0 && (!x1 || !y1 || !c)) return fail(NUASM_ERR_INVALID_ARG, "source pointer is NULL");
+  if (M2 > 0 && (!x2 || !y2 || !out)) return fail(NUASM_ERR_INVALID_ARG, "destination pointer is NULL");
+  if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(NUASM_ERR_INVALID_ARG, "lambda must be > 0");
+  if (!std::isfinite(z) || z == 0.0) return fail(NUASM_ERR_INVALID_ARG, "z must be finite and != 0");
+  if (!std::isfinite(ox) || !std::isfinite(oy)) return fail(NUASM_ERR_INVALID_ARG, "offset must be finite");
+  if ((M2 + 63) / 64 > (int64_t)INT32_MAX) return fail(NUASM_ERR_UNSUPPORTED, "too many destination points");
+  if (M2 == 0) return NUASM_OK;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    return fail(NUASM_ERR_NO_DEVICE, "no HIP device visible");
+  }
+  const double az = std::fabs(z);
+  const double zl = az / lambda;
+  const double k = 2.0 * kPi / lambda;
+  RsConst kc{};
+  kc.ox = ox;
+  kc.oy = oy;
+  kc.inv_z2 = 1.0 / (z * z);
+  kc.inv_lz = 1.0 / (lambda * az);
+  kc.c0 = zl - std::nearbyint(zl);
+  kc.inv_2pi = 1.0 / (2.0 * kPi);
+  kc.a3 = (float)(z / (az * az * az));
+  kc.ak = (float)(k * z / (z * z));
+  HIP_TRY(launch_rs_direct(x1, y1, (const float2*)c, M1, x2, y2, M2, kc, (float2*)out, (hipStream_t)stream),
+          "launch rs_direct");
+  return NUASM_OK;
+}
+
 // ================================================================ batches
 }  // extern "C"
 

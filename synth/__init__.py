@@ -23,7 +23,7 @@ import numpy as np
 
 __all__ = [
     "rng_for", "unit_phase", "uniform_box", "clustered_box", "three_clusters",
-    "jittered_roi", "gaussian_blobs", "quadrant_grid", "CONFIGS", "WORKLOAD_CFG2",
+    "jittered_roi", "gaussian_blobs", "quadrant_grid", "experiment_field", "CONFIGS", "WORKLOAD_CFG2",
 ]
 
 
@@ -149,6 +149,18 @@ def gaussian_blobs(rng: np.random.Generator, x: np.ndarray, y: np.ndarray,
     for b in range(nb):
         t += a[b] * np.exp(-((x - mu_x[b]) ** 2 + (y - mu_y[b]) ** 2) / (2.0 * s[b] ** 2))
     return t
+
+
+def experiment_field(rng: np.random.Generator, x: np.ndarray, y: np.ndarray, W: float) -> np.ndarray:
+    """Complex source values standing in for the paper's two photographs
+    (one as amplitude, one as phase): amplitude from a blob field scaled to
+    [0, 1], phase from a second blob field scaled to [-pi/2, pi/2] (the
+    paper's mapping of pixel values 0..255).  complex128 at the points."""
+    a = gaussian_blobs(rng, x, y, W)
+    p = gaussian_blobs(rng, x, y, W)
+    a = (a - a.min()) / max(a.max() - a.min(), 1e-300)
+    p = (p - p.min()) / max(p.max() - p.min(), 1e-300)
+    return a * np.exp(1j * np.pi * (p - 0.5))
 
 
 def quadrant_grid(N: int, pitch: float, factors=(0.9, 0.8, 0.7, 1.0)):
