@@ -61,7 +61,8 @@ __all__ = [
     "transfer_asm", "transfer_fresnel", "transfer", "nuasm1", "nuasm2",
     "nuasm1_adjoint", "nuasm2_adjoint", "type1_spectrum", "spectrum_at",
     "cgh_loss", "cgh_grad", "rayleigh_sommerfeld", "rel_l2", "snr_db", "uniform_spectrum",
-    "nuasm2_from_spectrum", "nuasm3", "nuasm3_adjoint", "rayleigh_sommerfeld_points",
+    "nuasm2_from_spectrum", "nuasm3", "nuasm3_adjoint", "rayleigh_sommerfeld_points", "grid_points",
+    "scaled_asm",
 ]
 
 
@@ -353,6 +354,26 @@ def nuasm3_adjoint(geo: Geometry, w: np.ndarray, x1, y1, x2, y2, H: np.ndarray |
         H = transfer(geo)
     W = type1_spectrum(geo, x2, y2, w)
     return _type2_eval(geo, np.conj(H) * W / float(geo.Np) ** 2, x1, y1)
+
+
+def grid_points(nx: int, ny: int, pitch: float, cx: float = 0.0, cy: float = 0.0):
+    """A uniform nx x ny grid of the given pitch centred at (cx, cy), as
+    point coordinates in row-major order: point [b][a] at
+    (cx + (a - nx/2) pitch, cy + (b - ny/2) pitch) (integer division)."""
+    a = np.arange(nx, dtype=np.float64) - (nx // 2)
+    b = np.arange(ny, dtype=np.float64) - (ny // 2)
+    X, Y = np.meshgrid(cx + a * pitch, cy + b * pitch, indexing="xy")
+    return X.ravel(), Y.ravel()
+
+
+def scaled_asm(geo: Geometry, u1: np.ndarray, n2: int, d2: float, cx: float = 0.0, cy: float = 0.0,
+               H: np.ndarray | None = None) -> np.ndarray:
+    """Scaled ASM / Fresnel (destination pitch d2 != source pitch g: the
+    scaled diffraction of the introduction, which NU-ASM generalises):
+    NU-ASM_2 of the N x N source at the n2 x n2 destination grid of
+    pitch d2 centred at (cx, cy).  [n2][n2], complex128."""
+    x, y = grid_points(n2, n2, d2, cx, cy)
+    return nuasm2(geo, u1, x, y, H).reshape(n2, n2)
 
 
 # ------------------------------------------------------------ hologram loss
