@@ -186,9 +186,11 @@ def batched_workload(a, torch, P, synth):
     return 0
 
 
-def stage_pass(runs, seq_step, steps, torch):
+def stage_pass(runs, seq_step, steps, torch, bytes_fn=None):
     """Run `steps` sequential steps with the library's per-launch HIP events
-    on and total time, launches and algorithmic bytes per stage."""
+    on and total time, launches and algorithmic bytes per stage
+    (bytes_fn(stage, info, launches) overrides stage_bytes(stage, info) x
+    launches)."""
     for r in runs:
         r["plan"].set_timing(True)
     for _ in range(steps):
@@ -204,7 +206,7 @@ def stage_pass(runs, seq_step, steps, torch):
             s = stages.setdefault(st, {"ms": 0.0, "launches": 0, "bytes": 0.0})
             s["ms"] += ms
             s["launches"] += n
-            s["bytes"] += stage_bytes(st, info) * n
+            s["bytes"] += bytes_fn(st, info, n) if bytes_fn else stage_bytes(st, info) * n
             per_type_ms[r["type"]] += ms
         r["plan"].set_timing(False)
     return stages, per_type_ms
@@ -417,6 +419,78 @@ def paper_workload(a, torch, P, synth):
     return 0
 
 
+def scaled_workload(a, torch, P, synth):
+    """Scaled diffraction (the zoom case NU-ASM generalises): the headline's
+    N = 1024 source plane (4 um, 633 nm, o = (1 mm, 0), band-limited ASM,
+    tol 1e-6) propagated z = 0.1 m to a 2048 x 2048 destination grid of pitch
+    2 um (a 2x zoom over the window).  One step = one one-shot run (bind the
+    grid + execute).  value = destination points / step time on the grid path
+    (separable interpolation, no binning); the same coordinates through the
+    binned path are timed beside it."""
+    import numpy as np
+    n2, d2, z = 2048, G / 2, 0.1
+    r = synth.rng_for(2, 1)
+    u1 = torch.from_numpy(np.ascontiguousarray(synth.unit_phase(r, (N, N)))).cuda()
+    spec = dict(N=N, type=2, lam=LAM, z=z, g=G, tf="asm", band="limited", ox=OX, oy=OY, tol=TOL)
+    pg = P.Plan(defer_range_check=True, **spec)
+    pb = P.Plan(defer_range_check=True, **spec)
+    k = torch.arange(n2, dtype=torch.float64, device="cuda") - n2 // 2
+    ys, xs = torch.meshgrid(k * d2, k * d2, indexing="ij")
+    xs, ys = xs.contiguous().view(-1), ys.contiguous().view(-1)
+    og = torch.empty(n2 * n2, dtype=torch.complex64, device="cuda")
+    ob = torch.empty_like(og)
+
+    def step_grid():
+        pg.set_grid_points(n2, n2, d2)
+        pg.execute(u1, og)
+
+    def step_binned():
+        pb.set_points(xs, ys)
+        pb.execute(u1, ob)
+
+    res = {}
+    for name, fn in (("grid", step_grid), ("binned", step_binned)):
+        for _ in range(a.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(a.steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        res[name] = e0.elapsed_time(e1) / a.steps
+    pb.check_points()
+    diff = float(torch.linalg.vector_norm(og - ob) / torch.linalg.vector_norm(ob))
+    M2 = n2 * n2
+    line = {
+        "metric": "scaled ASM destination pts/sec, N'=2048 source -> 2048x2048 grid at half pitch",
+        "value": M2 / (res["grid"] * 1e-3), "unit": "points/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": res["grid"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "NU-ASM_2 one-shot from the N=1024 (N'=2048) 4 um source to a 2048 x 2048 "
+                               "destination grid of 2 um pitch, 633 nm, z = 0.1 m, o = (1 mm, 0), band-limited "
+                               "ASM, tol 1e-6",
+                   "binned_path_ms": res["binned"], "speedup_vs_binned": res["binned"] / res["grid"],
+                   "grid_vs_binned_rel_l2": diff},
+    }
+    if a.profile_steps > 0:
+        runs = [dict(plan=pg, type=2)]
+
+        def gbytes(st, info, n):
+            # grid-mode interpolation (its two launches are timed as one
+            # stage): support read once, grid values written once (the
+            # intermediate rows are not compulsory)
+            if st == "interp":
+                return (8.0 * info["L"] * info["L"] + 8.0 * M2) * n
+            return stage_bytes(st, info) * n
+        stages, _ = stage_pass(runs, step_grid, a.profile_steps, torch, gbytes)
+        roof, report = roofline(stages, a.profile_steps)
+        line.update({"roofline": roof, "stages": report})
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -427,10 +501,11 @@ def main(argv=None):
     ap.add_argument("--mode", choices=("graph", "sequential"), default="graph",
                     help="graph: the 12 runs of a step recorded as one HIP graph on parallel branches; "
                          "sequential: plain plans one after another on one stream")
-    ap.add_argument("--workload", choices=("n2048", "batched", "nuasm3", "paper"), default="n2048",
+    ap.add_argument("--workload", choices=("n2048", "batched", "nuasm3", "paper", "scaled"), default="n2048",
                     help="n2048: the 12-run N'=2048 headline workload; batched: 64 mixed planes; "
                          "nuasm3: NU-ASM_3 with 2^20 source and 2^20 destination points, 6 runs; "
-                         "paper: the paper's 256 x 256 experiment against Rayleigh-Sommerfeld")
+                         "paper: the paper's 256 x 256 experiment against Rayleigh-Sommerfeld; "
+                         "scaled: a 2x zoom to a 2048 x 2048 destination grid")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (3 times), the "
                          "reference for the FETCH_SIZE / WRITE_SIZE counters, and exit")
@@ -463,6 +538,8 @@ def main(argv=None):
         return batched_workload(a, torch, P, synth)
     if a.workload == "paper":
         return paper_workload(a, torch, P, synth)
+    if a.workload == "scaled":
+        return scaled_workload(a, torch, P, synth)
     print(f"[bench] generating inputs N={N} M={M}", file=sys.stderr, flush=True)
     host, d = make_inputs(torch, synth)
     if a.workload == "nuasm3":

@@ -153,6 +153,22 @@ nuasm_status nuasm_set_points(nuasm_plan plan, int64_t M, const double* x_dev, c
  * can be rebound without touching the other. */
 nuasm_status nuasm_set_dest_points(nuasm_plan plan, int64_t M, const double* x_dev, const double* y_dev);
 
+/* Scaled diffraction (the introduction's scaled ASM / Fresnel, which NU-ASM
+ * generalises): bind a uniform nx x ny grid of pitch `pitch` metres centred
+ * at (cx, cy) as a point set -- which = 0 for the plan's points (type 3: the
+ * source), 1 for a type-3 plan's destination.  Point [b][a] of the grid sits
+ * at (cx + (a - nx/2) pitch, cy + (b - ny/2) pitch) (integer division) and
+ * the point-side arrays of execute / execute_adjoint are [ny][nx] in that
+ * order.  The whole grid must lie in the window [-N g/2, N g/2]^2
+ * (NUASM_ERR_OUT_OF_RANGE otherwise, checked on the host, nothing enqueued).
+ * Such a set needs no binning: spreading and interpolation run as two
+ * separable 1-D passes each (the stage timers record two launches under
+ * NUASM_STAGE_SPREAD / NUASM_STAGE_INTERP).  May allocate a workspace of
+ * max(rows reached x nx, ny x L) complex values; never synchronises
+ * otherwise.  nx, ny <= 2^18, nx ny <= 2^30. */
+nuasm_status nuasm_set_grid_points(nuasm_plan plan, int32_t which, int64_t nx, int64_t ny, double pitch, double cx,
+                                   double cy);
+
 /* With NUASM_DEFER_RANGE_CHECK: synchronise and report whether the last
  * set_points (and, for type 3, set_dest_points) saw out-of-range points
  * (NUASM_ERR_OUT_OF_RANGE) or not. */

@@ -76,6 +76,8 @@ _SIGS = {
     "nuasm_plan_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(PlanInfo)]),
     "nuasm_set_points": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
     "nuasm_set_dest_points": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
+    "nuasm_set_grid_points": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                                             ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "nuasm_check_points": (ctypes.c_int, [ctypes.c_void_p]),
     "nuasm_execute": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "nuasm_execute_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -235,6 +237,20 @@ class Plan:
         """Type 3: bind the destination points."""
         self.M_dest = self._bind(load().nuasm_set_dest_points, x, y)
         self._dest_points = (x, y)
+        return self
+
+    def set_grid_points(self, nx: int, ny: int, pitch: float, cx: float = 0.0, cy: float = 0.0,
+                        dest: bool = False):
+        """Bind a uniform nx x ny grid of the given pitch centred at (cx, cy)
+        (scaled diffraction): the point-side arrays become [ny * nx] in
+        row-major grid order.  dest=True binds a type-3 plan's destination."""
+        self._sync_stream()
+        _check(load().nuasm_set_grid_points(self._h, 1 if dest else 0, int(nx), int(ny), float(pitch),
+                                            float(cx), float(cy)))
+        if dest:
+            self.M_dest = int(nx) * int(ny)
+        else:
+            self.M = int(nx) * int(ny)
         return self
 
     def check_points(self):

@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libnuasm.so")
 
-SOURCES = ["nuasm.hip", "k_fft.hip", "k_points.hip", "k_rs.hip"]
+SOURCES = ["nuasm.hip", "k_fft.hip", "k_points.hip", "k_rs.hip", "k_grid.hip"]
 ARCH = "gfx950"
 
 

@@ -353,14 +353,6 @@ k_bin_scatter(const double* __restrict__ x, const double* __restrict__ y, int64_
 // chunks writes per-chunk partial tiles that k_spread_reduce sums.
 constexpr int kSpreadThreads = 256;
 
-// es_kernel with the hardware exp2 and square root (v_exp_f32, v_sqrt_f32):
-// absolute error below 3e-8 of the kernel's peak value 1.
-__device__ __forceinline__ float es_kernel_fast(float d, float two_over_w, float beta_log2e) {
-  const float t = d * two_over_w;
-  const float r = 1.0f - t * t;
-  return r > 0.0f ? __builtin_amdgcn_exp2f(beta_log2e * (__builtin_amdgcn_sqrtf(r) - 1.0f)) : 0.0f;
-}
-
 template <int W>
 struct SpreadCfg {
   static constexpr int SB = W <= 8 ? 448 : 256;  // records per LDS sub-batch (4 workgroups per CU at w = 7)

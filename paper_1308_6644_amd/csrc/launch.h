@@ -93,6 +93,23 @@ struct InterpArgs {
   float two_over_w, beta;
 };
 
+// A non-uniform plane that is a uniform grid (scaled diffraction): nx x ny
+// points, point [b][a] at (cx + (a - nx/2) pitch, cy + (b - ny/2) pitch)
+// metres (integer division).  Its fine-grid taps follow the same rule as a
+// binned point's (pixel 0 at support cell N + 8, two cells per pixel, first
+// tap ceil(tau - w/2)), so the separable kernels below apply the weights the
+// generic spreading and interpolation would.
+struct GridPts {
+  int nx, ny;
+  double pitch, cx, cy;
+  double inv_g;     // 1 / pitch of the plan's uniform plane
+  double half_n;    // N / 2 (pixels)
+  double tau0;      // support coordinate of pixel 0: N + kPad
+  int L;            // support side
+  float two_over_w, beta_log2e;
+  int ty0, nrows;   // support rows the interpolation's x pass produces
+};
+
 // ---- launchers (return hipGetLastError() of the launch) -------------------
 hipError_t launch_fill_i32(int* p, int v, int64_t n, hipStream_t st);
 // counting sort of (point, bin) pairs: hist -> colscan -> scan -> scatter
@@ -107,6 +124,10 @@ hipError_t launch_bin_scatter(const double* x, const double* y, int64_t M, BinGe
 hipError_t launch_spread(int w, const SpreadArgs& a, int grid, hipStream_t st);
 hipError_t launch_spread_reduce(const SpreadReduceArgs& a, int grid, hipStream_t st);
 hipError_t launch_interp(int w, const InterpArgs& a, int grid, hipStream_t st);
+// separable interpolation at a grid: support (L x L) -> R (nrows x nx) -> out (ny x nx)
+hipError_t launch_grid_interp(int w, const float2* fine, float2* R, float2* out, const GridPts& p, hipStream_t st);
+// separable spreading of grid values (ny x nx) -> S (ny x L) -> support (L x L)
+hipError_t launch_grid_spread(int w, const float2* vals, float2* S, float2* fine, const GridPts& p, hipStream_t st);
 
 // type-1 pipeline: fine support (L x L) -> rows -> fused columns -> rows -> plane
 hipError_t launch_t1_rows(int logNp, const float2* fine, float2* T, GridGeom g, const float* dinv,

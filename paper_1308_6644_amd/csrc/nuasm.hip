@@ -185,6 +185,11 @@ struct PointSet {
   bool ready = false;
   bool synced = false;
   int exact_sp = 0, exact_ip = 0, exact_multi = 0;
+  // a uniform grid bound with nuasm_set_grid_points (no records, no binning)
+  bool grid = false;
+  GridPts gp{};
+  float2* gbuf = nullptr;  // separable passes' intermediate rows
+  int64_t gbuf_cap = 0;
 };
 
 struct nuasm_plan_s {
@@ -251,6 +256,7 @@ void release(nuasm_plan_s* pl) {
     f(q.scratch);
     f(q.hist);
     f(q.hoff);
+    f(q.gbuf);
     if (q.host_stat) (void)hipHostFree(q.host_stat);
     q = PointSet{};
   }
@@ -420,6 +426,7 @@ nuasm_status bind_points(nuasm_plan_s* pl, PointSet& q, int64_t M, const double*
   if (M < 0) return fail(NUASM_ERR_INVALID_ARG, "M < 0");
   if (M > 0 && (!x || !y)) return fail(NUASM_ERR_INVALID_ARG, "coordinate pointer is NULL");
   q.ready = false;
+  q.grid = false;
   nuasm_status s = ensure_points_capacity(pl, q, M);
   if (s != NUASM_OK) return s;
   hipStream_t st = pl->stream;
@@ -463,9 +470,79 @@ nuasm_status bind_points(nuasm_plan_s* pl, PointSet& q, int64_t M, const double*
   return NUASM_OK;
 }
 
+// Bind a uniform nx x ny grid of the given pitch centred at (cx, cy) as a
+// point set: no device work, the separable kernels derive every tap from the
+// grid index.  Host-side range check of the grid's extreme points.
+nuasm_status bind_grid(nuasm_plan_s* pl, PointSet& q, int64_t nx, int64_t ny, double pitch, double cx,
+                       double cy) {
+  if (nx < 0 || ny < 0) return fail(NUASM_ERR_INVALID_ARG, "grid sizes must be >= 0");
+  if (!(pitch > 0.0) || !std::isfinite(pitch) || !std::isfinite(cx) || !std::isfinite(cy))
+    return fail(NUASM_ERR_INVALID_ARG, "grid pitch must be > 0 and the centre finite");
+  if (nx > (1 << 18) || ny > (1 << 18) || nx * ny > ((int64_t)1 << 30))
+    return fail(NUASM_ERR_UNSUPPORTED, "grid larger than 2^18 per side or 2^30 points");
+  q.ready = false;
+  const double g = plane_pitch(&pl->p);
+  const double half = 0.5 * (double)pl->geom.N + 1e-9;  // pixels, with the binning's rounding slack
+  if (nx > 0 && ny > 0) {
+    const double xs[2] = {cx + (double)(0 - nx / 2) * pitch, cx + (double)(nx - 1 - nx / 2) * pitch};
+    const double ys[2] = {cy + (double)(0 - ny / 2) * pitch, cy + (double)(ny - 1 - ny / 2) * pitch};
+    for (int i = 0; i < 2; ++i)
+      if (!(std::fabs(xs[i] / g) <= half) || !(std::fabs(ys[i] / g) <= half))
+        return fail(NUASM_ERR_OUT_OF_RANGE, "grid extends outside the window [-N g/2, N g/2]^2");
+  }
+  GridPts& p = q.gp;
+  p.nx = (int)nx;
+  p.ny = (int)ny;
+  p.pitch = pitch;
+  p.cx = cx;
+  p.cy = cy;
+  p.inv_g = 1.0 / g;
+  p.half_n = 0.5 * (double)pl->geom.N;
+  p.tau0 = (double)(pl->geom.N + kPad);
+  p.L = pl->geom.L;
+  p.two_over_w = 2.0f / (float)pl->w;
+  p.beta_log2e = pl->beta * 1.4426950408889634f;
+  // support rows the interpolation's taps reach, two rows of margin against
+  // the rounding of the host's and the device's tap positions
+  p.ty0 = 0;
+  p.nrows = 0;
+  if (nx > 0 && ny > 0) {
+    auto tap = [&](int64_t k) {
+      const double t = 2.0 * ((cy + (double)(k - ny / 2) * pitch) / g) + p.tau0;
+      return (int)std::ceil(t - 0.5 * pl->w);
+    };
+    const int lo = std::max(0, tap(0) - 2);
+    const int hi = std::min(p.L, tap(ny - 1) + pl->w + 2);
+    p.ty0 = lo;
+    p.nrows = std::max(0, hi - lo);
+  }
+  const int64_t need = std::max<int64_t>((int64_t)p.nrows * nx, ny * (int64_t)p.L);
+  if (need > q.gbuf_cap) {
+    HIP_TRY(hipStreamSynchronize(pl->stream), "hipStreamSynchronize");
+    if (q.gbuf) {
+      (void)hipFree(q.gbuf);
+      pl->bytes -= sizeof(float2) * q.gbuf_cap;
+      q.gbuf = nullptr;
+      q.gbuf_cap = 0;
+    }
+    HIP_TRY(dalloc(pl, &q.gbuf, (size_t)need), "hipMalloc(grid passes)");
+    q.gbuf_cap = need;
+  }
+  q.grid = true;
+  q.M = nx * ny;
+  q.synced = true;
+  q.ready = true;
+  return NUASM_OK;
+}
+
 // Spreading of one point set's values onto the fine support (gridA).
 nuasm_status run_spread(nuasm_plan_s* pl, PointSet& q, const float2* vals) {
   hipStream_t st = pl->stream;
+  if (q.grid) {
+    StageScope sc(pl, NUASM_STAGE_SPREAD);
+    HIP_TRY(launch_grid_spread(pl->w, vals, q.gbuf, pl->gridA, q.gp, st), "launch grid_spread");
+    return NUASM_OK;
+  }
   nuasm_status s = ensure_scratch(pl, q);
   if (s != NUASM_OK) return s;
   {
@@ -503,6 +580,10 @@ nuasm_status run_spread(nuasm_plan_s* pl, PointSet& q, const float2* vals) {
 nuasm_status run_interp(nuasm_plan_s* pl, PointSet& q, const float2* grid, float2* out) {
   if (q.M == 0) return NUASM_OK;
   StageScope sc(pl, NUASM_STAGE_INTERP);
+  if (q.grid) {
+    HIP_TRY(launch_grid_interp(pl->w, grid, q.gbuf, out, q.gp, pl->stream), "launch grid_interp");
+    return NUASM_OK;
+  }
   InterpArgs ia{};
   ia.recs = q.recs;
   ia.chunks = q.ip_chunks;
@@ -818,16 +899,26 @@ nuasm_status nuasm_set_dest_points(nuasm_plan pl, int64_t M, const double* x, co
   return bind_points(pl, pl->ps[1], M, x, y);
 }
 
+nuasm_status nuasm_set_grid_points(nuasm_plan pl, int32_t which, int64_t nx, int64_t ny, double pitch, double cx,
+                                   double cy) {
+  if (!pl) return fail(NUASM_ERR_INVALID_ARG, "plan is NULL");
+  if (which < 0 || which >= pl->nsets)
+    return fail(NUASM_ERR_INVALID_ARG, "which must be 0 (or 1 for a type-3 plan's destination)");
+  return bind_grid(pl, pl->ps[which], nx, ny, pitch, cx, cy);
+}
+
 nuasm_status nuasm_check_points(nuasm_plan pl) {
   if (!pl) return fail(NUASM_ERR_INVALID_ARG, "plan is NULL");
   for (int i = 0; i < pl->nsets; ++i) {
     PointSet& q = pl->ps[i];
+    if (q.grid) continue;  // range-checked on the host when bound
     HIP_TRY(hipMemcpyAsync(q.host_stat, q.nch, sizeof(int) * 5, hipMemcpyDeviceToHost, pl->stream),
             "hipMemcpyAsync");
   }
   HIP_TRY(hipStreamSynchronize(pl->stream), "hipStreamSynchronize");
   for (int i = 0; i < pl->nsets; ++i) {
     PointSet& q = pl->ps[i];
+    if (q.grid) continue;
     if (q.host_stat[4] != 0) {
       q.ready = false;
       return fail(NUASM_ERR_OUT_OF_RANGE, i == 0 ? "points outside the window in the last set_points"

@@ -1,0 +1,162 @@
+"""Scaled diffraction (destination or source pitch different from the
+uniform plane's) on the GPU: a uniform grid bound with
+nuasm_set_grid_points runs the separable spreading / interpolation passes
+and must match the FP64 oracle (scaled_asm, itself pinned to a chirp-z
+evaluation) and the generic binned path on the same coordinates.
+
+Bars as for the other operators (rel-L2 <= 1e-5 at kernel tolerance 1e-6,
+2e-2 at 1e-2, 2e-6 at 1e-9); grid path vs binned path <= 2e-6 (same taps and
+weights, different summation order)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from gpu_util import dev, geometry, host, make_plan, rel_l2
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+BOUND = {1e-2: 2e-2, 1e-6: 1e-5, 1e-9: 2e-6}
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1308_6644_amd as P
+    P.load()
+    return P
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+CASES = [
+    # (N, n2x, n2y, pitch / g, centre / g, geometry, tol)
+    (64, 96, 80, 0.6, (3.1, -2.2), dict(g=4e-6, lam=633e-9, z=0.01, tf="asm", band="limited", ox=1e-4), 1e-6),
+    (64, 64, 64, 1.0, (0.0, 0.0), dict(g=4e-6, lam=633e-9, z=0.02, tf="asm", band="full"), 1e-6),
+    (64, 33, 35, 1.7, (-4.0, 2.0), dict(g=4e-6, lam=633e-9, z=0.005, tf="fresnel", oy=2e-5), 1e-6),
+    (32, 200, 190, 0.15, (0.7, 0.5), dict(g=5e-6, lam=500e-9, z=0.008, tf="asm", band="limited"), 1e-9),
+    (128, 250, 250, 0.5, (0.0, 0.0), dict(g=4e-6, lam=532e-9, z=-0.03, tf="asm", band="limited"), 1e-2),
+    (64, 1, 1, 0.5, (10.0, -12.0), dict(g=4e-6, lam=633e-9, z=0.01, tf="asm", band="full"), 1e-6),
+]
+
+
+def _id(c):
+    N, nx, ny, s, cen, kw, tol = c
+    return f"N{N}-{nx}x{ny}-s{s}-{kw['tf']}-z{kw['z']}-tol{tol:g}"
+
+
+@pytest.mark.parametrize("case", CASES, ids=_id)
+def test_scaled_type2_matches_oracle_and_binned_path(P, case):
+    N, nx, ny, s, (cx, cy), kw, tol = case
+    _say("scaled type 2", _id(case))
+    geo = geometry(N=N, **kw)
+    pitch, cx, cy = s * geo.g, cx * geo.g, cy * geo.g
+    rng = np.random.default_rng(N + nx + ny)
+    u1 = synth.unit_phase(rng, (N, N))
+    plan = make_plan(P, geo, 2, tol=tol)
+    plan.set_grid_points(nx, ny, pitch, cx, cy)
+    got = host(plan.execute(dev(torch, u1)))
+    x, y = O.grid_points(nx, ny, pitch, cx, cy)
+    ref = O.nuasm2(geo, u1, x, y)
+    assert rel_l2(got, ref) <= BOUND[tol]
+    binned = make_plan(P, geo, 2, tol=tol)
+    binned.set_points(dev(torch, x), dev(torch, y))
+    assert rel_l2(got, host(binned.execute(dev(torch, u1)))) <= 2e-6
+    # adjoint: grid values -> N x N plane
+    w = synth.unit_phase(rng, nx * ny)
+    a = host(plan.adjoint(dev(torch, w)))
+    assert rel_l2(a, O.nuasm2_adjoint(geo, w, x, y)) <= BOUND[tol]
+
+
+@pytest.mark.parametrize("case", CASES[:4], ids=_id)
+def test_scaled_type1_source_grid(P, case):
+    """A uniform source grid of another pitch into the uniform N' x N' plane
+    (scaled source), and its adjoint."""
+    N, nx, ny, s, (cx, cy), kw, tol = case
+    _say("scaled type 1", _id(case))
+    geo = geometry(N=N, **kw)
+    pitch, cx, cy = s * geo.g, cx * geo.g, cy * geo.g
+    rng = np.random.default_rng(7 + N + nx)
+    c = synth.unit_phase(rng, nx * ny)
+    plan = make_plan(P, geo, 1, tol=tol)
+    plan.set_grid_points(nx, ny, pitch, cx, cy)
+    got = host(plan.execute(dev(torch, c)))
+    x, y = O.grid_points(nx, ny, pitch, cx, cy)
+    assert rel_l2(got, O.nuasm1(geo, x, y, c)) <= BOUND[tol]
+    v = synth.unit_phase(rng, (2 * N, 2 * N))
+    assert rel_l2(host(plan.adjoint(dev(torch, v))), O.nuasm1_adjoint(geo, v, x, y)) <= BOUND[tol]
+
+
+def test_scaled_type3_grids(P):
+    """Type 3 with a scattered source and a grid destination, then grids on
+    both sides."""
+    N = 64
+    _say("scaled type 3")
+    geo = geometry(N=N, g=4e-6, lam=633e-9, z=0.01, tf="asm", band="limited", ox=5e-5)
+    rng = np.random.default_rng(33)
+    x1, y1 = synth.clustered_box(rng, 3000, N * geo.g)
+    c = synth.unit_phase(rng, 3000)
+    plan = make_plan(P, geo, 3)
+    plan.set_points(dev(torch, x1), dev(torch, y1))
+    plan.set_grid_points(70, 50, 0.8 * geo.g, 2 * geo.g, -1 * geo.g, dest=True)
+    x2, y2 = O.grid_points(70, 50, 0.8 * geo.g, 2 * geo.g, -1 * geo.g)
+    assert rel_l2(host(plan.execute(dev(torch, c))), O.nuasm3(geo, x1, y1, c, x2, y2)) <= 1e-5
+    plan.set_grid_points(40, 44, 1.3 * geo.g, -3 * geo.g, 0.0)
+    xs, ys = O.grid_points(40, 44, 1.3 * geo.g, -3 * geo.g, 0.0)
+    cs = synth.unit_phase(rng, 40 * 44)
+    assert rel_l2(host(plan.execute(dev(torch, cs))), O.nuasm3(geo, xs, ys, cs, x2, y2)) <= 1e-5
+    # rebinding scattered points replaces the grid
+    plan.set_points(dev(torch, x1), dev(torch, y1))
+    assert rel_l2(host(plan.execute(dev(torch, c))), O.nuasm3(geo, x1, y1, c, x2, y2)) <= 1e-5
+
+
+def test_scaled_grid_errors_and_empty(P):
+    N = 32
+    _say("scaled errors")
+    geo = geometry(N=N, g=4e-6, lam=633e-9, z=0.01)
+    plan = make_plan(P, geo, 2)
+    with pytest.raises(P.NuasmError) as ei:   # 40 x 1.0 g does not fit in 32 g
+        plan.set_grid_points(40, 8, geo.g, 0.0, 0.0)
+    assert ei.value.name == "NUASM_ERR_OUT_OF_RANGE"
+    with pytest.raises(P.NuasmError) as ei:
+        plan.execute(torch.zeros((N, N), dtype=torch.complex64, device="cuda"))
+    assert ei.value.name == "NUASM_ERR_NOT_READY"
+    with pytest.raises(P.NuasmError) as ei:
+        plan.set_grid_points(8, 8, geo.g, dest=True)   # type 2 has one point set
+    assert ei.value.name == "NUASM_ERR_INVALID_ARG"
+    with pytest.raises(P.NuasmError) as ei:
+        plan.set_grid_points(8, 8, -geo.g)
+    assert ei.value.name == "NUASM_ERR_INVALID_ARG"
+    plan.set_grid_points(0, 8, geo.g)
+    assert plan.execute(torch.ones((N, N), dtype=torch.complex64, device="cuda")).shape == (0,)
+    p1 = make_plan(P, geo, 1)
+    p1.set_grid_points(8, 0, geo.g)
+    out = p1.execute(torch.empty(0, dtype=torch.complex64, device="cuda"))
+    assert out.shape == (2 * N, 2 * N) and float(out.abs().max()) == 0.0
+
+
+def test_scaled_fullsize_zoom(P):
+    """N = 1024 source (N' = 2048), 4 um, 633 nm, z = 0.1 m band-limited ASM
+    with o = (1 mm, 0): the 2048 x 2048 destination grid at 2 um (a 2x zoom
+    covering the window); 512 sampled grid points against the oracle."""
+    N, g, lam, z, ox = 1024, 4e-6, 633e-9, 0.1, 1e-3
+    _say("scaled full size")
+    geo = O.Geometry(N=N, g=g, lam=lam, z=z, ox=ox, tf="asm", band="limited")
+    r = synth.rng_for(2, 1)
+    u1 = synth.unit_phase(r, (N, N))
+    plan = P.Plan(N, 2, lam, z, g, tf="asm", band="limited", ox=ox, tol=1e-6)
+    n2, d2 = 2048, g / 2
+    plan.set_grid_points(n2, n2, d2)
+    got = host(plan.execute(dev(torch, u1)))
+    x, y = O.grid_points(n2, n2, d2)
+    sel = np.random.default_rng(4096).choice(x.size, size=512, replace=False)
+    U = O.uniform_spectrum(u1, 2 * N, "fft")
+    ref = O.nuasm2_from_spectrum(geo, U, x[sel], y[sel])
+    err = rel_l2(got[sel], ref)
+    _say(f"  sampled rel-L2 {err:.3e}")
+    assert err <= 1e-5
