@@ -468,14 +468,17 @@ __global__ void k_transfer_table(GridGeom g, Spectral sp, float2* __restrict__ o
 // One axis of the Fresnel transfer function (Eq. 5) in float64:
 // out[k + N'/2] = amp * sum_{m in K} exp(i pi (m g + o)^2 / (lambda z)) exp(-2 pi i k m / N').
 // Both phases are reduced to whole cycles exactly (k m mod N' in integers)
-// before the float64 sincospi.
-__global__ void k_fresnel_axis(int Np, double g, double two_lam_z, double o, double2 amp,
-                               float2* __restrict__ out) {
-  const int a = blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= Np) return;
+// before the float64 sincospi.  One workgroup per output frequency; its 256
+// threads split the N' terms and meet in an LDS tree.
+constexpr int kFresnelThreads = 256;
+
+__global__ void __launch_bounds__(kFresnelThreads)
+k_fresnel_axis(int Np, double g, double two_lam_z, double o, double2 amp, float2* __restrict__ out) {
+  __shared__ double2 part[kFresnelThreads];
+  const int a = blockIdx.x;
   const int64_t k = a - Np / 2;
   double re = 0.0, im = 0.0;
-  for (int m = -Np / 2; m < Np / 2; ++m) {
+  for (int m = -Np / 2 + (int)threadIdx.x; m < Np / 2; m += kFresnelThreads) {
     const double xm = m * g + o;
     double c = xm * xm / two_lam_z;
     c -= rint(c);
@@ -486,7 +489,20 @@ __global__ void k_fresnel_axis(int Np, double g, double two_lam_z, double o, dou
     re += cs;
     im += sn;
   }
-  out[a] = make_float2((float)(re * amp.x - im * amp.y), (float)(re * amp.y + im * amp.x));
+  part[threadIdx.x] = make_double2(re, im);
+  __syncthreads();
+  for (int h = kFresnelThreads / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      part[threadIdx.x].x += part[threadIdx.x + h].x;
+      part[threadIdx.x].y += part[threadIdx.x + h].y;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    re = part[0].x;
+    im = part[0].y;
+    out[a] = make_float2((float)(re * amp.x - im * amp.y), (float)(re * amp.y + im * amp.x));
+  }
 }
 
 // --------------------------------------------------------------- launchers
@@ -655,7 +671,7 @@ hipError_t launch_transfer_table(const GridGeom& g, const Spectral& sp, float2* 
 
 hipError_t launch_fresnel_axis(int Np, double g, double two_lam_z, double o, double2 amp,
                                float2* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_fresnel_axis, dim3((Np + 127) / 128), dim3(128), 0, st, Np, g, two_lam_z, o, amp, out);
+  hipLaunchKernelGGL(k_fresnel_axis, dim3(Np), dim3(kFresnelThreads), 0, st, Np, g, two_lam_z, o, amp, out);
   return hipGetLastError();
 }
 
