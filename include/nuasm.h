@@ -113,7 +113,23 @@ typedef struct {
   int64_t M;                  /* points of the last set_points (0 if none) */
   size_t device_bytes;        /* device memory the plan holds */
   int64_t M_dest;             /* type 3: points of the last set_dest_points */
+  int32_t spread_chunk;       /* records per spreading workgroup (tuning) */
+  int32_t interp_chunk;       /* records per interpolation workgroup (tuning) */
+  int32_t bin_range_points;   /* points per binning workgroup for M (tuning) */
+  int32_t reserved;
 } nuasm_plan_info;
+
+/* Launch-shape tuning of a plan (see nuasm_plan_set_tuning); 0 = default. */
+typedef struct {
+  int32_t spread_chunk;       /* max records per spreading workgroup: 0 = 1792;
+                                 a value below 1792 selects the small size
+                                 (896 records for w <= 8, 1024 above) */
+  int32_t interp_chunk;       /* max records per interpolation workgroup: 0 = 2048,
+                                 else 256 .. 65536 */
+  int32_t bin_range_points;   /* points per binning workgroup: 0 = automatic
+                                 (max(4096, M/256), at most 65535), else 1024 .. 65535 */
+  int32_t reserved;           /* must be 0 */
+} nuasm_tuning;
 
 typedef struct nuasm_plan_s* nuasm_plan;
 
@@ -136,6 +152,13 @@ nuasm_status nuasm_plan_destroy(nuasm_plan plan);
 nuasm_status nuasm_plan_set_stream(nuasm_plan plan, void* hip_stream);
 
 nuasm_status nuasm_plan_get_info(nuasm_plan plan, nuasm_plan_info* info);
+
+/* Set the plan's launch shapes (chunk sizes of the spreading and
+ * interpolation workgroups, points per binning workgroup), e.g. from an
+ * autotuner's cache.  Results do not depend on them beyond float32
+ * summation order.  Binned point sets must be bound again afterwards
+ * (execute returns NUASM_ERR_NOT_READY until then); grids stay bound. */
+nuasm_status nuasm_plan_set_tuning(nuasm_plan plan, const nuasm_tuning* t);
 
 /* Coordinate normalisation and binning of the non-uniform plane (Fig. 1 and
  * the text around Eqs. 7-9): M points x_dev[M], y_dev[M] (device FP64
@@ -261,6 +284,12 @@ nuasm_status nuasm_batch_destroy(nuasm_batch batch);  /* NULL-safe */
  * only launch it.  Never synchronises the host. */
 nuasm_status nuasm_batch_run(nuasm_batch batch, const int64_t* M, const double* const* x,
                              const double* const* y, const void* const* in, void* const* out);
+/* Tuning of one plane of a batch (as nuasm_plan_set_tuning) and the number
+ * of parallel graph branches (1 .. min(4, P); default the maximum), e.g. from
+ * an autotuner.  Either drops the recorded graph; the next run records it
+ * again. */
+nuasm_status nuasm_batch_set_tuning(nuasm_batch batch, int32_t plane, const nuasm_tuning* t);
+nuasm_status nuasm_batch_set_branches(nuasm_batch batch, int32_t branches);
 /* Synchronise; *bad_plane = index of the first plane with out-of-range
  * points in the last run, or -1. */
 nuasm_status nuasm_batch_check_points(nuasm_batch batch, int32_t* bad_plane);

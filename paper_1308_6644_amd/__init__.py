@@ -61,8 +61,14 @@ class PlanInfo(ctypes.Structure):
         ("tiles", ctypes.c_int32), ("kx_lo", ctypes.c_int32), ("kx_hi", ctypes.c_int32),
         ("ky_lo", ctypes.c_int32), ("ky_hi", ctypes.c_int32), ("in_elems", ctypes.c_int64),
         ("out_elems", ctypes.c_int64), ("M", ctypes.c_int64), ("device_bytes", ctypes.c_size_t),
-        ("M_dest", ctypes.c_int64),
+        ("M_dest", ctypes.c_int64), ("spread_chunk", ctypes.c_int32), ("interp_chunk", ctypes.c_int32),
+        ("bin_range_points", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("spread_chunk", ctypes.c_int32), ("interp_chunk", ctypes.c_int32),
+                ("bin_range_points", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _SIGS = {
@@ -79,6 +85,9 @@ _SIGS = {
     "nuasm_set_grid_points": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
                                              ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "nuasm_check_points": (ctypes.c_int, [ctypes.c_void_p]),
+    "nuasm_plan_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
+    "nuasm_batch_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Tuning)]),
+    "nuasm_batch_set_branches": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "nuasm_execute": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "nuasm_execute_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "nuasm_debug_transfer": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
@@ -256,6 +265,12 @@ class Plan:
     def check_points(self):
         _check(load().nuasm_check_points(self._h))
 
+    def set_tuning(self, spread_chunk: int = 0, interp_chunk: int = 0, bin_range_points: int = 0):
+        """Launch-shape tuning (0 = default); binned points must be set again."""
+        t = Tuning(int(spread_chunk), int(interp_chunk), int(bin_range_points), 0)
+        _check(load().nuasm_plan_set_tuning(self._h, ctypes.byref(t)))
+        return self
+
     def _in_shape(self, adjoint: bool):
         if self.type == TYPE_3:
             return (self.M_dest,) if adjoint else (self.M,)
@@ -354,6 +369,13 @@ class Batch:
         _check(load().nuasm_batch_run(self._h, M, px, py, pi, po))
         self._keep = (xs, ys, ins, outs)
         return outs
+
+    def set_tuning(self, plane: int, spread_chunk: int = 0, interp_chunk: int = 0, bin_range_points: int = 0):
+        t = Tuning(int(spread_chunk), int(interp_chunk), int(bin_range_points), 0)
+        _check(load().nuasm_batch_set_tuning(self._h, int(plane), ctypes.byref(t)))
+
+    def set_branches(self, branches: int):
+        _check(load().nuasm_batch_set_branches(self._h, int(branches)))
 
     def check_points(self) -> int:
         bad = ctypes.c_int32(-1)

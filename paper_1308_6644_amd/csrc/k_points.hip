@@ -104,8 +104,8 @@ k_bin_hist(const double* __restrict__ x, const double* __restrict__ y, int64_t M
 // Scan over the bins, run by one workgroup: first record of every bin (written to
 // `cursor`, the bin bases the scatter adds), and the chunk tables.  Spreading
 // needs a chunk for every bin (empty bins write zeros); interpolation only for
-// non-empty bins.  A bin with more than kSpreadChunk (kChunk) records is split
-// into several spreading (interpolation) chunks; for spreading those bins are
+// non-empty bins.  A bin with more than so.sp_chunk (so.ip_chunk) records is
+// split into several spreading (interpolation) chunks; for spreading those bins are
 // listed in `multi` for the reduction.  Both chunk tables are ordered by the
 // size of their bin, largest first (17 size classes, a bin's chunks kept
 // together), so that the dispatcher starts the longest workgroups first.
@@ -141,6 +141,7 @@ __device__ __forceinline__ void bin_scan_body(const int* counts, int T, const Bi
   int* __restrict__ multi = so.multi;
   int4* __restrict__ ip_chunks = so.ip_chunks;
   int* __restrict__ nch = so.nch;
+  const int spc = so.sp_chunk, ipc = so.ip_chunk;
   constexpr int NW = kScanThreads / 64;
   __shared__ int wsum[4][NW];
   __shared__ int cls_n[2][kSizeClasses], cls_base[2][kSizeClasses];  // spreading, interpolation
@@ -161,14 +162,14 @@ __device__ __forceinline__ void bin_scan_body(const int* counts, int T, const Bi
     for (int r = 0; r < kScanRegs; ++r)
       if (r == q) c = cr[r];
     if (q >= kScanRegs && valid) c = counts[b];
-    const int nsp = !valid ? 0 : c > kSpreadChunk ? (c + kSpreadChunk - 1) / kSpreadChunk : 1;
-    const int nip = (c + kChunk - 1) / kChunk;
+    const int nsp = !valid ? 0 : c > spc ? (c + spc - 1) / spc : 1;
+    const int nip = (c + ipc - 1) / ipc;
     acc[0] += c;
     acc[1] += nsp;
     acc[2] += nip;
     acc[3] += nsp > 1 ? 1 : 0;
-    if (nsp > 0) atomicAdd(&cls_n[0][size_class(c, kSpreadChunk)], nsp);
-    if (nip > 0) atomicAdd(&cls_n[1][size_class(c, kChunk)], nip);
+    if (nsp > 0) atomicAdd(&cls_n[0][size_class(c, spc)], nsp);
+    if (nip > 0) atomicAdd(&cls_n[1][size_class(c, ipc)], nip);
   }
   int incl[4];
 #pragma unroll
@@ -204,19 +205,19 @@ __device__ __forceinline__ void bin_scan_body(const int* counts, int T, const Bi
     for (int r = 0; r < kScanRegs; ++r)
       if (r == q) c = cr[r];
     if (q >= kScanRegs && valid) c = counts[b];
-    const int nsp = !valid ? 0 : c > kSpreadChunk ? (c + kSpreadChunk - 1) / kSpreadChunk : 1;
-    const int nip = (c + kChunk - 1) / kChunk;
+    const int nsp = !valid ? 0 : c > spc ? (c + spc - 1) / spc : 1;
+    const int nip = (c + ipc - 1) / ipc;
     if (!valid) continue;
-    const int first = atomicAdd(&cls_base[0][size_class(c, kSpreadChunk)], nsp);
-    const int ifirst = nip > 0 ? atomicAdd(&cls_base[1][size_class(c, kChunk)], nip) : 0;
+    const int first = atomicAdd(&cls_base[0][size_class(c, spc)], nsp);
+    const int ifirst = nip > 0 ? atomicAdd(&cls_base[1][size_class(c, ipc)], nip) : 0;
     cursor[b] = run[0];
     sp_first[b] = first;
     sp_n[b] = nsp;
     for (int r = 0; r < nsp; ++r)
       sp_chunks[first + r] =
-          make_int4(b, run[0] + r * kSpreadChunk, min(kSpreadChunk, c - r * kSpreadChunk), nsp);
+          make_int4(b, run[0] + r * spc, min(spc, c - r * spc), nsp);
     for (int r = 0; r < nip; ++r)
-      ip_chunks[ifirst + r] = make_int4(b, run[0] + r * kChunk, min(kChunk, c - r * kChunk), nip);
+      ip_chunks[ifirst + r] = make_int4(b, run[0] + r * ipc, min(ipc, c - r * ipc), nip);
     if (nsp > 1) multi[run[3]] = b;
     run[0] += c;
     run[1] += nsp;
@@ -355,11 +356,11 @@ constexpr int kSpreadThreads = 256;
 
 template <int W>
 struct SpreadCfg {
-  static constexpr int SB = W <= 8 ? 448 : 256;  // records per LDS sub-batch (4 workgroups per CU at w = 7)
+  static constexpr int SB = spread_subbatch(W);  // records per LDS sub-batch (4 workgroups per CU at w = 7)
   static constexpr int RS = kTile + W - 1;       // first-tap cells per axis
   static constexpr int NC = RS * RS;
   static constexpr int WP = W + 2;               // padded weights, d = -1 .. w
-  static_assert(kSpreadChunk % SB == 0, "a spreading chunk is a whole number of sub-batches");
+  static_assert(kSpreadChunk == spread_nsub(W, false) * SB, "the default chunk is a whole number of sub-batches");
 };
 
 // 16-bit counters packed two per LDS word (a sub-batch has at most 448
@@ -369,12 +370,13 @@ __device__ __forceinline__ int lds_bump16s(unsigned short* cnt, int k) {
   return (int)((atomicAdd(reinterpret_cast<unsigned*>(cnt) + (k >> 1), 1u << sft) >> sft) & 0xffffu);
 }
 
-template <int W>
+template <int W, int NSUB>
 __global__ void __launch_bounds__(kSpreadThreads) k_spread(SpreadArgs a) {
+  // NSUB: sub-batches per chunk (the chunk tables hold at most NSUB * SB
+  // records per chunk)
   using Cfg = SpreadCfg<W>;
   constexpr int SB = Cfg::SB, RS = Cfg::RS, NC = Cfg::NC, WP = Cfg::WP, NT = kSpreadThreads;
   constexpr int PER = (SB + NT - 1) / NT;  // records per thread per sub-batch
-  constexpr int NSUB = kSpreadChunk / SB;  // sub-batches per chunk
   __shared__ float2 sc[SB];
   __shared__ float swx[SB][WP];
   __shared__ float swy[SB][WP];
@@ -698,9 +700,15 @@ hipError_t launch_bin_scatter(const double* x, const double* y, int64_t M, BinGe
     default: return hipErrorInvalidValue;                                           \
   }
 
-hipError_t launch_spread(int w, const SpreadArgs& a, int grid, hipStream_t st) {
+hipError_t launch_spread(int w, bool small_chunks, const SpreadArgs& a, int grid, hipStream_t st) {
   if (grid <= 0) return hipSuccess;
-#define CALL(W) hipLaunchKernelGGL(k_spread<W>, dim3(grid), dim3(kSpreadThreads), 0, st, a)
+#define CALL(W)                                                                                          \
+  {                                                                                                      \
+    if (small_chunks)                                                                                    \
+      hipLaunchKernelGGL((k_spread<W, spread_nsub(W, true)>), dim3(grid), dim3(kSpreadThreads), 0, st, a);  \
+    else                                                                                                 \
+      hipLaunchKernelGGL((k_spread<W, spread_nsub(W, false)>), dim3(grid), dim3(kSpreadThreads), 0, st, a); \
+  }
   NUASM_DISPATCH_W(w, CALL)
 #undef CALL
   return hipGetLastError();

@@ -10,8 +10,14 @@ namespace nuasm {
 
 constexpr int kTile = 32;        // fine cells per bin side
 constexpr int kPad = 8;          // support margin: taps reach w/2 <= 8 cells past the window
-constexpr int kChunk = 2048;       // max records per interpolation workgroup
-constexpr int kSpreadChunk = 1792; // max records per spreading workgroup
+constexpr int kChunk = 2048;       // default max records per interpolation workgroup
+constexpr int kSpreadChunk = 1792; // default max records per spreading workgroup
+// Spreading chunk sizes the kernel is instantiated for: whole sub-batches of
+// 448 records (w <= 8) or 256 (w > 8); `small` is about half the default.
+__host__ __device__ constexpr int spread_subbatch(int w) { return w <= 8 ? 448 : 256; }
+__host__ __device__ constexpr int spread_nsub(int w, bool small) {
+  return small ? (w <= 8 ? 2 : 4) : (w <= 8 ? 4 : 7);
+}
 constexpr int kMaxW = 16;
 
 // Geometry of the fine-grid support and of the uniform planes.
@@ -59,6 +65,8 @@ struct BinScanOut {
   int* multi;        // bins with several spreading chunks
   int4* ip_chunks;   // interpolation chunks
   int* nch;          // spread chunks, interp chunks, records, multi bins, points out of range
+  int sp_chunk;      // max records per spreading chunk
+  int ip_chunk;      // max records per interpolation chunk
 };
 constexpr int kScanDone = 7;  // element of nch counting finished column-scan workgroups
 
@@ -121,7 +129,7 @@ hipError_t launch_bin_colscan(const uint16_t* hist, int G, int T, int* off, int*
                               int* done, hipStream_t st);
 hipError_t launch_bin_scatter(const double* x, const double* y, int64_t M, BinGeom g, int ppw, int G,
                               const int* off, const int* bin_base, BinRec* recs, hipStream_t st);
-hipError_t launch_spread(int w, const SpreadArgs& a, int grid, hipStream_t st);
+hipError_t launch_spread(int w, bool small_chunks, const SpreadArgs& a, int grid, hipStream_t st);
 hipError_t launch_spread_reduce(const SpreadReduceArgs& a, int grid, hipStream_t st);
 hipError_t launch_interp(int w, const InterpArgs& a, int grid, hipStream_t st);
 // separable interpolation at a grid: support (L x L) -> R (nrows x nx) -> out (ny x nx)

@@ -211,6 +211,11 @@ struct nuasm_plan_s {
   float2* fre = nullptr;  // [2][Np]
   // point sets: [0] the plan's points (type 3: the source), [1] type 3's destination
   PointSet ps[2];
+  // tuning (nuasm_plan_set_tuning): chunk sizes and binning ranges
+  bool sp_small = false;  // spreading chunks of about half the default size
+  int sp_chunk = kSpreadChunk;
+  int ip_chunk = kChunk;
+  int bin_ppw = 0;        // points per binning workgroup, 0 = automatic
   int nsets = 1;
   size_t bytes = 0;
   // stage timing
@@ -335,10 +340,11 @@ nuasm_status validate(const nuasm_params* p) {
   return NUASM_OK;
 }
 
-// Binning workgroups: contiguous ranges of ppw points (at least 4096, at most
-// kBinPointsMax, and about 256 ranges for large M).
-void bin_ranges(int64_t M, int* ppw, int* G) {
-  int64_t p = std::max<int64_t>(4096, (M + 255) / 256);
+// Binning workgroups: contiguous ranges of ppw points (automatic: at least
+// 4096, at most kBinPointsMax, and about 256 ranges for large M; or the
+// tuned count).
+void bin_ranges(int64_t M, int fixed, int* ppw, int* G) {
+  int64_t p = fixed > 0 ? fixed : std::max<int64_t>(4096, (M + 255) / 256);
   p = std::min<int64_t>(p, kBinPointsMax);
   *ppw = (int)p;
   *G = (int)((M + p - 1) / p);
@@ -389,13 +395,13 @@ nuasm_status ensure_points_capacity(nuasm_plan_s* pl, PointSet& q, int64_t M) {
   q.rec_cap = 0;
   {
     int ppw = 0, G = 0;
-    bin_ranges(cap, &ppw, &G);
+    bin_ranges(cap, pl->bin_ppw, &ppw, &G);
     q.hist_rows = std::max(G, 1);
     HIP_TRY(dalloc(pl, &q.hist, (size_t)q.hist_rows * (pl->T + 1)), "hipMalloc(bin histograms)");
     HIP_TRY(dalloc(pl, &q.hoff, (size_t)q.hist_rows * (pl->T + 1)), "hipMalloc(bin offsets)");
   }
   HIP_TRY(dalloc(pl, &q.recs, (size_t)(4 * cap)), "hipMalloc(records)");
-  q.chunk_cap = pl->T + (4 * cap) / kSpreadChunk + 1;  // covers both chunk tables
+  q.chunk_cap = pl->T + (4 * cap) / std::min(pl->sp_chunk, pl->ip_chunk) + 1;  // covers both chunk tables
   HIP_TRY(dalloc(pl, &q.sp_chunks, (size_t)q.chunk_cap), "hipMalloc(chunks)");
   HIP_TRY(dalloc(pl, &q.ip_chunks, (size_t)q.chunk_cap), "hipMalloc(chunks)");
   q.rec_cap = cap;
@@ -412,13 +418,13 @@ nuasm_status ensure_scratch(nuasm_plan_s* pl, PointSet& q) {
 // Grid sizes of the point kernels: the exact chunk counts once a set_points
 // has synchronised, else upper bounds (surplus workgroups exit at once).
 int sp_grid(const nuasm_plan_s* pl, const PointSet& q) {
-  return q.synced ? q.exact_sp : (int)std::min<int64_t>(q.chunk_cap, pl->T + (4 * q.M) / kSpreadChunk + 1);
+  return q.synced ? q.exact_sp : (int)std::min<int64_t>(q.chunk_cap, pl->T + (4 * q.M) / pl->sp_chunk + 1);
 }
 int ip_grid(const nuasm_plan_s* pl, const PointSet& q) {
-  return q.synced ? q.exact_ip : (int)std::min<int64_t>(q.chunk_cap, pl->T + (4 * q.M) / kChunk + 1);
+  return q.synced ? q.exact_ip : (int)std::min<int64_t>(q.chunk_cap, pl->T + (4 * q.M) / pl->ip_chunk + 1);
 }
 int multi_grid(const nuasm_plan_s* pl, const PointSet& q) {
-  return q.synced ? q.exact_multi : (int)std::min<int64_t>(pl->T, (4 * q.M) / kSpreadChunk + 1);
+  return q.synced ? q.exact_multi : (int)std::min<int64_t>(pl->T, (4 * q.M) / pl->sp_chunk + 1);
 }
 
 // Coordinate normalisation and binning of one point set (three launches).
@@ -432,7 +438,7 @@ nuasm_status bind_points(nuasm_plan_s* pl, PointSet& q, int64_t M, const double*
   hipStream_t st = pl->stream;
   {
     int ppw = 0, G = 0;
-    bin_ranges(M, &ppw, &G);
+    bin_ranges(M, pl->bin_ppw, &ppw, &G);
     if (M > 0) {
       StageScope sc(pl, NUASM_STAGE_BIN_HIST);
       HIP_TRY(launch_bin_hist(x, y, M, pl->bgeom, ppw, G, q.hist, st), "launch bin_hist");
@@ -440,7 +446,8 @@ nuasm_status bind_points(nuasm_plan_s* pl, PointSet& q, int64_t M, const double*
     {
       // column scan and bin scan in one launch; with no points (G = 0) it
       // writes zero totals and empty-bin chunk tables
-      const BinScanOut so{q.cursor, q.sp_chunks, q.sp_first, q.sp_n, q.multi, q.ip_chunks, q.nch};
+      const BinScanOut so{q.cursor, q.sp_chunks, q.sp_first, q.sp_n, q.multi, q.ip_chunks, q.nch, pl->sp_chunk,
+                          pl->ip_chunk};
       StageScope sc(pl, NUASM_STAGE_BIN_COLSCAN);
       HIP_TRY(launch_bin_colscan(q.hist, M > 0 ? G : 0, pl->T, q.hoff, q.counts, so, q.nch + kScanDone, st),
               "launch bin_colscan");
@@ -558,7 +565,7 @@ nuasm_status run_spread(nuasm_plan_s* pl, PointSet& q, const float2* vals) {
     sa.TX = pl->TX;
     sa.two_over_w = 2.0f / (float)pl->w;
     sa.beta = pl->beta;
-    HIP_TRY(launch_spread(pl->w, sa, sp_grid(pl, q), st), "launch spread");
+    HIP_TRY(launch_spread(pl->w, pl->sp_small, sa, sp_grid(pl, q), st), "launch spread");
   }
   {
     StageScope sc(pl, NUASM_STAGE_SPREAD_REDUCE);
@@ -885,6 +892,39 @@ nuasm_status nuasm_plan_get_info(nuasm_plan pl, nuasm_plan_info* info) {
   info->M = M;
   info->device_bytes = pl->bytes;
   info->M_dest = M2;
+  info->spread_chunk = pl->sp_chunk;
+  info->interp_chunk = pl->ip_chunk;
+  {
+    int ppw = 0, G = 0;
+    bin_ranges(M, pl->bin_ppw, &ppw, &G);
+    info->bin_range_points = ppw;
+  }
+  return NUASM_OK;
+}
+
+nuasm_status nuasm_plan_set_tuning(nuasm_plan pl, const nuasm_tuning* t) {
+  if (!pl || !t) return fail(NUASM_ERR_INVALID_ARG, "plan or tuning is NULL");
+  if (t->spread_chunk < 0 || t->interp_chunk < 0 || t->bin_range_points < 0 || t->reserved != 0)
+    return fail(NUASM_ERR_INVALID_ARG, "tuning fields must be >= 0 and reserved 0");
+  if (t->interp_chunk != 0 && (t->interp_chunk < 256 || t->interp_chunk > 65536))
+    return fail(NUASM_ERR_INVALID_ARG, "interp_chunk must be 0 or in [256, 65536]");
+  if (t->bin_range_points != 0 && (t->bin_range_points < 1024 || t->bin_range_points > kBinPointsMax))
+    return fail(NUASM_ERR_INVALID_ARG, "bin_range_points must be 0 or in [1024, 65535]");
+  // spreading chunks come in the two sizes the kernel is built for; a request
+  // below the default takes the small one
+  const int small = spread_nsub(pl->w, true) * spread_subbatch(pl->w);
+  pl->sp_small = t->spread_chunk != 0 && t->spread_chunk < kSpreadChunk;
+  pl->sp_chunk = pl->sp_small ? small : kSpreadChunk;
+  pl->ip_chunk = t->interp_chunk != 0 ? t->interp_chunk : kChunk;
+  pl->bin_ppw = t->bin_range_points;
+  // binned point sets must be bound again (their chunk tables and histogram
+  // rows follow the old sizes); grids need no tables
+  for (int i = 0; i < pl->nsets; ++i) {
+    PointSet& q = pl->ps[i];
+    if (q.grid) continue;
+    q.ready = false;
+    q.rec_cap = 0;
+  }
   return NUASM_OK;
 }
 
@@ -1068,6 +1108,7 @@ struct nuasm_batch_s {
   hipStream_t cap = nullptr;     // internal stream the graph is recorded and launched on
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   std::vector<hipStream_t> branch;
+  int active = 0;              // branches in use (nuasm_batch_set_branches)
   std::vector<int> branch_of;  // plane -> branch
   hipEvent_t fork = nullptr;
   std::vector<hipEvent_t> join;
@@ -1121,7 +1162,7 @@ static double plane_cost(const nuasm_plan_s* pl, int64_t M) {
 
 // Longest-processing-time assignment of the planes to the capture branches.
 static void assign_branches(nuasm_batch_s* b, const int64_t* M) {
-  const int P = (int)b->plans.size(), K = (int)b->branch.size();
+  const int P = (int)b->plans.size(), K = b->active;
   std::vector<double> work(P);
   std::vector<int> order(P);
   for (int p = 0; p < P; ++p) {
@@ -1171,6 +1212,7 @@ nuasm_status nuasm_batch_create(int32_t P, const nuasm_params* params, void* hip
     b->plans.push_back(pl);
   }
   const int K = std::min(kBranches, (int)P);
+  b->active = K;
   b->branch_of.assign(P, 0);
   hipError_t e;
   for (int k = 0; k < K; ++k) {
@@ -1258,14 +1300,14 @@ nuasm_status nuasm_batch_run(nuasm_batch b, const int64_t* M, const double* cons
   nuasm_status st = NUASM_OK;
   hipError_t e = launch_stamp(b->ts, b->cap);
   if (e == hipSuccess) e = hipEventRecord(b->fork, b->cap);
-  for (size_t k = 0; e == hipSuccess && k < b->branch.size(); ++k) e = hipStreamWaitEvent(b->branch[k], b->fork, 0);
+  for (size_t k = 0; e == hipSuccess && k < (size_t)b->active; ++k) e = hipStreamWaitEvent(b->branch[k], b->fork, 0);
   for (int p = 0; e == hipSuccess && st == NUASM_OK && p < P; ++p) {
     nuasm_plan_s* pl = b->plans[p];
     pl->stream = b->branch[b->branch_of[p]];
     st = batch_plane(pl, M[p], x[p], y[p], in[p], out[p]);
     if (st == NUASM_OK) e = launch_stamp(b->ts + 1 + p, pl->stream);
   }
-  for (size_t k = 0; e == hipSuccess && k < b->branch.size(); ++k) {
+  for (size_t k = 0; e == hipSuccess && k < (size_t)b->active; ++k) {
     e = hipEventRecord(b->join[k], b->branch[k]);
     if (e == hipSuccess) e = hipStreamWaitEvent(b->cap, b->join[k], 0);
   }
@@ -1285,6 +1327,36 @@ nuasm_status nuasm_batch_run(nuasm_batch b, const int64_t* M, const double* cons
   }
   b->key = key;
   return launch();
+}
+
+namespace {
+// Drop the recorded graph so that the next run records it again.
+nuasm_status batch_invalidate(nuasm_batch_s* b) {
+  if (!b->exec) return NUASM_OK;
+  HIP_TRY(hipStreamSynchronize(b->cap), "hipStreamSynchronize");
+  (void)hipGraphExecDestroy(b->exec);
+  b->exec = nullptr;
+  b->key.clear();
+  return NUASM_OK;
+}
+}  // namespace
+
+nuasm_status nuasm_batch_set_tuning(nuasm_batch b, int32_t plane, const nuasm_tuning* t) {
+  if (!b || !t) return fail(NUASM_ERR_INVALID_ARG, "batch or tuning is NULL");
+  if (plane < 0 || plane >= (int32_t)b->plans.size()) return fail(NUASM_ERR_INVALID_ARG, "plane index out of range");
+  nuasm_status s = batch_invalidate(b);
+  if (s != NUASM_OK) return s;
+  return nuasm_plan_set_tuning(b->plans[plane], t);
+}
+
+nuasm_status nuasm_batch_set_branches(nuasm_batch b, int32_t branches) {
+  if (!b) return fail(NUASM_ERR_INVALID_ARG, "batch is NULL");
+  if (branches < 1 || branches > (int32_t)b->branch.size())
+    return fail(NUASM_ERR_INVALID_ARG, "branches must be in [1, min(4, planes)]");
+  nuasm_status s = batch_invalidate(b);
+  if (s != NUASM_OK) return s;
+  b->active = branches;
+  return NUASM_OK;
 }
 
 nuasm_status nuasm_batch_check_points(nuasm_batch b, int32_t* bad_plane) {

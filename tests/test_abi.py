@@ -96,9 +96,19 @@ def test_type3_rejects_the_crop_flag(P):
 
 
 def test_plan_info_struct_layout_matches_header(P):
-    # 4 x int64, 8 x int32/float, 3 x int64, size_t, int64
-    assert ctypes.sizeof(P.PlanInfo) == 4 * 8 + 8 * 4 + 3 * 8 + 8 + 8
-    assert [f for f, _ in P.PlanInfo._fields_][-1] == "M_dest"
+    # 4 x int64, 8 x int32/float, 3 x int64, size_t, int64, 4 x int32
+    assert ctypes.sizeof(P.PlanInfo) == 4 * 8 + 8 * 4 + 3 * 8 + 8 + 8 + 4 * 4
+    assert [f for f, _ in P.PlanInfo._fields_][-4:] == ["spread_chunk", "interp_chunk", "bin_range_points",
+                                                         "reserved"]
+    assert ctypes.sizeof(P.Tuning) == 16
+
+
+def test_tuning_rejects_bad_values_without_a_device(P):
+    lib = P.load()
+    t = P.Tuning(0, 100, 0, 0)
+    assert lib.nuasm_status_string(lib.nuasm_plan_set_tuning(None, ctypes.byref(t))).decode() == \
+        "NUASM_ERR_INVALID_ARG"
+    assert lib.nuasm_batch_set_branches(None, 2) != 0
 
 
 def test_stage_names_match_header_count(P):
