@@ -641,6 +641,23 @@ def main(argv=None):
         print(json.dumps(line), flush=True)
         return 0
 
+    # execute-only time (points bound once and reused, as in the iterations of
+    # a hologram optimisation): the 12 runs' execute calls on plain plans
+    for r in runs:
+        r["plan"].set_points(r["x"], r["y"])
+    for _ in range(a.warmup):
+        for r in runs:
+            r["plan"].execute(r["inp"], r["out"])
+    e0.record()
+    for _ in range(a.steps):
+        for r in runs:
+            r["plan"].execute(r["inp"], r["out"])
+    e1.record()
+    torch.cuda.synchronize()
+    ex_ms = e0.elapsed_time(e1) / a.steps
+    line["execute_only"] = {"ms_per_step": ex_ms, "points_per_s": len(runs) * M / (ex_ms * 1e-3),
+                            "mode": "sequential plain plans, points bound once"}
+
     # second pass: per-stage HIP events recorded by the library
     print(f"[bench] per-stage timing {a.profile_steps} steps", file=sys.stderr, flush=True)
     stages, per_type_ms = stage_pass(runs, seq_step, a.profile_steps, torch)

@@ -78,6 +78,8 @@ enum { NUASM_BAND_FULL = 0, NUASM_BAND_LIMITED = 1, NUASM_BAND_EXPLICIT = 2 };
 /* params.flags */
 #define NUASM_OUT_CROP_N        0x1u  /* type 1: write only the central N x N */
 #define NUASM_DEFER_RANGE_CHECK 0x2u  /* set_points does not synchronise */
+#define NUASM_FULL_FINE_GRID    0x4u  /* keep the fine grid at 2 N' even when the
+                                         band of Eq. 4 would allow a smaller one */
 
 typedef struct {
   int32_t type;        /* NUASM_TYPE_1, NUASM_TYPE_2 or NUASM_TYPE_3 */
@@ -100,8 +102,8 @@ typedef struct {
 } nuasm_params;
 
 typedef struct {
-  int64_t N, Np, nf;          /* plane side, N' = 2N, fine grid sigma N' = 2N' */
-  int64_t L;                  /* side of the stored fine-grid support, N' + 16 */
+  int64_t N, Np, nf;          /* plane side, N' = 2N, fine grid nf = 2 N'' (N'' = Npf) */
+  int64_t L;                  /* side of the stored fine-grid support, N'' + 16 */
   int32_t w;                  /* spreading-kernel width in fine cells */
   float beta;                 /* exponential-of-semicircle shape parameter */
   int32_t tile;               /* fine cells per bin side */
@@ -116,7 +118,10 @@ typedef struct {
   int32_t spread_chunk;       /* records per spreading workgroup (tuning) */
   int32_t interp_chunk;       /* records per interpolation workgroup (tuning) */
   int32_t bin_range_points;   /* points per binning workgroup for M (tuning) */
-  int32_t reserved;
+  int32_t Npf;                /* spectral grid N'': N', or, when the band of Eq. 4
+                                 is narrow, the smallest power of two >= max(32,
+                                 N'/8) whose centred index set holds the band;
+                                 the fine grid is 2 N'' */
 } nuasm_plan_info;
 
 /* Launch-shape tuning of a plan (see nuasm_plan_set_tuning); 0 = default. */

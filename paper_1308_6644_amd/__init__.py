@@ -27,6 +27,7 @@ BAND = {"full": 0, "limited": 1, "explicit": 2}
 TF = {"asm": TF_ASM, "fresnel": TF_FRESNEL}
 OUT_CROP_N = 0x1
 DEFER_RANGE_CHECK = 0x2
+FULL_FINE_GRID = 0x4
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -62,7 +63,7 @@ class PlanInfo(ctypes.Structure):
         ("ky_lo", ctypes.c_int32), ("ky_hi", ctypes.c_int32), ("in_elems", ctypes.c_int64),
         ("out_elems", ctypes.c_int64), ("M", ctypes.c_int64), ("device_bytes", ctypes.c_size_t),
         ("M_dest", ctypes.c_int64), ("spread_chunk", ctypes.c_int32), ("interp_chunk", ctypes.c_int32),
-        ("bin_range_points", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("bin_range_points", ctypes.c_int32), ("Npf", ctypes.c_int32),
     ]
 
 
@@ -156,7 +157,7 @@ def _dev_ptr(t: torch.Tensor, dtype, what: str) -> int:
 def make_params(N: int, type: int, lam: float, z: float, g: float, *, tf: str = "asm",
                 ox: float = 0.0, oy: float = 0.0, band: str = "full", band_c=(0.0, 0.0),
                 band_w=(0.0, 0.0), tol: float = 1e-6, phase_fp64: bool = True, crop: bool = False,
-                defer_range_check: bool = False) -> Params:
+                defer_range_check: bool = False, full_fine_grid: bool = False) -> Params:
     lib = load()
     p = Params()
     _check(lib.nuasm_params_default(ctypes.byref(p)))
@@ -172,7 +173,8 @@ def make_params(N: int, type: int, lam: float, z: float, g: float, *, tf: str = 
     p.band_c[0], p.band_c[1] = float(band_c[0]), float(band_c[1])
     p.band_w[0], p.band_w[1] = float(band_w[0]), float(band_w[1])
     p.tol = float(tol)
-    p.flags = (OUT_CROP_N if crop else 0) | (DEFER_RANGE_CHECK if defer_range_check else 0)
+    p.flags = ((OUT_CROP_N if crop else 0) | (DEFER_RANGE_CHECK if defer_range_check else 0)
+               | (FULL_FINE_GRID if full_fine_grid else 0))
     return p
 
 
@@ -190,10 +192,11 @@ class Plan:
     def __init__(self, N: int, type: int, lam: float, z: float, g: float, *, tf: str = "asm",
                  ox: float = 0.0, oy: float = 0.0, band: str = "full", band_c=(0.0, 0.0),
                  band_w=(0.0, 0.0), tol: float = 1e-6, phase_fp64: bool = True, crop: bool = False,
-                 defer_range_check: bool = False, device=None):
+                 defer_range_check: bool = False, full_fine_grid: bool = False, device=None):
         lib = load()
         p = make_params(N, type, lam, z, g, tf=tf, ox=ox, oy=oy, band=band, band_c=band_c, band_w=band_w,
-                        tol=tol, phase_fp64=phase_fp64, crop=crop, defer_range_check=defer_range_check)
+                        tol=tol, phase_fp64=phase_fp64, crop=crop, defer_range_check=defer_range_check,
+                        full_fine_grid=full_fine_grid)
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self.params = p
         self.N, self.Np, self.type, self.crop = int(N), 2 * int(N), int(type), bool(crop)

@@ -117,21 +117,39 @@ k_t1_rows(const float2* __restrict__ fine, float2* __restrict__ T, GridGeom g,
   }
 }
 
-// Columns of T -> nf-point FFT along y -> keep k_y in K -> times
-// H(k) Rect(k) / psihat(k_y) / N'^2 -> N'-point inverse FFT along y.
-// The (-1)^k factors of the centred fine grid and of the centred inverse DFT
-// cancel (N'/2 is even); the remaining output sign (-1)^n_y is applied here.
-template <int LOGNP>
-__global__ void __launch_bounds__(ColCfg<LOGNP + 1>::NT)
+// Column passes that change length: a forward FFT of one length and an
+// inverse FFT of another over the same columns; C adjacent columns sized by
+// the longer of the two.
+template <int LOGA, int LOGB>
+struct Col2Cfg {
+  static constexpr int LMAX = LOGA > LOGB ? LOGA : LOGB;
+  static constexpr int NMAX = 1 << LMAX;
+  static constexpr int C0 = kColElems / NMAX;
+  static constexpr int C = C0 < 1 ? 1 : (C0 > 16 ? 16 : C0);
+  static constexpr int NB = C * NMAX / 8;
+  static constexpr int NT = NB < 64 ? 64 : (NB > 1024 ? 1024 : NB);
+  static constexpr int DATA = lds_elems(C * NMAX);
+  static constexpr int LDS = (DATA + Tw2<LOGA>::SIZE + Tw2<LOGB>::SIZE) * 8;
+};
+
+// Columns of T -> nf-point FFT along y -> keep k_y in the spectral grid K''
+// (N'' = NPF modes, a superset of the band of Eq. 4; N'' = N' unless the band
+// is narrow) -> times H(k) Rect(k) / psihat(k_y) / N'^2 -> embedded in K ->
+// N'-point inverse FFT along y.  T holds the columns k_x + N''/2; V is
+// written with N' columns, k_x + N'/2.  The (-1)^k factors of the centred
+// fine grid and of the centred inverse DFT cancel (N'/2 is even); the
+// remaining output sign (-1)^n_y is applied here.
+template <int LOGNPF, int LOGNP>
+__global__ void __launch_bounds__((Col2Cfg<LOGNPF + 1, LOGNP>::NT))
 k_t1_cols(const float2* __restrict__ T, float2* __restrict__ V, GridGeom g, Spectral sp,
           const float2* __restrict__ twall) {
-  constexpr int LOGN = LOGNP + 1, NF = 1 << LOGN, NP = 1 << LOGNP;
-  using Cfg = ColCfg<LOGN>;
+  constexpr int LOGN = LOGNPF + 1, NF = 1 << LOGN, NPF = 1 << LOGNPF, NP = 1 << LOGNP;
+  using Cfg = Col2Cfg<LOGN, LOGNP>;
   constexpr int C = Cfg::C, NT = Cfg::NT;
   extern __shared__ float2 s[];
   const int strip = xcd_remap(blockIdx.x, gridDim.x);
   const int a0 = strip * C;
-  const int kx0 = a0 - NP / 2;
+  const int kx0 = a0 - NPF / 2;
   if (kx0 + C - 1 < g.kxlo || kx0 > g.kxhi) return;  // whole strip outside the band
   float2* twf = s + Cfg::DATA;
   float2* twp = twf + Tw2<LOGN>::SIZE;
@@ -142,7 +160,7 @@ k_t1_cols(const float2* __restrict__ T, float2* __restrict__ V, GridGeom g, Spec
     const int t = e / C, c = e % C;
     const int i = t - s0;
     float2 v = czero();
-    if (i >= 0 && i < L && in_band(kx0 + c, g.kxlo, g.kxhi)) v = T[(size_t)i * NP + a0 + c];
+    if (i >= 0 && i < L && in_band(kx0 + c, g.kxlo, g.kxhi)) v = T[(size_t)i * NPF + a0 + c];
     s[pidx(e)] = v;
   }
   __syncthreads();
@@ -156,10 +174,10 @@ k_t1_cols(const float2* __restrict__ T, float2* __restrict__ V, GridGeom g, Spec
       const int ay = e / C, c = e % C;
       const int ky = ay - NP / 2, kx = kx0 + c;
       float2 x = czero();
-      if (in_band(kx, g.kxlo, g.kxhi) && in_band(ky, g.kylo, g.kyhi)) {
+      if (ky >= -NPF / 2 && ky < NPF / 2 && in_band(kx, g.kxlo, g.kxhi) && in_band(ky, g.kylo, g.kyhi)) {
         const float2 h = transfer_at(sp, NP, kx, ky);
         x = cmul(s[pidx(((ky + NF) & (NF - 1)) * C + c)], h);
-        x = cscale(x, sp.dinv[ay] * sp.scale);
+        x = cscale(x, sp.dinv[ky + NPF / 2] * sp.scale);
       }
       v[q] = x;
     }
@@ -171,13 +189,14 @@ k_t1_cols(const float2* __restrict__ T, float2* __restrict__ V, GridGeom g, Spec
     if (e < C * NP) s[pidx(e)] = v[q];
   }
   __syncthreads();
-  fft_lds<LOGNP, C, NT, +1>(s, twp);
+  fft_lds<LOGNP, C, NT, +1>(s, twp, opaque_tid());
   for (int e = threadIdx.x; e < C * NP; e += NT) {
     const int by = e / C, c = e % C;
-    if (in_band(kx0 + c, g.kxlo, g.kxhi)) {
+    const int kx = kx0 + c;
+    if (in_band(kx, g.kxlo, g.kxhi)) {
       float2 x = s[pidx(e)];
       if (by & 1) x = make_float2(-x.x, -x.y);
-      V[(size_t)by * NP + a0 + c] = x;
+      V[(size_t)by * NP + kx + NP / 2] = x;
     }
   }
 }
@@ -257,25 +276,27 @@ k_t2_rows(const float2* __restrict__ u1, float2* __restrict__ T, GridGeom g,
   }
 }
 
-// Columns of T (Nin rows) -> N'-point FFT along y -> times H(k) Rect(k)
-// (-1)^k_y / psihat(k_y) / N'^2 -> embed k_y into the nf-point spectrum ->
-// inverse nf-point FFT along y -> keep the support rows [s0, s0 + L).
-template <int LOGNP>
-__global__ void __launch_bounds__(ColCfg<LOGNP + 1>::NT)
+// Columns of T (Nin rows, N' columns k_x + N'/2) -> N'-point FFT along y ->
+// the modes k_y of the spectral grid K'' (N'' = NPF, a superset of the band
+// of Eq. 4) times H(k) Rect(k) (-1)^k_y / psihat(k_y) / N'^2, embedded in the
+// nf-point spectrum (nf = 2 N'', the gap zero) -> inverse nf-point FFT along
+// y -> the support rows [s0, s0 + L), written with N'' columns k_x + N''/2.
+template <int LOGNPF, int LOGNP>
+__global__ void __launch_bounds__((Col2Cfg<LOGNP, LOGNPF + 1>::NT))
 k_t2_cols(const float2* __restrict__ T, float2* __restrict__ V, GridGeom g, Spectral sp,
           const float2* __restrict__ twall) {
-  constexpr int LOGN = LOGNP + 1, NF = 1 << LOGN, NP = 1 << LOGNP;
-  using Cfg = ColCfg<LOGN>;
+  constexpr int LOGN = LOGNPF + 1, NF = 1 << LOGN, NPF = 1 << LOGNPF, NP = 1 << LOGNP;
+  using Cfg = Col2Cfg<LOGNP, LOGN>;
   constexpr int C = Cfg::C, NT = Cfg::NT;
   extern __shared__ float2 s[];
   const int strip = xcd_remap(blockIdx.x, gridDim.x);
   const int a0 = strip * C;
   const int kx0 = a0 - NP / 2;
   if (kx0 + C - 1 < g.kxlo || kx0 > g.kxhi) return;
-  float2* twf = s + Cfg::DATA;
-  float2* twp = twf + Tw2<LOGN>::SIZE;
-  load_tw2<LOGN, NT>(twf, tw_for(twall, LOGN));
+  float2* twp = s + Cfg::DATA;
+  float2* twf = twp + Tw2<LOGNP>::SIZE;
   load_tw2<LOGNP, NT>(twp, tw_for(twall, LOGNP));
+  load_tw2<LOGN, NT>(twf, tw_for(twall, LOGN));
   const int Nin = g.Nin;
   for (int e = threadIdx.x; e < C * NP; e += NT) {
     const int t = e / C, c = e % C;
@@ -287,14 +308,15 @@ k_t2_cols(const float2* __restrict__ T, float2* __restrict__ V, GridGeom g, Spec
   }
   __syncthreads();
   fft_lds<LOGNP, C, NT, -1>(s, twp);
-  constexpr int PER = (C * NP + NT - 1) / NT;
+  // the modes of K'' (position ky + N''/2) into registers
+  constexpr int PER = (C * NPF + NT - 1) / NT;
   float2 v[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int e = threadIdx.x + q * NT;
-    if (e < C * NP) {
+    if (e < C * NPF) {
       const int ay = e / C, c = e % C;
-      const int ky = ay - NP / 2, kx = kx0 + c;
+      const int ky = ay - NPF / 2, kx = kx0 + c;
       float2 x = czero();
       if (in_band(kx, g.kxlo, g.kxhi) && in_band(ky, g.kylo, g.kyhi)) {
         const float2 h = transfer_at(sp, NP, kx, ky);
@@ -305,26 +327,27 @@ k_t2_cols(const float2* __restrict__ T, float2* __restrict__ V, GridGeom g, Spec
     }
   }
   __syncthreads();
-  // the gap between the two halves of K inside the nf-point spectrum is zero
-  for (int e = threadIdx.x; e < C * (NF - NP); e += NT) {
-    const int t = NP / 2 + e / C, c = e % C;
+  // the gap between the two halves of K'' inside the nf-point spectrum is zero
+  for (int e = threadIdx.x; e < C * (NF - NPF); e += NT) {
+    const int t = NPF / 2 + e / C, c = e % C;
     s[pidx(t * C + c)] = czero();
   }
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int e = threadIdx.x + q * NT;
-    if (e < C * NP) {
+    if (e < C * NPF) {
       const int ay = e / C, c = e % C;
-      const int ky = ay - NP / 2;
+      const int ky = ay - NPF / 2;
       s[pidx(((ky + NF) & (NF - 1)) * C + c)] = v[q];
     }
   }
   __syncthreads();
-  fft_lds<LOGN, C, NT, +1>(s, twf);
+  fft_lds<LOGN, C, NT, +1>(s, twf, opaque_tid());
   const int L = g.L, s0 = g.s0;
   for (int e = threadIdx.x; e < C * L; e += NT) {
     const int i = e / C, c = e % C;
-    if (in_band(kx0 + c, g.kxlo, g.kxhi)) V[(size_t)i * NP + a0 + c] = s[pidx((s0 + i) * C + c)];
+    const int kx = kx0 + c;
+    if (in_band(kx, g.kxlo, g.kxhi)) V[(size_t)i * NPF + kx + NPF / 2] = s[pidx((s0 + i) * C + c)];
   }
 }
 
@@ -413,7 +436,7 @@ k_t3_cols(const float2* __restrict__ T, float2* __restrict__ V, GridGeom g, Spec
     const int kx = kx0 + c;
     float2 x = czero();
     if (ky >= -NP / 2 && ky < NP / 2 && in_band(kx, g.kxlo, g.kxhi) && in_band(ky, g.kylo, g.kyhi)) {
-      const float2 h = transfer_at(sp, NP, kx, ky);
+      const float2 h = transfer_at(sp, g.Np, kx, ky);
       const float dy = sp.dinv[ky + NP / 2];
       x = cmul(s[pidx(e)], h);
       x = cscale(x, dy * dy * sp.dinv[kx + NP / 2] * sp.scale);
@@ -542,19 +565,54 @@ hipError_t launch_t1_rows(int logNp, const float2* fine, float2* T, GridGeom g, 
   return hipGetLastError();
 }
 
-hipError_t launch_t1_cols(int logNp, const float2* T, float2* V, GridGeom g, Spectral sp,
-                          const float2* tw, hipStream_t st) {
-#define CALL(LP)                                                                         \
-  {                                                                                      \
-    using Cfg = ColCfg<LP + 1>;                                                          \
-    hipError_t e = set_lds(k_t1_cols<LP>, Cfg::LDS);                                     \
-    if (e != hipSuccess) return e;                                                       \
-    const int grid = (1 << LP) / Cfg::C;                                                 \
-    hipLaunchKernelGGL(k_t1_cols<LP>, dim3(grid), dim3(Cfg::NT), Cfg::LDS, st, T, V, g, sp, tw); \
+// Column passes: the spectral grid N'' = 2^logNpf may be N', N'/2, N'/4 or
+// N'/8 (at least 32).
+template <int LPF, int LP>
+static hipError_t t1_cols_at(const float2* T, float2* V, const GridGeom& g, const Spectral& sp, const float2* tw,
+                             hipStream_t st) {
+  using Cfg = Col2Cfg<LPF + 1, LP>;
+  hipError_t e = set_lds(k_t1_cols<LPF, LP>, Cfg::LDS);
+  if (e != hipSuccess) return e;
+  const int grid = (1 << LPF) / Cfg::C;
+  hipLaunchKernelGGL((k_t1_cols<LPF, LP>), dim3(grid), dim3(Cfg::NT), Cfg::LDS, st, T, V, g, sp, tw);
+  return hipGetLastError();
+}
+
+template <int LPF, int LP>
+static hipError_t t2_cols_at(const float2* T, float2* V, const GridGeom& g, const Spectral& sp, const float2* tw,
+                             hipStream_t st) {
+  using Cfg = Col2Cfg<LP, LPF + 1>;
+  hipError_t e = set_lds(k_t2_cols<LPF, LP>, Cfg::LDS);
+  if (e != hipSuccess) return e;
+  const int grid = (1 << LP) / Cfg::C;
+  hipLaunchKernelGGL((k_t2_cols<LPF, LP>), dim3(grid), dim3(Cfg::NT), Cfg::LDS, st, T, V, g, sp, tw);
+  return hipGetLastError();
+}
+
+template <int LP, bool T1>
+static hipError_t cols_by_reduction(int d, const float2* T, float2* V, const GridGeom& g, const Spectral& sp,
+                                    const float2* tw, hipStream_t st) {
+#define NUASM_COLS_AT(D)                                                    \
+  if constexpr (LP - D >= 5) {                                              \
+    if (d == D)                                                             \
+      return T1 ? t1_cols_at<LP - D, LP>(T, V, g, sp, tw, st)               \
+                : t2_cols_at<LP - D, LP>(T, V, g, sp, tw, st);              \
   }
+  NUASM_COLS_AT(0)
+  NUASM_COLS_AT(1)
+  NUASM_COLS_AT(2)
+  NUASM_COLS_AT(3)
+#undef NUASM_COLS_AT
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_t1_cols(int logNpf, int logNp, const float2* T, float2* V, GridGeom g, Spectral sp,
+                          const float2* tw, hipStream_t st) {
+  const int d = logNp - logNpf;
+#define CALL(LP) return cols_by_reduction<LP, true>(d, T, V, g, sp, tw, st)
   NUASM_DISPATCH_NP(logNp, CALL)
 #undef CALL
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_t1_rows_inv(int logNp, const float2* V, float2* out, GridGeom g, const float2* tw,
@@ -588,19 +646,13 @@ hipError_t launch_t2_rows(int logNp, const float2* u1, float2* T, GridGeom g, co
   return hipGetLastError();
 }
 
-hipError_t launch_t2_cols(int logNp, const float2* T, float2* V, GridGeom g, Spectral sp,
+hipError_t launch_t2_cols(int logNpf, int logNp, const float2* T, float2* V, GridGeom g, Spectral sp,
                           const float2* tw, hipStream_t st) {
-#define CALL(LP)                                                                         \
-  {                                                                                      \
-    using Cfg = ColCfg<LP + 1>;                                                          \
-    hipError_t e = set_lds(k_t2_cols<LP>, Cfg::LDS);                                     \
-    if (e != hipSuccess) return e;                                                       \
-    const int grid = (1 << LP) / Cfg::C;                                                 \
-    hipLaunchKernelGGL(k_t2_cols<LP>, dim3(grid), dim3(Cfg::NT), Cfg::LDS, st, T, V, g, sp, tw); \
-  }
+  const int d = logNp - logNpf;
+#define CALL(LP) return cols_by_reduction<LP, false>(d, T, V, g, sp, tw, st)
   NUASM_DISPATCH_NP(logNp, CALL)
 #undef CALL
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_t2_rows_inv(int logNp, const float2* V, float2* fine, GridGeom g, const float2* tw,

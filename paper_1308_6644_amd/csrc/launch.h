@@ -22,8 +22,9 @@ constexpr int kMaxW = 16;
 
 // Geometry of the fine-grid support and of the uniform planes.
 struct GridGeom {
-  int N, Np, nf;   // plane side, N' = 2N, fine grid 2N'
-  int L, s0;       // support side N' + 2*kPad, first support row/column in the fine grid
+  int N, Np, nf;   // plane side, N' = 2N, fine grid nf = 2 N''
+  int Npf;         // spectral grid N'': N', or a power of two >= 32 covering the band of Eq. 4
+  int L, s0;       // support side N'' + 2*kPad, first support row/column in the fine grid
   int kxlo, kxhi;  // inclusive band of Eq. 4, index units
   int kylo, kyhi;
   int Nin;         // side of the uniform input of the type-2 pipeline (N, or N' for the type-1 adjoint)
@@ -138,16 +139,17 @@ hipError_t launch_grid_interp(int w, const float2* fine, float2* R, float2* out,
 hipError_t launch_grid_spread(int w, const float2* vals, float2* S, float2* fine, const GridPts& p, hipStream_t st);
 
 // type-1 pipeline: fine support (L x L) -> rows -> fused columns -> rows -> plane
+// (row passes over the fine grid take log2 N'', the column pass both sizes)
 hipError_t launch_t1_rows(int logNp, const float2* fine, float2* T, GridGeom g, const float* dinv,
                           const float2* tw, hipStream_t st);
-hipError_t launch_t1_cols(int logNp, const float2* T, float2* V, GridGeom g, Spectral sp,
+hipError_t launch_t1_cols(int logNpf, int logNp, const float2* T, float2* V, GridGeom g, Spectral sp,
                           const float2* tw, hipStream_t st);
 hipError_t launch_t1_rows_inv(int logNp, const float2* V, float2* out, GridGeom g, const float2* tw,
                               hipStream_t st);
 // type-2 pipeline: plane (Nin x Nin) -> rows -> fused columns -> fine rows (L x L)
 hipError_t launch_t2_rows(int logNp, const float2* u1, float2* T, GridGeom g, const float* dinv,
                           const float2* tw, hipStream_t st);
-hipError_t launch_t2_cols(int logNp, const float2* T, float2* V, GridGeom g, Spectral sp,
+hipError_t launch_t2_cols(int logNpf, int logNp, const float2* T, float2* V, GridGeom g, Spectral sp,
                           const float2* tw, hipStream_t st);
 hipError_t launch_t2_rows_inv(int logNp, const float2* V, float2* fine, GridGeom g, const float2* tw,
                               hipStream_t st);

@@ -197,6 +197,7 @@ struct nuasm_plan_s {
   hipStream_t stream = nullptr;
   int device = 0;
   int logNp = 0;
+  int logNpf = 0;  // spectral grid N'' (the fine grid is 2 N'')
   int w = 0;
   float beta = 0.f;
   GridGeom geom{};
@@ -207,7 +208,9 @@ struct nuasm_plan_s {
   // device memory
   float2* gridA = nullptr;
   float2* gridB = nullptr;
-  float* dinv = nullptr;
+  float* dinv = nullptr;     // 1/psihat(k), k in K'' (N'' entries)
+  float* dinv_np = nullptr;  // the same at column k + N'/2 of an N'-wide row (zero outside K''),
+                             // for the type-2 row pass; == dinv when N'' = N'
   float2* fre = nullptr;  // [2][Np]
   // point sets: [0] the plan's points (type 3: the source), [1] type 3's destination
   PointSet ps[2];
@@ -246,6 +249,7 @@ void release(nuasm_plan_s* pl) {
   };
   f(pl->gridA);
   f(pl->gridB);
+  if (pl->dinv_np != pl->dinv) f(pl->dinv_np);
   f(pl->dinv);
   f(pl->fre);
   for (PointSet& q : pl->ps) {
@@ -330,7 +334,8 @@ nuasm_status validate(const nuasm_params* p) {
     return fail(NUASM_ERR_INVALID_ARG, "NUASM_OUT_CROP_N applies to type 1 only");
   if (p->tf == NUASM_TF_FRESNEL && p->z == 0.0) return fail(NUASM_ERR_INVALID_ARG, "Fresnel needs z != 0");
   if (!(p->tol >= 1e-12 && p->tol <= 1e-2)) return fail(NUASM_ERR_INVALID_ARG, "tol must be in [1e-12, 1e-2]");
-  if (p->flags & ~(NUASM_OUT_CROP_N | NUASM_DEFER_RANGE_CHECK)) return fail(NUASM_ERR_INVALID_ARG, "unknown flag bits");
+  if (p->flags & ~(NUASM_OUT_CROP_N | NUASM_DEFER_RANGE_CHECK | NUASM_FULL_FINE_GRID))
+    return fail(NUASM_ERR_INVALID_ARG, "unknown flag bits");
   if (p->reserved != 0) return fail(NUASM_ERR_INVALID_ARG, "reserved must be 0");
   if (p->band == NUASM_BAND_EXPLICIT) {
     for (int i = 0; i < 2; ++i)
@@ -503,9 +508,9 @@ nuasm_status bind_grid(nuasm_plan_s* pl, PointSet& q, int64_t nx, int64_t ny, do
   p.pitch = pitch;
   p.cx = cx;
   p.cy = cy;
-  p.inv_g = 1.0 / g;
-  p.half_n = 0.5 * (double)pl->geom.N;
-  p.tau0 = (double)(pl->geom.N + kPad);
+  p.inv_g = pl->bgeom.inv_g;
+  p.half_n = pl->bgeom.half_n;
+  p.tau0 = pl->bgeom.tau0;
   p.L = pl->geom.L;
   p.two_over_w = 2.0f / (float)pl->w;
   p.beta_log2e = pl->beta * 1.4426950408889634f;
@@ -515,7 +520,7 @@ nuasm_status bind_grid(nuasm_plan_s* pl, PointSet& q, int64_t nx, int64_t ny, do
   p.nrows = 0;
   if (nx > 0 && ny > 0) {
     auto tap = [&](int64_t k) {
-      const double t = 2.0 * ((cy + (double)(k - ny / 2) * pitch) / g) + p.tau0;
+      const double t = 2.0 * ((cy + (double)(k - ny / 2) * pitch) * p.inv_g) + p.tau0;
       return (int)std::ceil(t - 0.5 * pl->w);
     };
     const int lo = std::max(0, tap(0) - 2);
@@ -617,11 +622,11 @@ nuasm_status run_type1_pipeline(nuasm_plan_s* pl, PointSet& q, const float2* val
   sp.conj = conj ? 1 : 0;
   {
     StageScope sc(pl, NUASM_STAGE_T1_ROWS);
-    HIP_TRY(launch_t1_rows(pl->logNp, pl->gridA, pl->gridB, g, pl->dinv, pl->tw, st), "launch t1_rows");
+    HIP_TRY(launch_t1_rows(pl->logNpf, pl->gridA, pl->gridB, g, pl->dinv, pl->tw, st), "launch t1_rows");
   }
   {
     StageScope sc(pl, NUASM_STAGE_T1_COLS);
-    HIP_TRY(launch_t1_cols(pl->logNp, pl->gridB, pl->gridA, g, sp, pl->tw, st), "launch t1_cols");
+    HIP_TRY(launch_t1_cols(pl->logNpf, pl->logNp, pl->gridB, pl->gridA, g, sp, pl->tw, st), "launch t1_cols");
   }
   {
     StageScope sc(pl, NUASM_STAGE_T1_ROWS_INV);
@@ -641,15 +646,15 @@ nuasm_status run_type2_pipeline(nuasm_plan_s* pl, PointSet& q, const float2* pla
   sp.conj = conj ? 1 : 0;
   {
     StageScope sc(pl, NUASM_STAGE_T2_ROWS);
-    HIP_TRY(launch_t2_rows(pl->logNp, plane, pl->gridB, g, pl->dinv, pl->tw, st), "launch t2_rows");
+    HIP_TRY(launch_t2_rows(pl->logNp, plane, pl->gridB, g, pl->dinv_np, pl->tw, st), "launch t2_rows");
   }
   {
     StageScope sc(pl, NUASM_STAGE_T2_COLS);
-    HIP_TRY(launch_t2_cols(pl->logNp, pl->gridB, pl->gridA, g, sp, pl->tw, st), "launch t2_cols");
+    HIP_TRY(launch_t2_cols(pl->logNpf, pl->logNp, pl->gridB, pl->gridA, g, sp, pl->tw, st), "launch t2_cols");
   }
   {
     StageScope sc(pl, NUASM_STAGE_T2_ROWS_INV);
-    HIP_TRY(launch_t2_rows_inv(pl->logNp, pl->gridA, pl->gridB, g, pl->tw, st), "launch t2_rows_inv");
+    HIP_TRY(launch_t2_rows_inv(pl->logNpf, pl->gridA, pl->gridB, g, pl->tw, st), "launch t2_rows_inv");
   }
   return run_interp(pl, q, pl->gridB, out);
 }
@@ -669,15 +674,15 @@ nuasm_status run_type3_pipeline(nuasm_plan_s* pl, PointSet& src, PointSet& dst, 
   sp.conj = conj ? 1 : 0;
   {
     StageScope sc(pl, NUASM_STAGE_T1_ROWS);
-    HIP_TRY(launch_t1_rows(pl->logNp, pl->gridA, pl->gridB, g, pl->dinv, pl->tw, st), "launch t1_rows");
+    HIP_TRY(launch_t1_rows(pl->logNpf, pl->gridA, pl->gridB, g, pl->dinv, pl->tw, st), "launch t1_rows");
   }
   {
     StageScope sc(pl, NUASM_STAGE_T3_COLS);
-    HIP_TRY(launch_t3_cols(pl->logNp, pl->gridB, pl->gridA, g, sp, pl->tw, st), "launch t3_cols");
+    HIP_TRY(launch_t3_cols(pl->logNpf, pl->gridB, pl->gridA, g, sp, pl->tw, st), "launch t3_cols");
   }
   {
     StageScope sc(pl, NUASM_STAGE_T2_ROWS_INV);
-    HIP_TRY(launch_t2_rows_inv(pl->logNp, pl->gridA, pl->gridB, g, pl->tw, st), "launch t2_rows_inv");
+    HIP_TRY(launch_t2_rows_inv(pl->logNpf, pl->gridA, pl->gridB, g, pl->tw, st), "launch t2_rows_inv");
   }
   return run_interp(pl, dst, pl->gridB, out);
 }
@@ -740,7 +745,7 @@ nuasm_status nuasm_plan_create(const nuasm_params* p, void* hip_stream, nuasm_pl
     return st;
   };
   if (hipGetDevice(&pl->device) != hipSuccess) return bail(fail(NUASM_ERR_HIP, "hipGetDevice failed"));
-  const int N = (int)p->N, Np = 2 * N, nf = 2 * Np;
+  const int N = (int)p->N, Np = 2 * N;
   int logNp = 0;
   while ((1 << logNp) < Np) ++logNp;
   pl->logNp = logNp;
@@ -751,16 +756,9 @@ nuasm_status nuasm_plan_create(const nuasm_params* p, void* hip_stream, nuasm_pl
   w = std::max(2, std::min(kMaxW, w));
   pl->w = w;
   pl->beta = (float)(2.30 * w);
-  const int L = Np + 2 * kPad;
-  pl->TX = (L + kTile - 1) / kTile;
-  pl->T = pl->TX * pl->TX;
-
   GridGeom& G = pl->geom;
   G.N = N;
   G.Np = Np;
-  G.nf = nf;
-  G.L = L;
-  G.s0 = Np / 2 - kPad;
   G.Nin = N;
   G.crop = (p->flags & NUASM_OUT_CROP_N) ? 1 : 0;
   const int kmin = -Np / 2, kmax = Np / 2 - 1;
@@ -781,11 +779,38 @@ nuasm_status nuasm_plan_create(const nuasm_params* p, void* hip_stream, nuasm_pl
     G.kyhi = b[3];
   }
 
+  // Spectral grid N'': the smallest power of two (>= 32, >= N'/8) whose index
+  // set K'' = [-N''/2, N''/2) holds the band of Eq. 4 on both axes; N' for a
+  // full band, for Fresnel, or with NUASM_FULL_FINE_GRID.  The non-uniform
+  // sums keep their accuracy on the smaller fine grid 2 N'' (same
+  // oversampling, same kernel) because no mode outside the band is needed;
+  // the fine cells become N'/N'' times wider.
+  {
+    int need = 0;
+    if (G.kxlo <= G.kxhi && G.kylo <= G.kyhi)
+      need = 2 * std::max(std::max(-G.kxlo, G.kxhi + 1), std::max(-G.kylo, G.kyhi + 1));
+    int lpf = 5;
+    while ((1 << lpf) < need) ++lpf;
+    lpf = std::max(lpf, logNp - 3);
+    if (lpf > logNp || (p->flags & NUASM_FULL_FINE_GRID)) lpf = logNp;
+    pl->logNpf = lpf;
+  }
+  const int Npf = 1 << pl->logNpf, nf = 2 * Npf;
+  const int L = Npf + 2 * kPad;
+  pl->TX = (L + kTile - 1) / kTile;
+  pl->T = pl->TX * pl->TX;
+  G.Npf = Npf;
+  G.nf = nf;
+  G.L = L;
+  G.s0 = Npf / 2 - kPad;
+
+  // the non-uniform plane in fine-cell units: N'' / 2 cells of N'/N'' pixels
+  // across the window, pixel 0 of that coarser raster at support cell N''/2 + 8
   BinGeom& B = pl->bgeom;
-  B.N = N;
-  B.inv_g = 1.0 / g;
-  B.half_n = 0.5 * N;
-  B.tau0 = (double)(N + kPad);
+  B.N = Npf / 2;
+  B.inv_g = (double)Npf / ((double)Np * g);
+  B.half_n = 0.25 * Npf;
+  B.tau0 = (double)(Npf / 2 + kPad);
   B.w = w;
   B.L = L;
   B.TX = pl->TX;
@@ -811,20 +836,32 @@ nuasm_status nuasm_plan_create(const nuasm_params* p, void* hip_stream, nuasm_pl
 
   s = twiddles_for_device(pl->device, &pl->tw);
   if (s != NUASM_OK) return bail(s);
-  pl->grid_elems = (int64_t)L * L;
+  // the fine support, and the N' x N' intermediates of the column passes
+  pl->grid_elems = std::max<int64_t>((int64_t)L * L, (int64_t)Np * Np);
   hipError_t e;
   if ((e = dalloc(pl, &pl->gridA, (size_t)pl->grid_elems)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(gridA)"));
   if ((e = dalloc(pl, &pl->gridB, (size_t)pl->grid_elems)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(gridB)"));
-  if ((e = dalloc(pl, &pl->dinv, (size_t)Np)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(dinv)"));
+  if ((e = dalloc(pl, &pl->dinv, (size_t)Npf)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(dinv)"));
+  pl->dinv_np = pl->dinv;
+  if (Npf != Np && (e = dalloc(pl, &pl->dinv_np, (size_t)Np)) != hipSuccess)
+    return bail(hip_fail(e, "hipMalloc(dinv)"));
   pl->nsets = p->type == NUASM_TYPE_3 ? 2 : 1;
   for (int i = 0; i < pl->nsets; ++i) {
     s = alloc_point_set(pl, pl->ps[i]);
     if (s != NUASM_OK) return bail(s);
   }
   {
-    std::vector<float> dv = deconvolution_table(Np, nf, w, (double)pl->beta);
-    if ((e = hipMemcpyAsync(pl->dinv, dv.data(), sizeof(float) * Np, hipMemcpyHostToDevice, pl->stream)) != hipSuccess)
+    std::vector<float> dv = deconvolution_table(Npf, nf, w, (double)pl->beta);
+    if ((e = hipMemcpyAsync(pl->dinv, dv.data(), sizeof(float) * Npf, hipMemcpyHostToDevice, pl->stream)) != hipSuccess)
       return bail(hip_fail(e, "hipMemcpy(dinv)"));
+    std::vector<float> dn;
+    if (Npf != Np) {
+      dn.assign(Np, 0.f);
+      for (int a = 0; a < Npf; ++a) dn[a - Npf / 2 + Np / 2] = dv[a];
+      if ((e = hipMemcpyAsync(pl->dinv_np, dn.data(), sizeof(float) * Np, hipMemcpyHostToDevice, pl->stream)) !=
+          hipSuccess)
+        return bail(hip_fail(e, "hipMemcpy(dinv)"));
+    }
     if ((e = hipStreamSynchronize(pl->stream)) != hipSuccess) return bail(hip_fail(e, "hipStreamSynchronize"));
   }
   S.dinv = pl->dinv;
@@ -892,6 +929,7 @@ nuasm_status nuasm_plan_get_info(nuasm_plan pl, nuasm_plan_info* info) {
   info->M = M;
   info->device_bytes = pl->bytes;
   info->M_dest = M2;
+  info->Npf = pl->geom.Npf;
   info->spread_chunk = pl->sp_chunk;
   info->interp_chunk = pl->ip_chunk;
   {

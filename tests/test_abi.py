@@ -76,6 +76,7 @@ def _create(P, p):
     ("d2", -1.0, "NUASM_ERR_INVALID_ARG"),
     ("tol", 0.5, "NUASM_ERR_INVALID_ARG"),
     ("flags", 0x80, "NUASM_ERR_INVALID_ARG"),
+    ("flags", 0x8, "NUASM_ERR_INVALID_ARG"),
     ("reserved", 1, "NUASM_ERR_INVALID_ARG"),
     ("phase_fp64", 2, "NUASM_ERR_INVALID_ARG"),
 ])
@@ -99,7 +100,7 @@ def test_plan_info_struct_layout_matches_header(P):
     # 4 x int64, 8 x int32/float, 3 x int64, size_t, int64, 4 x int32
     assert ctypes.sizeof(P.PlanInfo) == 4 * 8 + 8 * 4 + 3 * 8 + 8 + 8 + 4 * 4
     assert [f for f, _ in P.PlanInfo._fields_][-4:] == ["spread_chunk", "interp_chunk", "bin_range_points",
-                                                         "reserved"]
+                                                         "Npf"]
     assert ctypes.sizeof(P.Tuning) == 16
 
 
