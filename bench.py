@@ -504,6 +504,63 @@ def scaled_workload(a, torch, P, synth):
     return 0
 
 
+def precision_workload(a, torch, P, synth):
+    """NU-ASM_2 at N = 4096 (N' = 8192) with 2^24 destination points
+    (jittered pixel grid, 4x denser in a 512 x 512 region of interest),
+    532 nm, z = 1 m, band-limited ASM, FP64 phase, kernel tolerances 1e-3,
+    1e-6 and 1e-9: one-shot time (binning + execute) per tolerance, on the
+    band-adaptive fine grid (N'' = 2048 here) and on the full 2 N' grid.
+    value = points/s at tolerance 1e-6 on the band-adaptive grid."""
+    import numpy as np
+    Nc, Mc, lam, z = 4096, 1 << 24, 532e-9, 1.0
+    print(f"[bench] generating N={Nc} M={Mc}", file=sys.stderr, flush=True)
+    rng = synth.rng_for(3, 0)
+    x, y = synth.jittered_roi(rng, Nc, G, M=Mc)
+    u1 = synth.unit_phase(rng, (Nc, Nc))
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.from_numpy(y).cuda()
+    ud = torch.from_numpy(np.ascontiguousarray(u1)).cuda()
+    del x, y, u1
+    out = torch.empty(Mc, dtype=torch.complex64, device="cuda")
+    res = {}
+    for tol in (1e-3, 1e-6, 1e-9):
+        for full in (False, True):
+            plan = P.Plan(Nc, 2, lam, z, G, tf="asm", band="limited", tol=tol, defer_range_check=True,
+                          full_fine_grid=full)
+
+            def step(plan=plan):
+                plan.set_points(xd, yd)
+                plan.execute(ud, out)
+            for _ in range(max(1, a.warmup)):
+                step()
+            torch.cuda.synchronize()
+            plan.check_points()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = max(3, a.steps // 4)
+            e0.record()
+            for _ in range(reps):
+                step()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            res[f"tol{tol:g}_{'full' if full else 'band'}"] = {"ms": ms, "points_per_s": Mc / (ms * 1e-3),
+                                                              "Npf": plan.info["Npf"], "w": plan.info["w"]}
+            print(f"[bench] tol {tol:g} {'full' if full else 'band'} grid: {ms:.3f} ms", file=sys.stderr, flush=True)
+            del plan
+    main_ = res["tol1e-06_band"]
+    line = {
+        "metric": "non-uniform pts/sec NUASM_2 at N'=8192, M=16M, z=1 m (precision-sweep configuration)",
+        "value": main_["points_per_s"], "unit": "points/s", "n_gpus": 1, "steps": max(3, a.steps // 4),
+        "warmup": a.warmup, "ms_per_step": main_["ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "NU-ASM_2 one-shot, N=4096 (N'=8192), 2^24 jittered points with a 4x denser "
+                               "512x512 ROI, 532 nm, 4 um, z = 1 m, band-limited ASM, FP64 phase",
+                   "runs": res},
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -514,11 +571,13 @@ def main(argv=None):
     ap.add_argument("--mode", choices=("graph", "sequential"), default="graph",
                     help="graph: the 12 runs of a step recorded as one HIP graph on parallel branches; "
                          "sequential: plain plans one after another on one stream")
-    ap.add_argument("--workload", choices=("n2048", "batched", "nuasm3", "paper", "scaled"), default="n2048",
+    ap.add_argument("--workload", choices=("n2048", "batched", "nuasm3", "paper", "scaled", "precision"),
+                    default="n2048",
                     help="n2048: the 12-run N'=2048 headline workload; batched: 64 mixed planes; "
                          "nuasm3: NU-ASM_3 with 2^20 source and 2^20 destination points, 6 runs; "
                          "paper: the paper's 256 x 256 experiment against Rayleigh-Sommerfeld; "
-                         "scaled: a 2x zoom to a 2048 x 2048 destination grid")
+                         "scaled: a 2x zoom to a 2048 x 2048 destination grid; precision: NU-ASM_2 at "
+                         "N'=8192, M=2^24, z=1 m on the band-adaptive and the full fine grid")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (3 times), the "
                          "reference for the FETCH_SIZE / WRITE_SIZE counters, and exit")
@@ -553,6 +612,8 @@ def main(argv=None):
         return paper_workload(a, torch, P, synth)
     if a.workload == "scaled":
         return scaled_workload(a, torch, P, synth)
+    if a.workload == "precision":
+        return precision_workload(a, torch, P, synth)
     print(f"[bench] generating inputs N={N} M={M}", file=sys.stderr, flush=True)
     host, d = make_inputs(torch, synth)
     if a.workload == "nuasm3":
