@@ -5,9 +5,12 @@
 //
 // Index conventions (centred, as in Eqs. 3, 6 and 9): a plane element [b][a]
 // of an N' x N' array holds n = (a - N'/2, b - N'/2); frequency k = a - N'/2.
-// The fine grid of the non-uniform sums has nf = 2 N' cells per axis; the
-// non-uniform window occupies fine cells [N'/2, 3N'/2), and only the support
-// rows/columns [s0, s0 + L), L = N' + 16, are ever stored.
+// The non-uniform sums run on the spectral grid K'' of N'' modes (N'' = N',
+// or smaller when the band of Eq. 4 is narrow) and a fine grid of nf = 2 N''
+// cells per axis; the non-uniform window occupies fine cells
+// [N''/2, 3N''/2), and only the support rows/columns [s0, s0 + L),
+// L = N'' + 16, are ever stored.  Row passes over the fine grid are
+// instantiated at N''; the column passes go between N'' and N'.
 #include "launch.h"
 
 namespace nuasm {

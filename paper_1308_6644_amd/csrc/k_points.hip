@@ -3,8 +3,10 @@
 // spreading (gridding of the type-1 sum, Eq. 7) and LDS-tiled interpolation
 // (the type-2 sum, Eq. 8).
 //
-// Fine-grid coordinates: a point at x metres sits at tau = 2 x / g + N + 8 in
-// support cells (pixel 0 at support cell N + 8; two fine cells per pixel).
+// Fine-grid coordinates: the window is N''/2 cells of pitch g N'/N'' (the
+// plan's pixels when N'' = N'), two fine cells each, and a point at x metres
+// sits at tau = 2 x inv_g + tau0 support cells (tau0 = N''/2 + 8: that
+// raster's pixel 0; BinGeom holds inv_g and tau0).
 // Its w taps are the cells i0 .. i0 + w - 1, i0 = ceil(tau - w/2).  The
 // support is cut into 32 x 32 bins; a point is recorded in every bin its taps
 // touch (at most 4), flagged "primary" in the bin holding its first tap.

@@ -47,11 +47,13 @@ struct Spectral {
   const float* dinv;    // 1 / psihat(k), index k + N'/2
 };
 
+// The non-uniform plane in fine-grid units: N''/2 raster pixels of pitch
+// g N'/N'' across the window (the plan's own pixels when N'' = N').
 struct BinGeom {
-  int N;            // plane side
-  double inv_g;     // 1 / pitch
-  double half_n;    // N / 2 (range check, pixels)
-  double tau0;      // support coordinate of pixel 0: N + kPad
+  int N;            // raster pixels across the window, N''/2
+  double inv_g;     // 1 / raster pitch, N'' / (N' g)
+  double half_n;    // N''/4: the window's half-width in raster pixels (range check)
+  double tau0;      // support coordinate of raster pixel 0: N''/2 + kPad
   int w;            // kernel width
   int L;            // support side
   int TX;           // bins per axis
@@ -105,15 +107,15 @@ struct InterpArgs {
 // A non-uniform plane that is a uniform grid (scaled diffraction): nx x ny
 // points, point [b][a] at (cx + (a - nx/2) pitch, cy + (b - ny/2) pitch)
 // metres (integer division).  Its fine-grid taps follow the same rule as a
-// binned point's (pixel 0 at support cell N + 8, two cells per pixel, first
-// tap ceil(tau - w/2)), so the separable kernels below apply the weights the
-// generic spreading and interpolation would.
+// binned point's (tau = 2 x inv_g + tau0 as in BinGeom, first tap
+// ceil(tau - w/2)), so the separable kernels apply the weights the generic
+// spreading and interpolation would.
 struct GridPts {
   int nx, ny;
   double pitch, cx, cy;
-  double inv_g;     // 1 / pitch of the plan's uniform plane
-  double half_n;    // N / 2 (pixels)
-  double tau0;      // support coordinate of pixel 0: N + kPad
+  double inv_g;     // as BinGeom
+  double half_n;
+  double tau0;
   int L;            // support side
   float two_over_w, beta_log2e;
   int ty0, nrows;   // support rows the interpolation's x pass produces
