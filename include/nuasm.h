@@ -153,7 +153,11 @@ nuasm_status nuasm_plan_create(const nuasm_params* p, void* hip_stream, nuasm_pl
  * stream first. */
 nuasm_status nuasm_plan_destroy(nuasm_plan plan);
 
-/* Change the stream later calls are enqueued on (borrowed). */
+/* Change the stream later calls are enqueued on (borrowed).  Work the plan
+ * has already enqueued on its previous stream (plan tables, a binning, an
+ * execute) is ordered before anything later enqueued on the new one: an event
+ * recorded on the old stream is waited on by the new stream, without blocking
+ * the host.  The previous stream must still be valid when this is called. */
 nuasm_status nuasm_plan_set_stream(nuasm_plan plan, void* hip_stream);
 
 nuasm_status nuasm_plan_get_info(nuasm_plan plan, nuasm_plan_info* info);

@@ -195,6 +195,7 @@ struct PointSet {
 struct nuasm_plan_s {
   nuasm_params p{};
   hipStream_t stream = nullptr;
+  hipEvent_t handoff = nullptr;  // orders a new stream after the previous one
   int device = 0;
   int logNp = 0;
   int logNpf = 0;  // spectral grid N'' (the fine grid is 2 N'')
@@ -269,6 +270,8 @@ void release(nuasm_plan_s* pl) {
     if (q.host_stat) (void)hipHostFree(q.host_stat);
     q = PointSet{};
   }
+  if (pl->handoff) (void)hipEventDestroy(pl->handoff);
+  pl->handoff = nullptr;
   for (hipEvent_t e : pl->ev_pool) (void)hipEventDestroy(e);
   for (hipEvent_t e : pl->ev_pairs) (void)hipEventDestroy(e);
   pl->ev_pool.clear();
@@ -895,7 +898,14 @@ nuasm_status nuasm_plan_destroy(nuasm_plan pl) {
 
 nuasm_status nuasm_plan_set_stream(nuasm_plan pl, void* hip_stream) {
   if (!pl) return fail(NUASM_ERR_INVALID_ARG, "plan is NULL");
-  pl->stream = (hipStream_t)hip_stream;
+  const hipStream_t ns = (hipStream_t)hip_stream;
+  if (ns == pl->stream) return NUASM_OK;
+  // what the plan enqueued on the old stream (its tables, a binning) must
+  // finish before the new stream's work reads it
+  if (!pl->handoff) HIP_TRY(hipEventCreateWithFlags(&pl->handoff, hipEventDisableTiming), "hipEventCreate");
+  HIP_TRY(hipEventRecord(pl->handoff, pl->stream), "hipEventRecord");
+  HIP_TRY(hipStreamWaitEvent(ns, pl->handoff, 0), "hipStreamWaitEvent");
+  pl->stream = ns;
   return NUASM_OK;
 }
 
@@ -956,12 +966,12 @@ nuasm_status nuasm_plan_set_tuning(nuasm_plan pl, const nuasm_tuning* t) {
   pl->ip_chunk = t->interp_chunk != 0 ? t->interp_chunk : kChunk;
   pl->bin_ppw = t->bin_range_points;
   // binned point sets must be bound again (their chunk tables and histogram
-  // rows follow the old sizes); grids need no tables
+  // rows follow the old sizes); a set bound as a grid stays ready, but its
+  // buffers are resized too at its next binning
   for (int i = 0; i < pl->nsets; ++i) {
     PointSet& q = pl->ps[i];
-    if (q.grid) continue;
-    q.ready = false;
     q.rec_cap = 0;
+    if (!q.grid) q.ready = false;
   }
   return NUASM_OK;
 }

@@ -272,8 +272,9 @@ def test_crop_output(P):
 
 
 def test_repeated_execute_is_stable(P):
-    """Spreading accumulates with LDS float atomics, so sums may reorder
-    between runs; repeated runs must agree to float32 rounding."""
+    """The counting sorts rank records with LDS atomics, so the order in
+    which a cell's contributions are summed may change between runs;
+    repeated runs must agree to float32 rounding."""
     _say("repeat")
     geo = geometry(N=128, g=4e-6, lam=633e-9, z=0.05, tf="asm", band="limited")
     x, y, rng = _points("clustered", 4, 50000, 128, geo.g)
@@ -284,6 +285,31 @@ def test_repeated_execute_is_stable(P):
     for _ in range(5):
         assert rel_l2(host(p.execute(c)), a) <= 1e-6
 
+
+
+def test_stream_change_orders_after_previous_work(P):
+    """Points bound on one stream, the operator run on another with no host
+    synchronisation in between: the plan orders the new stream after the
+    old one, so the result is the oracle's."""
+    _say("stream handoff")
+    geo = geometry(N=128, g=4e-6, lam=633e-9, z=0.05, tf="asm", band="limited")
+    x, y, rng = _points("clustered", 6, 200000, 128, geo.g)
+    xs, ys = dev(torch, x), dev(torch, y)
+    sub = 4000
+    c = synth.unit_phase(rng, 200000)
+    c[sub:] = 0
+    ref = O.nuasm1(geo, x[:sub], y[:sub], c[:sub])
+    cd = dev(torch, c)
+    p = make_plan(P, geo, 1, defer_range_check=True)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s1):
+        p.set_points(xs, ys)
+    with torch.cuda.stream(s2):
+        out = p.execute(cd)
+        got = out.cpu()
+    torch.cuda.synchronize()
+    assert rel_l2(got.numpy(), ref) <= 1e-5
 
 def test_stage_timing_counts_every_kernel(P):
     """Stage timing records one (start, end) pair per launch on the plan's

@@ -84,6 +84,29 @@ def test_set_tuning_requires_rebinding(P):
     plan.execute(dev(torch, synth.unit_phase(rng, 100)))
 
 
+
+def test_tuning_while_grid_bound_resizes_tables(P):
+    """A point set bound as a grid across a tuning change keeps buffers sized
+    for the old chunk sizes; binning points into it again afterwards, with
+    fewer points than it held before and much smaller chunks, must resize its
+    chunk tables and histogram rows and give the oracle's result."""
+    N = 64
+    geo = geometry(N=N, g=4e-6, lam=633e-9, z=0.01, tf="asm", band="limited", ox=1e-4)
+    rng = np.random.default_rng(29)
+    x0, y0 = synth.uniform_box(rng, 20000, N * geo.g)
+    x, y = synth.clustered_box(rng, 12000, N * geo.g, frac=0.9, sigma_frac=0.03)
+    c = synth.unit_phase(rng, 12000)
+    u1 = synth.unit_phase(rng, (N, N))
+    for t, inp, ref in ((1, c, O.nuasm1(geo, x, y, c)), (2, u1, O.nuasm2(geo, u1, x, y))):
+        _say("tuning while grid-bound, type", t)
+        plan = make_plan(P, geo, t)
+        plan.set_points(dev(torch, x0), dev(torch, y0))
+        plan.set_grid_points(16, 16, geo.g)
+        plan.set_tuning(spread_chunk=896, interp_chunk=256, bin_range_points=1024)
+        plan.set_points(dev(torch, x), dev(torch, y))
+        assert plan.info["interp_chunk"] == 256
+        assert rel_l2(host(plan.execute(dev(torch, inp))), ref) <= 1e-5
+
 def test_autotuner_batch(P, tmp_path):
     """Tune a small mixed batch into a fresh cache, check the cache and the
     results against plain plans, then apply the cache to a new batch."""
