@@ -80,6 +80,16 @@ enum { NUASM_BAND_FULL = 0, NUASM_BAND_LIMITED = 1, NUASM_BAND_EXPLICIT = 2 };
 #define NUASM_DEFER_RANGE_CHECK 0x2u  /* set_points does not synchronise */
 #define NUASM_FULL_FINE_GRID    0x4u  /* keep the fine grid at 2 N' even when the
                                          band of Eq. 4 would allow a smaller one */
+#define NUASM_DETERMINISTIC     0x8u  /* bitwise-reproducible results: after binning,
+                                         the records of every bin are sorted by
+                                         (first-tap cell, point index), so every
+                                         sum runs in one order on every run, in
+                                         every plan and batch.  Costs one sort
+                                         launch per binning and 2 x 64 B of extra
+                                         workspace per point; a bin of 2^21
+                                         records or more is NUASM_ERR_UNSUPPORTED
+                                         (reported by set_points, or by
+                                         check_points when deferred) */
 
 typedef struct {
   int32_t type;        /* NUASM_TYPE_1, NUASM_TYPE_2 or NUASM_TYPE_3 */
@@ -224,6 +234,19 @@ nuasm_status nuasm_execute_adjoint(nuasm_plan plan, const void* in_dev, void* ou
  * it, H(k) of Eq. 4 or Eq. 5 times its Rect, as complex64 [N'][N'] centred
  * ([b][a] holds k = (a - N'/2, b - N'/2)), to out_dev.  For testing. */
 nuasm_status nuasm_debug_transfer(nuasm_plan plan, void* out_dev);
+
+/* Copy the records of a bound point set (which = 0; 1 for a type-3 plan's
+ * destination) in the order the point kernels read them, and the number of
+ * records of every bin, for testing.  recs_out_dev: device buffer of rec_cap
+ * 16-byte records {int32 packed: bits 0-7 and 8-15 the first tap's column and
+ * row relative to the bin origin (int8), bit 16 set in the bin that holds
+ * the first tap; float dx, dy: first tap minus the point, fine cells; int32
+ * the point's index}; bins are consecutive, row-major.  counts_out_dev:
+ * device int32[tiles] (nuasm_plan_info.tiles).  *n_records receives the total.
+ * Synchronises the plan's stream.  NUASM_ERR_NOT_READY unless the set holds
+ * binned points; NUASM_ERR_INVALID_ARG if rec_cap is below the total. */
+nuasm_status nuasm_debug_records(nuasm_plan plan, int32_t which, void* recs_out_dev, int64_t rec_cap,
+                                 int32_t* counts_out_dev, int64_t* n_records);
 
 /* Plain batched 1-D FFT with the library's Stockham kernels, for testing:
  * `batch` contiguous rows of length n (power of two, 32..16384), complex64,

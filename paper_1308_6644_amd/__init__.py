@@ -28,6 +28,7 @@ TF = {"asm": TF_ASM, "fresnel": TF_FRESNEL}
 OUT_CROP_N = 0x1
 DEFER_RANGE_CHECK = 0x2
 FULL_FINE_GRID = 0x4
+DETERMINISTIC = 0x8
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -95,6 +96,8 @@ _SIGS = {
     "nuasm_plan_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "nuasm_plan_read_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                               ctypes.POINTER(ctypes.c_int64)]),
+    "nuasm_debug_records": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
+                                            ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "nuasm_debug_fft": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_void_p]),
     "nuasm_batch_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(Params), ctypes.c_void_p,
@@ -157,7 +160,8 @@ def _dev_ptr(t: torch.Tensor, dtype, what: str) -> int:
 def make_params(N: int, type: int, lam: float, z: float, g: float, *, tf: str = "asm",
                 ox: float = 0.0, oy: float = 0.0, band: str = "full", band_c=(0.0, 0.0),
                 band_w=(0.0, 0.0), tol: float = 1e-6, phase_fp64: bool = True, crop: bool = False,
-                defer_range_check: bool = False, full_fine_grid: bool = False) -> Params:
+                defer_range_check: bool = False, full_fine_grid: bool = False,
+                deterministic: bool = False) -> Params:
     lib = load()
     p = Params()
     _check(lib.nuasm_params_default(ctypes.byref(p)))
@@ -174,7 +178,7 @@ def make_params(N: int, type: int, lam: float, z: float, g: float, *, tf: str = 
     p.band_w[0], p.band_w[1] = float(band_w[0]), float(band_w[1])
     p.tol = float(tol)
     p.flags = ((OUT_CROP_N if crop else 0) | (DEFER_RANGE_CHECK if defer_range_check else 0)
-               | (FULL_FINE_GRID if full_fine_grid else 0))
+               | (FULL_FINE_GRID if full_fine_grid else 0) | (DETERMINISTIC if deterministic else 0))
     return p
 
 
@@ -192,11 +196,12 @@ class Plan:
     def __init__(self, N: int, type: int, lam: float, z: float, g: float, *, tf: str = "asm",
                  ox: float = 0.0, oy: float = 0.0, band: str = "full", band_c=(0.0, 0.0),
                  band_w=(0.0, 0.0), tol: float = 1e-6, phase_fp64: bool = True, crop: bool = False,
-                 defer_range_check: bool = False, full_fine_grid: bool = False, device=None):
+                 defer_range_check: bool = False, full_fine_grid: bool = False,
+                 deterministic: bool = False, device=None):
         lib = load()
         p = make_params(N, type, lam, z, g, tf=tf, ox=ox, oy=oy, band=band, band_c=band_c, band_w=band_w,
                         tol=tol, phase_fp64=phase_fp64, crop=crop, defer_range_check=defer_range_check,
-                        full_fine_grid=full_fine_grid)
+                        full_fine_grid=full_fine_grid, deterministic=deterministic)
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self.params = p
         self.N, self.Np, self.type, self.crop = int(N), 2 * int(N), int(type), bool(crop)
@@ -267,6 +272,19 @@ class Plan:
 
     def check_points(self):
         _check(load().nuasm_check_points(self._h))
+
+    def debug_records(self, dest: bool = False):
+        """The bound point set's bin records in the order the point kernels
+        read them, as int32 [R][4] (packed, dx and dy as float32 bits, point
+        index), and the records per bin, int32 [tiles]."""
+        cap = 4 * max(1, self.M_dest if dest else self.M)
+        recs = torch.empty((cap, 4), dtype=torch.int32, device=self.device)
+        counts = torch.empty((self.info["tiles"],), dtype=torch.int32, device=self.device)
+        n = ctypes.c_int64()
+        self._sync_stream()
+        _check(load().nuasm_debug_records(self._h, 1 if dest else 0, ctypes.c_void_p(recs.data_ptr()), cap,
+                                          ctypes.c_void_p(counts.data_ptr()), ctypes.byref(n)))
+        return recs[:n.value], counts
 
     def set_tuning(self, spread_chunk: int = 0, interp_chunk: int = 0, bin_range_points: int = 0):
         """Launch-shape tuning (0 = default); binned points must be set again."""

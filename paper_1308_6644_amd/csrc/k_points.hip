@@ -232,6 +232,7 @@ __device__ __forceinline__ void bin_scan_body(const int* counts, int T, const Bi
     nch[2] = run[0];
     nch[3] = run[3];
     nch[4] = counts[T];
+    nch[kSortErr] = 0;  // set by k_bin_sort in deterministic mode
   }
 }
 
@@ -344,6 +345,63 @@ k_bin_scatter(const double* __restrict__ x, const double* __restrict__ y, int64_
   }
 }
 
+// Deterministic mode: the records of every bin sorted by (first-tap row,
+// first-tap column, point index), a total order, so that spreading sums every
+// cell in the same order on every run.  One workgroup per bin; a 64-bit key
+// holds the order and the record's position in the bin, sorted by a bitonic
+// network in LDS (bins of up to kSortLds records) or in the global key buffer
+// (larger bins; the bin starting at record c uses keys[2c, 2c + 2n)), then the
+// records are gathered in key order into `out`.  A bin of 2^21 records or more
+// does not fit the key and sets nch[kSortErr] (its records are copied
+// unsorted).
+constexpr int kSortThreads = 1024;
+constexpr int kSortLds = 8192;
+constexpr int kSortPosBits = 21;
+
+__device__ __forceinline__ uint64_t det_key(const BinRec& r, int pos) {
+  const uint64_t cell = (uint64_t)(((rec_ly(r.packed) + 16) << 6) | (rec_lx(r.packed) + 16));  // 12 bits
+  return (cell << 52) | ((uint64_t)(uint32_t)r.idx << kSortPosBits) | (uint64_t)pos;
+}
+
+__device__ __forceinline__ void bitonic_sort(uint64_t* k, int np) {
+  for (int kk = 2; kk <= np; kk <<= 1)
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < np; i += kSortThreads) {
+        const int l = i ^ j;
+        if (l > i) {
+          const uint64_t a = k[i], c = k[l];
+          if ((a > c) == ((i & kk) == 0)) {
+            k[i] = c;
+            k[l] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(kSortThreads)
+k_bin_sort(const BinRec* __restrict__ recs, const int* __restrict__ counts, const int* __restrict__ base,
+           uint64_t* __restrict__ gkeys, BinRec* __restrict__ out, int* __restrict__ nch) {
+  __shared__ uint64_t sk[kSortLds];
+  const int b = blockIdx.x;
+  const int n = counts[b], c0 = base[b];
+  if (n <= 0) return;
+  if (n >= (1 << kSortPosBits)) {
+    for (int i = threadIdx.x; i < n; i += kSortThreads) out[c0 + i] = recs[c0 + i];
+    if (threadIdx.x == 0) atomicOr(nch + kSortErr, 1);
+    return;
+  }
+  int np = 1;
+  while (np < n) np <<= 1;
+  uint64_t* k = np <= kSortLds ? sk : gkeys + 2 * (size_t)c0;
+  for (int i = threadIdx.x; i < np; i += kSortThreads) k[i] = i < n ? det_key(recs[c0 + i], i) : ~0ull;
+  __syncthreads();
+  bitonic_sort(k, np);
+  for (int i = threadIdx.x; i < n; i += kSortThreads)
+    out[c0 + i] = recs[c0 + (int)(k[i] & ((1u << kSortPosBits) - 1))];
+}
+
 // ------------------------------------------------------------- spreading
 // Gather form, no atomics on the grid.  One workgroup per chunk of a bin.  A
 // sub-batch of the chunk's records is counting-sorted in LDS by first-tap
@@ -452,7 +510,8 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(SpreadArgs a) {
       const int r = t + q * NT;
       if (r < nsb) {
         const BinRec& rc = rl[sb][q];
-        const int slot = soff[key[q]] + rank[q];
+        // presorted bins (deterministic mode) are already in key order
+        const int slot = a.presorted ? r : soff[key[q]] + rank[q];
         sc[slot] = cv[sb][q];
         slx[slot] = rec_lx(rc.packed);
         swx[slot][0] = 0.f;
@@ -679,6 +738,13 @@ hipError_t launch_bin_scatter(const double* x, const double* y, int64_t M, BinGe
     hipLaunchKernelGGL(k_bin_scatter<false>, dim3(G), dim3(kBinThreads), bytes, st, x, y, M, g, ppw, off, bin_base,
                        recs);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_sort(const BinRec* recs, const int* counts, const int* base, int T, uint64_t* gkeys,
+                           BinRec* out, int* nch, hipStream_t st) {
+  if (T <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bin_sort, dim3(T), dim3(kSortThreads), 0, st, recs, counts, base, gkeys, out, nch);
   return hipGetLastError();
 }
 

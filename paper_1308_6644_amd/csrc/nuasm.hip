@@ -178,6 +178,9 @@ struct PointSet {
   int64_t chunk_cap = 0;
   BinRec* recs = nullptr;
   int64_t rec_cap = 0;  // points the record buffer is sized for
+  // deterministic mode: records sorted inside every bin, and the sort's keys
+  BinRec* recs_sorted = nullptr;
+  uint64_t* sort_keys = nullptr;
   float2* scratch = nullptr;
   int64_t scratch_chunks = 0;
   int* host_stat = nullptr;  // pinned [8]
@@ -263,6 +266,8 @@ void release(nuasm_plan_s* pl) {
     f(q.sp_chunks);
     f(q.ip_chunks);
     f(q.recs);
+    f(q.recs_sorted);
+    f(q.sort_keys);
     f(q.scratch);
     f(q.hist);
     f(q.hoff);
@@ -337,7 +342,7 @@ nuasm_status validate(const nuasm_params* p) {
     return fail(NUASM_ERR_INVALID_ARG, "NUASM_OUT_CROP_N applies to type 1 only");
   if (p->tf == NUASM_TF_FRESNEL && p->z == 0.0) return fail(NUASM_ERR_INVALID_ARG, "Fresnel needs z != 0");
   if (!(p->tol >= 1e-12 && p->tol <= 1e-2)) return fail(NUASM_ERR_INVALID_ARG, "tol must be in [1e-12, 1e-2]");
-  if (p->flags & ~(NUASM_OUT_CROP_N | NUASM_DEFER_RANGE_CHECK | NUASM_FULL_FINE_GRID))
+  if (p->flags & ~(NUASM_OUT_CROP_N | NUASM_DEFER_RANGE_CHECK | NUASM_FULL_FINE_GRID | NUASM_DETERMINISTIC))
     return fail(NUASM_ERR_INVALID_ARG, "unknown flag bits");
   if (p->reserved != 0) return fail(NUASM_ERR_INVALID_ARG, "reserved must be 0");
   if (p->band == NUASM_BAND_EXPLICIT) {
@@ -381,6 +386,13 @@ nuasm_status ensure_points_capacity(nuasm_plan_s* pl, PointSet& q, int64_t M) {
     pl->bytes -= sizeof(BinRec) * 4 * q.rec_cap;
     q.recs = nullptr;
   }
+  if (q.recs_sorted) {
+    (void)hipFree(q.recs_sorted);
+    (void)hipFree(q.sort_keys);
+    pl->bytes -= (sizeof(BinRec) * 4 + sizeof(uint64_t) * 8) * q.rec_cap;
+    q.recs_sorted = nullptr;
+    q.sort_keys = nullptr;
+  }
   if (q.sp_chunks) {
     (void)hipFree(q.sp_chunks);
     (void)hipFree(q.ip_chunks);
@@ -409,6 +421,10 @@ nuasm_status ensure_points_capacity(nuasm_plan_s* pl, PointSet& q, int64_t M) {
     HIP_TRY(dalloc(pl, &q.hoff, (size_t)q.hist_rows * (pl->T + 1)), "hipMalloc(bin offsets)");
   }
   HIP_TRY(dalloc(pl, &q.recs, (size_t)(4 * cap)), "hipMalloc(records)");
+  if (pl->p.flags & NUASM_DETERMINISTIC) {
+    HIP_TRY(dalloc(pl, &q.recs_sorted, (size_t)(4 * cap)), "hipMalloc(sorted records)");
+    HIP_TRY(dalloc(pl, &q.sort_keys, (size_t)(8 * cap)), "hipMalloc(sort keys)");
+  }
   q.chunk_cap = pl->T + (4 * cap) / std::min(pl->sp_chunk, pl->ip_chunk) + 1;  // covers both chunk tables
   HIP_TRY(dalloc(pl, &q.sp_chunks, (size_t)q.chunk_cap), "hipMalloc(chunks)");
   HIP_TRY(dalloc(pl, &q.ip_chunks, (size_t)q.chunk_cap), "hipMalloc(chunks)");
@@ -420,6 +436,26 @@ nuasm_status ensure_scratch(nuasm_plan_s* pl, PointSet& q) {
   if (q.scratch) return NUASM_OK;
   HIP_TRY(dalloc(pl, &q.scratch, (size_t)q.chunk_cap * kTile * kTile), "hipMalloc(spread scratch)");
   q.scratch_chunks = q.chunk_cap;
+  return NUASM_OK;
+}
+
+// The records the point kernels read: sorted inside every bin in
+// deterministic mode.
+const BinRec* final_recs(const nuasm_plan_s* pl, const PointSet& q) {
+  return (pl->p.flags & NUASM_DETERMINISTIC) ? q.recs_sorted : q.recs;
+}
+
+// A point-set status word read back from the device: points outside the
+// window (nch[4]) or a bin too large for the deterministic sort (nch[5]).
+nuasm_status point_status(const PointSet& q, int which) {
+  if (q.host_stat[4] != 0) {
+    char buf[160];
+    std::snprintf(buf, sizeof(buf), "%d point(s) outside the window [-N g/2, N g/2]^2 or not finite%s",
+                  q.host_stat[4], which == 1 ? " (destination points)" : "");
+    return fail(NUASM_ERR_OUT_OF_RANGE, buf);
+  }
+  if (q.host_stat[kSortErr] != 0)
+    return fail(NUASM_ERR_UNSUPPORTED, "deterministic mode: a bin holds 2^21 records or more");
   return NUASM_OK;
 }
 
@@ -462,6 +498,9 @@ nuasm_status bind_points(nuasm_plan_s* pl, PointSet& q, int64_t M, const double*
     }
     StageScope sc(pl, NUASM_STAGE_BIN_SCATTER);
     HIP_TRY(launch_bin_scatter(x, y, M, pl->bgeom, ppw, G, q.hoff, q.cursor, q.recs, st), "launch bin_scatter");
+    if (pl->p.flags & NUASM_DETERMINISTIC)
+      HIP_TRY(launch_bin_sort(q.recs, q.counts, q.cursor, pl->T, q.sort_keys, q.recs_sorted, q.nch, st),
+              "launch bin_sort");
   }
   q.M = M;
   q.synced = false;
@@ -469,13 +508,11 @@ nuasm_status bind_points(nuasm_plan_s* pl, PointSet& q, int64_t M, const double*
     q.ready = true;
     return NUASM_OK;
   }
-  HIP_TRY(hipMemcpyAsync(q.host_stat, q.nch, sizeof(int) * 5, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+  HIP_TRY(hipMemcpyAsync(q.host_stat, q.nch, sizeof(int) * 6, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
   HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
-  if (q.host_stat[4] != 0) {
-    char buf[128];
-    std::snprintf(buf, sizeof(buf), "%d point(s) outside the window [-N g/2, N g/2]^2 or not finite",
-                  q.host_stat[4]);
-    return fail(NUASM_ERR_OUT_OF_RANGE, buf);
+  {
+    const nuasm_status ps = point_status(q, &q == &pl->ps[1] ? 1 : 0);
+    if (ps != NUASM_OK) return ps;
   }
   q.exact_sp = q.host_stat[0];
   q.exact_ip = q.host_stat[1];
@@ -563,7 +600,8 @@ nuasm_status run_spread(nuasm_plan_s* pl, PointSet& q, const float2* vals) {
   {
     StageScope sc(pl, NUASM_STAGE_SPREAD);
     SpreadArgs sa{};
-    sa.recs = q.recs;
+    sa.recs = final_recs(pl, q);
+    sa.presorted = (pl->p.flags & NUASM_DETERMINISTIC) ? 1 : 0;
     sa.chunks = q.sp_chunks;
     sa.nchunks = q.nch + 0;
     sa.scratch = q.scratch;
@@ -600,7 +638,7 @@ nuasm_status run_interp(nuasm_plan_s* pl, PointSet& q, const float2* grid, float
     return NUASM_OK;
   }
   InterpArgs ia{};
-  ia.recs = q.recs;
+  ia.recs = final_recs(pl, q);
   ia.chunks = q.ip_chunks;
   ia.nchunks = q.nch + 1;
   ia.grid = grid;
@@ -1000,17 +1038,17 @@ nuasm_status nuasm_check_points(nuasm_plan pl) {
   for (int i = 0; i < pl->nsets; ++i) {
     PointSet& q = pl->ps[i];
     if (q.grid) continue;  // range-checked on the host when bound
-    HIP_TRY(hipMemcpyAsync(q.host_stat, q.nch, sizeof(int) * 5, hipMemcpyDeviceToHost, pl->stream),
+    HIP_TRY(hipMemcpyAsync(q.host_stat, q.nch, sizeof(int) * 6, hipMemcpyDeviceToHost, pl->stream),
             "hipMemcpyAsync");
   }
   HIP_TRY(hipStreamSynchronize(pl->stream), "hipStreamSynchronize");
   for (int i = 0; i < pl->nsets; ++i) {
     PointSet& q = pl->ps[i];
     if (q.grid) continue;
-    if (q.host_stat[4] != 0) {
+    const nuasm_status ps = point_status(q, i);
+    if (ps != NUASM_OK) {
       q.ready = false;
-      return fail(NUASM_ERR_OUT_OF_RANGE, i == 0 ? "points outside the window in the last set_points"
-                                                 : "points outside the window in the last set_dest_points");
+      return ps;
     }
   }
   return NUASM_OK;
@@ -1088,6 +1126,26 @@ nuasm_status nuasm_plan_read_timing(nuasm_plan pl, double* ms, int64_t* launches
 nuasm_status nuasm_debug_transfer(nuasm_plan pl, void* out) {
   if (!pl || !out) return fail(NUASM_ERR_INVALID_ARG, "plan or out is NULL");
   HIP_TRY(launch_transfer_table(pl->geom, pl->spec, (float2*)out, pl->stream), "launch transfer_table");
+  return NUASM_OK;
+}
+
+nuasm_status nuasm_debug_records(nuasm_plan pl, int32_t which, void* recs_out, int64_t rec_cap, int32_t* counts_out,
+                                 int64_t* n_records) {
+  if (!pl || !recs_out || !counts_out || !n_records) return fail(NUASM_ERR_INVALID_ARG, "NULL argument");
+  if (which < 0 || which >= pl->nsets) return fail(NUASM_ERR_INVALID_ARG, "which must be 0 (or 1 for type 3)");
+  PointSet& q = pl->ps[which];
+  if (!q.ready || q.grid) return fail(NUASM_ERR_NOT_READY, "the point set holds no binned points");
+  HIP_TRY(hipMemcpyAsync(q.host_stat, q.nch, sizeof(int) * 6, hipMemcpyDeviceToHost, pl->stream), "hipMemcpyAsync");
+  HIP_TRY(hipStreamSynchronize(pl->stream), "hipStreamSynchronize");
+  const int64_t total = q.host_stat[2];
+  *n_records = total;
+  if (rec_cap < total) return fail(NUASM_ERR_INVALID_ARG, "rec_cap is below the number of records");
+  if (total > 0)
+    HIP_TRY(hipMemcpyAsync(recs_out, final_recs(pl, q), sizeof(BinRec) * total, hipMemcpyDeviceToDevice, pl->stream),
+            "hipMemcpyAsync");
+  HIP_TRY(hipMemcpyAsync(counts_out, q.counts, sizeof(int) * pl->T, hipMemcpyDeviceToDevice, pl->stream),
+          "hipMemcpyAsync");
+  HIP_TRY(hipStreamSynchronize(pl->stream), "hipStreamSynchronize");
   return NUASM_OK;
 }
 
@@ -1415,10 +1473,11 @@ nuasm_status nuasm_batch_check_points(nuasm_batch b, int32_t* bad_plane) {
   for (size_t p = 0; p < b->plans.size(); ++p) {
     nuasm_plan_s* pl = b->plans[p];
     PointSet& q = pl->ps[0];
-    HIP_TRY(hipMemcpy(q.host_stat, q.nch, sizeof(int) * 5, hipMemcpyDeviceToHost), "hipMemcpy");
-    if (q.host_stat[4] != 0) {
+    HIP_TRY(hipMemcpy(q.host_stat, q.nch, sizeof(int) * 6, hipMemcpyDeviceToHost), "hipMemcpy");
+    const nuasm_status ps = point_status(q, 0);
+    if (ps != NUASM_OK) {
       *bad_plane = (int32_t)p;
-      return fail(NUASM_ERR_OUT_OF_RANGE, "plane " + std::to_string(p) + " has points outside its window");
+      return fail(ps, "plane " + std::to_string(p) + ": " + g_last_error);
     }
   }
   return NUASM_OK;

@@ -76,7 +76,7 @@ def _create(P, p):
     ("d2", -1.0, "NUASM_ERR_INVALID_ARG"),
     ("tol", 0.5, "NUASM_ERR_INVALID_ARG"),
     ("flags", 0x80, "NUASM_ERR_INVALID_ARG"),
-    ("flags", 0x8, "NUASM_ERR_INVALID_ARG"),
+    ("flags", 0x10, "NUASM_ERR_INVALID_ARG"),
     ("reserved", 1, "NUASM_ERR_INVALID_ARG"),
     ("phase_fp64", 2, "NUASM_ERR_INVALID_ARG"),
 ])
@@ -126,6 +126,16 @@ def test_fresnel_needs_nonzero_z(P):
     assert P.load().nuasm_status_string(st).decode() == "NUASM_ERR_INVALID_ARG"
 
 
+def test_deterministic_flag_passes_validation(P):
+    """NUASM_DETERMINISTIC is a known flag: without a device the plan gets as
+    far as the device check."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is visible")
+    st, h = _create(P, _params(P, flags=0x8 | 0x2))
+    assert P.load().nuasm_status_string(st).decode() == "NUASM_ERR_NO_DEVICE"
+
+
 def test_null_arguments(P):
     lib = P.load()
     h = ctypes.c_void_p()
@@ -138,6 +148,8 @@ def test_null_arguments(P):
     assert lib.nuasm_set_points(None, 0, None, None) != 0
     assert lib.nuasm_set_dest_points(None, 0, None, None) != 0
     assert lib.nuasm_plan_set_timing(None, 1) != 0
+    n = ctypes.c_int64()
+    assert lib.nuasm_debug_records(None, 0, None, 0, None, ctypes.byref(n)) != 0
 
 
 def test_no_device_is_reported(P):
