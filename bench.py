@@ -578,6 +578,8 @@ def main(argv=None):
                          "paper: the paper's 256 x 256 experiment against Rayleigh-Sommerfeld; "
                          "scaled: a 2x zoom to a 2048 x 2048 destination grid; precision: NU-ASM_2 at "
                          "N'=8192, M=2^24, z=1 m on the band-adaptive and the full fine grid")
+    ap.add_argument("--deterministic", action="store_true",
+                    help="n2048 with NUASM_DETERMINISTIC on every plan (bitwise-reproducible runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (3 times), the "
                          "reference for the FETCH_SIZE / WRITE_SIZE counters, and exit")
@@ -623,7 +625,8 @@ def main(argv=None):
     for z in ZS:
         for tf, band in TFS:
             for t in (1, 2):
-                spec = dict(N=N, type=t, lam=LAM, z=z, g=G, tf=tf, band=band, ox=OX, oy=OY, tol=TOL)
+                spec = dict(N=N, type=t, lam=LAM, z=z, g=G, tf=tf, band=band, ox=OX, oy=OY, tol=TOL,
+                            deterministic=a.deterministic)
                 plan = P.Plan(defer_range_check=True, **spec)
                 if t == 1:
                     x, y, inp = d["x1"], d["y1"], d["c1"]
@@ -694,7 +697,7 @@ def main(argv=None):
                         "points per run, pitch 4 um, 633 nm, o=(1 mm, 0), z in {0.01, 0.1, 0.5} m x "
                         "{band-limited ASM, Fresnel}, tol 1e-6 (w=7), 12 runs per step",
             "N": N, "Np": 2 * N, "M": M, "runs_per_step": len(runs), "phase": "f64",
-            "mode": a.mode,
+            "mode": a.mode, "deterministic": a.deterministic,
         },
         "wall_s_timed": wall,
     }

@@ -80,16 +80,13 @@ enum { NUASM_BAND_FULL = 0, NUASM_BAND_LIMITED = 1, NUASM_BAND_EXPLICIT = 2 };
 #define NUASM_DEFER_RANGE_CHECK 0x2u  /* set_points does not synchronise */
 #define NUASM_FULL_FINE_GRID    0x4u  /* keep the fine grid at 2 N' even when the
                                          band of Eq. 4 would allow a smaller one */
-#define NUASM_DETERMINISTIC     0x8u  /* bitwise-reproducible results: after binning,
-                                         the records of every bin are sorted by
-                                         (first-tap cell, point index), so every
-                                         sum runs in one order on every run, in
-                                         every plan and batch.  Costs one sort
-                                         launch per binning and 2 x 64 B of extra
-                                         workspace per point; a bin of 2^21
-                                         records or more is NUASM_ERR_UNSUPPORTED
-                                         (reported by set_points, or by
-                                         check_points when deferred) */
+#define NUASM_DETERMINISTIC     0x8u  /* bitwise-reproducible results: binning
+                                         keeps every bin's records in point
+                                         order (a stable scatter; ranges of at
+                                         most 1024 points) and spreading ranks
+                                         each sub-batch stably, so every sum
+                                         runs in one order on every run, in
+                                         every plan and batch */
 
 typedef struct {
   int32_t type;        /* NUASM_TYPE_1, NUASM_TYPE_2 or NUASM_TYPE_3 */

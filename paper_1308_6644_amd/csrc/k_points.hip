@@ -232,7 +232,6 @@ __device__ __forceinline__ void bin_scan_body(const int* counts, int T, const Bi
     nch[2] = run[0];
     nch[3] = run[3];
     nch[4] = counts[T];
-    nch[kSortErr] = 0;  // set by k_bin_sort in deterministic mode
   }
 }
 
@@ -345,31 +344,28 @@ k_bin_scatter(const double* __restrict__ x, const double* __restrict__ y, int64_
   }
 }
 
-// Deterministic mode: the records of every bin sorted by (first-tap row,
-// first-tap column, point index), a total order, so that spreading sums every
-// cell in the same order on every run.  One workgroup per bin; a 64-bit key
-// holds the order and the record's position in the bin, sorted by a bitonic
-// network in LDS (bins of up to kSortLds records) or in the global key buffer
-// (larger bins; the bin starting at record c uses keys[2c, 2c + 2n)), then the
-// records are gathered in key order into `out`.  A bin of 2^21 records or more
-// does not fit the key and sets nch[kSortErr] (its records are copied
-// unsorted).
-constexpr int kSortThreads = 1024;
-constexpr int kSortLds = 8192;
-constexpr int kSortPosBits = 21;
+// Deterministic mode: the same counting sort with a stable scatter, so that
+// the records of every bin are in point order whatever the timing of the
+// workgroups.  A range holds at most kDetPoints points, one per thread; the
+// range's records are compacted (a block scan of the per-point counts) and
+// keyed (bin, 4 p + k) for the k-th bin of its p-th point, sorted by a
+// bitonic network in LDS, and a record's slot is its bin's base plus the
+// range's offset in the bin plus its index in the run of its bin (found by a
+// max-scan of the run starts).
+constexpr int kDetPoints = kBinThreads;  // 1024
+constexpr int kDetRecs = 4 * kDetPoints;
+constexpr int kDetRecBits = 12;          // 4 p + k < 2^12
+static_assert(kDetRecs == 1 << kDetRecBits, "record ids fill the low key bits");
+static_assert(kDetPoints == kBinPointsStable, "ranges of the stable scatter");
 
-__device__ __forceinline__ uint64_t det_key(const BinRec& r, int pos) {
-  const uint64_t cell = (uint64_t)(((rec_ly(r.packed) + 16) << 6) | (rec_lx(r.packed) + 16));  // 12 bits
-  return (cell << 52) | ((uint64_t)(uint32_t)r.idx << kSortPosBits) | (uint64_t)pos;
-}
-
-__device__ __forceinline__ void bitonic_sort(uint64_t* k, int np) {
+template <int NTH>
+__device__ __forceinline__ void bitonic_sort_u32(unsigned* k, int np) {
   for (int kk = 2; kk <= np; kk <<= 1)
     for (int j = kk >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < np; i += kSortThreads) {
+      for (int i = threadIdx.x; i < np; i += NTH) {
         const int l = i ^ j;
         if (l > i) {
-          const uint64_t a = k[i], c = k[l];
+          const unsigned a = k[i], c = k[l];
           if ((a > c) == ((i & kk) == 0)) {
             k[i] = c;
             k[l] = a;
@@ -380,26 +376,85 @@ __device__ __forceinline__ void bitonic_sort(uint64_t* k, int np) {
     }
 }
 
-__global__ void __launch_bounds__(kSortThreads)
-k_bin_sort(const BinRec* __restrict__ recs, const int* __restrict__ counts, const int* __restrict__ base,
-           uint64_t* __restrict__ gkeys, BinRec* __restrict__ out, int* __restrict__ nch) {
-  __shared__ uint64_t sk[kSortLds];
-  const int b = blockIdx.x;
-  const int n = counts[b], c0 = base[b];
-  if (n <= 0) return;
-  if (n >= (1 << kSortPosBits)) {
-    for (int i = threadIdx.x; i < n; i += kSortThreads) out[c0 + i] = recs[c0 + i];
-    if (threadIdx.x == 0) atomicOr(nch + kSortErr, 1);
-    return;
-  }
-  int np = 1;
-  while (np < n) np <<= 1;
-  uint64_t* k = np <= kSortLds ? sk : gkeys + 2 * (size_t)c0;
-  for (int i = threadIdx.x; i < np; i += kSortThreads) k[i] = i < n ? det_key(recs[c0 + i], i) : ~0ull;
+__global__ void __launch_bounds__(kBinThreads)
+k_bin_scatter_det(const double* __restrict__ x, const double* __restrict__ y, int64_t M, BinGeom g, int ppw,
+                  const int* __restrict__ off, const int* __restrict__ bin_base, BinRec* __restrict__ recs) {
+  constexpr int NW = kBinThreads / 64;
+  __shared__ unsigned key[kDetRecs];
+  __shared__ int slot_of[kDetRecs];  // by record id 4 p + k
+  __shared__ int wsum[NW], wmax[NW];
+  const int T = g.TX * g.TX;
+  const int* myoff = off + (size_t)blockIdx.x * (T + 1);
+  const int64_t j0 = (int64_t)blockIdx.x * ppw;
+  const int np = (int)(min(M, j0 + ppw) - j0);  // <= kDetPoints (checked by the launcher)
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  PointCells pc = point_cells(t < np ? x[j0 + t] : 0.0, t < np ? y[j0 + t] : 0.0, g);
+  if (t >= np) pc.ok = false;
+  const int bx0 = pc.i0x / kTile, nbx = (pc.i0x + g.w - 1) / kTile - bx0 + 1;
+  const int by0 = pc.i0y / kTile, nby = (pc.i0y + g.w - 1) / kTile - by0 + 1;
+  const int nrec = pc.ok ? nbx * nby : 0;
+  // compaction: exclusive block scan of the per-point record counts
+  const int incl = wave_incl_scan(nrec, lane);
+  if (lane == 63) wsum[wv] = incl;
   __syncthreads();
-  bitonic_sort(k, np);
-  for (int i = threadIdx.x; i < n; i += kSortThreads)
-    out[c0 + i] = recs[c0 + (int)(k[i] & ((1u << kSortPosBits) - 1))];
+  int base = incl - nrec, total = 0;
+  for (int w2 = 0; w2 < NW; ++w2) {
+    if (w2 < wv) base += wsum[w2];
+    total += wsum[w2];
+  }
+  int E = 2;
+  while (E < total) E <<= 1;
+  {
+    int o = base;
+    for (int k = 0; k < 4; ++k) {
+      const int kx = k & 1, ky = k >> 1;
+      if (!pc.ok || kx >= nbx || ky >= nby) continue;
+      key[o++] = ((unsigned)((by0 + ky) * g.TX + bx0 + kx) << kDetRecBits) | (unsigned)(4 * t + k);
+    }
+  }
+  for (int i = total + t; i < E; i += kBinThreads) key[i] = 0xffffffffu;
+  __syncthreads();
+  bitonic_sort_u32<kBinThreads>(key, E);
+  // run starts: start(i) = max over i' <= i of (i' if a bin's run begins at
+  // i'); each thread scans a contiguous block of the sorted keys
+  const int per = (E + kBinThreads - 1) / kBinThreads;
+  const int i0 = min(E, t * per), i1 = min(E, i0 + per);
+  int run = -1;
+  for (int i = i0; i < i1; ++i)
+    if (i == 0 || (key[i] >> kDetRecBits) != (key[i - 1] >> kDetRecBits)) run = i;
+  int rmax = run;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(rmax, o, 64);
+    if (lane >= o) rmax = max(rmax, v);
+  }
+  if (lane == 63) wmax[wv] = rmax;
+  __syncthreads();
+  int before = -1;  // latest run start before this thread's block
+  for (int w2 = 0; w2 < wv; ++w2) before = max(before, wmax[w2]);
+  {
+    const int up = __shfl_up(rmax, 1, 64);
+    if (lane > 0) before = max(before, up);
+  }
+  run = before;
+  for (int i = i0; i < i1 && i < total; ++i) {
+    const unsigned kv = key[i];
+    const int b = (int)(kv >> kDetRecBits);
+    if (i == 0 || b != (int)(key[i - 1] >> kDetRecBits)) run = i;
+    slot_of[kv & (kDetRecs - 1)] = bin_base[b] + myoff[b] + (i - run);
+  }
+  __syncthreads();
+  for (int k = 0; k < 4; ++k) {
+    const int kx = k & 1, ky = k >> 1;
+    if (!pc.ok || kx >= nbx || ky >= nby) continue;
+    const int bx = bx0 + kx, by = by0 + ky;
+    const int lx = pc.i0x - bx * kTile, ly = pc.i0y - by * kTile;
+    BinRec r;
+    r.packed = (lx & 0xff) | ((ly & 0xff) << 8) | ((k == 0) ? (1 << 16) : 0);
+    r.dx = pc.dx;
+    r.dy = pc.dy;
+    r.idx = (int32_t)(j0 + t);
+    recs[slot_of[4 * t + k]] = r;
+  }
 }
 
 // ------------------------------------------------------------- spreading
@@ -505,13 +560,36 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(SpreadArgs a) {
       if (t == 63) soff[NC] = run;
     }
     __syncthreads();
+    if (a.stable) {
+      // deterministic mode: ranks in position order.  The positions are
+      // placed at the atomic ranks (in the weight array, not yet in use); a
+      // record's stable rank counts the lower positions in its cell's run.
+      static_assert(SB * 2 <= (int)sizeof(swy), "stable-rank scratch");
+      unsigned short* spos = reinterpret_cast<unsigned short*>(&swy[0][0]);
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int r = t + q * NT;
+        if (r < nsb) spos[soff[key[q]] + rank[q]] = (unsigned short)r;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int r = t + q * NT;
+        if (r < nsb) {
+          const int s0 = soff[key[q]], s1 = soff[key[q] + 1];
+          int below = 0;
+          for (int i = s0; i < s1; ++i) below += spos[i] < r ? 1 : 0;
+          rank[q] = below;  // rank inside the run, in position order
+        }
+      }
+      __syncthreads();  // before the staging below overwrites the scratch
+    }
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int r = t + q * NT;
       if (r < nsb) {
         const BinRec& rc = rl[sb][q];
-        // presorted bins (deterministic mode) are already in key order
-        const int slot = a.presorted ? r : soff[key[q]] + rank[q];
+        const int slot = soff[key[q]] + rank[q];
         sc[slot] = cv[sb][q];
         slx[slot] = rec_lx(rc.packed);
         swx[slot][0] = 0.f;
@@ -725,9 +803,15 @@ hipError_t launch_bin_colscan(const uint16_t* hist, int G, int T, int* off, int*
 }
 
 hipError_t launch_bin_scatter(const double* x, const double* y, int64_t M, BinGeom g, int ppw, int G,
-                              const int* off, const int* bin_base, BinRec* recs, hipStream_t st) {
+                              const int* off, const int* bin_base, BinRec* recs, bool stable, hipStream_t st) {
   if (G <= 0) return hipSuccess;
   const int T = g.TX * g.TX;
+  if (stable) {
+    if (ppw > kDetPoints) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_bin_scatter_det, dim3(G), dim3(kBinThreads), 0, st, x, y, M, g, ppw, off, bin_base,
+                       recs);
+    return hipGetLastError();
+  }
   if (T * 4 <= kScatterCursorBytes) {
     hipLaunchKernelGGL(k_bin_scatter<true>, dim3(G), dim3(kBinThreads), T * 4, st, x, y, M, g, ppw, off, bin_base,
                        recs);
@@ -738,13 +822,6 @@ hipError_t launch_bin_scatter(const double* x, const double* y, int64_t M, BinGe
     hipLaunchKernelGGL(k_bin_scatter<false>, dim3(G), dim3(kBinThreads), bytes, st, x, y, M, g, ppw, off, bin_base,
                        recs);
   }
-  return hipGetLastError();
-}
-
-hipError_t launch_bin_sort(const BinRec* recs, const int* counts, const int* base, int T, uint64_t* gkeys,
-                           BinRec* out, int* nch, hipStream_t st) {
-  if (T <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_bin_sort, dim3(T), dim3(kSortThreads), 0, st, recs, counts, base, gkeys, out, nch);
   return hipGetLastError();
 }
 

@@ -72,7 +72,6 @@ struct BinScanOut {
   int ip_chunk;      // max records per interpolation chunk
 };
 constexpr int kScanDone = 7;  // element of nch counting finished column-scan workgroups
-constexpr int kSortErr = 5;   // element of nch set when a bin is too large for the deterministic sort
 
 struct SpreadArgs {
   const BinRec* recs;
@@ -83,7 +82,7 @@ struct SpreadArgs {
   float2* grid;           // L x L support
   int L, TX;
   float two_over_w, beta;
-  int presorted;          // bins sorted by first-tap cell (deterministic mode)
+  int stable;             // deterministic mode: records ranked in position order
 };
 
 struct SpreadReduceArgs {
@@ -127,17 +126,14 @@ struct GridPts {
 hipError_t launch_fill_i32(int* p, int v, int64_t n, hipStream_t st);
 // counting sort of (point, bin) pairs: hist -> colscan -> scan -> scatter
 constexpr int kBinPointsMax = 65535;  // points per binning workgroup (16-bit LDS counters)
+constexpr int kBinPointsStable = 1024;  // the same in deterministic mode (stable scatter in LDS)
 // hist rows and offset rows have T + 1 entries (entry T: points outside the window)
 hipError_t launch_bin_hist(const double* x, const double* y, int64_t M, BinGeom g, int ppw, int G,
                            uint16_t* hist, hipStream_t st);
 hipError_t launch_bin_colscan(const uint16_t* hist, int G, int T, int* off, int* total, const BinScanOut& so,
                               int* done, hipStream_t st);
 hipError_t launch_bin_scatter(const double* x, const double* y, int64_t M, BinGeom g, int ppw, int G,
-                              const int* off, const int* bin_base, BinRec* recs, hipStream_t st);
-// deterministic mode: records of every bin in (first-tap cell, point index)
-// order into `out`; gkeys holds 2 x (records) keys
-hipError_t launch_bin_sort(const BinRec* recs, const int* counts, const int* base, int T, uint64_t* gkeys,
-                           BinRec* out, int* nch, hipStream_t st);
+                              const int* off, const int* bin_base, BinRec* recs, bool stable, hipStream_t st);
 hipError_t launch_spread(int w, bool small_chunks, const SpreadArgs& a, int grid, hipStream_t st);
 hipError_t launch_spread_reduce(const SpreadReduceArgs& a, int grid, hipStream_t st);
 hipError_t launch_interp(int w, const InterpArgs& a, int grid, hipStream_t st);

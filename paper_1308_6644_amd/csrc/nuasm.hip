@@ -178,9 +178,6 @@ struct PointSet {
   int64_t chunk_cap = 0;
   BinRec* recs = nullptr;
   int64_t rec_cap = 0;  // points the record buffer is sized for
-  // deterministic mode: records sorted inside every bin, and the sort's keys
-  BinRec* recs_sorted = nullptr;
-  uint64_t* sort_keys = nullptr;
   float2* scratch = nullptr;
   int64_t scratch_chunks = 0;
   int* host_stat = nullptr;  // pinned [8]
@@ -266,8 +263,6 @@ void release(nuasm_plan_s* pl) {
     f(q.sp_chunks);
     f(q.ip_chunks);
     f(q.recs);
-    f(q.recs_sorted);
-    f(q.sort_keys);
     f(q.scratch);
     f(q.hist);
     f(q.hoff);
@@ -320,6 +315,9 @@ struct StageScope {
 
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
+// Deterministic mode: stable binning scatter and stable ranks in spreading.
+bool stable_bins(const nuasm_plan_s* pl) { return (pl->p.flags & NUASM_DETERMINISTIC) != 0; }
+
 // Pitch of the plan's grid: the uniform plane's (d2 for type 1, d1 for type
 // 2); type 3 takes the destination's, d2.
 double plane_pitch(const nuasm_params* p) { return p->type == NUASM_TYPE_2 ? p->d1 : p->d2; }
@@ -355,10 +353,10 @@ nuasm_status validate(const nuasm_params* p) {
 
 // Binning workgroups: contiguous ranges of ppw points (automatic: at least
 // 4096, at most kBinPointsMax, and about 256 ranges for large M; or the
-// tuned count).
-void bin_ranges(int64_t M, int fixed, int* ppw, int* G) {
+// tuned count; at most kBinPointsStable in deterministic mode).
+void bin_ranges(int64_t M, int fixed, bool stable, int* ppw, int* G) {
   int64_t p = fixed > 0 ? fixed : std::max<int64_t>(4096, (M + 255) / 256);
-  p = std::min<int64_t>(p, kBinPointsMax);
+  p = std::min<int64_t>(p, stable ? kBinPointsStable : kBinPointsMax);
   *ppw = (int)p;
   *G = (int)((M + p - 1) / p);
 }
@@ -386,13 +384,7 @@ nuasm_status ensure_points_capacity(nuasm_plan_s* pl, PointSet& q, int64_t M) {
     pl->bytes -= sizeof(BinRec) * 4 * q.rec_cap;
     q.recs = nullptr;
   }
-  if (q.recs_sorted) {
-    (void)hipFree(q.recs_sorted);
-    (void)hipFree(q.sort_keys);
-    pl->bytes -= (sizeof(BinRec) * 4 + sizeof(uint64_t) * 8) * q.rec_cap;
-    q.recs_sorted = nullptr;
-    q.sort_keys = nullptr;
-  }
+
   if (q.sp_chunks) {
     (void)hipFree(q.sp_chunks);
     (void)hipFree(q.ip_chunks);
@@ -415,16 +407,12 @@ nuasm_status ensure_points_capacity(nuasm_plan_s* pl, PointSet& q, int64_t M) {
   q.rec_cap = 0;
   {
     int ppw = 0, G = 0;
-    bin_ranges(cap, pl->bin_ppw, &ppw, &G);
+    bin_ranges(cap, pl->bin_ppw, stable_bins(pl), &ppw, &G);
     q.hist_rows = std::max(G, 1);
     HIP_TRY(dalloc(pl, &q.hist, (size_t)q.hist_rows * (pl->T + 1)), "hipMalloc(bin histograms)");
     HIP_TRY(dalloc(pl, &q.hoff, (size_t)q.hist_rows * (pl->T + 1)), "hipMalloc(bin offsets)");
   }
   HIP_TRY(dalloc(pl, &q.recs, (size_t)(4 * cap)), "hipMalloc(records)");
-  if (pl->p.flags & NUASM_DETERMINISTIC) {
-    HIP_TRY(dalloc(pl, &q.recs_sorted, (size_t)(4 * cap)), "hipMalloc(sorted records)");
-    HIP_TRY(dalloc(pl, &q.sort_keys, (size_t)(8 * cap)), "hipMalloc(sort keys)");
-  }
   q.chunk_cap = pl->T + (4 * cap) / std::min(pl->sp_chunk, pl->ip_chunk) + 1;  // covers both chunk tables
   HIP_TRY(dalloc(pl, &q.sp_chunks, (size_t)q.chunk_cap), "hipMalloc(chunks)");
   HIP_TRY(dalloc(pl, &q.ip_chunks, (size_t)q.chunk_cap), "hipMalloc(chunks)");
@@ -439,14 +427,8 @@ nuasm_status ensure_scratch(nuasm_plan_s* pl, PointSet& q) {
   return NUASM_OK;
 }
 
-// The records the point kernels read: sorted inside every bin in
-// deterministic mode.
-const BinRec* final_recs(const nuasm_plan_s* pl, const PointSet& q) {
-  return (pl->p.flags & NUASM_DETERMINISTIC) ? q.recs_sorted : q.recs;
-}
-
-// A point-set status word read back from the device: points outside the
-// window (nch[4]) or a bin too large for the deterministic sort (nch[5]).
+// The point-set status read back from the device: points outside the
+// window (nch[4]).
 nuasm_status point_status(const PointSet& q, int which) {
   if (q.host_stat[4] != 0) {
     char buf[160];
@@ -454,8 +436,6 @@ nuasm_status point_status(const PointSet& q, int which) {
                   q.host_stat[4], which == 1 ? " (destination points)" : "");
     return fail(NUASM_ERR_OUT_OF_RANGE, buf);
   }
-  if (q.host_stat[kSortErr] != 0)
-    return fail(NUASM_ERR_UNSUPPORTED, "deterministic mode: a bin holds 2^21 records or more");
   return NUASM_OK;
 }
 
@@ -482,7 +462,7 @@ nuasm_status bind_points(nuasm_plan_s* pl, PointSet& q, int64_t M, const double*
   hipStream_t st = pl->stream;
   {
     int ppw = 0, G = 0;
-    bin_ranges(M, pl->bin_ppw, &ppw, &G);
+    bin_ranges(M, pl->bin_ppw, stable_bins(pl), &ppw, &G);
     if (M > 0) {
       StageScope sc(pl, NUASM_STAGE_BIN_HIST);
       HIP_TRY(launch_bin_hist(x, y, M, pl->bgeom, ppw, G, q.hist, st), "launch bin_hist");
@@ -497,10 +477,8 @@ nuasm_status bind_points(nuasm_plan_s* pl, PointSet& q, int64_t M, const double*
               "launch bin_colscan");
     }
     StageScope sc(pl, NUASM_STAGE_BIN_SCATTER);
-    HIP_TRY(launch_bin_scatter(x, y, M, pl->bgeom, ppw, G, q.hoff, q.cursor, q.recs, st), "launch bin_scatter");
-    if (pl->p.flags & NUASM_DETERMINISTIC)
-      HIP_TRY(launch_bin_sort(q.recs, q.counts, q.cursor, pl->T, q.sort_keys, q.recs_sorted, q.nch, st),
-              "launch bin_sort");
+    HIP_TRY(launch_bin_scatter(x, y, M, pl->bgeom, ppw, G, q.hoff, q.cursor, q.recs, stable_bins(pl), st),
+            "launch bin_scatter");
   }
   q.M = M;
   q.synced = false;
@@ -508,7 +486,7 @@ nuasm_status bind_points(nuasm_plan_s* pl, PointSet& q, int64_t M, const double*
     q.ready = true;
     return NUASM_OK;
   }
-  HIP_TRY(hipMemcpyAsync(q.host_stat, q.nch, sizeof(int) * 6, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+  HIP_TRY(hipMemcpyAsync(q.host_stat, q.nch, sizeof(int) * 5, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
   HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
   {
     const nuasm_status ps = point_status(q, &q == &pl->ps[1] ? 1 : 0);
@@ -600,8 +578,8 @@ nuasm_status run_spread(nuasm_plan_s* pl, PointSet& q, const float2* vals) {
   {
     StageScope sc(pl, NUASM_STAGE_SPREAD);
     SpreadArgs sa{};
-    sa.recs = final_recs(pl, q);
-    sa.presorted = (pl->p.flags & NUASM_DETERMINISTIC) ? 1 : 0;
+    sa.recs = q.recs;
+    sa.stable = stable_bins(pl) ? 1 : 0;
     sa.chunks = q.sp_chunks;
     sa.nchunks = q.nch + 0;
     sa.scratch = q.scratch;
@@ -638,7 +616,7 @@ nuasm_status run_interp(nuasm_plan_s* pl, PointSet& q, const float2* grid, float
     return NUASM_OK;
   }
   InterpArgs ia{};
-  ia.recs = final_recs(pl, q);
+  ia.recs = q.recs;
   ia.chunks = q.ip_chunks;
   ia.nchunks = q.nch + 1;
   ia.grid = grid;
@@ -982,7 +960,7 @@ nuasm_status nuasm_plan_get_info(nuasm_plan pl, nuasm_plan_info* info) {
   info->interp_chunk = pl->ip_chunk;
   {
     int ppw = 0, G = 0;
-    bin_ranges(M, pl->bin_ppw, &ppw, &G);
+    bin_ranges(M, pl->bin_ppw, stable_bins(pl), &ppw, &G);
     info->bin_range_points = ppw;
   }
   return NUASM_OK;
@@ -1038,7 +1016,7 @@ nuasm_status nuasm_check_points(nuasm_plan pl) {
   for (int i = 0; i < pl->nsets; ++i) {
     PointSet& q = pl->ps[i];
     if (q.grid) continue;  // range-checked on the host when bound
-    HIP_TRY(hipMemcpyAsync(q.host_stat, q.nch, sizeof(int) * 6, hipMemcpyDeviceToHost, pl->stream),
+    HIP_TRY(hipMemcpyAsync(q.host_stat, q.nch, sizeof(int) * 5, hipMemcpyDeviceToHost, pl->stream),
             "hipMemcpyAsync");
   }
   HIP_TRY(hipStreamSynchronize(pl->stream), "hipStreamSynchronize");
@@ -1135,13 +1113,13 @@ nuasm_status nuasm_debug_records(nuasm_plan pl, int32_t which, void* recs_out, i
   if (which < 0 || which >= pl->nsets) return fail(NUASM_ERR_INVALID_ARG, "which must be 0 (or 1 for type 3)");
   PointSet& q = pl->ps[which];
   if (!q.ready || q.grid) return fail(NUASM_ERR_NOT_READY, "the point set holds no binned points");
-  HIP_TRY(hipMemcpyAsync(q.host_stat, q.nch, sizeof(int) * 6, hipMemcpyDeviceToHost, pl->stream), "hipMemcpyAsync");
+  HIP_TRY(hipMemcpyAsync(q.host_stat, q.nch, sizeof(int) * 5, hipMemcpyDeviceToHost, pl->stream), "hipMemcpyAsync");
   HIP_TRY(hipStreamSynchronize(pl->stream), "hipStreamSynchronize");
   const int64_t total = q.host_stat[2];
   *n_records = total;
   if (rec_cap < total) return fail(NUASM_ERR_INVALID_ARG, "rec_cap is below the number of records");
   if (total > 0)
-    HIP_TRY(hipMemcpyAsync(recs_out, final_recs(pl, q), sizeof(BinRec) * total, hipMemcpyDeviceToDevice, pl->stream),
+    HIP_TRY(hipMemcpyAsync(recs_out, q.recs, sizeof(BinRec) * total, hipMemcpyDeviceToDevice, pl->stream),
             "hipMemcpyAsync");
   HIP_TRY(hipMemcpyAsync(counts_out, q.counts, sizeof(int) * pl->T, hipMemcpyDeviceToDevice, pl->stream),
           "hipMemcpyAsync");
@@ -1473,7 +1451,7 @@ nuasm_status nuasm_batch_check_points(nuasm_batch b, int32_t* bad_plane) {
   for (size_t p = 0; p < b->plans.size(); ++p) {
     nuasm_plan_s* pl = b->plans[p];
     PointSet& q = pl->ps[0];
-    HIP_TRY(hipMemcpy(q.host_stat, q.nch, sizeof(int) * 6, hipMemcpyDeviceToHost), "hipMemcpy");
+    HIP_TRY(hipMemcpy(q.host_stat, q.nch, sizeof(int) * 5, hipMemcpyDeviceToHost), "hipMemcpy");
     const nuasm_status ps = point_status(q, 0);
     if (ps != NUASM_OK) {
       *bad_plane = (int32_t)p;

@@ -4,10 +4,10 @@
   footprint, with first-tap offsets and kernel offsets as the binning rule
   defines them, whatever the mode (checked against a numpy restatement of that
   rule from the coordinates).
-* In deterministic mode every bin's records are in (first-tap row, first-tap
-  column, point index) order, so repeated bindings and executions, other plans
-  and batches give bitwise-identical results, still the oracle's to the
-  operator bar.  Bins larger than the LDS sort take the global-memory sort.
+* In deterministic mode every bin's records are in point order and spreading
+  ranks its sub-batches stably, so repeated bindings and executions, other
+  plans and batches give bitwise-identical results, still the oracle's to the
+  operator bar, however dense the bins.
 """
 import sys
 
@@ -97,10 +97,8 @@ def test_records_are_the_footprint_pairs(P, deterministic):
     d = np.array([ed[(int(i), int(b))] for i, b in zip(idx, bins)])
     assert np.max(np.abs(dx - d[:, 0])) <= 1e-6 and np.max(np.abs(dy - d[:, 1])) <= 1e-6
     if deterministic:
-        key = (ly.astype(np.int64) << 40) | (lx.astype(np.int64) + 64 << 32) | idx.astype(np.int64)
         for b in np.unique(bins):
-            k = key[bins == b]
-            assert np.all(np.diff(k) > 0), f"bin {b} not in (row, column, index) order"
+            assert np.all(np.diff(idx[bins == b]) > 0), f"bin {b} not in point order"
 
 
 def _run(P, geo, t, x, y, inp, **kw):
@@ -146,10 +144,9 @@ def test_deterministic_matches_oracle(P, t):
 
 
 @pytest.mark.parametrize("t", [1, 2])
-def test_bins_beyond_the_lds_sort(P, t):
+def test_dense_bin_deterministic(P, t):
     """20000 points within half a pixel of the window centre: one bin holds
-    them all (more than the 8192 records the LDS sort takes), so it is sorted
-    in the global key buffer."""
+    them all, split over several spreading chunks and binning ranges."""
     N, M = 32, 20000
     _say("big bin", t)
     geo = geometry(N=N, g=4e-6, lam=633e-9, z=0.002, tf="asm", band="full")
@@ -159,39 +156,37 @@ def test_bins_beyond_the_lds_sort(P, t):
     inp = synth.unit_phase(rng, M if t == 1 else (N, N))
     plan, a = _run(P, geo, t, x, y, inp, deterministic=True)
     recs, counts = plan.debug_records()
-    assert int(counts.max()) > 8192
+    assert int(counts.max()) == M
     idx, bins, lx, ly, prim, dx, dy, c = decode(recs, counts)
-    key = (ly.astype(np.int64) << 40) | (lx.astype(np.int64) + 64 << 32) | idx.astype(np.int64)
     for b in np.unique(bins):
-        assert np.all(np.diff(key[bins == b]) > 0)
+        assert np.all(np.diff(idx[bins == b]) > 0)
     plan.set_points(dev(torch, x), dev(torch, y))
     assert torch.equal(plan.execute(dev(torch, inp)), a)
     ref = O.nuasm1(geo, x, y, inp) if t == 1 else O.nuasm2(geo, inp, x, y)
     assert rel_l2(host(a), ref) <= 1e-5
 
 
-def test_bin_too_large_for_the_sort_is_reported(P):
-    """2^21 + 5 points on the window centre put that many records in one bin,
-    more than the sort key can index: set_points reports it, and so does
-    check_points when the range check is deferred."""
+def test_deterministic_ranges_and_a_very_dense_bin(P):
+    """Deterministic binning takes ranges of at most 1024 points (tuned or
+    not); 2^21 + 5 points on the window centre (one bin of that many records)
+    give bitwise-equal results on rebinding."""
     N, M = 16, (1 << 21) + 5
-    _say("sort overflow")
+    _say("dense bin, 2^21 + 5 records")
     geo = geometry(N=N, g=4e-6, lam=633e-9, z=0.002)
-    z = torch.zeros(M, dtype=torch.float64, device="cuda")
+    zc = torch.zeros(M, dtype=torch.float64, device="cuda")
+    c = torch.ones(M, dtype=torch.complex64, device="cuda")
     plan = make_plan(P, geo, 1, deterministic=True)
-    with pytest.raises(P.NuasmError) as ei:
-        plan.set_points(z, z)
-    assert ei.value.name == "NUASM_ERR_UNSUPPORTED"
-    plan = make_plan(P, geo, 1, deterministic=True, defer_range_check=True)
-    plan.set_points(z, z)
-    with pytest.raises(P.NuasmError) as ei:
-        plan.check_points()
-    assert ei.value.name == "NUASM_ERR_UNSUPPORTED"
-    # the same points without the flag are an ordinary (dense) binning
-    plan = make_plan(P, geo, 1)
-    plan.set_points(z, z)
-    out = plan.execute(torch.ones(M, dtype=torch.complex64, device="cuda"))
-    assert torch.isfinite(torch.view_as_real(out)).all()
+    plan.set_points(zc, zc)
+    assert plan.info["bin_range_points"] == 1024
+    a = plan.execute(c).clone()
+    assert torch.isfinite(torch.view_as_real(a)).all()
+    plan.set_tuning(bin_range_points=65535)
+    plan.set_points(zc, zc)
+    assert plan.info["bin_range_points"] == 1024
+    assert torch.equal(plan.execute(c), a)
+    ref = make_plan(P, geo, 1)
+    ref.set_points(zc, zc)
+    assert rel_l2(host(ref.execute(c)), host(a)) <= 1e-5
 
 
 def test_batch_matches_plain_plans_bitwise(P):
