@@ -245,6 +245,20 @@ nuasm_status nuasm_debug_transfer(nuasm_plan plan, void* out_dev);
 nuasm_status nuasm_debug_records(nuasm_plan plan, int32_t which, void* recs_out_dev, int64_t rec_cap,
                                  int32_t* counts_out_dev, int64_t* n_records);
 
+/* Spreading alone, for testing: the values vals_dev (complex64, one per point
+ * of the bound set `which`) spread with the plan's kernel onto the fine-grid
+ * support, copied to grid_out_dev as complex64 [L][L] (nuasm_plan_info.L;
+ * support cell (i, j) of a point's taps as the binning defines them).
+ * Enqueued on the plan's stream.  NUASM_ERR_NOT_READY unless the set is
+ * bound. */
+nuasm_status nuasm_debug_spread(nuasm_plan plan, int32_t which, const void* vals_dev, void* grid_out_dev);
+
+/* Interpolation alone, for testing: the support grid grid_dev (complex64
+ * [L][L]) interpolated with the plan's kernel at the points of the bound set
+ * `which`, into out_dev (complex64, one per point, caller order).  Enqueued on
+ * the plan's stream.  NUASM_ERR_NOT_READY unless the set is bound. */
+nuasm_status nuasm_debug_interp(nuasm_plan plan, int32_t which, const void* grid_dev, void* out_dev);
+
 /* Plain batched 1-D FFT with the library's Stockham kernels, for testing:
  * `batch` contiguous rows of length n (power of two, 32..16384), complex64,
  * forward (sign = -1) or unnormalised inverse (sign = +1), out of place. */

@@ -98,6 +98,8 @@ _SIGS = {
                                               ctypes.POINTER(ctypes.c_int64)]),
     "nuasm_debug_records": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
                                             ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "nuasm_debug_spread": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "nuasm_debug_interp": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "nuasm_debug_fft": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_void_p]),
     "nuasm_batch_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(Params), ctypes.c_void_p,
@@ -272,6 +274,34 @@ class Plan:
 
     def check_points(self):
         _check(load().nuasm_check_points(self._h))
+
+    def debug_spread(self, vals: torch.Tensor, dest: bool = False) -> torch.Tensor:
+        """Spreading alone: the point values spread onto the fine-grid
+        support, complex64 [L][L]."""
+        L = self.info["L"]
+        grid = torch.empty((L, L), dtype=torch.complex64, device=self.device)
+        n = self.M_dest if dest else self.M
+        vp = _dev_ptr(vals, torch.complex64, "vals") if n else None
+        if n and vals.numel() != n:
+            raise ValueError(f"vals must hold {n} values")
+        self._sync_stream()
+        _check(load().nuasm_debug_spread(self._h, 1 if dest else 0, ctypes.c_void_p(vp),
+                                         ctypes.c_void_p(grid.data_ptr())))
+        return grid
+
+    def debug_interp(self, grid: torch.Tensor, dest: bool = False) -> torch.Tensor:
+        """Interpolation alone: the support grid (complex64 [L][L]) at the
+        bound points, complex64 [M]."""
+        L = self.info["L"]
+        if tuple(grid.shape) != (L, L):
+            raise ValueError(f"grid must be [{L}][{L}]")
+        n = self.M_dest if dest else self.M
+        out = torch.empty((n,), dtype=torch.complex64, device=self.device)
+        gp = _dev_ptr(grid, torch.complex64, "grid")
+        self._sync_stream()
+        _check(load().nuasm_debug_interp(self._h, 1 if dest else 0, ctypes.c_void_p(gp),
+                                         ctypes.c_void_p(out.data_ptr() if n else None)))
+        return out
 
     def debug_records(self, dest: bool = False):
         """The bound point set's bin records in the order the point kernels

@@ -1127,6 +1127,29 @@ nuasm_status nuasm_debug_records(nuasm_plan pl, int32_t which, void* recs_out, i
   return NUASM_OK;
 }
 
+nuasm_status nuasm_debug_spread(nuasm_plan pl, int32_t which, const void* vals, void* grid_out) {
+  if (!pl || !grid_out) return fail(NUASM_ERR_INVALID_ARG, "plan or grid_out is NULL");
+  if (which < 0 || which >= pl->nsets) return fail(NUASM_ERR_INVALID_ARG, "which must be 0 (or 1 for type 3)");
+  PointSet& q = pl->ps[which];
+  if (!q.ready) return fail(NUASM_ERR_NOT_READY, "the point set is not bound");
+  if (!vals && q.M > 0) return fail(NUASM_ERR_INVALID_ARG, "vals is NULL");
+  nuasm_status s = run_spread(pl, q, (const float2*)vals);
+  if (s != NUASM_OK) return s;
+  const size_t n = (size_t)pl->geom.L * pl->geom.L;
+  HIP_TRY(hipMemcpyAsync(grid_out, pl->gridA, sizeof(float2) * n, hipMemcpyDeviceToDevice, pl->stream),
+          "hipMemcpyAsync");
+  return NUASM_OK;
+}
+
+nuasm_status nuasm_debug_interp(nuasm_plan pl, int32_t which, const void* grid, void* out) {
+  if (!pl || !grid) return fail(NUASM_ERR_INVALID_ARG, "plan or grid is NULL");
+  if (which < 0 || which >= pl->nsets) return fail(NUASM_ERR_INVALID_ARG, "which must be 0 (or 1 for type 3)");
+  PointSet& q = pl->ps[which];
+  if (!q.ready) return fail(NUASM_ERR_NOT_READY, "the point set is not bound");
+  if (!out && q.M > 0) return fail(NUASM_ERR_INVALID_ARG, "out is NULL");
+  return run_interp(pl, q, (const float2*)grid, (float2*)out);
+}
+
 nuasm_status nuasm_debug_fft(int64_t n, int64_t batch, int32_t sign, const void* in, void* out, void* stream) {
   if (!is_pow2(n) || n < 32 || n > (1 << kMaxLogN)) return fail(NUASM_ERR_UNSUPPORTED, "n must be 2^5..2^14");
   if (batch < 0 || (sign != -1 && sign != 1)) return fail(NUASM_ERR_INVALID_ARG, "bad batch or sign");
