@@ -35,7 +35,7 @@ M = 1 << 20
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes over this
 # workload (scaled by a plain-copy calibration), for kernels whose code has not
 # changed since the counters were taken; see profiles/bench_N2048_M1M_kernels.md.
-COUNTER_TRAFFIC = {"spread": (138.7 + 31.5) * 1e6}
+COUNTER_TRAFFIC = {"spread": (138.5 + 31.5) * 1e6}
 
 
 def stage_bytes(stage: str, info: dict) -> float:
