@@ -241,6 +241,26 @@ def roofline(stages, steps):
     return roof, report
 
 
+def copy_bandwidth(torch, nbytes=1 << 30, reps=5) -> float:
+    """Device-to-device copy bandwidth (GB/s, bytes read + written), median of
+    `reps` timed copies of `nbytes` after one untimed: the practical ceiling
+    the roofline fraction is also stated against."""
+    import statistics
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    times = []
+    for i in range(reps + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        if i:
+            times.append(e0.elapsed_time(e1))
+    del src, dst
+    return 2.0 * nbytes / (statistics.median(times) * 1e-3) / 1e9
+
+
 def nuasm3_workload(a, torch, P, d):
     """NU-ASM_3 / NU-FRE_3 at the headline geometry: 2^20 clustered source
     points and 2^20 clustered destination points (the two point sets of the
@@ -726,6 +746,9 @@ def main(argv=None):
     print(f"[bench] per-stage timing {a.profile_steps} steps", file=sys.stderr, flush=True)
     stages, per_type_ms = stage_pass(runs, seq_step, a.profile_steps, torch)
     roof, stage_report = roofline(stages, a.profile_steps)
+    cbw = copy_bandwidth(torch)
+    roof["copy_GBps"] = cbw
+    roof["frac_of_copy"] = roof["achieved"] / cbw
     # whole-path byte model per type (pass-minimal): 64 M + 56 N'^2 and 56 M + 44 N'^2
     Np = 2 * N
     nruns = len(runs) // 2
@@ -733,7 +756,8 @@ def main(argv=None):
     for t, bpp in ((1, 64.0 * M + 56.0 * Np * Np), (2, 56.0 * M + 44.0 * Np * Np)):
         t_ms = per_type_ms[t] / (a.profile_steps * nruns)
         path[f"nuasm{t}"] = {"avg_ms": t_ms, "model_bytes": bpp,
-                             "frac": bpp / (t_ms * 1e-3) / (HBM_PEAK_GBS * 1e9)}
+                             "frac": bpp / (t_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+                             "frac_of_copy": bpp / (t_ms * 1e-3) / (cbw * 1e9)}
 
     line.update({"roofline": roof, "stages": stage_report, "path_model": path})
     if not a.no_cpu_baseline:
