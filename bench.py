@@ -739,8 +739,15 @@ def main(argv=None):
     e1.record()
     torch.cuda.synchronize()
     ex_ms = e0.elapsed_time(e1) / a.steps
+    # execute-only byte model: the whole-path model without the binning
+    # (B - 44 M for type 1, B - 32 M for type 2), summed over the step's runs
+    Np_ = 2 * N
+    ex_bytes = sum((64.0 * M + 56.0 * Np_ * Np_ - 44.0 * M) if r["type"] == 1
+                   else (56.0 * M + 44.0 * Np_ * Np_ - 32.0 * M) for r in runs)
     line["execute_only"] = {"ms_per_step": ex_ms, "points_per_s": len(runs) * M / (ex_ms * 1e-3),
-                            "mode": "sequential plain plans, points bound once"}
+                            "mode": "sequential plain plans, points bound once",
+                            "model_bytes": ex_bytes,
+                            "frac": ex_bytes / (ex_ms * 1e-3) / (HBM_PEAK_GBS * 1e9)}
 
     # second pass: per-stage HIP events recorded by the library
     print(f"[bench] per-stage timing {a.profile_steps} steps", file=sys.stderr, flush=True)

@@ -260,8 +260,9 @@ nuasm_status nuasm_debug_spread(nuasm_plan plan, int32_t which, const void* vals
 nuasm_status nuasm_debug_interp(nuasm_plan plan, int32_t which, const void* grid_dev, void* out_dev);
 
 /* Plain batched 1-D FFT with the library's Stockham kernels, for testing:
- * `batch` contiguous rows of length n (power of two, 32..16384), complex64,
- * forward (sign = -1) or unnormalised inverse (sign = +1), out of place. */
+ * `batch` (< 2^31) contiguous rows of length n (power of two, 32..16384),
+ * complex64, forward (sign = -1) or unnormalised inverse (sign = +1), out of
+ * place. */
 nuasm_status nuasm_debug_fft(int64_t n, int64_t batch, int32_t sign, const void* in_dev,
                              void* out_dev, void* hip_stream);
 

@@ -1153,6 +1153,7 @@ nuasm_status nuasm_debug_interp(nuasm_plan pl, int32_t which, const void* grid, 
 nuasm_status nuasm_debug_fft(int64_t n, int64_t batch, int32_t sign, const void* in, void* out, void* stream) {
   if (!is_pow2(n) || n < 32 || n > (1 << kMaxLogN)) return fail(NUASM_ERR_UNSUPPORTED, "n must be 2^5..2^14");
   if (batch < 0 || (sign != -1 && sign != 1)) return fail(NUASM_ERR_INVALID_ARG, "bad batch or sign");
+  if (batch > (int64_t)INT32_MAX) return fail(NUASM_ERR_UNSUPPORTED, "batch must be below 2^31");
   if (batch == 0) return NUASM_OK;
   if (!in || !out) return fail(NUASM_ERR_INVALID_ARG, "in/out pointer is NULL");
   int ndev = 0;
