@@ -189,6 +189,33 @@ def test_deterministic_ranges_and_a_very_dense_bin(P):
     assert rel_l2(host(ref.execute(c)), host(a)) <= 1e-5
 
 
+def test_deterministic_type3_and_adjoints(P):
+    """Type 3 (two binned point sets) and the adjoints of types 1 and 2 (the
+    other pipeline on the same bins) are bitwise reproducible too."""
+    N = 64
+    _say("deterministic type 3 and adjoints")
+    geo = geometry(N=N, g=4e-6, lam=633e-9, z=0.02, tf="asm", band="limited", ox=1e-4)
+    rng = np.random.default_rng(73)
+    xs, ys = synth.clustered_box(rng, 5000, N * geo.g)
+    xd, yd = synth.clustered_box(rng, 4000, N * geo.g)
+    c, wv = synth.unit_phase(rng, 5000), synth.unit_phase(rng, 4000)
+    v = synth.unit_phase(rng, (2 * N, 2 * N))
+
+    def run():
+        p3 = make_plan(P, geo, 3, deterministic=True)
+        p3.set_points(dev(torch, xs), dev(torch, ys)).set_dest_points(dev(torch, xd), dev(torch, yd))
+        p1 = make_plan(P, geo, 1, deterministic=True)
+        p1.set_points(dev(torch, xs), dev(torch, ys))
+        p2 = make_plan(P, geo, 2, deterministic=True)
+        p2.set_points(dev(torch, xd), dev(torch, yd))
+        return (p3.execute(dev(torch, c)), p3.adjoint(dev(torch, wv)), p1.adjoint(dev(torch, v)),
+                p2.adjoint(dev(torch, wv)))
+    first, second = run(), run()
+    for a, b in zip(first, second):
+        assert torch.equal(a, b)
+    assert rel_l2(host(first[0]), O.nuasm3(geo, xs, ys, c, xd, yd)) <= 1e-5
+
+
 def test_batch_matches_plain_plans_bitwise(P):
     rng = np.random.default_rng(59)
     specs, xs, ys, ins, outs = [], [], [], [], []
