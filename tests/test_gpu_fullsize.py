@@ -101,3 +101,46 @@ def test_fullsize_nuasm1_spectral_samples(data, z, tf):
     err = rel_l2(got, ref)
     print(f"  rel-L2 on 512 spectral samples = {err:.3e}", flush=True)
     assert err <= 1e-5
+
+
+def test_fullsize_bench_graph_every_run(data):
+    """The benchmark's launch configuration itself: the 12 runs of a step
+    recorded as one batch graph on parallel branches (range check deferred),
+    run twice (recording, then a replay); every run's output checked against
+    the oracle on samples (128 destination points for NU-ASM_2, 128 in-band
+    frequencies for NU-ASM_1)."""
+    P, d = data["P"], data["d"]
+    specs, xs, ys, ins, outs = [], [], [], [], []
+    for z in (0.01, 0.1, 0.5):
+        for tf in ("asm", "fresnel"):
+            for t in (1, 2):
+                specs.append(dict(N=N, type=t, lam=LAM, z=z, g=G, tf=tf,
+                                  band="limited" if tf == "asm" else "full", ox=OX, oy=0.0, tol=1e-6))
+                xs.append(d["x1"] if t == 1 else d["x2"])
+                ys.append(d["y1"] if t == 1 else d["y2"])
+                ins.append(d["c1"] if t == 1 else d["u1"])
+                outs.append(torch.empty((2 * N, 2 * N) if t == 1 else (M,), dtype=torch.complex64,
+                                        device="cuda"))
+    print(f"fullsize bench graph: {len(specs)} runs, N={N} M={M}", flush=True)
+    b = P.Batch(specs)
+    b.run(xs, ys, ins, outs)
+    b.run(xs, ys, ins, outs)
+    assert b.check_points() == -1
+    sel = data["sel"][:128]
+    for p, s in enumerate(specs):
+        geo = _geo(s["z"], s["tf"])
+        H = O.transfer(geo)
+        if s["type"] == 2:
+            G2 = H * data["U"] / float(geo.Np) ** 2
+            ref = O.nuasm_oracle._type2_eval(geo, G2, data["x2"][sel], data["y2"][sel])
+            got = host(outs[p])[sel]
+        else:
+            (xlo, xhi), (ylo, yhi) = O.band_index_bounds(geo)
+            rs = np.random.default_rng(31 + p)
+            kx = rs.integers(xlo, xhi + 1, size=128)
+            ky = rs.integers(ylo, yhi + 1, size=128)
+            ref = H[ky + N, kx + N] * O.spectrum_at(geo, data["x1"], data["y1"], data["c1"], kx, ky)
+            got = type1_spectral_samples(host(outs[p]), kx, ky)
+        err = rel_l2(got, ref)
+        print(f"  run {p}: type {s['type']} z={s['z']} {s['tf']}: rel-L2 {err:.3e}", flush=True)
+        assert err <= 1e-5
