@@ -23,12 +23,14 @@ import numpy as np
 
 __all__ = [
     "rng_for", "unit_phase", "uniform_box", "clustered_box", "three_clusters",
-    "jittered_roi", "gaussian_blobs", "quadrant_grid", "experiment_field", "CONFIGS", "WORKLOAD_CFG2",
+    "jittered_roi", "gaussian_blobs", "quadrant_grid", "experiment_field", "WORKLOADS", "HEADLINE",
 ]
 
 
-def rng_for(cfg: int, rep: int = 0) -> np.random.Generator:
-    return np.random.default_rng(1000 * int(cfg) + int(rep))
+def rng_for(stream: int, rep: int = 0) -> np.random.Generator:
+    """Seeded generator of input stream `stream` (a workload's `seed`),
+    repetition `rep`: PCG64 seeded with 1000 stream + rep."""
+    return np.random.default_rng(1000 * int(stream) + int(rep))
 
 
 def unit_phase(rng: np.random.Generator, shape) -> np.ndarray:
@@ -181,29 +183,31 @@ def quadrant_grid(N: int, pitch: float, factors=(0.9, 0.8, 0.7, 1.0)):
     return np.concatenate(xs), np.concatenate(ys)
 
 
-# Workload table.  Each entry is plain data; the tests, the benchmark and the
-# smoke check read it.  Pitch, wavelength, band and offset follow the stated
-# workloads; where a workload leaves them open the values here fill them in.
-CONFIGS = {
-    1: dict(name="nuasm1_tiny_N64_M4096", N=64, g=8e-6, lam=532e-9, z=0.05,
-            ox=0.0, oy=0.0, tf="asm", band="full", tol=1e-6, M=4096,
-            points="uniform", types=(1,)),
-    2: dict(name="nuasm12_N1024_M1M_clustered", N=1024, g=4e-6, lam=633e-9,
-            zs=(0.01, 0.1, 0.5), ox=1e-3, oy=0.0, tfs=("asm", "fresnel"),
-            band="limited", tol=1e-6, M=1 << 20, points="clustered",
-            types=(1, 2)),
-    3: dict(name="nuasm2_N4096_M16M_roi", N=4096, g=4e-6, lam=532e-9, z=1.0,
-            ox=0.0, oy=0.0, tf="asm", band="limited", tols=(1e-3, 1e-6, 1e-9),
-            M=1 << 24, points="jittered_roi", types=(2,)),
-    4: dict(name="batched_64_planes", P=64, Ns=(256, 512, 1024, 2048), g=4e-6,
-            lam=633e-9, zrange=(0.005, 0.5), Mrange=(1e4, 2e6), ox=0.0, oy=0.0,
-            band="limited", tol=1e-6, points="clustered"),
-    5: dict(name="cgh_N2048_M4M", N=2048, g=4e-6, lam=532e-9, z=0.2, ox=0.0,
-            oy=0.0, tf="asm", band="limited", tol=1e-6, M=1 << 22,
-            points="three_clusters", types=(2,)),
+# Workload table, keyed by what each workload is.  Each entry is plain data;
+# the tests, the benchmark and the smoke check read it.  Pitch, wavelength,
+# band and offset follow the stated workloads; where a workload leaves them
+# open the values here fill them in.  `seed` is the stream number its inputs
+# are drawn from (rng_for).
+WORKLOADS = {
+    "nuasm1_tiny_N64_M4096": dict(seed=1, N=64, g=8e-6, lam=532e-9, z=0.05,
+                                  ox=0.0, oy=0.0, tf="asm", band="full", tol=1e-6, M=4096,
+                                  points="uniform", types=(1,)),
+    "nuasm12_N1024_M1M_clustered": dict(seed=2, N=1024, g=4e-6, lam=633e-9,
+                                        zs=(0.01, 0.1, 0.5), ox=1e-3, oy=0.0, tfs=("asm", "fresnel"),
+                                        band="limited", tol=1e-6, M=1 << 20, points="clustered",
+                                        types=(1, 2)),
+    "nuasm2_N4096_M16M_roi": dict(seed=3, N=4096, g=4e-6, lam=532e-9, z=1.0,
+                                  ox=0.0, oy=0.0, tf="asm", band="limited", tols=(1e-3, 1e-6, 1e-9),
+                                  M=1 << 24, points="jittered_roi", types=(2,)),
+    "batched_64_planes": dict(seed=4, P=64, Ns=(256, 512, 1024, 2048), g=4e-6,
+                              lam=633e-9, zrange=(0.005, 0.5), Mrange=(1e4, 2e6), ox=0.0, oy=0.0,
+                              band="limited", tol=1e-6, points="clustered"),
+    "cgh_N2048_M4M": dict(seed=5, N=2048, g=4e-6, lam=532e-9, z=0.2, ox=0.0,
+                          oy=0.0, tf="asm", band="limited", tol=1e-6, M=1 << 22,
+                          points="three_clusters", types=(2,)),
 }
 
-WORKLOAD_CFG2 = CONFIGS[2]
+HEADLINE = WORKLOADS["nuasm12_N1024_M1M_clustered"]
 
 
 def plane_width(N: int, g: float) -> float:

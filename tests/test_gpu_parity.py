@@ -135,13 +135,13 @@ def test_nuasm2_matches_oracle(P, case):
     assert rel_l2(got, ref) <= BOUND[tol]
 
 
-def test_cfg1_tiny_nuasm1(P):
+def test_tiny_nuasm1_N64_M4096(P):
     """N = 64 (N' = 128), M = 4096 uniform, pitch 8 um, 532 nm, z = 0.05 m,
     full band, tolerance 1e-6: the whole 128 x 128 output vs the oracle."""
-    cfg = synth.CONFIGS[1]
-    _say("cfg1", cfg["name"])
+    cfg = synth.WORKLOADS["nuasm1_tiny_N64_M4096"]
+    _say("tiny", cfg)
     geo = geometry(N=cfg["N"], g=cfg["g"], lam=cfg["lam"], z=cfg["z"], tf="asm", band="full")
-    rng = synth.rng_for(1)
+    rng = synth.rng_for(cfg["seed"])
     x, y = synth.uniform_box(rng, cfg["M"], cfg["N"] * cfg["g"])
     c = synth.unit_phase(rng, cfg["M"])
     plan = make_plan(P, geo, 1, tol=cfg["tol"])
