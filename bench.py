@@ -92,9 +92,13 @@ def cpu_baseline(host, n1=40960, n2=40960):
     n1 source points and NU-ASM_2 on the first n2 destination points of the
     same workload at z = 0.1 m, band-limited ASM (transfer function included)."""
     import oracle as O
+    blas = "unknown"
     try:
         from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        info = threadpool_info()
+        threads = max([i.get("num_threads", 1) for i in info] or [1])
+        blas = ",".join(sorted({f"{i.get('internal_api', '?')}-{i.get('version', '?')}" for i in info
+                                if i.get("user_api") == "blas"})) or blas
     except Exception:
         threads = os.cpu_count() or 1
     geo = O.Geometry(N=N, g=G, lam=LAM, z=0.1, ox=OX, oy=OY, tf="asm", band="limited")
@@ -104,6 +108,7 @@ def cpu_baseline(host, n1=40960, n2=40960):
     O.nuasm2(geo, host["u1"], host["x2"][:n2], host["y2"][:n2], H)
     dt = time.perf_counter() - t0
     return {"value": (n1 + n2) / dt, "unit": "points/s", "cores": int(threads), "kind": "oracle",
+            "blas": blas, "host_cpus": os.cpu_count(),
             "sample": f"FP64 direct-sum oracle, z=0.1 m band-limited ASM, N'=2048: NU-ASM_1 on "
                       f"{n1} source points + NU-ASM_2 on {n2} destination points, {dt:.1f} s wall",
             "seconds": dt}
