@@ -266,6 +266,76 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=5) -> float:
     return 2.0 * nbytes / (statistics.median(times) * 1e-3) / 1e9
 
 
+def cgh_workload(a, torch, P, synth):
+    """The hologram-phase optimisation configuration: NU-ASM_2 (band-limited
+    ASM) from a phase-only uniform source, N = 2048 (N' = 4096), to 2^22
+    destination points in three Gaussian clusters, 532 nm, z = 0.2 m,
+    tolerance 1e-6, target a sum of 32 Gaussian blobs scaled to the initial
+    intensity.  The points are bound once, as in an optimisation loop.  Timed
+    with HIP events: the forward operator, the hand-written adjoint (the
+    type-1 pipeline with conj H and the N x N crop) on a field of the same
+    size, and one whole iteration (phase to field, forward, loss, autograd
+    backward through the adjoint).  value = M / iteration time."""
+    import numpy as np
+    Nc, Gc, lam, z, Mc = 2048, 4e-6, 532e-9, 0.2, 1 << 22
+    rng = synth.rng_for(5, 1)
+    x, y = synth.three_clusters(rng, Mc, Nc * Gc)
+    phi0 = rng.uniform(0.0, 2.0 * np.pi, size=(Nc, Nc)).astype(np.float32)
+    T = synth.gaussian_blobs(rng, x, y, Nc * Gc)
+    plan = P.Plan(Nc, 2, lam, z, Gc, tf="asm", band="limited", tol=1e-6)
+    plan.set_points(torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda())
+    phi = torch.from_numpy(phi0).cuda().requires_grad_(True)
+    pd = phi.detach()
+    u1 = torch.polar(torch.ones_like(pd), pd)
+    with torch.no_grad():
+        u0 = plan.execute(u1)
+        s0 = float((u0.real.double() ** 2 + u0.imag.double() ** 2).sum())
+    T_t = torch.from_numpy(T * (s0 / float(T.sum()))).cuda()
+    out_f = torch.empty((Mc,), dtype=torch.complex64, device="cuda")
+    out_a = torch.empty((Nc, Nc), dtype=torch.complex64, device="cuda")
+
+    def forward():
+        plan.execute(u1, out_f)
+
+    def adjoint():
+        plan.adjoint(u0, out_a)
+
+    def iteration():
+        phi.grad = None
+        u = P.nuasm2(torch.polar(torch.ones_like(phi), phi), plan)
+        r = (u.real.double() ** 2 + u.imag.double() ** 2) - T_t
+        torch.sum(r * r).backward()
+
+    def timed(fn):
+        for _ in range(a.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(a.steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / a.steps
+
+    print(f"[bench] cgh: N'={2 * Nc}, M={Mc}", file=sys.stderr, flush=True)
+    f_ms, a_ms, it_ms = timed(forward), timed(adjoint), timed(iteration)
+    line = {
+        "metric": "CGH iteration non-uniform pts/sec (NU-ASM_2 forward + adjoint, autograd)",
+        "value": Mc / (it_ms * 1e-3), "unit": "points/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": it_ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "CGH phase optimisation: NU-ASM_2 band-limited ASM, N=2048 (N'=4096), "
+                               "M=2^22 points in three Gaussian clusters, 532 nm, z=0.2 m, tol 1e-6, "
+                               "points bound once",
+                   "N": Nc, "Np": 2 * Nc, "M": Mc},
+        "forward_ms": f_ms, "adjoint_ms": a_ms, "adjoint_over_forward": a_ms / f_ms,
+        "iteration_ms": it_ms,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def nuasm3_workload(a, torch, P, d):
     """NU-ASM_3 / NU-FRE_3 at the headline geometry: 2^20 clustered source
     points and 2^20 clustered destination points (the two point sets of the
@@ -596,13 +666,14 @@ def main(argv=None):
     ap.add_argument("--mode", choices=("graph", "sequential"), default="graph",
                     help="graph: the 12 runs of a step recorded as one HIP graph on parallel branches; "
                          "sequential: plain plans one after another on one stream")
-    ap.add_argument("--workload", choices=("n2048", "batched", "nuasm3", "paper", "scaled", "precision"),
+    ap.add_argument("--workload", choices=("n2048", "batched", "nuasm3", "paper", "scaled", "precision", "cgh"),
                     default="n2048",
                     help="n2048: the 12-run N'=2048 headline workload; batched: 64 mixed planes; "
                          "nuasm3: NU-ASM_3 with 2^20 source and 2^20 destination points, 6 runs; "
                          "paper: the paper's 256 x 256 experiment against Rayleigh-Sommerfeld; "
                          "scaled: a 2x zoom to a 2048 x 2048 destination grid; precision: NU-ASM_2 at "
-                         "N'=8192, M=2^24, z=1 m on the band-adaptive and the full fine grid")
+                         "N'=8192, M=2^24, z=1 m on the band-adaptive and the full fine grid; cgh: one "
+                         "hologram-optimisation iteration at N'=4096, M=2^22 (forward, adjoint timed beside)")
     ap.add_argument("--deterministic", action="store_true",
                     help="n2048 with NUASM_DETERMINISTIC on every plan (bitwise-reproducible runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -641,6 +712,8 @@ def main(argv=None):
         return scaled_workload(a, torch, P, synth)
     if a.workload == "precision":
         return precision_workload(a, torch, P, synth)
+    if a.workload == "cgh":
+        return cgh_workload(a, torch, P, synth)
     print(f"[bench] generating inputs N={N} M={M}", file=sys.stderr, flush=True)
     host, d = make_inputs(torch, synth)
     if a.workload == "nuasm3":
