@@ -180,22 +180,24 @@ def test_adjoints_match_oracle_and_dot_test(P, tf, band, z):
 
 
 # ------------------------------------------------------------- edge cases
-def test_empty_point_set(P):
-    _say("empty")
+@pytest.mark.parametrize("det", [False, True], ids=["default", "deterministic"])
+def test_empty_point_set(P, det):
+    _say("empty", det)
     geo = geometry(N=32, g=4e-6, lam=633e-9, z=0.01, tf="asm", band="limited")
     e = torch.empty(0, dtype=torch.float64, device="cuda")
-    p1 = make_plan(P, geo, 1)
+    p1 = make_plan(P, geo, 1, deterministic=det)
     p1.set_points(e, e)
     out = p1.execute(torch.empty(0, dtype=torch.complex64, device="cuda"))
     assert out.shape == (64, 64) and float(out.abs().max()) == 0.0
-    p2 = make_plan(P, geo, 2)
+    p2 = make_plan(P, geo, 2, deterministic=det)
     p2.set_points(e, e)
     out2 = p2.execute(torch.ones((32, 32), dtype=torch.complex64, device="cuda"))
     assert out2.shape == (0,)
 
 
-def test_points_on_window_edges(P):
-    _say("edges")
+@pytest.mark.parametrize("det", [False, True], ids=["default", "deterministic"])
+def test_points_on_window_edges(P, det):
+    _say("edges", det)
     N, g = 32, 4e-6
     geo = geometry(N=N, g=g, lam=633e-9, z=0.01, tf="asm", band="full")
     h = N * g / 2
@@ -204,19 +206,20 @@ def test_points_on_window_edges(P):
     rng = np.random.default_rng(5)
     c = synth.unit_phase(rng, x.size)
     for tol in (1e-6, 1e-9):
-        p1 = make_plan(P, geo, 1, tol=tol)
+        p1 = make_plan(P, geo, 1, tol=tol, deterministic=det)
         p1.set_points(dev(torch, x), dev(torch, y))
         assert rel_l2(host(p1.execute(dev(torch, c))), O.nuasm1(geo, x, y, c)) <= 1e-5
         u1 = synth.unit_phase(rng, (N, N))
-        p2 = make_plan(P, geo, 2, tol=tol)
+        p2 = make_plan(P, geo, 2, tol=tol, deterministic=det)
         p2.set_points(dev(torch, x), dev(torch, y))
         assert rel_l2(host(p2.execute(dev(torch, u1))), O.nuasm2(geo, u1, x, y)) <= 1e-5
 
 
-def test_out_of_range_and_not_ready(P):
-    _say("errors")
+@pytest.mark.parametrize("det", [False, True], ids=["default", "deterministic"])
+def test_out_of_range_and_not_ready(P, det):
+    _say("errors", det)
     geo = geometry(N=32, g=4e-6, lam=633e-9, z=0.01)
-    p = make_plan(P, geo, 1)
+    p = make_plan(P, geo, 1, deterministic=det)
     with pytest.raises(P.NuasmError) as ei:
         p.execute(torch.zeros(0, dtype=torch.complex64, device="cuda"))
     assert ei.value.name == "NUASM_ERR_NOT_READY"
@@ -229,7 +232,7 @@ def test_out_of_range_and_not_ready(P):
     with pytest.raises(P.NuasmError) as ei:
         p.execute(torch.zeros(0, dtype=torch.complex64, device="cuda"))
     assert ei.value.name == "NUASM_ERR_NOT_READY"
-    pd = make_plan(P, geo, 1, defer_range_check=True)
+    pd = make_plan(P, geo, 1, defer_range_check=True, deterministic=det)
     pd.set_points(x, y)
     with pytest.raises(P.NuasmError):
         pd.check_points()
