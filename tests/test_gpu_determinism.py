@@ -216,6 +216,31 @@ def test_deterministic_type3_and_adjoints(P):
     assert rel_l2(host(first[0]), O.nuasm3(geo, xs, ys, c, xd, yd)) <= 1e-5
 
 
+def test_deterministic_at_the_largest_grid(P):
+    """N' = 8192 on the full fine grid (257 x 257 bins, the largest bin keys
+    and histogram rows of the stable scatter), 2^24 jittered points: the
+    deterministic result equals itself bitwise on rebinding and the default
+    mode's to float32 rounding."""
+    N, M = 4096, 1 << 24
+    _say("deterministic, N'=8192, M=2^24, full fine grid")
+    geo = geometry(N=N, g=4e-6, lam=532e-9, z=1.0, tf="asm", band="limited")
+    rng = synth.rng_for(3, 0)
+    x, y = synth.jittered_roi(rng, N, geo.g, M=M)
+    xs, ys = dev(torch, x), dev(torch, y)
+    u1 = dev(torch, synth.unit_phase(rng, (N, N)))
+    pd = make_plan(P, geo, 2, deterministic=True, full_fine_grid=True, defer_range_check=True)
+    assert pd.info["tiles"] == 257 * 257
+    pd.set_points(xs, ys)
+    a = pd.execute(u1).clone()
+    pd.set_points(xs, ys)
+    assert torch.equal(pd.execute(u1), a)
+    pd.check_points()
+    del pd
+    p0 = make_plan(P, geo, 2, full_fine_grid=True, defer_range_check=True)
+    p0.set_points(xs, ys)
+    assert rel_l2(host(p0.execute(u1)), host(a)) <= 1e-6
+
+
 def test_batch_matches_plain_plans_bitwise(P):
     rng = np.random.default_rng(59)
     specs, xs, ys, ins, outs = [], [], [], [], []
