@@ -605,55 +605,59 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(SpreadArgs a) {
     }
     __syncthreads();
     // candidates: first taps in rows y0-(w-1) .. y0+1 and columns x0-(w-1) ..
-    // x0+1, i.e. w+1 contiguous runs of the sorted order, walked as one loop
-    int k = 0;
-    int row = x0;                      // soff index of run k: (ly + w - 1) * RS + x0, ly = y0 - (w-1) + k
-    row += y0 * RS;
-    int r = soff[row], re = soff[row + W + 1];
-    for (;;) {
-      if (r >= re) {
-        if (++k > W) break;
-        row += RS;
-        r = soff[row];
-        re = soff[row + W + 1];
-        continue;
+    // x0+1, i.e. w+1 contiguous runs of the sorted order.  Runs are walked in
+    // pairs as one sequence (positions 0 .. la-1 in run k, then run k+1), two
+    // candidates per step, so a wave steps as often as its longest pair needs
+    // rather than its longest run twice.
+#pragma unroll
+    for (int k = 0; k <= W; k += 2) {
+      const int rowA = x0 + (y0 + k) * RS;  // soff index of run k: (ly + w - 1) * RS + x0, ly = y0 - (w-1) + k
+      const int ra = soff[rowA], la = soff[rowA + W + 1] - ra;
+      int rb = 0, lb = 0;
+      if (k + 1 <= W) {
+        rb = soff[rowA + RS];
+        lb = soff[rowA + RS + W + 1] - rb;
       }
-      // two candidates of the run per iteration when it has them, so their
-      // LDS reads are in flight together; the second is masked by a zero value
-      const int dy = W - k;            // index of wy for output row y0
-      const bool two = r + 1 < re;
-      const int r2 = two ? r + 1 : r;
-      const int dxa = x0 - slx[r] + 1, dxb = x0 - slx[r2] + 1;
-      const float wa0 = swx[r][dxa], wa1 = swx[r][dxa + 1];
-      const float wb0 = swx[r2][dxb], wb1 = swx[r2][dxb + 1];
-      const float ya0 = swy[r][dy], ya1 = swy[r][dy + 1];
-      const float yb0 = swy[r2][dy], yb1 = swy[r2][dy + 1];
-      const float2 ca = sc[r];
-      float2 cb = sc[r2];
-      if (!two) cb = czero();
-      {
-        const float p0r = ca.x * ya0, p0i = ca.y * ya0, p1r = ca.x * ya1, p1i = ca.y * ya1;
-        a00.x += p0r * wa0;
-        a00.y += p0i * wa0;
-        a01.x += p0r * wa1;
-        a01.y += p0i * wa1;
-        a10.x += p1r * wa0;
-        a10.y += p1i * wa0;
-        a11.x += p1r * wa1;
-        a11.y += p1i * wa1;
+      const int n = la + lb;
+      const int shift = rb - la;  // position p >= la lies at record rb + (p - la)
+      for (int q = 0; q < n; q += 2) {
+        const bool inA = q < la, two = q + 1 < n, inA2 = q + 1 < la;
+        const int r = inA ? ra + q : shift + q;
+        const int r2 = !two ? r : (inA2 ? ra + q + 1 : shift + q + 1);
+        const int dya = inA ? W - k : W - k - 1;  // index of wy for output row y0
+        const int dyb = inA2 ? W - k : W - k - 1;
+        // the second candidate is masked by a zero value when there is none
+        const int dxa = x0 - slx[r] + 1, dxb = x0 - slx[r2] + 1;
+        const float wa0 = swx[r][dxa], wa1 = swx[r][dxa + 1];
+        const float wb0 = swx[r2][dxb], wb1 = swx[r2][dxb + 1];
+        const float ya0 = swy[r][dya], ya1 = swy[r][dya + 1];
+        const float yb0 = swy[r2][dyb], yb1 = swy[r2][dyb + 1];
+        const float2 ca = sc[r];
+        float2 cb = sc[r2];
+        if (!two) cb = czero();
+        {
+          const float p0r = ca.x * ya0, p0i = ca.y * ya0, p1r = ca.x * ya1, p1i = ca.y * ya1;
+          a00.x += p0r * wa0;
+          a00.y += p0i * wa0;
+          a01.x += p0r * wa1;
+          a01.y += p0i * wa1;
+          a10.x += p1r * wa0;
+          a10.y += p1i * wa0;
+          a11.x += p1r * wa1;
+          a11.y += p1i * wa1;
+        }
+        {
+          const float p0r = cb.x * yb0, p0i = cb.y * yb0, p1r = cb.x * yb1, p1i = cb.y * yb1;
+          a00.x += p0r * wb0;
+          a00.y += p0i * wb0;
+          a01.x += p0r * wb1;
+          a01.y += p0i * wb1;
+          a10.x += p1r * wb0;
+          a10.y += p1i * wb0;
+          a11.x += p1r * wb1;
+          a11.y += p1i * wb1;
+        }
       }
-      {
-        const float p0r = cb.x * yb0, p0i = cb.y * yb0, p1r = cb.x * yb1, p1i = cb.y * yb1;
-        a00.x += p0r * wb0;
-        a00.y += p0i * wb0;
-        a01.x += p0r * wb1;
-        a01.y += p0i * wb1;
-        a10.x += p1r * wb0;
-        a10.y += p1i * wb0;
-        a11.x += p1r * wb1;
-        a11.y += p1i * wb1;
-      }
-      r += 2;
     }
     __syncthreads();
   }
