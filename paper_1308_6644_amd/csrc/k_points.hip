@@ -625,8 +625,9 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(SpreadArgs a) {
         const int r = inA ? ra + q : shift + q;
         const int r2 = !two ? r : (inA2 ? ra + q + 1 : shift + q + 1);
         const int dya = inA ? W - k : W - k - 1;  // index of wy for output row y0
-        const int dyb = inA2 ? W - k : W - k - 1;
-        // the second candidate is masked by a zero value when there is none
+        // the second candidate, when there is none, repeats the first (so
+        // every read stays inside the staged rows) and is masked by a zero value
+        const int dyb = !two ? dya : (inA2 ? W - k : W - k - 1);
         const int dxa = x0 - slx[r] + 1, dxb = x0 - slx[r2] + 1;
         const float wa0 = swx[r][dxa], wa1 = swx[r][dxa + 1];
         const float wb0 = swx[r2][dxb], wb1 = swx[r2][dxb + 1];
