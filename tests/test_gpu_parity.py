@@ -99,6 +99,11 @@ OP_CASES = [
     # the narrowest and the widest kernels the tolerance range allows (w = 3 and w = 13)
     (64, 3000, "clustered", dict(g=4e-6, lam=633e-9, z=0.01, tf="asm", band="full"), 1e-2),
     (64, 3000, "clustered", dict(g=4e-6, lam=633e-9, z=0.01, tf="fresnel", ox=1e-5), 1e-12),
+    # back-propagation with the Fresnel transfer function and a 2-D offset
+    (128, 6000, "three_clusters", dict(g=4e-6, lam=532e-9, z=-0.04, tf="fresnel", ox=-2e-4, oy=1.5e-4), 1e-6),
+    # a narrow explicit band off the centre (the band-adaptive grid shrinks N'')
+    (128, 8000, "uniform", dict(g=4e-6, lam=633e-9, z=0.03, tf="asm", band="explicit",
+                                band_c=(-20.0, 9.0), band_w=(40.0, 26.0)), 1e-6),
 ]
 
 
