@@ -465,8 +465,9 @@ k_bin_scatter_det(const double* __restrict__ x, const double* __restrict__ y, in
 // on both sides).  Thread t owns a 2 x 2 block of the 32 x 32 bin in
 // registers and walks only the records whose w x w footprint covers it: first
 // taps in a (w+1) x (w+1) window, i.e. w+1 contiguous runs of the sorted
-// order.  Every grid cell is then written once.  A bin split into several
-// chunks writes per-chunk partial tiles that k_spread_reduce sums.
+// order, taken two runs at a time.  Every grid cell is then written once.  A
+// bin split into several chunks writes per-chunk partial tiles that
+// k_spread_reduce sums in chunk order.
 constexpr int kSpreadThreads = 256;
 
 template <int W>
