@@ -121,22 +121,15 @@ def batched_workload(a, torch, P, synth):
     step runs every plane one-shot, either as one recorded HIP graph (Batch)
     or as a sequential loop of plain plans on one stream."""
     import numpy as np
-    rng = synth.rng_for(4)
     specs, xs, ys, ins, outs = [], [], [], [], []
-    for p in range(64):
-        n = int(rng.choice([256, 512, 1024, 2048]))
-        m = synth.log_uniform_int(rng, 1e4, 2e6)
-        z = float(rng.uniform(0.005, 0.5))
-        t = int(rng.integers(1, 3))
-        tf = "asm" if rng.uniform() < 0.5 else "fresnel"
-        x, y = synth.clustered_box(rng, m, n * G)
-        inp = synth.unit_phase(rng, m if t == 1 else (n, n))
-        specs.append(dict(N=n, type=t, lam=633e-9, z=z, g=G, tf=tf,
-                          band="limited" if tf == "asm" else "full", tol=TOL))
-        xs.append(torch.from_numpy(x).cuda())
-        ys.append(torch.from_numpy(y).cuda())
-        ins.append(torch.from_numpy(np.ascontiguousarray(inp)).cuda())
-        outs.append(torch.empty((2 * n, 2 * n) if t == 1 else (m,), dtype=torch.complex64, device="cuda"))
+    for q in synth.batched_planes(g=G, tol=TOL):
+        s = q["spec"]
+        n, m = s["N"], q["x"].size
+        specs.append(s)
+        xs.append(torch.from_numpy(q["x"]).cuda())
+        ys.append(torch.from_numpy(q["y"]).cuda())
+        ins.append(torch.from_numpy(q["inp"]).cuda())
+        outs.append(torch.empty((2 * n, 2 * n) if s["type"] == 1 else (m,), dtype=torch.complex64, device="cuda"))
     total = sum(int(x.numel()) for x in xs)
     plans = [P.Plan(defer_range_check=True, **s) for s in specs]
     batch = P.Batch(specs)

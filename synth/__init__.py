@@ -24,6 +24,7 @@ import numpy as np
 __all__ = [
     "rng_for", "unit_phase", "uniform_box", "clustered_box", "three_clusters",
     "jittered_roi", "gaussian_blobs", "quadrant_grid", "experiment_field", "WORKLOADS", "HEADLINE",
+    "batched_planes",
 ]
 
 
@@ -229,3 +230,27 @@ def make_points(kind: str, rng: np.random.Generator, M: int, N: int, g: float):
 
 def log_uniform_int(rng: np.random.Generator, lo: float, hi: float) -> int:
     return int(math.floor(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+
+
+def batched_planes(P: int = 64, g: float = 4e-6, lam: float = 633e-9, tol: float = 1e-6):
+    """The 64-plane batched workload (input stream 4), drawn plane by plane in
+    one fixed order: N ~ U{256, 512, 1024, 2048}, M = floor(exp(U[ln 1e4,
+    ln 2e6])), z ~ U[0.005, 0.5] m, type ~ U{1, 2}, transfer function
+    ~ U{band-limited ASM, Fresnel}, clustered points in the N g window, then
+    the plane's input (c[M] for type 1, u1[N][N] for type 2).  Returns a list
+    of dicts: ``spec`` (keyword arguments of a plan: N, type, lam, z, g, tf,
+    band, tol) and the host arrays ``x``, ``y``, ``inp``."""
+    rng = rng_for(4)
+    planes = []
+    for _ in range(P):
+        n = int(rng.choice([256, 512, 1024, 2048]))
+        m = log_uniform_int(rng, 1e4, 2e6)
+        z = float(rng.uniform(0.005, 0.5))
+        t = int(rng.integers(1, 3))
+        tf = "asm" if rng.uniform() < 0.5 else "fresnel"
+        x, y = clustered_box(rng, m, n * g)
+        inp = unit_phase(rng, m if t == 1 else (n, n))
+        planes.append(dict(spec=dict(N=n, type=t, lam=lam, z=z, g=g, tf=tf,
+                                     band="limited" if tf == "asm" else "full", tol=tol),
+                           x=x, y=y, inp=np.ascontiguousarray(inp)))
+    return planes

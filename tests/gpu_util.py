@@ -42,3 +42,21 @@ def type1_spectral_samples(u2: np.ndarray, kx: np.ndarray, ky: np.ndarray) -> np
     ey = O.cis_cycles(-np.outer(n, ky) / Np)      # [ny, s]
     a = u2 @ ex                                   # [ny, s]
     return np.sum(ey * a, axis=0)
+
+
+def check_close(got, ref, bound: float, what: str = "", k: float = 10.0) -> float:
+    """Element-wise and whole-array agreement: rel-L2 <= bound, and every
+    element within k * bound * rms(ref) of the reference (a localised defect
+    on a few bins or window-edge points fails the second even when the norm
+    hides it).  Returns the rel-L2."""
+    got = np.asarray(got).astype(np.complex128)
+    ref = np.asarray(ref).astype(np.complex128)
+    assert got.shape == ref.shape, (what, got.shape, ref.shape)
+    d = np.abs(got - ref).ravel()
+    rms = float(np.sqrt(np.mean(np.abs(ref.ravel()) ** 2))) if ref.size else 0.0
+    rel = O.rel_l2(got, ref) if ref.size and rms > 0 else float(d.max(initial=0.0))
+    assert rel <= bound, f"{what} rel-L2 {rel:.3e} > {bound:.1e}"
+    worst = float(d.max(initial=0.0))
+    assert worst <= k * bound * rms, (f"{what} max |err| {worst:.3e} > {k:g} * {bound:.1e} * rms(ref) "
+                                      f"= {k * bound * rms:.3e} (at element {int(np.argmax(d))})")
+    return rel

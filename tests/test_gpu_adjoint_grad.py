@@ -7,7 +7,7 @@ import pytest
 
 import oracle as O
 import synth
-from gpu_util import dev, geometry, host, make_plan, rel_l2
+from gpu_util import check_close, dev, geometry, host, make_plan, rel_l2
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -50,10 +50,10 @@ def test_cgh_gradient_matches_oracle(P):
     loss.backward()
     g_gpu = phi_t.grad.detach().cpu().numpy().astype(np.float64)
     g_ref = O.cgh_grad(geo, phi.astype(np.float64), x, y, T, H)
-    err = rel_l2(g_gpu, g_ref)
+    err = check_close(g_gpu, g_ref, 1e-4)
     cos = float(np.dot(g_gpu.ravel(), g_ref.ravel()) / np.linalg.norm(g_gpu) / np.linalg.norm(g_ref))
     print(f"  rel-L2 {err:.3e} cosine {cos:.8f}", flush=True)
-    assert err <= 1e-4 and cos >= 0.99999
+    assert cos >= 0.99999
 
 
 def test_cgh_gradient_central_differences_full_size(P):
@@ -127,7 +127,7 @@ def test_type1_autograd_is_adjoint(P):
     loss.backward()
     # torch's gradient of a real loss w.r.t. complex c is 2 dL/d(conj c) = 2 A^H (A c - v)
     ref = 2.0 * O.nuasm1_adjoint(geo, O.nuasm1(geo, x, y, c) - v, x, y)
-    assert rel_l2(host(ct.grad), ref) <= 1e-5
+    check_close(host(ct.grad), ref, 1e-5)
 
 
 def test_phase_optimisation_reduces_loss(P):

@@ -10,7 +10,7 @@ import pytest
 
 import oracle as O
 import synth
-from gpu_util import dev, geometry, host, make_plan, rel_l2
+from gpu_util import check_close, dev, geometry, host, make_plan, rel_l2
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -73,8 +73,8 @@ def test_band_grid_types_1_2_3_and_adjoints(P, case):
             O.nuasm1_adjoint(geo, v, x1, y1), O.nuasm2_adjoint(geo, w2, x2, y2),
             O.nuasm3_adjoint(geo, w2, x1, y1, x2, y2)]
     for k, ref in enumerate(refs):
-        assert rel_l2(outs[False][k], ref) <= 1e-5, k
-        assert rel_l2(outs[False][k], outs[True][k]) <= 3e-6, k
+        check_close(outs[False][k], ref, 1e-5, what=str(k))
+        check_close(outs[False][k], outs[True][k], 3e-6, what=str(k))
 
 
 def test_band_grid_with_grid_points(P):
@@ -89,11 +89,11 @@ def test_band_grid_with_grid_points(P):
     assert plan.info["Npf"] == 64
     plan.set_grid_points(150, 130, 1.3 * geo.g, 2 * geo.g, -3 * geo.g)
     x, y = O.grid_points(150, 130, 1.3 * geo.g, 2 * geo.g, -3 * geo.g)
-    assert rel_l2(host(plan.execute(dev(torch, u1))), O.nuasm2(geo, u1, x, y)) <= 1e-5
+    check_close(host(plan.execute(dev(torch, u1))), O.nuasm2(geo, u1, x, y), 1e-5)
     c = synth.unit_phase(rng, 150 * 130)
     p1 = make_plan(P, geo, 1)
     p1.set_grid_points(150, 130, 1.3 * geo.g, 2 * geo.g, -3 * geo.g)
-    assert rel_l2(host(p1.execute(dev(torch, c))), O.nuasm1(geo, x, y, c)) <= 1e-5
+    check_close(host(p1.execute(dev(torch, c))), O.nuasm1(geo, x, y, c), 1e-5)
 
 
 def test_band_grid_choice(P):

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_util import dev, host, rel_l2
+from gpu_util import check_close, dev, host, rel_l2
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -55,7 +55,6 @@ def test_batch_matches_plain_plans_and_replays(capfd):
         b.run(xs, ys, ins, outs)
         assert b.check_points() == -1
         for p, (o, r) in enumerate(zip(outs, refs)):
-            err = rel_l2(host(o), r)
-            assert err <= 1e-6, (rep, p, specs[p], err)
+            err = check_close(host(o), r, 1e-6, what=str((rep, p, specs[p])))
     t = b.plane_times()
     assert len(t) == len(specs) and all(v > 0 for v in t)

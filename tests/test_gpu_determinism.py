@@ -16,7 +16,7 @@ import pytest
 
 import oracle as O
 import synth
-from gpu_util import dev, geometry, host, make_plan, rel_l2
+from gpu_util import check_close, dev, geometry, host, make_plan, rel_l2
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -123,7 +123,7 @@ def test_deterministic_runs_are_bitwise_equal(P, t):
     _, b = _run(P, geo, t, x, y, inp, deterministic=True)
     assert torch.equal(a, b)
     _, c = _run(P, geo, t, x, y, inp)
-    assert rel_l2(host(a), host(c)) <= 1e-6
+    check_close(host(a), host(c), 1e-6)
 
 
 @pytest.mark.parametrize("t", [1, 2])
@@ -140,7 +140,7 @@ def test_deterministic_matches_oracle(P, t):
         u1 = synth.unit_phase(rng, (N, N))
         ref, inp = O.nuasm2(geo, u1, x, y), u1
     _, got = _run(P, geo, t, x, y, inp, deterministic=True)
-    assert rel_l2(host(got), ref) <= 1e-5
+    check_close(host(got), ref, 1e-5)
 
 
 @pytest.mark.parametrize("t", [1, 2])
@@ -163,7 +163,7 @@ def test_dense_bin_deterministic(P, t):
     plan.set_points(dev(torch, x), dev(torch, y))
     assert torch.equal(plan.execute(dev(torch, inp)), a)
     ref = O.nuasm1(geo, x, y, inp) if t == 1 else O.nuasm2(geo, inp, x, y)
-    assert rel_l2(host(a), ref) <= 1e-5
+    check_close(host(a), ref, 1e-5)
 
 
 def test_deterministic_ranges_and_a_very_dense_bin(P):
@@ -186,7 +186,7 @@ def test_deterministic_ranges_and_a_very_dense_bin(P):
     assert torch.equal(plan.execute(c), a)
     ref = make_plan(P, geo, 1)
     ref.set_points(zc, zc)
-    assert rel_l2(host(ref.execute(c)), host(a)) <= 1e-5
+    check_close(host(ref.execute(c)), host(a), 1e-5)
 
 
 def test_deterministic_type3_and_adjoints(P):
@@ -213,7 +213,7 @@ def test_deterministic_type3_and_adjoints(P):
     first, second = run(), run()
     for a, b in zip(first, second):
         assert torch.equal(a, b)
-    assert rel_l2(host(first[0]), O.nuasm3(geo, xs, ys, c, xd, yd)) <= 1e-5
+    check_close(host(first[0]), O.nuasm3(geo, xs, ys, c, xd, yd), 1e-5)
 
 
 def test_deterministic_at_the_largest_grid(P):
@@ -238,7 +238,7 @@ def test_deterministic_at_the_largest_grid(P):
     del pd
     p0 = make_plan(P, geo, 2, full_fine_grid=True, defer_range_check=True)
     p0.set_points(xs, ys)
-    assert rel_l2(host(p0.execute(u1)), host(a)) <= 1e-6
+    check_close(host(p0.execute(u1)), host(a), 1e-6)
 
 
 def test_batch_matches_plain_plans_bitwise(P):

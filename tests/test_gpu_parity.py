@@ -12,7 +12,7 @@ import pytest
 
 import oracle as O
 import synth
-from gpu_util import dev, geometry, host, make_plan, rel_l2, type1_spectral_samples
+from gpu_util import check_close, dev, geometry, host, make_plan, rel_l2, type1_spectral_samples
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -45,7 +45,7 @@ def test_stockham_fft_matches_numpy(P, logn, sign):
     xd = x.astype(np.complex128)
     ref = np.fft.fft(xd, axis=-1) if sign < 0 else np.fft.ifft(xd, axis=-1) * n
     # float32 Stockham: error grows like eps32 * sqrt(log2 n)
-    assert rel_l2(got, ref) < 2e-6
+    check_close(got, ref, 2e-6)
 
 
 # ---------------------------------------------------- transfer function
@@ -123,7 +123,7 @@ def test_nuasm1_matches_oracle(P, case):
     plan.set_points(dev(torch, x), dev(torch, y))
     got = host(plan.execute(dev(torch, c)))
     ref = O.nuasm1(geo, x, y, c)
-    assert rel_l2(got, ref) <= BOUND[tol]
+    check_close(got, ref, BOUND[tol])
 
 
 @pytest.mark.parametrize("case", OP_CASES, ids=_id)
@@ -137,7 +137,7 @@ def test_nuasm2_matches_oracle(P, case):
     plan.set_points(dev(torch, x), dev(torch, y))
     got = host(plan.execute(dev(torch, u1)))
     ref = O.nuasm2(geo, u1, x, y)
-    assert rel_l2(got, ref) <= BOUND[tol]
+    check_close(got, ref, BOUND[tol])
 
 
 def test_tiny_nuasm1_N64_M4096(P):
@@ -153,7 +153,7 @@ def test_tiny_nuasm1_N64_M4096(P):
     plan.set_points(dev(torch, x), dev(torch, y))
     got = host(plan.execute(dev(torch, c)))
     assert got.shape == (128, 128)
-    assert rel_l2(got, O.nuasm1(geo, x, y, c)) <= 1e-5
+    check_close(got, O.nuasm1(geo, x, y, c), 1e-5)
 
 
 # --------------------------------------------------------------- adjoints
@@ -174,8 +174,8 @@ def test_adjoints_match_oracle_and_dot_test(P, tf, band, z):
     u1 = synth.unit_phase(rng, (N, N))
     a1 = host(p1.adjoint(dev(torch, v)))
     a2 = host(p2.adjoint(dev(torch, w)))
-    assert rel_l2(a1, O.nuasm1_adjoint(geo, v, x, y)) <= 1e-5
-    assert rel_l2(a2, O.nuasm2_adjoint(geo, w, x, y)) <= 1e-5
+    check_close(a1, O.nuasm1_adjoint(geo, v, x, y), 1e-5)
+    check_close(a2, O.nuasm2_adjoint(geo, w, x, y), 1e-5)
     f1 = host(p1.execute(dev(torch, c)))
     f2 = host(p2.execute(dev(torch, u1)))
     lhs, rhs = np.vdot(v, f1), np.vdot(a1, c.astype(np.complex128))
@@ -213,11 +213,11 @@ def test_points_on_window_edges(P, det):
     for tol in (1e-6, 1e-9):
         p1 = make_plan(P, geo, 1, tol=tol, deterministic=det)
         p1.set_points(dev(torch, x), dev(torch, y))
-        assert rel_l2(host(p1.execute(dev(torch, c))), O.nuasm1(geo, x, y, c)) <= 1e-5
+        check_close(host(p1.execute(dev(torch, c))), O.nuasm1(geo, x, y, c), 1e-5)
         u1 = synth.unit_phase(rng, (N, N))
         p2 = make_plan(P, geo, 2, tol=tol, deterministic=det)
         p2.set_points(dev(torch, x), dev(torch, y))
-        assert rel_l2(host(p2.execute(dev(torch, u1))), O.nuasm2(geo, u1, x, y)) <= 1e-5
+        check_close(host(p2.execute(dev(torch, u1))), O.nuasm2(geo, u1, x, y), 1e-5)
 
 
 @pytest.mark.parametrize("det", [False, True], ids=["default", "deterministic"])
@@ -257,13 +257,13 @@ def test_dense_bin_multi_chunk(P):
     c = synth.unit_phase(rng, M)
     p1 = make_plan(P, geo, 1)
     p1.set_points(dev(torch, x), dev(torch, y))
-    assert rel_l2(host(p1.execute(dev(torch, c))), O.nuasm1(geo, x, y, c)) <= 1e-5
+    check_close(host(p1.execute(dev(torch, c))), O.nuasm1(geo, x, y, c), 1e-5)
     u1 = synth.unit_phase(rng, (N, N))
     p2 = make_plan(P, geo, 2)
     p2.set_points(dev(torch, x), dev(torch, y))
-    assert rel_l2(host(p2.execute(dev(torch, u1))), O.nuasm2(geo, u1, x, y)) <= 1e-5
+    check_close(host(p2.execute(dev(torch, u1))), O.nuasm2(geo, u1, x, y), 1e-5)
     w = synth.unit_phase(rng, M)
-    assert rel_l2(host(p2.adjoint(dev(torch, w))), O.nuasm2_adjoint(geo, w, x, y)) <= 1e-5
+    check_close(host(p2.adjoint(dev(torch, w))), O.nuasm2_adjoint(geo, w, x, y), 1e-5)
 
 
 def test_crop_output(P):
@@ -276,7 +276,8 @@ def test_crop_output(P):
     p.set_points(dev(torch, x), dev(torch, y))
     got = host(p.execute(dev(torch, c)))
     ref = O.nuasm1(geo, x, y, c)[N // 2:3 * N // 2, N // 2:3 * N // 2]
-    assert got.shape == (N, N) and rel_l2(got, ref) <= 1e-5
+    assert got.shape == (N, N)
+    check_close(got, ref, 1e-5)
 
 
 def test_repeated_execute_is_stable(P):
@@ -291,7 +292,7 @@ def test_repeated_execute_is_stable(P):
     p.set_points(dev(torch, x), dev(torch, y))
     a = host(p.execute(c))
     for _ in range(5):
-        assert rel_l2(host(p.execute(c)), a) <= 1e-6
+        check_close(host(p.execute(c)), a, 1e-6)
 
 
 
@@ -317,7 +318,7 @@ def test_stream_change_orders_after_previous_work(P):
         out = p.execute(cd)
         got = out.cpu()
     torch.cuda.synchronize()
-    assert rel_l2(got.numpy(), ref) <= 1e-5
+    check_close(got.numpy(), ref, 1e-5)
 
 def test_stage_timing_counts_every_kernel(P):
     """Stage timing records one (start, end) pair per launch on the plan's

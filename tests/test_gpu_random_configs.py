@@ -11,7 +11,7 @@ import pytest
 
 import oracle as O
 import synth
-from gpu_util import dev, geometry, host, make_plan, rel_l2
+from gpu_util import check_close, dev, geometry, host, make_plan, rel_l2
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -65,6 +65,5 @@ def test_random_configuration_matches_oracle(P, c):
         plan.set_dest_points(dev(torch, x2), dev(torch, y2))
         v = synth.unit_phase(rng, c["M"])
         got, ref = plan.execute(dev(torch, v)), O.nuasm3(geo, x, y, v, x2, y2)
-    err = rel_l2(host(got), ref)
+    err = check_close(host(got), ref, BOUND[c["tol"]])
     print(f"  rel-L2 {err:.3e}", flush=True)
-    assert err <= BOUND[c["tol"]]

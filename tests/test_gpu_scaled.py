@@ -14,7 +14,7 @@ import pytest
 
 import oracle as O
 import synth
-from gpu_util import dev, geometry, host, make_plan, rel_l2
+from gpu_util import check_close, dev, geometry, host, make_plan, rel_l2
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -63,14 +63,14 @@ def test_scaled_type2_matches_oracle_and_binned_path(P, case):
     got = host(plan.execute(dev(torch, u1)))
     x, y = O.grid_points(nx, ny, pitch, cx, cy)
     ref = O.nuasm2(geo, u1, x, y)
-    assert rel_l2(got, ref) <= BOUND[tol]
+    check_close(got, ref, BOUND[tol])
     binned = make_plan(P, geo, 2, tol=tol)
     binned.set_points(dev(torch, x), dev(torch, y))
-    assert rel_l2(got, host(binned.execute(dev(torch, u1)))) <= 2e-6
+    check_close(got, host(binned.execute(dev(torch, u1))), 2e-6)
     # adjoint: grid values -> N x N plane
     w = synth.unit_phase(rng, nx * ny)
     a = host(plan.adjoint(dev(torch, w)))
-    assert rel_l2(a, O.nuasm2_adjoint(geo, w, x, y)) <= BOUND[tol]
+    check_close(a, O.nuasm2_adjoint(geo, w, x, y), BOUND[tol])
 
 
 @pytest.mark.parametrize("case", CASES[:4], ids=_id)
@@ -87,9 +87,9 @@ def test_scaled_type1_source_grid(P, case):
     plan.set_grid_points(nx, ny, pitch, cx, cy)
     got = host(plan.execute(dev(torch, c)))
     x, y = O.grid_points(nx, ny, pitch, cx, cy)
-    assert rel_l2(got, O.nuasm1(geo, x, y, c)) <= BOUND[tol]
+    check_close(got, O.nuasm1(geo, x, y, c), BOUND[tol])
     v = synth.unit_phase(rng, (2 * N, 2 * N))
-    assert rel_l2(host(plan.adjoint(dev(torch, v))), O.nuasm1_adjoint(geo, v, x, y)) <= BOUND[tol]
+    check_close(host(plan.adjoint(dev(torch, v))), O.nuasm1_adjoint(geo, v, x, y), BOUND[tol])
 
 
 def test_scaled_type3_grids(P):
@@ -105,14 +105,14 @@ def test_scaled_type3_grids(P):
     plan.set_points(dev(torch, x1), dev(torch, y1))
     plan.set_grid_points(70, 50, 0.8 * geo.g, 2 * geo.g, -1 * geo.g, dest=True)
     x2, y2 = O.grid_points(70, 50, 0.8 * geo.g, 2 * geo.g, -1 * geo.g)
-    assert rel_l2(host(plan.execute(dev(torch, c))), O.nuasm3(geo, x1, y1, c, x2, y2)) <= 1e-5
+    check_close(host(plan.execute(dev(torch, c))), O.nuasm3(geo, x1, y1, c, x2, y2), 1e-5)
     plan.set_grid_points(40, 44, 1.3 * geo.g, -3 * geo.g, 0.0)
     xs, ys = O.grid_points(40, 44, 1.3 * geo.g, -3 * geo.g, 0.0)
     cs = synth.unit_phase(rng, 40 * 44)
-    assert rel_l2(host(plan.execute(dev(torch, cs))), O.nuasm3(geo, xs, ys, cs, x2, y2)) <= 1e-5
+    check_close(host(plan.execute(dev(torch, cs))), O.nuasm3(geo, xs, ys, cs, x2, y2), 1e-5)
     # rebinding scattered points replaces the grid
     plan.set_points(dev(torch, x1), dev(torch, y1))
-    assert rel_l2(host(plan.execute(dev(torch, c))), O.nuasm3(geo, x1, y1, c, x2, y2)) <= 1e-5
+    check_close(host(plan.execute(dev(torch, c))), O.nuasm3(geo, x1, y1, c, x2, y2), 1e-5)
 
 
 def test_scaled_grid_errors_and_empty(P):
@@ -157,6 +157,5 @@ def test_scaled_fullsize_zoom(P):
     sel = np.random.default_rng(4096).choice(x.size, size=512, replace=False)
     U = O.uniform_spectrum(u1, 2 * N, "fft")
     ref = O.nuasm2_from_spectrum(geo, U, x[sel], y[sel])
-    err = rel_l2(got[sel], ref)
+    err = check_close(got[sel], ref, 1e-5)
     _say(f"  sampled rel-L2 {err:.3e}")
-    assert err <= 1e-5

@@ -10,7 +10,7 @@ import pytest
 
 import oracle as O
 import synth
-from gpu_util import dev, geometry, host, make_plan, rel_l2
+from gpu_util import check_close, dev, geometry, host, make_plan, rel_l2
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -58,7 +58,7 @@ def test_tuned_shapes_match_oracle(P, tuning, tol):
             assert info["interp_chunk"] == tuning["interp_chunk"]
         if tuning.get("spread_chunk"):
             assert info["spread_chunk"] == (896 if tol == 1e-6 else 1024)
-        assert rel_l2(host(plan.execute(dev(torch, inp))), ref) <= bound
+        check_close(host(plan.execute(dev(torch, inp))), ref, bound)
 
 
 def test_set_tuning_requires_rebinding(P):
@@ -105,7 +105,7 @@ def test_tuning_while_grid_bound_resizes_tables(P):
         plan.set_tuning(spread_chunk=896, interp_chunk=256, bin_range_points=1024)
         plan.set_points(dev(torch, x), dev(torch, y))
         assert plan.info["interp_chunk"] == 256
-        assert rel_l2(host(plan.execute(dev(torch, inp))), ref) <= 1e-5
+        check_close(host(plan.execute(dev(torch, inp))), ref, 1e-5)
 
 def test_autotuner_batch(P, tmp_path):
     """Tune a small mixed batch into a fresh cache, check the cache and the
@@ -138,7 +138,7 @@ def test_autotuner_batch(P, tmp_path):
         plain = P.Plan(**s)
         plain.set_points(xs[p], ys[p])
         ref = host(plain.execute(ins[p]))
-        assert rel_l2(host(outs[p]), ref) <= 2e-6
+        check_close(host(outs[p]), ref, 2e-6)
     # a second batch of the same shapes takes everything from the cache
     b2 = P.Batch(specs)
     assert tune.apply_cached(b2, specs, [x.numel() for x in xs], tune.TuneCache(str(tmp_path / "tune.json"))) == 6
@@ -147,6 +147,6 @@ def test_autotuner_batch(P, tmp_path):
         b2.set_branches(k)
         b2.run(xs, ys, ins, outs2)
         for p in range(6):
-            assert rel_l2(host(outs2[p]), host(outs[p])) <= 2e-6
+            check_close(host(outs2[p]), host(outs[p]), 2e-6)
     with pytest.raises(P.NuasmError):
         b2.set_branches(5)

@@ -103,6 +103,84 @@ def test_band_edges_satisfy_local_frequency_condition(z, ox, oy):
         assert ok(mid, o)
 
 
+# explicit Rect of Eq. 4: (centre, width) pairs in index units, chosen so that
+# every comparison below is exact in binary floating point
+EXPLICIT_CASES = [
+    ((10.5, -3.0), (40.0, 61.0)),     # half-integer centre, odd width: both edges on K
+    ((10.5, 2.25), (3.0, 0.5)),       # edges exactly at +-1.5 and +-0.25 from the centre
+    ((7.0, -4.0), (0.0, 0.0)),        # w = 0 at an integer centre: one index per axis
+    ((7.5, -4.25), (0.0, 0.0)),       # w = 0 off the integers: empty
+    ((30.0, -29.5), (20.0, 9.0)),     # crosses the top (x) and the bottom (y) of K: clipped
+    ((-3.75, 0.0), (200.0, 1.0)),     # wider than K on x
+]
+
+
+@pytest.mark.parametrize("c,w", EXPLICIT_CASES)
+def test_explicit_band_is_the_closed_interval_around_the_centre(c, w):
+    """Explicit band of Eq. 4: per axis k is kept iff |k - c| <= w/2 (edges
+    inclusive), clipped to K.  Checked index by index against that
+    inequality, not through the ceil/floor bounds the oracle computes."""
+    geo = _geo(N=32, band="explicit", band_c=c, band_w=w)
+    K = O.freq_index(geo.Np)
+    mask = O.band_mask(geo)
+    for axis in (0, 1):
+        keep = np.array([abs(k - c[axis]) <= 0.5 * w[axis] for k in K])
+        got = mask.any(axis=0) if axis == 0 else mask.any(axis=1)
+        assert np.array_equal(got, keep), (axis, c, w)
+    # the mask is the outer product of the two axes
+    keep_x = np.array([abs(k - c[0]) <= 0.5 * w[0] for k in K])
+    keep_y = np.array([abs(k - c[1]) <= 0.5 * w[1] for k in K])
+    assert np.array_equal(mask, keep_y[:, None] & keep_x[None, :])
+    if w == (0.0, 0.0) and float(c[0]).is_integer() and float(c[1]).is_integer():
+        assert mask.sum() == 1
+
+
+def _local_frequency_edge(geo, o, target):
+    """Frequency f (m^-1) where the local spatial frequency of H's phase,
+    o - z f / s(f), equals `target`, by bisection on the monotone map
+    f -> z f / s(f) (an independent route to the closed-form edges)."""
+    lo, hi = -0.999999 / geo.lam, 0.999999 / geo.lam
+
+    def u(f):
+        return geo.z * f / math.sqrt(1.0 / geo.lam ** 2 - f * f)
+
+    want = o - target
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if (u(mid) < want) == (geo.z > 0):
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+@pytest.mark.parametrize("z,ox,oy", [(0.1, 1e-3, 0.0), (0.5, -1e-3, 2e-4), (-0.2, 3e-4, -5e-4),
+                                     (0.3, -7.3e-4, 6.1e-4)])
+def test_explicit_band_from_limited_edges_reproduces_limited_mask(z, ox, oy):
+    """The limited band of Eq. 4 written as an explicit (c, w) pair: the band
+    edges f_lo, f_hi (where the local frequency reaches +-S) give
+    c = (f_lo + f_hi) / (2 df) and w = (f_hi - f_lo) / df.  An explicit plan
+    with that centre and width must keep exactly the limited plan's
+    frequencies on both axes, for offsets of both signs and both signs of z."""
+    base = dict(N=1024, g=4e-6, lam=633e-9, z=z, ox=ox, oy=oy)
+    lim = _geo(band="limited", **base)
+    S = lim.N * lim.g
+    cs, ws = [], []
+    for o in (ox, oy):
+        f1 = _local_frequency_edge(lim, o, S)
+        f2 = _local_frequency_edge(lim, o, -S)
+        flo, fhi = min(f1, f2), max(f1, f2)
+        # the edges must not sit on an integer index (a rounding there could
+        # legitimately flip a boundary frequency)
+        for f in (flo, fhi):
+            assert abs(f / lim.df - round(f / lim.df)) > 1e-6
+        cs.append((flo + fhi) / (2.0 * lim.df))
+        ws.append((fhi - flo) / lim.df)
+    exp = _geo(band="explicit", band_c=tuple(cs), band_w=tuple(ws), **base)
+    assert np.array_equal(O.band_mask(exp), O.band_mask(lim))
+    assert O.band_index_bounds(exp) == O.band_index_bounds(lim)
+
+
 def test_fresnel_separable_equals_direct_2d_dft():
     geo = _geo(N=8, g=5e-6, lam=500e-9, z=0.002, ox=7e-6, oy=-3e-6, tf="fresnel")
     H = O.transfer_fresnel(geo)
