@@ -140,7 +140,11 @@ typedef struct {
                                  else 256 .. 65536 */
   int32_t bin_range_points;   /* points per binning workgroup: 0 = automatic
                                  (max(4096, M/256), at most 65535), else 1024 .. 65535 */
-  int32_t reserved;           /* must be 0 */
+  int32_t spread_method;      /* 0 = automatic (LDS scatter; the gather form in
+                                 deterministic mode), 1 = gather (each output cell
+                                 sums the records covering it, in registers),
+                                 2 = LDS scatter (float atomic adds into an LDS
+                                 tile; not allowed in deterministic mode) */
 } nuasm_tuning;
 
 typedef struct nuasm_plan_s* nuasm_plan;
@@ -175,6 +179,29 @@ nuasm_status nuasm_plan_get_info(nuasm_plan plan, nuasm_plan_info* info);
  * summation order.  Binned point sets must be bound again afterwards
  * (execute returns NUASM_ERR_NOT_READY until then); grids stay bound. */
 nuasm_status nuasm_plan_set_tuning(nuasm_plan plan, const nuasm_tuning* t);
+
+/* Caller-owned workspace (e.g. memory from a framework's caching allocator).
+ * nuasm_plan_workspace_bytes: bytes a workspace needs so that every point set
+ * of the plan (type 3: each of the two) can hold M_max points, for the plan's
+ * current tuning: the two grid buffers of the pipelines of Eqs. 6 and 9 and
+ * the point-count-dependent buffers of the binning (records, chunk tables,
+ * per-range histograms, partial tiles of split bins).  0 <= M_max < 2^29.
+ * nuasm_plan_set_workspace: carve those buffers from the device memory `dev`
+ * (256-byte aligned, `bytes` long, caller-owned: it must stay valid and
+ * otherwise unused until the plan is destroyed or given another workspace).
+ * The plan frees its own copies of them and from then on allocates none of
+ * them; its capacity becomes the largest point count per set that fits, and
+ * set_points with more points returns NUASM_ERR_INVALID_ARG.  dev = NULL goes
+ * back to plan-owned memory.  Binned point sets must be bound again
+ * afterwards (execute returns NUASM_ERR_NOT_READY until then).  Small
+ * T-sized bin arrays, the plan's tables and the buffers of a grid bound with
+ * nuasm_set_grid_points stay plan-owned (nuasm_plan_info.device_bytes counts
+ * what the plan itself holds).  A nuasm_plan_set_tuning that changes the sizes
+ * carves the workspace again (and fails, keeping the old tuning, if the new
+ * minimum does not fit).  Synchronises the plan's stream.  Errors:
+ * NUASM_ERR_INVALID_ARG (misaligned, or below the minimum for 1024 points). */
+nuasm_status nuasm_plan_workspace_bytes(nuasm_plan plan, int64_t M_max, size_t* bytes);
+nuasm_status nuasm_plan_set_workspace(nuasm_plan plan, void* dev, size_t bytes);
 
 /* Coordinate normalisation and binning of the non-uniform plane (Fig. 1 and
  * the text around Eqs. 7-9): M points x_dev[M], y_dev[M] (device FP64
@@ -328,6 +355,19 @@ nuasm_status nuasm_batch_destroy(nuasm_batch batch);  /* NULL-safe */
  * only launch it.  Never synchronises the host. */
 nuasm_status nuasm_batch_run(nuasm_batch batch, const int64_t* M, const double* const* x,
                              const double* const* y, const void* const* in, void* const* out);
+/* The same work in two steps, for many operator runs on points bound once
+ * (the iterations of a hologram optimisation over many planes): binning of
+ * every plane's points (M[p], x[p], y[p] as above), recorded as one graph on
+ * first use, then the operators of every plane (in[p] -> out[p]) recorded as
+ * another.  Each graph is recorded again only when its arguments change
+ * (execute_many's also when a plane's point count changed).  execute_many
+ * returns NUASM_ERR_NOT_READY until every plane has points (and again after
+ * nuasm_batch_set_tuning).  Never synchronise the host once recorded. */
+nuasm_status nuasm_set_points_many(nuasm_batch batch, const int64_t* M, const double* const* x,
+                                   const double* const* y);
+nuasm_status nuasm_execute_many(nuasm_batch batch, const void* const* in, void* const* out);
+/* Same as nuasm_batch_create. */
+nuasm_status nuasm_plan_many_create(int32_t P, const nuasm_params* params, void* hip_stream, nuasm_batch* out);
 /* Tuning of one plane of a batch (as nuasm_plan_set_tuning) and the number
  * of parallel graph branches (1 .. min(4, P); default the maximum), e.g. from
  * an autotuner.  Either drops the recorded graph; the next run records it
@@ -337,8 +377,9 @@ nuasm_status nuasm_batch_set_branches(nuasm_batch batch, int32_t branches);
 /* Synchronise; *bad_plane = index of the first plane with out-of-range
  * points in the last run, or -1. */
 nuasm_status nuasm_batch_check_points(nuasm_batch batch, int32_t* bad_plane);
-/* Synchronise; ms[p] = device wall-clock time from the start of the last run
- * to the completion of plane p (caller-owned host array of P floats). */
+/* Synchronise; ms[p] = device wall-clock time from the start of the last
+ * recorded-graph launch (run, set_points_many or execute_many) to the
+ * completion of plane p (caller-owned host array of P floats). */
 nuasm_status nuasm_batch_plane_times(nuasm_batch batch, float* ms);
 
 const char* nuasm_status_string(nuasm_status s);

@@ -70,7 +70,7 @@ class PlanInfo(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("spread_chunk", ctypes.c_int32), ("interp_chunk", ctypes.c_int32),
-                ("bin_range_points", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("bin_range_points", ctypes.c_int32), ("spread_method", ctypes.c_int32)]
 
 
 _SIGS = {
@@ -108,6 +108,14 @@ _SIGS = {
     "nuasm_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
                                        ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
                                        ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p)]),
+    "nuasm_set_points_many": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                             ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p)]),
+    "nuasm_execute_many": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                          ctypes.POINTER(ctypes.c_void_p)]),
+    "nuasm_plan_many_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(Params), ctypes.c_void_p,
+                                              ctypes.POINTER(ctypes.c_void_p)]),
+    "nuasm_plan_workspace_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]),
+    "nuasm_plan_set_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
     "nuasm_batch_check_points": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     "nuasm_batch_plane_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float)]),
     "nuasm_rs_direct": (ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -316,9 +324,30 @@ class Plan:
                                           ctypes.c_void_p(counts.data_ptr()), ctypes.byref(n)))
         return recs[:n.value], counts
 
-    def set_tuning(self, spread_chunk: int = 0, interp_chunk: int = 0, bin_range_points: int = 0):
-        """Launch-shape tuning (0 = default); binned points must be set again."""
-        t = Tuning(int(spread_chunk), int(interp_chunk), int(bin_range_points), 0)
+    def workspace_bytes(self, M_max: int) -> int:
+        """Bytes of a caller-owned workspace holding M_max points per point set."""
+        b = ctypes.c_size_t()
+        _check(load().nuasm_plan_workspace_bytes(self._h, int(M_max), ctypes.byref(b)))
+        return b.value
+
+    def set_workspace(self, ws: torch.Tensor | None):
+        """Carve the plan's grids and point buffers from a caller-owned device
+        tensor (uint8, 256-byte aligned; kept alive by the plan), or go back to
+        plan-owned memory with None.  Binned points must be set again."""
+        self._sync_stream()
+        if ws is None:
+            _check(load().nuasm_plan_set_workspace(self._h, None, 0))
+        else:
+            p = _dev_ptr(ws, torch.uint8, "workspace")
+            _check(load().nuasm_plan_set_workspace(self._h, ctypes.c_void_p(p), ws.numel()))
+        self._ws = ws
+        return self
+
+    def set_tuning(self, spread_chunk: int = 0, interp_chunk: int = 0, bin_range_points: int = 0,
+                   spread_method: int = 0):
+        """Launch-shape tuning (0 = default); binned points must be set again.
+        spread_method: 0 automatic, 1 gather, 2 LDS scatter."""
+        t = Tuning(int(spread_chunk), int(interp_chunk), int(bin_range_points), int(spread_method))
         _check(load().nuasm_plan_set_tuning(self._h, ctypes.byref(t)))
         return self
 
@@ -421,8 +450,33 @@ class Batch:
         self._keep = (xs, ys, ins, outs)
         return outs
 
-    def set_tuning(self, plane: int, spread_chunk: int = 0, interp_chunk: int = 0, bin_range_points: int = 0):
-        t = Tuning(int(spread_chunk), int(interp_chunk), int(bin_range_points), 0)
+    def set_points(self, xs, ys):
+        """Bin every plane's points (one recorded graph; see nuasm_set_points_many)."""
+        if not (len(xs) == len(ys) == self.P):
+            raise ValueError("need one x and y per plane")
+        M = (ctypes.c_int64 * self.P)(*[int(x.numel()) for x in xs])
+        vp = ctypes.c_void_p * self.P
+        px = vp(*[(_dev_ptr(t, torch.float64, "x") if t.numel() else None) for t in xs])
+        py = vp(*[(_dev_ptr(t, torch.float64, "y") if t.numel() else None) for t in ys])
+        _check(load().nuasm_set_points_many(self._h, M, px, py))
+        self._keep_pts = (xs, ys)
+        return self
+
+    def execute(self, ins, outs):
+        """Apply every plane's operator to ins[p] -> outs[p] on the points bound
+        by set_points (one recorded graph; see nuasm_execute_many)."""
+        if not (len(ins) == len(outs) == self.P):
+            raise ValueError("need one in and out per plane")
+        vp = ctypes.c_void_p * self.P
+        pi = vp(*[(_dev_ptr(t, torch.complex64, "in") if t.numel() else None) for t in ins])
+        po = vp(*[(_dev_ptr(t, torch.complex64, "out") if t.numel() else None) for t in outs])
+        _check(load().nuasm_execute_many(self._h, pi, po))
+        self._keep_io = (ins, outs)
+        return outs
+
+    def set_tuning(self, plane: int, spread_chunk: int = 0, interp_chunk: int = 0, bin_range_points: int = 0,
+                   spread_method: int = 0):
+        t = Tuning(int(spread_chunk), int(interp_chunk), int(bin_range_points), int(spread_method))
         _check(load().nuasm_batch_set_tuning(self._h, int(plane), ctypes.byref(t)))
 
     def set_branches(self, branches: int):

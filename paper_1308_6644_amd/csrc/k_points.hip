@@ -108,7 +108,8 @@ k_bin_hist(const double* __restrict__ x, const double* __restrict__ y, int64_t M
 // needs a chunk for every bin (empty bins write zeros); interpolation only for
 // non-empty bins.  A bin with more than so.sp_chunk (so.ip_chunk) records is
 // split into several spreading (interpolation) chunks; for spreading those bins are
-// listed in `multi` for the reduction.  Both chunk tables are ordered by the
+// listed in `multi` for the reduction, and their chunks get consecutive slots
+// of the partial-tile scratch (nch[5] slots in all).  Both chunk tables are ordered by the
 // size of their bin, largest first (17 size classes, a bin's chunks kept
 // together), so that the dispatcher starts the longest workgroups first.
 // counts[T] (one past the bins) is the number of points outside the window;
@@ -145,7 +146,7 @@ __device__ __forceinline__ void bin_scan_body(const int* counts, int T, const Bi
   int* __restrict__ nch = so.nch;
   const int spc = so.sp_chunk, ipc = so.ip_chunk;
   constexpr int NW = kScanThreads / 64;
-  __shared__ int wsum[4][NW];
+  __shared__ int wsum[5][NW];
   __shared__ int cls_n[2][kSizeClasses], cls_base[2][kSizeClasses];  // spreading, interpolation
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (tid < 2 * kSizeClasses) cls_n[tid / kSizeClasses][tid % kSizeClasses] = 0;
@@ -155,7 +156,7 @@ __device__ __forceinline__ void bin_scan_body(const int* counts, int T, const Bi
 #pragma unroll
   for (int q = 0; q < kScanRegs; ++q) cr[q] = (b0 + q < b1) ? counts[b0 + q] : 0;
   __syncthreads();  // cls_n cleared
-  int acc[4] = {0, 0, 0, 0};  // records, spread chunks, interp chunks, multi bins
+  int acc[5] = {0, 0, 0, 0, 0};  // records, spread chunks, interp chunks, multi bins, split-bin chunks
   for (int q = 0; q < per; ++q) {
     const int b = b0 + q;
     const bool valid = b < b1;
@@ -170,19 +171,20 @@ __device__ __forceinline__ void bin_scan_body(const int* counts, int T, const Bi
     acc[1] += nsp;
     acc[2] += nip;
     acc[3] += nsp > 1 ? 1 : 0;
+    acc[4] += nsp > 1 ? nsp : 0;
     if (nsp > 0) atomicAdd(&cls_n[0][size_class(c, spc)], nsp);
     if (nip > 0) atomicAdd(&cls_n[1][size_class(c, ipc)], nip);
   }
-  int incl[4];
+  int incl[5];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < 5; ++k) {
     incl[k] = wave_incl_scan(acc[k], lane);
     if (lane == 63) wsum[k][wv] = incl[k];
   }
   __syncthreads();
   if (wv == 0) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < 5; ++k) {
       const int v = lane < NW ? wsum[k][lane] : 0;
       const int w = wave_incl_scan(v, lane);
       if (lane < NW) wsum[k][lane] = w - v;  // exclusive wave bases
@@ -196,9 +198,9 @@ __device__ __forceinline__ void bin_scan_body(const int* counts, int T, const Bi
     }
   }
   __syncthreads();
-  int run[4];
+  int run[5];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) run[k] = wsum[k][wv] + incl[k] - acc[k];
+  for (int k = 0; k < 5; ++k) run[k] = wsum[k][wv] + incl[k] - acc[k];
   for (int q = 0; q < per; ++q) {
     const int b = b0 + q;
     const bool valid = b < b1;
@@ -215,9 +217,10 @@ __device__ __forceinline__ void bin_scan_body(const int* counts, int T, const Bi
     cursor[b] = run[0];
     sp_first[b] = first;
     sp_n[b] = nsp;
+    // .w: the chunk's partial-tile slot when the bin is split, else -1
     for (int r = 0; r < nsp; ++r)
       sp_chunks[first + r] =
-          make_int4(b, run[0] + r * spc, min(spc, c - r * spc), nsp);
+          make_int4(b, run[0] + r * spc, min(spc, c - r * spc), nsp > 1 ? run[4] + r : -1);
     for (int r = 0; r < nip; ++r)
       ip_chunks[ifirst + r] = make_int4(b, run[0] + r * ipc, min(ipc, c - r * ipc), nip);
     if (nsp > 1) multi[run[3]] = b;
@@ -225,6 +228,7 @@ __device__ __forceinline__ void bin_scan_body(const int* counts, int T, const Bi
     run[1] += nsp;
     run[2] += nip;
     run[3] += nsp > 1 ? 1 : 0;
+    run[4] += nsp > 1 ? nsp : 0;
   }
   if (tid == kScanThreads - 1) {
     nch[0] = run[1];
@@ -232,6 +236,7 @@ __device__ __forceinline__ void bin_scan_body(const int* counts, int T, const Bi
     nch[2] = run[0];
     nch[3] = run[3];
     nch[4] = counts[T];
+    nch[5] = run[4];
   }
 }
 
@@ -501,7 +506,7 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(SpreadArgs a) {
   const int cid = blockIdx.x;
   if (cid >= a.nchunks[0]) return;
   const int4 ch = a.chunks[cid];
-  const int bin = ch.x, start = ch.y, n = ch.z, nb = ch.w;
+  const int bin = ch.x, start = ch.y, n = ch.z, slot = ch.w;
   const int t = threadIdx.x;
   const int x0 = 2 * (t & 15), y0 = 2 * (t >> 4);
   const float blog = a.beta * 1.4426950408889634f;
@@ -663,7 +668,7 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(SpreadArgs a) {
     }
     __syncthreads();
   }
-  if (nb == 1) {
+  if (slot < 0) {
     const int bx = bin % a.TX, by = bin / a.TX;
     const int gx = bx * kTile + x0, gy = by * kTile + y0;
     float2* g = a.grid;
@@ -676,7 +681,7 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(SpreadArgs a) {
       if (gx + 1 < a.L) g[(size_t)(gy + 1) * a.L + gx + 1] = a11;
     }
   } else {
-    float2* part = a.scratch + (size_t)cid * (kTile * kTile);
+    float2* part = a.scratch + (size_t)slot * (kTile * kTile);
     part[y0 * kTile + x0] = a00;
     part[y0 * kTile + x0 + 1] = a01;
     part[(y0 + 1) * kTile + x0] = a10;
@@ -684,18 +689,103 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(SpreadArgs a) {
   }
 }
 
-// Sum the partial tiles of every multi-chunk bin, in chunk order.
+// Sum the partial tiles of every multi-chunk bin, in chunk order (the bin's
+// chunks hold consecutive scratch slots, the first one's in its table entry).
 __global__ void __launch_bounds__(256) k_spread_reduce(SpreadReduceArgs a) {
   if ((int)blockIdx.x >= a.nmulti[0]) return;
   const int bin = a.multi[blockIdx.x];
   const int c0 = a.bin_chunk0[bin], nb = a.bin_nchunk[bin];
+  const int slot0 = a.chunks[c0].w;
   const int bx = bin % a.TX, by = bin / a.TX;
   for (int e = threadIdx.x; e < kTile * kTile; e += 256) {
     float2 s = czero();
-    for (int q = 0; q < nb; ++q) s = cadd(s, a.scratch[(size_t)(c0 + q) * (kTile * kTile) + e]);
+    for (int q = 0; q < nb; ++q) s = cadd(s, a.scratch[(size_t)(slot0 + q) * (kTile * kTile) + e]);
     const int yy = e / kTile, xx = e % kTile;
     const int gy = by * kTile + yy, gx = bx * kTile + xx;
     if (gy < a.L && gx < a.L) a.grid[(size_t)gy * a.L + gx] = s;
+  }
+}
+
+// Scatter form: one workgroup per chunk of a bin accumulates every record's
+// w x w taps into an LDS tile with native float atomic adds (ds_add_f32), one
+// plane for the real and one for the imaginary parts.  The tile is the bin
+// padded by w - 1 cells on every side, so that the taps of a record whose
+// first tap lies up to w - 1 cells before the bin (a duplicate recorded in
+// this bin) land in the padding without a bounds test; only the 32 x 32
+// interior is written out.  Tap (my, mx) of a record is at a compile-time
+// offset my * TS + mx from the record's first tap, so each add is one LDS
+// instruction with an immediate offset.  The order of the additions into a
+// cell is not fixed (deterministic mode uses the gather form).
+template <int W>
+struct SpreadLdsCfg {
+  static constexpr int TS = kTile + 2 * (W - 1);  // padded tile side
+  static constexpr int NT = 256;
+  static constexpr int B = 2;                     // records per thread in flight
+};
+
+template <int W>
+__global__ void __launch_bounds__(SpreadLdsCfg<W>::NT) k_spread_lds(SpreadArgs a) {
+  using Cfg = SpreadLdsCfg<W>;
+  constexpr int TS = Cfg::TS, NT = Cfg::NT, B = Cfg::B;
+  __shared__ float sre[TS * TS];
+  __shared__ float sim[TS * TS];
+  const int cid = blockIdx.x;
+  if (cid >= a.nchunks[0]) return;
+  const int4 ch = a.chunks[cid];
+  const int bin = ch.x, start = ch.y, n = ch.z, slot = ch.w;
+  const int t = threadIdx.x;
+  for (int e = t; e < TS * TS; e += NT) {
+    sre[e] = 0.f;
+    sim[e] = 0.f;
+  }
+  __syncthreads();
+  const float blog = a.beta * 1.4426950408889634f;
+  for (int r0 = 0; r0 < n; r0 += NT * B) {
+    BinRec rl[B];
+    float2 cv[B];
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      const int r = r0 + t + q * NT;
+      rl[q].packed = 0;
+      rl[q].dx = rl[q].dy = 0.f;
+      rl[q].idx = -1;
+      if (r < n) rl[q] = a.recs[start + r];
+    }
+#pragma unroll
+    for (int q = 0; q < B; ++q) cv[q] = rl[q].idx >= 0 ? a.vals[rl[q].idx] : czero();
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      if (rl[q].idx < 0) continue;
+      const int base = (rec_ly(rl[q].packed) + W - 1) * TS + rec_lx(rl[q].packed) + W - 1;
+      float wx[W];
+#pragma unroll
+      for (int m = 0; m < W; ++m) wx[m] = es_kernel_fast(rl[q].dx + (float)m, a.two_over_w, blog);
+#pragma unroll
+      for (int my = 0; my < W; ++my) {
+        const float wy = es_kernel_fast(rl[q].dy + (float)my, a.two_over_w, blog);
+        const float cr = cv[q].x * wy, ci = cv[q].y * wy;
+        float* pr = sre + base + my * TS;
+        float* pi = sim + base + my * TS;
+#pragma unroll
+        for (int mx = 0; mx < W; ++mx) {
+          atomicAdd(pr + mx, cr * wx[mx]);
+          atomicAdd(pi + mx, ci * wx[mx]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const int bx = bin % a.TX, by = bin / a.TX;
+  for (int e = t; e < kTile * kTile; e += NT) {
+    const int yy = e / kTile, xx = e % kTile;
+    const int s = (yy + W - 1) * TS + xx + W - 1;
+    const float2 v = make_float2(sre[s], sim[s]);
+    if (slot < 0) {
+      const int gy = by * kTile + yy, gx = bx * kTile + xx;
+      if (gy < a.L && gx < a.L) a.grid[(size_t)gy * a.L + gx] = v;
+    } else {
+      a.scratch[(size_t)slot * (kTile * kTile) + e] = v;
+    }
   }
 }
 
@@ -860,6 +950,14 @@ hipError_t launch_spread(int w, bool small_chunks, const SpreadArgs& a, int grid
     else                                                                                                 \
       hipLaunchKernelGGL((k_spread<W, spread_nsub(W, false)>), dim3(grid), dim3(kSpreadThreads), 0, st, a); \
   }
+  NUASM_DISPATCH_W(w, CALL)
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_spread_lds(int w, const SpreadArgs& a, int grid, hipStream_t st) {
+  if (grid <= 0) return hipSuccess;
+#define CALL(W) hipLaunchKernelGGL(k_spread_lds<W>, dim3(grid), dim3(SpreadLdsCfg<W>::NT), 0, st, a)
   NUASM_DISPATCH_W(w, CALL)
 #undef CALL
   return hipGetLastError();

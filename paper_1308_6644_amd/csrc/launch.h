@@ -62,12 +62,13 @@ struct BinGeom {
 // Outputs of the bin scan (bin bases, chunk tables and their counts).
 struct BinScanOut {
   int* cursor;       // first record of each bin
-  int4* sp_chunks;   // spreading chunks (bin, first record, count, chunks of the bin)
+  int4* sp_chunks;   // spreading chunks (bin, first record, count, partial-tile slot or -1)
   int* sp_first;     // first spreading chunk of each bin
   int* sp_n;         // spreading chunks of each bin
   int* multi;        // bins with several spreading chunks
   int4* ip_chunks;   // interpolation chunks
-  int* nch;          // spread chunks, interp chunks, records, multi bins, points out of range
+  int* nch;          // spread chunks, interp chunks, records, multi bins, points out of range,
+                     // partial-tile slots of split bins
   int sp_chunk;      // max records per spreading chunk
   int ip_chunk;      // max records per interpolation chunk
 };
@@ -75,9 +76,9 @@ constexpr int kScanDone = 7;  // element of nch counting finished column-scan wo
 
 struct SpreadArgs {
   const BinRec* recs;
-  const int4* chunks;     // (bin, first record, count, chunks of the bin)
+  const int4* chunks;     // (bin, first record, count, partial-tile slot or -1)
   const int* nchunks;     // device count of valid chunks (element 0)
-  float2* scratch;        // per-chunk partial bins of multi-chunk bins
+  float2* scratch;        // partial tiles of split bins, one per slot
   const float2* vals;     // point values, caller order
   float2* grid;           // L x L support
   int L, TX;
@@ -86,6 +87,7 @@ struct SpreadArgs {
 };
 
 struct SpreadReduceArgs {
+  const int4* chunks;     // spreading chunk table (slot of a chunk in .w)
   const int* multi;       // multi-chunk bins
   const int* nmulti;      // their count
   const int* bin_chunk0;  // first chunk of each bin
@@ -135,6 +137,8 @@ hipError_t launch_bin_colscan(const uint16_t* hist, int G, int T, int* off, int*
 hipError_t launch_bin_scatter(const double* x, const double* y, int64_t M, BinGeom g, int ppw, int G,
                               const int* off, const int* bin_base, BinRec* recs, bool stable, hipStream_t st);
 hipError_t launch_spread(int w, bool small_chunks, const SpreadArgs& a, int grid, hipStream_t st);
+// spreading by LDS atomic accumulation (order of the sums not fixed)
+hipError_t launch_spread_lds(int w, const SpreadArgs& a, int grid, hipStream_t st);
 hipError_t launch_spread_reduce(const SpreadReduceArgs& a, int grid, hipStream_t st);
 hipError_t launch_interp(int w, const InterpArgs& a, int grid, hipStream_t st);
 // separable interpolation at a grid: support (L x L) -> R (nrows x nx) -> out (ny x nx)

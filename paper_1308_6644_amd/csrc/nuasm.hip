@@ -172,19 +172,20 @@ struct PointSet {
   int* sp_first = nullptr;
   int* sp_n = nullptr;
   int* multi = nullptr;
-  int* nch = nullptr;  // [8]: chunk and record counts [0..3], points out of range [4], scan hand-off counter [7]
+  int* nch = nullptr;  // [8]: chunk and record counts [0..3], points out of range [4], split-bin slots [5],
+                       // scan hand-off counter [7]
   int4* sp_chunks = nullptr;
   int4* ip_chunks = nullptr;
   int64_t chunk_cap = 0;
   BinRec* recs = nullptr;
   int64_t rec_cap = 0;  // points the record buffer is sized for
-  float2* scratch = nullptr;
-  int64_t scratch_chunks = 0;
+  float2* scratch = nullptr;  // partial tiles of split bins
+  int64_t scratch_chunks = 0;  // tiles it holds
   int* host_stat = nullptr;  // pinned [8]
   int64_t M = 0;
   bool ready = false;
   bool synced = false;
-  int exact_sp = 0, exact_ip = 0, exact_multi = 0;
+  int exact_sp = 0, exact_ip = 0, exact_multi = 0, exact_slots = 0;
   // a uniform grid bound with nuasm_set_grid_points (no records, no binning)
   bool grid = false;
   GridPts gp{};
@@ -220,8 +221,14 @@ struct nuasm_plan_s {
   int sp_chunk = kSpreadChunk;
   int ip_chunk = kChunk;
   int bin_ppw = 0;        // points per binning workgroup, 0 = automatic
+  int sp_method = 0;      // spreading: 0 automatic, 1 gather, 2 LDS scatter
   int nsets = 1;
-  size_t bytes = 0;
+  size_t bytes = 0;          // device memory the plan allocated itself
+  // caller-owned workspace (nuasm_plan_set_workspace): the two grids and the
+  // point-count-dependent buffers of every point set are carved from it
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  int64_t ws_cap = 0;        // points per set the workspace holds
   // stage timing
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -248,8 +255,12 @@ void release(nuasm_plan_s* pl) {
   auto f = [](void* p) {
     if (p) (void)hipFree(p);
   };
-  f(pl->gridA);
-  f(pl->gridB);
+  // buffers carved from a caller's workspace are not the plan's to free
+  auto fo = [&](void* p) {
+    if (!pl->ws) f(p);
+  };
+  fo(pl->gridA);
+  fo(pl->gridB);
   if (pl->dinv_np != pl->dinv) f(pl->dinv_np);
   f(pl->dinv);
   f(pl->fre);
@@ -260,12 +271,12 @@ void release(nuasm_plan_s* pl) {
     f(q.sp_n);
     f(q.multi);
     f(q.nch);
-    f(q.sp_chunks);
-    f(q.ip_chunks);
-    f(q.recs);
-    f(q.scratch);
-    f(q.hist);
-    f(q.hoff);
+    fo(q.sp_chunks);
+    fo(q.ip_chunks);
+    fo(q.recs);
+    fo(q.scratch);
+    fo(q.hist);
+    fo(q.hoff);
     f(q.gbuf);
     if (q.host_stat) (void)hipHostFree(q.host_stat);
     q = PointSet{};
@@ -374,7 +385,144 @@ nuasm_status alloc_point_set(nuasm_plan_s* pl, PointSet& q) {
   return NUASM_OK;
 }
 
+// Sizes of the point-count-dependent buffers of one point set sized for `cap`
+// points (each rounded up to 256 bytes): records (at most 4 per point), the
+// two chunk tables, the per-range histograms and offsets, and the partial
+// tiles of split bins (the bound of scratch_tiles_needed).
+size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct PointLayout {
+  int64_t cap = 0, chunk_cap = 0, hist_rows = 0, tiles = 0;
+  size_t recs = 0, chunks = 0, hist = 0, hoff = 0, scratch = 0;
+  size_t total() const { return recs + 2 * chunks + hist + hoff + scratch; }
+};
+
+PointLayout point_layout(const nuasm_plan_s* pl, int64_t cap) {
+  PointLayout L;
+  L.cap = std::max<int64_t>(cap, 1024);
+  int ppw = 0, G = 0;
+  bin_ranges(L.cap, pl->bin_ppw, stable_bins(pl), &ppw, &G);
+  L.hist_rows = std::max(G, 1);
+  L.chunk_cap = pl->T + (4 * L.cap) / std::min(pl->sp_chunk, pl->ip_chunk) + 1;  // covers both chunk tables
+  L.tiles = std::max<int64_t>(1, std::min<int64_t>(L.chunk_cap, (8 * L.cap) / pl->sp_chunk + 1));
+  L.recs = round256(sizeof(BinRec) * 4 * (size_t)L.cap);
+  L.chunks = round256(sizeof(int4) * (size_t)L.chunk_cap);
+  L.hist = round256(sizeof(uint16_t) * (size_t)L.hist_rows * (pl->T + 1));
+  L.hoff = round256(sizeof(int) * (size_t)L.hist_rows * (pl->T + 1));
+  L.scratch = round256(sizeof(float2) * kTile * kTile * (size_t)L.tiles);
+  return L;
+}
+
+size_t grid_bytes(const nuasm_plan_s* pl) { return round256(sizeof(float2) * (size_t)pl->grid_elems); }
+
+size_t workspace_bytes_for(const nuasm_plan_s* pl, int64_t cap) {
+  return 2 * grid_bytes(pl) + (size_t)pl->nsets * point_layout(pl, cap).total();
+}
+
+// Point the grids and every point set's buffers into the caller's workspace
+// (sized for pl->ws_cap points per set).
+void carve_workspace(nuasm_plan_s* pl) {
+  char* p = pl->ws;
+  const size_t gb = grid_bytes(pl);
+  pl->gridA = (float2*)p;
+  pl->gridB = (float2*)(p + gb);
+  p += 2 * gb;
+  const PointLayout L = point_layout(pl, pl->ws_cap);
+  for (int i = 0; i < pl->nsets; ++i) {
+    PointSet& q = pl->ps[i];
+    q.recs = (BinRec*)p;
+    p += L.recs;
+    q.sp_chunks = (int4*)p;
+    p += L.chunks;
+    q.ip_chunks = (int4*)p;
+    p += L.chunks;
+    q.hist = (uint16_t*)p;
+    p += L.hist;
+    q.hoff = (int*)p;
+    p += L.hoff;
+    q.scratch = (float2*)p;
+    p += L.scratch;
+    q.rec_cap = L.cap;
+    q.chunk_cap = L.chunk_cap;
+    q.hist_rows = L.hist_rows;
+    q.scratch_chunks = L.tiles;
+  }
+}
+
+// Free the plan-owned grids and point buffers (not a caller's workspace).
+void free_owned_buffers(nuasm_plan_s* pl) {
+  auto f = [&](void* p, size_t b) {
+    if (p && !pl->ws) {
+      (void)hipFree(p);
+      pl->bytes -= b;
+    }
+  };
+  f(pl->gridA, sizeof(float2) * pl->grid_elems);
+  f(pl->gridB, sizeof(float2) * pl->grid_elems);
+  pl->gridA = pl->gridB = nullptr;
+  for (int i = 0; i < pl->nsets; ++i) {
+    PointSet& q = pl->ps[i];
+    f(q.recs, sizeof(BinRec) * 4 * q.rec_cap);
+    f(q.sp_chunks, sizeof(int4) * q.chunk_cap);
+    f(q.ip_chunks, sizeof(int4) * q.chunk_cap);
+    f(q.hist, sizeof(uint16_t) * q.hist_rows * (pl->T + 1));
+    f(q.hoff, sizeof(int) * q.hist_rows * (pl->T + 1));
+    f(q.scratch, sizeof(float2) * kTile * kTile * q.scratch_chunks);
+    q.recs = nullptr;
+    q.sp_chunks = q.ip_chunks = nullptr;
+    q.hist = nullptr;
+    q.hoff = nullptr;
+    q.scratch = nullptr;
+    q.rec_cap = q.chunk_cap = q.hist_rows = q.scratch_chunks = 0;
+    if (!q.grid) q.ready = false;
+  }
+}
+
+// Bind the caller's workspace `dev` of `bytes` bytes (NULL: go back to
+// plan-owned memory).  The capacity is the largest point count per set whose
+// buffers fit; binned point sets must be bound again.
+nuasm_status bind_workspace(nuasm_plan_s* pl, void* dev, size_t bytes) {
+  if (dev && ((uintptr_t)dev & 255)) return fail(NUASM_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (!dev && !pl->ws) return NUASM_OK;  // already plan-owned
+  int64_t cap = 0;
+  if (dev) {
+    const size_t need = workspace_bytes_for(pl, 1024);
+    if (bytes < need) {
+      char buf[160];
+      std::snprintf(buf, sizeof(buf), "workspace of %zu bytes is below this plan's minimum of %zu bytes", bytes,
+                    need);
+      return fail(NUASM_ERR_INVALID_ARG, buf);
+    }
+    int64_t lo = 1024, hi = (int64_t)INT32_MAX / 4;  // 4 records per point must fit in int32
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo + 1) / 2;
+      if (workspace_bytes_for(pl, mid) <= bytes) lo = mid;
+      else hi = mid - 1;
+    }
+    cap = lo;
+  }
+  HIP_TRY(hipStreamSynchronize(pl->stream), "hipStreamSynchronize");
+  free_owned_buffers(pl);
+  pl->ws = (char*)dev;
+  pl->ws_bytes = dev ? bytes : 0;
+  pl->ws_cap = cap;
+  if (dev) {
+    carve_workspace(pl);
+    return NUASM_OK;
+  }
+  HIP_TRY(dalloc(pl, &pl->gridA, (size_t)pl->grid_elems), "hipMalloc(gridA)");
+  HIP_TRY(dalloc(pl, &pl->gridB, (size_t)pl->grid_elems), "hipMalloc(gridB)");
+  return NUASM_OK;
+}
+
 nuasm_status ensure_points_capacity(nuasm_plan_s* pl, PointSet& q, int64_t M) {
+  if (pl->ws) {
+    if (M <= q.rec_cap) return NUASM_OK;
+    char buf[160];
+    std::snprintf(buf, sizeof(buf), "%lld points exceed the workspace's capacity of %lld points per set",
+                  (long long)M, (long long)q.rec_cap);
+    return fail(NUASM_ERR_INVALID_ARG, buf);
+  }
   if (M <= q.rec_cap && q.recs) return NUASM_OK;
   const int64_t cap = std::max<int64_t>(M, 1024);
   if (cap * 4 > (int64_t)INT32_MAX) return fail(NUASM_ERR_UNSUPPORTED, "too many points (4 M must fit in int32)");
@@ -420,10 +568,29 @@ nuasm_status ensure_points_capacity(nuasm_plan_s* pl, PointSet& q, int64_t M) {
   return NUASM_OK;
 }
 
+// Partial tiles the split bins of a bound set may need: the exact count once
+// a set_points has synchronised, else a bound.  A split bin holds c > chunk
+// records in ceil(c / chunk) < 2 c / chunk chunks, and there are at most 4 M
+// records, so fewer than 8 M / chunk slots are ever used.
+int64_t scratch_tiles_needed(const nuasm_plan_s* pl, const PointSet& q) {
+  if (q.synced) return q.exact_slots;
+  return std::min<int64_t>(q.chunk_cap, (8 * q.M) / pl->sp_chunk + 1);
+}
+
 nuasm_status ensure_scratch(nuasm_plan_s* pl, PointSet& q) {
-  if (q.scratch) return NUASM_OK;
-  HIP_TRY(dalloc(pl, &q.scratch, (size_t)q.chunk_cap * kTile * kTile), "hipMalloc(spread scratch)");
-  q.scratch_chunks = q.chunk_cap;
+  const int64_t need = std::max<int64_t>(scratch_tiles_needed(pl, q), 1);
+  if (q.scratch && need <= q.scratch_chunks) return NUASM_OK;
+  // a workspace holds the bound for its capacity, which covers every M <= it
+  if (pl->ws) return fail(NUASM_ERR_INVALID_ARG, "split-bin scratch exceeds the workspace");
+  if (q.scratch) {
+    HIP_TRY(hipStreamSynchronize(pl->stream), "hipStreamSynchronize");
+    (void)hipFree(q.scratch);
+    pl->bytes -= sizeof(float2) * kTile * kTile * q.scratch_chunks;
+    q.scratch = nullptr;
+    q.scratch_chunks = 0;
+  }
+  HIP_TRY(dalloc(pl, &q.scratch, (size_t)need * kTile * kTile), "hipMalloc(spread scratch)");
+  q.scratch_chunks = need;
   return NUASM_OK;
 }
 
@@ -486,7 +653,7 @@ nuasm_status bind_points(nuasm_plan_s* pl, PointSet& q, int64_t M, const double*
     q.ready = true;
     return NUASM_OK;
   }
-  HIP_TRY(hipMemcpyAsync(q.host_stat, q.nch, sizeof(int) * 5, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+  HIP_TRY(hipMemcpyAsync(q.host_stat, q.nch, sizeof(int) * 6, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
   HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
   {
     const nuasm_status ps = point_status(q, &q == &pl->ps[1] ? 1 : 0);
@@ -495,6 +662,7 @@ nuasm_status bind_points(nuasm_plan_s* pl, PointSet& q, int64_t M, const double*
   q.exact_sp = q.host_stat[0];
   q.exact_ip = q.host_stat[1];
   q.exact_multi = q.host_stat[3];
+  q.exact_slots = q.host_stat[5];
   q.synced = true;
   q.ready = true;
   return NUASM_OK;
@@ -565,6 +733,13 @@ nuasm_status bind_grid(nuasm_plan_s* pl, PointSet& q, int64_t nx, int64_t ny, do
   return NUASM_OK;
 }
 
+// Spreading method: the LDS-atomic scatter unless the plan is deterministic
+// (whose sums must run in one fixed order) or the gather form was asked for.
+bool use_lds_spread(const nuasm_plan_s* pl) {
+  if (stable_bins(pl)) return false;
+  return pl->sp_method != 1;
+}
+
 // Spreading of one point set's values onto the fine support (gridA).
 nuasm_status run_spread(nuasm_plan_s* pl, PointSet& q, const float2* vals) {
   hipStream_t st = pl->stream;
@@ -589,11 +764,15 @@ nuasm_status run_spread(nuasm_plan_s* pl, PointSet& q, const float2* vals) {
     sa.TX = pl->TX;
     sa.two_over_w = 2.0f / (float)pl->w;
     sa.beta = pl->beta;
-    HIP_TRY(launch_spread(pl->w, pl->sp_small, sa, sp_grid(pl, q), st), "launch spread");
+    if (use_lds_spread(pl))
+      HIP_TRY(launch_spread_lds(pl->w, sa, sp_grid(pl, q), st), "launch spread_lds");
+    else
+      HIP_TRY(launch_spread(pl->w, pl->sp_small, sa, sp_grid(pl, q), st), "launch spread");
   }
   {
     StageScope sc(pl, NUASM_STAGE_SPREAD_REDUCE);
     SpreadReduceArgs ra{};
+    ra.chunks = q.sp_chunks;
     ra.multi = q.multi;
     ra.nmulti = q.nch + 3;
     ra.bin_chunk0 = q.sp_first;
@@ -968,8 +1147,12 @@ nuasm_status nuasm_plan_get_info(nuasm_plan pl, nuasm_plan_info* info) {
 
 nuasm_status nuasm_plan_set_tuning(nuasm_plan pl, const nuasm_tuning* t) {
   if (!pl || !t) return fail(NUASM_ERR_INVALID_ARG, "plan or tuning is NULL");
-  if (t->spread_chunk < 0 || t->interp_chunk < 0 || t->bin_range_points < 0 || t->reserved != 0)
-    return fail(NUASM_ERR_INVALID_ARG, "tuning fields must be >= 0 and reserved 0");
+  if (t->spread_chunk < 0 || t->interp_chunk < 0 || t->bin_range_points < 0)
+    return fail(NUASM_ERR_INVALID_ARG, "tuning fields must be >= 0");
+  if (t->spread_method < 0 || t->spread_method > 2)
+    return fail(NUASM_ERR_INVALID_ARG, "spread_method must be 0 (automatic), 1 (gather) or 2 (LDS scatter)");
+  if (t->spread_method == 2 && stable_bins(pl))
+    return fail(NUASM_ERR_INVALID_ARG, "the LDS scatter's sums have no fixed order: not in deterministic mode");
   if (t->interp_chunk != 0 && (t->interp_chunk < 256 || t->interp_chunk > 65536))
     return fail(NUASM_ERR_INVALID_ARG, "interp_chunk must be 0 or in [256, 65536]");
   if (t->bin_range_points != 0 && (t->bin_range_points < 1024 || t->bin_range_points > kBinPointsMax))
@@ -977,19 +1160,47 @@ nuasm_status nuasm_plan_set_tuning(nuasm_plan pl, const nuasm_tuning* t) {
   // spreading chunks come in the two sizes the kernel is built for; a request
   // below the default takes the small one
   const int small = spread_nsub(pl->w, true) * spread_subbatch(pl->w);
+  const bool old_small = pl->sp_small;
+  const int old_sp = pl->sp_chunk, old_ip = pl->ip_chunk, old_ppw = pl->bin_ppw, old_m = pl->sp_method;
   pl->sp_small = t->spread_chunk != 0 && t->spread_chunk < kSpreadChunk;
   pl->sp_chunk = pl->sp_small ? small : kSpreadChunk;
   pl->ip_chunk = t->interp_chunk != 0 ? t->interp_chunk : kChunk;
   pl->bin_ppw = t->bin_range_points;
+  pl->sp_method = t->spread_method;
   // binned point sets must be bound again (their chunk tables and histogram
   // rows follow the old sizes); a set bound as a grid stays ready, but its
   // buffers are resized too at its next binning
+  // a caller's workspace is carved again for the new sizes (the old tuning
+  // stays if they do not fit)
+  if (pl->ws) {
+    const nuasm_status s = bind_workspace(pl, pl->ws, pl->ws_bytes);
+    if (s != NUASM_OK) {
+      pl->sp_small = old_small;
+      pl->sp_chunk = old_sp;
+      pl->ip_chunk = old_ip;
+      pl->bin_ppw = old_ppw;
+      pl->sp_method = old_m;
+    }
+    return s;
+  }
   for (int i = 0; i < pl->nsets; ++i) {
     PointSet& q = pl->ps[i];
     q.rec_cap = 0;
     if (!q.grid) q.ready = false;
   }
   return NUASM_OK;
+}
+
+nuasm_status nuasm_plan_workspace_bytes(nuasm_plan pl, int64_t M_max, size_t* bytes) {
+  if (!pl || !bytes) return fail(NUASM_ERR_INVALID_ARG, "plan or bytes is NULL");
+  if (M_max < 0 || M_max > (int64_t)INT32_MAX / 4) return fail(NUASM_ERR_INVALID_ARG, "M_max must be in [0, 2^29)");
+  *bytes = workspace_bytes_for(pl, M_max);
+  return NUASM_OK;
+}
+
+nuasm_status nuasm_plan_set_workspace(nuasm_plan pl, void* dev, size_t bytes) {
+  if (!pl) return fail(NUASM_ERR_INVALID_ARG, "plan is NULL");
+  return bind_workspace(pl, dev, bytes);
 }
 
 nuasm_status nuasm_set_points(nuasm_plan pl, int64_t M, const double* x, const double* y) {
@@ -1016,7 +1227,7 @@ nuasm_status nuasm_check_points(nuasm_plan pl) {
   for (int i = 0; i < pl->nsets; ++i) {
     PointSet& q = pl->ps[i];
     if (q.grid) continue;  // range-checked on the host when bound
-    HIP_TRY(hipMemcpyAsync(q.host_stat, q.nch, sizeof(int) * 5, hipMemcpyDeviceToHost, pl->stream),
+    HIP_TRY(hipMemcpyAsync(q.host_stat, q.nch, sizeof(int) * 6, hipMemcpyDeviceToHost, pl->stream),
             "hipMemcpyAsync");
   }
   HIP_TRY(hipStreamSynchronize(pl->stream), "hipStreamSynchronize");
@@ -1113,7 +1324,7 @@ nuasm_status nuasm_debug_records(nuasm_plan pl, int32_t which, void* recs_out, i
   if (which < 0 || which >= pl->nsets) return fail(NUASM_ERR_INVALID_ARG, "which must be 0 (or 1 for type 3)");
   PointSet& q = pl->ps[which];
   if (!q.ready || q.grid) return fail(NUASM_ERR_NOT_READY, "the point set holds no binned points");
-  HIP_TRY(hipMemcpyAsync(q.host_stat, q.nch, sizeof(int) * 5, hipMemcpyDeviceToHost, pl->stream), "hipMemcpyAsync");
+  HIP_TRY(hipMemcpyAsync(q.host_stat, q.nch, sizeof(int) * 6, hipMemcpyDeviceToHost, pl->stream), "hipMemcpyAsync");
   HIP_TRY(hipStreamSynchronize(pl->stream), "hipStreamSynchronize");
   const int64_t total = q.host_stat[2];
   *n_records = total;
@@ -1210,18 +1421,24 @@ nuasm_status nuasm_rs_direct(int64_t M1, const double* x1, const double* y1, con
 // ================================================================ batches
 }  // extern "C"
 
+// One recorded graph of a batch and the arguments it was recorded with.
+struct BatchGraph {
+  hipGraphExec_t exec = nullptr;
+  std::vector<const void*> key;
+};
+
 struct nuasm_batch_s {
   std::vector<nuasm_plan_s*> plans;
   hipStream_t stream = nullptr;  // caller's stream
-  hipStream_t cap = nullptr;     // internal stream the graph is recorded and launched on
+  hipStream_t cap = nullptr;     // internal stream the graphs are recorded and launched on
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   std::vector<hipStream_t> branch;
   int active = 0;              // branches in use (nuasm_batch_set_branches)
   std::vector<int> branch_of;  // plane -> branch
   hipEvent_t fork = nullptr;
   std::vector<hipEvent_t> join;
-  hipGraphExec_t exec = nullptr;
-  std::vector<const void*> key;
+  // one-shot (binning + operator), binning alone, operator alone
+  BatchGraph g_run, g_bin, g_exec;
   long long* ts = nullptr;     // [P + 1] device wall-clock stamps
   int clock_khz = 0;
 };
@@ -1230,8 +1447,16 @@ namespace {
 
 constexpr int kBranches = 4;
 
+void drop_graph(BatchGraph& g) {
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  g.exec = nullptr;
+  g.key.clear();
+}
+
 void batch_release(nuasm_batch_s* b) {
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  drop_graph(b->g_run);
+  drop_graph(b->g_bin);
+  drop_graph(b->g_exec);
   for (nuasm_plan_s* pl : b->plans) {
     if (!pl) continue;
     release(pl);
@@ -1244,14 +1469,6 @@ void batch_release(nuasm_batch_s* b) {
   if (b->fork) (void)hipEventDestroy(b->fork);
   for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
   if (b->ts) (void)hipFree(b->ts);
-}
-
-// enqueue the one-shot work of plane p on the plan's current stream
-nuasm_status batch_plane(nuasm_plan_s* pl, int64_t M, const double* x, const double* y, const void* in,
-                         void* out) {
-  nuasm_status s = nuasm_set_points(pl, M, x, y);
-  if (s != NUASM_OK) return s;
-  return nuasm_execute(pl, in, out);
 }
 
 }  // namespace
@@ -1269,7 +1486,7 @@ static double plane_cost(const nuasm_plan_s* pl, int64_t M) {
 }
 
 // Longest-processing-time assignment of the planes to the capture branches.
-static void assign_branches(nuasm_batch_s* b, const int64_t* M) {
+static void assign_branches(nuasm_batch_s* b, const std::vector<int64_t>& M) {
   const int P = (int)b->plans.size(), K = b->active;
   std::vector<double> work(P);
   std::vector<int> order(P);
@@ -1284,6 +1501,73 @@ static void assign_branches(nuasm_batch_s* b, const int64_t* M) {
     b->branch_of[p] = k;
     load[k] += work[p];
   }
+}
+
+// Launch graph g, or record it first when it is missing or was recorded with
+// other arguments (key).  plane(pl, p) enqueues plane p's work on the plan's
+// current stream.  Recording: one eager pass on the caller's stream (sizes every
+// buffer and sets kernel attributes, so that the capture enqueues launches
+// only), then the capture on the internal stream -- stamp, fork onto the
+// branches, every plane on its branch followed by its completion stamp, join.
+// The graph runs on the internal stream, ordered after the caller's stream and
+// before the caller's later work.
+template <typename F>
+static nuasm_status batch_launch(nuasm_batch_s* b, BatchGraph& g, const std::vector<const void*>& key,
+                                 const std::vector<int64_t>& M, F plane) {
+  const int P = (int)b->plans.size();
+  auto launch = [&]() -> nuasm_status {
+    HIP_TRY(hipEventRecord(b->ev_in, b->stream), "hipEventRecord");
+    HIP_TRY(hipStreamWaitEvent(b->cap, b->ev_in, 0), "hipStreamWaitEvent");
+    HIP_TRY(hipGraphLaunch(g.exec, b->cap), "hipGraphLaunch");
+    HIP_TRY(hipEventRecord(b->ev_out, b->cap), "hipEventRecord");
+    HIP_TRY(hipStreamWaitEvent(b->stream, b->ev_out, 0), "hipStreamWaitEvent");
+    return NUASM_OK;
+  };
+  if (g.exec && key == g.key) return launch();
+  if (g.exec) {
+    HIP_TRY(hipStreamSynchronize(b->cap), "hipStreamSynchronize");
+    drop_graph(g);
+  }
+  for (int p = 0; p < P; ++p) {
+    nuasm_plan_s* pl = b->plans[p];
+    pl->stream = b->stream;
+    pl->timing = false;
+    nuasm_status s = plane(pl, p);
+    if (s != NUASM_OK) return fail(s, "plane " + std::to_string(p) + ": " + g_last_error);
+  }
+  HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+  assign_branches(b, M);
+  HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+  nuasm_status st = NUASM_OK;
+  hipError_t e = launch_stamp(b->ts, b->cap);
+  if (e == hipSuccess) e = hipEventRecord(b->fork, b->cap);
+  for (size_t k = 0; e == hipSuccess && k < (size_t)b->active; ++k) e = hipStreamWaitEvent(b->branch[k], b->fork, 0);
+  for (int p = 0; e == hipSuccess && st == NUASM_OK && p < P; ++p) {
+    nuasm_plan_s* pl = b->plans[p];
+    pl->stream = b->branch[b->branch_of[p]];
+    st = plane(pl, p);
+    if (st == NUASM_OK) e = launch_stamp(b->ts + 1 + p, pl->stream);
+  }
+  for (size_t k = 0; e == hipSuccess && k < (size_t)b->active; ++k) {
+    e = hipEventRecord(b->join[k], b->branch[k]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->cap, b->join[k], 0);
+  }
+  hipGraph_t graph = nullptr;
+  hipError_t e2 = hipStreamEndCapture(b->cap, &graph);
+  for (nuasm_plan_s* pl : b->plans) pl->stream = b->stream;
+  if (st != NUASM_OK || e != hipSuccess || e2 != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    if (st != NUASM_OK) return st;
+    return hip_fail(e != hipSuccess ? e : e2, "graph capture");
+  }
+  e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    g.exec = nullptr;
+    return hip_fail(e, "hipGraphInstantiate");
+  }
+  g.key = key;
+  return launch();
 }
 
 extern "C" {
@@ -1350,6 +1634,10 @@ nuasm_status nuasm_batch_create(int32_t P, const nuasm_params* params, void* hip
   return NUASM_OK;
 }
 
+nuasm_status nuasm_plan_many_create(int32_t P, const nuasm_params* params, void* hip_stream, nuasm_batch* out) {
+  return nuasm_batch_create(P, params, hip_stream, out);
+}
+
 nuasm_status nuasm_batch_destroy(nuasm_batch b) {
   if (!b) return NUASM_OK;
   (void)hipStreamSynchronize(b->stream);
@@ -1365,86 +1653,66 @@ nuasm_status nuasm_batch_run(nuasm_batch b, const int64_t* M, const double* cons
   if (!b || !M || !x || !y || !in || !out) return fail(NUASM_ERR_INVALID_ARG, "NULL argument");
   const int P = (int)b->plans.size();
   std::vector<const void*> key;
+  std::vector<int64_t> Ms(P);
   key.reserve(5 * P);
   for (int p = 0; p < P; ++p) {
     if (M[p] < 0) return fail(NUASM_ERR_INVALID_ARG, "M < 0");
+    Ms[p] = M[p];
     key.push_back((const void*)(intptr_t)M[p]);
     key.push_back(x[p]);
     key.push_back(y[p]);
     key.push_back(in[p]);
     key.push_back(out[p]);
   }
-  // the graph runs on the internal stream, ordered after the caller's stream
-  // and before the caller's later work
-  auto launch = [&]() -> nuasm_status {
-    HIP_TRY(hipEventRecord(b->ev_in, b->stream), "hipEventRecord");
-    HIP_TRY(hipStreamWaitEvent(b->cap, b->ev_in, 0), "hipStreamWaitEvent");
-    HIP_TRY(hipGraphLaunch(b->exec, b->cap), "hipGraphLaunch");
-    HIP_TRY(hipEventRecord(b->ev_out, b->cap), "hipEventRecord");
-    HIP_TRY(hipStreamWaitEvent(b->stream, b->ev_out, 0), "hipStreamWaitEvent");
-    return NUASM_OK;
-  };
-  if (b->exec && key == b->key) return launch();
-  if (b->exec) {
-    HIP_TRY(hipStreamSynchronize(b->cap), "hipStreamSynchronize");
-    (void)hipGraphExecDestroy(b->exec);
-    b->exec = nullptr;
-    b->key.clear();
-  }
-  // eager pass: sizes every workspace and sets kernel attributes, so the
-  // capture below enqueues launches only
+  return batch_launch(b, b->g_run, key, Ms, [&](nuasm_plan_s* pl, int p) {
+    nuasm_status s = nuasm_set_points(pl, M[p], x[p], y[p]);
+    if (s != NUASM_OK) return s;
+    return nuasm_execute(pl, in[p], out[p]);
+  });
+}
+
+nuasm_status nuasm_set_points_many(nuasm_batch b, const int64_t* M, const double* const* x, const double* const* y) {
+  if (!b || !M || !x || !y) return fail(NUASM_ERR_INVALID_ARG, "NULL argument");
+  const int P = (int)b->plans.size();
+  std::vector<const void*> key;
+  std::vector<int64_t> Ms(P);
+  key.reserve(3 * P);
   for (int p = 0; p < P; ++p) {
-    nuasm_plan_s* pl = b->plans[p];
-    pl->stream = b->stream;
-    pl->timing = false;
-    nuasm_status s = batch_plane(pl, M[p], x[p], y[p], in[p], out[p]);
-    if (s != NUASM_OK) return fail(s, "plane " + std::to_string(p) + ": " + g_last_error);
+    if (M[p] < 0) return fail(NUASM_ERR_INVALID_ARG, "M < 0");
+    Ms[p] = M[p];
+    key.push_back((const void*)(intptr_t)M[p]);
+    key.push_back(x[p]);
+    key.push_back(y[p]);
   }
-  HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
-  assign_branches(b, M);
-  // capture on the internal stream: stamp, fork onto the branches, every
-  // plane on its branch followed by its completion stamp, join
-  HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-  nuasm_status st = NUASM_OK;
-  hipError_t e = launch_stamp(b->ts, b->cap);
-  if (e == hipSuccess) e = hipEventRecord(b->fork, b->cap);
-  for (size_t k = 0; e == hipSuccess && k < (size_t)b->active; ++k) e = hipStreamWaitEvent(b->branch[k], b->fork, 0);
-  for (int p = 0; e == hipSuccess && st == NUASM_OK && p < P; ++p) {
-    nuasm_plan_s* pl = b->plans[p];
-    pl->stream = b->branch[b->branch_of[p]];
-    st = batch_plane(pl, M[p], x[p], y[p], in[p], out[p]);
-    if (st == NUASM_OK) e = launch_stamp(b->ts + 1 + p, pl->stream);
+  return batch_launch(b, b->g_bin, key, Ms,
+                      [&](nuasm_plan_s* pl, int p) { return nuasm_set_points(pl, M[p], x[p], y[p]); });
+}
+
+nuasm_status nuasm_execute_many(nuasm_batch b, const void* const* in, void* const* out) {
+  if (!b || !in || !out) return fail(NUASM_ERR_INVALID_ARG, "NULL argument");
+  const int P = (int)b->plans.size();
+  std::vector<const void*> key;
+  std::vector<int64_t> Ms(P);
+  key.reserve(3 * P);
+  for (int p = 0; p < P; ++p) {
+    const nuasm_plan_s* pl = b->plans[p];
+    if (!pl->ready()) return fail(NUASM_ERR_NOT_READY, "plane " + std::to_string(p) + ": execute_many before set_points_many");
+    // launch grids follow the bound point counts, so they are part of the key
+    Ms[p] = pl->ps[0].M;
+    key.push_back((const void*)(intptr_t)Ms[p]);
+    key.push_back(in[p]);
+    key.push_back(out[p]);
   }
-  for (size_t k = 0; e == hipSuccess && k < (size_t)b->active; ++k) {
-    e = hipEventRecord(b->join[k], b->branch[k]);
-    if (e == hipSuccess) e = hipStreamWaitEvent(b->cap, b->join[k], 0);
-  }
-  hipGraph_t graph = nullptr;
-  hipError_t e2 = hipStreamEndCapture(b->cap, &graph);
-  for (nuasm_plan_s* pl : b->plans) pl->stream = b->stream;
-  if (st != NUASM_OK || e != hipSuccess || e2 != hipSuccess) {
-    if (graph) (void)hipGraphDestroy(graph);
-    if (st != NUASM_OK) return st;
-    return hip_fail(e != hipSuccess ? e : e2, "graph capture");
-  }
-  e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(graph);
-  if (e != hipSuccess) {
-    b->exec = nullptr;
-    return hip_fail(e, "hipGraphInstantiate");
-  }
-  b->key = key;
-  return launch();
+  return batch_launch(b, b->g_exec, key, Ms, [&](nuasm_plan_s* pl, int p) { return nuasm_execute(pl, in[p], out[p]); });
 }
 
 namespace {
-// Drop the recorded graph so that the next run records it again.
+// Drop the recorded graphs so that the next runs record them again.
 nuasm_status batch_invalidate(nuasm_batch_s* b) {
-  if (!b->exec) return NUASM_OK;
   HIP_TRY(hipStreamSynchronize(b->cap), "hipStreamSynchronize");
-  (void)hipGraphExecDestroy(b->exec);
-  b->exec = nullptr;
-  b->key.clear();
+  drop_graph(b->g_run);
+  drop_graph(b->g_bin);
+  drop_graph(b->g_exec);
   return NUASM_OK;
 }
 }  // namespace
@@ -1475,7 +1743,7 @@ nuasm_status nuasm_batch_check_points(nuasm_batch b, int32_t* bad_plane) {
   for (size_t p = 0; p < b->plans.size(); ++p) {
     nuasm_plan_s* pl = b->plans[p];
     PointSet& q = pl->ps[0];
-    HIP_TRY(hipMemcpy(q.host_stat, q.nch, sizeof(int) * 5, hipMemcpyDeviceToHost), "hipMemcpy");
+    HIP_TRY(hipMemcpy(q.host_stat, q.nch, sizeof(int) * 6, hipMemcpyDeviceToHost), "hipMemcpy");
     const nuasm_status ps = point_status(q, 0);
     if (ps != NUASM_OK) {
       *bad_plane = (int32_t)p;

@@ -165,3 +165,22 @@ def test_status_strings(P):
     names = [lib.nuasm_status_string(i).decode() for i in range(8)]
     assert names[0] == "NUASM_OK" and len(set(names)) == 8
     assert lib.nuasm_version() >= 100
+
+
+def test_boundary_calls_reject_null_handles(P):
+    lib = P.load()
+    b = ctypes.c_size_t()
+    name = lambda st: lib.nuasm_status_string(st).decode()  # noqa: E731
+    assert name(lib.nuasm_plan_workspace_bytes(None, 100, ctypes.byref(b))) == "NUASM_ERR_INVALID_ARG"
+    assert name(lib.nuasm_plan_set_workspace(None, None, 0)) == "NUASM_ERR_INVALID_ARG"
+    M = (ctypes.c_int64 * 1)(10)
+    vp = (ctypes.c_void_p * 1)(None)
+    assert name(lib.nuasm_set_points_many(None, M, vp, vp)) == "NUASM_ERR_INVALID_ARG"
+    assert name(lib.nuasm_execute_many(None, vp, vp)) == "NUASM_ERR_INVALID_ARG"
+    h = ctypes.c_void_p(123)
+    p = P.Params()
+    assert lib.nuasm_params_default(ctypes.byref(p)) == 0
+    assert name(lib.nuasm_plan_many_create(0, ctypes.byref(p), None, ctypes.byref(h))) == "NUASM_ERR_INVALID_ARG"
+    assert h.value is None
+    t = P.Tuning(0, 0, 0, 3)
+    assert name(lib.nuasm_plan_set_tuning(None, ctypes.byref(t))) == "NUASM_ERR_INVALID_ARG"
