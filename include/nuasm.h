@@ -140,11 +140,12 @@ typedef struct {
                                  else 256 .. 65536 */
   int32_t bin_range_points;   /* points per binning workgroup: 0 = automatic
                                  (max(4096, M/256), at most 65535), else 1024 .. 65535 */
-  int32_t spread_method;      /* 0 = automatic (LDS scatter; the gather form in
-                                 deterministic mode), 1 = gather (each output cell
-                                 sums the records covering it, in registers),
-                                 2 = LDS scatter (float atomic adds into an LDS
-                                 tile; not allowed in deterministic mode) */
+  int32_t spread_method;      /* 0 = automatic (matrix cores), 1 = register gather
+                                 (each output cell sums the records covering it on
+                                 the vector ALUs), 2 = matrix cores (each quarter
+                                 bin as sums of outer products on v_mfma_f32 units).
+                                 Both are float32 and reproducible in
+                                 deterministic mode */
 } nuasm_tuning;
 
 typedef struct nuasm_plan_s* nuasm_plan;

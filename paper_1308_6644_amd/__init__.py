@@ -346,7 +346,7 @@ class Plan:
     def set_tuning(self, spread_chunk: int = 0, interp_chunk: int = 0, bin_range_points: int = 0,
                    spread_method: int = 0):
         """Launch-shape tuning (0 = default); binned points must be set again.
-        spread_method: 0 automatic, 1 gather, 2 LDS scatter."""
+        spread_method: 0 automatic, 1 register gather, 2 matrix cores."""
         t = Tuning(int(spread_chunk), int(interp_chunk), int(bin_range_points), int(spread_method))
         _check(load().nuasm_plan_set_tuning(self._h, ctypes.byref(t)))
         return self

@@ -103,26 +103,44 @@ k_bin_hist(const double* __restrict__ x, const double* __restrict__ y, int64_t M
   for (int b = threadIdx.x; b <= T; b += kBinThreads) row[b] = (uint16_t)((sh[b >> 1] >> ((b & 1) * 16)) & 0xffffu);
 }
 
-// Scan over the bins, run by one workgroup: first record of every bin (written to
-// `cursor`, the bin bases the scatter adds), and the chunk tables.  Spreading
-// needs a chunk for every bin (empty bins write zeros); interpolation only for
-// non-empty bins.  A bin with more than so.sp_chunk (so.ip_chunk) records is
-// split into several spreading (interpolation) chunks; for spreading those bins are
-// listed in `multi` for the reduction, and their chunks get consecutive slots
-// of the partial-tile scratch (nch[5] slots in all).  Both chunk tables are ordered by the
-// size of their bin, largest first (17 size classes, a bin's chunks kept
-// together), so that the dispatcher starts the longest workgroups first.
-// counts[T] (one past the bins) is the number of points outside the window;
-// it is copied to nch[4].  Each thread owns a contiguous run of bins; the
-// block-wide exclusive scan is two wave-shuffle scans around one LDS step.
-constexpr int kScanThreads = 1024;
-constexpr int kScanRegs = 8;  // bins per thread kept in registers
-constexpr int kSizeClasses = 17;
+// Column scan and bin scan.  The column scan gives off[g][b] = sum_{g' < g}
+// hist[g'][b] and the bin totals (records per bin; entry T of the rows counts
+// the points outside the window).  The bin scan turns the totals into the
+// first record of every bin (`cursor`, the bin bases the scatter adds) and the
+// chunk tables.  Spreading needs a chunk for every bin (empty bins write
+// zeros); interpolation only for non-empty bins.  A bin with more than
+// so.sp_chunk (so.ip_chunk) records is split into several spreading
+// (interpolation) chunks; for spreading those bins are listed in `multi` for
+// the reduction, and their chunks get consecutive slots of the partial-tile
+// scratch (nch[5] slots in all).  Both chunk tables are ordered by the size
+// class of their bin, largest first (a bin's chunks kept together, bins in
+// index order inside a class), so that the dispatcher starts the longest
+// workgroups first.
+//
+// One launch does both.  A workgroup owns 64 consecutive bins (a lane each)
+// and splits the G ranges over its 16 waves; its last wave, holding the
+// totals, also scans its 64 bins: exclusive prefixes of the records, of the
+// split bins, of their slots and of the chunks of each size class, stored per
+// bin, and the workgroup's sums of the same quantities.  The last workgroup
+// to finish (counted in `done`, which it resets) scans those sums over the
+// workgroups and writes every bin's entries.  The counter is bumped after a
+// release fence and read back before an acquire fence, so every workgroup's
+// stores are visible to the last one.  No workgroup waits for another.
+constexpr int kColWaves = 16;
+constexpr int kColThreads = 64 * kColWaves;
+constexpr int kClasses = 4;       // chunk size classes per table
+constexpr int kColRegs = 16;      // ranges per wave held in registers (G <= 256)
+constexpr int kColBatch = 5;      // bins per thread whose entries are read together (T <= 5120 in one pass)
+// per-workgroup sums: records, split bins, slots, then the chunks of each
+// class of the spreading and of the interpolation table
+constexpr int kWgRec = 0, kWgMulti = 1, kWgSlot = 2, kWgSp = 3, kWgIp = 3 + kClasses;
+constexpr int kWgVals = 3 + 2 * kClasses;  // 11
+static_assert(kWgVals <= kBinPre, "per-bin prefixes fit the table row");
 
-// size class of a bin's chunks of at most `chunk` records: 16 for bins of at
-// least one full chunk, else 16 c / chunk
+// size class of a bin of c records split into chunks of at most `chunk`:
+// 3 for a full chunk, 2 for at least half, 1 for at least an eighth, else 0
 __device__ __forceinline__ int size_class(int c, int chunk) {
-  return c >= chunk ? kSizeClasses - 1 : (c * (kSizeClasses - 1)) / chunk;
+  return c >= chunk ? 3 : 2 * c >= chunk ? 2 : 8 * c >= chunk ? 1 : 0;
 }
 
 __device__ __forceinline__ int wave_incl_scan(int v, int lane) {
@@ -134,156 +152,100 @@ __device__ __forceinline__ int wave_incl_scan(int v, int lane) {
   return v;
 }
 
-// `counts` is written by other workgroups of the same launch (see
-// k_bin_colscan), so it is read through a plain pointer.
-__device__ __forceinline__ void bin_scan_body(const int* counts, int T, const BinScanOut& so) {
-  int* __restrict__ cursor = so.cursor;
-  int4* __restrict__ sp_chunks = so.sp_chunks;
-  int* __restrict__ sp_first = so.sp_first;
-  int* __restrict__ sp_n = so.sp_n;
-  int* __restrict__ multi = so.multi;
-  int4* __restrict__ ip_chunks = so.ip_chunks;
-  int* __restrict__ nch = so.nch;
-  const int spc = so.sp_chunk, ipc = so.ip_chunk;
-  constexpr int NW = kScanThreads / 64;
-  __shared__ int wsum[5][NW];
-  __shared__ int cls_n[2][kSizeClasses], cls_base[2][kSizeClasses];  // spreading, interpolation
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  if (tid < 2 * kSizeClasses) cls_n[tid / kSizeClasses][tid % kSizeClasses] = 0;
-  const int per = (T + kScanThreads - 1) / kScanThreads;
-  const int b0 = min(T, tid * per), b1 = min(T, b0 + per);
-  int cr[kScanRegs];
-#pragma unroll
-  for (int q = 0; q < kScanRegs; ++q) cr[q] = (b0 + q < b1) ? counts[b0 + q] : 0;
-  __syncthreads();  // cls_n cleared
-  int acc[5] = {0, 0, 0, 0, 0};  // records, spread chunks, interp chunks, multi bins, split-bin chunks
-  for (int q = 0; q < per; ++q) {
-    const int b = b0 + q;
-    const bool valid = b < b1;
-    int c = 0;
-#pragma unroll
-    for (int r = 0; r < kScanRegs; ++r)
-      if (r == q) c = cr[r];
-    if (q >= kScanRegs && valid) c = counts[b];
-    const int nsp = !valid ? 0 : c > spc ? (c + spc - 1) / spc : 1;
-    const int nip = (c + ipc - 1) / ipc;
-    acc[0] += c;
-    acc[1] += nsp;
-    acc[2] += nip;
-    acc[3] += nsp > 1 ? 1 : 0;
-    acc[4] += nsp > 1 ? nsp : 0;
-    if (nsp > 0) atomicAdd(&cls_n[0][size_class(c, spc)], nsp);
-    if (nip > 0) atomicAdd(&cls_n[1][size_class(c, ipc)], nip);
-  }
-  int incl[5];
-#pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    incl[k] = wave_incl_scan(acc[k], lane);
-    if (lane == 63) wsum[k][wv] = incl[k];
-  }
-  __syncthreads();
-  if (wv == 0) {
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      const int v = lane < NW ? wsum[k][lane] : 0;
-      const int w = wave_incl_scan(v, lane);
-      if (lane < NW) wsum[k][lane] = w - v;  // exclusive wave bases
-    }
-  }
-  if (tid < 2) {  // chunk bases of the size classes, largest class first
-    int run = 0;
-    for (int k = kSizeClasses - 1; k >= 0; --k) {
-      cls_base[tid][k] = run;
-      run += cls_n[tid][k];
-    }
-  }
-  __syncthreads();
-  int run[5];
-#pragma unroll
-  for (int k = 0; k < 5; ++k) run[k] = wsum[k][wv] + incl[k] - acc[k];
-  for (int q = 0; q < per; ++q) {
-    const int b = b0 + q;
-    const bool valid = b < b1;
-    int c = 0;
-#pragma unroll
-    for (int r = 0; r < kScanRegs; ++r)
-      if (r == q) c = cr[r];
-    if (q >= kScanRegs && valid) c = counts[b];
-    const int nsp = !valid ? 0 : c > spc ? (c + spc - 1) / spc : 1;
-    const int nip = (c + ipc - 1) / ipc;
-    if (!valid) continue;
-    const int first = atomicAdd(&cls_base[0][size_class(c, spc)], nsp);
-    const int ifirst = nip > 0 ? atomicAdd(&cls_base[1][size_class(c, ipc)], nip) : 0;
-    cursor[b] = run[0];
-    sp_first[b] = first;
-    sp_n[b] = nsp;
-    // .w: the chunk's partial-tile slot when the bin is split, else -1
-    for (int r = 0; r < nsp; ++r)
-      sp_chunks[first + r] =
-          make_int4(b, run[0] + r * spc, min(spc, c - r * spc), nsp > 1 ? run[4] + r : -1);
-    for (int r = 0; r < nip; ++r)
-      ip_chunks[ifirst + r] = make_int4(b, run[0] + r * ipc, min(ipc, c - r * ipc), nip);
-    if (nsp > 1) multi[run[3]] = b;
-    run[0] += c;
-    run[1] += nsp;
-    run[2] += nip;
-    run[3] += nsp > 1 ? 1 : 0;
-    run[4] += nsp > 1 ? nsp : 0;
-  }
-  if (tid == kScanThreads - 1) {
-    nch[0] = run[1];
-    nch[1] = run[2];
-    nch[2] = run[0];
-    nch[3] = run[3];
-    nch[4] = counts[T];
-    nch[5] = run[4];
-  }
-}
+__device__ __forceinline__ int spread_chunks(int c, int spc) { return c > spc ? (c + spc - 1) / spc : 1; }
 
-// Column scan: off[g][b] = sum_{g' < g} hist[g'][b], total[b] = sum_g hist[g][b].
-// A workgroup takes 64 consecutive bins (one per lane) and splits the G
-// ranges over its 16 waves.  The last workgroup to finish (counted in `done`,
-// which it resets to zero) then runs the bin scan over the totals; the
-// counter is bumped after a release fence and read back before an acquire
-// fence, so every workgroup's totals are visible to it.  No workgroup waits
-// for another.
-constexpr int kColWaves = 16;
-static_assert(64 * kColWaves == kScanThreads, "the last column-scan workgroup runs the bin scan");
-
-__global__ void __launch_bounds__(64 * kColWaves)
+__global__ void __launch_bounds__(kColThreads)
 k_bin_colscan(const uint16_t* __restrict__ hist, int G, int T, int* __restrict__ off, int* total,
               BinScanOut so, int* __restrict__ done) {
-  // T here is the row length (bins + 1)
+  // T: bins; rows of hist and off have T + 1 entries
+  const int R = T + 1;
   __shared__ int part[kColWaves][64];
+  __shared__ int last;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int b = blockIdx.x * 64 + lane;
   const int per = (G + kColWaves - 1) / kColWaves;
   const int g0 = min(G, wv * per), g1 = min(G, g0 + per);
   int s = 0;
-  if (b < T) {
-#pragma unroll 8
-    for (int gg = g0; gg < g1; ++gg) s += hist[(size_t)gg * T + b];
-  }
-  part[wv][lane] = s;
-  __syncthreads();
-  int base = 0;
-  for (int q = 0; q < wv; ++q) base += part[q][lane];
-  if (b < T) {
-    int run = base;
-#pragma unroll 8
-    for (int gg = g0; gg < g1; ++gg) {
-      const int h = hist[(size_t)gg * T + b];
-      off[(size_t)gg * T + b] = run;
-      run += h;
+  if (per <= kColRegs) {
+    // one pass: the wave's rows held in registers
+    int h[kColRegs];
+#pragma unroll
+    for (int q = 0; q < kColRegs; ++q) h[q] = (b < R && g0 + q < g1) ? hist[(size_t)(g0 + q) * R + b] : 0;
+#pragma unroll
+    for (int q = 0; q < kColRegs; ++q) s += h[q];
+    part[wv][lane] = s;
+    __syncthreads();
+    int run = 0;
+    for (int q = 0; q < wv; ++q) run += part[q][lane];
+    if (b < R) {
+#pragma unroll
+      for (int q = 0; q < kColRegs; ++q) {
+        if (g0 + q < g1) off[(size_t)(g0 + q) * R + b] = run;
+        run += h[q];
+      }
+      if (wv == kColWaves - 1) total[b] = run;
     }
-    if (wv == kColWaves - 1) total[b] = run;
+  } else {
+    if (b < R) {
+#pragma unroll 8
+      for (int gg = g0; gg < g1; ++gg) s += hist[(size_t)gg * R + b];
+    }
+    part[wv][lane] = s;
+    __syncthreads();
+    int run = 0;
+    for (int q = 0; q < wv; ++q) run += part[q][lane];
+    if (b < R) {
+#pragma unroll 8
+      for (int gg = g0; gg < g1; ++gg) {
+        const int hv = hist[(size_t)gg * R + b];
+        off[(size_t)gg * R + b] = run;
+        run += hv;
+      }
+      if (wv == kColWaves - 1) total[b] = run;
+    }
   }
-  // the totals come from the last wave only: it releases them and bumps the
-  // counter; in the last workgroup it also acquires the others' totals for
-  // the whole workgroup (one CU, one L2), which the barrier then orders
-  // before every wave's reads
-  __shared__ int last;
   if (wv == kColWaves - 1) {
+    // the workgroup's 64 bins: per-bin exclusive prefixes and the sums
+    int c = 0;
+    if (b < T) {
+      c = part[0][lane];
+      for (int q = 1; q < kColWaves; ++q) c += part[q][lane];
+    }
+    const bool valid = b < T;
+    const int nsp = valid ? spread_chunks(c, so.sp_chunk) : 0;
+    const int nip = (c + so.ip_chunk - 1) / so.ip_chunk;
+    const int ksp = size_class(c, so.sp_chunk), kip = size_class(c, so.ip_chunk);
+    int v[kWgVals];
+    v[kWgRec] = c;
+    v[kWgMulti] = nsp > 1 ? 1 : 0;
+    v[kWgSlot] = nsp > 1 ? nsp : 0;
+#pragma unroll
+    for (int k = 0; k < kClasses; ++k) {
+      v[kWgSp + k] = ksp == k ? nsp : 0;
+      v[kWgIp + k] = kip == k ? nip : 0;
+    }
+    int pre[kWgVals];
+#pragma unroll
+    for (int i = 0; i < kWgVals; ++i) {
+      const int inc = wave_incl_scan(v[i], lane);
+      pre[i] = inc - v[i];
+      if (lane == 63) so.wg_sum[(size_t)blockIdx.x * kBinPre + i] = inc;
+    }
+    if (valid) {
+      int* bp = so.bin_pre + (size_t)b * kBinPre;
+      bp[0] = pre[kWgRec];
+      bp[1] = pre[kWgMulti];
+      bp[2] = pre[kWgSlot];
+      int psp = 0, pip = 0;
+#pragma unroll
+      for (int k = 0; k < kClasses; ++k) {
+        if (ksp == k) psp = pre[kWgSp + k];
+        if (kip == k) pip = pre[kWgIp + k];
+      }
+      bp[3] = psp;
+      bp[4] = pip;
+    }
+    // release this workgroup's stores, then count it
     __threadfence();
     if (lane == 0) {
       const bool l = atomicAdd(done, 1) == (int)gridDim.x - 1;
@@ -293,8 +255,92 @@ k_bin_colscan(const uint16_t* __restrict__ hist, int G, int T, int* __restrict__
   }
   __syncthreads();
   if (!last) return;
-  bin_scan_body(total, T - 1, so);
-  if (threadIdx.x == 0) *done = 0;
+
+  // ---- the last workgroup: scan the workgroup sums, write every bin's entries
+  const int nwg = (int)gridDim.x;
+  extern __shared__ int wgpre[];  // [nwg][kWgVals] exclusive prefixes over the workgroups
+  __shared__ int tot[kWgVals];
+  __shared__ int cbase[2][kClasses];
+  if (wv < kWgVals) {
+    // wave i scans value i over the workgroups, 64 at a time
+    const int i = wv;
+    int carry = 0;
+    for (int w0 = 0; w0 < nwg; w0 += 64) {
+      const int w = w0 + lane;
+      const int x = w < nwg ? so.wg_sum[(size_t)w * kBinPre + i] : 0;
+      const int inc = wave_incl_scan(x, lane);
+      if (w < nwg) wgpre[w * kWgVals + i] = carry + inc - x;
+      carry += __shfl(inc, 63, 64);
+    }
+    if (lane == 0) tot[i] = carry;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    // class bases, largest class first
+    const int t = threadIdx.x, o = t == 0 ? kWgSp : kWgIp;
+    int run = 0;
+    for (int k = kClasses - 1; k >= 0; --k) {
+      cbase[t][k] = run;
+      run += tot[o + k];
+    }
+  }
+  __syncthreads();
+  const int spc = so.sp_chunk, ipc = so.ip_chunk;
+  // every bin's entries: the reads of up to kColBatch bins per thread are
+  // issued together before any is used
+  for (int b0 = 0; b0 < T; b0 += kColThreads * kColBatch) {
+    int cb[kColBatch], pre[kColBatch][5];
+#pragma unroll
+    for (int u = 0; u < kColBatch; ++u) {
+      const int bb = b0 + threadIdx.x + u * kColThreads;
+      cb[u] = 0;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) pre[u][v] = 0;
+      if (bb < T) {
+        cb[u] = total[bb];
+        const int* bp = so.bin_pre + (size_t)bb * kBinPre;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) pre[u][v] = bp[v];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kColBatch; ++u) {
+      const int bb = b0 + threadIdx.x + u * kColThreads;
+      if (bb >= T) continue;
+      const int w = bb >> 6;
+      const int c = cb[u];
+      const int nsp = spread_chunks(c, spc);
+      const int nip = (c + ipc - 1) / ipc;
+      const int ksp = size_class(c, spc), kip = size_class(c, ipc);
+      const int rec0 = wgpre[w * kWgVals + kWgRec] + pre[u][0];
+      const int first = cbase[0][ksp] + wgpre[w * kWgVals + kWgSp + ksp] + pre[u][3];
+      const int ifirst = cbase[1][kip] + wgpre[w * kWgVals + kWgIp + kip] + pre[u][4];
+      const int slot0 = wgpre[w * kWgVals + kWgSlot] + pre[u][2];
+      so.cursor[bb] = rec0;
+      so.sp_first[bb] = first;
+      so.sp_n[bb] = nsp;
+      // .w: the chunk's partial-tile slot when the bin is split, else -1
+      for (int r = 0; r < nsp; ++r)
+        so.sp_chunks[first + r] = make_int4(bb, rec0 + r * spc, min(spc, c - r * spc), nsp > 1 ? slot0 + r : -1);
+      for (int r = 0; r < nip; ++r)
+        so.ip_chunks[ifirst + r] = make_int4(bb, rec0 + r * ipc, min(ipc, c - r * ipc), nip);
+      if (nsp > 1) so.multi[wgpre[w * kWgVals + kWgMulti] + pre[u][1]] = bb;
+    }
+  }
+  if (threadIdx.x == 0) {
+    int nsp_all = 0, nip_all = 0;
+    for (int k = 0; k < kClasses; ++k) {
+      nsp_all += tot[kWgSp + k];
+      nip_all += tot[kWgIp + k];
+    }
+    so.nch[0] = nsp_all;
+    so.nch[1] = nip_all;
+    so.nch[2] = tot[kWgRec];
+    so.nch[3] = tot[kWgMulti];
+    so.nch[4] = total[T];
+    so.nch[5] = tot[kWgSlot];
+    *done = 0;
+  }
 }
 
 // CURSORS: the workgroup's write cursors bin_base[b] + off[g][b] are staged in
@@ -689,6 +735,170 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(SpreadArgs a) {
   }
 }
 
+// ----------------------------------------------- spreading on the matrix cores
+// The spreading of one bin is a sum of outer products: cell (y, x) receives
+// sum_j c_j wy_j(y) wx_j(x) over the bin's records j, where wy_j, wx_j are the
+// record's kernel weights (zero outside its w taps).  For a 16 x 16 quarter of
+// the bin that is D = A B with A[y][j] = c_j wy_j(y) and B[j][x] = wx_j(x): a
+// contraction over the record index, which v_mfma_f32_16x16x4f32 evaluates
+// four records at a time (float32 products and sums; the real and imaginary
+// parts of c in two accumulators).  Each of the workgroup's four waves owns a
+// quarter and walks, in groups of four, the records of the sub-batch whose
+// footprint meets it (lists built with wave ballots, in record order, so the
+// result does not depend on timing).  Operand lane l supplies A[i][k] and
+// B[k][i] for record k = l / 16 of the group and row / column i = l % 16; the
+// accumulator element e of lane l is D[4 (l / 16) + e][l % 16].
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+struct __align__(16) MfmaRec {
+  float cr, ci;  // the point's value
+  int lxy;       // first tap relative to the bin origin: column (low 16 bits), row (high)
+  int pad;
+};
+
+// Sub-batches of 256 records (one per thread), loaded one ahead: the LDS
+// footprint (about 21 KB at w = 7) and the registers leave room for six to
+// seven workgroups per CU, which hide the load and LDS latencies.
+constexpr int kMfmaSB = kSpreadThreads;
+
+template <int W>
+__global__ void __launch_bounds__(kSpreadThreads) k_spread_mfma(SpreadArgs a) {
+  constexpr int SB = kMfmaSB, NWV = kSpreadThreads / 64;  // 4 waves, one quarter each
+  __shared__ MfmaRec srec[SB];
+  __shared__ float swx[SB * W];
+  __shared__ float swy[SB * W];
+  __shared__ unsigned short slist[4][SB];
+  __shared__ int scnt[NWV][4];
+  __shared__ int sbase[NWV][4];
+  __shared__ int slen[4];
+  const int cid = blockIdx.x;
+  if (cid >= a.nchunks[0]) return;
+  const int4 ch = a.chunks[cid];
+  const int bin = ch.x, start = ch.y, n = ch.z, slot = ch.w;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const float blog = a.beta * 1.4426950408889634f;
+  // this wave's quarter and the lane's operand row / column and record slot
+  const int sx0 = 16 * (wv & 1), sy0 = 16 * (wv >> 1);
+  const int kk = lane >> 4, ii = lane & 15;
+  v4f accr = {0.f, 0.f, 0.f, 0.f}, acci = {0.f, 0.f, 0.f, 0.f};
+  v4f accr2 = {0.f, 0.f, 0.f, 0.f}, acci2 = {0.f, 0.f, 0.f, 0.f};
+  const unsigned long long below = (1ull << lane) - 1ull;
+  // the thread's record of the first sub-batch and its value
+  BinRec rc;
+  rc.packed = 0;
+  rc.dx = rc.dy = 0.f;
+  rc.idx = -1;
+  if (t < n) rc = a.recs[start + t];
+  float2 cv = t < n ? a.vals[rc.idx] : czero();
+  for (int b0 = 0; b0 < n; b0 += SB) {
+    const int nsb = min(SB, n - b0);
+    const bool ok = t < nsb;
+    // the next sub-batch's record, in flight while this one is staged; its
+    // value is requested once the record has arrived (after the staging)
+    BinRec nx;
+    nx.packed = 0;
+    nx.dx = nx.dy = 0.f;
+    nx.idx = -1;
+    const bool more = b0 + SB + t < n;
+    if (more) nx = a.recs[start + b0 + SB + t];
+    // stage: value, first tap, kernel weights; list the record under every
+    // quarter its footprint meets
+    int lx = 0, ly = 0;
+    if (ok) {
+      lx = rec_lx(rc.packed);
+      ly = rec_ly(rc.packed);
+      MfmaRec m;
+      m.cr = cv.x;
+      m.ci = cv.y;
+      m.lxy = (lx & 0xffff) | (ly << 16);
+      m.pad = 0;
+      srec[t] = m;
+#pragma unroll
+      for (int mm = 0; mm < W; ++mm) {
+        swx[t * W + mm] = es_kernel_fast(rc.dx + (float)mm, a.two_over_w, blog);
+        swy[t * W + mm] = es_kernel_fast(rc.dy + (float)mm, a.two_over_w, blog);
+      }
+    }
+    int rank[4];
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int qx = 16 * (s4 & 1), qy = 16 * (s4 >> 1);
+      const bool meets = ok && lx <= qx + 15 && lx + W - 1 >= qx && ly <= qy + 15 && ly + W - 1 >= qy;
+      const unsigned long long bal = __ballot(meets);
+      rank[s4] = meets ? __popcll(bal & below) : -1;
+      if (lane == 0) scnt[wv][s4] = __popcll(bal);
+    }
+    __syncthreads();
+    // list bases: records of earlier waves first
+    if (t < 4) {
+      int run = 0;
+      for (int w2 = 0; w2 < NWV; ++w2) {
+        const int c2 = scnt[w2][t];
+        sbase[w2][t] = run;
+        run += c2;
+      }
+      slen[t] = run;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4)
+      if (rank[s4] >= 0) slist[s4][sbase[wv][s4] + rank[s4]] = (unsigned short)t;
+    __syncthreads();
+    const float2 nv = more ? a.vals[nx.idx] : czero();
+    const int len = slen[wv];
+    // the wave's quarter: groups of four listed records, two groups per step
+    // into two accumulator pairs, so that consecutive matrix operations are
+    // independent and both groups' loads are in flight together
+    for (int g = 0; g < len; g += 8) {
+      int j[2];
+      bool valid[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int idx = g + 4 * h + kk;
+        valid[h] = idx < len;
+        j[h] = valid[h] ? (int)slist[wv][idx] : 0;
+      }
+      MfmaRec m[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) m[h] = srec[j[h]];
+      float ay[2], bx[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int mlx = (int)(short)(m[h].lxy & 0xffff), mly = m[h].lxy >> 16;
+        const int dy = sy0 + ii - mly, dx = sx0 + ii - mlx;
+        const bool iny = valid[h] && (unsigned)dy < (unsigned)W;
+        const bool inx = valid[h] && (unsigned)dx < (unsigned)W;
+        const float wy = swy[j[h] * W + (iny ? dy : 0)];
+        const float wx = swx[j[h] * W + (inx ? dx : 0)];
+        ay[h] = iny ? wy : 0.f;
+        bx[h] = inx ? wx : 0.f;
+      }
+      accr = __builtin_amdgcn_mfma_f32_16x16x4f32(m[0].cr * ay[0], bx[0], accr, 0, 0, 0);
+      acci = __builtin_amdgcn_mfma_f32_16x16x4f32(m[0].ci * ay[0], bx[0], acci, 0, 0, 0);
+      accr2 = __builtin_amdgcn_mfma_f32_16x16x4f32(m[1].cr * ay[1], bx[1], accr2, 0, 0, 0);
+      acci2 = __builtin_amdgcn_mfma_f32_16x16x4f32(m[1].ci * ay[1], bx[1], acci2, 0, 0, 0);
+    }
+    __syncthreads();
+    rc = nx;
+    cv = nv;
+  }
+  accr += accr2;
+  acci += acci2;
+  // accumulator element e of lane l: quarter row 4 (l / 16) + e, column l % 16
+  const int bx = bin % a.TX, by = bin / a.TX;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int yy = sy0 + 4 * kk + e, xx = sx0 + ii;
+    const float2 v = make_float2(accr[e], acci[e]);
+    if (slot < 0) {
+      const int gy = by * kTile + yy, gx = bx * kTile + xx;
+      if (gy < a.L && gx < a.L) a.grid[(size_t)gy * a.L + gx] = v;
+    } else {
+      a.scratch[(size_t)slot * (kTile * kTile) + yy * kTile + xx] = v;
+    }
+  }
+}
+
 // Sum the partial tiles of every multi-chunk bin, in chunk order (the bin's
 // chunks hold consecutive scratch slots, the first one's in its table entry).
 __global__ void __launch_bounds__(256) k_spread_reduce(SpreadReduceArgs a) {
@@ -703,89 +913,6 @@ __global__ void __launch_bounds__(256) k_spread_reduce(SpreadReduceArgs a) {
     const int yy = e / kTile, xx = e % kTile;
     const int gy = by * kTile + yy, gx = bx * kTile + xx;
     if (gy < a.L && gx < a.L) a.grid[(size_t)gy * a.L + gx] = s;
-  }
-}
-
-// Scatter form: one workgroup per chunk of a bin accumulates every record's
-// w x w taps into an LDS tile with native float atomic adds (ds_add_f32), one
-// plane for the real and one for the imaginary parts.  The tile is the bin
-// padded by w - 1 cells on every side, so that the taps of a record whose
-// first tap lies up to w - 1 cells before the bin (a duplicate recorded in
-// this bin) land in the padding without a bounds test; only the 32 x 32
-// interior is written out.  Tap (my, mx) of a record is at a compile-time
-// offset my * TS + mx from the record's first tap, so each add is one LDS
-// instruction with an immediate offset.  The order of the additions into a
-// cell is not fixed (deterministic mode uses the gather form).
-template <int W>
-struct SpreadLdsCfg {
-  static constexpr int TS = kTile + 2 * (W - 1);  // padded tile side
-  static constexpr int NT = 256;
-  static constexpr int B = 2;                     // records per thread in flight
-};
-
-template <int W>
-__global__ void __launch_bounds__(SpreadLdsCfg<W>::NT) k_spread_lds(SpreadArgs a) {
-  using Cfg = SpreadLdsCfg<W>;
-  constexpr int TS = Cfg::TS, NT = Cfg::NT, B = Cfg::B;
-  __shared__ float sre[TS * TS];
-  __shared__ float sim[TS * TS];
-  const int cid = blockIdx.x;
-  if (cid >= a.nchunks[0]) return;
-  const int4 ch = a.chunks[cid];
-  const int bin = ch.x, start = ch.y, n = ch.z, slot = ch.w;
-  const int t = threadIdx.x;
-  for (int e = t; e < TS * TS; e += NT) {
-    sre[e] = 0.f;
-    sim[e] = 0.f;
-  }
-  __syncthreads();
-  const float blog = a.beta * 1.4426950408889634f;
-  for (int r0 = 0; r0 < n; r0 += NT * B) {
-    BinRec rl[B];
-    float2 cv[B];
-#pragma unroll
-    for (int q = 0; q < B; ++q) {
-      const int r = r0 + t + q * NT;
-      rl[q].packed = 0;
-      rl[q].dx = rl[q].dy = 0.f;
-      rl[q].idx = -1;
-      if (r < n) rl[q] = a.recs[start + r];
-    }
-#pragma unroll
-    for (int q = 0; q < B; ++q) cv[q] = rl[q].idx >= 0 ? a.vals[rl[q].idx] : czero();
-#pragma unroll
-    for (int q = 0; q < B; ++q) {
-      if (rl[q].idx < 0) continue;
-      const int base = (rec_ly(rl[q].packed) + W - 1) * TS + rec_lx(rl[q].packed) + W - 1;
-      float wx[W];
-#pragma unroll
-      for (int m = 0; m < W; ++m) wx[m] = es_kernel_fast(rl[q].dx + (float)m, a.two_over_w, blog);
-#pragma unroll
-      for (int my = 0; my < W; ++my) {
-        const float wy = es_kernel_fast(rl[q].dy + (float)my, a.two_over_w, blog);
-        const float cr = cv[q].x * wy, ci = cv[q].y * wy;
-        float* pr = sre + base + my * TS;
-        float* pi = sim + base + my * TS;
-#pragma unroll
-        for (int mx = 0; mx < W; ++mx) {
-          atomicAdd(pr + mx, cr * wx[mx]);
-          atomicAdd(pi + mx, ci * wx[mx]);
-        }
-      }
-    }
-  }
-  __syncthreads();
-  const int bx = bin % a.TX, by = bin / a.TX;
-  for (int e = t; e < kTile * kTile; e += NT) {
-    const int yy = e / kTile, xx = e % kTile;
-    const int s = (yy + W - 1) * TS + xx + W - 1;
-    const float2 v = make_float2(sre[s], sim[s]);
-    if (slot < 0) {
-      const int gy = by * kTile + yy, gx = bx * kTile + xx;
-      if (gy < a.L && gx < a.L) a.grid[(size_t)gy * a.L + gx] = v;
-    } else {
-      a.scratch[(size_t)slot * (kTile * kTile) + e] = v;
-    }
   }
 }
 
@@ -890,11 +1017,15 @@ hipError_t launch_bin_hist(const double* x, const double* y, int64_t M, BinGeom 
   return hipGetLastError();
 }
 
+int bin_scan_workgroups(int T) { return (T + 1 + 63) / 64; }
+
 hipError_t launch_bin_colscan(const uint16_t* hist, int G, int T, int* off, int* total, const BinScanOut& so,
                               int* done, hipStream_t st) {
-  const int cols = T + 1;
-  hipLaunchKernelGGL(k_bin_colscan, dim3((cols + 63) / 64), dim3(64 * kColWaves), 0, st, hist, G, cols, off,
-                     total, so, done);
+  const int nwg = bin_scan_workgroups(T);
+  const int bytes = nwg * kWgVals * (int)sizeof(int);
+  hipError_t e = bin_lds_attr((const void*)k_bin_colscan, bytes + 8 * 1024);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_bin_colscan, dim3(nwg), dim3(kColThreads), bytes, st, hist, G, T, off, total, so, done);
   return hipGetLastError();
 }
 
@@ -955,9 +1086,10 @@ hipError_t launch_spread(int w, bool small_chunks, const SpreadArgs& a, int grid
   return hipGetLastError();
 }
 
-hipError_t launch_spread_lds(int w, const SpreadArgs& a, int grid, hipStream_t st) {
+hipError_t launch_spread_mfma(int w, bool small_chunks, const SpreadArgs& a, int grid, hipStream_t st) {
   if (grid <= 0) return hipSuccess;
-#define CALL(W) hipLaunchKernelGGL(k_spread_lds<W>, dim3(grid), dim3(SpreadLdsCfg<W>::NT), 0, st, a)
+  (void)small_chunks;  // any chunk size: sub-batches of 256 records
+#define CALL(W) hipLaunchKernelGGL(k_spread_mfma<W>, dim3(grid), dim3(kSpreadThreads), 0, st, a)
   NUASM_DISPATCH_W(w, CALL)
 #undef CALL
   return hipGetLastError();

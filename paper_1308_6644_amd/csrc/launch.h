@@ -69,9 +69,13 @@ struct BinScanOut {
   int4* ip_chunks;   // interpolation chunks
   int* nch;          // spread chunks, interp chunks, records, multi bins, points out of range,
                      // partial-tile slots of split bins
+  int* bin_pre;      // [T][kBinPre] per-bin prefixes inside the bin's column-scan workgroup
+  int* wg_sum;       // [bin_scan_workgroups(T)][kBinPre] that workgroup's sums
   int sp_chunk;      // max records per spreading chunk
   int ip_chunk;      // max records per interpolation chunk
 };
+constexpr int kBinPre = 12;  // ints per row of bin_pre / wg_sum
+int bin_scan_workgroups(int T);  // workgroups of the column scan over T bins
 constexpr int kScanDone = 7;  // element of nch counting finished column-scan workgroups
 
 struct SpreadArgs {
@@ -132,13 +136,14 @@ constexpr int kBinPointsStable = 1024;  // the same in deterministic mode (stabl
 // hist rows and offset rows have T + 1 entries (entry T: points outside the window)
 hipError_t launch_bin_hist(const double* x, const double* y, int64_t M, BinGeom g, int ppw, int G,
                            uint16_t* hist, hipStream_t st);
+// column scan + bin scan (T bins; hist / off rows of T + 1 entries)
 hipError_t launch_bin_colscan(const uint16_t* hist, int G, int T, int* off, int* total, const BinScanOut& so,
                               int* done, hipStream_t st);
 hipError_t launch_bin_scatter(const double* x, const double* y, int64_t M, BinGeom g, int ppw, int G,
                               const int* off, const int* bin_base, BinRec* recs, bool stable, hipStream_t st);
 hipError_t launch_spread(int w, bool small_chunks, const SpreadArgs& a, int grid, hipStream_t st);
-// spreading by LDS atomic accumulation (order of the sums not fixed)
-hipError_t launch_spread_lds(int w, const SpreadArgs& a, int grid, hipStream_t st);
+// the same spreading as sums of outer products on the matrix cores
+hipError_t launch_spread_mfma(int w, bool small_chunks, const SpreadArgs& a, int grid, hipStream_t st);
 hipError_t launch_spread_reduce(const SpreadReduceArgs& a, int grid, hipStream_t st);
 hipError_t launch_interp(int w, const InterpArgs& a, int grid, hipStream_t st);
 // separable interpolation at a grid: support (L x L) -> R (nrows x nx) -> out (ny x nx)

@@ -172,6 +172,8 @@ struct PointSet {
   int* sp_first = nullptr;
   int* sp_n = nullptr;
   int* multi = nullptr;
+  int* bin_pre = nullptr;    // [T][kBinPre] bin-scan prefixes
+  int* wg_sum = nullptr;     // [column-scan workgroups][kBinPre] their sums
   int* nch = nullptr;  // [8]: chunk and record counts [0..3], points out of range [4], split-bin slots [5],
                        // scan hand-off counter [7]
   int4* sp_chunks = nullptr;
@@ -221,7 +223,7 @@ struct nuasm_plan_s {
   int sp_chunk = kSpreadChunk;
   int ip_chunk = kChunk;
   int bin_ppw = 0;        // points per binning workgroup, 0 = automatic
-  int sp_method = 0;      // spreading: 0 automatic, 1 gather, 2 LDS scatter
+  int sp_method = 0;      // spreading: 0 automatic, 1 register gather, 2 matrix cores
   int nsets = 1;
   size_t bytes = 0;          // device memory the plan allocated itself
   // caller-owned workspace (nuasm_plan_set_workspace): the two grids and the
@@ -270,6 +272,8 @@ void release(nuasm_plan_s* pl) {
     f(q.sp_first);
     f(q.sp_n);
     f(q.multi);
+    f(q.bin_pre);
+    f(q.wg_sum);
     f(q.nch);
     fo(q.sp_chunks);
     fo(q.ip_chunks);
@@ -379,6 +383,8 @@ nuasm_status alloc_point_set(nuasm_plan_s* pl, PointSet& q) {
   HIP_TRY(dalloc(pl, &q.sp_first, (size_t)pl->T), "hipMalloc(bins)");
   HIP_TRY(dalloc(pl, &q.sp_n, (size_t)pl->T), "hipMalloc(bins)");
   HIP_TRY(dalloc(pl, &q.multi, (size_t)pl->T), "hipMalloc(bins)");
+  HIP_TRY(dalloc(pl, &q.bin_pre, (size_t)pl->T * kBinPre), "hipMalloc(bins)");
+  HIP_TRY(dalloc(pl, &q.wg_sum, (size_t)bin_scan_workgroups(pl->T) * kBinPre), "hipMalloc(bins)");
   HIP_TRY(dalloc(pl, &q.nch, (size_t)8), "hipMalloc(counters)");
   HIP_TRY(hipHostMalloc((void**)&q.host_stat, sizeof(int) * 8, hipHostMallocDefault), "hipHostMalloc(status)");
   HIP_TRY(launch_fill_i32(q.nch, 0, 8, pl->stream), "launch fill");
@@ -637,8 +643,8 @@ nuasm_status bind_points(nuasm_plan_s* pl, PointSet& q, int64_t M, const double*
     {
       // column scan and bin scan in one launch; with no points (G = 0) it
       // writes zero totals and empty-bin chunk tables
-      const BinScanOut so{q.cursor, q.sp_chunks, q.sp_first, q.sp_n, q.multi, q.ip_chunks, q.nch, pl->sp_chunk,
-                          pl->ip_chunk};
+      const BinScanOut so{q.cursor, q.sp_chunks, q.sp_first, q.sp_n, q.multi, q.ip_chunks, q.nch,
+                          q.bin_pre, q.wg_sum, pl->sp_chunk, pl->ip_chunk};
       StageScope sc(pl, NUASM_STAGE_BIN_COLSCAN);
       HIP_TRY(launch_bin_colscan(q.hist, M > 0 ? G : 0, pl->T, q.hoff, q.counts, so, q.nch + kScanDone, st),
               "launch bin_colscan");
@@ -733,13 +739,6 @@ nuasm_status bind_grid(nuasm_plan_s* pl, PointSet& q, int64_t nx, int64_t ny, do
   return NUASM_OK;
 }
 
-// Spreading method: the LDS-atomic scatter unless the plan is deterministic
-// (whose sums must run in one fixed order) or the gather form was asked for.
-bool use_lds_spread(const nuasm_plan_s* pl) {
-  if (stable_bins(pl)) return false;
-  return pl->sp_method != 1;
-}
-
 // Spreading of one point set's values onto the fine support (gridA).
 nuasm_status run_spread(nuasm_plan_s* pl, PointSet& q, const float2* vals) {
   hipStream_t st = pl->stream;
@@ -750,6 +749,7 @@ nuasm_status run_spread(nuasm_plan_s* pl, PointSet& q, const float2* vals) {
   }
   nuasm_status s = ensure_scratch(pl, q);
   if (s != NUASM_OK) return s;
+  float2* scratch = q.scratch;
   {
     StageScope sc(pl, NUASM_STAGE_SPREAD);
     SpreadArgs sa{};
@@ -757,17 +757,17 @@ nuasm_status run_spread(nuasm_plan_s* pl, PointSet& q, const float2* vals) {
     sa.stable = stable_bins(pl) ? 1 : 0;
     sa.chunks = q.sp_chunks;
     sa.nchunks = q.nch + 0;
-    sa.scratch = q.scratch;
+    sa.scratch = scratch;
     sa.vals = vals;
     sa.grid = pl->gridA;
     sa.L = pl->geom.L;
     sa.TX = pl->TX;
     sa.two_over_w = 2.0f / (float)pl->w;
     sa.beta = pl->beta;
-    if (use_lds_spread(pl))
-      HIP_TRY(launch_spread_lds(pl->w, sa, sp_grid(pl, q), st), "launch spread_lds");
-    else
+    if (pl->sp_method == 1)
       HIP_TRY(launch_spread(pl->w, pl->sp_small, sa, sp_grid(pl, q), st), "launch spread");
+    else
+      HIP_TRY(launch_spread_mfma(pl->w, pl->sp_small, sa, sp_grid(pl, q), st), "launch spread_mfma");
   }
   {
     StageScope sc(pl, NUASM_STAGE_SPREAD_REDUCE);
@@ -777,7 +777,7 @@ nuasm_status run_spread(nuasm_plan_s* pl, PointSet& q, const float2* vals) {
     ra.nmulti = q.nch + 3;
     ra.bin_chunk0 = q.sp_first;
     ra.bin_nchunk = q.sp_n;
-    ra.scratch = q.scratch;
+    ra.scratch = scratch;
     ra.grid = pl->gridA;
     ra.L = pl->geom.L;
     ra.TX = pl->TX;
@@ -1150,9 +1150,7 @@ nuasm_status nuasm_plan_set_tuning(nuasm_plan pl, const nuasm_tuning* t) {
   if (t->spread_chunk < 0 || t->interp_chunk < 0 || t->bin_range_points < 0)
     return fail(NUASM_ERR_INVALID_ARG, "tuning fields must be >= 0");
   if (t->spread_method < 0 || t->spread_method > 2)
-    return fail(NUASM_ERR_INVALID_ARG, "spread_method must be 0 (automatic), 1 (gather) or 2 (LDS scatter)");
-  if (t->spread_method == 2 && stable_bins(pl))
-    return fail(NUASM_ERR_INVALID_ARG, "the LDS scatter's sums have no fixed order: not in deterministic mode");
+    return fail(NUASM_ERR_INVALID_ARG, "spread_method must be 0 (automatic), 1 (register gather) or 2 (matrix cores)");
   if (t->interp_chunk != 0 && (t->interp_chunk < 256 || t->interp_chunk > 65536))
     return fail(NUASM_ERR_INVALID_ARG, "interp_chunk must be 0 or in [256, 65536]");
   if (t->bin_range_points != 0 && (t->bin_range_points < 1024 || t->bin_range_points > kBinPointsMax))

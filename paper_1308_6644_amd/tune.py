@@ -5,7 +5,7 @@ transfer function, log2 of the point count):
   * spread_chunk      -- records per spreading workgroup (1792 or the small size),
   * interp_chunk      -- records per interpolation workgroup (1024 .. 8192),
   * bin_range_points  -- points per binning workgroup (automatic or 4096 .. 65535),
-  * spread_method     -- spreading by LDS atomic scatter or by register gather,
+  * spread_method     -- spreading on the matrix cores or by register gather,
 and, per batch, the number of parallel graph branches (1 .. 4).  The 32 x 32
 bin tile itself is fixed: the spreading and interpolation kernels size their
 LDS tiles and register blocks for it at compile time.
