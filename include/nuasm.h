@@ -248,6 +248,23 @@ nuasm_status nuasm_check_points(nuasm_plan plan);
  * caller-owned, non-overlapping. */
 nuasm_status nuasm_execute(nuasm_plan plan, const void* in_dev, void* out_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): nuasm_execute
+ * exactly, except that the partial tiles of bins split over several spreading
+ * workgroups go to a static device array of the library (2048 tiles of 32 x 32
+ * complex64, 16 MiB per device, held until the process ends) instead of the
+ * plan's own scratch, and no stage-timing events are recorded.  Calls no
+ * hipMalloc / hipFree or any other allocating routine: every other buffer was
+ * sized when the plan was created and its points bound.  The array is shared
+ * by every call on a device and keeps the last call's contents; every tile a
+ * call reads is written earlier in that call, so nothing needs clearing, but
+ * calls whose work overlaps on one device (two streams, two threads) race on
+ * it.  Returns NUASM_ERR_UNSUPPORTED, enqueuing nothing, if the bound points
+ * may need more tiles than the array holds (the exact need is known when
+ * set_points synchronised; with NUASM_DEFER_RANGE_CHECK a bound of
+ * 8 M / spread_chunk tiles is used), and the errors of nuasm_execute. */
+nuasm_status nuasm_execute_noalloc(nuasm_plan plan, const void* in_dev, void* out_dev);
+
 /* Apply the adjoint (conjugate transpose) of the plan's operator, derived
  * from Eqs. 6 and 9 by reversing every step and conjugating H.  Type 1:
  * in_dev = v[N'][N'], out_dev = w[M].  Type 2: in_dev = w[M], out_dev =

@@ -92,6 +92,7 @@ _SIGS = {
     "nuasm_batch_set_branches": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "nuasm_execute": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "nuasm_execute_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "nuasm_execute_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "nuasm_debug_transfer": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "nuasm_plan_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "nuasm_plan_read_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),

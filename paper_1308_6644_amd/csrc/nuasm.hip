@@ -231,6 +231,9 @@ struct nuasm_plan_s {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   int64_t ws_cap = 0;        // points per set the workspace holds
+  // set only during nuasm_execute_noalloc: the device's static partial-tile
+  // array replaces the point sets' own scratch
+  float2* scratch_override = nullptr;
   // stage timing
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -747,9 +750,12 @@ nuasm_status run_spread(nuasm_plan_s* pl, PointSet& q, const float2* vals) {
     HIP_TRY(launch_grid_spread(pl->w, vals, q.gbuf, pl->gridA, q.gp, st), "launch grid_spread");
     return NUASM_OK;
   }
-  nuasm_status s = ensure_scratch(pl, q);
-  if (s != NUASM_OK) return s;
-  float2* scratch = q.scratch;
+  float2* scratch = pl->scratch_override;
+  if (!scratch) {
+    nuasm_status s = ensure_scratch(pl, q);
+    if (s != NUASM_OK) return s;
+    scratch = q.scratch;
+  }
   {
     StageScope sc(pl, NUASM_STAGE_SPREAD);
     SpreadArgs sa{};
@@ -1286,6 +1292,74 @@ nuasm_status nuasm_execute_adjoint(nuasm_plan pl, const void* in, void* out) {
     return run_type2_pipeline(pl, q, (const float2*)in, pl->geom.Np, (float2*)out, true);
   }
   return run_type1_pipeline(pl, q, (const float2*)in, (float2*)out, true, true);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------ allocation-free execute
+// Partial tiles of split bins for nuasm_execute_noalloc: one array per device
+// in the library's code object, kStaticTiles tiles of 32 x 32 complex64
+// (16 MiB), held until the process ends.  Host code never passes `scratch`
+// itself to a kernel (on the host it is only a stand-in for the symbol): the
+// device address comes from hipGetSymbolAddress, once per device.
+constexpr int64_t kStaticTiles = 2048;
+static __device__ __align__(256) float2 scratch[kStaticTiles * kTile * kTile];
+
+namespace {
+std::mutex g_static_mutex;
+float2* g_static_ptr[64] = {nullptr};
+
+// Device address of `scratch` on device `dev` (taken once, with that device
+// current; the caller's current device is restored).
+nuasm_status static_scratch_for_device(int dev, float2** out) {
+  std::lock_guard<std::mutex> lk(g_static_mutex);
+  if (dev < 0 || dev >= 64) return fail(NUASM_ERR_UNSUPPORTED, "device ordinal >= 64");
+  if (!g_static_ptr[dev]) {
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur), "hipGetDevice");
+    if (cur != dev) HIP_TRY(hipSetDevice(dev), "hipSetDevice");
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return fail(NUASM_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_static_ptr[dev] = (float2*)ptr;
+  }
+  *out = g_static_ptr[dev];
+  return NUASM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+nuasm_status nuasm_execute_noalloc(nuasm_plan pl, const void* in, void* out) {
+  if (!pl) return fail(NUASM_ERR_INVALID_ARG, "plan is NULL");
+  if (!pl->ready()) return fail(NUASM_ERR_NOT_READY, not_ready_msg(pl));
+  // the point set that is spread: the plan's points (type 1, and type 3's
+  // sources); type 2 spreads nothing
+  const PointSet& q = pl->ps[0];
+  if (pl->p.type != NUASM_TYPE_2 && !q.grid) {
+    const int64_t need = scratch_tiles_needed(pl, q);
+    if (need > kStaticTiles) {
+      char buf[256];
+      std::snprintf(buf, sizeof(buf),
+                    "split bins may need %lld partial tiles, above the static scratch's %lld (bind the points "
+                    "without NUASM_DEFER_RANGE_CHECK so that the exact count is known, or use nuasm_execute)",
+                    (long long)need, (long long)kStaticTiles);
+      return fail(NUASM_ERR_UNSUPPORTED, buf);
+    }
+  }
+  float2* ptr = nullptr;
+  nuasm_status s = static_scratch_for_device(pl->device, &ptr);
+  if (s != NUASM_OK) return s;
+  // no stage events either (creating one may allocate)
+  const bool timing = pl->timing;
+  pl->timing = false;
+  pl->scratch_override = ptr;
+  s = nuasm_execute(pl, in, out);
+  pl->scratch_override = nullptr;
+  pl->timing = timing;
+  return s;
 }
 
 nuasm_status nuasm_plan_set_timing(nuasm_plan pl, int32_t enable) {
