@@ -32,10 +32,43 @@ ZS = (0.01, 0.1, 0.5)
 TFS = (("asm", "limited"), ("fresnel", "full"))
 M = 1 << 20
 
-# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes over this
-# workload (scaled by a plain-copy calibration), for kernels whose code has not
-# changed since the counters were taken; see profiles/bench_N2048_M1M_kernels.md.
-COUNTER_TRAFFIC = {"spread": (138.5 + 31.5) * 1e6}
+# Per-launch hardware counters of the kernels (rocprofv3 FETCH_SIZE / WRITE_SIZE
+# passes scaled by a plain-copy calibration, SQ_INSTS_VALU / SQ_INSTS_MFMA)
+# with the SHA-256 of the sources each kernel is built from when they were
+# taken; a kernel whose sources have changed since gets no counter figures.
+COUNTERS = os.path.join(ROOT, "profiles", "counters.json")
+CSRC = os.path.join(ROOT, "paper_1308_6644_amd", "csrc")
+POINT_STAGES = ("bin_hist", "bin_colscan", "bin_scatter", "spread", "spread_reduce", "interp")
+SHARED_SOURCES = ("device_common.h", "launch.h", "group.h")
+# VALU issue: one wave64 instruction per SIMD every 4 cycles, 256 CUs x 4 SIMDs at 2.4 GHz
+SIMDS, CLOCK_HZ, VALU_CYCLES = 1024, 2.4e9, 4
+
+
+def kernel_sources(stage: str):
+    main = "k_points.hip" if stage in POINT_STAGES else "k_fft.hip"
+    return (main,) + SHARED_SOURCES
+
+
+def sources_sha256(stage: str) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in kernel_sources(stage):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def counter_record(stage: str):
+    """Committed counters of a stage's kernel, or None when absent or taken on
+    other sources."""
+    try:
+        with open(COUNTERS) as f:
+            rec = json.load(f)["kernels"].get(stage)
+    except (OSError, ValueError, KeyError):
+        return None
+    if not rec or rec.get("sources_sha256") != sources_sha256(stage):
+        return None
+    return rec
 
 
 def stage_bytes(stage: str, info: dict) -> float:
@@ -224,7 +257,16 @@ def stage_pass(runs, seq_step, steps, torch, bytes_fn=None):
 
 
 def roofline(stages, steps):
-    """Roofline object of the dominant kernel and the per-stage report."""
+    """Roofline object of the dominant kernel and the per-stage report.
+
+    achieved / frac: the kernel's algorithmic bytes per launch over its
+    measured average launch time against 8 TB/s of HBM.  With committed
+    counters taken on the current sources it also gets the counter-measured
+    HBM traffic per launch and its VALU issue fraction (SQ_INSTS_VALU x 4
+    cycles over 1024 SIMDs x 2.4 GHz x the launch time); `bound` names the
+    resource the counters show closest to its peak ("hbm" by counter traffic,
+    or "alu" by VALU issue, in which case achieved / peak / frac are VALU lane
+    instructions per second against 256 CUs x 64 lanes x 2.4 GHz)."""
     dom = max(stages, key=lambda k: stages[k]["ms"])
     ds = stages[dom]
     avg_ms = ds["ms"] / ds["launches"]
@@ -234,8 +276,23 @@ def roofline(stages, steps):
                   "share": v["ms"] / total, "GBps": v["bytes"] / max(v["ms"] * 1e-3, 1e-12) / 1e9}
               for k, v in sorted(stages.items(), key=lambda kv: -kv[1]["ms"])}
     roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": COUNTER_TRAFFIC.get(dom),
-            "avg_launch_us": avg_ms * 1e3}
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "avg_launch_us": avg_ms * 1e3,
+            "hbm_algorithmic_frac": achieved / HBM_PEAK_GBS}
+    rec = counter_record(dom)
+    t_launch = avg_ms * 1e-3
+    if rec is not None:
+        traffic = float(rec["fetch_bytes"]) + float(rec["write_bytes"])
+        roof["traffic"] = traffic
+        roof["hbm_counter_frac"] = traffic / t_launch / (HBM_PEAK_GBS * 1e9)
+        valu = float(rec.get("valu_insts", 0.0))
+        roof["valu_issue_frac"] = valu * VALU_CYCLES / (SIMDS * CLOCK_HZ * t_launch)
+        if rec.get("mfma_insts") is not None:
+            roof["mfma_insts_per_launch"] = float(rec["mfma_insts"])
+        roof["counters"] = {"source": "profiles/counters.json", "sources_sha256": rec["sources_sha256"]}
+        if roof["valu_issue_frac"] > max(roof["hbm_counter_frac"], roof["hbm_algorithmic_frac"]):
+            lanes = SIMDS * 16 * CLOCK_HZ / 1e9  # G lane-instructions/s
+            roof.update({"bound": "alu", "achieved": valu * 64 / t_launch / 1e9, "peak": lanes,
+                         "unit": "Glane-inst/s", "frac": roof["valu_issue_frac"]})
     return roof, report
 
 

@@ -113,7 +113,7 @@ typedef struct {
   int64_t L;                  /* side of the stored fine-grid support, N'' + 16 */
   int32_t w;                  /* spreading-kernel width in fine cells */
   float beta;                 /* exponential-of-semicircle shape parameter */
-  int32_t tile;               /* fine cells per bin side */
+  int32_t tile;               /* fine cells per bin side (nuasm_tuning.bin_tile) */
   int32_t tiles;              /* number of bins */
   int32_t kx_lo, kx_hi;       /* inclusive band of Eq. 4 in index units */
   int32_t ky_lo, ky_hi;
@@ -146,6 +146,12 @@ typedef struct {
                                  bin as sums of outer products on v_mfma_f32 units).
                                  Both are float32 and reproducible in
                                  deterministic mode */
+  int32_t bin_tile;           /* bin side in fine cells: 0 = 32, else 32 or 64
+                                 (64: fewer records per point -- a point is
+                                 recorded in every bin its w x w taps touch --
+                                 and 16 times fewer bins, but larger spreading
+                                 and interpolation workgroups; matrix-core
+                                 spreading only) */
 } nuasm_tuning;
 
 typedef struct nuasm_plan_s* nuasm_plan;
@@ -356,7 +362,8 @@ nuasm_status nuasm_plan_read_timing(nuasm_plan plan, double* ms, int64_t* launch
 /* ------------------------------------------------------------ batches
  * Many independent planes (each its own N, type, transfer function, z, point
  * count) run as one HIP graph: the binning and the operator of every plane
- * are captured once, on parallel branches, and replayed by each run.  For
+ * are captured once as grouped stage launches (see nuasm_batch_set_grouped)
+ * and replayed by each run.  For
  * callers that propagate many planes per step (a batch of holograms, a
  * focal stack).  Plans inside a batch always defer their range checks.
  * Type-3 planes are not batched (nuasm_batch_create returns
@@ -387,11 +394,21 @@ nuasm_status nuasm_execute_many(nuasm_batch batch, const void* const* in, void* 
 /* Same as nuasm_batch_create. */
 nuasm_status nuasm_plan_many_create(int32_t P, const nuasm_params* params, void* hip_stream, nuasm_batch* out);
 /* Tuning of one plane of a batch (as nuasm_plan_set_tuning) and the number
- * of parallel graph branches (1 .. min(4, P); default the maximum), e.g. from
- * an autotuner.  Either drops the recorded graph; the next run records it
- * again. */
+ * of parallel graph branches of the per-plane form (1 .. min(4, P); default
+ * the maximum), e.g. from an autotuner.  Either drops the recorded graphs; the
+ * next run records them again. */
 nuasm_status nuasm_batch_set_tuning(nuasm_batch batch, int32_t plane, const nuasm_tuning* t);
 nuasm_status nuasm_batch_set_branches(nuasm_batch batch, int32_t branches);
+/* How a batch's graphs are recorded.  grouped = 1 (default): grouped stage
+ * launches -- every stage (binning histogram, column scan, scatter, spreading,
+ * split-bin reduction, the row and column passes, interpolation) is one
+ * launch per kernel instantiation covering every plane that has it, each
+ * workgroup finding its plane's arguments in a per-stage descriptor table;
+ * binning and the type-1 operator run on one graph branch, the type-2 grid
+ * passes on another, joined after binning for the interpolation.  grouped = 0:
+ * every plane's own launch sequence on one of `branches` parallel branches.
+ * Drops the recorded graphs. */
+nuasm_status nuasm_batch_set_grouped(nuasm_batch batch, int32_t grouped);
 /* Synchronise; *bad_plane = index of the first plane with out-of-range
  * points in the last run, or -1. */
 nuasm_status nuasm_batch_check_points(nuasm_batch batch, int32_t* bad_plane);

@@ -70,7 +70,8 @@ class PlanInfo(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("spread_chunk", ctypes.c_int32), ("interp_chunk", ctypes.c_int32),
-                ("bin_range_points", ctypes.c_int32), ("spread_method", ctypes.c_int32)]
+                ("bin_range_points", ctypes.c_int32), ("spread_method", ctypes.c_int32),
+                ("bin_tile", ctypes.c_int32)]
 
 
 _SIGS = {
@@ -90,6 +91,7 @@ _SIGS = {
     "nuasm_plan_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
     "nuasm_batch_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Tuning)]),
     "nuasm_batch_set_branches": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "nuasm_batch_set_grouped": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "nuasm_execute": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "nuasm_execute_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "nuasm_execute_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -345,10 +347,11 @@ class Plan:
         return self
 
     def set_tuning(self, spread_chunk: int = 0, interp_chunk: int = 0, bin_range_points: int = 0,
-                   spread_method: int = 0):
+                   spread_method: int = 0, bin_tile: int = 0):
         """Launch-shape tuning (0 = default); binned points must be set again.
-        spread_method: 0 automatic, 1 register gather, 2 matrix cores."""
-        t = Tuning(int(spread_chunk), int(interp_chunk), int(bin_range_points), int(spread_method))
+        spread_method: 0 automatic, 1 register gather, 2 matrix cores;
+        bin_tile: 0 (32) or the bin side, 32 or 64."""
+        t = Tuning(int(spread_chunk), int(interp_chunk), int(bin_range_points), int(spread_method), int(bin_tile))
         _check(load().nuasm_plan_set_tuning(self._h, ctypes.byref(t)))
         return self
 
@@ -476,12 +479,17 @@ class Batch:
         return outs
 
     def set_tuning(self, plane: int, spread_chunk: int = 0, interp_chunk: int = 0, bin_range_points: int = 0,
-                   spread_method: int = 0):
-        t = Tuning(int(spread_chunk), int(interp_chunk), int(bin_range_points), int(spread_method))
+                   spread_method: int = 0, bin_tile: int = 0):
+        t = Tuning(int(spread_chunk), int(interp_chunk), int(bin_range_points), int(spread_method), int(bin_tile))
         _check(load().nuasm_batch_set_tuning(self._h, int(plane), ctypes.byref(t)))
 
     def set_branches(self, branches: int):
         _check(load().nuasm_batch_set_branches(self._h, int(branches)))
+
+    def set_grouped(self, grouped: bool):
+        """Grouped stage launches (default) or every plane's own launches on
+        parallel branches."""
+        _check(load().nuasm_batch_set_grouped(self._h, 1 if grouped else 0))
 
     def check_points(self) -> int:
         bad = ctypes.c_int32(-1)

@@ -11,6 +11,7 @@
 // [N''/2, 3N''/2), and only the support rows/columns [s0, s0 + L),
 // L = N'' + 16, are ever stored.  Row passes over the fine grid are
 // instantiated at N''; the column passes go between N'' and N'.
+#include "group.h"
 #include "launch.h"
 
 namespace nuasm {
@@ -92,16 +93,18 @@ __device__ __forceinline__ float2 transfer_at(const Spectral& sp, int Np, int kx
 // Fine support rows -> nf-point FFT along x -> keep k_x in K, times 1/psihat.
 // T[i][a] = sum_l G[i][l] exp(-2 pi i k_x (s0 + l) / nf) / psihat(k_x).
 template <int LOGNP>
-__global__ void __launch_bounds__(RowCfg<LOGNP + 1>::NT)
-k_t1_rows(const float2* __restrict__ fine, float2* __restrict__ T, GridGeom g,
-          const float* __restrict__ dinv, const float2* __restrict__ twall) {
+__device__ __forceinline__ void t1_rows_body(const RowArgs& a, int bid, int) {
+  const float2* __restrict__ fine = a.in;
+  float2* __restrict__ T = a.out;
+  const GridGeom& g = a.g;
+  const float* __restrict__ dinv = a.dinv;
   constexpr int LOGN = LOGNP + 1, NF = 1 << LOGN, NP = 1 << LOGNP;
   using Cfg = RowCfg<LOGN>;
   constexpr int C = Cfg::C, NT = Cfg::NT;
   extern __shared__ float2 s[];
   float2* tw = s + Cfg::DATA;
-  load_tw2<LOGN, NT>(tw, tw_for(twall, LOGN));
-  const int r0 = blockIdx.x * C;
+  load_tw2<LOGN, NT>(tw, tw_for(a.tw, LOGN));
+  const int r0 = bid * C;
   const int L = g.L, s0 = g.s0;
   for (int e = threadIdx.x; e < C * NF; e += NT) {
     const int c = e / NF, t = e % NF;
@@ -143,14 +146,17 @@ struct Col2Cfg {
 // fine grid and of the centred inverse DFT cancel (N'/2 is even); the
 // remaining output sign (-1)^n_y is applied here.
 template <int LOGNPF, int LOGNP>
-__global__ void __launch_bounds__((Col2Cfg<LOGNPF + 1, LOGNP>::NT))
-k_t1_cols(const float2* __restrict__ T, float2* __restrict__ V, GridGeom g, Spectral sp,
-          const float2* __restrict__ twall) {
+__device__ __forceinline__ void t1_cols_body(const ColArgs& a, int bid, int nbid) {
+  const float2* __restrict__ T = a.in;
+  float2* __restrict__ V = a.out;
+  const GridGeom& g = a.g;
+  const Spectral& sp = a.sp;
+  const float2* __restrict__ twall = a.tw;
   constexpr int LOGN = LOGNPF + 1, NF = 1 << LOGN, NPF = 1 << LOGNPF, NP = 1 << LOGNP;
   using Cfg = Col2Cfg<LOGN, LOGNP>;
   constexpr int C = Cfg::C, NT = Cfg::NT;
   extern __shared__ float2 s[];
-  const int strip = xcd_remap(blockIdx.x, gridDim.x);
+  const int strip = xcd_remap(bid, nbid);
   const int a0 = strip * C;
   const int kx0 = a0 - NPF / 2;
   if (kx0 + C - 1 < g.kxlo || kx0 > g.kxhi) return;  // whole strip outside the band
@@ -207,18 +213,19 @@ k_t1_cols(const float2* __restrict__ T, float2* __restrict__ V, GridGeom g, Spec
 // Rows of V -> N'-point inverse FFT along x -> times (-1)^n_x -> plane
 // (N' x N', or the central N x N when cropping).
 template <int LOGNP>
-__global__ void __launch_bounds__(RowCfg<LOGNP>::NT)
-k_t1_rows_inv(const float2* __restrict__ V, float2* __restrict__ out, GridGeom g,
-              const float2* __restrict__ twall) {
+__device__ __forceinline__ void t1_rows_inv_body(const RowArgs& a, int bid, int) {
+  const float2* __restrict__ V = a.in;
+  float2* __restrict__ out = a.out;
+  const GridGeom& g = a.g;
   constexpr int NP = 1 << LOGNP;
   using Cfg = RowCfg<LOGNP>;
   constexpr int C = Cfg::C, NT = Cfg::NT;
   extern __shared__ float2 s[];
   float2* tw = s + Cfg::DATA;
-  load_tw2<LOGNP, NT>(tw, tw_for(twall, LOGNP));
+  load_tw2<LOGNP, NT>(tw, tw_for(a.tw, LOGNP));
   const int nrows = g.crop ? g.N : NP;
   const int rowoff = g.crop ? g.N / 2 : 0;
-  const int r0 = blockIdx.x * C;
+  const int r0 = bid * C;
   for (int e = threadIdx.x; e < C * NP; e += NT) {
     const int c = e / NP, a = e % NP;
     const int r = r0 + c, kx = a - NP / 2;
@@ -247,17 +254,19 @@ k_t1_rows_inv(const float2* __restrict__ V, float2* __restrict__ out, GridGeom g
 // Rows of the Nin x Nin plane, zero-padded circularly to N' -> FFT along x ->
 // times (-1)^k_x / psihat(k_x), centred output T[row][k_x + N'/2].
 template <int LOGNP>
-__global__ void __launch_bounds__(RowCfg<LOGNP>::NT)
-k_t2_rows(const float2* __restrict__ u1, float2* __restrict__ T, GridGeom g,
-          const float* __restrict__ dinv, const float2* __restrict__ twall) {
+__device__ __forceinline__ void t2_rows_body(const RowArgs& a, int bid, int) {
+  const float2* __restrict__ u1 = a.in;
+  float2* __restrict__ T = a.out;
+  const GridGeom& g = a.g;
+  const float* __restrict__ dinv = a.dinv;
   constexpr int NP = 1 << LOGNP;
   using Cfg = RowCfg<LOGNP>;
   constexpr int C = Cfg::C, NT = Cfg::NT;
   extern __shared__ float2 s[];
   float2* tw = s + Cfg::DATA;
-  load_tw2<LOGNP, NT>(tw, tw_for(twall, LOGNP));
+  load_tw2<LOGNP, NT>(tw, tw_for(a.tw, LOGNP));
   const int Nin = g.Nin;
-  const int r0 = blockIdx.x * C;
+  const int r0 = bid * C;
   for (int e = threadIdx.x; e < C * NP; e += NT) {
     const int c = e / NP, t = e % NP;
     const int r = r0 + c;
@@ -285,14 +294,17 @@ k_t2_rows(const float2* __restrict__ u1, float2* __restrict__ T, GridGeom g,
 // nf-point spectrum (nf = 2 N'', the gap zero) -> inverse nf-point FFT along
 // y -> the support rows [s0, s0 + L), written with N'' columns k_x + N''/2.
 template <int LOGNPF, int LOGNP>
-__global__ void __launch_bounds__((Col2Cfg<LOGNP, LOGNPF + 1>::NT))
-k_t2_cols(const float2* __restrict__ T, float2* __restrict__ V, GridGeom g, Spectral sp,
-          const float2* __restrict__ twall) {
+__device__ __forceinline__ void t2_cols_body(const ColArgs& a, int bid, int nbid) {
+  const float2* __restrict__ T = a.in;
+  float2* __restrict__ V = a.out;
+  const GridGeom& g = a.g;
+  const Spectral& sp = a.sp;
+  const float2* __restrict__ twall = a.tw;
   constexpr int LOGN = LOGNPF + 1, NF = 1 << LOGN, NPF = 1 << LOGNPF, NP = 1 << LOGNP;
   using Cfg = Col2Cfg<LOGNP, LOGN>;
   constexpr int C = Cfg::C, NT = Cfg::NT;
   extern __shared__ float2 s[];
-  const int strip = xcd_remap(blockIdx.x, gridDim.x);
+  const int strip = xcd_remap(bid, nbid);
   const int a0 = strip * C;
   const int kx0 = a0 - NP / 2;
   if (kx0 + C - 1 < g.kxlo || kx0 > g.kxhi) return;
@@ -357,17 +369,18 @@ k_t2_cols(const float2* __restrict__ T, float2* __restrict__ V, GridGeom g, Spec
 // Support rows of V -> embed k_x into nf -> inverse nf-point FFT along x ->
 // keep support columns: the fine grid the interpolation reads.
 template <int LOGNP>
-__global__ void __launch_bounds__(RowCfg<LOGNP + 1>::NT)
-k_t2_rows_inv(const float2* __restrict__ V, float2* __restrict__ fine, GridGeom g,
-              const float2* __restrict__ twall) {
+__device__ __forceinline__ void t2_rows_inv_body(const RowArgs& a, int bid, int) {
+  const float2* __restrict__ V = a.in;
+  float2* __restrict__ fine = a.out;
+  const GridGeom& g = a.g;
   constexpr int LOGN = LOGNP + 1, NF = 1 << LOGN, NP = 1 << LOGNP;
   using Cfg = RowCfg<LOGN>;
   constexpr int C = Cfg::C, NT = Cfg::NT;
   extern __shared__ float2 s[];
   float2* tw = s + Cfg::DATA;
-  load_tw2<LOGN, NT>(tw, tw_for(twall, LOGN));
+  load_tw2<LOGN, NT>(tw, tw_for(a.tw, LOGN));
   const int L = g.L, s0 = g.s0;
-  const int r0 = blockIdx.x * C;
+  const int r0 = bid * C;
   for (int e = threadIdx.x; e < C * NF; e += NT) {
     const int c = e / NF, t = e % NF;
     const int r = r0 + c;
@@ -555,17 +568,16 @@ static hipError_t set_lds(K kernel, int bytes) {
 
 hipError_t launch_t1_rows(int logNp, const float2* fine, float2* T, GridGeom g, const float* dinv,
                           const float2* tw, hipStream_t st) {
-#define CALL(LP)                                                                         \
-  {                                                                                      \
-    using Cfg = RowCfg<LP + 1>;                                                          \
-    hipError_t e = set_lds(k_t1_rows<LP>, Cfg::LDS);                                     \
-    if (e != hipSuccess) return e;                                                       \
-    const int grid = (g.L + Cfg::C - 1) / Cfg::C;                                        \
-    hipLaunchKernelGGL(k_t1_rows<LP>, dim3(grid), dim3(Cfg::NT), Cfg::LDS, st, fine, T, g, dinv, tw); \
+  const RowArgs a{fine, T, g, dinv, tw};
+#define CALL(LP)                                                                              \
+  {                                                                                           \
+    using Cfg = RowCfg<LP + 1>;                                                               \
+    return launch_or_record<RowArgs, t1_rows_body<LP>, Cfg::NT>(a, (g.L + Cfg::C - 1) / Cfg::C, \
+                                                                Cfg::LDS, st);                \
   }
   NUASM_DISPATCH_NP(logNp, CALL)
 #undef CALL
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 // Column passes: the spectral grid N'' = 2^logNpf may be N', N'/2, N'/4 or
@@ -574,22 +586,16 @@ template <int LPF, int LP>
 static hipError_t t1_cols_at(const float2* T, float2* V, const GridGeom& g, const Spectral& sp, const float2* tw,
                              hipStream_t st) {
   using Cfg = Col2Cfg<LPF + 1, LP>;
-  hipError_t e = set_lds(k_t1_cols<LPF, LP>, Cfg::LDS);
-  if (e != hipSuccess) return e;
-  const int grid = (1 << LPF) / Cfg::C;
-  hipLaunchKernelGGL((k_t1_cols<LPF, LP>), dim3(grid), dim3(Cfg::NT), Cfg::LDS, st, T, V, g, sp, tw);
-  return hipGetLastError();
+  return launch_or_record<ColArgs, t1_cols_body<LPF, LP>, Cfg::NT>(ColArgs{T, V, g, sp, tw}, (1 << LPF) / Cfg::C,
+                                                                   Cfg::LDS, st);
 }
 
 template <int LPF, int LP>
 static hipError_t t2_cols_at(const float2* T, float2* V, const GridGeom& g, const Spectral& sp, const float2* tw,
                              hipStream_t st) {
   using Cfg = Col2Cfg<LP, LPF + 1>;
-  hipError_t e = set_lds(k_t2_cols<LPF, LP>, Cfg::LDS);
-  if (e != hipSuccess) return e;
-  const int grid = (1 << LP) / Cfg::C;
-  hipLaunchKernelGGL((k_t2_cols<LPF, LP>), dim3(grid), dim3(Cfg::NT), Cfg::LDS, st, T, V, g, sp, tw);
-  return hipGetLastError();
+  return launch_or_record<ColArgs, t2_cols_body<LPF, LP>, Cfg::NT>(ColArgs{T, V, g, sp, tw}, (1 << LP) / Cfg::C,
+                                                                   Cfg::LDS, st);
 }
 
 template <int LP, bool T1>
@@ -620,33 +626,31 @@ hipError_t launch_t1_cols(int logNpf, int logNp, const float2* T, float2* V, Gri
 
 hipError_t launch_t1_rows_inv(int logNp, const float2* V, float2* out, GridGeom g, const float2* tw,
                               hipStream_t st) {
-#define CALL(LP)                                                                         \
-  {                                                                                      \
-    using Cfg = RowCfg<LP>;                                                              \
-    hipError_t e = set_lds(k_t1_rows_inv<LP>, Cfg::LDS);                                 \
-    if (e != hipSuccess) return e;                                                       \
-    const int nrows = g.crop ? g.N : (1 << LP);                                          \
-    const int grid = (nrows + Cfg::C - 1) / Cfg::C;                                      \
-    hipLaunchKernelGGL(k_t1_rows_inv<LP>, dim3(grid), dim3(Cfg::NT), Cfg::LDS, st, V, out, g, tw); \
+  const RowArgs a{V, out, g, nullptr, tw};
+#define CALL(LP)                                                                                      \
+  {                                                                                                   \
+    using Cfg = RowCfg<LP>;                                                                           \
+    const int nrows = g.crop ? g.N : (1 << LP);                                                       \
+    return launch_or_record<RowArgs, t1_rows_inv_body<LP>, Cfg::NT>(a, (nrows + Cfg::C - 1) / Cfg::C, \
+                                                                    Cfg::LDS, st);                    \
   }
   NUASM_DISPATCH_NP(logNp, CALL)
 #undef CALL
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_t2_rows(int logNp, const float2* u1, float2* T, GridGeom g, const float* dinv,
                           const float2* tw, hipStream_t st) {
-#define CALL(LP)                                                                         \
-  {                                                                                      \
-    using Cfg = RowCfg<LP>;                                                              \
-    hipError_t e = set_lds(k_t2_rows<LP>, Cfg::LDS);                                     \
-    if (e != hipSuccess) return e;                                                       \
-    const int grid = (g.Nin + Cfg::C - 1) / Cfg::C;                                      \
-    hipLaunchKernelGGL(k_t2_rows<LP>, dim3(grid), dim3(Cfg::NT), Cfg::LDS, st, u1, T, g, dinv, tw); \
+  const RowArgs a{u1, T, g, dinv, tw};
+#define CALL(LP)                                                                                \
+  {                                                                                             \
+    using Cfg = RowCfg<LP>;                                                                     \
+    return launch_or_record<RowArgs, t2_rows_body<LP>, Cfg::NT>(a, (g.Nin + Cfg::C - 1) / Cfg::C, \
+                                                                Cfg::LDS, st);                  \
   }
   NUASM_DISPATCH_NP(logNp, CALL)
 #undef CALL
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_t2_cols(int logNpf, int logNp, const float2* T, float2* V, GridGeom g, Spectral sp,
@@ -660,17 +664,16 @@ hipError_t launch_t2_cols(int logNpf, int logNp, const float2* T, float2* V, Gri
 
 hipError_t launch_t2_rows_inv(int logNp, const float2* V, float2* fine, GridGeom g, const float2* tw,
                               hipStream_t st) {
-#define CALL(LP)                                                                         \
-  {                                                                                      \
-    using Cfg = RowCfg<LP + 1>;                                                          \
-    hipError_t e = set_lds(k_t2_rows_inv<LP>, Cfg::LDS);                                 \
-    if (e != hipSuccess) return e;                                                       \
-    const int grid = (g.L + Cfg::C - 1) / Cfg::C;                                        \
-    hipLaunchKernelGGL(k_t2_rows_inv<LP>, dim3(grid), dim3(Cfg::NT), Cfg::LDS, st, V, fine, g, tw); \
+  const RowArgs a{V, fine, g, nullptr, tw};
+#define CALL(LP)                                                                                   \
+  {                                                                                                \
+    using Cfg = RowCfg<LP + 1>;                                                                    \
+    return launch_or_record<RowArgs, t2_rows_inv_body<LP>, Cfg::NT>(a, (g.L + Cfg::C - 1) / Cfg::C, \
+                                                                    Cfg::LDS, st);                 \
   }
   NUASM_DISPATCH_NP(logNp, CALL)
 #undef CALL
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_t3_cols(int logNp, const float2* T, float2* V, GridGeom g, Spectral sp,

@@ -10,6 +10,7 @@
 // Its w taps are the cells i0 .. i0 + w - 1, i0 = ceil(tau - w/2).  The
 // support is cut into 32 x 32 bins; a point is recorded in every bin its taps
 // touch (at most 4), flagged "primary" in the bin holding its first tap.
+#include "group.h"
 #include "launch.h"
 
 namespace nuasm {
@@ -66,14 +67,18 @@ __device__ __forceinline__ unsigned lds_bump16(unsigned* sh, int b) {
 
 // Histogram rows have T + 1 entries: entry T counts the range's points that
 // are outside the window (they get no record).
-__global__ void __launch_bounds__(kBinThreads)
-k_bin_hist(const double* __restrict__ x, const double* __restrict__ y, int64_t M, BinGeom g, int ppw,
-           uint16_t* __restrict__ hist) {
+__device__ __forceinline__ void bin_hist_body(const BinArgs& a, int bid, int) {
+  const double* __restrict__ x = a.x;
+  const double* __restrict__ y = a.y;
+  const int64_t M = a.M;
+  const BinGeom& g = a.g;
+  const int ppw = a.ppw;
+  uint16_t* __restrict__ hist = a.hist;
   extern __shared__ unsigned sh[];
   const int T = g.TX * g.TX, TW = (T + 2) / 2;
   for (int e = threadIdx.x; e < TW; e += kBinThreads) sh[e] = 0u;
   __syncthreads();
-  const int64_t j0 = (int64_t)blockIdx.x * ppw;
+  const int64_t j0 = (int64_t)bid * ppw;
   const int64_t j1 = min(M, j0 + ppw);
   for (int64_t jb = j0; jb < j1; jb += kBinThreads * kBinBatch) {
     double xv[kBinBatch], yv[kBinBatch];  // all loads of a batch in flight together
@@ -92,14 +97,14 @@ k_bin_hist(const double* __restrict__ x, const double* __restrict__ y, int64_t M
         lds_bump16(sh, T);
         continue;
       }
-      const int bx0 = pc.i0x / kTile, bx1 = (pc.i0x + g.w - 1) / kTile;
-      const int by0 = pc.i0y / kTile, by1 = (pc.i0y + g.w - 1) / kTile;
+      const int bx0 = pc.i0x >> g.tile_log, bx1 = (pc.i0x + g.w - 1) >> g.tile_log;
+      const int by0 = pc.i0y >> g.tile_log, by1 = (pc.i0y + g.w - 1) >> g.tile_log;
       for (int by = by0; by <= by1; ++by)
         for (int bx = bx0; bx <= bx1; ++bx) lds_bump16(sh, by * g.TX + bx);
     }
   }
   __syncthreads();
-  uint16_t* row = hist + (size_t)blockIdx.x * (T + 1);
+  uint16_t* row = hist + (size_t)bid * (T + 1);
   for (int b = threadIdx.x; b <= T; b += kBinThreads) row[b] = (uint16_t)((sh[b >> 1] >> ((b & 1) * 16)) & 0xffffu);
 }
 
@@ -154,15 +159,18 @@ __device__ __forceinline__ int wave_incl_scan(int v, int lane) {
 
 __device__ __forceinline__ int spread_chunks(int c, int spc) { return c > spc ? (c + spc - 1) / spc : 1; }
 
-__global__ void __launch_bounds__(kColThreads)
-k_bin_colscan(const uint16_t* __restrict__ hist, int G, int T, int* __restrict__ off, int* total,
-              BinScanOut so, int* __restrict__ done) {
-  // T: bins; rows of hist and off have T + 1 entries
+__device__ __forceinline__ void bin_colscan_body(const ColscanArgs& a, int bid, int nbid) {
+  const uint16_t* __restrict__ hist = a.hist;
+  const int G = a.G, T = a.T;  // T: bins; rows of hist and off have T + 1 entries
+  int* __restrict__ off = a.off;
+  int* total = a.total;
+  const BinScanOut& so = a.so;
+  int* __restrict__ done = a.done;
   const int R = T + 1;
   __shared__ int part[kColWaves][64];
   __shared__ int last;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int b = blockIdx.x * 64 + lane;
+  const int b = bid * 64 + lane;
   const int per = (G + kColWaves - 1) / kColWaves;
   const int g0 = min(G, wv * per), g1 = min(G, g0 + per);
   int s = 0;
@@ -229,7 +237,7 @@ k_bin_colscan(const uint16_t* __restrict__ hist, int G, int T, int* __restrict__
     for (int i = 0; i < kWgVals; ++i) {
       const int inc = wave_incl_scan(v[i], lane);
       pre[i] = inc - v[i];
-      if (lane == 63) so.wg_sum[(size_t)blockIdx.x * kBinPre + i] = inc;
+      if (lane == 63) so.wg_sum[(size_t)bid * kBinPre + i] = inc;
     }
     if (valid) {
       int* bp = so.bin_pre + (size_t)b * kBinPre;
@@ -248,7 +256,7 @@ k_bin_colscan(const uint16_t* __restrict__ hist, int G, int T, int* __restrict__
     // release this workgroup's stores, then count it
     __threadfence();
     if (lane == 0) {
-      const bool l = atomicAdd(done, 1) == (int)gridDim.x - 1;
+      const bool l = atomicAdd(done, 1) == nbid - 1;
       if (l) __threadfence();
       last = l;
     }
@@ -257,7 +265,7 @@ k_bin_colscan(const uint16_t* __restrict__ hist, int G, int T, int* __restrict__
   if (!last) return;
 
   // ---- the last workgroup: scan the workgroup sums, write every bin's entries
-  const int nwg = (int)gridDim.x;
+  const int nwg = nbid;
   extern __shared__ int wgpre[];  // [nwg][kWgVals] exclusive prefixes over the workgroups
   __shared__ int tot[kWgVals];
   __shared__ int cbase[2][kClasses];
@@ -348,19 +356,25 @@ k_bin_colscan(const uint16_t* __restrict__ hist, int G, int T, int* __restrict__
 // otherwise 16-bit LDS ranks are added to the two global tables per record
 // (for supports with too many bins to stage 32-bit cursors).
 template <bool CURSORS>
-__global__ void __launch_bounds__(kBinThreads)
-k_bin_scatter(const double* __restrict__ x, const double* __restrict__ y, int64_t M, BinGeom g, int ppw,
-              const int* __restrict__ off, const int* __restrict__ bin_base, BinRec* __restrict__ recs) {
+__device__ __forceinline__ void bin_scatter_body(const BinArgs& a, int bid, int) {
+  const double* __restrict__ x = a.x;
+  const double* __restrict__ y = a.y;
+  const int64_t M = a.M;
+  const BinGeom& g = a.g;
+  const int ppw = a.ppw;
+  const int* __restrict__ off = a.off;
+  const int* __restrict__ bin_base = a.bin_base;
+  BinRec* __restrict__ recs = a.recs;
   extern __shared__ unsigned sh[];
   const int T = g.TX * g.TX, TW = (T + 1) / 2;
-  const int* myoff = off + (size_t)blockIdx.x * (T + 1);
+  const int* myoff = off + (size_t)bid * (T + 1);
   if (CURSORS) {
     for (int b = threadIdx.x; b < T; b += kBinThreads) sh[b] = (unsigned)(bin_base[b] + myoff[b]);
   } else {
     for (int e = threadIdx.x; e < TW; e += kBinThreads) sh[e] = 0u;
   }
   __syncthreads();
-  const int64_t j0 = (int64_t)blockIdx.x * ppw;
+  const int64_t j0 = (int64_t)bid * ppw;
   const int64_t j1 = min(M, j0 + ppw);
   for (int64_t jb = j0; jb < j1; jb += kBinThreads * kBinBatch) {
     double xv[kBinBatch], yv[kBinBatch];
@@ -376,14 +390,14 @@ k_bin_scatter(const double* __restrict__ x, const double* __restrict__ y, int64_
       if (j >= j1) continue;
       const PointCells pc = point_cells(xv[q], yv[q], g);
       if (!pc.ok) continue;
-      const int bx0 = pc.i0x / kTile, bx1 = (pc.i0x + g.w - 1) / kTile;
-      const int by0 = pc.i0y / kTile, by1 = (pc.i0y + g.w - 1) / kTile;
+      const int bx0 = pc.i0x >> g.tile_log, bx1 = (pc.i0x + g.w - 1) >> g.tile_log;
+      const int by0 = pc.i0y >> g.tile_log, by1 = (pc.i0y + g.w - 1) >> g.tile_log;
       for (int by = by0; by <= by1; ++by)
         for (int bx = bx0; bx <= bx1; ++bx) {
           const int b = by * g.TX + bx;
           const int slot = CURSORS ? (int)atomicAdd(&sh[b], 1u)
                                    : bin_base[b] + myoff[b] + (int)lds_bump16(sh, b);
-          const int lx = pc.i0x - bx * kTile, ly = pc.i0y - by * kTile;
+          const int lx = pc.i0x - (bx << g.tile_log), ly = pc.i0y - (by << g.tile_log);
           BinRec r;
           r.packed = (lx & 0xff) | ((ly & 0xff) << 8) | ((bx == bx0 && by == by0) ? (1 << 16) : 0);
           r.dx = pc.dx;
@@ -427,22 +441,28 @@ __device__ __forceinline__ void bitonic_sort_u32(unsigned* k, int np) {
     }
 }
 
-__global__ void __launch_bounds__(kBinThreads)
-k_bin_scatter_det(const double* __restrict__ x, const double* __restrict__ y, int64_t M, BinGeom g, int ppw,
-                  const int* __restrict__ off, const int* __restrict__ bin_base, BinRec* __restrict__ recs) {
+__device__ __forceinline__ void bin_scatter_det_body(const BinArgs& a, int bid, int) {
+  const double* __restrict__ x = a.x;
+  const double* __restrict__ y = a.y;
+  const int64_t M = a.M;
+  const BinGeom& g = a.g;
+  const int ppw = a.ppw;
+  const int* __restrict__ off = a.off;
+  const int* __restrict__ bin_base = a.bin_base;
+  BinRec* __restrict__ recs = a.recs;
   constexpr int NW = kBinThreads / 64;
   __shared__ unsigned key[kDetRecs];
   __shared__ int slot_of[kDetRecs];  // by record id 4 p + k
   __shared__ int wsum[NW], wmax[NW];
   const int T = g.TX * g.TX;
-  const int* myoff = off + (size_t)blockIdx.x * (T + 1);
-  const int64_t j0 = (int64_t)blockIdx.x * ppw;
+  const int* myoff = off + (size_t)bid * (T + 1);
+  const int64_t j0 = (int64_t)bid * ppw;
   const int np = (int)(min(M, j0 + ppw) - j0);  // <= kDetPoints (checked by the launcher)
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   PointCells pc = point_cells(t < np ? x[j0 + t] : 0.0, t < np ? y[j0 + t] : 0.0, g);
   if (t >= np) pc.ok = false;
-  const int bx0 = pc.i0x / kTile, nbx = (pc.i0x + g.w - 1) / kTile - bx0 + 1;
-  const int by0 = pc.i0y / kTile, nby = (pc.i0y + g.w - 1) / kTile - by0 + 1;
+  const int bx0 = pc.i0x >> g.tile_log, nbx = ((pc.i0x + g.w - 1) >> g.tile_log) - bx0 + 1;
+  const int by0 = pc.i0y >> g.tile_log, nby = ((pc.i0y + g.w - 1) >> g.tile_log) - by0 + 1;
   const int nrec = pc.ok ? nbx * nby : 0;
   // compaction: exclusive block scan of the per-point record counts
   const int incl = wave_incl_scan(nrec, lane);
@@ -498,7 +518,7 @@ k_bin_scatter_det(const double* __restrict__ x, const double* __restrict__ y, in
     const int kx = k & 1, ky = k >> 1;
     if (!pc.ok || kx >= nbx || ky >= nby) continue;
     const int bx = bx0 + kx, by = by0 + ky;
-    const int lx = pc.i0x - bx * kTile, ly = pc.i0y - by * kTile;
+    const int lx = pc.i0x - (bx << g.tile_log), ly = pc.i0y - (by << g.tile_log);
     BinRec r;
     r.packed = (lx & 0xff) | ((ly & 0xff) << 8) | ((k == 0) ? (1 << 16) : 0);
     r.dx = pc.dx;
@@ -538,7 +558,7 @@ __device__ __forceinline__ int lds_bump16s(unsigned short* cnt, int k) {
 }
 
 template <int W, int NSUB>
-__global__ void __launch_bounds__(kSpreadThreads) k_spread(SpreadArgs a) {
+__device__ __forceinline__ void spread_body(const SpreadArgs& a, int bid, int) {
   // NSUB: sub-batches per chunk (the chunk tables hold at most NSUB * SB
   // records per chunk)
   using Cfg = SpreadCfg<W>;
@@ -549,7 +569,7 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(SpreadArgs a) {
   __shared__ float swy[SB][WP];
   __shared__ int slx[SB];
   __shared__ __align__(4) unsigned short soff[(NC + 2) & ~1];  // cell counts, then offsets
-  const int cid = blockIdx.x;
+  const int cid = bid;
   if (cid >= a.nchunks[0]) return;
   const int4 ch = a.chunks[cid];
   const int bin = ch.x, start = ch.y, n = ch.z, slot = ch.w;
@@ -761,27 +781,36 @@ struct __align__(16) MfmaRec {
 // seven workgroups per CU, which hide the load and LDS latencies.
 constexpr int kMfmaSB = kSpreadThreads;
 
-template <int W>
-__global__ void __launch_bounds__(kSpreadThreads) k_spread_mfma(SpreadArgs a) {
-  constexpr int SB = kMfmaSB, NWV = kSpreadThreads / 64;  // 4 waves, one quarter each
+template <int W, int TILE>
+__device__ __forceinline__ void spread_mfma_body(const SpreadArgs& a, int bid, int) {
+  constexpr int SB = kMfmaSB, NWV = kSpreadThreads / 64;  // 4 waves
+  constexpr int QS = TILE / 16, NQ = QS * QS;  // 16 x 16 quarter tiles of the bin
+  constexpr int QPW = NQ / NWV;                // quarter tiles per wave: 1 (32 x 32 bins) or 4 (64 x 64)
+  constexpr int NACC = QPW == 1 ? 2 : 1;       // accumulator pairs per quarter tile
+  static_assert(NQ % NWV == 0, "whole quarter tiles per wave");
   __shared__ MfmaRec srec[SB];
   __shared__ float swx[SB * W];
   __shared__ float swy[SB * W];
-  __shared__ unsigned short slist[4][SB];
-  __shared__ int scnt[NWV][4];
-  __shared__ int sbase[NWV][4];
-  __shared__ int slen[4];
-  const int cid = blockIdx.x;
+  __shared__ unsigned short slist[NQ][SB];
+  __shared__ int scnt[NWV][NQ];
+  __shared__ int sbase[NWV][NQ];
+  __shared__ int slen[NQ];
+  const int cid = bid;
   if (cid >= a.nchunks[0]) return;
   const int4 ch = a.chunks[cid];
   const int bin = ch.x, start = ch.y, n = ch.z, slot = ch.w;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const float blog = a.beta * 1.4426950408889634f;
-  // this wave's quarter and the lane's operand row / column and record slot
-  const int sx0 = 16 * (wv & 1), sy0 = 16 * (wv >> 1);
+  // the lane's operand row / column and record slot inside a group of four
   const int kk = lane >> 4, ii = lane & 15;
-  v4f accr = {0.f, 0.f, 0.f, 0.f}, acci = {0.f, 0.f, 0.f, 0.f};
-  v4f accr2 = {0.f, 0.f, 0.f, 0.f}, acci2 = {0.f, 0.f, 0.f, 0.f};
+  v4f accr[QPW][NACC], acci[QPW][NACC];
+#pragma unroll
+  for (int u = 0; u < QPW; ++u)
+#pragma unroll
+    for (int h = 0; h < NACC; ++h) {
+      accr[u][h] = v4f{0.f, 0.f, 0.f, 0.f};
+      acci[u][h] = v4f{0.f, 0.f, 0.f, 0.f};
+    }
   const unsigned long long below = (1ull << lane) - 1ull;
   // the thread's record of the first sub-batch and its value
   BinRec rc;
@@ -802,7 +831,7 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread_mfma(SpreadArgs a) {
     const bool more = b0 + SB + t < n;
     if (more) nx = a.recs[start + b0 + SB + t];
     // stage: value, first tap, kernel weights; list the record under every
-    // quarter its footprint meets
+    // quarter tile its footprint meets
     int lx = 0, ly = 0;
     if (ok) {
       lx = rec_lx(rc.packed);
@@ -819,18 +848,18 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread_mfma(SpreadArgs a) {
         swy[t * W + mm] = es_kernel_fast(rc.dy + (float)mm, a.two_over_w, blog);
       }
     }
-    int rank[4];
+    int rank[NQ];
 #pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4) {
-      const int qx = 16 * (s4 & 1), qy = 16 * (s4 >> 1);
+    for (int q = 0; q < NQ; ++q) {
+      const int qx = 16 * (q % QS), qy = 16 * (q / QS);
       const bool meets = ok && lx <= qx + 15 && lx + W - 1 >= qx && ly <= qy + 15 && ly + W - 1 >= qy;
       const unsigned long long bal = __ballot(meets);
-      rank[s4] = meets ? __popcll(bal & below) : -1;
-      if (lane == 0) scnt[wv][s4] = __popcll(bal);
+      rank[q] = meets ? __popcll(bal & below) : -1;
+      if (lane == 0) scnt[wv][q] = __popcll(bal);
     }
     __syncthreads();
     // list bases: records of earlier waves first
-    if (t < 4) {
+    if (t < NQ) {
       int run = 0;
       for (int w2 = 0; w2 < NWV; ++w2) {
         const int c2 = scnt[w2][t];
@@ -841,77 +870,92 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread_mfma(SpreadArgs a) {
     }
     __syncthreads();
 #pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4)
-      if (rank[s4] >= 0) slist[s4][sbase[wv][s4] + rank[s4]] = (unsigned short)t;
+    for (int q = 0; q < NQ; ++q)
+      if (rank[q] >= 0) slist[q][sbase[wv][q] + rank[q]] = (unsigned short)t;
     __syncthreads();
     const float2 nv = more ? a.vals[nx.idx] : czero();
-    const int len = slen[wv];
-    // the wave's quarter: groups of four listed records, two groups per step
-    // into two accumulator pairs, so that consecutive matrix operations are
-    // independent and both groups' loads are in flight together
-    for (int g = 0; g < len; g += 8) {
-      int j[2];
-      bool valid[2];
+    // the wave's quarter tiles: groups of four listed records, NACC groups
+    // per step into NACC accumulator pairs (independent matrix operations,
+    // loads in flight together)
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int idx = g + 4 * h + kk;
-        valid[h] = idx < len;
-        j[h] = valid[h] ? (int)slist[wv][idx] : 0;
+    for (int u = 0; u < QPW; ++u) {
+      const int q = wv * QPW + u;
+      const int sx0 = 16 * (q % QS), sy0 = 16 * (q / QS);
+      const int len = slen[q];
+      for (int g = 0; g < len; g += 4 * NACC) {
+        int j[NACC];
+        bool valid[NACC];
+#pragma unroll
+        for (int h = 0; h < NACC; ++h) {
+          const int idx = g + 4 * h + kk;
+          valid[h] = idx < len;
+          j[h] = valid[h] ? (int)slist[q][idx] : 0;
+        }
+        MfmaRec m[NACC];
+#pragma unroll
+        for (int h = 0; h < NACC; ++h) m[h] = srec[j[h]];
+#pragma unroll
+        for (int h = 0; h < NACC; ++h) {
+          const int mlx = (int)(short)(m[h].lxy & 0xffff), mly = m[h].lxy >> 16;
+          const int dy = sy0 + ii - mly, dx = sx0 + ii - mlx;
+          const bool iny = valid[h] && (unsigned)dy < (unsigned)W;
+          const bool inx = valid[h] && (unsigned)dx < (unsigned)W;
+          const float wy = swy[j[h] * W + (iny ? dy : 0)];
+          const float wx = swx[j[h] * W + (inx ? dx : 0)];
+          const float ay = iny ? wy : 0.f;
+          const float bx = inx ? wx : 0.f;
+          accr[u][h] = __builtin_amdgcn_mfma_f32_16x16x4f32(m[h].cr * ay, bx, accr[u][h], 0, 0, 0);
+          acci[u][h] = __builtin_amdgcn_mfma_f32_16x16x4f32(m[h].ci * ay, bx, acci[u][h], 0, 0, 0);
+        }
       }
-      MfmaRec m[2];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) m[h] = srec[j[h]];
-      float ay[2], bx[2];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int mlx = (int)(short)(m[h].lxy & 0xffff), mly = m[h].lxy >> 16;
-        const int dy = sy0 + ii - mly, dx = sx0 + ii - mlx;
-        const bool iny = valid[h] && (unsigned)dy < (unsigned)W;
-        const bool inx = valid[h] && (unsigned)dx < (unsigned)W;
-        const float wy = swy[j[h] * W + (iny ? dy : 0)];
-        const float wx = swx[j[h] * W + (inx ? dx : 0)];
-        ay[h] = iny ? wy : 0.f;
-        bx[h] = inx ? wx : 0.f;
-      }
-      accr = __builtin_amdgcn_mfma_f32_16x16x4f32(m[0].cr * ay[0], bx[0], accr, 0, 0, 0);
-      acci = __builtin_amdgcn_mfma_f32_16x16x4f32(m[0].ci * ay[0], bx[0], acci, 0, 0, 0);
-      accr2 = __builtin_amdgcn_mfma_f32_16x16x4f32(m[1].cr * ay[1], bx[1], accr2, 0, 0, 0);
-      acci2 = __builtin_amdgcn_mfma_f32_16x16x4f32(m[1].ci * ay[1], bx[1], acci2, 0, 0, 0);
     }
     __syncthreads();
     rc = nx;
     cv = nv;
   }
-  accr += accr2;
-  acci += acci2;
-  // accumulator element e of lane l: quarter row 4 (l / 16) + e, column l % 16
+  // accumulator element e of lane l: quarter-tile row 4 (l / 16) + e, column l % 16
   const int bx = bin % a.TX, by = bin / a.TX;
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int yy = sy0 + 4 * kk + e, xx = sx0 + ii;
-    const float2 v = make_float2(accr[e], acci[e]);
-    if (slot < 0) {
-      const int gy = by * kTile + yy, gx = bx * kTile + xx;
-      if (gy < a.L && gx < a.L) a.grid[(size_t)gy * a.L + gx] = v;
-    } else {
-      a.scratch[(size_t)slot * (kTile * kTile) + yy * kTile + xx] = v;
+  for (int u = 0; u < QPW; ++u) {
+    const int q = wv * QPW + u;
+    const int sx0 = 16 * (q % QS), sy0 = 16 * (q / QS);
+    v4f r = accr[u][0], i = acci[u][0];
+#pragma unroll
+    for (int h = 1; h < NACC; ++h) {
+      r += accr[u][h];
+      i += acci[u][h];
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int yy = sy0 + 4 * kk + e, xx = sx0 + ii;
+      const float2 v = make_float2(r[e], i[e]);
+      if (slot < 0) {
+        const int gy = by * TILE + yy, gx = bx * TILE + xx;
+        if (gy < a.L && gx < a.L) a.grid[(size_t)gy * a.L + gx] = v;
+      } else {
+        a.scratch[(size_t)slot * (TILE * TILE) + yy * TILE + xx] = v;
+      }
     }
   }
 }
 
 // Sum the partial tiles of every multi-chunk bin, in chunk order (the bin's
 // chunks hold consecutive scratch slots, the first one's in its table entry).
-__global__ void __launch_bounds__(256) k_spread_reduce(SpreadReduceArgs a) {
-  if ((int)blockIdx.x >= a.nmulti[0]) return;
-  const int bin = a.multi[blockIdx.x];
+// Each workgroup sums 1024 cells of one bin: (tile / 32)^2 workgroups per bin.
+__device__ __forceinline__ void spread_reduce_body(const SpreadReduceArgs& a, int bid, int) {
+  const int tl = a.tile_log, tile = 1 << tl, cells = tile * tile;
+  const int parts = cells >> 10;
+  const int mb = bid / parts, part = bid - mb * parts;
+  if (mb >= a.nmulti[0]) return;
+  const int bin = a.multi[mb];
   const int c0 = a.bin_chunk0[bin], nb = a.bin_nchunk[bin];
   const int slot0 = a.chunks[c0].w;
   const int bx = bin % a.TX, by = bin / a.TX;
-  for (int e = threadIdx.x; e < kTile * kTile; e += 256) {
+  for (int e = (part << 10) + threadIdx.x; e < ((part + 1) << 10); e += 256) {
     float2 s = czero();
-    for (int q = 0; q < nb; ++q) s = cadd(s, a.scratch[(size_t)(slot0 + q) * (kTile * kTile) + e]);
-    const int yy = e / kTile, xx = e % kTile;
-    const int gy = by * kTile + yy, gx = bx * kTile + xx;
+    for (int q = 0; q < nb; ++q) s = cadd(s, a.scratch[(size_t)(slot0 + q) * cells + e]);
+    const int yy = e >> tl, xx = e & (tile - 1);
+    const int gy = (by << tl) + yy, gx = (bx << tl) + xx;
     if (gy < a.L && gx < a.L) a.grid[(size_t)gy * a.L + gx] = s;
   }
 }
@@ -926,12 +970,12 @@ constexpr int kInterpThreads = 256;
 constexpr int kInterpBatch = 4;
 // (launch bound: at least 5 waves per SIMD, i.e. at most 96 VGPRs)
 
-template <int W>
-__global__ void __launch_bounds__(kInterpThreads, 5) k_interp(InterpArgs a) {
-  constexpr int RS = kTile + W - 1;
+template <int W, int TILE>
+__device__ __forceinline__ void interp_body(const InterpArgs& a, int bid, int) {
+  constexpr int RS = TILE + W - 1;
   constexpr int NT = kInterpThreads, B = kInterpBatch;
   __shared__ float2 sg[RS * RS];
-  const int cid = blockIdx.x;
+  const int cid = bid;
   if (cid >= a.nchunks[0]) return;
   const int4 ch = a.chunks[cid];
   const int bin = ch.x, start = ch.y, n = ch.z;
@@ -939,7 +983,7 @@ __global__ void __launch_bounds__(kInterpThreads, 5) k_interp(InterpArgs a) {
   const int t = threadIdx.x;
   for (int e = t; e < RS * RS; e += NT) {
     const int yy = e / RS, xx = e % RS;
-    const int gy = by * kTile + yy, gx = bx * kTile + xx;
+    const int gy = by * TILE + yy, gx = bx * TILE + xx;
     sg[e] = (gy < a.L && gx < a.L) ? a.grid[(size_t)gy * a.L + gx] : czero();
   }
   __syncthreads();
@@ -1002,19 +1046,18 @@ hipError_t launch_fill_i32(int* p, int v, int64_t n, hipStream_t st) {
   return hipGetLastError();
 }
 
-static hipError_t bin_lds_attr(const void* k, int bytes) {
-  if (bytes > 64 * 1024) return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  return hipSuccess;
-}
 
 hipError_t launch_bin_hist(const double* x, const double* y, int64_t M, BinGeom g, int ppw, int G,
                            uint16_t* hist, hipStream_t st) {
-  if (G <= 0) return hipSuccess;
   const int T = g.TX * g.TX, bytes = ((T + 2) / 2) * 4;
-  hipError_t e = bin_lds_attr((const void*)k_bin_hist, bytes);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_bin_hist, dim3(G), dim3(kBinThreads), bytes, st, x, y, M, g, ppw, hist);
-  return hipGetLastError();
+  BinArgs a{};
+  a.x = x;
+  a.y = y;
+  a.M = M;
+  a.g = g;
+  a.ppw = ppw;
+  a.hist = hist;
+  return launch_or_record<BinArgs, bin_hist_body, kBinThreads>(a, G, bytes, st);
 }
 
 int bin_scan_workgroups(int T) { return (T + 1 + 63) / 64; }
@@ -1023,33 +1066,29 @@ hipError_t launch_bin_colscan(const uint16_t* hist, int G, int T, int* off, int*
                               int* done, hipStream_t st) {
   const int nwg = bin_scan_workgroups(T);
   const int bytes = nwg * kWgVals * (int)sizeof(int);
-  hipError_t e = bin_lds_attr((const void*)k_bin_colscan, bytes + 8 * 1024);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_bin_colscan, dim3(nwg), dim3(kColThreads), bytes, st, hist, G, T, off, total, so, done);
-  return hipGetLastError();
+  const ColscanArgs a{hist, G, T, off, total, so, done};
+  return launch_or_record<ColscanArgs, bin_colscan_body, kColThreads>(a, nwg, bytes, st);
 }
 
 hipError_t launch_bin_scatter(const double* x, const double* y, int64_t M, BinGeom g, int ppw, int G,
                               const int* off, const int* bin_base, BinRec* recs, bool stable, hipStream_t st) {
   if (G <= 0) return hipSuccess;
   const int T = g.TX * g.TX;
+  BinArgs a{};
+  a.x = x;
+  a.y = y;
+  a.M = M;
+  a.g = g;
+  a.ppw = ppw;
+  a.off = off;
+  a.bin_base = bin_base;
+  a.recs = recs;
   if (stable) {
     if (ppw > kDetPoints) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_bin_scatter_det, dim3(G), dim3(kBinThreads), 0, st, x, y, M, g, ppw, off, bin_base,
-                       recs);
-    return hipGetLastError();
+    return launch_or_record<BinArgs, bin_scatter_det_body, kBinThreads>(a, G, 0, st);
   }
-  if (T * 4 <= kScatterCursorBytes) {
-    hipLaunchKernelGGL(k_bin_scatter<true>, dim3(G), dim3(kBinThreads), T * 4, st, x, y, M, g, ppw, off, bin_base,
-                       recs);
-  } else {
-    const int bytes = ((T + 1) / 2) * 4;
-    hipError_t e = bin_lds_attr((const void*)k_bin_scatter<false>, bytes);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bin_scatter<false>, dim3(G), dim3(kBinThreads), bytes, st, x, y, M, g, ppw, off, bin_base,
-                       recs);
-  }
-  return hipGetLastError();
+  if (T * 4 <= kScatterCursorBytes) return launch_or_record<BinArgs, bin_scatter_body<true>, kBinThreads>(a, G, T * 4, st);
+  return launch_or_record<BinArgs, bin_scatter_body<false>, kBinThreads>(a, G, ((T + 1) / 2) * 4, st);
 }
 
 #define NUASM_DISPATCH_W(w, CALL)                                                   \
@@ -1074,39 +1113,45 @@ hipError_t launch_bin_scatter(const double* x, const double* y, int64_t M, BinGe
 
 hipError_t launch_spread(int w, bool small_chunks, const SpreadArgs& a, int grid, hipStream_t st) {
   if (grid <= 0) return hipSuccess;
-#define CALL(W)                                                                                          \
-  {                                                                                                      \
-    if (small_chunks)                                                                                    \
-      hipLaunchKernelGGL((k_spread<W, spread_nsub(W, true)>), dim3(grid), dim3(kSpreadThreads), 0, st, a);  \
-    else                                                                                                 \
-      hipLaunchKernelGGL((k_spread<W, spread_nsub(W, false)>), dim3(grid), dim3(kSpreadThreads), 0, st, a); \
+#define CALL(W)                                                                                               \
+  {                                                                                                           \
+    if (small_chunks)                                                                                         \
+      return launch_or_record<SpreadArgs, spread_body<W, spread_nsub(W, true)>, kSpreadThreads>(a, grid, 0, st); \
+    return launch_or_record<SpreadArgs, spread_body<W, spread_nsub(W, false)>, kSpreadThreads>(a, grid, 0, st);  \
   }
   NUASM_DISPATCH_W(w, CALL)
 #undef CALL
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
-hipError_t launch_spread_mfma(int w, bool small_chunks, const SpreadArgs& a, int grid, hipStream_t st) {
+hipError_t launch_spread_mfma(int w, int tile, const SpreadArgs& a, int grid, hipStream_t st) {
   if (grid <= 0) return hipSuccess;
-  (void)small_chunks;  // any chunk size: sub-batches of 256 records
-#define CALL(W) hipLaunchKernelGGL(k_spread_mfma<W>, dim3(grid), dim3(kSpreadThreads), 0, st, a)
+  // any chunk size: sub-batches of 256 records
+#define CALL(W)                                                                                           \
+  {                                                                                                       \
+    if (tile == 64) return launch_or_record<SpreadArgs, spread_mfma_body<W, 64>, kSpreadThreads>(a, grid, 0, st); \
+    return launch_or_record<SpreadArgs, spread_mfma_body<W, 32>, kSpreadThreads>(a, grid, 0, st);           \
+  }
   NUASM_DISPATCH_W(w, CALL)
 #undef CALL
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_spread_reduce(const SpreadReduceArgs& a, int grid, hipStream_t st) {
-  if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_spread_reduce, dim3(grid), dim3(256), 0, st, a);
-  return hipGetLastError();
+  return launch_or_record<SpreadReduceArgs, spread_reduce_body, 256>(a, grid, 0, st);
 }
 
-hipError_t launch_interp(int w, const InterpArgs& a, int grid, hipStream_t st) {
+hipError_t launch_interp(int w, int tile, const InterpArgs& a, int grid, hipStream_t st) {
   if (grid <= 0) return hipSuccess;
-#define CALL(W) hipLaunchKernelGGL(k_interp<W>, dim3(grid), dim3(kInterpThreads), 0, st, a)
+  // at least five waves per SIMD: at most 96 VGPRs
+#define CALL(W)                                                                                         \
+  {                                                                                                     \
+    if (tile == 64) return launch_or_record<InterpArgs, interp_body<W, 64>, kInterpThreads, 5>(a, grid, 0, st); \
+    return launch_or_record<InterpArgs, interp_body<W, 32>, kInterpThreads, 5>(a, grid, 0, st);           \
+  }
   NUASM_DISPATCH_W(w, CALL)
 #undef CALL
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 }  // namespace nuasm

@@ -8,7 +8,7 @@
 
 namespace nuasm {
 
-constexpr int kTile = 32;        // fine cells per bin side
+constexpr int kTile = 32;        // default fine cells per bin side (32 or 64)
 constexpr int kPad = 8;          // support margin: taps reach w/2 <= 8 cells past the window
 constexpr int kChunk = 2048;       // default max records per interpolation workgroup
 constexpr int kSpreadChunk = 1792; // default max records per spreading workgroup
@@ -57,6 +57,23 @@ struct BinGeom {
   int w;            // kernel width
   int L;            // support side
   int TX;           // bins per axis
+  int tile_log;     // log2 of the bin side in fine cells (5 or 6)
+};
+
+// Arguments of the row and column passes of the grid pipelines.
+struct RowArgs {
+  const float2* in;
+  float2* out;
+  GridGeom g;
+  const float* dinv;   // deconvolution weights (row passes that apply them)
+  const float2* tw;    // twiddle tables
+};
+struct ColArgs {
+  const float2* in;
+  float2* out;
+  GridGeom g;
+  Spectral sp;
+  const float2* tw;
 };
 
 // Outputs of the bin scan (bin bases, chunk tables and their counts).
@@ -76,7 +93,29 @@ struct BinScanOut {
 };
 constexpr int kBinPre = 12;  // ints per row of bin_pre / wg_sum
 int bin_scan_workgroups(int T);  // workgroups of the column scan over T bins
+
+struct ColscanArgs {
+  const uint16_t* hist;
+  int G, T;                // ranges, bins
+  int* off;
+  int* total;
+  BinScanOut so;
+  int* done;               // finished-workgroup counter (reset by the last one)
+};
 constexpr int kScanDone = 7;  // element of nch counting finished column-scan workgroups
+
+// Arguments of the binning kernels (histogram, scatter).
+struct BinArgs {
+  const double* x;
+  const double* y;
+  int64_t M;
+  BinGeom g;
+  int ppw;                 // points per binning workgroup
+  uint16_t* hist;          // histogram rows (histogram pass)
+  const int* off;          // per-range offsets (scatter)
+  const int* bin_base;     // first record of each bin (scatter)
+  BinRec* recs;            // records (scatter)
+};
 
 struct SpreadArgs {
   const BinRec* recs;
@@ -99,6 +138,7 @@ struct SpreadReduceArgs {
   const float2* scratch;
   float2* grid;
   int L, TX;
+  int tile_log;           // log2 of the bin side
 };
 
 struct InterpArgs {
@@ -143,9 +183,9 @@ hipError_t launch_bin_scatter(const double* x, const double* y, int64_t M, BinGe
                               const int* off, const int* bin_base, BinRec* recs, bool stable, hipStream_t st);
 hipError_t launch_spread(int w, bool small_chunks, const SpreadArgs& a, int grid, hipStream_t st);
 // the same spreading as sums of outer products on the matrix cores
-hipError_t launch_spread_mfma(int w, bool small_chunks, const SpreadArgs& a, int grid, hipStream_t st);
+hipError_t launch_spread_mfma(int w, int tile, const SpreadArgs& a, int grid, hipStream_t st);
 hipError_t launch_spread_reduce(const SpreadReduceArgs& a, int grid, hipStream_t st);
-hipError_t launch_interp(int w, const InterpArgs& a, int grid, hipStream_t st);
+hipError_t launch_interp(int w, int tile, const InterpArgs& a, int grid, hipStream_t st);
 // separable interpolation at a grid: support (L x L) -> R (nrows x nx) -> out (ny x nx)
 hipError_t launch_grid_interp(int w, const float2* fine, float2* R, float2* out, const GridPts& p, hipStream_t st);
 // separable spreading of grid values (ny x nx) -> S (ny x L) -> support (L x L)

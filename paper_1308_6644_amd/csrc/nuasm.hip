@@ -14,6 +14,7 @@
 #include <string>
 #include <vector>
 
+#include "group.h"
 #include "launch.h"
 #include "nuasm.h"
 
@@ -183,6 +184,7 @@ struct PointSet {
   int64_t rec_cap = 0;  // points the record buffer is sized for
   float2* scratch = nullptr;  // partial tiles of split bins
   int64_t scratch_chunks = 0;  // tiles it holds
+  size_t scratch_bytes = 0;
   int* host_stat = nullptr;  // pinned [8]
   int64_t M = 0;
   bool ready = false;
@@ -208,6 +210,8 @@ struct nuasm_plan_s {
   BinGeom bgeom{};
   Spectral spec{};
   int T = 0, TX = 0;
+  int tile = kTile;          // bin side in fine cells (32 or 64)
+  int tile_log = 5;
   const float2* tw = nullptr;
   // device memory
   float2* gridA = nullptr;
@@ -313,6 +317,11 @@ struct StageScope {
   int stage;
   hipEvent_t start = nullptr;
   StageScope(nuasm_plan_s* p, int s) : pl(p), stage(s) {
+    // a batch collecting launches for grouped execution: tag them, time nothing
+    if (LaunchRecorder* r = active_recorder()) {
+      r->stage = s;
+      return;
+    }
     if (!pl->timing) return;
     start = take_event(pl);
     if (start) (void)hipEventRecord(start, pl->stream);
@@ -418,7 +427,7 @@ PointLayout point_layout(const nuasm_plan_s* pl, int64_t cap) {
   L.chunks = round256(sizeof(int4) * (size_t)L.chunk_cap);
   L.hist = round256(sizeof(uint16_t) * (size_t)L.hist_rows * (pl->T + 1));
   L.hoff = round256(sizeof(int) * (size_t)L.hist_rows * (pl->T + 1));
-  L.scratch = round256(sizeof(float2) * kTile * kTile * (size_t)L.tiles);
+  L.scratch = round256(sizeof(float2) * (size_t)pl->tile * pl->tile * (size_t)L.tiles);
   return L;
 }
 
@@ -450,6 +459,7 @@ void carve_workspace(nuasm_plan_s* pl) {
     q.hoff = (int*)p;
     p += L.hoff;
     q.scratch = (float2*)p;
+    q.scratch_bytes = L.scratch;
     p += L.scratch;
     q.rec_cap = L.cap;
     q.chunk_cap = L.chunk_cap;
@@ -476,13 +486,14 @@ void free_owned_buffers(nuasm_plan_s* pl) {
     f(q.ip_chunks, sizeof(int4) * q.chunk_cap);
     f(q.hist, sizeof(uint16_t) * q.hist_rows * (pl->T + 1));
     f(q.hoff, sizeof(int) * q.hist_rows * (pl->T + 1));
-    f(q.scratch, sizeof(float2) * kTile * kTile * q.scratch_chunks);
+    f(q.scratch, q.scratch_bytes);
     q.recs = nullptr;
     q.sp_chunks = q.ip_chunks = nullptr;
     q.hist = nullptr;
     q.hoff = nullptr;
     q.scratch = nullptr;
     q.rec_cap = q.chunk_cap = q.hist_rows = q.scratch_chunks = 0;
+    q.scratch_bytes = 0;
     if (!q.grid) q.ready = false;
   }
 }
@@ -524,6 +535,39 @@ nuasm_status bind_workspace(nuasm_plan_s* pl, void* dev, size_t bytes) {
   return NUASM_OK;
 }
 
+// Free the T-sized bin arrays of a point set (before the bin tile changes).
+void free_bin_arrays(nuasm_plan_s* pl, PointSet& q) {
+  const size_t T = (size_t)pl->T;
+  auto f = [&](void* p, size_t b) {
+    if (p) {
+      (void)hipFree(p);
+      pl->bytes -= b;
+    }
+  };
+  f(q.counts, sizeof(int) * (T + 1));
+  f(q.cursor, sizeof(int) * T);
+  f(q.sp_first, sizeof(int) * T);
+  f(q.sp_n, sizeof(int) * T);
+  f(q.multi, sizeof(int) * T);
+  f(q.bin_pre, sizeof(int) * T * kBinPre);
+  f(q.wg_sum, sizeof(int) * (size_t)bin_scan_workgroups(pl->T) * kBinPre);
+  f(q.nch, sizeof(int) * 8);
+  q.counts = q.cursor = q.sp_first = q.sp_n = q.multi = q.bin_pre = q.wg_sum = q.nch = nullptr;
+  if (q.host_stat) (void)hipHostFree(q.host_stat);
+  q.host_stat = nullptr;
+}
+
+// The bin side and everything that follows from it (bins per axis, the
+// binning geometry).
+void set_tile(nuasm_plan_s* pl, int tile) {
+  pl->tile = tile;
+  pl->tile_log = tile == 64 ? 6 : 5;
+  pl->TX = (pl->geom.L + tile - 1) / tile;
+  pl->T = pl->TX * pl->TX;
+  pl->bgeom.TX = pl->TX;
+  pl->bgeom.tile_log = pl->tile_log;
+}
+
 nuasm_status ensure_points_capacity(nuasm_plan_s* pl, PointSet& q, int64_t M) {
   if (pl->ws) {
     if (M <= q.rec_cap) return NUASM_OK;
@@ -550,9 +594,10 @@ nuasm_status ensure_points_capacity(nuasm_plan_s* pl, PointSet& q, int64_t M) {
   }
   if (q.scratch) {
     (void)hipFree(q.scratch);
-    pl->bytes -= sizeof(float2) * kTile * kTile * q.scratch_chunks;
+    pl->bytes -= q.scratch_bytes;
     q.scratch = nullptr;
     q.scratch_chunks = 0;
+    q.scratch_bytes = 0;
   }
   if (q.hist) {
     (void)hipFree(q.hist);
@@ -594,12 +639,14 @@ nuasm_status ensure_scratch(nuasm_plan_s* pl, PointSet& q) {
   if (q.scratch) {
     HIP_TRY(hipStreamSynchronize(pl->stream), "hipStreamSynchronize");
     (void)hipFree(q.scratch);
-    pl->bytes -= sizeof(float2) * kTile * kTile * q.scratch_chunks;
+    pl->bytes -= q.scratch_bytes;
     q.scratch = nullptr;
     q.scratch_chunks = 0;
+    q.scratch_bytes = 0;
   }
-  HIP_TRY(dalloc(pl, &q.scratch, (size_t)need * kTile * kTile), "hipMalloc(spread scratch)");
+  HIP_TRY(dalloc(pl, &q.scratch, (size_t)need * pl->tile * pl->tile), "hipMalloc(spread scratch)");
   q.scratch_chunks = need;
+  q.scratch_bytes = sizeof(float2) * (size_t)need * pl->tile * pl->tile;
   return NUASM_OK;
 }
 
@@ -773,7 +820,7 @@ nuasm_status run_spread(nuasm_plan_s* pl, PointSet& q, const float2* vals) {
     if (pl->sp_method == 1)
       HIP_TRY(launch_spread(pl->w, pl->sp_small, sa, sp_grid(pl, q), st), "launch spread");
     else
-      HIP_TRY(launch_spread_mfma(pl->w, pl->sp_small, sa, sp_grid(pl, q), st), "launch spread_mfma");
+      HIP_TRY(launch_spread_mfma(pl->w, pl->tile, sa, sp_grid(pl, q), st), "launch spread_mfma");
   }
   {
     StageScope sc(pl, NUASM_STAGE_SPREAD_REDUCE);
@@ -787,7 +834,9 @@ nuasm_status run_spread(nuasm_plan_s* pl, PointSet& q, const float2* vals) {
     ra.grid = pl->gridA;
     ra.L = pl->geom.L;
     ra.TX = pl->TX;
-    HIP_TRY(launch_spread_reduce(ra, multi_grid(pl, q), st), "launch spread_reduce");
+    ra.tile_log = pl->tile_log;
+    const int parts = (pl->tile / kTile) * (pl->tile / kTile);  // 1024 cells per workgroup
+    HIP_TRY(launch_spread_reduce(ra, multi_grid(pl, q) * parts, st), "launch spread_reduce");
   }
   return NUASM_OK;
 }
@@ -810,7 +859,7 @@ nuasm_status run_interp(nuasm_plan_s* pl, PointSet& q, const float2* grid, float
   ia.TX = pl->TX;
   ia.two_over_w = 2.0f / (float)pl->w;
   ia.beta = pl->beta;
-  HIP_TRY(launch_interp(pl->w, ia, ip_grid(pl, q), pl->stream), "launch interp");
+  HIP_TRY(launch_interp(pl->w, pl->tile, ia, ip_grid(pl, q), pl->stream), "launch interp");
   return NUASM_OK;
 }
 
@@ -1001,7 +1050,7 @@ nuasm_status nuasm_plan_create(const nuasm_params* p, void* hip_stream, nuasm_pl
   }
   const int Npf = 1 << pl->logNpf, nf = 2 * Npf;
   const int L = Npf + 2 * kPad;
-  pl->TX = (L + kTile - 1) / kTile;
+  pl->TX = (L + pl->tile - 1) / pl->tile;
   pl->T = pl->TX * pl->TX;
   G.Npf = Npf;
   G.nf = nf;
@@ -1018,6 +1067,7 @@ nuasm_status nuasm_plan_create(const nuasm_params* p, void* hip_stream, nuasm_pl
   B.w = w;
   B.L = L;
   B.TX = pl->TX;
+  B.tile_log = pl->tile_log;
 
   Spectral& S = pl->spec;
   S.tf = p->tf == NUASM_TF_FRESNEL ? 1 : 0;
@@ -1119,7 +1169,7 @@ nuasm_status nuasm_plan_get_info(nuasm_plan pl, nuasm_plan_info* info) {
   info->L = pl->geom.L;
   info->w = pl->w;
   info->beta = pl->beta;
-  info->tile = kTile;
+  info->tile = pl->tile;
   info->tiles = pl->T;
   info->kx_lo = pl->geom.kxlo;
   info->kx_hi = pl->geom.kxhi;
@@ -1157,36 +1207,66 @@ nuasm_status nuasm_plan_set_tuning(nuasm_plan pl, const nuasm_tuning* t) {
     return fail(NUASM_ERR_INVALID_ARG, "tuning fields must be >= 0");
   if (t->spread_method < 0 || t->spread_method > 2)
     return fail(NUASM_ERR_INVALID_ARG, "spread_method must be 0 (automatic), 1 (register gather) or 2 (matrix cores)");
+  if (t->bin_tile != 0 && t->bin_tile != 32 && t->bin_tile != 64)
+    return fail(NUASM_ERR_INVALID_ARG, "bin_tile must be 0 (32), 32 or 64");
+  const int new_tile = t->bin_tile == 0 ? kTile : t->bin_tile;
+  if (new_tile != kTile && t->spread_method == 1)
+    return fail(NUASM_ERR_INVALID_ARG, "the register-gather spreading takes 32 x 32 bins only");
   if (t->interp_chunk != 0 && (t->interp_chunk < 256 || t->interp_chunk > 65536))
     return fail(NUASM_ERR_INVALID_ARG, "interp_chunk must be 0 or in [256, 65536]");
   if (t->bin_range_points != 0 && (t->bin_range_points < 1024 || t->bin_range_points > kBinPointsMax))
     return fail(NUASM_ERR_INVALID_ARG, "bin_range_points must be 0 or in [1024, 65535]");
-  // spreading chunks come in the two sizes the kernel is built for; a request
-  // below the default takes the small one
+  // spreading chunks come in the two sizes the kernels are built for; a
+  // request below the default takes the small one
   const int small = spread_nsub(pl->w, true) * spread_subbatch(pl->w);
-  const bool old_small = pl->sp_small;
-  const int old_sp = pl->sp_chunk, old_ip = pl->ip_chunk, old_ppw = pl->bin_ppw, old_m = pl->sp_method;
-  pl->sp_small = t->spread_chunk != 0 && t->spread_chunk < kSpreadChunk;
-  pl->sp_chunk = pl->sp_small ? small : kSpreadChunk;
-  pl->ip_chunk = t->interp_chunk != 0 ? t->interp_chunk : kChunk;
-  pl->bin_ppw = t->bin_range_points;
-  pl->sp_method = t->spread_method;
+  struct Sizes {
+    bool sp_small;
+    int sp_chunk, ip_chunk, bin_ppw, sp_method, tile;
+  };
+  const Sizes old{pl->sp_small, pl->sp_chunk, pl->ip_chunk, pl->bin_ppw, pl->sp_method, pl->tile};
+  Sizes nw;
+  nw.sp_small = t->spread_chunk != 0 && t->spread_chunk < kSpreadChunk;
+  nw.sp_chunk = nw.sp_small ? small : kSpreadChunk;
+  nw.ip_chunk = t->interp_chunk != 0 ? t->interp_chunk : kChunk;
+  nw.bin_ppw = t->bin_range_points;
+  nw.sp_method = t->spread_method;
+  nw.tile = new_tile;
+  auto apply = [&](const Sizes& z) {
+    pl->sp_small = z.sp_small;
+    pl->sp_chunk = z.sp_chunk;
+    pl->ip_chunk = z.ip_chunk;
+    pl->bin_ppw = z.bin_ppw;
+    pl->sp_method = z.sp_method;
+    set_tile(pl, z.tile);
+  };
+  // a caller's workspace must hold the new sizes' minimum; else nothing changes
+  if (pl->ws) {
+    apply(nw);
+    const size_t need = workspace_bytes_for(pl, 1024);
+    apply(old);
+    if (need > pl->ws_bytes) {
+      char buf[200];
+      std::snprintf(buf, sizeof(buf), "the workspace (%zu bytes) is below this tuning's minimum of %zu bytes",
+                    pl->ws_bytes, need);
+      return fail(NUASM_ERR_INVALID_ARG, buf);
+    }
+  }
+  if (new_tile != old.tile) {
+    // new bins: the T-sized arrays of every set are allocated again
+    HIP_TRY(hipStreamSynchronize(pl->stream), "hipStreamSynchronize");
+    for (int i = 0; i < pl->nsets; ++i) free_bin_arrays(pl, pl->ps[i]);
+    apply(nw);
+    for (int i = 0; i < pl->nsets; ++i) {
+      const nuasm_status s = alloc_point_set(pl, pl->ps[i]);
+      if (s != NUASM_OK) return s;
+    }
+  }
+  apply(nw);
   // binned point sets must be bound again (their chunk tables and histogram
   // rows follow the old sizes); a set bound as a grid stays ready, but its
-  // buffers are resized too at its next binning
-  // a caller's workspace is carved again for the new sizes (the old tuning
-  // stays if they do not fit)
-  if (pl->ws) {
-    const nuasm_status s = bind_workspace(pl, pl->ws, pl->ws_bytes);
-    if (s != NUASM_OK) {
-      pl->sp_small = old_small;
-      pl->sp_chunk = old_sp;
-      pl->ip_chunk = old_ip;
-      pl->bin_ppw = old_ppw;
-      pl->sp_method = old_m;
-    }
-    return s;
-  }
+  // buffers are resized too at its next binning.  A caller's workspace is
+  // carved again for the new sizes.
+  if (pl->ws) return bind_workspace(pl, pl->ws, pl->ws_bytes);
   for (int i = 0; i < pl->nsets; ++i) {
     PointSet& q = pl->ps[i];
     q.rec_cap = 0;
@@ -1339,12 +1419,13 @@ nuasm_status nuasm_execute_noalloc(nuasm_plan pl, const void* in, void* out) {
   // sources); type 2 spreads nothing
   const PointSet& q = pl->ps[0];
   if (pl->p.type != NUASM_TYPE_2 && !q.grid) {
-    const int64_t need = scratch_tiles_needed(pl, q);
+    // partial tiles of the plan's bin side, counted in 32 x 32 units
+    const int64_t need = scratch_tiles_needed(pl, q) * (pl->tile / kTile) * (pl->tile / kTile);
     if (need > kStaticTiles) {
       char buf[256];
       std::snprintf(buf, sizeof(buf),
-                    "split bins may need %lld partial tiles, above the static scratch's %lld (bind the points "
-                    "without NUASM_DEFER_RANGE_CHECK so that the exact count is known, or use nuasm_execute)",
+                    "split bins may need %lld partial 32 x 32 tiles, above the static scratch's %lld (bind the "
+                    "points without NUASM_DEFER_RANGE_CHECK so that the exact count is known, or use nuasm_execute)",
                     (long long)need, (long long)kStaticTiles);
       return fail(NUASM_ERR_UNSUPPORTED, buf);
     }
@@ -1493,10 +1574,26 @@ nuasm_status nuasm_rs_direct(int64_t M1, const double* x1, const double* y1, con
 // ================================================================ batches
 }  // extern "C"
 
+// One grouped launch: the same kernel instantiation for every plane that has
+// it in one stage, its planes' arguments in a device table.
+struct GroupedStage {
+  int stage = 0;
+  hipError_t (*grouped)(const void*, const int*, int, int, size_t, hipStream_t) = nullptr;
+  int n = 0;            // planes (table entries)
+  int blocks = 0;       // blocks of all entries
+  size_t lds = 0;       // the largest entry's dynamic LDS
+  size_t tab_off = 0;   // entry table and block offsets inside the batch's table buffer
+  size_t first_off = 0;
+  std::vector<int> planes;
+};
+
 // One recorded graph of a batch and the arguments it was recorded with.
 struct BatchGraph {
   hipGraphExec_t exec = nullptr;
   std::vector<const void*> key;
+  bool grouped = false;
+  std::vector<GroupedStage> stages;
+  char* tables = nullptr;  // device: every grouped stage's entry table and block offsets
 };
 
 struct nuasm_batch_s {
@@ -1508,9 +1605,11 @@ struct nuasm_batch_s {
   int active = 0;              // branches in use (nuasm_batch_set_branches)
   std::vector<int> branch_of;  // plane -> branch
   hipEvent_t fork = nullptr;
+  hipEvent_t binned = nullptr;   // grouped graphs: binning done (the interpolation waits for it)
   std::vector<hipEvent_t> join;
   // one-shot (binning + operator), binning alone, operator alone
   BatchGraph g_run, g_bin, g_exec;
+  bool grouped = true;         // grouped stage launches (nuasm_batch_set_grouped)
   long long* ts = nullptr;     // [P + 1] device wall-clock stamps
   int clock_khz = 0;
 };
@@ -1523,6 +1622,10 @@ void drop_graph(BatchGraph& g) {
   if (g.exec) (void)hipGraphExecDestroy(g.exec);
   g.exec = nullptr;
   g.key.clear();
+  if (g.tables) (void)hipFree(g.tables);
+  g.tables = nullptr;
+  g.stages.clear();
+  g.grouped = false;
 }
 
 void batch_release(nuasm_batch_s* b) {
@@ -1539,6 +1642,7 @@ void batch_release(nuasm_batch_s* b) {
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->ev_out) (void)hipEventDestroy(b->ev_out);
   if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->binned) (void)hipEventDestroy(b->binned);
   for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
   if (b->ts) (void)hipFree(b->ts);
 }
@@ -1575,6 +1679,115 @@ static void assign_branches(nuasm_batch_s* b, const std::vector<int64_t>& M) {
   }
 }
 
+// Pipeline order of the stages for grouped execution, and which chain each
+// belongs to: binning, then the type-1 operator, on one branch; the type-2
+// grid passes (which need no points) on a second branch, joining the first
+// after binning for the interpolation.
+static const int kGroupOrderA[] = {NUASM_STAGE_BIN_HIST, NUASM_STAGE_BIN_COLSCAN, NUASM_STAGE_BIN_SCATTER,
+                                   NUASM_STAGE_SPREAD,   NUASM_STAGE_SPREAD_REDUCE, NUASM_STAGE_T1_ROWS,
+                                   NUASM_STAGE_T1_COLS,  NUASM_STAGE_T1_ROWS_INV};
+static const int kGroupOrderB[] = {NUASM_STAGE_T2_ROWS, NUASM_STAGE_T2_COLS, NUASM_STAGE_T2_ROWS_INV,
+                                   NUASM_STAGE_INTERP};
+
+// Collect every plane's launches (plane(pl, p) with the recorder active: host
+// logic and allocations run, kernels are only recorded), group them by stage
+// and kernel instantiation, and upload the grouped launches' tables.
+template <typename F>
+static nuasm_status batch_collect(nuasm_batch_s* b, BatchGraph& g, F plane) {
+  const int P = (int)b->plans.size();
+  std::vector<LaunchRecorder> rec(P);
+  for (int p = 0; p < P; ++p) {
+    nuasm_plan_s* pl = b->plans[p];
+    pl->stream = b->stream;
+    pl->timing = false;
+    active_recorder() = &rec[p];
+    const nuasm_status s = plane(pl, p);
+    active_recorder() = nullptr;
+    if (s != NUASM_OK) return fail(s, "plane " + std::to_string(p) + ": " + g_last_error);
+  }
+  // group: for each stage in pipeline order, one launch per instantiation
+  std::vector<int> order(std::begin(kGroupOrderA), std::end(kGroupOrderA));
+  order.insert(order.end(), std::begin(kGroupOrderB), std::end(kGroupOrderB));
+  std::vector<std::vector<const RecordedLaunch*>> members;
+  for (int stage : order) {
+    std::vector<const void*> keys;
+    for (int p = 0; p < P; ++p)
+      for (const RecordedLaunch& L : rec[p].launches)
+        if (L.stage == stage && std::find(keys.begin(), keys.end(), L.key) == keys.end()) keys.push_back(L.key);
+    for (const void* key : keys) {
+      GroupedStage gs;
+      gs.stage = stage;
+      std::vector<const RecordedLaunch*> mem;
+      for (int p = 0; p < P; ++p)
+        for (const RecordedLaunch& L : rec[p].launches)
+          if (L.stage == stage && L.key == key) {
+            mem.push_back(&L);
+            gs.planes.push_back(p);
+            gs.grouped = L.grouped;
+            gs.lds = std::max(gs.lds, L.lds);
+            gs.blocks += L.blocks;
+          }
+      gs.n = (int)mem.size();
+      g.stages.push_back(gs);
+      members.push_back(mem);
+    }
+  }
+  // tables: entries (each stage's argument struct), then block offsets
+  size_t bytes = 0;
+  for (size_t i = 0; i < g.stages.size(); ++i) {
+    GroupedStage& gs = g.stages[i];
+    gs.tab_off = bytes;
+    bytes = round256(bytes + (size_t)gs.n * members[i][0]->arg_bytes);
+    gs.first_off = bytes;
+    bytes = round256(bytes + sizeof(int) * (size_t)(gs.n + 1));
+  }
+  std::vector<unsigned char> host(std::max<size_t>(bytes, 1), 0);
+  for (size_t i = 0; i < g.stages.size(); ++i) {
+    const GroupedStage& gs = g.stages[i];
+    int* first = (int*)(host.data() + gs.first_off);
+    int run = 0;
+    for (int e = 0; e < gs.n; ++e) {
+      const RecordedLaunch& L = *members[i][e];
+      std::memcpy(host.data() + gs.tab_off + (size_t)e * L.arg_bytes, L.args.data(), L.arg_bytes);
+      first[e] = run;
+      run += L.blocks;
+    }
+    first[gs.n] = run;
+  }
+  HIP_TRY(hipMalloc((void**)&g.tables, host.size()), "hipMalloc(grouped tables)");
+  HIP_TRY(hipMemcpy(g.tables, host.data(), host.size(), hipMemcpyHostToDevice), "hipMemcpy(grouped tables)");
+  return NUASM_OK;
+}
+
+// Enqueue the grouped launches of one chain (stages in `order`) on stream st,
+// a completion stamp after each launch for the planes it finishes.  After
+// stage `wait_before` (if any) the chain first waits for event `ev`.
+static hipError_t enqueue_chain(nuasm_batch_s* b, const BatchGraph& g, const int* order, int norder,
+                                hipStream_t st, int wait_before, hipEvent_t ev, std::vector<int>& last_stage_of,
+                                hipEvent_t record_after_binning) {
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < norder && e == hipSuccess; ++k) {
+    const int stage = order[k];
+    if (stage == wait_before && ev) e = hipStreamWaitEvent(st, ev, 0);
+    for (size_t i = 0; i < g.stages.size() && e == hipSuccess; ++i) {
+      const GroupedStage& gs = g.stages[i];
+      if (gs.stage != stage) continue;
+      e = gs.grouped(g.tables + gs.tab_off, (const int*)(g.tables + gs.first_off), gs.n, gs.blocks, gs.lds, st);
+      // a plane is finished after the last grouped launch it is in
+      bool finishes = false;
+      for (int p : gs.planes)
+        if (last_stage_of[p] == (int)i) finishes = true;
+      if (e == hipSuccess && finishes) {
+        for (int p : gs.planes)
+          if (last_stage_of[p] == (int)i) e = launch_stamp(b->ts + 1 + p, st);
+      }
+    }
+    if (stage == NUASM_STAGE_BIN_SCATTER && record_after_binning && e == hipSuccess)
+      e = hipEventRecord(record_after_binning, st);
+  }
+  return e;
+}
+
 // Launch graph g, or record it first when it is missing or was recorded with
 // other arguments (key).  plane(pl, p) enqueues plane p's work on the plan's
 // current stream.  Recording: one eager pass on the caller's stream (sizes every
@@ -1595,11 +1808,13 @@ static nuasm_status batch_launch(nuasm_batch_s* b, BatchGraph& g, const std::vec
     HIP_TRY(hipStreamWaitEvent(b->stream, b->ev_out, 0), "hipStreamWaitEvent");
     return NUASM_OK;
   };
-  if (g.exec && key == g.key) return launch();
-  if (g.exec) {
+  if (g.exec && key == g.key && g.grouped == b->grouped) return launch();
+  if (g.exec || g.tables) {
     HIP_TRY(hipStreamSynchronize(b->cap), "hipStreamSynchronize");
     drop_graph(g);
   }
+  // eager pass on the caller's stream: sizes every buffer and sets kernel
+  // attributes, so that the capture below enqueues launches only
   for (int p = 0; p < P; ++p) {
     nuasm_plan_s* pl = b->plans[p];
     pl->stream = b->stream;
@@ -1608,27 +1823,63 @@ static nuasm_status batch_launch(nuasm_batch_s* b, BatchGraph& g, const std::vec
     if (s != NUASM_OK) return fail(s, "plane " + std::to_string(p) + ": " + g_last_error);
   }
   HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
-  assign_branches(b, M);
+  if (b->grouped) {
+    g.grouped = true;
+    nuasm_status s = batch_collect(b, g, plane);
+    for (nuasm_plan_s* pl : b->plans) pl->stream = b->stream;
+    if (s != NUASM_OK) {
+      drop_graph(g);
+      return s;
+    }
+  }
+  if (!b->grouped) assign_branches(b, M);
   HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
   nuasm_status st = NUASM_OK;
   hipError_t e = launch_stamp(b->ts, b->cap);
   if (e == hipSuccess) e = hipEventRecord(b->fork, b->cap);
-  for (size_t k = 0; e == hipSuccess && k < (size_t)b->active; ++k) e = hipStreamWaitEvent(b->branch[k], b->fork, 0);
-  for (int p = 0; e == hipSuccess && st == NUASM_OK && p < P; ++p) {
-    nuasm_plan_s* pl = b->plans[p];
-    pl->stream = b->branch[b->branch_of[p]];
-    st = plane(pl, p);
-    if (st == NUASM_OK) e = launch_stamp(b->ts + 1 + p, pl->stream);
-  }
-  for (size_t k = 0; e == hipSuccess && k < (size_t)b->active; ++k) {
-    e = hipEventRecord(b->join[k], b->branch[k]);
-    if (e == hipSuccess) e = hipStreamWaitEvent(b->cap, b->join[k], 0);
+  if (b->grouped) {
+    // two chains: binning and the type-1 operator on branch 0, the type-2 grid
+    // passes on branch 1 (interpolation after binning); stamps per plane
+    std::vector<int> last(P, -1);
+    for (size_t i = 0; i < g.stages.size(); ++i)
+      for (int p : g.stages[i].planes) last[p] = (int)i;
+    hipStream_t s0 = b->branch[0], s1 = b->branch[1];
+    if (e == hipSuccess) e = hipStreamWaitEvent(s0, b->fork, 0);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s1, b->fork, 0);
+    hipEvent_t binned = b->binned;
+    if (e == hipSuccess)
+      e = enqueue_chain(b, g, kGroupOrderA, (int)(sizeof(kGroupOrderA) / sizeof(int)), s0, -1, nullptr, last,
+                        binned);
+    if (e == hipSuccess)
+      e = enqueue_chain(b, g, kGroupOrderB, (int)(sizeof(kGroupOrderB) / sizeof(int)), s1, NUASM_STAGE_INTERP,
+                        binned, last, nullptr);
+    // planes with no launch at all (no points, type 2) finish at once
+    for (int p = 0; e == hipSuccess && p < P; ++p)
+      if (last[p] < 0) e = launch_stamp(b->ts + 1 + p, s0);
+    for (size_t k = 0; e == hipSuccess && k < 2; ++k) {
+      e = hipEventRecord(b->join[k], b->branch[k]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(b->cap, b->join[k], 0);
+    }
+  } else {
+    for (size_t k = 0; e == hipSuccess && k < (size_t)b->active; ++k)
+      e = hipStreamWaitEvent(b->branch[k], b->fork, 0);
+    for (int p = 0; e == hipSuccess && st == NUASM_OK && p < P; ++p) {
+      nuasm_plan_s* pl = b->plans[p];
+      pl->stream = b->branch[b->branch_of[p]];
+      st = plane(pl, p);
+      if (st == NUASM_OK) e = launch_stamp(b->ts + 1 + p, pl->stream);
+    }
+    for (size_t k = 0; e == hipSuccess && k < (size_t)b->active; ++k) {
+      e = hipEventRecord(b->join[k], b->branch[k]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(b->cap, b->join[k], 0);
+    }
   }
   hipGraph_t graph = nullptr;
   hipError_t e2 = hipStreamEndCapture(b->cap, &graph);
   for (nuasm_plan_s* pl : b->plans) pl->stream = b->stream;
   if (st != NUASM_OK || e != hipSuccess || e2 != hipSuccess) {
     if (graph) (void)hipGraphDestroy(graph);
+    drop_graph(g);
     if (st != NUASM_OK) return st;
     return hip_fail(e != hipSuccess ? e : e2, "graph capture");
   }
@@ -1636,6 +1887,7 @@ static nuasm_status batch_launch(nuasm_batch_s* b, BatchGraph& g, const std::vec
   (void)hipGraphDestroy(graph);
   if (e != hipSuccess) {
     g.exec = nullptr;
+    drop_graph(g);
     return hip_fail(e, "hipGraphInstantiate");
   }
   g.key = key;
@@ -1675,11 +1927,10 @@ nuasm_status nuasm_batch_create(int32_t P, const nuasm_params* params, void* hip
     }
     b->plans.push_back(pl);
   }
-  const int K = std::min(kBranches, (int)P);
-  b->active = K;
+  b->active = std::min(kBranches, (int)P);
   b->branch_of.assign(P, 0);
   hipError_t e;
-  for (int k = 0; k < K; ++k) {
+  for (int k = 0; k < kBranches; ++k) {
     hipStream_t st = nullptr;
     if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess)
       return bail(hip_fail(e, "hipStreamCreate"));
@@ -1690,6 +1941,8 @@ nuasm_status nuasm_batch_create(int32_t P, const nuasm_params* params, void* hip
     b->join.push_back(ev);
   }
   if ((e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming)) != hipSuccess)
+    return bail(hip_fail(e, "hipEventCreate"));
+  if ((e = hipEventCreateWithFlags(&b->binned, hipEventDisableTiming)) != hipSuccess)
     return bail(hip_fail(e, "hipEventCreate"));
   if ((e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming)) != hipSuccess)
     return bail(hip_fail(e, "hipEventCreate"));
@@ -1799,11 +2052,20 @@ nuasm_status nuasm_batch_set_tuning(nuasm_batch b, int32_t plane, const nuasm_tu
 
 nuasm_status nuasm_batch_set_branches(nuasm_batch b, int32_t branches) {
   if (!b) return fail(NUASM_ERR_INVALID_ARG, "batch is NULL");
-  if (branches < 1 || branches > (int32_t)b->branch.size())
+  if (branches < 1 || branches > std::min<int32_t>(kBranches, (int32_t)b->plans.size()))
     return fail(NUASM_ERR_INVALID_ARG, "branches must be in [1, min(4, planes)]");
   nuasm_status s = batch_invalidate(b);
   if (s != NUASM_OK) return s;
   b->active = branches;
+  return NUASM_OK;
+}
+
+nuasm_status nuasm_batch_set_grouped(nuasm_batch b, int32_t grouped) {
+  if (!b) return fail(NUASM_ERR_INVALID_ARG, "batch is NULL");
+  if (grouped != 0 && grouped != 1) return fail(NUASM_ERR_INVALID_ARG, "grouped must be 0 or 1");
+  nuasm_status s = batch_invalidate(b);
+  if (s != NUASM_OK) return s;
+  b->grouped = grouped != 0;
   return NUASM_OK;
 }
 
@@ -1836,3 +2098,10 @@ nuasm_status nuasm_batch_plane_times(nuasm_batch b, float* ms) {
 }
 
 }  // extern "C"
+
+namespace nuasm {
+LaunchRecorder*& active_recorder() {
+  static thread_local LaunchRecorder* r = nullptr;
+  return r;
+}
+}  // namespace nuasm

@@ -6,9 +6,10 @@ transfer function, log2 of the point count):
   * interp_chunk      -- records per interpolation workgroup (1024 .. 8192),
   * bin_range_points  -- points per binning workgroup (automatic or 4096 .. 65535),
   * spread_method     -- spreading on the matrix cores or by register gather,
-and, per batch, the number of parallel graph branches (1 .. 4).  The 32 x 32
-bin tile itself is fixed: the spreading and interpolation kernels size their
-LDS tiles and register blocks for it at compile time.
+  * bin_tile          -- bin side, 32 or 64 fine cells (64: fewer duplicated
+                         records and bins, larger workgroups),
+and, per batch, the graph form (grouped stage launches or per-plane branches)
+and the number of parallel branches of the per-plane form (1 .. 4).
 
 Each candidate is timed on the GPU with HIP events as the one-shot operation
 it tunes (set_points + execute for a plane, a whole graph replay for a
@@ -26,15 +27,16 @@ import statistics
 
 import torch
 
-from . import Batch, Plan, make_params
+from . import Batch, NuasmError, Plan, make_params
 
 CANDIDATES = {
     "bin_range_points": (0, 4096, 16384, 65535),
     "interp_chunk": (0, 1024, 4096, 8192),
     "spread_chunk": (0, 896),
     "spread_method": (0, 1),
+    "bin_tile": (0, 64),
 }
-DEFAULT = {"spread_chunk": 0, "interp_chunk": 0, "bin_range_points": 0, "spread_method": 0}
+DEFAULT = {"spread_chunk": 0, "interp_chunk": 0, "bin_range_points": 0, "spread_method": 0, "bin_tile": 0}
 
 
 def cache_path() -> str:
@@ -97,7 +99,10 @@ def tune_plane(spec: dict, x: torch.Tensor, y: torch.Tensor, inp: torch.Tensor, 
     plan = Plan(defer_range_check=True, **spec)
 
     def run(t):
-        plan.set_tuning(**t)
+        try:
+            plan.set_tuning(**t)
+        except NuasmError:
+            return float("inf")  # a combination the library does not take
 
         def once():
             plan.set_points(x, y)
@@ -134,21 +139,28 @@ def tune_batch(batch: Batch, specs, xs, ys, ins, outs, cache: TuneCache | None =
             tuned += 1
         else:
             reused += 1
-        batch.set_tuning(p, **{k: t[k] for k in DEFAULT})
+        batch.set_tuning(p, **{k: t.get(k, 0) for k in DEFAULT})
     bkey = "batch:" + ",".join(sorted({plane_key(s, xs[p].numel()) for p, s in enumerate(specs)}))
     choice = cache.get(bkey)
     times = {}
-    if choice is None:
+    if choice is None or "grouped" not in choice:
+        # graph forms: grouped stage launches, or per-plane launches on 1..4 branches
+        batch.set_grouped(True)
+        times["grouped"] = _time(lambda: batch.run(xs, ys, ins, outs), reps)
+        batch.set_grouped(False)
         for k in range(1, min(4, len(specs)) + 1):
             batch.set_branches(k)
-            times[k] = _time(lambda: batch.run(xs, ys, ins, outs), reps)
-        k_best = min(times, key=times.get)
-        choice = {"branches": k_best, "ms": times[k_best]}
+            times[str(k)] = _time(lambda: batch.run(xs, ys, ins, outs), reps)
+        best = min(times, key=times.get)
+        choice = {"grouped": best == "grouped", "branches": 1 if best == "grouped" else int(best),
+                  "ms": times[best]}
         cache.put(bkey, choice)
-    batch.set_branches(choice["branches"])
+    batch.set_grouped(bool(choice["grouped"]))
+    if not choice["grouped"]:
+        batch.set_branches(int(choice["branches"]))
     cache.save()
-    return {"planes_tuned": tuned, "planes_from_cache": reused, "branches": choice["branches"],
-            "branch_ms": {str(k): v for k, v in times.items()}, "cache": cache.path}
+    return {"planes_tuned": tuned, "planes_from_cache": reused, "grouped": bool(choice["grouped"]),
+            "branches": int(choice["branches"]), "form_ms": times, "cache": cache.path}
 
 
 def apply_cached(batch: Batch, specs, Ms, cache: TuneCache | None = None) -> int:
@@ -159,6 +171,6 @@ def apply_cached(batch: Batch, specs, Ms, cache: TuneCache | None = None) -> int
     for p, spec in enumerate(specs):
         t = cache.get(plane_key(spec, int(Ms[p])))
         if t is not None:
-            batch.set_tuning(p, **{k: t[k] for k in DEFAULT})
+            batch.set_tuning(p, **{k: t.get(k, 0) for k in DEFAULT})
             n += 1
     return n

@@ -101,12 +101,12 @@ def test_plan_info_struct_layout_matches_header(P):
     assert ctypes.sizeof(P.PlanInfo) == 4 * 8 + 8 * 4 + 3 * 8 + 8 + 8 + 4 * 4
     assert [f for f, _ in P.PlanInfo._fields_][-4:] == ["spread_chunk", "interp_chunk", "bin_range_points",
                                                          "Npf"]
-    assert ctypes.sizeof(P.Tuning) == 16
+    assert ctypes.sizeof(P.Tuning) == 20
 
 
 def test_tuning_rejects_bad_values_without_a_device(P):
     lib = P.load()
-    t = P.Tuning(0, 100, 0, 0)
+    t = P.Tuning(0, 100, 0, 0, 0)
     assert lib.nuasm_status_string(lib.nuasm_plan_set_tuning(None, ctypes.byref(t))).decode() == \
         "NUASM_ERR_INVALID_ARG"
     assert lib.nuasm_batch_set_branches(None, 2) != 0
@@ -182,5 +182,5 @@ def test_boundary_calls_reject_null_handles(P):
     assert lib.nuasm_params_default(ctypes.byref(p)) == 0
     assert name(lib.nuasm_plan_many_create(0, ctypes.byref(p), None, ctypes.byref(h))) == "NUASM_ERR_INVALID_ARG"
     assert h.value is None
-    t = P.Tuning(0, 0, 0, 3)
+    t = P.Tuning(0, 0, 0, 3, 0)
     assert name(lib.nuasm_plan_set_tuning(None, ctypes.byref(t))) == "NUASM_ERR_INVALID_ARG"

@@ -58,3 +58,44 @@ def test_batch_matches_plain_plans_and_replays(capfd):
             err = check_close(host(o), r, 1e-6, what=str((rep, p, specs[p])))
     t = b.plane_times()
     assert len(t) == len(specs) and all(v > 0 for v in t)
+
+
+def test_grouped_and_per_plane_forms_match_plain_plans():
+    """The batch's two graph forms -- grouped stage launches over descriptor
+    tables (default) and every plane's own launches on parallel branches --
+    against plain plans, for the one-shot run and for points bound once with
+    two operator runs (set_points_many / execute_many)."""
+    import paper_1308_6644_amd as P
+    P.load()
+    specs, data = _planes(23, 10)
+    print(f"grouped vs per-plane: {len(specs)} planes", flush=True)
+    xs = [dev(torch, d[0]) for d in data]
+    ys = [dev(torch, d[1]) for d in data]
+    ins = [dev(torch, d[2]) for d in data]
+    refs = []
+    for s, x, y, i in zip(specs, xs, ys, ins):
+        plan = P.Plan(**s)
+        plan.set_points(x, y)
+        refs.append(host(plan.execute(i)))
+
+    def outs():
+        return [torch.full((2 * s["N"], 2 * s["N"]) if s["type"] == 1 else (x.numel(),), float("nan"),
+                           dtype=torch.complex64, device="cuda") for s, x in zip(specs, xs)]
+    for grouped in (True, False):
+        b = P.Batch(specs)
+        b.set_grouped(grouped)
+        o = outs()
+        for rep in range(2):
+            b.run(xs, ys, ins, o)
+            assert b.check_points() == -1
+            for p, r in enumerate(refs):
+                check_close(host(o[p]), r, 1e-6, what=f"run grouped={grouped} rep={rep} plane {p}")
+        o2 = outs()
+        b.set_points(xs, ys)
+        for rep in range(2):
+            b.execute(ins, o2)
+            for p, r in enumerate(refs):
+                check_close(host(o2[p]), r, 1e-6, what=f"many grouped={grouped} rep={rep} plane {p}")
+        t = b.plane_times()
+        assert len(t) == len(specs) and all(v > 0 for v in t)
+        b.close()

@@ -33,6 +33,9 @@ TUNINGS = [
     dict(interp_chunk=256),
     dict(interp_chunk=8192, bin_range_points=1024),
     dict(spread_chunk=896, interp_chunk=1024, bin_range_points=65535),
+    dict(bin_tile=64),
+    dict(bin_tile=64, spread_chunk=896, interp_chunk=1024, bin_range_points=1024),
+    dict(spread_method=1),
 ]
 
 
@@ -56,6 +59,7 @@ def test_tuned_shapes_match_oracle(P, tuning, tol):
         info = plan.info
         if tuning.get("interp_chunk"):
             assert info["interp_chunk"] == tuning["interp_chunk"]
+        assert info["tile"] == (tuning.get("bin_tile") or 32)
         if tuning.get("spread_chunk"):
             assert info["spread_chunk"] == (896 if tol == 1e-6 else 1024)
         check_close(host(plan.execute(dev(torch, inp))), ref, bound)
@@ -143,6 +147,11 @@ def test_autotuner_batch(P, tmp_path):
     b2 = P.Batch(specs)
     assert tune.apply_cached(b2, specs, [x.numel() for x in xs], tune.TuneCache(str(tmp_path / "tune.json"))) == 6
     outs2 = [torch.empty_like(o) for o in outs]
+    b2.set_grouped(True)
+    b2.run(xs, ys, ins, outs2)
+    for p in range(6):
+        check_close(host(outs2[p]), host(outs[p]), 2e-6)
+    b2.set_grouped(False)
     for k in (1, 2, 3, 4):
         b2.set_branches(k)
         b2.run(xs, ys, ins, outs2)

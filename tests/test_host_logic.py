@@ -55,3 +55,32 @@ def test_bench_byte_model():
     Np = 2048
     assert math.isclose((64 * M + 56 * Np * Np) / 1e6, 302.0, abs_tol=0.1)
     assert math.isclose((56 * M + 44 * Np * Np) / 1e6, 243.3, abs_tol=0.1)
+
+
+def test_bench_counters_follow_the_kernel_sources(tmp_path, monkeypatch):
+    """Counter figures are used only while the kernel's sources are the ones
+    they were taken on; the roofline's bound follows the counters."""
+    import json
+    import bench
+    sha = bench.sources_sha256("spread")
+    assert sha != bench.sources_sha256("t1_cols")
+    path = tmp_path / "counters.json"
+    rec = {"sources_sha256": sha, "fetch_bytes": 60e6, "write_bytes": 35e6, "valu_insts": 18e6,
+           "mfma_insts": 1e6}
+    path.write_text(json.dumps({"kernels": {"spread": rec, "t1_cols": dict(rec, sources_sha256="0" * 64)}}))
+    monkeypatch.setattr(bench, "COUNTERS", str(path))
+    assert bench.counter_record("spread")["valu_insts"] == 18e6
+    assert bench.counter_record("t1_cols") is None      # taken on other sources
+    assert bench.counter_record("interp") is None       # never taken
+    # 1 launch of 60 us per step: VALU issue 18e6 x 4 / (1024 x 2.4e9 x 60e-6) = 0.49
+    stages = {"spread": {"ms": 0.06, "launches": 1, "bytes": 50e6},
+              "t1_cols": {"ms": 0.05, "launches": 1, "bytes": 50e6}}
+    roof, report = bench.roofline(stages, 1)
+    assert roof["kernel"] == "spread" and roof["bound"] == "alu"
+    assert abs(roof["frac"] - 18e6 * 4 / (1024 * 2.4e9 * 60e-6)) < 1e-9
+    assert roof["traffic"] == 95e6
+    assert abs(roof["hbm_algorithmic_frac"] - 50e6 / 60e-6 / 8e12) < 1e-9
+    # without counters the HBM roofline of the algorithmic bytes stays
+    monkeypatch.setattr(bench, "COUNTERS", str(tmp_path / "missing.json"))
+    roof, _ = bench.roofline(stages, 1)
+    assert roof["bound"] == "hbm" and roof["traffic"] is None
