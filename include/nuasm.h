@@ -64,7 +64,10 @@ typedef enum {
   NUASM_ERR_UNSUPPORTED = 4,   /* N not a power of two in [16, 4096], ... */
   NUASM_ERR_NO_DEVICE = 5,     /* no HIP device visible */
   NUASM_ERR_ALLOC = 6,         /* device or pinned-host allocation failed */
-  NUASM_ERR_HIP = 7            /* a HIP runtime call failed */
+  NUASM_ERR_HIP = 7,           /* a HIP runtime call failed */
+  NUASM_STATUS_MAX = 0x7fffffff /* not a status: widens the type's range so
+                                   that any value 0..INT32_MAX a caller passes
+                                   to nuasm_status_string is a valid one */
 } nuasm_status;
 
 enum { NUASM_TYPE_1 = 1, NUASM_TYPE_2 = 2, NUASM_TYPE_3 = 3 };
@@ -419,6 +422,14 @@ nuasm_status nuasm_batch_plane_times(nuasm_batch batch, float* ms);
 
 const char* nuasm_status_string(nuasm_status s);
 const char* nuasm_last_error(void);
+
+/* Testing aid: make the k-th device or pinned-host allocation the library
+ * attempts from now on fail as if memory had run out (NUASM_ERR_ALLOC from
+ * the call that needed it), then allocate normally again; k = 0 turns it off.
+ * The environment variable NUASM_FAIL_ALLOC=k does the same when the library
+ * is first used.  Every failing call leaves its plan or batch destroyable
+ * (and a plan whose set_points failed usable after a later successful one). */
+nuasm_status nuasm_debug_fail_alloc(int64_t k);
 
 /* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
 int32_t nuasm_version(void);

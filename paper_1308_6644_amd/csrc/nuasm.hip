@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -43,6 +44,50 @@ nuasm_status hip_fail(hipError_t e, const char* what) {
 
 constexpr double kPi = 3.14159265358979323846264338327950288;
 
+// ------------------------------------------------ allocation-failure injection
+// Testing aid: with NUASM_FAIL_ALLOC=k in the environment (or after
+// nuasm_debug_fail_alloc(k)), the k-th device or pinned-host allocation the
+// library attempts from then on fails as if memory had run out (1-based; 0 or
+// unset: never).  Every allocation of the library goes through dev_malloc /
+// host_malloc.
+std::atomic<int64_t> g_fail_at{-1};  // allocations left before the failing one; < 0: off
+std::once_flag g_fail_env_once;
+
+void read_fail_env() {
+  std::call_once(g_fail_env_once, [] {
+    const char* v = std::getenv("NUASM_FAIL_ALLOC");
+    if (v && *v) {
+      const long long k = std::atoll(v);
+      if (k > 0) g_fail_at.store(k - 1);
+    }
+  });
+}
+
+bool inject_alloc_failure() {
+  read_fail_env();
+  int64_t left = g_fail_at.load();
+  while (left >= 0) {
+    if (g_fail_at.compare_exchange_weak(left, left - 1)) return left == 0;
+  }
+  return false;
+}
+
+hipError_t dev_malloc(void** p, size_t bytes) {
+  if (inject_alloc_failure()) {
+    *p = nullptr;
+    return hipErrorOutOfMemory;
+  }
+  return hipMalloc(p, bytes);
+}
+
+hipError_t host_malloc(void** p, size_t bytes) {
+  if (inject_alloc_failure()) {
+    *p = nullptr;
+    return hipErrorOutOfMemory;
+  }
+  return hipHostMalloc(p, bytes, hipHostMallocDefault);
+}
+
 // ------------------------------------------------------- twiddle tables
 // One table per device: for n = 2^l, tw[n + m] = exp(-2 pi i m / n).
 std::mutex g_tw_mutex;
@@ -64,7 +109,7 @@ nuasm_status twiddles_for_device(int dev, const float2** out) {
       }
     }
     float2* d = nullptr;
-    HIP_TRY(hipMalloc(&d, sizeof(float2) * total), "hipMalloc(twiddles)");
+    HIP_TRY(dev_malloc((void**)&d, sizeof(float2) * total), "hipMalloc(twiddles)");
     hipError_t e = hipMemcpy(d, h.data(), sizeof(float2) * total, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
       (void)hipFree(d);
@@ -255,7 +300,7 @@ namespace {
 
 template <typename T>
 hipError_t dalloc(nuasm_plan_s* pl, T** p, size_t n) {
-  hipError_t e = hipMalloc((void**)p, sizeof(T) * std::max<size_t>(n, 1));
+  hipError_t e = dev_malloc((void**)p, sizeof(T) * std::max<size_t>(n, 1));
   if (e == hipSuccess) pl->bytes += sizeof(T) * std::max<size_t>(n, 1);
   return e;
 }
@@ -398,7 +443,7 @@ nuasm_status alloc_point_set(nuasm_plan_s* pl, PointSet& q) {
   HIP_TRY(dalloc(pl, &q.bin_pre, (size_t)pl->T * kBinPre), "hipMalloc(bins)");
   HIP_TRY(dalloc(pl, &q.wg_sum, (size_t)bin_scan_workgroups(pl->T) * kBinPre), "hipMalloc(bins)");
   HIP_TRY(dalloc(pl, &q.nch, (size_t)8), "hipMalloc(counters)");
-  HIP_TRY(hipHostMalloc((void**)&q.host_stat, sizeof(int) * 8, hipHostMallocDefault), "hipHostMalloc(status)");
+  HIP_TRY(host_malloc((void**)&q.host_stat, sizeof(int) * 8), "hipHostMalloc(status)");
   HIP_TRY(launch_fill_i32(q.nch, 0, 8, pl->stream), "launch fill");
   return NUASM_OK;
 }
@@ -957,11 +1002,19 @@ const char* nuasm_status_string(nuasm_status s) {
     case NUASM_ERR_NO_DEVICE: return "NUASM_ERR_NO_DEVICE";
     case NUASM_ERR_ALLOC: return "NUASM_ERR_ALLOC";
     case NUASM_ERR_HIP: return "NUASM_ERR_HIP";
+    default: break;
   }
   return "NUASM_UNKNOWN_STATUS";
 }
 
 const char* nuasm_last_error(void) { return g_last_error.c_str(); }
+
+nuasm_status nuasm_debug_fail_alloc(int64_t k) {
+  if (k < 0) return fail(NUASM_ERR_INVALID_ARG, "k must be >= 0");
+  read_fail_env();  // the environment first, so that this call wins
+  g_fail_at.store(k > 0 ? k - 1 : -1);
+  return NUASM_OK;
+}
 
 nuasm_status nuasm_params_default(nuasm_params* p) {
   if (!p) return fail(NUASM_ERR_INVALID_ARG, "params is NULL");
@@ -1754,7 +1807,7 @@ static nuasm_status batch_collect(nuasm_batch_s* b, BatchGraph& g, F plane) {
     }
     first[gs.n] = run;
   }
-  HIP_TRY(hipMalloc((void**)&g.tables, host.size()), "hipMalloc(grouped tables)");
+  HIP_TRY(dev_malloc((void**)&g.tables, host.size()), "hipMalloc(grouped tables)");
   HIP_TRY(hipMemcpy(g.tables, host.data(), host.size(), hipMemcpyHostToDevice), "hipMemcpy(grouped tables)");
   return NUASM_OK;
 }
@@ -1950,7 +2003,8 @@ nuasm_status nuasm_batch_create(int32_t P, const nuasm_params* params, void* hip
     return bail(hip_fail(e, "hipEventCreate"));
   if ((e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking)) != hipSuccess)
     return bail(hip_fail(e, "hipStreamCreate"));
-  if ((e = hipMalloc(&b->ts, sizeof(long long) * (P + 1))) != hipSuccess) return bail(hip_fail(e, "hipMalloc(stamps)"));
+  if ((e = dev_malloc((void**)&b->ts, sizeof(long long) * (P + 1))) != hipSuccess)
+    return bail(hip_fail(e, "hipMalloc(stamps)"));
   int dev = 0;
   (void)hipGetDevice(&dev);
   if ((e = hipDeviceGetAttribute(&b->clock_khz, hipDeviceAttributeWallClockRate, dev)) != hipSuccess)
