@@ -87,7 +87,7 @@ struct Dft<1, DIR> {
 
 // LDS index with one pad slot per 16 complex elements: breaks the stride-16
 // bank pattern of the first Stockham pass.
-__device__ __forceinline__ int pidx(int e) { return e + (e >> 4); }
+__host__ __device__ constexpr int pidx(int e) { return e + (e >> 4); }
 __host__ __device__ constexpr int lds_elems(int n) { return n + (n >> 4) + 1; }
 
 // Two-level twiddle table for length N = 2^LOGN, held in LDS:
@@ -134,8 +134,16 @@ __device__ __forceinline__ void stockham_pass(float2* __restrict__ s, const floa
     if (NB % NT == 0 || b < NB) {
       const int c = b % C, i = b / C;
       const int k = i & (P - 1);
+      // inputs NR * C elements apart: one padded address and constant offsets
+      // when the stride is a whole number of pad groups
+      if constexpr ((NR * C) % 16 == 0) {
+        const int p0 = pidx(i * C + c);
 #pragma unroll
-      for (int j = 0; j < R; ++j) x[q][j] = s[pidx((i + j * NR) * C + c)];
+        for (int j = 0; j < R; ++j) x[q][j] = s[p0 + j * pidx(NR * C)];
+      } else {
+#pragma unroll
+        for (int j = 0; j < R; ++j) x[q][j] = s[pidx((i + j * NR) * C + c)];
+      }
       if (P > 1) {
         // w^j, w = exp(-2 pi i k TWS / N): one table lookup, then a power
         // tree (each w^j a few products away from the table value)
@@ -165,8 +173,14 @@ __device__ __forceinline__ void stockham_pass(float2* __restrict__ s, const floa
       }
       Dft<R, DIR>::run(x[q]);
       const int base = (i - k) * R + k;
+      if constexpr ((P * C) % 16 == 0) {
+        const int p0 = pidx(base * C + c);
 #pragma unroll
-      for (int j = 0; j < R; ++j) s[pidx((base + j * P) * C + c)] = x[q][j];
+        for (int j = 0; j < R; ++j) s[p0 + j * pidx(P * C)] = x[q][j];
+      } else {
+#pragma unroll
+        for (int j = 0; j < R; ++j) s[pidx((base + j * P) * C + c)] = x[q][j];
+      }
     }
   }
   __syncthreads();

@@ -812,24 +812,19 @@ __device__ __forceinline__ void spread_mfma_body(const SpreadArgs& a, int bid, i
       acci[u][h] = v4f{0.f, 0.f, 0.f, 0.f};
     }
   const unsigned long long below = (1ull << lane) - 1ull;
-  // the thread's record of the first sub-batch and its value
-  BinRec rc;
-  rc.packed = 0;
-  rc.dx = rc.dy = 0.f;
-  rc.idx = -1;
-  if (t < n) rc = a.recs[start + t];
-  float2 cv = t < n ? a.vals[rc.idx] : czero();
+  // the thread's record of the first sub-batch and its value.  Every thread
+  // loads, from a position clamped into the chunk, so that no load sits
+  // behind a branch (a load whose result merges with a default at a branch
+  // join is waited for at once, which would serialise the prefetch below).
+  const int last = start + n - 1;
+  BinRec rc = a.recs[min(start + t, last)];
+  float2 cv = a.vals[rc.idx];
   for (int b0 = 0; b0 < n; b0 += SB) {
     const int nsb = min(SB, n - b0);
     const bool ok = t < nsb;
     // the next sub-batch's record, in flight while this one is staged; its
     // value is requested once the record has arrived (after the staging)
-    BinRec nx;
-    nx.packed = 0;
-    nx.dx = nx.dy = 0.f;
-    nx.idx = -1;
-    const bool more = b0 + SB + t < n;
-    if (more) nx = a.recs[start + b0 + SB + t];
+    const BinRec nx = a.recs[min(start + b0 + SB + t, last)];
     // stage: value, first tap, kernel weights; list the record under every
     // quarter tile its footprint meets
     int lx = 0, ly = 0;
@@ -873,7 +868,7 @@ __device__ __forceinline__ void spread_mfma_body(const SpreadArgs& a, int bid, i
     for (int q = 0; q < NQ; ++q)
       if (rank[q] >= 0) slist[q][sbase[wv][q] + rank[q]] = (unsigned short)t;
     __syncthreads();
-    const float2 nv = more ? a.vals[nx.idx] : czero();
+    const float2 nv = a.vals[nx.idx];
     // the wave's quarter tiles: groups of four listed records, NACC groups
     // per step into NACC accumulator pairs (independent matrix operations,
     // loads in flight together)
@@ -881,7 +876,7 @@ __device__ __forceinline__ void spread_mfma_body(const SpreadArgs& a, int bid, i
     for (int u = 0; u < QPW; ++u) {
       const int q = wv * QPW + u;
       const int sx0 = 16 * (q % QS), sy0 = 16 * (q / QS);
-      const int len = slen[q];
+      const int len = __builtin_amdgcn_readfirstlane(slen[q]);  // uniform: a scalar loop
       for (int g = 0; g < len; g += 4 * NACC) {
         int j[NACC];
         bool valid[NACC];
