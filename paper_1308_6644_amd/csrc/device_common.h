@@ -115,17 +115,33 @@ __device__ __forceinline__ float2 tw2_get(const float2* __restrict__ t, int m) {
   return cmul(t[m >> 6], t[Tw2<LOGN>::HI + (m & 63)]);
 }
 
+// No-op input / output / hook for the passes below.
+struct NoIO {
+  __device__ __forceinline__ float2 operator()(int, int) const { return czero(); }
+  __device__ __forceinline__ void operator()(int, int, float2) const {}
+  __device__ __forceinline__ void operator()() const {}
+};
+
 // One radix-R Stockham pass over C interleaved transforms of length N held in
 // LDS (element t of transform c at pidx(t * C + c)), NT threads.  P is the
 // product of the radices of the earlier passes.  tw is the LDS two-level
 // twiddle table of length N (see Tw2).
-template <int LOGN, int C, int NT, int DIR, int R, int P>
-__device__ __forceinline__ void stockham_pass(float2* __restrict__ s, const float2* __restrict__ tw, int tid) {
+//
+// LOAD: the inputs come from ld(t, c) instead of LDS (first pass only, P = 1:
+// the kernel's global load feeds the butterflies directly, and no barrier is
+// needed before the LDS writes).  STORE: the outputs, in natural order at
+// this point (last pass, P R = N), go to st(t, c, v) instead of LDS, and
+// post() runs after them, before the closing barrier.
+template <int LOGN, int C, int NT, int DIR, int R, int P, bool LOAD, bool STORE, class Ld, class St, class Post>
+__device__ __forceinline__ void stockham_pass_io(float2* __restrict__ s, const float2* __restrict__ tw, int tid,
+                                                 const Ld& ld, const St& st, const Post& post) {
   constexpr int N = 1 << LOGN;
   constexpr int NR = N / R;
   constexpr int NB = C * NR;
   constexpr int PER = (NB + NT - 1) / NT;
   constexpr int TWS = N / (P * R);
+  static_assert(!LOAD || P == 1, "only the first pass reads from the loader");
+  static_assert(!STORE || P * R == N, "only the last pass writes to the store");
   float2 x[PER][R];
   float2 w[PER][R];
 #pragma unroll
@@ -134,9 +150,12 @@ __device__ __forceinline__ void stockham_pass(float2* __restrict__ s, const floa
     if (NB % NT == 0 || b < NB) {
       const int c = b % C, i = b / C;
       const int k = i & (P - 1);
-      // inputs NR * C elements apart: one padded address and constant offsets
-      // when the stride is a whole number of pad groups
-      if constexpr ((NR * C) % 16 == 0) {
+      if constexpr (LOAD) {
+#pragma unroll
+        for (int j = 0; j < R; ++j) x[q][j] = ld(i + j * NR, c);
+      } else if constexpr ((NR * C) % 16 == 0) {
+        // inputs NR * C elements apart: one padded address and constant
+        // offsets when the stride is a whole number of pad groups
         const int p0 = pidx(i * C + c);
 #pragma unroll
         for (int j = 0; j < R; ++j) x[q][j] = s[p0 + j * pidx(NR * C)];
@@ -156,7 +175,7 @@ __device__ __forceinline__ void stockham_pass(float2* __restrict__ s, const floa
       }
     }
   }
-  __syncthreads();
+  if constexpr (!LOAD) __syncthreads();
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int b = tid + q * NT;
@@ -173,7 +192,10 @@ __device__ __forceinline__ void stockham_pass(float2* __restrict__ s, const floa
       }
       Dft<R, DIR>::run(x[q]);
       const int base = (i - k) * R + k;
-      if constexpr ((P * C) % 16 == 0) {
+      if constexpr (STORE) {
+#pragma unroll
+        for (int j = 0; j < R; ++j) st(base + j * P, c, x[q][j]);
+      } else if constexpr ((P * C) % 16 == 0) {
         const int p0 = pidx(base * C + c);
 #pragma unroll
         for (int j = 0; j < R; ++j) s[p0 + j * pidx(P * C)] = x[q][j];
@@ -183,22 +205,53 @@ __device__ __forceinline__ void stockham_pass(float2* __restrict__ s, const floa
       }
     }
   }
+  if constexpr (STORE) post();
   __syncthreads();
 }
+
+template <int LOGN, int C, int NT, int DIR, int R, int P>
+__device__ __forceinline__ void stockham_pass(float2* __restrict__ s, const float2* __restrict__ tw, int tid) {
+  stockham_pass_io<LOGN, C, NT, DIR, R, P, false, false>(s, tw, tid, NoIO{}, NoIO{}, NoIO{});
+}
+
+// Radix-8 passes (a radix-4 or radix-2 tail) from P on, REM bits left; the
+// first one may read from the loader and the last one write to the store.
+template <int LOGN, int C, int NT, int DIR, int P, int REM, bool LOAD, bool STORE>
+struct FftPassesIO {
+  template <class Ld, class St, class Post>
+  static __device__ __forceinline__ void run(float2* s, const float2* tw, int tid, const Ld& ld, const St& st,
+                                             const Post& post) {
+    constexpr int LR = REM >= 3 ? 3 : REM;
+    constexpr int R = 1 << LR;
+    constexpr bool LAST = REM == LR;
+    stockham_pass_io<LOGN, C, NT, DIR, R, P, LOAD, STORE && LAST>(s, tw, tid, ld, st, post);
+    FftPassesIO<LOGN, C, NT, DIR, P * R, REM - LR, false, STORE>::run(s, tw, tid, ld, st, post);
+  }
+};
+template <int LOGN, int C, int NT, int DIR, int P, bool LOAD, bool STORE>
+struct FftPassesIO<LOGN, C, NT, DIR, P, 0, LOAD, STORE> {
+  template <class Ld, class St, class Post>
+  static __device__ __forceinline__ void run(float2*, const float2*, int, const Ld&, const St&, const Post&) {}
+};
 
 template <int LOGN, int C, int NT, int DIR, int P, int REM>
 struct FftPasses {
   static __device__ __forceinline__ void run(float2* s, const float2* tw, int tid) {
-    constexpr int LR = REM >= 3 ? 3 : REM;
-    constexpr int R = 1 << LR;
-    stockham_pass<LOGN, C, NT, DIR, R, P>(s, tw, tid);
-    FftPasses<LOGN, C, NT, DIR, P * R, REM - LR>::run(s, tw, tid);
+    FftPassesIO<LOGN, C, NT, DIR, P, REM, false, false>::run(s, tw, tid, NoIO{}, NoIO{}, NoIO{});
   }
 };
-template <int LOGN, int C, int NT, int DIR, int P>
-struct FftPasses<LOGN, C, NT, DIR, P, 0> {
-  static __device__ __forceinline__ void run(float2*, const float2*, int) {}
-};
+
+// FFT of C interleaved transforms of length 2^LOGN whose first pass reads
+// ld(t, c) (LOAD) and whose last pass hands the outputs, in natural order, to
+// st(t, c, v) and then runs post() (STORE); the passes in between use LDS as
+// fft_lds does.  Entered by all NT threads; with LOAD the twiddle table only
+// has to be in LDS by the end of the first pass (which has no twiddles), so
+// its staging needs no barrier of its own.  Ends with a barrier.
+template <int LOGN, int C, int NT, int DIR, bool LOAD, bool STORE, class Ld, class St, class Post>
+__device__ __forceinline__ void fft_io(float2* s, const float2* tw, int tid, const Ld& ld, const St& st,
+                                       const Post& post) {
+  FftPassesIO<LOGN, C, NT, DIR, 1, LOGN, LOAD, STORE>::run(s, tw, tid, ld, st, post);
+}
 
 // Unnormalised in-LDS FFT of C interleaved transforms of length 2^LOGN,
 // kernel exp(DIR * 2 pi i t k / N).  tw is the LDS two-level twiddle table of

@@ -106,21 +106,19 @@ __device__ __forceinline__ void t1_rows_body(const RowArgs& a, int bid, int) {
   load_tw2<LOGN, NT>(tw, tw_for(a.tw, LOGN));
   const int r0 = bid * C;
   const int L = g.L, s0 = g.s0;
-  for (int e = threadIdx.x; e < C * NF; e += NT) {
-    const int c = e / NF, t = e % NF;
+  // the first pass reads the support rows (zero outside), the last one
+  // writes the kept k_x; loads are clamped and selected, never branched over
+  const auto ld = [&](int t, int c) -> float2 {
     const int row = r0 + c, i = t - s0;
-    float2 v = czero();
-    if (row < L && i >= 0 && i < L) v = fine[(size_t)row * L + i];
-    s[pidx(t * C + c)] = v;
-  }
-  __syncthreads();
-  fft_lds<LOGN, C, NT, -1>(s, tw);
-  for (int e = threadIdx.x; e < C * NP; e += NT) {
-    const int c = e / NP, a = e % NP;
-    const int row = r0 + c, kx = a - NP / 2;
-    if (row < L && in_band(kx, g.kxlo, g.kxhi))
-      T[(size_t)row * NP + a] = cscale(s[pidx(((kx + NF) & (NF - 1)) * C + c)], dinv[a]);
-  }
+    const float2 v = fine[(size_t)min(row, L - 1) * L + min(max(i, 0), L - 1)];
+    return (row < L && i >= 0 && i < L) ? v : czero();
+  };
+  const auto st = [&](int t, int c, float2 v) {
+    const int row = r0 + c, kx = t < NF / 2 ? t : t - NF;
+    if (row < L && kx >= -NP / 2 && kx < NP / 2 && in_band(kx, g.kxlo, g.kxhi))
+      T[(size_t)row * NP + kx + NP / 2] = cscale(v, dinv[kx + NP / 2]);
+  };
+  fft_io<LOGN, C, NT, -1, true, true>(s, tw, (int)threadIdx.x, ld, st, NoIO{});
 }
 
 // Column passes that change length: a forward FFT of one length and an
@@ -165,49 +163,45 @@ __device__ __forceinline__ void t1_cols_body(const ColArgs& a, int bid, int nbid
   load_tw2<LOGN, NT>(twf, tw_for(twall, LOGN));
   load_tw2<LOGNP, NT>(twp, tw_for(twall, LOGNP));
   const int L = g.L, s0 = g.s0;
-  for (int e = threadIdx.x; e < C * NF; e += NT) {
-    const int t = e / C, c = e % C;
+  // forward transform: the first pass reads the support rows of T, the last
+  // one applies H Rect / psihat / N'^2 to the modes of K'' and writes them,
+  // embedded in K, as the inverse transform's input (the rest of K zeroed)
+  const auto ld = [&](int t, int c) -> float2 {
     const int i = t - s0;
-    float2 v = czero();
-    if (i >= 0 && i < L && in_band(kx0 + c, g.kxlo, g.kxhi)) v = T[(size_t)i * NPF + a0 + c];
-    s[pidx(e)] = v;
-  }
-  __syncthreads();
-  fft_lds<LOGN, C, NT, -1>(s, twf);
-  constexpr int PER = (C * NP + NT - 1) / NT;
-  float2 v[PER];
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int e = threadIdx.x + q * NT;
-    if (e < C * NP) {
-      const int ay = e / C, c = e % C;
-      const int ky = ay - NP / 2, kx = kx0 + c;
-      float2 x = czero();
-      if (ky >= -NPF / 2 && ky < NPF / 2 && in_band(kx, g.kxlo, g.kxhi) && in_band(ky, g.kylo, g.kyhi)) {
-        const float2 h = transfer_at(sp, NP, kx, ky);
-        x = cmul(s[pidx(((ky + NF) & (NF - 1)) * C + c)], h);
-        x = cscale(x, sp.dinv[ky + NPF / 2] * sp.scale);
-      }
-      v[q] = x;
+    const float2 v = T[(size_t)min(max(i, 0), L - 1) * NPF + a0 + c];
+    return (i >= 0 && i < L && in_band(kx0 + c, g.kxlo, g.kxhi)) ? v : czero();
+  };
+  const auto mid = [&](int t, int c, float2 v) {
+    const int ky = t < NF / 2 ? t : t - NF, kx = kx0 + c;
+    if (ky < -NPF / 2 || ky >= NPF / 2) return;  // outside K''
+    float2 x = czero();
+    if (in_band(kx, g.kxlo, g.kxhi) && in_band(ky, g.kylo, g.kyhi)) {
+      x = cmul(v, transfer_at(sp, NP, kx, ky));
+      x = cscale(x, sp.dinv[ky + NPF / 2] * sp.scale);
     }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int e = threadIdx.x + q * NT;
-    if (e < C * NP) s[pidx(e)] = v[q];
-  }
-  __syncthreads();
-  fft_lds<LOGNP, C, NT, +1>(s, twp, opaque_tid());
-  for (int e = threadIdx.x; e < C * NP; e += NT) {
-    const int by = e / C, c = e % C;
+    s[pidx((ky + NP / 2) * C + c)] = x;
+  };
+  const auto gap = [&]() {
+    if constexpr (NPF < NP) {
+      // K outside K'': [0, (N' - N'')/2) and [(N' + N'')/2, N')
+      constexpr int H = (NP - NPF) / 2;
+      for (int e = threadIdx.x; e < 2 * H * C; e += NT) {
+        const int u = e / C, c = e % C;
+        const int ay = u < H ? u : u + NPF;
+        s[pidx(ay * C + c)] = czero();
+      }
+    }
+  };
+  fft_io<LOGN, C, NT, -1, true, true>(s, twf, (int)threadIdx.x, ld, mid, gap);
+  // inverse transform along y; the last pass writes V with the (-1)^n_y sign
+  const auto st = [&](int by, int c, float2 x) {
     const int kx = kx0 + c;
     if (in_band(kx, g.kxlo, g.kxhi)) {
-      float2 x = s[pidx(e)];
       if (by & 1) x = make_float2(-x.x, -x.y);
       V[(size_t)by * NP + kx + NP / 2] = x;
     }
-  }
+  };
+  fft_io<LOGNP, C, NT, +1, false, true>(s, twp, opaque_tid(), NoIO{}, st, NoIO{});
 }
 
 // Rows of V -> N'-point inverse FFT along x -> times (-1)^n_x -> plane
@@ -226,20 +220,14 @@ __device__ __forceinline__ void t1_rows_inv_body(const RowArgs& a, int bid, int)
   const int nrows = g.crop ? g.N : NP;
   const int rowoff = g.crop ? g.N / 2 : 0;
   const int r0 = bid * C;
-  for (int e = threadIdx.x; e < C * NP; e += NT) {
-    const int c = e / NP, a = e % NP;
+  const auto ld = [&](int a, int c) -> float2 {
     const int r = r0 + c, kx = a - NP / 2;
-    float2 v = czero();
-    if (r < nrows && in_band(kx, g.kxlo, g.kxhi)) v = V[(size_t)(r + rowoff) * NP + a];
-    s[pidx(a * C + c)] = v;
-  }
-  __syncthreads();
-  fft_lds<LOGNP, C, NT, +1>(s, tw);
-  for (int e = threadIdx.x; e < C * NP; e += NT) {
-    const int c = e / NP, bx = e % NP;
+    const float2 v = V[(size_t)(min(r, nrows - 1) + rowoff) * NP + a];
+    return (r < nrows && in_band(kx, g.kxlo, g.kxhi)) ? v : czero();
+  };
+  const auto st = [&](int bx, int c, float2 x) {
     const int r = r0 + c;
-    if (r >= nrows) continue;
-    float2 x = s[pidx(bx * C + c)];
+    if (r >= nrows) return;
     if (bx & 1) x = make_float2(-x.x, -x.y);
     if (g.crop) {
       const int ox = bx - g.N / 2;
@@ -247,7 +235,8 @@ __device__ __forceinline__ void t1_rows_inv_body(const RowArgs& a, int bid, int)
     } else {
       out[(size_t)r * NP + bx] = x;
     }
-  }
+  };
+  fft_io<LOGNP, C, NT, +1, true, true>(s, tw, (int)threadIdx.x, ld, st, NoIO{});
 }
 
 // ----------------------------------------------------------------- type 2
@@ -267,25 +256,21 @@ __device__ __forceinline__ void t2_rows_body(const RowArgs& a, int bid, int) {
   load_tw2<LOGNP, NT>(tw, tw_for(a.tw, LOGNP));
   const int Nin = g.Nin;
   const int r0 = bid * C;
-  for (int e = threadIdx.x; e < C * NP; e += NT) {
-    const int c = e / NP, t = e % NP;
-    const int r = r0 + c;
-    const int mx = t < NP / 2 ? t : t - NP;
-    float2 v = czero();
-    if (r < Nin && mx >= -Nin / 2 && mx < Nin / 2) v = u1[(size_t)r * Nin + mx + Nin / 2];
-    s[pidx(t * C + c)] = v;
-  }
-  __syncthreads();
-  fft_lds<LOGNP, C, NT, -1>(s, tw);
-  for (int e = threadIdx.x; e < C * NP; e += NT) {
-    const int c = e / NP, a = e % NP;
-    const int r = r0 + c, kx = a - NP / 2;
+  const auto ld = [&](int t, int c) -> float2 {
+    const int r = r0 + c, mx = t < NP / 2 ? t : t - NP;
+    const int mc = min(max(mx, -Nin / 2), Nin / 2 - 1);
+    const float2 v = u1[(size_t)min(r, Nin - 1) * Nin + mc + Nin / 2];
+    return (r < Nin && mx >= -Nin / 2 && mx < Nin / 2) ? v : czero();
+  };
+  const auto st = [&](int t, int c, float2 v) {
+    const int r = r0 + c, kx = t < NP / 2 ? t : t - NP;
     if (r < Nin && in_band(kx, g.kxlo, g.kxhi)) {
-      float2 x = cscale(s[pidx(((kx + NP) & (NP - 1)) * C + c)], dinv[a]);
+      float2 x = cscale(v, dinv[kx + NP / 2]);
       if (kx & 1) x = make_float2(-x.x, -x.y);
-      T[(size_t)r * NP + a] = x;
+      T[(size_t)r * NP + kx + NP / 2] = x;
     }
-  }
+  };
+  fft_io<LOGNP, C, NT, -1, true, true>(s, tw, (int)threadIdx.x, ld, st, NoIO{});
 }
 
 // Columns of T (Nin rows, N' columns k_x + N'/2) -> N'-point FFT along y ->
@@ -313,57 +298,41 @@ __device__ __forceinline__ void t2_cols_body(const ColArgs& a, int bid, int nbid
   load_tw2<LOGNP, NT>(twp, tw_for(twall, LOGNP));
   load_tw2<LOGN, NT>(twf, tw_for(twall, LOGN));
   const int Nin = g.Nin;
-  for (int e = threadIdx.x; e < C * NP; e += NT) {
-    const int t = e / C, c = e % C;
+  // forward transform along y: the first pass reads the Nin rows of T
+  // (circularly zero-padded), the last one applies H Rect (-1)^k_y / psihat /
+  // N'^2 to the modes of K'' and writes them into the nf-point spectrum of the
+  // inverse transform, whose gap it zeroes
+  const auto ld = [&](int t, int c) -> float2 {
     const int my = t < NP / 2 ? t : t - NP;
-    float2 v = czero();
-    if (my >= -Nin / 2 && my < Nin / 2 && in_band(kx0 + c, g.kxlo, g.kxhi))
-      v = T[(size_t)(my + Nin / 2) * NP + a0 + c];
-    s[pidx(e)] = v;
-  }
-  __syncthreads();
-  fft_lds<LOGNP, C, NT, -1>(s, twp);
-  // the modes of K'' (position ky + N''/2) into registers
-  constexpr int PER = (C * NPF + NT - 1) / NT;
-  float2 v[PER];
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int e = threadIdx.x + q * NT;
-    if (e < C * NPF) {
-      const int ay = e / C, c = e % C;
-      const int ky = ay - NPF / 2, kx = kx0 + c;
-      float2 x = czero();
-      if (in_band(kx, g.kxlo, g.kxhi) && in_band(ky, g.kylo, g.kyhi)) {
-        const float2 h = transfer_at(sp, NP, kx, ky);
-        x = cmul(s[pidx(((ky + NP) & (NP - 1)) * C + c)], h);
-        x = cscale(x, sp.dinv[ay] * sp.scale * ((ky & 1) ? -1.0f : 1.0f));
-      }
-      v[q] = x;
+    const int mc = min(max(my, -Nin / 2), Nin / 2 - 1);
+    const float2 v = T[(size_t)(mc + Nin / 2) * NP + a0 + c];
+    return (my >= -Nin / 2 && my < Nin / 2 && in_band(kx0 + c, g.kxlo, g.kxhi)) ? v : czero();
+  };
+  const auto mid = [&](int t, int c, float2 v) {
+    const int ky = t < NP / 2 ? t : t - NP, kx = kx0 + c;
+    if (ky < -NPF / 2 || ky >= NPF / 2) return;  // outside K''
+    float2 x = czero();
+    if (in_band(kx, g.kxlo, g.kxhi) && in_band(ky, g.kylo, g.kyhi)) {
+      x = cmul(v, transfer_at(sp, NP, kx, ky));
+      x = cscale(x, sp.dinv[ky + NPF / 2] * sp.scale * ((ky & 1) ? -1.0f : 1.0f));
     }
-  }
-  __syncthreads();
-  // the gap between the two halves of K'' inside the nf-point spectrum is zero
-  for (int e = threadIdx.x; e < C * (NF - NPF); e += NT) {
-    const int t = NPF / 2 + e / C, c = e % C;
-    s[pidx(t * C + c)] = czero();
-  }
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int e = threadIdx.x + q * NT;
-    if (e < C * NPF) {
-      const int ay = e / C, c = e % C;
-      const int ky = ay - NPF / 2;
-      s[pidx(((ky + NF) & (NF - 1)) * C + c)] = v[q];
+    s[pidx(((ky + NF) & (NF - 1)) * C + c)] = x;
+  };
+  const auto gap = [&]() {
+    // the gap between the two halves of K'' inside the nf-point spectrum
+    for (int e = threadIdx.x; e < C * (NF - NPF); e += NT) {
+      const int t = NPF / 2 + e / C, c = e % C;
+      s[pidx(t * C + c)] = czero();
     }
-  }
-  __syncthreads();
-  fft_lds<LOGN, C, NT, +1>(s, twf, opaque_tid());
+  };
+  fft_io<LOGNP, C, NT, -1, true, true>(s, twp, (int)threadIdx.x, ld, mid, gap);
+  // inverse nf-point transform; the last pass keeps the support rows
   const int L = g.L, s0 = g.s0;
-  for (int e = threadIdx.x; e < C * L; e += NT) {
-    const int i = e / C, c = e % C;
-    const int kx = kx0 + c;
-    if (in_band(kx, g.kxlo, g.kxhi)) V[(size_t)i * NPF + kx + NPF / 2] = s[pidx((s0 + i) * C + c)];
-  }
+  const auto st = [&](int t, int c, float2 v) {
+    const int i = t - s0, kx = kx0 + c;
+    if (i >= 0 && i < L && in_band(kx, g.kxlo, g.kxhi)) V[(size_t)i * NPF + kx + NPF / 2] = v;
+  };
+  fft_io<LOGN, C, NT, +1, false, true>(s, twf, opaque_tid(), NoIO{}, st, NoIO{});
 }
 
 // Support rows of V -> embed k_x into nf -> inverse nf-point FFT along x ->
@@ -381,23 +350,20 @@ __device__ __forceinline__ void t2_rows_inv_body(const RowArgs& a, int bid, int)
   load_tw2<LOGN, NT>(tw, tw_for(a.tw, LOGN));
   const int L = g.L, s0 = g.s0;
   const int r0 = bid * C;
-  for (int e = threadIdx.x; e < C * NF; e += NT) {
-    const int c = e / NF, t = e % NF;
+  // the first pass reads the row's k_x into the nf-point spectrum (the gap
+  // zero), the last one keeps the support columns
+  const auto ld = [&](int t, int c) -> float2 {
     const int r = r0 + c;
-    int kx = NP;  // marks the zero gap
-    if (t < NP / 2) kx = t;
-    else if (t >= NF - NP / 2) kx = t - NF;
-    float2 v = czero();
-    if (r < L && kx != NP && in_band(kx, g.kxlo, g.kxhi)) v = V[(size_t)r * NP + kx + NP / 2];
-    s[pidx(t * C + c)] = v;
-  }
-  __syncthreads();
-  fft_lds<LOGN, C, NT, +1>(s, tw);
-  for (int e = threadIdx.x; e < C * L; e += NT) {
-    const int c = e / L, i = e % L;
-    const int r = r0 + c;
-    if (r < L) fine[(size_t)r * L + i] = s[pidx((s0 + i) * C + c)];
-  }
+    const bool lo = t < NP / 2, hi = t >= NF - NP / 2;
+    const int kx = lo ? t : hi ? t - NF : 0;
+    const float2 v = V[(size_t)min(r, L - 1) * NP + kx + NP / 2];
+    return (r < L && (lo || hi) && in_band(kx, g.kxlo, g.kxhi)) ? v : czero();
+  };
+  const auto st = [&](int t, int c, float2 v) {
+    const int r = r0 + c, i = t - s0;
+    if (r < L && i >= 0 && i < L) fine[(size_t)r * L + i] = v;
+  };
+  fft_io<LOGN, C, NT, +1, true, true>(s, tw, (int)threadIdx.x, ld, st, NoIO{});
 }
 
 // ----------------------------------------------------------------- type 3
