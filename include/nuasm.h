@@ -431,6 +431,11 @@ const char* nuasm_last_error(void);
  * (and a plan whose set_points failed usable after a later successful one). */
 nuasm_status nuasm_debug_fail_alloc(int64_t k);
 
+/* Testing aid: the bytes of device memory and of pinned host memory the
+ * library holds at this moment (every plan, batch and per-device table), so
+ * that a test can check that a call sequence gave back all it allocated. */
+nuasm_status nuasm_debug_live_bytes(int64_t* device_bytes, int64_t* host_bytes);
+
 /* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
 int32_t nuasm_version(void);
 

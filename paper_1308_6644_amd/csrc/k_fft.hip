@@ -403,34 +403,32 @@ k_t3_cols(const float2* __restrict__ T, float2* __restrict__ V, GridGeom g, Spec
   float2* twf = s + Cfg::DATA;
   load_tw2<LOGN, NT>(twf, tw_for(twall, LOGN));
   const int L = g.L, s0 = g.s0;
-  for (int e = threadIdx.x; e < C * NF; e += NT) {
-    const int t = e / C, c = e % C;
+  // forward transform: the first pass reads the support rows of T, the last
+  // one scales every mode in place (zero outside K and the band)
+  const auto ld = [&](int t, int c) -> float2 {
     const int i = t - s0;
-    float2 v = czero();
-    if (i >= 0 && i < L && in_band(kx0 + c, g.kxlo, g.kxhi)) v = T[(size_t)i * NP + a0 + c];
-    s[pidx(e)] = v;
-  }
-  __syncthreads();
-  fft_lds<LOGN, C, NT, -1>(s, twf);
-  for (int e = threadIdx.x; e < C * NF; e += NT) {
-    const int t = e / C, c = e % C;
+    const float2 v = T[(size_t)min(max(i, 0), L - 1) * NP + a0 + c];
+    return (i >= 0 && i < L && in_band(kx0 + c, g.kxlo, g.kxhi)) ? v : czero();
+  };
+  const auto mid = [&](int t, int c, float2 v) {
     const int ky = t < NF / 2 ? t : t - NF;
     const int kx = kx0 + c;
     float2 x = czero();
     if (ky >= -NP / 2 && ky < NP / 2 && in_band(kx, g.kxlo, g.kxhi) && in_band(ky, g.kylo, g.kyhi)) {
       const float2 h = transfer_at(sp, g.Np, kx, ky);
       const float dy = sp.dinv[ky + NP / 2];
-      x = cmul(s[pidx(e)], h);
+      x = cmul(v, h);
       x = cscale(x, dy * dy * sp.dinv[kx + NP / 2] * sp.scale);
     }
-    s[pidx(e)] = x;
-  }
-  __syncthreads();
-  fft_lds<LOGN, C, NT, +1>(s, twf, opaque_tid());
-  for (int e = threadIdx.x; e < C * L; e += NT) {
-    const int i = e / C, c = e % C;
-    if (in_band(kx0 + c, g.kxlo, g.kxhi)) V[(size_t)i * NP + a0 + c] = s[pidx((s0 + i) * C + c)];
-  }
+    s[pidx(t * C + c)] = x;
+  };
+  fft_io<LOGN, C, NT, -1, true, true>(s, twf, (int)threadIdx.x, ld, mid, NoIO{});
+  // inverse transform; the last pass keeps the support rows
+  const auto st = [&](int t, int c, float2 v) {
+    const int i = t - s0;
+    if (i >= 0 && i < L && in_band(kx0 + c, g.kxlo, g.kxhi)) V[(size_t)i * NP + a0 + c] = v;
+  };
+  fft_io<LOGN, C, NT, +1, false, true>(s, twf, opaque_tid(), NoIO{}, st, NoIO{});
 }
 
 // ----------------------------------------------------------- test kernels
@@ -445,18 +443,16 @@ k_fft_rows(const float2* __restrict__ in, float2* __restrict__ out, int64_t batc
   float2* tw = s + Cfg::DATA;
   load_tw2<LOGN, NT>(tw, tw_for(twall, LOGN));
   const int64_t r0 = (int64_t)blockIdx.x * C;
-  for (int e = threadIdx.x; e < C * N; e += NT) {
-    const int c = e / N, t = e % N;
+  const auto ld = [&](int t, int c) -> float2 {
     const int64_t r = r0 + c;
-    s[pidx(t * C + c)] = r < batch ? in[r * N + t] : czero();
-  }
-  __syncthreads();
-  fft_lds<LOGN, C, NT, DIR>(s, tw);
-  for (int e = threadIdx.x; e < C * N; e += NT) {
-    const int c = e / N, t = e % N;
+    const float2 v = in[(r < batch ? r : batch - 1) * N + t];
+    return r < batch ? v : czero();
+  };
+  const auto st = [&](int t, int c, float2 v) {
     const int64_t r = r0 + c;
-    if (r < batch) out[r * N + t] = s[pidx(t * C + c)];
-  }
+    if (r < batch) out[r * N + t] = v;
+  };
+  fft_io<LOGN, C, NT, DIR, true, true>(s, tw, (int)threadIdx.x, ld, st, NoIO{});
 }
 
 __global__ void k_transfer_table(GridGeom g, Spectral sp, float2* __restrict__ out) {

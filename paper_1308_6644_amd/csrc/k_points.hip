@@ -369,7 +369,22 @@ __device__ __forceinline__ void bin_scatter_body(const BinArgs& a, int bid, int)
   const int T = g.TX * g.TX, TW = (T + 1) / 2;
   const int* myoff = off + (size_t)bid * (T + 1);
   if (CURSORS) {
-    for (int b = threadIdx.x; b < T; b += kBinThreads) sh[b] = (unsigned)(bin_base[b] + myoff[b]);
+    // the loads of eight bins per thread in flight together (clamped
+    // addresses), then the LDS writes
+    constexpr int NB = 8;
+    for (int b0 = 0; b0 < T; b0 += kBinThreads * NB) {
+      unsigned v[NB];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int b = min(b0 + (int)threadIdx.x + u * kBinThreads, T - 1);
+        v[u] = (unsigned)(bin_base[b] + myoff[b]);
+      }
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int b = b0 + (int)threadIdx.x + u * kBinThreads;
+        if (b < T) sh[b] = v[u];
+      }
+    }
   } else {
     for (int e = threadIdx.x; e < TW; e += kBinThreads) sh[e] = 0u;
   }
@@ -936,23 +951,31 @@ __device__ __forceinline__ void spread_mfma_body(const SpreadArgs& a, int bid, i
 
 // Sum the partial tiles of every multi-chunk bin, in chunk order (the bin's
 // chunks hold consecutive scratch slots, the first one's in its table entry).
-// Each workgroup sums 1024 cells of one bin: (tile / 32)^2 workgroups per bin.
+// Each workgroup sums 256 cells of one bin, a cell per thread:
+// (tile / 16)^2 workgroups per bin.  The partial tiles are read four at a
+// time (loads in flight together) and added in chunk order.
 __device__ __forceinline__ void spread_reduce_body(const SpreadReduceArgs& a, int bid, int) {
   const int tl = a.tile_log, tile = 1 << tl, cells = tile * tile;
-  const int parts = cells >> 10;
+  const int parts = cells >> 8;
   const int mb = bid / parts, part = bid - mb * parts;
   if (mb >= a.nmulti[0]) return;
   const int bin = a.multi[mb];
   const int c0 = a.bin_chunk0[bin], nb = a.bin_nchunk[bin];
   const int slot0 = a.chunks[c0].w;
   const int bx = bin % a.TX, by = bin / a.TX;
-  for (int e = (part << 10) + threadIdx.x; e < ((part + 1) << 10); e += 256) {
-    float2 s = czero();
-    for (int q = 0; q < nb; ++q) s = cadd(s, a.scratch[(size_t)(slot0 + q) * cells + e]);
-    const int yy = e >> tl, xx = e & (tile - 1);
-    const int gy = (by << tl) + yy, gx = (bx << tl) + xx;
-    if (gy < a.L && gx < a.L) a.grid[(size_t)gy * a.L + gx] = s;
+  const int e = (part << 8) + threadIdx.x;
+  const float2* p = a.scratch + (size_t)slot0 * cells + e;
+  float2 s = czero();
+  int q = 0;
+  for (; q + 4 <= nb; q += 4) {
+    const float2 v0 = p[(size_t)q * cells], v1 = p[(size_t)(q + 1) * cells];
+    const float2 v2 = p[(size_t)(q + 2) * cells], v3 = p[(size_t)(q + 3) * cells];
+    s = cadd(cadd(cadd(cadd(s, v0), v1), v2), v3);
   }
+  for (; q < nb; ++q) s = cadd(s, p[(size_t)q * cells]);
+  const int yy = e >> tl, xx = e & (tile - 1);
+  const int gy = (by << tl) + yy, gx = (bx << tl) + xx;
+  if (gy < a.L && gx < a.L) a.grid[(size_t)gy * a.L + gx] = s;
 }
 
 // --------------------------------------------------------- interpolation
@@ -976,10 +999,21 @@ __device__ __forceinline__ void interp_body(const InterpArgs& a, int bid, int) {
   const int bin = ch.x, start = ch.y, n = ch.z;
   const int bx = bin % a.TX, by = bin / a.TX;
   const int t = threadIdx.x;
-  for (int e = t; e < RS * RS; e += NT) {
-    const int yy = e / RS, xx = e % RS;
-    const int gy = by * TILE + yy, gx = bx * TILE + xx;
-    sg[e] = (gy < a.L && gx < a.L) ? a.grid[(size_t)gy * a.L + gx] : czero();
+  {
+    // every load of the staging first (clamped addresses, values selected
+    // afterwards), then the LDS writes: one memory latency, not one per element
+    constexpr int NS = (RS * RS + NT - 1) / NT;
+    float2 v[NS];
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      const int e = min(t + u * NT, RS * RS - 1);
+      const int gy = by * TILE + e / RS, gx = bx * TILE + e % RS;
+      v[u] = a.grid[(size_t)min(gy, a.L - 1) * a.L + min(gx, a.L - 1)];
+      if (gy >= a.L || gx >= a.L) v[u] = czero();
+    }
+#pragma unroll
+    for (int u = 0; u < NS; ++u)
+      if (t + u * NT < RS * RS) sg[t + u * NT] = v[u];
   }
   __syncthreads();
   const float blog = a.beta * 1.4426950408889634f;

@@ -13,6 +13,7 @@
 #include <atomic>
 #include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "group.h"
@@ -72,12 +73,36 @@ bool inject_alloc_failure() {
   return false;
 }
 
+// Every live allocation of the library with its size (device and pinned
+// host apart), so that a test can check that what a call sequence allocated
+// was all given back (nuasm_debug_live_bytes).  Frees go through dev_free /
+// host_free.
+std::mutex g_live_mutex;
+std::unordered_map<void*, size_t> g_live[2];  // 0: device, 1: pinned host
+int64_t g_live_bytes[2] = {0, 0};
+
+void live_add(int kind, void* p, size_t bytes) {
+  std::lock_guard<std::mutex> lk(g_live_mutex);
+  g_live[kind][p] = bytes;
+  g_live_bytes[kind] += (int64_t)bytes;
+}
+
+void live_remove(int kind, void* p) {
+  std::lock_guard<std::mutex> lk(g_live_mutex);
+  auto it = g_live[kind].find(p);
+  if (it == g_live[kind].end()) return;
+  g_live_bytes[kind] -= (int64_t)it->second;
+  g_live[kind].erase(it);
+}
+
 hipError_t dev_malloc(void** p, size_t bytes) {
   if (inject_alloc_failure()) {
     *p = nullptr;
     return hipErrorOutOfMemory;
   }
-  return hipMalloc(p, bytes);
+  const hipError_t e = hipMalloc(p, bytes);
+  if (e == hipSuccess) live_add(0, *p, bytes);
+  return e;
 }
 
 hipError_t host_malloc(void** p, size_t bytes) {
@@ -85,7 +110,21 @@ hipError_t host_malloc(void** p, size_t bytes) {
     *p = nullptr;
     return hipErrorOutOfMemory;
   }
-  return hipHostMalloc(p, bytes, hipHostMallocDefault);
+  const hipError_t e = hipHostMalloc(p, bytes, hipHostMallocDefault);
+  if (e == hipSuccess) live_add(1, *p, bytes);
+  return e;
+}
+
+hipError_t dev_free(void* p) {
+  if (!p) return hipSuccess;
+  live_remove(0, p);
+  return hipFree(p);
+}
+
+hipError_t host_free(void* p) {
+  if (!p) return hipSuccess;
+  live_remove(1, p);
+  return hipHostFree(p);
 }
 
 // ------------------------------------------------------- twiddle tables
@@ -112,7 +151,7 @@ nuasm_status twiddles_for_device(int dev, const float2** out) {
     HIP_TRY(dev_malloc((void**)&d, sizeof(float2) * total), "hipMalloc(twiddles)");
     hipError_t e = hipMemcpy(d, h.data(), sizeof(float2) * total, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
-      (void)hipFree(d);
+      (void)dev_free(d);
       return hip_fail(e, "hipMemcpy(twiddles)");
     }
     g_tw[dev] = d;
@@ -307,7 +346,7 @@ hipError_t dalloc(nuasm_plan_s* pl, T** p, size_t n) {
 
 void release(nuasm_plan_s* pl) {
   auto f = [](void* p) {
-    if (p) (void)hipFree(p);
+    if (p) (void)dev_free(p);
   };
   // buffers carved from a caller's workspace are not the plan's to free
   auto fo = [&](void* p) {
@@ -334,7 +373,7 @@ void release(nuasm_plan_s* pl) {
     fo(q.hist);
     fo(q.hoff);
     f(q.gbuf);
-    if (q.host_stat) (void)hipHostFree(q.host_stat);
+    if (q.host_stat) (void)host_free(q.host_stat);
     q = PointSet{};
   }
   if (pl->handoff) (void)hipEventDestroy(pl->handoff);
@@ -517,7 +556,7 @@ void carve_workspace(nuasm_plan_s* pl) {
 void free_owned_buffers(nuasm_plan_s* pl) {
   auto f = [&](void* p, size_t b) {
     if (p && !pl->ws) {
-      (void)hipFree(p);
+      (void)dev_free(p);
       pl->bytes -= b;
     }
   };
@@ -585,7 +624,7 @@ void free_bin_arrays(nuasm_plan_s* pl, PointSet& q) {
   const size_t T = (size_t)pl->T;
   auto f = [&](void* p, size_t b) {
     if (p) {
-      (void)hipFree(p);
+      (void)dev_free(p);
       pl->bytes -= b;
     }
   };
@@ -598,7 +637,7 @@ void free_bin_arrays(nuasm_plan_s* pl, PointSet& q) {
   f(q.wg_sum, sizeof(int) * (size_t)bin_scan_workgroups(pl->T) * kBinPre);
   f(q.nch, sizeof(int) * 8);
   q.counts = q.cursor = q.sp_first = q.sp_n = q.multi = q.bin_pre = q.wg_sum = q.nch = nullptr;
-  if (q.host_stat) (void)hipHostFree(q.host_stat);
+  if (q.host_stat) (void)host_free(q.host_stat);
   q.host_stat = nullptr;
 }
 
@@ -626,27 +665,27 @@ nuasm_status ensure_points_capacity(nuasm_plan_s* pl, PointSet& q, int64_t M) {
   if (cap * 4 > (int64_t)INT32_MAX) return fail(NUASM_ERR_UNSUPPORTED, "too many points (4 M must fit in int32)");
   HIP_TRY(hipStreamSynchronize(pl->stream), "hipStreamSynchronize");
   if (q.recs) {
-    (void)hipFree(q.recs);
+    (void)dev_free(q.recs);
     pl->bytes -= sizeof(BinRec) * 4 * q.rec_cap;
     q.recs = nullptr;
   }
 
   if (q.sp_chunks) {
-    (void)hipFree(q.sp_chunks);
-    (void)hipFree(q.ip_chunks);
+    (void)dev_free(q.sp_chunks);
+    (void)dev_free(q.ip_chunks);
     pl->bytes -= 2 * sizeof(int4) * q.chunk_cap;
     q.sp_chunks = q.ip_chunks = nullptr;
   }
   if (q.scratch) {
-    (void)hipFree(q.scratch);
+    (void)dev_free(q.scratch);
     pl->bytes -= q.scratch_bytes;
     q.scratch = nullptr;
     q.scratch_chunks = 0;
     q.scratch_bytes = 0;
   }
   if (q.hist) {
-    (void)hipFree(q.hist);
-    (void)hipFree(q.hoff);
+    (void)dev_free(q.hist);
+    (void)dev_free(q.hoff);
     pl->bytes -= (sizeof(uint16_t) + sizeof(int)) * q.hist_rows * (pl->T + 1);
     q.hist = nullptr;
     q.hoff = nullptr;
@@ -683,7 +722,7 @@ nuasm_status ensure_scratch(nuasm_plan_s* pl, PointSet& q) {
   if (pl->ws) return fail(NUASM_ERR_INVALID_ARG, "split-bin scratch exceeds the workspace");
   if (q.scratch) {
     HIP_TRY(hipStreamSynchronize(pl->stream), "hipStreamSynchronize");
-    (void)hipFree(q.scratch);
+    (void)dev_free(q.scratch);
     pl->bytes -= q.scratch_bytes;
     q.scratch = nullptr;
     q.scratch_chunks = 0;
@@ -819,7 +858,7 @@ nuasm_status bind_grid(nuasm_plan_s* pl, PointSet& q, int64_t nx, int64_t ny, do
   if (need > q.gbuf_cap) {
     HIP_TRY(hipStreamSynchronize(pl->stream), "hipStreamSynchronize");
     if (q.gbuf) {
-      (void)hipFree(q.gbuf);
+      (void)dev_free(q.gbuf);
       pl->bytes -= sizeof(float2) * q.gbuf_cap;
       q.gbuf = nullptr;
       q.gbuf_cap = 0;
@@ -880,7 +919,7 @@ nuasm_status run_spread(nuasm_plan_s* pl, PointSet& q, const float2* vals) {
     ra.L = pl->geom.L;
     ra.TX = pl->TX;
     ra.tile_log = pl->tile_log;
-    const int parts = (pl->tile / kTile) * (pl->tile / kTile);  // 1024 cells per workgroup
+    const int parts = (pl->tile / 16) * (pl->tile / 16);  // 256 cells per workgroup
     HIP_TRY(launch_spread_reduce(ra, multi_grid(pl, q) * parts, st), "launch spread_reduce");
   }
   return NUASM_OK;
@@ -1008,6 +1047,14 @@ const char* nuasm_status_string(nuasm_status s) {
 }
 
 const char* nuasm_last_error(void) { return g_last_error.c_str(); }
+
+nuasm_status nuasm_debug_live_bytes(int64_t* device_bytes, int64_t* host_bytes) {
+  if (!device_bytes || !host_bytes) return fail(NUASM_ERR_INVALID_ARG, "output pointer is NULL");
+  std::lock_guard<std::mutex> lk(g_live_mutex);
+  *device_bytes = g_live_bytes[0];
+  *host_bytes = g_live_bytes[1];
+  return NUASM_OK;
+}
 
 nuasm_status nuasm_debug_fail_alloc(int64_t k) {
   if (k < 0) return fail(NUASM_ERR_INVALID_ARG, "k must be >= 0");
@@ -1675,7 +1722,7 @@ void drop_graph(BatchGraph& g) {
   if (g.exec) (void)hipGraphExecDestroy(g.exec);
   g.exec = nullptr;
   g.key.clear();
-  if (g.tables) (void)hipFree(g.tables);
+  if (g.tables) (void)dev_free(g.tables);
   g.tables = nullptr;
   g.stages.clear();
   g.grouped = false;
@@ -1697,7 +1744,7 @@ void batch_release(nuasm_batch_s* b) {
   if (b->fork) (void)hipEventDestroy(b->fork);
   if (b->binned) (void)hipEventDestroy(b->binned);
   for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
-  if (b->ts) (void)hipFree(b->ts);
+  if (b->ts) (void)dev_free(b->ts);
 }
 
 }  // namespace

@@ -11,8 +11,9 @@
 //                    (nuasm_debug_fail_alloc), for every k up to the number a
 //                    clean run makes: each failure must come back as
 //                    NUASM_ERR_ALLOC from the call that allocated, every
-//                    object must then destroy cleanly, and device memory must
-//                    return to where it started
+//                    object must then destroy cleanly, and the memory the
+//                    library holds (nuasm_debug_live_bytes) must return to
+//                    where it started
 //
 // Prints one line per check group and "ABI_DRIVER_OK" at the end; any failed
 // check prints its line and exits with status 1.  Leaks of host memory and
@@ -103,6 +104,9 @@ static void cpu_checks(bool have_device) {
   CHECK(nuasm_rs_direct(0, nullptr, nullptr, nullptr, 0, nullptr, nullptr, 5e-7, 0.0, 0, 0, nullptr,
                         nullptr) == NUASM_ERR_INVALID_ARG);
   CHECK(nuasm_debug_fail_alloc(-1) == NUASM_ERR_INVALID_ARG);
+  int64_t db = -1, hb = -1;
+  CHECK(nuasm_debug_live_bytes(nullptr, &hb) == NUASM_ERR_INVALID_ARG);
+  CHECK(nuasm_debug_live_bytes(&db, &hb) == NUASM_OK && db >= 0 && hb >= 0);
   CHECK(nuasm_debug_fail_alloc(0) == NUASM_OK);
   // a valid plan: no device -> NUASM_ERR_NO_DEVICE; else a full life cycle
   pl = (nuasm_plan)0x1;
@@ -230,6 +234,8 @@ static void gpu_checks() {
   CHECK(scenario(d, M, ws_bytes) == NUASM_OK);
   size_t free0 = 0, total = 0;
   CHECK(hipMemGetInfo(&free0, &total) == hipSuccess);
+  int64_t dev0 = 0, host0 = 0;
+  CHECK(nuasm_debug_live_bytes(&dev0, &host0) == NUASM_OK);
   int failures = 0, k = 1;
   for (; k <= 400; ++k) {
     CHECK(nuasm_debug_fail_alloc(k) == NUASM_OK);
@@ -248,10 +254,14 @@ static void gpu_checks() {
   CHECK(scenario(d, M, ws_bytes) == NUASM_OK);  // and everything works again
   size_t free1 = 0;
   CHECK(hipMemGetInfo(&free1, &total) == hipSuccess);
-  std::printf("gpu: %d injected allocation failures, each reported and cleaned up; device free memory "
-              "%zu -> %zu bytes\n", failures, free0, free1);
-  // the runtime may round; allow one 2 MiB page of drift
-  CHECK(free1 + ((size_t)2 << 20) >= free0);
+  int64_t dev1 = 0, host1 = 0;
+  CHECK(nuasm_debug_live_bytes(&dev1, &host1) == NUASM_OK);
+  std::printf("gpu: %d injected allocation failures, each reported and cleaned up; library-held device "
+              "bytes %lld -> %lld, pinned host bytes %lld -> %lld; device free memory %zu -> %zu bytes "
+              "(the runtime's own pools may move it)\n", failures, (long long)dev0, (long long)dev1,
+              (long long)host0, (long long)host1, free0, free1);
+  // every allocation the library made during the failures was given back
+  CHECK(dev1 == dev0 && host1 == host0);
   hipFree(d.x);
   hipFree(d.y);
   hipFree(d.c);
