@@ -43,6 +43,9 @@ def compile_flags() -> list[str]:
         f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
         # no packed-FP32 instructions in any kernel
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+        # matrix-core accumulators in ordinary VGPRs, updated in place (the
+        # accumulation-register form copies them around the spreading loop)
+        "-mllvm", "-amdgpu-mfma-vgpr-form",
         "-I", INCLUDE, "-I", CSRC,
     ]
 

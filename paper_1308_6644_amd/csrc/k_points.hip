@@ -792,8 +792,8 @@ struct __align__(16) MfmaRec {
 };
 
 // Sub-batches of 256 records (one per thread), loaded one ahead: the LDS
-// footprint (about 21 KB at w = 7) and the registers leave room for six to
-// seven workgroups per CU, which hide the load and LDS latencies.
+// footprint (about 24 KB at w = 7) and the registers leave room for six
+// workgroups per CU, which hide the load and LDS latencies.
 constexpr int kMfmaSB = kSpreadThreads;
 
 template <int W, int TILE>
@@ -803,10 +803,17 @@ __device__ __forceinline__ void spread_mfma_body(const SpreadArgs& a, int bid, i
   constexpr int QPW = NQ / NWV;                // quarter tiles per wave: 1 (32 x 32 bins) or 4 (64 x 64)
   constexpr int NACC = QPW == 1 ? 2 : 1;       // accumulator pairs per quarter tile
   static_assert(NQ % NWV == 0, "whole quarter tiles per wave");
-  __shared__ MfmaRec srec[SB];
-  __shared__ float swx[SB * W];
-  __shared__ float swy[SB * W];
-  __shared__ unsigned short slist[NQ][SB];
+  // one LDS row per record: its MfmaRec, then its x weights and its y
+  // weights, each with a zero on either side (tap m at 1 + m), so that an
+  // operand is one read at a clamped tap index.  The lists hold row byte
+  // offsets.  Record SB is a sentinel (zero value and weights) that pads the
+  // lists to whole steps.
+  constexpr int WP = W + 2, STEP = 4 * NACC;
+  constexpr int RX = 4, RY = 4 + WP;                 // floats: x and y weights in a row
+  constexpr int RSZ = (4 + 2 * WP + 3) / 4 * 4;      // row length, whole 16-byte units
+  static_assert((SB + 1) * RSZ * 4 < 65536, "row offsets fit 16 bits");
+  __shared__ __align__(16) float srow[(SB + 1) * RSZ];
+  __shared__ unsigned short slist[NQ][SB + STEP];
   __shared__ int scnt[NWV][NQ];
   __shared__ int sbase[NWV][NQ];
   __shared__ int slen[NQ];
@@ -816,6 +823,13 @@ __device__ __forceinline__ void spread_mfma_body(const SpreadArgs& a, int bid, i
   const int bin = ch.x, start = ch.y, n = ch.z, slot = ch.w;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const float blog = a.beta * 1.4426950408889634f;
+  // the pads and the sentinel row (never written again: the staging below
+  // writes only the record and the taps)
+  for (int e = t; e < SB + 1; e += kSpreadThreads) {
+    float* row = srow + e * RSZ;
+    row[RX] = row[RX + W + 1] = row[RY] = row[RY + W + 1] = 0.f;
+  }
+  for (int e = t; e < RSZ; e += kSpreadThreads) srow[SB * RSZ + e] = 0.f;
   // the lane's operand row / column and record slot inside a group of four
   const int kk = lane >> 4, ii = lane & 15;
   v4f accr[QPW][NACC], acci[QPW][NACC];
@@ -851,11 +865,12 @@ __device__ __forceinline__ void spread_mfma_body(const SpreadArgs& a, int bid, i
       m.ci = cv.y;
       m.lxy = (lx & 0xffff) | (ly << 16);
       m.pad = 0;
-      srec[t] = m;
+      float* row = srow + t * RSZ;
+      *reinterpret_cast<MfmaRec*>(row) = m;
 #pragma unroll
       for (int mm = 0; mm < W; ++mm) {
-        swx[t * W + mm] = es_kernel_fast(rc.dx + (float)mm, a.two_over_w, blog);
-        swy[t * W + mm] = es_kernel_fast(rc.dy + (float)mm, a.two_over_w, blog);
+        row[RX + 1 + mm] = es_kernel_fast(rc.dx + (float)mm, a.two_over_w, blog);
+        row[RY + 1 + mm] = es_kernel_fast(rc.dy + (float)mm, a.two_over_w, blog);
       }
     }
     int rank[NQ];
@@ -868,7 +883,8 @@ __device__ __forceinline__ void spread_mfma_body(const SpreadArgs& a, int bid, i
       if (lane == 0) scnt[wv][q] = __popcll(bal);
     }
     __syncthreads();
-    // list bases: records of earlier waves first
+    // list bases: records of earlier waves first; each list padded with the
+    // sentinel to a whole step
     if (t < NQ) {
       int run = 0;
       for (int w2 = 0; w2 < NWV; ++w2) {
@@ -876,12 +892,14 @@ __device__ __forceinline__ void spread_mfma_body(const SpreadArgs& a, int bid, i
         sbase[w2][t] = run;
         run += c2;
       }
-      slen[t] = run;
+      const int padded = (run + STEP - 1) / STEP * STEP;
+      for (int p = run; p < padded; ++p) slist[t][p] = (unsigned short)(SB * RSZ * 4);
+      slen[t] = padded;
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
-      if (rank[q] >= 0) slist[q][sbase[wv][q] + rank[q]] = (unsigned short)t;
+      if (rank[q] >= 0) slist[q][sbase[wv][q] + rank[q]] = (unsigned short)(t * RSZ * 4);
     __syncthreads();
     const float2 nv = a.vals[nx.idx];
     // the wave's quarter tiles: groups of four listed records, NACC groups
@@ -892,28 +910,24 @@ __device__ __forceinline__ void spread_mfma_body(const SpreadArgs& a, int bid, i
       const int q = wv * QPW + u;
       const int sx0 = 16 * (q % QS), sy0 = 16 * (q / QS);
       const int len = __builtin_amdgcn_readfirstlane(slen[q]);  // uniform: a scalar loop
-      for (int g = 0; g < len; g += 4 * NACC) {
-        int j[NACC];
-        bool valid[NACC];
+      const int oy = sy0 + ii + 1, ox = sx0 + ii + 1;
+      const char* base = reinterpret_cast<const char*>(srow);
+      for (int g = 0; g < len; g += STEP) {
+        const char* rp[NACC];
 #pragma unroll
-        for (int h = 0; h < NACC; ++h) {
-          const int idx = g + 4 * h + kk;
-          valid[h] = idx < len;
-          j[h] = valid[h] ? (int)slist[q][idx] : 0;
-        }
+        for (int h = 0; h < NACC; ++h) rp[h] = base + slist[q][g + 4 * h + kk];
         MfmaRec m[NACC];
 #pragma unroll
-        for (int h = 0; h < NACC; ++h) m[h] = srec[j[h]];
+        for (int h = 0; h < NACC; ++h) m[h] = *reinterpret_cast<const MfmaRec*>(rp[h]);
 #pragma unroll
         for (int h = 0; h < NACC; ++h) {
           const int mlx = (int)(short)(m[h].lxy & 0xffff), mly = m[h].lxy >> 16;
-          const int dy = sy0 + ii - mly, dx = sx0 + ii - mlx;
-          const bool iny = valid[h] && (unsigned)dy < (unsigned)W;
-          const bool inx = valid[h] && (unsigned)dx < (unsigned)W;
-          const float wy = swy[j[h] * W + (iny ? dy : 0)];
-          const float wx = swx[j[h] * W + (inx ? dx : 0)];
-          const float ay = iny ? wy : 0.f;
-          const float bx = inx ? wx : 0.f;
+          // tap index of this row / column, clamped onto a zero pad outside
+          const int ty = min(max(oy - mly, 0), W + 1);
+          const int tx = min(max(ox - mlx, 0), W + 1);
+          const float* wr = reinterpret_cast<const float*>(rp[h]);
+          const float ay = wr[RY + ty];
+          const float bx = wr[RX + tx];
           accr[u][h] = __builtin_amdgcn_mfma_f32_16x16x4f32(m[h].cr * ay, bx, accr[u][h], 0, 0, 0);
           acci[u][h] = __builtin_amdgcn_mfma_f32_16x16x4f32(m[h].ci * ay, bx, acci[u][h], 0, 0, 0);
         }
