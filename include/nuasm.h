@@ -407,8 +407,9 @@ nuasm_status nuasm_batch_set_branches(nuasm_batch batch, int32_t branches);
  * split-bin reduction, the row and column passes, interpolation) is one
  * launch per kernel instantiation covering every plane that has it, each
  * workgroup finding its plane's arguments in a per-stage descriptor table;
- * binning and the type-1 operator run on one graph branch, the type-2 grid
- * passes on another, joined after binning for the interpolation.  grouped = 0:
+ * the type-1 planes' binning and operator run on one graph branch, the
+ * type-2 planes' grid passes, binning and interpolation on another (each
+ * stage grouped over the planes of its branch).  grouped = 0:
  * every plane's own launch sequence on one of `branches` parallel branches.
  * Drops the recorded graphs. */
 nuasm_status nuasm_batch_set_grouped(nuasm_batch batch, int32_t grouped);

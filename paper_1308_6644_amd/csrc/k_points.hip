@@ -813,7 +813,7 @@ __device__ __forceinline__ void spread_mfma_body(const SpreadArgs& a, int bid, i
   constexpr int RSZ = (4 + 2 * WP + 3) / 4 * 4;      // row length, whole 16-byte units
   static_assert((SB + 1) * RSZ * 4 < 65536, "row offsets fit 16 bits");
   __shared__ __align__(16) float srow[(SB + 1) * RSZ];
-  __shared__ unsigned short slist[NQ][SB + STEP];
+  __shared__ unsigned short slist[NQ][SB + 2 * STEP];
   __shared__ int scnt[NWV][NQ];
   __shared__ int sbase[NWV][NQ];
   __shared__ int slen[NQ];
@@ -912,10 +912,18 @@ __device__ __forceinline__ void spread_mfma_body(const SpreadArgs& a, int bid, i
       const int len = __builtin_amdgcn_readfirstlane(slen[q]);  // uniform: a scalar loop
       const int oy = sy0 + ii + 1, ox = sx0 + ii + 1;
       const char* base = reinterpret_cast<const char*>(srow);
+      // the list entries of the next step are read one step ahead (the list
+      // has room for the reads past its end; those values go unused)
+      int off[NACC];
+#pragma unroll
+      for (int h = 0; h < NACC; ++h) off[h] = slist[q][4 * h + kk];
       for (int g = 0; g < len; g += STEP) {
         const char* rp[NACC];
 #pragma unroll
-        for (int h = 0; h < NACC; ++h) rp[h] = base + slist[q][g + 4 * h + kk];
+        for (int h = 0; h < NACC; ++h) {
+          rp[h] = base + off[h];
+          off[h] = slist[q][g + STEP + 4 * h + kk];
+        }
         MfmaRec m[NACC];
 #pragma unroll
         for (int h = 0; h < NACC; ++h) m[h] = *reinterpret_cast<const MfmaRec*>(rp[h]);

@@ -1705,7 +1705,6 @@ struct nuasm_batch_s {
   int active = 0;              // branches in use (nuasm_batch_set_branches)
   std::vector<int> branch_of;  // plane -> branch
   hipEvent_t fork = nullptr;
-  hipEvent_t binned = nullptr;   // grouped graphs: binning done (the interpolation waits for it)
   std::vector<hipEvent_t> join;
   // one-shot (binning + operator), binning alone, operator alone
   BatchGraph g_run, g_bin, g_exec;
@@ -1742,7 +1741,6 @@ void batch_release(nuasm_batch_s* b) {
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->ev_out) (void)hipEventDestroy(b->ev_out);
   if (b->fork) (void)hipEventDestroy(b->fork);
-  if (b->binned) (void)hipEventDestroy(b->binned);
   for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
   if (b->ts) (void)dev_free(b->ts);
 }
@@ -1780,13 +1778,21 @@ static void assign_branches(nuasm_batch_s* b, const std::vector<int64_t>& M) {
 }
 
 // Pipeline order of the stages for grouped execution, and which chain each
-// belongs to: binning, then the type-1 operator, on one branch; the type-2
-// grid passes (which need no points) on a second branch, joining the first
-// after binning for the interpolation.
+// belongs to: the type-1 planes' binning, then the type-1 operator, on one
+// branch; the type-2 grid passes (which need no points), the type-2 planes'
+// binning and the interpolation on a second.  The type-2 planes' binning
+// launches are told apart by a stage offset (kStageBinB) when they are
+// collected, so that the two chains share nothing.
+constexpr int kStageBinB = 100;
 static const int kGroupOrderA[] = {NUASM_STAGE_BIN_HIST, NUASM_STAGE_BIN_COLSCAN, NUASM_STAGE_BIN_SCATTER,
                                    NUASM_STAGE_SPREAD,   NUASM_STAGE_SPREAD_REDUCE, NUASM_STAGE_T1_ROWS,
                                    NUASM_STAGE_T1_COLS,  NUASM_STAGE_T1_ROWS_INV};
-static const int kGroupOrderB[] = {NUASM_STAGE_T2_ROWS, NUASM_STAGE_T2_COLS, NUASM_STAGE_T2_ROWS_INV,
+static const int kGroupOrderB[] = {NUASM_STAGE_T2_ROWS,
+                                   NUASM_STAGE_T2_COLS,
+                                   NUASM_STAGE_T2_ROWS_INV,
+                                   kStageBinB + NUASM_STAGE_BIN_HIST,
+                                   kStageBinB + NUASM_STAGE_BIN_COLSCAN,
+                                   kStageBinB + NUASM_STAGE_BIN_SCATTER,
                                    NUASM_STAGE_INTERP};
 
 // Collect every plane's launches (plane(pl, p) with the recorder active: host
@@ -1804,6 +1810,10 @@ static nuasm_status batch_collect(nuasm_batch_s* b, BatchGraph& g, F plane) {
     const nuasm_status s = plane(pl, p);
     active_recorder() = nullptr;
     if (s != NUASM_OK) return fail(s, "plane " + std::to_string(p) + ": " + g_last_error);
+    if (pl->p.type == NUASM_TYPE_2)
+      for (RecordedLaunch& L : rec[p].launches)
+        if (L.stage == NUASM_STAGE_BIN_HIST || L.stage == NUASM_STAGE_BIN_COLSCAN || L.stage == NUASM_STAGE_BIN_SCATTER)
+          L.stage += kStageBinB;
   }
   // group: for each stage in pipeline order, one launch per instantiation
   std::vector<int> order(std::begin(kGroupOrderA), std::end(kGroupOrderA));
@@ -1863,12 +1873,10 @@ static nuasm_status batch_collect(nuasm_batch_s* b, BatchGraph& g, F plane) {
 // a completion stamp after each launch for the planes it finishes.  After
 // stage `wait_before` (if any) the chain first waits for event `ev`.
 static hipError_t enqueue_chain(nuasm_batch_s* b, const BatchGraph& g, const int* order, int norder,
-                                hipStream_t st, int wait_before, hipEvent_t ev, std::vector<int>& last_stage_of,
-                                hipEvent_t record_after_binning) {
+                                hipStream_t st, std::vector<int>& last_stage_of) {
   hipError_t e = hipSuccess;
   for (int k = 0; k < norder && e == hipSuccess; ++k) {
     const int stage = order[k];
-    if (stage == wait_before && ev) e = hipStreamWaitEvent(st, ev, 0);
     for (size_t i = 0; i < g.stages.size() && e == hipSuccess; ++i) {
       const GroupedStage& gs = g.stages[i];
       if (gs.stage != stage) continue;
@@ -1882,8 +1890,6 @@ static hipError_t enqueue_chain(nuasm_batch_s* b, const BatchGraph& g, const int
           if (last_stage_of[p] == (int)i) e = launch_stamp(b->ts + 1 + p, st);
       }
     }
-    if (stage == NUASM_STAGE_BIN_SCATTER && record_after_binning && e == hipSuccess)
-      e = hipEventRecord(record_after_binning, st);
   }
   return e;
 }
@@ -1938,21 +1944,19 @@ static nuasm_status batch_launch(nuasm_batch_s* b, BatchGraph& g, const std::vec
   hipError_t e = launch_stamp(b->ts, b->cap);
   if (e == hipSuccess) e = hipEventRecord(b->fork, b->cap);
   if (b->grouped) {
-    // two chains: binning and the type-1 operator on branch 0, the type-2 grid
-    // passes on branch 1 (interpolation after binning); stamps per plane
+    // two independent chains: the type-1 planes (binning, operator) on branch
+    // 0, the type-2 planes (grid passes, binning, interpolation) on branch 1;
+    // stamps per plane
     std::vector<int> last(P, -1);
     for (size_t i = 0; i < g.stages.size(); ++i)
       for (int p : g.stages[i].planes) last[p] = (int)i;
     hipStream_t s0 = b->branch[0], s1 = b->branch[1];
     if (e == hipSuccess) e = hipStreamWaitEvent(s0, b->fork, 0);
     if (e == hipSuccess) e = hipStreamWaitEvent(s1, b->fork, 0);
-    hipEvent_t binned = b->binned;
     if (e == hipSuccess)
-      e = enqueue_chain(b, g, kGroupOrderA, (int)(sizeof(kGroupOrderA) / sizeof(int)), s0, -1, nullptr, last,
-                        binned);
+      e = enqueue_chain(b, g, kGroupOrderA, (int)(sizeof(kGroupOrderA) / sizeof(int)), s0, last);
     if (e == hipSuccess)
-      e = enqueue_chain(b, g, kGroupOrderB, (int)(sizeof(kGroupOrderB) / sizeof(int)), s1, NUASM_STAGE_INTERP,
-                        binned, last, nullptr);
+      e = enqueue_chain(b, g, kGroupOrderB, (int)(sizeof(kGroupOrderB) / sizeof(int)), s1, last);
     // planes with no launch at all (no points, type 2) finish at once
     for (int p = 0; e == hipSuccess && p < P; ++p)
       if (last[p] < 0) e = launch_stamp(b->ts + 1 + p, s0);
@@ -2041,8 +2045,6 @@ nuasm_status nuasm_batch_create(int32_t P, const nuasm_params* params, void* hip
     b->join.push_back(ev);
   }
   if ((e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming)) != hipSuccess)
-    return bail(hip_fail(e, "hipEventCreate"));
-  if ((e = hipEventCreateWithFlags(&b->binned, hipEventDisableTiming)) != hipSuccess)
     return bail(hip_fail(e, "hipEventCreate"));
   if ((e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming)) != hipSuccess)
     return bail(hip_fail(e, "hipEventCreate"));
