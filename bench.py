@@ -42,6 +42,7 @@ POINT_STAGES = ("bin_hist", "bin_colscan", "bin_scatter", "spread", "spread_redu
 SHARED_SOURCES = ("device_common.h", "launch.h", "group.h")
 # VALU issue: one wave64 instruction per SIMD every 4 cycles, 256 CUs x 4 SIMDs at 2.4 GHz
 SIMDS, CLOCK_HZ, VALU_CYCLES = 1024, 2.4e9, 4
+CUS, MFMA_F32_16X16X4_CYCLES = 256, 32
 
 
 def kernel_sources(stage: str):
@@ -69,6 +70,84 @@ def counter_record(stage: str):
     if not rec or rec.get("sources_sha256") != sources_sha256(stage):
         return None
     return rec
+
+
+# kernel body name in the symbol -> stage (longer names first where one
+# contains another)
+_STAGE_OF_BODY = (
+    ("bin_hist_body", "bin_hist"), ("bin_colscan_body", "bin_colscan"), ("bin_scatter_det_body", "bin_scatter"),
+    ("bin_scatter_body", "bin_scatter"), ("spread_mfma_body", "spread"), ("spread_reduce_body", "spread_reduce"),
+    ("spread_body", "spread"), ("interp_body", "interp"), ("t1_rows_inv_body", "t1_rows_inv"),
+    ("t1_rows_body", "t1_rows"), ("t1_cols_body", "t1_cols"), ("t2_rows_inv_body", "t2_rows_inv"),
+    ("t2_rows_body", "t2_rows"), ("t2_cols_body", "t2_cols"), ("copyBuffer", "copy"))
+
+
+def _counter_rows(db: str):
+    """Per-dispatch counter sums of one rocprofv3 database, by stage: only the
+    single-plane launches (a grouped launch covers several planes) and, for
+    the copy, only the dispatches of the calibration size (the largest)."""
+    import collections
+    import sqlite3
+    con = sqlite3.connect(db)
+    rows = con.execute("select kernel_name, dispatch_id, counter_name, value from counters_collection").fetchall()
+    con.close()
+    per = collections.defaultdict(lambda: collections.defaultdict(float))
+    for name, did, counter, value in rows:
+        if "k_grouped" in name:
+            continue
+        stage = next((st for key, st in _STAGE_OF_BODY if key in name), None)
+        if stage is not None:
+            per[(stage, did)][counter] += value
+    copies = [(k, d) for k, d in per.items() if k[0] == "copy"]
+    if copies:
+        key = "FETCH_SIZE" if "FETCH_SIZE" in copies[0][1] else "WRITE_SIZE"
+        top = max(d.get(key, 0.0) for _, d in copies)
+        for k, d in copies:
+            if d.get(key, 0.0) < 0.9 * top:
+                del per[k]
+    out = collections.defaultdict(lambda: collections.defaultdict(float))
+    n = collections.Counter()
+    for (stage, _), d in per.items():
+        n[stage] += 1
+        for counter, value in d.items():
+            out[stage][counter] += value
+    return {st: {c: v / n[st] for c, v in d.items()} | {"launches": n[st]} for st, d in out.items()}
+
+
+def write_counters(fetch_db: str, write_db: str, copy_fetch_db: str, copy_write_db: str, command: str) -> dict:
+    """profiles/counters.json from four rocprofv3 --pmc databases: FETCH_SIZE
+    (with the SQ counters) and WRITE_SIZE passes of the benchmark, and the same
+    two counters over plain device copies of a known size, which scale them to
+    bytes.  Each kernel's record carries the hash of the sources it was taken
+    on, so that the benchmark only uses it while they are unchanged."""
+    a, b = _counter_rows(fetch_db), _counter_rows(write_db)
+    ca, cb = _counter_rows(copy_fetch_db), _counter_rows(copy_write_db)
+    copy_bytes = 268435456
+    fs = copy_bytes / (ca["copy"]["FETCH_SIZE"] * 1024)
+    ws = copy_bytes / (cb["copy"]["WRITE_SIZE"] * 1024)
+    out = {"command": command,
+           "calibration": {"copy_bytes": copy_bytes, "fetch_scale": fs, "write_scale": ws,
+                           "copy_fetch_kib": ca["copy"]["FETCH_SIZE"], "copy_write_kib": cb["copy"]["WRITE_SIZE"]},
+           "kernels": {}}
+    for st in sorted(set(a) & set(b)):
+        if st == "copy":
+            continue
+        rec = {"sources_sha256": sources_sha256(st), "launches": a[st]["launches"],
+               "fetch_bytes": a[st].get("FETCH_SIZE", 0.0) * 1024 * fs,
+               "write_bytes": b[st].get("WRITE_SIZE", 0.0) * 1024 * ws}
+        for counter, key in (("SQ_INSTS_VALU", "valu_insts"), ("SQ_INSTS_MFMA", "mfma_insts"),
+                             ("SQ_INSTS_LDS", "lds_insts"), ("SQ_WAVES", "waves"),
+                             ("SQ_LDS_BANK_CONFLICT", "lds_bank_conflict_cycles"),
+                             ("SQ_ACTIVE_INST_LDS", "lds_active_cycles")):
+            for src in (a, b):
+                if counter in src[st]:
+                    rec[key] = src[st][counter]
+                    break
+        out["kernels"][st] = rec
+    with open(COUNTERS, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    return out
 
 
 def stage_bytes(stage: str, info: dict) -> float:
@@ -288,6 +367,12 @@ def roofline(stages, steps):
         roof["valu_issue_frac"] = valu * VALU_CYCLES / (SIMDS * CLOCK_HZ * t_launch)
         if rec.get("mfma_insts") is not None:
             roof["mfma_insts_per_launch"] = float(rec["mfma_insts"])
+            # v_mfma_f32_16x16x4f32 (the only matrix instruction used): 8
+            # passes of 4 cycles on its SIMD's matrix core
+            roof["mfma_busy_frac"] = float(rec["mfma_insts"]) * MFMA_F32_16X16X4_CYCLES / (SIMDS * CLOCK_HZ * t_launch)
+        if rec.get("lds_bank_conflict_cycles") is not None:
+            # LDS cycles lost to bank conflicts, per CU, over the launch
+            roof["lds_conflict_frac"] = float(rec["lds_bank_conflict_cycles"]) / (CUS * CLOCK_HZ * t_launch)
         roof["counters"] = {"source": "profiles/counters.json", "sources_sha256": rec["sources_sha256"]}
         if roof["valu_issue_frac"] > max(roof["hbm_counter_frac"], roof["hbm_algorithmic_frac"]):
             lanes = SIMDS * 16 * CLOCK_HZ / 1e9  # G lane-instructions/s
@@ -729,7 +814,14 @@ def main(argv=None):
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (3 times), the "
                          "reference for the FETCH_SIZE / WRITE_SIZE counters, and exit")
+    ap.add_argument("--write-counters", nargs=4, metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB"),
+                    help="write profiles/counters.json from four rocprofv3 --pmc databases (no GPU needed) "
+                         "and exit")
     a = ap.parse_args(argv)
+    if a.write_counters:
+        out = write_counters(*a.write_counters, command=os.environ.get("NUASM_COUNTERS_COMMAND", ""))
+        print(json.dumps({"kernels": sorted(out["kernels"]), "calibration": out["calibration"]}))
+        return 0
     if a.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {a.gpus}). "
               "Run with --gpus 1.", file=sys.stderr)
