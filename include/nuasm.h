@@ -41,6 +41,11 @@
  * never synchronises the host.  set_points() synchronises once (a 4-byte
  * readback) to report out-of-range points, unless the plan was created with
  * NUASM_DEFER_RANGE_CHECK, in which case nuasm_check_points() reports it.
+ * Under a deferred check, points outside the window (or with NaN
+ * coordinates) take no part in the operator: every output slot of such a
+ * point (type-2 and type-3 destinations, type-1 adjoint values) is NaN, and a
+ * type-1 result is the sum over the other points only, so a result is not to
+ * be used unless nuasm_check_points() returns NUASM_OK.
  *
  * Errors: every call returns nuasm_status; nothing throws across the ABI.
  * nuasm_last_error() gives a thread-local human-readable detail of the most

@@ -370,19 +370,20 @@ __device__ __forceinline__ void bin_scatter_body(const BinArgs& a, int bid, int)
   const int* myoff = off + (size_t)bid * (T + 1);
   if (CURSORS) {
     // the loads of eight bins per thread in flight together (clamped
-    // addresses), then the LDS writes
+    // addresses), then the LDS writes; entry T is the cursor of the range's
+    // points outside the window
     constexpr int NB = 8;
-    for (int b0 = 0; b0 < T; b0 += kBinThreads * NB) {
+    for (int b0 = 0; b0 <= T; b0 += kBinThreads * NB) {
       unsigned v[NB];
 #pragma unroll
       for (int u = 0; u < NB; ++u) {
-        const int b = min(b0 + (int)threadIdx.x + u * kBinThreads, T - 1);
-        v[u] = (unsigned)(bin_base[b] + myoff[b]);
+        const int b = min(b0 + (int)threadIdx.x + u * kBinThreads, T);
+        v[u] = (unsigned)((b < T ? bin_base[min(b, T - 1)] : 0) + myoff[b]);
       }
 #pragma unroll
       for (int u = 0; u < NB; ++u) {
         const int b = b0 + (int)threadIdx.x + u * kBinThreads;
-        if (b < T) sh[b] = v[u];
+        if (b <= T) sh[b] = v[u];
       }
     }
   } else {
@@ -404,7 +405,13 @@ __device__ __forceinline__ void bin_scatter_body(const BinArgs& a, int bid, int)
       const int64_t j = jb + threadIdx.x + q * kBinThreads;
       if (j >= j1) continue;
       const PointCells pc = point_cells(xv[q], yv[q], g);
-      if (!pc.ok) continue;
+      if (!pc.ok) {
+        // outside the window: no record; its index is listed for the NaN
+        // outputs of a deferred range check
+        const int r = CURSORS ? (int)atomicAdd(&sh[T], 1u) : myoff[T] + (int)lds_bump16(sh, T);
+        a.rej_end[-1 - r] = (int)j;
+        continue;
+      }
       const int bx0 = pc.i0x >> g.tile_log, bx1 = (pc.i0x + g.w - 1) >> g.tile_log;
       const int by0 = pc.i0y >> g.tile_log, by1 = (pc.i0y + g.w - 1) >> g.tile_log;
       for (int by = by0; by <= by1; ++by)
@@ -469,12 +476,15 @@ __device__ __forceinline__ void bin_scatter_det_body(const BinArgs& a, int bid, 
   __shared__ unsigned key[kDetRecs];
   __shared__ int slot_of[kDetRecs];  // by record id 4 p + k
   __shared__ int wsum[NW], wmax[NW];
+  __shared__ int nrej;
   const int T = g.TX * g.TX;
   const int* myoff = off + (size_t)bid * (T + 1);
   const int64_t j0 = (int64_t)bid * ppw;
   const int np = (int)(min(M, j0 + ppw) - j0);  // <= kDetPoints (checked by the launcher)
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  if (t == 0) nrej = 0;
   PointCells pc = point_cells(t < np ? x[j0 + t] : 0.0, t < np ? y[j0 + t] : 0.0, g);
+  const bool rejected = t < np && !pc.ok;  // outside the window: listed for NaN outputs
   if (t >= np) pc.ok = false;
   const int bx0 = pc.i0x >> g.tile_log, nbx = ((pc.i0x + g.w - 1) >> g.tile_log) - bx0 + 1;
   const int by0 = pc.i0y >> g.tile_log, nby = ((pc.i0y + g.w - 1) >> g.tile_log) - by0 + 1;
@@ -483,6 +493,7 @@ __device__ __forceinline__ void bin_scatter_det_body(const BinArgs& a, int bid, 
   const int incl = wave_incl_scan(nrec, lane);
   if (lane == 63) wsum[wv] = incl;
   __syncthreads();
+  if (rejected) a.rej_end[-1 - (myoff[T] + atomicAdd(&nrej, 1))] = (int)(j0 + t);
   int base = incl - nrec, total = 0;
   for (int w2 = 0; w2 < NW; ++w2) {
     if (w2 < wv) base += wsum[w2];
@@ -1122,7 +1133,8 @@ hipError_t launch_bin_colscan(const uint16_t* hist, int G, int T, int* off, int*
 }
 
 hipError_t launch_bin_scatter(const double* x, const double* y, int64_t M, BinGeom g, int ppw, int G,
-                              const int* off, const int* bin_base, BinRec* recs, bool stable, hipStream_t st) {
+                              const int* off, const int* bin_base, BinRec* recs, int* rej_end, bool stable,
+                              hipStream_t st) {
   if (G <= 0) return hipSuccess;
   const int T = g.TX * g.TX;
   BinArgs a{};
@@ -1134,12 +1146,28 @@ hipError_t launch_bin_scatter(const double* x, const double* y, int64_t M, BinGe
   a.off = off;
   a.bin_base = bin_base;
   a.recs = recs;
+  a.rej_end = rej_end;
   if (stable) {
     if (ppw > kDetPoints) return hipErrorInvalidValue;
     return launch_or_record<BinArgs, bin_scatter_det_body, kBinThreads>(a, G, 0, st);
   }
-  if (T * 4 <= kScatterCursorBytes) return launch_or_record<BinArgs, bin_scatter_body<true>, kBinThreads>(a, G, T * 4, st);
+  if ((T + 1) * 4 <= kScatterCursorBytes)
+    return launch_or_record<BinArgs, bin_scatter_body<true>, kBinThreads>(a, G, (T + 1) * 4, st);
   return launch_or_record<BinArgs, bin_scatter_body<false>, kBinThreads>(a, G, ((T + 1) / 2) * 4, st);
+}
+
+// NaN at the output slot of every point outside the window (a fixed grid
+// striding over their count, which only the device knows).
+constexpr int kRejThreads = 256, kRejBlocks = 64;
+__device__ __forceinline__ void fill_rejected_body(const RejArgs& a, int bid, int nbid) {
+  const int n = a.nrej[0];
+  const float nan = __builtin_nanf("");
+  for (int i = bid * kRejThreads + (int)threadIdx.x; i < n; i += nbid * kRejThreads)
+    a.out[a.rej_end[-1 - i]] = make_float2(nan, nan);
+}
+
+hipError_t launch_fill_rejected(const RejArgs& a, hipStream_t st) {
+  return launch_or_record<RejArgs, fill_rejected_body, kRejThreads>(a, kRejBlocks, 0, st);
 }
 
 #define NUASM_DISPATCH_W(w, CALL)                                                   \

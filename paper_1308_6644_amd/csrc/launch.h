@@ -115,6 +115,17 @@ struct BinArgs {
   const int* off;          // per-range offsets (scatter)
   const int* bin_base;     // first record of each bin (scatter)
   BinRec* recs;            // records (scatter)
+  int* rej_end;            // one past the end of the record buffer: the caller
+                           // indices of points outside the window are stored
+                           // downwards from here (scatter; the records, at
+                           // most four per accepted point, never reach them)
+};
+
+// Outputs of the points outside the window (deferred range check) set to NaN.
+struct RejArgs {
+  float2* out;
+  const int* rej_end;  // rejected caller indices at rej_end[-1 - i]
+  const int* nrej;     // their count (device)
 };
 
 struct SpreadArgs {
@@ -180,7 +191,9 @@ hipError_t launch_bin_hist(const double* x, const double* y, int64_t M, BinGeom 
 hipError_t launch_bin_colscan(const uint16_t* hist, int G, int T, int* off, int* total, const BinScanOut& so,
                               int* done, hipStream_t st);
 hipError_t launch_bin_scatter(const double* x, const double* y, int64_t M, BinGeom g, int ppw, int G,
-                              const int* off, const int* bin_base, BinRec* recs, bool stable, hipStream_t st);
+                              const int* off, const int* bin_base, BinRec* recs, int* rej_end, bool stable,
+                              hipStream_t st);
+hipError_t launch_fill_rejected(const RejArgs& a, hipStream_t st);
 hipError_t launch_spread(int w, bool small_chunks, const SpreadArgs& a, int grid, hipStream_t st);
 // the same spreading as sums of outer products on the matrix cores
 hipError_t launch_spread_mfma(int w, int tile, const SpreadArgs& a, int grid, hipStream_t st);

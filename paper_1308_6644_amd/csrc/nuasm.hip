@@ -758,6 +758,11 @@ int multi_grid(const nuasm_plan_s* pl, const PointSet& q) {
   return q.synced ? q.exact_multi : (int)std::min<int64_t>(pl->T, (4 * q.M) / pl->sp_chunk + 1);
 }
 
+// The rejected points' indices are stored downwards from the end of the
+// record buffer (capacity four records per point; the records of the
+// accepted points, at most four each, never reach them).
+int* rej_end(const PointSet& q) { return reinterpret_cast<int*>(q.recs + 4 * q.rec_cap); }
+
 // Coordinate normalisation and binning of one point set (three launches).
 nuasm_status bind_points(nuasm_plan_s* pl, PointSet& q, int64_t M, const double* x, const double* y) {
   if (M < 0) return fail(NUASM_ERR_INVALID_ARG, "M < 0");
@@ -784,7 +789,8 @@ nuasm_status bind_points(nuasm_plan_s* pl, PointSet& q, int64_t M, const double*
               "launch bin_colscan");
     }
     StageScope sc(pl, NUASM_STAGE_BIN_SCATTER);
-    HIP_TRY(launch_bin_scatter(x, y, M, pl->bgeom, ppw, G, q.hoff, q.cursor, q.recs, stable_bins(pl), st),
+    HIP_TRY(launch_bin_scatter(x, y, M, pl->bgeom, ppw, G, q.hoff, q.cursor, q.recs, rej_end(q), stable_bins(pl),
+                               st),
             "launch bin_scatter");
   }
   q.M = M;
@@ -944,6 +950,12 @@ nuasm_status run_interp(nuasm_plan_s* pl, PointSet& q, const float2* grid, float
   ia.two_over_w = 2.0f / (float)pl->w;
   ia.beta = pl->beta;
   HIP_TRY(launch_interp(pl->w, pl->tile, ia, ip_grid(pl, q), pl->stream), "launch interp");
+  if (!q.synced) {
+    // a deferred range check may have left points without records: NaN at
+    // their outputs (a synchronised set_points refuses such points)
+    const RejArgs ra{out, rej_end(q), q.nch + 4};
+    HIP_TRY(launch_fill_rejected(ra, pl->stream), "launch fill_rejected");
+  }
   return NUASM_OK;
 }
 
