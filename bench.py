@@ -7,7 +7,9 @@ tolerance 1e-6, clustered point sets (70 % in a Gaussian of sigma = 0.1 W at
 the centre, 30 % uniform), for z in {0.01, 0.1, 0.5} m and both the
 band-limited ASM (Eq. 4) and the Fresnel (Eq. 5) transfer functions: 12 runs.
 One step runs all 12 one-shot (binning of the points + operator) on inputs
-already resident in HBM.  value = 12 M / step time, in non-uniform points/s.
+already resident in HBM, recorded as one batch graph whose launch shapes and
+graph form the autotuner picks before the timed steps (`--no-tune`: the
+defaults).  value = 12 M / step time, in non-uniform points/s.
 
 Prints one JSON line.  The per-kernel roofline figure comes from HIP events
 the library records around every launch during a second, separately timed
@@ -150,6 +152,22 @@ def write_counters(fetch_db: str, write_db: str, copy_fetch_db: str, copy_write_
     return out
 
 
+def tune_headline_batch(batch, specs, xs, ys, ins, outs) -> dict:
+    """The autotuner on a batch (launch shapes per plane class, then the
+    graph form), into a fresh cache so that a run stands alone; the summary
+    with each plane's chosen shapes.  Every choice is a launch shape of the
+    same arithmetic (the parity tests cover each one)."""
+    import tempfile
+    from paper_1308_6644_amd import tune
+    t0 = time.perf_counter()
+    cache = tune.TuneCache(os.path.join(tempfile.mkdtemp(prefix="nuasm_tune_"), "tune.json"))
+    tuning = tune.tune_batch(batch, specs, xs, ys, ins, outs, cache, reps=3)
+    tuning["seconds"] = time.perf_counter() - t0
+    tuning["planes"] = {str(p): {k: v for k, v in cache.get(tune.plane_key(sp, xs[p].numel())).items() if k != "ms"}
+                        for p, sp in enumerate(specs)}
+    return tuning
+
+
 def stage_bytes(stage: str, info: dict) -> float:
     """Algorithmic (compulsory) HBM bytes of one launch of a kernel: every
     input the kernel's job needs read once, every output written once.  M is
@@ -257,16 +275,7 @@ def batched_workload(a, torch, P, synth):
     tuning = None
     for mode in ("sequential", "graph", "graph_tuned"):
         if mode == "graph_tuned":
-            # the autotuner (launch shapes per plane class, then the graph's
-            # branch count), into a fresh cache so that the run stands alone
-            import tempfile
-            from paper_1308_6644_amd import tune
-            t0 = time.perf_counter()
-            cache = tune.TuneCache(os.path.join(tempfile.mkdtemp(prefix="nuasm_tune_"), "tune.json"))
-            tuning = tune.tune_batch(batch, specs, xs, ys, ins, outs, cache, reps=3)
-            tuning["seconds"] = time.perf_counter() - t0
-            tuning["planes"] = {str(p): {k: v for k, v in cache.get(tune.plane_key(s, xs[p].numel())).items()
-                                         if k != "ms"} for p, s in enumerate(specs)}
+            tuning = tune_headline_batch(batch, specs, xs, ys, ins, outs)
         for _ in range(a.warmup):
             seq_step() if mode == "sequential" else batch.run(xs, ys, ins, outs)
         torch.cuda.synchronize()
@@ -809,6 +818,9 @@ def main(argv=None):
                          "scaled: a 2x zoom to a 2048 x 2048 destination grid; precision: NU-ASM_2 at "
                          "N'=8192, M=2^24, z=1 m on the band-adaptive and the full fine grid; cgh: one "
                          "hologram-optimisation iteration at N'=4096, M=2^22 (forward, adjoint timed beside)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="graph mode with the default launch shapes and form (no autotuning before the "
+                         "timed steps)")
     ap.add_argument("--deterministic", action="store_true",
                     help="n2048 with NUASM_DETERMINISTIC on every plan (bitwise-reproducible runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -882,12 +894,16 @@ def main(argv=None):
             r["plan"].execute(r["inp"], r["out"])
 
     batch = None
+    tuning = None
     if a.mode == "graph":
         batch = P.Batch([r["spec"] for r in runs])
         bx = [r["x"] for r in runs]
         by = [r["y"] for r in runs]
         bi = [r["inp"] for r in runs]
         bo = [r["out"] for r in runs]
+        if not a.no_tune:
+            print("[bench] autotuning the batch", file=sys.stderr, flush=True)
+            tuning = tune_headline_batch(batch, [r["spec"] for r in runs], bx, by, bi, bo)
 
         def step():
             batch.run(bx, by, bi, bo)
@@ -938,6 +954,9 @@ def main(argv=None):
                         "{band-limited ASM, Fresnel}, tol 1e-6 (w=7), 12 runs per step",
             "N": N, "Np": 2 * N, "M": M, "runs_per_step": len(runs), "phase": "f64",
             "mode": a.mode, "deterministic": a.deterministic,
+            "tuning": None if tuning is None else {
+                "form": "grouped" if tuning["grouped"] else f"per-plane, {tuning['branches']} branches",
+                "form_ms": tuning["form_ms"], "seconds": tuning["seconds"], "planes": tuning["planes"]},
         },
         "wall_s_timed": wall,
     }

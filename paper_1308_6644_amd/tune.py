@@ -96,7 +96,7 @@ def _time(fn, reps: int) -> float:
 def tune_plane(spec: dict, x: torch.Tensor, y: torch.Tensor, inp: torch.Tensor, reps: int = 3) -> dict:
     """Coordinate descent over CANDIDATES for one plane (binned points);
     returns the best tuning and its one-shot time in ms."""
-    plan = Plan(defer_range_check=True, **spec)
+    plan = Plan(**{**spec, "defer_range_check": True})
 
     def run(t):
         try:

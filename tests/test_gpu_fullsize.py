@@ -101,12 +101,17 @@ def test_fullsize_nuasm1_spectral_samples(data, z, tf):
     print(f"  rel-L2 on 512 spectral samples = {err:.3e}", flush=True)
 
 
-def test_fullsize_bench_graph_every_run(data):
+@pytest.mark.parametrize("form", ["default", "tuned", "tile64_branches"])
+def test_fullsize_bench_graph_every_run(data, form):
     """The benchmark's launch configuration itself: the 12 runs of a step
-    recorded as one batch graph on parallel branches (range check deferred),
-    run twice (recording, then a replay); every run's output checked against
-    the oracle on samples (128 destination points for NU-ASM_2, 128 in-band
-    frequencies for NU-ASM_1)."""
+    recorded as one batch graph (range check deferred), run twice
+    (recording, then a replay); every run's output checked against the
+    oracle on samples (128 destination points for NU-ASM_2, 128 in-band
+    frequencies for NU-ASM_1).  Forms: the default grouped graph; the batch
+    as the benchmark autotunes it (whatever shapes and form the tuner picks
+    on this machine); and the choice it usually makes, forced (64 x 64 bins for
+    the type-2 planes, per-plane launches on four branches)."""
+    import bench
     P, d = data["P"], data["d"]
     specs, xs, ys, ins, outs = [], [], [], [], []
     for z in (0.01, 0.1, 0.5):
@@ -119,8 +124,19 @@ def test_fullsize_bench_graph_every_run(data):
                 ins.append(d["c1"] if t == 1 else d["u1"])
                 outs.append(torch.empty((2 * N, 2 * N) if t == 1 else (M,), dtype=torch.complex64,
                                         device="cuda"))
-    print(f"fullsize bench graph: {len(specs)} runs, N={N} M={M}", flush=True)
+    print(f"fullsize bench graph ({form}): {len(specs)} runs, N={N} M={M}", flush=True)
     b = P.Batch(specs)
+    if form == "tuned":
+        tuning = bench.tune_headline_batch(b, specs, xs, ys, ins, outs)
+        print(f"  tuned: grouped={tuning['grouped']} branches={tuning['branches']}", flush=True)
+    elif form == "tile64_branches":
+        for p, s in enumerate(specs):
+            if s["type"] == 2:
+                b.set_tuning(p, bin_tile=64)
+        b.set_grouped(False)
+        b.set_branches(4)
+    for o in outs:
+        o.fill_(float("nan"))
     b.run(xs, ys, ins, outs)
     b.run(xs, ys, ins, outs)
     assert b.check_points() == -1
