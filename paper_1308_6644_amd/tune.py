@@ -30,7 +30,7 @@ import torch
 from . import Batch, NuasmError, Plan, make_params
 
 CANDIDATES = {
-    "bin_range_points": (0, 4096, 16384, 65535),
+    "bin_range_points": (0, 2048, 4096, 16384, 65535),
     "interp_chunk": (0, 1024, 4096, 8192),
     "spread_chunk": (0, 896),
     "spread_method": (0, 1),
@@ -111,15 +111,21 @@ def tune_plane(spec: dict, x: torch.Tensor, y: torch.Tensor, inp: torch.Tensor, 
 
     best = dict(DEFAULT)
     best_ms = run(best)
-    for name, cands in CANDIDATES.items():
-        for v in cands:
-            if v == best[name]:
-                continue
-            t = dict(best)
-            t[name] = v
-            ms = run(t)
-            if ms < best_ms * 0.98:  # keep the simpler setting unless clearly faster
-                best, best_ms = t, ms
+    # two sweeps of coordinate descent: a setting can pay only once another
+    # has changed (a 64 x 64 bin tile wants other chunk sizes)
+    for _ in range(2):
+        changed = False
+        for name, cands in CANDIDATES.items():
+            for v in cands:
+                if v == best[name]:
+                    continue
+                t = dict(best)
+                t[name] = v
+                ms = run(t)
+                if ms < best_ms * 0.98:  # keep the simpler setting unless clearly faster
+                    best, best_ms, changed = t, ms, True
+        if not changed:
+            break
     plan.check_points()
     return {**best, "ms": best_ms}
 
