@@ -40,7 +40,7 @@ M = 1 << 20
 # taken; a kernel whose sources have changed since gets no counter figures.
 COUNTERS = os.path.join(ROOT, "profiles", "counters.json")
 CSRC = os.path.join(ROOT, "paper_1308_6644_amd", "csrc")
-POINT_STAGES = ("bin_hist", "bin_colscan", "bin_scatter", "spread", "spread_reduce", "interp")
+POINT_STAGES = ("bin_hist", "bin_colscan", "bin_scan", "bin_scatter", "spread", "spread_reduce", "interp")
 SHARED_SOURCES = ("device_common.h", "launch.h", "group.h")
 # VALU issue: one wave64 instruction per SIMD every 4 cycles, 256 CUs x 4 SIMDs at 2.4 GHz
 SIMDS, CLOCK_HZ, VALU_CYCLES = 1024, 2.4e9, 4
@@ -77,7 +77,8 @@ def counter_record(stage: str):
 # kernel body name in the symbol -> stage (longer names first where one
 # contains another)
 _STAGE_OF_BODY = (
-    ("bin_hist_body", "bin_hist"), ("bin_colscan_body", "bin_colscan"), ("bin_scatter_det_body", "bin_scatter"),
+    ("bin_hist_body", "bin_hist"), ("bin_colscan_body", "bin_colscan"), ("bin_scan_body", "bin_scan"),
+    ("bin_scatter_det_body", "bin_scatter"),
     ("bin_scatter_body", "bin_scatter"), ("spread_mfma_body", "spread"), ("spread_reduce_body", "spread_reduce"),
     ("spread_body", "spread"), ("interp_body", "interp"), ("t1_rows_inv_body", "t1_rows_inv"),
     ("t1_rows_body", "t1_rows"), ("t1_cols_body", "t1_cols"), ("t2_rows_inv_body", "t2_rows_inv"),
@@ -187,8 +188,10 @@ def stage_bytes(stage: str, info: dict) -> float:
     c = 8.0  # complex64
     return {
         "bin_hist": 16.0 * m + 2.0 * G * T,            # coordinates in, 16-bit histograms out
-        # histograms in, offsets + totals out; then the bin scan: totals in, bases + chunk tables out
-        "bin_colscan": 2.0 * G * T + 4.0 * G * T + 4.0 * T + 4.0 * T + 4.0 * T + 32.0 * T,
+        # histograms in, offsets + totals + per-bin prefixes out
+        "bin_colscan": 2.0 * G * T + 4.0 * G * T + 4.0 * T + 20.0 * T,
+        # totals + prefixes in, bases + first chunks + chunk counts + chunk tables out
+        "bin_scan": 24.0 * T + 12.0 * T + 32.0 * T,
         "bin_scatter": 16.0 * m + 4.0 * G * T + 16.0 * m,  # coordinates + offsets in, records out
         "spread": 16.0 * m + c * m + c * L * L,        # records + values in, support grid out
         "spread_reduce": 0.0,

@@ -345,8 +345,8 @@ nuasm_status nuasm_rs_direct(int64_t M1, const double* x1_dev, const double* y1_
 /* Per-kernel device timing with HIP events recorded on the plan's stream
  * around each kernel launch (off by default).  Stages, one kernel each: */
 #define NUASM_STAGE_BIN_HIST 0     /* set_points: per-range bin histograms */
-#define NUASM_STAGE_BIN_COLSCAN 1  /* set_points: offsets across ranges, bin bases and chunk tables */
-#define NUASM_STAGE_BIN_SCAN 2     /* (folded into NUASM_STAGE_BIN_COLSCAN; records no launches) */
+#define NUASM_STAGE_BIN_COLSCAN 1  /* set_points: offsets across ranges, per-bin prefixes */
+#define NUASM_STAGE_BIN_SCAN 2     /* set_points: bin bases and chunk tables */
 #define NUASM_STAGE_BIN_SCATTER 3  /* set_points: records into bin order */
 #define NUASM_STAGE_SPREAD 4       /* spreading */
 #define NUASM_STAGE_SPREAD_REDUCE 5 /* sum of split bins' partial tiles */

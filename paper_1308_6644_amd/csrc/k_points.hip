@@ -108,34 +108,33 @@ __device__ __forceinline__ void bin_hist_body(const BinArgs& a, int bid, int) {
   for (int b = threadIdx.x; b <= T; b += kBinThreads) row[b] = (uint16_t)((sh[b >> 1] >> ((b & 1) * 16)) & 0xffffu);
 }
 
-// Column scan and bin scan.  The column scan gives off[g][b] = sum_{g' < g}
-// hist[g'][b] and the bin totals (records per bin; entry T of the rows counts
-// the points outside the window).  The bin scan turns the totals into the
-// first record of every bin (`cursor`, the bin bases the scatter adds) and the
-// chunk tables.  Spreading needs a chunk for every bin (empty bins write
-// zeros); interpolation only for non-empty bins.  A bin with more than
-// so.sp_chunk (so.ip_chunk) records is split into several spreading
-// (interpolation) chunks; for spreading those bins are listed in `multi` for
-// the reduction, and their chunks get consecutive slots of the partial-tile
-// scratch (nch[5] slots in all).  Both chunk tables are ordered by the size
-// class of their bin, largest first (a bin's chunks kept together, bins in
-// index order inside a class), so that the dispatcher starts the longest
-// workgroups first.
+// Column scan and bin scan (two launches).  The column scan gives
+// off[g][b] = sum_{g' < g} hist[g'][b] and the bin totals (records per bin;
+// entry T of the rows counts the points outside the window).  The bin scan
+// turns the totals into the first record of every bin (`cursor`, the bin bases
+// the scatter adds) and the chunk tables.  Spreading needs a chunk for every
+// bin (empty bins write zeros); interpolation only for non-empty bins.  A bin
+// with more than so.sp_chunk (so.ip_chunk) records is split into several
+// spreading (interpolation) chunks; for spreading those bins are listed in
+// `multi` for the reduction, and their chunks get consecutive slots of the
+// partial-tile scratch (nch[5] slots in all).  Both chunk tables are ordered by
+// the size class of their bin, largest first (a bin's chunks kept together,
+// bins in index order inside a class), so that the dispatcher starts the
+// longest workgroups first.
 //
-// One launch does both.  A workgroup owns 64 consecutive bins (a lane each)
-// and splits the G ranges over its 16 waves; its last wave, holding the
-// totals, also scans its 64 bins: exclusive prefixes of the records, of the
-// split bins, of their slots and of the chunks of each size class, stored per
-// bin, and the workgroup's sums of the same quantities.  The last workgroup
-// to finish (counted in `done`, which it resets) scans those sums over the
-// workgroups and writes every bin's entries.  The counter is bumped after a
-// release fence and read back before an acquire fence, so every workgroup's
-// stores are visible to the last one.  No workgroup waits for another.
+// Column scan: a workgroup owns 64 consecutive bins (a lane each) and splits
+// the G ranges over its 16 waves; its last wave, holding the totals, also
+// scans its 64 bins: exclusive prefixes of the records, of the split bins, of
+// their slots and of the chunks of each size class, stored per bin, and the
+// workgroup's sums of the same quantities.  Bin scan: one workgroup per
+// column-scan workgroup reduces those sums to its own exclusive prefix and to
+// the totals, and writes its 64 bins' entries.  No workgroup of either launch
+// waits for another.
 constexpr int kColWaves = 16;
 constexpr int kColThreads = 64 * kColWaves;
 constexpr int kClasses = 4;       // chunk size classes per table
 constexpr int kColRegs = 16;      // ranges per wave held in registers (G <= 256)
-constexpr int kColBatch = 5;      // bins per thread whose entries are read together (T <= 5120 in one pass)
+constexpr int kScanThreads = 256;
 // per-workgroup sums: records, split bins, slots, then the chunks of each
 // class of the spreading and of the interpolation table
 constexpr int kWgRec = 0, kWgMulti = 1, kWgSlot = 2, kWgSp = 3, kWgIp = 3 + kClasses;
@@ -157,18 +156,22 @@ __device__ __forceinline__ int wave_incl_scan(int v, int lane) {
   return v;
 }
 
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 __device__ __forceinline__ int spread_chunks(int c, int spc) { return c > spc ? (c + spc - 1) / spc : 1; }
 
-__device__ __forceinline__ void bin_colscan_body(const ColscanArgs& a, int bid, int nbid) {
+__device__ __forceinline__ void bin_colscan_body(const ColscanArgs& a, int bid, int) {
   const uint16_t* __restrict__ hist = a.hist;
   const int G = a.G, T = a.T;  // T: bins; rows of hist and off have T + 1 entries
   int* __restrict__ off = a.off;
   int* total = a.total;
   const BinScanOut& so = a.so;
-  int* __restrict__ done = a.done;
   const int R = T + 1;
   __shared__ int part[kColWaves][64];
-  __shared__ int last;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int b = bid * 64 + lane;
   const int per = (G + kColWaves - 1) / kColWaves;
@@ -212,130 +215,86 @@ __device__ __forceinline__ void bin_colscan_body(const ColscanArgs& a, int bid, 
       if (wv == kColWaves - 1) total[b] = run;
     }
   }
-  if (wv == kColWaves - 1) {
-    // the workgroup's 64 bins: per-bin exclusive prefixes and the sums
-    int c = 0;
-    if (b < T) {
-      c = part[0][lane];
-      for (int q = 1; q < kColWaves; ++q) c += part[q][lane];
-    }
-    const bool valid = b < T;
-    const int nsp = valid ? spread_chunks(c, so.sp_chunk) : 0;
-    const int nip = (c + so.ip_chunk - 1) / so.ip_chunk;
-    const int ksp = size_class(c, so.sp_chunk), kip = size_class(c, so.ip_chunk);
-    int v[kWgVals];
-    v[kWgRec] = c;
-    v[kWgMulti] = nsp > 1 ? 1 : 0;
-    v[kWgSlot] = nsp > 1 ? nsp : 0;
+  if (wv != kColWaves - 1) return;
+  // the workgroup's 64 bins: per-bin exclusive prefixes and the sums
+  int c = 0;
+  if (b < T) {
+    c = part[0][lane];
+    for (int q = 1; q < kColWaves; ++q) c += part[q][lane];
+  }
+  const bool valid = b < T;
+  const int nsp = valid ? spread_chunks(c, so.sp_chunk) : 0;
+  const int nip = (c + so.ip_chunk - 1) / so.ip_chunk;
+  const int ksp = size_class(c, so.sp_chunk), kip = size_class(c, so.ip_chunk);
+  int v[kWgVals];
+  v[kWgRec] = c;
+  v[kWgMulti] = nsp > 1 ? 1 : 0;
+  v[kWgSlot] = nsp > 1 ? nsp : 0;
+#pragma unroll
+  for (int k = 0; k < kClasses; ++k) {
+    v[kWgSp + k] = ksp == k ? nsp : 0;
+    v[kWgIp + k] = kip == k ? nip : 0;
+  }
+  int pre[kWgVals];
+#pragma unroll
+  for (int i = 0; i < kWgVals; ++i) {
+    const int inc = wave_incl_scan(v[i], lane);
+    pre[i] = inc - v[i];
+    if (lane == 63) so.wg_sum[(size_t)bid * kBinPre + i] = inc;
+  }
+  if (valid) {
+    int* bp = so.bin_pre + (size_t)b * kBinPre;
+    bp[0] = pre[kWgRec];
+    bp[1] = pre[kWgMulti];
+    bp[2] = pre[kWgSlot];
+    int psp = 0, pip = 0;
 #pragma unroll
     for (int k = 0; k < kClasses; ++k) {
-      v[kWgSp + k] = ksp == k ? nsp : 0;
-      v[kWgIp + k] = kip == k ? nip : 0;
+      if (ksp == k) psp = pre[kWgSp + k];
+      if (kip == k) pip = pre[kWgIp + k];
     }
-    int pre[kWgVals];
-#pragma unroll
-    for (int i = 0; i < kWgVals; ++i) {
-      const int inc = wave_incl_scan(v[i], lane);
-      pre[i] = inc - v[i];
-      if (lane == 63) so.wg_sum[(size_t)bid * kBinPre + i] = inc;
-    }
-    if (valid) {
-      int* bp = so.bin_pre + (size_t)b * kBinPre;
-      bp[0] = pre[kWgRec];
-      bp[1] = pre[kWgMulti];
-      bp[2] = pre[kWgSlot];
-      int psp = 0, pip = 0;
-#pragma unroll
-      for (int k = 0; k < kClasses; ++k) {
-        if (ksp == k) psp = pre[kWgSp + k];
-        if (kip == k) pip = pre[kWgIp + k];
-      }
-      bp[3] = psp;
-      bp[4] = pip;
-    }
-    // release this workgroup's stores, then count it
-    __threadfence();
-    if (lane == 0) {
-      const bool l = atomicAdd(done, 1) == nbid - 1;
-      if (l) __threadfence();
-      last = l;
-    }
+    bp[3] = psp;
+    bp[4] = pip;
   }
-  __syncthreads();
-  if (!last) return;
+}
 
-  // ---- the last workgroup: scan the workgroup sums, write every bin's entries
-  const int nwg = nbid;
-  extern __shared__ int wgpre[];  // [nwg][kWgVals] exclusive prefixes over the workgroups
-  __shared__ int tot[kWgVals];
-  __shared__ int cbase[2][kClasses];
-  if (wv < kWgVals) {
-    // wave i scans value i over the workgroups, 64 at a time
-    const int i = wv;
-    int carry = 0;
-    for (int w0 = 0; w0 < nwg; w0 += 64) {
+// Bin scan: workgroup w (of the nbid column-scan workgroups) sums the
+// column-scan sums of workgroups 0..w-1 (its prefix) and of all (the totals),
+// wave v taking values v, v + 4, ..., and then its first wave writes the
+// entries of bins 64 w .. 64 w + 63.  Workgroup 0 also writes the counts.
+__device__ __forceinline__ void bin_scan_body(const ColscanArgs& a, int bid, int nbid) {
+  const int T = a.T;
+  const int* __restrict__ total = a.total;
+  const BinScanOut& so = a.so;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int bb = bid * 64 + lane;
+  __shared__ int wpre[kWgVals], tot[kWgVals];
+  // the bin's own entries first, so that their latency overlaps the sums
+  int c = 0, pre[5] = {0, 0, 0, 0, 0};
+  if (wv == 0 && bb < T) {
+    c = total[bb];
+    const int* bp = so.bin_pre + (size_t)bb * kBinPre;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) pre[v] = bp[v];
+  }
+  for (int i = wv; i < kWgVals; i += kScanThreads / 64) {
+    int sp = 0, st = 0;
+    for (int w0 = 0; w0 < nbid; w0 += 64) {
       const int w = w0 + lane;
-      const int x = w < nwg ? so.wg_sum[(size_t)w * kBinPre + i] : 0;
-      const int inc = wave_incl_scan(x, lane);
-      if (w < nwg) wgpre[w * kWgVals + i] = carry + inc - x;
-      carry += __shfl(inc, 63, 64);
+      const int x = w < nbid ? so.wg_sum[(size_t)w * kBinPre + i] : 0;
+      st += x;
+      sp += w < bid ? x : 0;
     }
-    if (lane == 0) tot[i] = carry;
-  }
-  __syncthreads();
-  if (threadIdx.x < 2) {
-    // class bases, largest class first
-    const int t = threadIdx.x, o = t == 0 ? kWgSp : kWgIp;
-    int run = 0;
-    for (int k = kClasses - 1; k >= 0; --k) {
-      cbase[t][k] = run;
-      run += tot[o + k];
+    sp = wave_sum(sp);
+    st = wave_sum(st);
+    if (lane == 0) {
+      wpre[i] = sp;
+      tot[i] = st;
     }
   }
   __syncthreads();
-  const int spc = so.sp_chunk, ipc = so.ip_chunk;
-  // every bin's entries: the reads of up to kColBatch bins per thread are
-  // issued together before any is used
-  for (int b0 = 0; b0 < T; b0 += kColThreads * kColBatch) {
-    int cb[kColBatch], pre[kColBatch][5];
-#pragma unroll
-    for (int u = 0; u < kColBatch; ++u) {
-      const int bb = b0 + threadIdx.x + u * kColThreads;
-      cb[u] = 0;
-#pragma unroll
-      for (int v = 0; v < 5; ++v) pre[u][v] = 0;
-      if (bb < T) {
-        cb[u] = total[bb];
-        const int* bp = so.bin_pre + (size_t)bb * kBinPre;
-#pragma unroll
-        for (int v = 0; v < 5; ++v) pre[u][v] = bp[v];
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < kColBatch; ++u) {
-      const int bb = b0 + threadIdx.x + u * kColThreads;
-      if (bb >= T) continue;
-      const int w = bb >> 6;
-      const int c = cb[u];
-      const int nsp = spread_chunks(c, spc);
-      const int nip = (c + ipc - 1) / ipc;
-      const int ksp = size_class(c, spc), kip = size_class(c, ipc);
-      const int rec0 = wgpre[w * kWgVals + kWgRec] + pre[u][0];
-      const int first = cbase[0][ksp] + wgpre[w * kWgVals + kWgSp + ksp] + pre[u][3];
-      const int ifirst = cbase[1][kip] + wgpre[w * kWgVals + kWgIp + kip] + pre[u][4];
-      const int slot0 = wgpre[w * kWgVals + kWgSlot] + pre[u][2];
-      so.cursor[bb] = rec0;
-      so.sp_first[bb] = first;
-      so.sp_n[bb] = nsp;
-      // .w: the chunk's partial-tile slot when the bin is split, else -1
-      for (int r = 0; r < nsp; ++r)
-        so.sp_chunks[first + r] = make_int4(bb, rec0 + r * spc, min(spc, c - r * spc), nsp > 1 ? slot0 + r : -1);
-      for (int r = 0; r < nip; ++r)
-        so.ip_chunks[ifirst + r] = make_int4(bb, rec0 + r * ipc, min(ipc, c - r * ipc), nip);
-      if (nsp > 1) so.multi[wgpre[w * kWgVals + kWgMulti] + pre[u][1]] = bb;
-    }
-  }
-  if (threadIdx.x == 0) {
+  if (wv != 0) return;
+  if (bid == 0 && lane == 0) {
     int nsp_all = 0, nip_all = 0;
     for (int k = 0; k < kClasses; ++k) {
       nsp_all += tot[kWgSp + k];
@@ -347,8 +306,32 @@ __device__ __forceinline__ void bin_colscan_body(const ColscanArgs& a, int bid, 
     so.nch[3] = tot[kWgMulti];
     so.nch[4] = total[T];
     so.nch[5] = tot[kWgSlot];
-    *done = 0;
   }
+  if (bb >= T) return;
+  const int spc = so.sp_chunk, ipc = so.ip_chunk;
+  const int nsp = spread_chunks(c, spc);
+  const int nip = (c + ipc - 1) / ipc;
+  const int ksp = size_class(c, spc), kip = size_class(c, ipc);
+  // class bases, largest class first
+  int bsp = 0, bip = 0;
+#pragma unroll
+  for (int k = kClasses - 1; k >= 0; --k) {
+    if (k > ksp) bsp += tot[kWgSp + k];
+    if (k > kip) bip += tot[kWgIp + k];
+  }
+  const int rec0 = wpre[kWgRec] + pre[0];
+  const int first = bsp + wpre[kWgSp + ksp] + pre[3];
+  const int ifirst = bip + wpre[kWgIp + kip] + pre[4];
+  const int slot0 = wpre[kWgSlot] + pre[2];
+  so.cursor[bb] = rec0;
+  so.sp_first[bb] = first;
+  so.sp_n[bb] = nsp;
+  // .w: the chunk's partial-tile slot when the bin is split, else -1
+  for (int r = 0; r < nsp; ++r)
+    so.sp_chunks[first + r] = make_int4(bb, rec0 + r * spc, min(spc, c - r * spc), nsp > 1 ? slot0 + r : -1);
+  for (int r = 0; r < nip; ++r)
+    so.ip_chunks[ifirst + r] = make_int4(bb, rec0 + r * ipc, min(ipc, c - r * ipc), nip);
+  if (nsp > 1) so.multi[wpre[kWgMulti] + pre[1]] = bb;
 }
 
 // CURSORS: the workgroup's write cursors bin_base[b] + off[g][b] are staged in
@@ -1125,11 +1108,14 @@ hipError_t launch_bin_hist(const double* x, const double* y, int64_t M, BinGeom 
 int bin_scan_workgroups(int T) { return (T + 1 + 63) / 64; }
 
 hipError_t launch_bin_colscan(const uint16_t* hist, int G, int T, int* off, int* total, const BinScanOut& so,
-                              int* done, hipStream_t st) {
-  const int nwg = bin_scan_workgroups(T);
-  const int bytes = nwg * kWgVals * (int)sizeof(int);
-  const ColscanArgs a{hist, G, T, off, total, so, done};
-  return launch_or_record<ColscanArgs, bin_colscan_body, kColThreads>(a, nwg, bytes, st);
+                              hipStream_t st) {
+  const ColscanArgs a{hist, G, T, off, total, so};
+  return launch_or_record<ColscanArgs, bin_colscan_body, kColThreads>(a, bin_scan_workgroups(T), 0, st);
+}
+
+hipError_t launch_bin_scan(int T, const int* total, const BinScanOut& so, hipStream_t st) {
+  const ColscanArgs a{nullptr, 0, T, nullptr, const_cast<int*>(total), so};
+  return launch_or_record<ColscanArgs, bin_scan_body, kScanThreads>(a, bin_scan_workgroups(T), 0, st);
 }
 
 hipError_t launch_bin_scatter(const double* x, const double* y, int64_t M, BinGeom g, int ppw, int G,

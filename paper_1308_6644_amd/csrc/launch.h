@@ -100,9 +100,7 @@ struct ColscanArgs {
   int* off;
   int* total;
   BinScanOut so;
-  int* done;               // finished-workgroup counter (reset by the last one)
 };
-constexpr int kScanDone = 7;  // element of nch counting finished column-scan workgroups
 
 // Arguments of the binning kernels (histogram, scatter).
 struct BinArgs {
@@ -189,7 +187,8 @@ hipError_t launch_bin_hist(const double* x, const double* y, int64_t M, BinGeom 
                            uint16_t* hist, hipStream_t st);
 // column scan + bin scan (T bins; hist / off rows of T + 1 entries)
 hipError_t launch_bin_colscan(const uint16_t* hist, int G, int T, int* off, int* total, const BinScanOut& so,
-                              int* done, hipStream_t st);
+                              hipStream_t st);
+hipError_t launch_bin_scan(int T, const int* total, const BinScanOut& so, hipStream_t st);
 hipError_t launch_bin_scatter(const double* x, const double* y, int64_t M, BinGeom g, int ppw, int G,
                               const int* off, const int* bin_base, BinRec* recs, int* rej_end, bool stable,
                               hipStream_t st);

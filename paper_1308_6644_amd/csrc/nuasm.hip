@@ -259,8 +259,7 @@ struct PointSet {
   int* multi = nullptr;
   int* bin_pre = nullptr;    // [T][kBinPre] bin-scan prefixes
   int* wg_sum = nullptr;     // [column-scan workgroups][kBinPre] their sums
-  int* nch = nullptr;  // [8]: chunk and record counts [0..3], points out of range [4], split-bin slots [5],
-                       // scan hand-off counter [7]
+  int* nch = nullptr;  // [8]: chunk and record counts [0..3], points out of range [4], split-bin slots [5]
   int4* sp_chunks = nullptr;
   int4* ip_chunks = nullptr;
   int64_t chunk_cap = 0;
@@ -780,13 +779,16 @@ nuasm_status bind_points(nuasm_plan_s* pl, PointSet& q, int64_t M, const double*
       HIP_TRY(launch_bin_hist(x, y, M, pl->bgeom, ppw, G, q.hist, st), "launch bin_hist");
     }
     {
-      // column scan and bin scan in one launch; with no points (G = 0) it
-      // writes zero totals and empty-bin chunk tables
+      // column scan, then bin scan; with no points (G = 0) they write zero
+      // totals and empty-bin chunk tables
       const BinScanOut so{q.cursor, q.sp_chunks, q.sp_first, q.sp_n, q.multi, q.ip_chunks, q.nch,
                           q.bin_pre, q.wg_sum, pl->sp_chunk, pl->ip_chunk};
-      StageScope sc(pl, NUASM_STAGE_BIN_COLSCAN);
-      HIP_TRY(launch_bin_colscan(q.hist, M > 0 ? G : 0, pl->T, q.hoff, q.counts, so, q.nch + kScanDone, st),
-              "launch bin_colscan");
+      {
+        StageScope sc(pl, NUASM_STAGE_BIN_COLSCAN);
+        HIP_TRY(launch_bin_colscan(q.hist, M > 0 ? G : 0, pl->T, q.hoff, q.counts, so, st), "launch bin_colscan");
+      }
+      StageScope sc(pl, NUASM_STAGE_BIN_SCAN);
+      HIP_TRY(launch_bin_scan(pl->T, q.counts, so, st), "launch bin_scan");
     }
     StageScope sc(pl, NUASM_STAGE_BIN_SCATTER);
     HIP_TRY(launch_bin_scatter(x, y, M, pl->bgeom, ppw, G, q.hoff, q.cursor, q.recs, rej_end(q), stable_bins(pl),
@@ -1796,7 +1798,8 @@ static void assign_branches(nuasm_batch_s* b, const std::vector<int64_t>& M) {
 // launches are told apart by a stage offset (kStageBinB) when they are
 // collected, so that the two chains share nothing.
 constexpr int kStageBinB = 100;
-static const int kGroupOrderA[] = {NUASM_STAGE_BIN_HIST, NUASM_STAGE_BIN_COLSCAN, NUASM_STAGE_BIN_SCATTER,
+static const int kGroupOrderA[] = {NUASM_STAGE_BIN_HIST, NUASM_STAGE_BIN_COLSCAN, NUASM_STAGE_BIN_SCAN,
+                                   NUASM_STAGE_BIN_SCATTER,
                                    NUASM_STAGE_SPREAD,   NUASM_STAGE_SPREAD_REDUCE, NUASM_STAGE_T1_ROWS,
                                    NUASM_STAGE_T1_COLS,  NUASM_STAGE_T1_ROWS_INV};
 static const int kGroupOrderB[] = {NUASM_STAGE_T2_ROWS,
@@ -1804,6 +1807,7 @@ static const int kGroupOrderB[] = {NUASM_STAGE_T2_ROWS,
                                    NUASM_STAGE_T2_ROWS_INV,
                                    kStageBinB + NUASM_STAGE_BIN_HIST,
                                    kStageBinB + NUASM_STAGE_BIN_COLSCAN,
+                                   kStageBinB + NUASM_STAGE_BIN_SCAN,
                                    kStageBinB + NUASM_STAGE_BIN_SCATTER,
                                    NUASM_STAGE_INTERP};
 
@@ -1824,7 +1828,8 @@ static nuasm_status batch_collect(nuasm_batch_s* b, BatchGraph& g, F plane) {
     if (s != NUASM_OK) return fail(s, "plane " + std::to_string(p) + ": " + g_last_error);
     if (pl->p.type == NUASM_TYPE_2)
       for (RecordedLaunch& L : rec[p].launches)
-        if (L.stage == NUASM_STAGE_BIN_HIST || L.stage == NUASM_STAGE_BIN_COLSCAN || L.stage == NUASM_STAGE_BIN_SCATTER)
+        if (L.stage == NUASM_STAGE_BIN_HIST || L.stage == NUASM_STAGE_BIN_COLSCAN || L.stage == NUASM_STAGE_BIN_SCAN ||
+            L.stage == NUASM_STAGE_BIN_SCATTER)
           L.stage += kStageBinB;
   }
   // group: for each stage in pipeline order, one launch per instantiation

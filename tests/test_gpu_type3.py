@@ -191,7 +191,7 @@ def test_nuasm3_stage_timing(P):
     plan.execute(c)
     got = plan.read_timing()
     expect = dict(bin_hist=2, bin_colscan=2, bin_scatter=2, spread=1, spread_reduce=1, t1_rows=1, t3_cols=1,
-                  t2_rows_inv=1, interp=1, t1_cols=0, t1_rows_inv=0, t2_rows=0, t2_cols=0, bin_scan=0)
+                  t2_rows_inv=1, interp=1, t1_cols=0, t1_rows_inv=0, t2_rows=0, t2_cols=0, bin_scan=2)
     for st, n in expect.items():
         assert got[st][1] == n, (st, got[st])
 
