@@ -76,18 +76,24 @@ __device__ __forceinline__ void bin_hist_body(const BinArgs& a, int bid, int) {
   uint16_t* __restrict__ hist = a.hist;
   extern __shared__ unsigned sh[];
   const int T = g.TX * g.TX, TW = (T + 2) / 2;
-  for (int e = threadIdx.x; e < TW; e += kBinThreads) sh[e] = 0u;
-  __syncthreads();
   const int64_t j0 = (int64_t)bid * ppw;
   const int64_t j1 = min(M, j0 + ppw);
-  for (int64_t jb = j0; jb < j1; jb += kBinThreads * kBinBatch) {
-    double xv[kBinBatch], yv[kBinBatch];  // all loads of a batch in flight together
+  double xv[kBinBatch], yv[kBinBatch];  // all loads of a batch in flight together
+  // positions clamped into the range (never empty), so that no load sits
+  // behind a branch; points past its end are skipped where they are used
+  auto load = [&](int64_t jb) {
 #pragma unroll
     for (int q = 0; q < kBinBatch; ++q) {
-      const int64_t j = jb + threadIdx.x + q * kBinThreads;
-      xv[q] = j < j1 ? x[j] : 0.0;
-      yv[q] = j < j1 ? y[j] : 0.0;
+      const int64_t j = min(jb + threadIdx.x + q * kBinThreads, j1 - 1);
+      xv[q] = x[j];
+      yv[q] = y[j];
     }
+  };
+  load(j0);  // the first batch in flight while the counters are cleared
+  for (int e = threadIdx.x; e < TW; e += kBinThreads) sh[e] = 0u;
+  __syncthreads();
+  for (int64_t jb = j0; jb < j1; jb += kBinThreads * kBinBatch) {
+    if (jb != j0) load(jb);
 #pragma unroll
     for (int q = 0; q < kBinBatch; ++q) {
       const int64_t j = jb + threadIdx.x + q * kBinThreads;
@@ -351,38 +357,58 @@ __device__ __forceinline__ void bin_scatter_body(const BinArgs& a, int bid, int)
   extern __shared__ unsigned sh[];
   const int T = g.TX * g.TX, TW = (T + 1) / 2;
   const int* myoff = off + (size_t)bid * (T + 1);
+  const int64_t j0 = (int64_t)bid * ppw;
+  const int64_t j1 = min(M, j0 + ppw);
+  double xv[kBinBatch], yv[kBinBatch];
+  // positions clamped into the range (never empty), so that no load sits
+  // behind a branch; points past its end are skipped where they are used
+  auto load = [&](int64_t jb) {
+#pragma unroll
+    for (int q = 0; q < kBinBatch; ++q) {
+      const int64_t j = min(jb + threadIdx.x + q * kBinThreads, j1 - 1);
+      xv[q] = x[j];
+      yv[q] = y[j];
+    }
+  };
+  load(j0);  // the first batch in flight with the cursor staging
   if (CURSORS) {
     // the loads of eight bins per thread in flight together (clamped
     // addresses), then the LDS writes; entry T is the cursor of the range's
     // points outside the window
+    // Every load and LDS write is unconditional (no load behind a branch): an
+    // entry past T is clamped to T and written, with the same value, by
+    // several lanes.
     constexpr int NB = 8;
-    for (int b0 = 0; b0 <= T; b0 += kBinThreads * NB) {
-      unsigned v[NB];
+    int base[NB], o[NB];
+    auto stage_load = [&](int b0) {
 #pragma unroll
       for (int u = 0; u < NB; ++u) {
         const int b = min(b0 + (int)threadIdx.x + u * kBinThreads, T);
-        v[u] = (unsigned)((b < T ? bin_base[min(b, T - 1)] : 0) + myoff[b]);
+        base[u] = bin_base[min(b, T - 1)];
+        o[u] = myoff[b];
       }
+    };
+    auto stage_write = [&](int b0) {
 #pragma unroll
       for (int u = 0; u < NB; ++u) {
-        const int b = b0 + (int)threadIdx.x + u * kBinThreads;
-        if (b <= T) sh[b] = v[u];
+        const int b = min(b0 + (int)threadIdx.x + u * kBinThreads, T);
+        sh[b] = (unsigned)((b < T ? base[u] : 0) + o[u]);
       }
+    };
+    stage_load(0);
+    // every load above (and the first coordinates) issued before any is used
+    __builtin_amdgcn_sched_barrier(0);
+    stage_write(0);
+    for (int b0 = kBinThreads * NB; b0 <= T; b0 += kBinThreads * NB) {
+      stage_load(b0);
+      stage_write(b0);
     }
   } else {
     for (int e = threadIdx.x; e < TW; e += kBinThreads) sh[e] = 0u;
   }
   __syncthreads();
-  const int64_t j0 = (int64_t)bid * ppw;
-  const int64_t j1 = min(M, j0 + ppw);
   for (int64_t jb = j0; jb < j1; jb += kBinThreads * kBinBatch) {
-    double xv[kBinBatch], yv[kBinBatch];
-#pragma unroll
-    for (int q = 0; q < kBinBatch; ++q) {
-      const int64_t j = jb + threadIdx.x + q * kBinThreads;
-      xv[q] = j < j1 ? x[j] : 0.0;
-      yv[q] = j < j1 ? y[j] : 0.0;
-    }
+    if (jb != j0) load(jb);
 #pragma unroll
     for (int q = 0; q < kBinBatch; ++q) {
       const int64_t j = jb + threadIdx.x + q * kBinThreads;
@@ -790,6 +816,12 @@ struct __align__(16) MfmaRec {
 // workgroups per CU, which hide the load and LDS latencies.
 constexpr int kMfmaSB = kSpreadThreads;
 
+// What an empty chunk (a bin with no records, which still writes its zero
+// tile) reads in place of its first record and that record's value: every
+// load of the kernel stays unconditional and in bounds.
+__device__ const BinRec kNoRecord = {0, 0.f, 0.f, 0};
+__device__ const float2 kNoValue = {0.f, 0.f};
+
 template <int W, int TILE>
 __device__ __forceinline__ void spread_mfma_body(const SpreadArgs& a, int bid, int) {
   constexpr int SB = kMfmaSB, NWV = kSpreadThreads / 64;  // 4 waves
@@ -812,8 +844,13 @@ __device__ __forceinline__ void spread_mfma_body(const SpreadArgs& a, int bid, i
   __shared__ int sbase[NWV][NQ];
   __shared__ int slen[NQ];
   const int cid = bid;
-  if (cid >= a.nchunks[0]) return;
+  // count and descriptor requested together (in bounds: the launch grid never
+  // exceeds the table's capacity)
+  const int nchunks = a.nchunks[0];
   const int4 ch = a.chunks[cid];
+  // (bin, first record and count are never negative: testing them keeps the
+  // descriptor's load ahead of the branch)
+  if ((cid >= nchunks) | ((ch.x | ch.y | ch.z) < 0)) return;
   const int bin = ch.x, start = ch.y, n = ch.z, slot = ch.w;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const float blog = a.beta * 1.4426950408889634f;
@@ -840,8 +877,10 @@ __device__ __forceinline__ void spread_mfma_body(const SpreadArgs& a, int bid, i
   // behind a branch (a load whose result merges with a default at a branch
   // join is waited for at once, which would serialise the prefetch below).
   const int last = start + n - 1;
-  BinRec rc = a.recs[min(start + t, last)];
-  float2 cv = a.vals[rc.idx];
+  const BinRec* rsrc = n > 0 ? a.recs + min(start + t, last) : &kNoRecord;
+  BinRec rc = *rsrc;
+  const float2* vsrc = n > 0 ? a.vals : &kNoValue;  // kNoRecord.idx = 0
+  float2 cv = vsrc[rc.idx];
   for (int b0 = 0; b0 < n; b0 += SB) {
     const int nsb = min(SB, n - b0);
     const bool ok = t < nsb;
@@ -1010,40 +1049,50 @@ __device__ __forceinline__ void interp_body(const InterpArgs& a, int bid, int) {
   constexpr int NT = kInterpThreads, B = kInterpBatch;
   __shared__ float2 sg[RS * RS];
   const int cid = bid;
-  if (cid >= a.nchunks[0]) return;
+  // the chunk count and the descriptor requested together (the launch grid
+  // never exceeds the table's capacity, so the read is in bounds even for a
+  // workgroup beyond the count, which leaves)
+  const int nchunks = a.nchunks[0];
   const int4 ch = a.chunks[cid];
+  // (bin, first record and count are never negative: testing them keeps the
+  // descriptor's load ahead of the branch)
+  if ((cid >= nchunks) | ((ch.x | ch.y | ch.z) < 0)) return;
   const int bin = ch.x, start = ch.y, n = ch.z;
   const int bx = bin % a.TX, by = bin / a.TX;
   const int t = threadIdx.x;
+  // the first batch of records, in flight with the staging below (positions
+  // clamped into the chunk, which is never empty; validity is checked on use)
+  BinRec rl[B];
+#pragma unroll
+  for (int q = 0; q < B; ++q) rl[q] = a.recs[start + min(t + q * NT, n - 1)];
   {
     // every load of the staging first (clamped addresses, values selected
-    // afterwards), then the LDS writes: one memory latency, not one per element
+    // afterwards), then the LDS writes: one memory latency, not one per
+    // element.  The writes are unconditional (no load is moved behind a
+    // branch): a clamped element is written by several lanes, with one value.
     constexpr int NS = (RS * RS + NT - 1) / NT;
     float2 v[NS];
+    int e[NS];
 #pragma unroll
     for (int u = 0; u < NS; ++u) {
-      const int e = min(t + u * NT, RS * RS - 1);
-      const int gy = by * TILE + e / RS, gx = bx * TILE + e % RS;
+      e[u] = min(t + u * NT, RS * RS - 1);
+      const int gy = by * TILE + e[u] / RS, gx = bx * TILE + e[u] % RS;
       v[u] = a.grid[(size_t)min(gy, a.L - 1) * a.L + min(gx, a.L - 1)];
       if (gy >= a.L || gx >= a.L) v[u] = czero();
     }
 #pragma unroll
-    for (int u = 0; u < NS; ++u)
-      if (t + u * NT < RS * RS) sg[t + u * NT] = v[u];
+    for (int u = 0; u < NS; ++u) sg[e[u]] = v[u];
   }
   __syncthreads();
   const float blog = a.beta * 1.4426950408889634f;
   for (int r0 = 0; r0 < n; r0 += NT * B) {
-    BinRec rl[B];
+    if (r0 > 0) {
 #pragma unroll
-    for (int q = 0; q < B; ++q) {
-      const int r = r0 + t + q * NT;
-      rl[q].packed = 0;  // not primary
-      if (r < n) rl[q] = a.recs[start + r];
+      for (int q = 0; q < B; ++q) rl[q] = a.recs[start + min(r0 + t + q * NT, n - 1)];
     }
 #pragma unroll
     for (int q = 0; q < B; ++q) {
-      if (!rec_primary(rl[q].packed)) continue;
+      if (r0 + t + q * NT >= n || !rec_primary(rl[q].packed)) continue;
       const int lx = rec_lx(rl[q].packed), ly = rec_ly(rl[q].packed);
       float wx[W];
 #pragma unroll
