@@ -266,6 +266,7 @@ def batched_workload(a, torch, P, synth):
     total = sum(int(x.numel()) for x in xs)
     plans = [P.Plan(defer_range_check=True, **s) for s in specs]
     batch = P.Batch(specs)
+    batch.set_plane_times(False)  # throughput without completion stamps; latency measured apart
 
     def seq_step(ev=None):
         for i, pl in enumerate(plans):
@@ -298,8 +299,10 @@ def batched_workload(a, torch, P, synth):
             torch.cuda.synchronize()
             lat = [s0.elapsed_time(e) for e in evs]
         else:
+            batch.set_plane_times(True)
             batch.run(xs, ys, ins, outs)
             lat = batch.plane_times()
+            batch.set_plane_times(False)
         lat = np.asarray(lat)
         res[mode] = {"ms_per_step": ms, "points_per_s": total / (ms * 1e-3),
                      "latency_ms_p50": float(np.percentile(lat, 50)),
@@ -900,6 +903,7 @@ def main(argv=None):
     tuning = None
     if a.mode == "graph":
         batch = P.Batch([r["spec"] for r in runs])
+        batch.set_plane_times(False)  # no per-plane completion stamps in the timed graph
         bx = [r["x"] for r in runs]
         by = [r["y"] for r in runs]
         bi = [r["inp"] for r in runs]

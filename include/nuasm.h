@@ -421,9 +421,18 @@ nuasm_status nuasm_batch_set_grouped(nuasm_batch batch, int32_t grouped);
 /* Synchronise; *bad_plane = index of the first plane with out-of-range
  * points in the last run, or -1. */
 nuasm_status nuasm_batch_check_points(nuasm_batch batch, int32_t* bad_plane);
+/* Completion stamps for nuasm_batch_plane_times (enabled = 1, the default)
+ * or none (0): each stamp is one small launch on its graph branch after the
+ * launch that completes its planes (in the grouped form one stamp serves
+ * every plane a grouped launch completes), plus one at the start.  A change
+ * drops the recorded graphs. */
+nuasm_status nuasm_batch_set_plane_times(nuasm_batch batch, int32_t enabled);
 /* Synchronise; ms[p] = device wall-clock time from the start of the last
  * recorded-graph launch (run, set_points_many or execute_many) to the
- * completion of plane p (caller-owned host array of P floats). */
+ * completion of plane p (caller-owned host array of P floats).  A plane with
+ * no launch (no points, type 2 with nothing to do) completes at 0.
+ * NUASM_ERR_NOT_READY when stamps are off or no recorded graph has run since
+ * the graphs were last dropped. */
 nuasm_status nuasm_batch_plane_times(nuasm_batch batch, float* ms);
 
 const char* nuasm_status_string(nuasm_status s);

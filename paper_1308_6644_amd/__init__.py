@@ -123,6 +123,7 @@ _SIGS = {
     "nuasm_plan_set_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
     "nuasm_batch_check_points": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     "nuasm_batch_plane_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float)]),
+    "nuasm_batch_set_plane_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "nuasm_rs_direct": (ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                        ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
@@ -497,6 +498,10 @@ class Batch:
         bad = ctypes.c_int32(-1)
         _check(load().nuasm_batch_check_points(self._h, ctypes.byref(bad)))
         return bad.value
+
+    def set_plane_times(self, enabled: bool):
+        """Record completion stamps for plane_times (default) or none."""
+        _check(load().nuasm_batch_set_plane_times(self._h, 1 if enabled else 0))
 
     def plane_times(self):
         """Milliseconds from the start of the last run to each plane's completion."""

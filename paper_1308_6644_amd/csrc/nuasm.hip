@@ -1708,6 +1708,7 @@ struct BatchGraph {
   bool grouped = false;
   std::vector<GroupedStage> stages;
   char* tables = nullptr;  // device: every grouped stage's entry table and block offsets
+  std::vector<int> slot_of;  // plane -> its completion stamp in ts (0: finished at the start)
 };
 
 struct nuasm_batch_s {
@@ -1723,7 +1724,9 @@ struct nuasm_batch_s {
   // one-shot (binning + operator), binning alone, operator alone
   BatchGraph g_run, g_bin, g_exec;
   bool grouped = true;         // grouped stage launches (nuasm_batch_set_grouped)
-  long long* ts = nullptr;     // [P + 1] device wall-clock stamps
+  bool stamps = true;          // completion stamps recorded (nuasm_batch_set_plane_times)
+  long long* ts = nullptr;     // [P + 1] device wall-clock stamps: the start, then completions
+  const BatchGraph* last = nullptr;  // the graph launched last
   int clock_khz = 0;
 };
 
@@ -1738,6 +1741,7 @@ void drop_graph(BatchGraph& g) {
   if (g.tables) (void)dev_free(g.tables);
   g.tables = nullptr;
   g.stages.clear();
+  g.slot_of.clear();
   g.grouped = false;
 }
 
@@ -1886,27 +1890,34 @@ static nuasm_status batch_collect(nuasm_batch_s* b, BatchGraph& g, F plane) {
   return NUASM_OK;
 }
 
-// Enqueue the grouped launches of one chain (stages in `order`) on stream st,
-// a completion stamp after each launch for the planes it finishes.  After
-// stage `wait_before` (if any) the chain first waits for event `ev`.
-static hipError_t enqueue_chain(nuasm_batch_s* b, const BatchGraph& g, const int* order, int norder,
-                                hipStream_t st, std::vector<int>& last_stage_of) {
+// Enqueue the grouped launches of the two chains (stages in orderA on sA,
+// orderB on sB), one stage of each in turn: the graph launches its nodes in
+// recorded order, so neither chain's first kernels wait for the other chain's
+// whole submission.  With stamps on, a launch that finishes planes (their
+// last grouped launch) is followed by one completion stamp in the next free
+// slot of ts, which g.slot_of maps them to.
+static hipError_t enqueue_chains(nuasm_batch_s* b, BatchGraph& g, const int* orderA, int nA, hipStream_t sA,
+                                 const int* orderB, int nB, hipStream_t sB, const std::vector<int>& last_stage_of) {
   hipError_t e = hipSuccess;
-  for (int k = 0; k < norder && e == hipSuccess; ++k) {
-    const int stage = order[k];
+  int next_slot = 1;
+  auto stage_launches = [&](int stage, hipStream_t st) {
     for (size_t i = 0; i < g.stages.size() && e == hipSuccess; ++i) {
       const GroupedStage& gs = g.stages[i];
       if (gs.stage != stage) continue;
       e = gs.grouped(g.tables + gs.tab_off, (const int*)(g.tables + gs.first_off), gs.n, gs.blocks, gs.lds, st);
-      // a plane is finished after the last grouped launch it is in
+      if (e != hipSuccess || !b->stamps) continue;
       bool finishes = false;
       for (int p : gs.planes)
-        if (last_stage_of[p] == (int)i) finishes = true;
-      if (e == hipSuccess && finishes) {
-        for (int p : gs.planes)
-          if (last_stage_of[p] == (int)i) e = launch_stamp(b->ts + 1 + p, st);
-      }
+        if (last_stage_of[p] == (int)i) {
+          finishes = true;
+          g.slot_of[p] = next_slot;
+        }
+      if (finishes) e = launch_stamp(b->ts + next_slot++, st);
     }
+  };
+  for (int k = 0; k < std::max(nA, nB) && e == hipSuccess; ++k) {
+    if (k < nA) stage_launches(orderA[k], sA);
+    if (k < nB && e == hipSuccess) stage_launches(orderB[k], sB);
   }
   return e;
 }
@@ -1924,6 +1935,7 @@ static nuasm_status batch_launch(nuasm_batch_s* b, BatchGraph& g, const std::vec
                                  const std::vector<int64_t>& M, F plane) {
   const int P = (int)b->plans.size();
   auto launch = [&]() -> nuasm_status {
+    b->last = &g;
     HIP_TRY(hipEventRecord(b->ev_in, b->stream), "hipEventRecord");
     HIP_TRY(hipStreamWaitEvent(b->cap, b->ev_in, 0), "hipStreamWaitEvent");
     HIP_TRY(hipGraphLaunch(g.exec, b->cap), "hipGraphLaunch");
@@ -1958,12 +1970,13 @@ static nuasm_status batch_launch(nuasm_batch_s* b, BatchGraph& g, const std::vec
   if (!b->grouped) assign_branches(b, M);
   HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
   nuasm_status st = NUASM_OK;
-  hipError_t e = launch_stamp(b->ts, b->cap);
+  // planes with no launch at all finish at the start (slot 0)
+  g.slot_of.assign(P, 0);
+  hipError_t e = b->stamps ? launch_stamp(b->ts, b->cap) : hipSuccess;
   if (e == hipSuccess) e = hipEventRecord(b->fork, b->cap);
   if (b->grouped) {
     // two independent chains: the type-1 planes (binning, operator) on branch
-    // 0, the type-2 planes (grid passes, binning, interpolation) on branch 1;
-    // stamps per plane
+    // 0, the type-2 planes (grid passes, binning, interpolation) on branch 1
     std::vector<int> last(P, -1);
     for (size_t i = 0; i < g.stages.size(); ++i)
       for (int p : g.stages[i].planes) last[p] = (int)i;
@@ -1971,12 +1984,8 @@ static nuasm_status batch_launch(nuasm_batch_s* b, BatchGraph& g, const std::vec
     if (e == hipSuccess) e = hipStreamWaitEvent(s0, b->fork, 0);
     if (e == hipSuccess) e = hipStreamWaitEvent(s1, b->fork, 0);
     if (e == hipSuccess)
-      e = enqueue_chain(b, g, kGroupOrderA, (int)(sizeof(kGroupOrderA) / sizeof(int)), s0, last);
-    if (e == hipSuccess)
-      e = enqueue_chain(b, g, kGroupOrderB, (int)(sizeof(kGroupOrderB) / sizeof(int)), s1, last);
-    // planes with no launch at all (no points, type 2) finish at once
-    for (int p = 0; e == hipSuccess && p < P; ++p)
-      if (last[p] < 0) e = launch_stamp(b->ts + 1 + p, s0);
+      e = enqueue_chains(b, g, kGroupOrderA, (int)(sizeof(kGroupOrderA) / sizeof(int)), s0, kGroupOrderB,
+                         (int)(sizeof(kGroupOrderB) / sizeof(int)), s1, last);
     for (size_t k = 0; e == hipSuccess && k < 2; ++k) {
       e = hipEventRecord(b->join[k], b->branch[k]);
       if (e == hipSuccess) e = hipStreamWaitEvent(b->cap, b->join[k], 0);
@@ -1988,7 +1997,10 @@ static nuasm_status batch_launch(nuasm_batch_s* b, BatchGraph& g, const std::vec
       nuasm_plan_s* pl = b->plans[p];
       pl->stream = b->branch[b->branch_of[p]];
       st = plane(pl, p);
-      if (st == NUASM_OK) e = launch_stamp(b->ts + 1 + p, pl->stream);
+      if (st == NUASM_OK && b->stamps) {
+        g.slot_of[p] = 1 + p;
+        e = launch_stamp(b->ts + 1 + p, pl->stream);
+      }
     }
     for (size_t k = 0; e == hipSuccess && k < (size_t)b->active; ++k) {
       e = hipEventRecord(b->join[k], b->branch[k]);
@@ -2207,13 +2219,27 @@ nuasm_status nuasm_batch_check_points(nuasm_batch b, int32_t* bad_plane) {
   return NUASM_OK;
 }
 
+nuasm_status nuasm_batch_set_plane_times(nuasm_batch b, int32_t enabled) {
+  if (!b) return fail(NUASM_ERR_INVALID_ARG, "batch is NULL");
+  if (enabled != 0 && enabled != 1) return fail(NUASM_ERR_INVALID_ARG, "enabled must be 0 or 1");
+  if (b->stamps == (enabled != 0)) return NUASM_OK;
+  nuasm_status s = batch_invalidate(b);
+  if (s != NUASM_OK) return s;
+  b->stamps = enabled != 0;
+  b->last = nullptr;
+  return NUASM_OK;
+}
+
 nuasm_status nuasm_batch_plane_times(nuasm_batch b, float* ms) {
   if (!b || !ms) return fail(NUASM_ERR_INVALID_ARG, "NULL argument");
+  if (!b->stamps) return fail(NUASM_ERR_NOT_READY, "plane times are off (nuasm_batch_set_plane_times)");
+  if (!b->last || !b->last->exec) return fail(NUASM_ERR_NOT_READY, "no recorded graph has run");
   HIP_TRY(hipStreamSynchronize(b->cap), "hipStreamSynchronize");
   const size_t P = b->plans.size();
   std::vector<long long> h(P + 1);
   HIP_TRY(hipMemcpy(h.data(), b->ts, sizeof(long long) * (P + 1), hipMemcpyDeviceToHost), "hipMemcpy");
-  for (size_t p = 0; p < P; ++p) ms[p] = (float)((double)(h[p + 1] - h[0]) / (double)b->clock_khz);
+  const std::vector<int>& slot = b->last->slot_of;
+  for (size_t p = 0; p < P; ++p) ms[p] = (float)((double)(h[slot[p]] - h[0]) / (double)b->clock_khz);
   return NUASM_OK;
 }
 

@@ -98,4 +98,18 @@ def test_grouped_and_per_plane_forms_match_plain_plans():
                 check_close(host(o2[p]), r, 1e-6, what=f"many grouped={grouped} rep={rep} plane {p}")
         t = b.plane_times()
         assert len(t) == len(specs) and all(v > 0 for v in t)
+        # without completion stamps: the same results; plane times refused
+        b.set_plane_times(False)
+        o3 = outs()
+        b.run(xs, ys, ins, o3)
+        for p, r in enumerate(refs):
+            check_close(host(o3[p]), r, 1e-6, what=f"no stamps grouped={grouped} plane {p}")
+        with pytest.raises(P.NuasmError):
+            b.plane_times()
+        b.set_plane_times(True)
+        with pytest.raises(P.NuasmError):
+            b.plane_times()  # the graphs were dropped: nothing has run since
+        b.run(xs, ys, ins, o3)
+        t2 = b.plane_times()
+        assert all(v > 0 for v in t2)
         b.close()
