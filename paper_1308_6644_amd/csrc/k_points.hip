@@ -1044,7 +1044,7 @@ constexpr int kInterpBatch = 4;
 // (launch bound: at least 5 waves per SIMD, i.e. at most 96 VGPRs)
 
 template <int W, int TILE>
-__device__ __forceinline__ void interp_body(const InterpArgs& a, int bid, int) {
+__device__ __forceinline__ void interp_body(const InterpArgs& a, int bid, int nbid) {
   constexpr int RS = TILE + W - 1;
   constexpr int NT = kInterpThreads, B = kInterpBatch;
   __shared__ float2 sg[RS * RS];
@@ -1054,6 +1054,11 @@ __device__ __forceinline__ void interp_body(const InterpArgs& a, int bid, int) {
   // workgroup beyond the count, which leaves)
   const int nchunks = a.nchunks[0];
   const int4 ch = a.chunks[cid];
+  const int nrej = a.nrej[0];
+  // points outside the window (a deferred range check; they have no
+  // records): NaN at their outputs, strided over every workgroup
+  for (int i = bid * kInterpThreads + (int)threadIdx.x; i < nrej; i += nbid * kInterpThreads)
+    a.out[a.rej_end[-1 - i]] = make_float2(__builtin_nanf(""), __builtin_nanf(""));
   // (bin, first record and count are never negative: testing them keeps the
   // descriptor's load ahead of the branch)
   if ((cid >= nchunks) | ((ch.x | ch.y | ch.z) < 0)) return;
@@ -1189,20 +1194,6 @@ hipError_t launch_bin_scatter(const double* x, const double* y, int64_t M, BinGe
   if ((T + 1) * 4 <= kScatterCursorBytes)
     return launch_or_record<BinArgs, bin_scatter_body<true>, kBinThreads>(a, G, (T + 1) * 4, st);
   return launch_or_record<BinArgs, bin_scatter_body<false>, kBinThreads>(a, G, ((T + 1) / 2) * 4, st);
-}
-
-// NaN at the output slot of every point outside the window (a fixed grid
-// striding over their count, which only the device knows).
-constexpr int kRejThreads = 256, kRejBlocks = 64;
-__device__ __forceinline__ void fill_rejected_body(const RejArgs& a, int bid, int nbid) {
-  const int n = a.nrej[0];
-  const float nan = __builtin_nanf("");
-  for (int i = bid * kRejThreads + (int)threadIdx.x; i < n; i += nbid * kRejThreads)
-    a.out[a.rej_end[-1 - i]] = make_float2(nan, nan);
-}
-
-hipError_t launch_fill_rejected(const RejArgs& a, hipStream_t st) {
-  return launch_or_record<RejArgs, fill_rejected_body, kRejThreads>(a, kRejBlocks, 0, st);
 }
 
 #define NUASM_DISPATCH_W(w, CALL)                                                   \

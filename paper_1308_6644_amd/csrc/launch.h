@@ -120,11 +120,6 @@ struct BinArgs {
 };
 
 // Outputs of the points outside the window (deferred range check) set to NaN.
-struct RejArgs {
-  float2* out;
-  const int* rej_end;  // rejected caller indices at rej_end[-1 - i]
-  const int* nrej;     // their count (device)
-};
 
 struct SpreadArgs {
   const BinRec* recs;
@@ -156,6 +151,8 @@ struct InterpArgs {
   const int* nchunks;
   const float2* grid;
   float2* out;            // caller order
+  const int* rej_end;     // end of the list of points outside the window (indices stored downwards)
+  const int* nrej;        // their count (0 once a synchronised set_points has accepted every point)
   int L, TX;
   float two_over_w, beta;
 };
@@ -192,7 +189,6 @@ hipError_t launch_bin_scan(int T, const int* total, const BinScanOut& so, hipStr
 hipError_t launch_bin_scatter(const double* x, const double* y, int64_t M, BinGeom g, int ppw, int G,
                               const int* off, const int* bin_base, BinRec* recs, int* rej_end, bool stable,
                               hipStream_t st);
-hipError_t launch_fill_rejected(const RejArgs& a, hipStream_t st);
 hipError_t launch_spread(int w, bool small_chunks, const SpreadArgs& a, int grid, hipStream_t st);
 // the same spreading as sums of outer products on the matrix cores
 hipError_t launch_spread_mfma(int w, int tile, const SpreadArgs& a, int grid, hipStream_t st);

@@ -947,17 +947,16 @@ nuasm_status run_interp(nuasm_plan_s* pl, PointSet& q, const float2* grid, float
   ia.nchunks = q.nch + 1;
   ia.grid = grid;
   ia.out = out;
+  // a deferred range check may have left points without records; the kernel
+  // writes NaN at their outputs (a synchronised set_points refuses such
+  // points, so their count is then 0)
+  ia.rej_end = rej_end(q);
+  ia.nrej = q.nch + 4;
   ia.L = pl->geom.L;
   ia.TX = pl->TX;
   ia.two_over_w = 2.0f / (float)pl->w;
   ia.beta = pl->beta;
   HIP_TRY(launch_interp(pl->w, pl->tile, ia, ip_grid(pl, q), pl->stream), "launch interp");
-  if (!q.synced) {
-    // a deferred range check may have left points without records: NaN at
-    // their outputs (a synchronised set_points refuses such points)
-    const RejArgs ra{out, rej_end(q), q.nch + 4};
-    HIP_TRY(launch_fill_rejected(ra, pl->stream), "launch fill_rejected");
-  }
   return NUASM_OK;
 }
 
