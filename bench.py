@@ -350,7 +350,7 @@ def stage_pass(runs, seq_step, steps, torch, bytes_fn=None):
     return stages, per_type_ms
 
 
-def roofline(stages, steps):
+def roofline(stages, steps, no_counters=()):
     """Roofline object of the dominant kernel and the per-stage report.
 
     achieved / frac: the kernel's algorithmic bytes per launch over its
@@ -372,7 +372,9 @@ def roofline(stages, steps):
     roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": None, "avg_launch_us": avg_ms * 1e3,
             "hbm_algorithmic_frac": achieved / HBM_PEAK_GBS}
-    rec = counter_record(dom)
+    # (no_counters: stages whose kernel here is not the one the committed
+    # counters were taken on)
+    rec = None if dom in no_counters else counter_record(dom)
     t_launch = avg_ms * 1e-3
     if rec is not None:
         traffic = float(rec["fetch_bytes"]) + float(rec["write_bytes"])
@@ -743,7 +745,9 @@ def scaled_workload(a, torch, P, synth):
                 return (8.0 * info["L"] * info["L"] + 8.0 * M2) * n
             return stage_bytes(st, info) * n
         stages, _ = stage_pass(runs, step_grid, a.profile_steps, torch, gbytes)
-        roof, report = roofline(stages, a.profile_steps)
+        # the grid interpolation kernels are not the binned ones the counters
+        # describe
+        roof, report = roofline(stages, a.profile_steps, no_counters=("interp",))
         line.update({"roofline": roof, "stages": report})
     print(json.dumps(line), flush=True)
     return 0
@@ -998,7 +1002,10 @@ def main(argv=None):
     # second pass: per-stage HIP events recorded by the library
     print(f"[bench] per-stage timing {a.profile_steps} steps", file=sys.stderr, flush=True)
     stages, per_type_ms = stage_pass(runs, seq_step, a.profile_steps, torch)
-    roof, stage_report = roofline(stages, a.profile_steps)
+    # the counters were taken on the default scatter, not the stable one
+    roof, stage_report = roofline(stages, a.profile_steps,
+                                  no_counters=("bin_scatter", "bin_colscan", "bin_hist", "bin_scan")
+                                  if a.deterministic else ())
     cbw = copy_bandwidth(torch)
     roof["copy_GBps"] = cbw
     # the kernel's algorithmic bandwidth against the measured device copy
