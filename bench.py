@@ -887,8 +887,10 @@ def main(argv=None):
     for z in ZS:
         for tf, band in TFS:
             for t in (1, 2):
+                # the type-2 runs are never adjoined: their points are binned
+                # for interpolation alone (one record per point)
                 spec = dict(N=N, type=t, lam=LAM, z=z, g=G, tf=tf, band=band, ox=OX, oy=OY, tol=TOL,
-                            deterministic=a.deterministic)
+                            deterministic=a.deterministic, forward_only=t == 2)
                 plan = P.Plan(defer_range_check=True, **spec)
                 if t == 1:
                     x, y, inp = d["x1"], d["y1"], d["c1"]

@@ -95,6 +95,12 @@ enum { NUASM_BAND_FULL = 0, NUASM_BAND_LIMITED = 1, NUASM_BAND_EXPLICIT = 2 };
                                          each sub-batch stably, so every sum
                                          runs in one order on every run, in
                                          every plan and batch */
+#define NUASM_FORWARD_ONLY      0x10u /* type 2 only: the points are binned for
+                                         interpolation alone, one record per
+                                         point (in the bin of its first tap)
+                                         instead of one per bin its taps touch;
+                                         nuasm_execute_adjoint (which spreads)
+                                         returns NUASM_ERR_UNSUPPORTED */
 
 typedef struct {
   int32_t type;        /* NUASM_TYPE_1, NUASM_TYPE_2 or NUASM_TYPE_3 */
@@ -112,7 +118,9 @@ typedef struct {
   double band_c[2];    /* NUASM_BAND_EXPLICIT: band centre (c_m, c_n), index units */
   double band_w[2];    /* NUASM_BAND_EXPLICIT: band width  (w_m, w_n), index units */
   double tol;          /* spreading-kernel tolerance, 1e-12 .. 1e-2 */
-  uint32_t flags;      /* NUASM_OUT_CROP_N (type 1 only) | NUASM_DEFER_RANGE_CHECK */
+  uint32_t flags;      /* NUASM_OUT_CROP_N (type 1 only) | NUASM_DEFER_RANGE_CHECK |
+                          NUASM_FULL_FINE_GRID | NUASM_DETERMINISTIC |
+                          NUASM_FORWARD_ONLY (type 2 only) */
   uint32_t reserved;   /* must be 0 */
 } nuasm_params;
 
@@ -282,8 +290,9 @@ nuasm_status nuasm_execute_noalloc(nuasm_plan plan, const void* in_dev, void* ou
 /* Apply the adjoint (conjugate transpose) of the plan's operator, derived
  * from Eqs. 6 and 9 by reversing every step and conjugating H.  Type 1:
  * in_dev = v[N'][N'], out_dev = w[M].  Type 2: in_dev = w[M], out_dev =
- * u1'[N][N].  Type 3: in_dev = w[M_dest], out_dev = c'[M] (the type-3
- * operator from the destination to the source points with conj H). */
+ * u1'[N][N] (NUASM_ERR_UNSUPPORTED for a NUASM_FORWARD_ONLY plan).  Type 3:
+ * in_dev = w[M_dest], out_dev = c'[M] (the type-3 operator from the
+ * destination to the source points with conj H). */
 nuasm_status nuasm_execute_adjoint(nuasm_plan plan, const void* in_dev, void* out_dev);
 
 /* Write the transfer function exactly as the fused spectral kernel applies

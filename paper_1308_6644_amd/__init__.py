@@ -29,6 +29,7 @@ OUT_CROP_N = 0x1
 DEFER_RANGE_CHECK = 0x2
 FULL_FINE_GRID = 0x4
 DETERMINISTIC = 0x8
+FORWARD_ONLY = 0x10
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -177,7 +178,7 @@ def make_params(N: int, type: int, lam: float, z: float, g: float, *, tf: str = 
                 ox: float = 0.0, oy: float = 0.0, band: str = "full", band_c=(0.0, 0.0),
                 band_w=(0.0, 0.0), tol: float = 1e-6, phase_fp64: bool = True, crop: bool = False,
                 defer_range_check: bool = False, full_fine_grid: bool = False,
-                deterministic: bool = False) -> Params:
+                deterministic: bool = False, forward_only: bool = False) -> Params:
     lib = load()
     p = Params()
     _check(lib.nuasm_params_default(ctypes.byref(p)))
@@ -194,7 +195,8 @@ def make_params(N: int, type: int, lam: float, z: float, g: float, *, tf: str = 
     p.band_w[0], p.band_w[1] = float(band_w[0]), float(band_w[1])
     p.tol = float(tol)
     p.flags = ((OUT_CROP_N if crop else 0) | (DEFER_RANGE_CHECK if defer_range_check else 0)
-               | (FULL_FINE_GRID if full_fine_grid else 0) | (DETERMINISTIC if deterministic else 0))
+               | (FULL_FINE_GRID if full_fine_grid else 0) | (DETERMINISTIC if deterministic else 0)
+               | (FORWARD_ONLY if forward_only else 0))
     return p
 
 
@@ -213,11 +215,11 @@ class Plan:
                  ox: float = 0.0, oy: float = 0.0, band: str = "full", band_c=(0.0, 0.0),
                  band_w=(0.0, 0.0), tol: float = 1e-6, phase_fp64: bool = True, crop: bool = False,
                  defer_range_check: bool = False, full_fine_grid: bool = False,
-                 deterministic: bool = False, device=None):
+                 deterministic: bool = False, forward_only: bool = False, device=None):
         lib = load()
         p = make_params(N, type, lam, z, g, tf=tf, ox=ox, oy=oy, band=band, band_c=band_c, band_w=band_w,
                         tol=tol, phase_fp64=phase_fp64, crop=crop, defer_range_check=defer_range_check,
-                        full_fine_grid=full_fine_grid, deterministic=deterministic)
+                        full_fine_grid=full_fine_grid, deterministic=deterministic, forward_only=forward_only)
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self.params = p
         self.N, self.Np, self.type, self.crop = int(N), 2 * int(N), int(type), bool(crop)

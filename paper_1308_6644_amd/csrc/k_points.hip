@@ -103,8 +103,9 @@ __device__ __forceinline__ void bin_hist_body(const BinArgs& a, int bid, int) {
         lds_bump16(sh, T);
         continue;
       }
-      const int bx0 = pc.i0x >> g.tile_log, bx1 = (pc.i0x + g.w - 1) >> g.tile_log;
-      const int by0 = pc.i0y >> g.tile_log, by1 = (pc.i0y + g.w - 1) >> g.tile_log;
+      // every bin the taps touch, or only the first tap's (interpolation only)
+      const int bx0 = pc.i0x >> g.tile_log, bx1 = g.primary_only ? bx0 : (pc.i0x + g.w - 1) >> g.tile_log;
+      const int by0 = pc.i0y >> g.tile_log, by1 = g.primary_only ? by0 : (pc.i0y + g.w - 1) >> g.tile_log;
       for (int by = by0; by <= by1; ++by)
         for (int bx = bx0; bx <= bx1; ++bx) lds_bump16(sh, by * g.TX + bx);
     }
@@ -421,8 +422,8 @@ __device__ __forceinline__ void bin_scatter_body(const BinArgs& a, int bid, int)
         a.rej_end[-1 - r] = (int)j;
         continue;
       }
-      const int bx0 = pc.i0x >> g.tile_log, bx1 = (pc.i0x + g.w - 1) >> g.tile_log;
-      const int by0 = pc.i0y >> g.tile_log, by1 = (pc.i0y + g.w - 1) >> g.tile_log;
+      const int bx0 = pc.i0x >> g.tile_log, bx1 = g.primary_only ? bx0 : (pc.i0x + g.w - 1) >> g.tile_log;
+      const int by0 = pc.i0y >> g.tile_log, by1 = g.primary_only ? by0 : (pc.i0y + g.w - 1) >> g.tile_log;
       for (int by = by0; by <= by1; ++by)
         for (int bx = bx0; bx <= bx1; ++bx) {
           const int b = by * g.TX + bx;
@@ -495,8 +496,8 @@ __device__ __forceinline__ void bin_scatter_det_body(const BinArgs& a, int bid, 
   PointCells pc = point_cells(t < np ? x[j0 + t] : 0.0, t < np ? y[j0 + t] : 0.0, g);
   const bool rejected = t < np && !pc.ok;  // outside the window: listed for NaN outputs
   if (t >= np) pc.ok = false;
-  const int bx0 = pc.i0x >> g.tile_log, nbx = ((pc.i0x + g.w - 1) >> g.tile_log) - bx0 + 1;
-  const int by0 = pc.i0y >> g.tile_log, nby = ((pc.i0y + g.w - 1) >> g.tile_log) - by0 + 1;
+  const int bx0 = pc.i0x >> g.tile_log, nbx = g.primary_only ? 1 : ((pc.i0x + g.w - 1) >> g.tile_log) - bx0 + 1;
+  const int by0 = pc.i0y >> g.tile_log, nby = g.primary_only ? 1 : ((pc.i0y + g.w - 1) >> g.tile_log) - by0 + 1;
   const int nrec = pc.ok ? nbx * nby : 0;
   // compaction: exclusive block scan of the per-point record counts
   const int incl = wave_incl_scan(nrec, lane);

@@ -58,6 +58,7 @@ struct BinGeom {
   int L;            // support side
   int TX;           // bins per axis
   int tile_log;     // log2 of the bin side in fine cells (5 or 6)
+  int primary_only; // one record per point, in the bin of its first tap (interpolation only)
 };
 
 // Arguments of the row and column passes of the grid pipelines.

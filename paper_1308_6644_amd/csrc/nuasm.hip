@@ -450,8 +450,11 @@ nuasm_status validate(const nuasm_params* p) {
     return fail(NUASM_ERR_INVALID_ARG, "NUASM_OUT_CROP_N applies to type 1 only");
   if (p->tf == NUASM_TF_FRESNEL && p->z == 0.0) return fail(NUASM_ERR_INVALID_ARG, "Fresnel needs z != 0");
   if (!(p->tol >= 1e-12 && p->tol <= 1e-2)) return fail(NUASM_ERR_INVALID_ARG, "tol must be in [1e-12, 1e-2]");
-  if (p->flags & ~(NUASM_OUT_CROP_N | NUASM_DEFER_RANGE_CHECK | NUASM_FULL_FINE_GRID | NUASM_DETERMINISTIC))
+  if (p->flags &
+      ~(NUASM_OUT_CROP_N | NUASM_DEFER_RANGE_CHECK | NUASM_FULL_FINE_GRID | NUASM_DETERMINISTIC | NUASM_FORWARD_ONLY))
     return fail(NUASM_ERR_INVALID_ARG, "unknown flag bits");
+  if ((p->flags & NUASM_FORWARD_ONLY) && p->type != NUASM_TYPE_2)
+    return fail(NUASM_ERR_INVALID_ARG, "NUASM_FORWARD_ONLY applies to type 2 only");
   if (p->reserved != 0) return fail(NUASM_ERR_INVALID_ARG, "reserved must be 0");
   if (p->band == NUASM_BAND_EXPLICIT) {
     for (int i = 0; i < 2; ++i)
@@ -1181,6 +1184,7 @@ nuasm_status nuasm_plan_create(const nuasm_params* p, void* hip_stream, nuasm_pl
   B.L = L;
   B.TX = pl->TX;
   B.tile_log = pl->tile_log;
+  B.primary_only = (p->flags & NUASM_FORWARD_ONLY) ? 1 : 0;
 
   Spectral& S = pl->spec;
   S.tf = p->tf == NUASM_TF_FRESNEL ? 1 : 0;
@@ -1475,6 +1479,8 @@ nuasm_status nuasm_execute_adjoint(nuasm_plan pl, const void* in, void* out) {
     if ((!in && d.M > 0) || (!out && q.M > 0)) return fail(NUASM_ERR_INVALID_ARG, "in/out pointer is NULL");
     return run_type3_pipeline(pl, d, q, (const float2*)in, (float2*)out, true);
   }
+  if (pl->p.flags & NUASM_FORWARD_ONLY)
+    return fail(NUASM_ERR_UNSUPPORTED, "the plan was created NUASM_FORWARD_ONLY: its bins hold no records for spreading");
   const bool t1 = pl->p.type == NUASM_TYPE_1;
   const void* pts = t1 ? out : in;
   const void* plane = t1 ? in : out;

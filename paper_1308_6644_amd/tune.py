@@ -27,7 +27,7 @@ import statistics
 
 import torch
 
-from . import Batch, NuasmError, Plan, make_params
+from . import FORWARD_ONLY, Batch, NuasmError, Plan, make_params
 
 CANDIDATES = {
     "bin_range_points": (0, 2048, 4096, 16384, 65535),
@@ -76,7 +76,8 @@ def plane_key(spec: dict, M: int) -> str:
     w = max(2, min(16, int(math.ceil(-math.log10(p.tol) - 1e-9)) + 1))
     mb = int(round(math.log2(max(M, 1))))
     tf = "fresnel" if p.tf == 1 else "asm"
-    return f"plane:t{p.type}:N{p.N}:w{w}:{tf}:m{mb}"
+    fwd = ":fwd" if p.flags & FORWARD_ONLY else ""  # one record per point
+    return f"plane:t{p.type}:N{p.N}:w{w}:{tf}:m{mb}{fwd}"
 
 
 def _time(fn, reps: int) -> float:

@@ -118,7 +118,8 @@ def test_fullsize_bench_graph_every_run(data, form):
         for tf in ("asm", "fresnel"):
             for t in (1, 2):
                 specs.append(dict(N=N, type=t, lam=LAM, z=z, g=G, tf=tf,
-                                  band="limited" if tf == "asm" else "full", ox=OX, oy=0.0, tol=1e-6))
+                                  band="limited" if tf == "asm" else "full", ox=OX, oy=0.0, tol=1e-6,
+                                  forward_only=t == 2))
                 xs.append(d["x1"] if t == 1 else d["x2"])
                 ys.append(d["y1"] if t == 1 else d["y2"])
                 ins.append(d["c1"] if t == 1 else d["u1"])
