@@ -394,7 +394,10 @@ nuasm_status nuasm_batch_destroy(nuasm_batch batch);  /* NULL-safe */
  * metres) and apply the operator to in[p] -> out[p] (device complex64, shapes
  * as for nuasm_execute).  The first call with a given set of pointers and
  * counts records the graph (and runs it); later calls with the same arguments
- * only launch it.  Never synchronises the host. */
+ * only launch it.  Never synchronises the host then.  In the grouped form a
+ * call with other buffers but the same counts keeps the recorded graph: it
+ * waits for the graph's last run, rewrites the per-stage argument tables and
+ * launches (any other change records the graph again). */
 nuasm_status nuasm_batch_run(nuasm_batch batch, const int64_t* M, const double* const* x,
                              const double* const* y, const void* const* in, void* const* out);
 /* The same work in two steps, for many operator runs on points bound once
@@ -443,6 +446,10 @@ nuasm_status nuasm_batch_set_plane_times(nuasm_batch batch, int32_t enabled);
  * NUASM_ERR_NOT_READY when stamps are off or no recorded graph has run since
  * the graphs were last dropped. */
 nuasm_status nuasm_batch_plane_times(nuasm_batch batch, float* ms);
+/* How often a batch has recorded a graph, and how often it has only
+ * rewritten a grouped graph's argument tables for new buffers (see
+ * nuasm_batch_run), since it was created.  For testing. */
+nuasm_status nuasm_debug_batch_graphs(nuasm_batch batch, int64_t* recorded, int64_t* refreshed);
 
 const char* nuasm_status_string(nuasm_status s);
 const char* nuasm_last_error(void);

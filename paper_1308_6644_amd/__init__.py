@@ -125,6 +125,8 @@ _SIGS = {
     "nuasm_batch_check_points": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     "nuasm_batch_plane_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float)]),
     "nuasm_batch_set_plane_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "nuasm_debug_batch_graphs": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                                ctypes.POINTER(ctypes.c_int64)]),
     "nuasm_rs_direct": (ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                        ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
@@ -500,6 +502,12 @@ class Batch:
         bad = ctypes.c_int32(-1)
         _check(load().nuasm_batch_check_points(self._h, ctypes.byref(bad)))
         return bad.value
+
+    def debug_graphs(self):
+        """(graphs recorded, grouped tables rewritten in place) so far."""
+        r, f = ctypes.c_int64(), ctypes.c_int64()
+        _check(load().nuasm_debug_batch_graphs(self._h, ctypes.byref(r), ctypes.byref(f)))
+        return r.value, f.value
 
     def set_plane_times(self, enabled: bool):
         """Record completion stamps for plane_times (default) or none."""

@@ -113,3 +113,81 @@ def test_grouped_and_per_plane_forms_match_plain_plans():
         t2 = b.plane_times()
         assert all(v > 0 for v in t2)
         b.close()
+
+
+def test_grouped_graph_takes_new_buffers_without_recording():
+    """A grouped graph run with other buffers but the same point counts keeps
+    its recording and only rewrites its argument tables (one-shot run and
+    execute_many); the results are those of plain plans on the new data.
+    A changed count, and any change in the per-plane form, record again."""
+    import paper_1308_6644_amd as P
+    P.load()
+    specs, data_a = _planes(29, 6)
+    rng = np.random.default_rng(30)
+    data_b = []
+    for s, (x, y, inp) in zip(specs, data_a):
+        M = x.size
+        xb, yb = synth.clustered_box(rng, M, s["N"] * s["g"])
+        data_b.append((xb, yb, synth.unit_phase(rng, M if s["type"] == 1 else (s["N"], s["N"]))))
+    print(f"new buffers: {len(specs)} planes", flush=True)
+
+    def upload(data):
+        return ([dev(torch, d[0]) for d in data], [dev(torch, d[1]) for d in data],
+                [dev(torch, d[2]) for d in data])
+
+    def plain(data):
+        refs = []
+        for s, (x, y, inp) in zip(specs, data):
+            plan = P.Plan(**s)
+            plan.set_points(dev(torch, x), dev(torch, y))
+            refs.append(host(plan.execute(dev(torch, inp))))
+        return refs
+
+    def outs():
+        return [torch.full((2 * s["N"], 2 * s["N"]) if s["type"] == 1 else (d[0].size,), float("nan"),
+                           dtype=torch.complex64, device="cuda") for s, d in zip(specs, data_a)]
+
+    A, B = upload(data_a), upload(data_b)
+    ref_a, ref_b = plain(data_a), plain(data_b)
+    b = P.Batch(specs)
+    oa, ob = outs(), outs()
+    b.run(*A, oa)
+    assert b.debug_graphs() == (1, 0)
+    b.run(*B, ob)
+    assert b.debug_graphs() == (1, 1)
+    oa2 = outs()
+    b.run(*A, oa2)
+    assert b.debug_graphs() == (1, 2)
+    for p in range(len(specs)):
+        check_close(host(oa[p]), ref_a[p], 1e-6, what=f"A plane {p}")
+        check_close(host(ob[p]), ref_b[p], 1e-6, what=f"B plane {p}")
+        check_close(host(oa2[p]), ref_a[p], 1e-6, what=f"A again plane {p}")
+    # points bound once, operators on other buffers: the execute graph too
+    b.set_points(A[0], A[1])
+    r0, f0 = b.debug_graphs()
+    e1, e2 = outs(), outs()
+    b.execute(A[2], e1)
+    b.execute(A[2], e2)
+    assert b.debug_graphs() == (r0 + 1, f0 + 1)
+    for p in range(len(specs)):
+        check_close(host(e1[p]), ref_a[p], 1e-6, what=f"execute plane {p}")
+        check_close(host(e2[p]), ref_a[p], 1e-6, what=f"execute, new outputs, plane {p}")
+    # a changed point count records again
+    xs, ys, ins = A
+    xs2, ys2 = list(xs), list(ys)
+    p1 = next(p for p, s in enumerate(specs) if s["type"] == 1)
+    xs2[p1], ys2[p1] = xs[p1][:100].clone(), ys[p1][:100].clone()
+    ins2 = list(ins)
+    ins2[p1] = ins[p1][:100].clone()
+    r0, f0 = b.debug_graphs()
+    b.run(xs2, ys2, ins2, outs())
+    assert b.debug_graphs() == (r0 + 1, f0)
+    # the per-plane form records on every change
+    b.set_grouped(False)
+    r0, f0 = b.debug_graphs()
+    b.run(*A, outs())
+    b.run(*B, ob)
+    assert b.debug_graphs() == (r0 + 2, f0)
+    for p in range(len(specs)):
+        check_close(host(ob[p]), ref_b[p], 1e-6, what=f"per-plane B plane {p}")
+    b.close()
