@@ -1721,8 +1721,7 @@ struct BatchGraph {
 struct nuasm_batch_s {
   std::vector<nuasm_plan_s*> plans;
   hipStream_t stream = nullptr;  // caller's stream
-  hipStream_t cap = nullptr;     // internal stream the graphs are recorded and launched on
-  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipStream_t cap = nullptr;     // internal stream the graphs are recorded on (they run on `stream`)
   std::vector<hipStream_t> branch;
   int active = 0;              // branches in use (nuasm_batch_set_branches)
   std::vector<int> branch_of;  // plane -> branch
@@ -1766,8 +1765,6 @@ void batch_release(nuasm_batch_s* b) {
   }
   for (hipStream_t s : b->branch) (void)hipStreamDestroy(s);
   if (b->cap) (void)hipStreamDestroy(b->cap);
-  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
-  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
   if (b->fork) (void)hipEventDestroy(b->fork);
   for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
   if (b->ts) (void)dev_free(b->ts);
@@ -1960,19 +1957,16 @@ static hipError_t enqueue_chains(nuasm_batch_s* b, BatchGraph& g, const int* ord
 // buffer and sets kernel attributes, so that the capture enqueues launches
 // only), then the capture on the internal stream -- stamp, fork onto the
 // branches, every plane on its branch followed by its completion stamp, join.
-// The graph runs on the internal stream, ordered after the caller's stream and
-// before the caller's later work.
+// The graph is launched on the caller's stream itself.
 template <typename F>
 static nuasm_status batch_launch(nuasm_batch_s* b, BatchGraph& g, const std::vector<const void*>& key,
                                  const std::vector<int64_t>& M, F plane) {
   const int P = (int)b->plans.size();
   auto launch = [&]() -> nuasm_status {
+    // on the caller's stream itself: ordered with its other work, no event
+    // hops between streams
     b->last = &g;
-    HIP_TRY(hipEventRecord(b->ev_in, b->stream), "hipEventRecord");
-    HIP_TRY(hipStreamWaitEvent(b->cap, b->ev_in, 0), "hipStreamWaitEvent");
-    HIP_TRY(hipGraphLaunch(g.exec, b->cap), "hipGraphLaunch");
-    HIP_TRY(hipEventRecord(b->ev_out, b->cap), "hipEventRecord");
-    HIP_TRY(hipStreamWaitEvent(b->stream, b->ev_out, 0), "hipStreamWaitEvent");
+    HIP_TRY(hipGraphLaunch(g.exec, b->stream), "hipGraphLaunch");
     return NUASM_OK;
   };
   if (g.exec && key == g.key && g.grouped == b->grouped) return launch();
@@ -1987,7 +1981,7 @@ static nuasm_status batch_launch(nuasm_batch_s* b, BatchGraph& g, const std::vec
     for (nuasm_plan_s* pl : b->plans) pl->stream = b->stream;
     if (s != NUASM_OK) return s;
     if (same_layout(stages, g.stages) && host.size() == g.table_bytes) {
-      HIP_TRY(hipStreamSynchronize(b->cap), "hipStreamSynchronize");
+      HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
       HIP_TRY(hipMemcpy(g.tables, host.data(), host.size(), hipMemcpyHostToDevice), "hipMemcpy(grouped tables)");
       g.key = key;
       ++b->refreshed;
@@ -1995,7 +1989,7 @@ static nuasm_status batch_launch(nuasm_batch_s* b, BatchGraph& g, const std::vec
     }
   }
   if (g.exec || g.tables) {
-    HIP_TRY(hipStreamSynchronize(b->cap), "hipStreamSynchronize");
+    HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
     drop_graph(g);
   }
   // eager pass on the caller's stream: sizes every buffer and sets kernel
@@ -2127,10 +2121,6 @@ nuasm_status nuasm_batch_create(int32_t P, const nuasm_params* params, void* hip
   }
   if ((e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming)) != hipSuccess)
     return bail(hip_fail(e, "hipEventCreate"));
-  if ((e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming)) != hipSuccess)
-    return bail(hip_fail(e, "hipEventCreate"));
-  if ((e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming)) != hipSuccess)
-    return bail(hip_fail(e, "hipEventCreate"));
   if ((e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking)) != hipSuccess)
     return bail(hip_fail(e, "hipStreamCreate"));
   if ((e = dev_malloc((void**)&b->ts, sizeof(long long) * (P + 1))) != hipSuccess)
@@ -2218,7 +2208,7 @@ nuasm_status nuasm_execute_many(nuasm_batch b, const void* const* in, void* cons
 namespace {
 // Drop the recorded graphs so that the next runs record them again.
 nuasm_status batch_invalidate(nuasm_batch_s* b) {
-  HIP_TRY(hipStreamSynchronize(b->cap), "hipStreamSynchronize");
+  HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
   drop_graph(b->g_run);
   drop_graph(b->g_bin);
   drop_graph(b->g_exec);
@@ -2255,7 +2245,6 @@ nuasm_status nuasm_batch_set_grouped(nuasm_batch b, int32_t grouped) {
 
 nuasm_status nuasm_batch_check_points(nuasm_batch b, int32_t* bad_plane) {
   if (!b || !bad_plane) return fail(NUASM_ERR_INVALID_ARG, "NULL argument");
-  HIP_TRY(hipStreamSynchronize(b->cap), "hipStreamSynchronize");
   HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
   *bad_plane = -1;
   for (size_t p = 0; p < b->plans.size(); ++p) {
@@ -2293,7 +2282,7 @@ nuasm_status nuasm_batch_plane_times(nuasm_batch b, float* ms) {
   if (!b || !ms) return fail(NUASM_ERR_INVALID_ARG, "NULL argument");
   if (!b->stamps) return fail(NUASM_ERR_NOT_READY, "plane times are off (nuasm_batch_set_plane_times)");
   if (!b->last || !b->last->exec) return fail(NUASM_ERR_NOT_READY, "no recorded graph has run");
-  HIP_TRY(hipStreamSynchronize(b->cap), "hipStreamSynchronize");
+  HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
   const size_t P = b->plans.size();
   std::vector<long long> h(P + 1);
   HIP_TRY(hipMemcpy(h.data(), b->ts, sizeof(long long) * (P + 1), hipMemcpyDeviceToHost), "hipMemcpy");
