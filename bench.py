@@ -117,7 +117,22 @@ def _counter_rows(db: str):
     return {st: {c: v / n[st] for c, v in d.items()} | {"launches": n[st]} for st, d in out.items()}
 
 
-def write_counters(fetch_db: str, write_db: str, copy_fetch_db: str, copy_write_db: str, command: str) -> dict:
+# The rocprofv3 passes whose databases write_counters reads (run from the
+# repository root with TMPDIR=/tmp), in its argument order.
+PMC_COMMANDS = [
+    "rocprofv3 --pmc FETCH_SIZE SQ_INSTS_VALU SQ_INSTS_MFMA SQ_INSTS_LDS SQ_WAVES -d gpurun_out/prof/pmcA -o p -- "
+    "python3 bench.py --steps 1 --warmup 0 --profile-steps 0 --no-cpu-baseline --no-tune",
+    "rocprofv3 --pmc WRITE_SIZE SQ_LDS_BANK_CONFLICT SQ_ACTIVE_INST_LDS SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR "
+    "SQ_BUSY_CYCLES SQ_WAVE_CYCLES -d gpurun_out/prof/pmcB -o p -- "
+    "python3 bench.py --steps 1 --warmup 0 --profile-steps 0 --no-cpu-baseline --no-tune",
+    "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof/pmcE -o p -- python3 bench.py --copy-calibration 268435456",
+    "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof/pmcF -o p -- python3 bench.py --copy-calibration 268435456",
+    "python3 bench.py --write-counters gpurun_out/prof/pmcA/p_results.db gpurun_out/prof/pmcB/p_results.db "
+    "gpurun_out/prof/pmcE/p_results.db gpurun_out/prof/pmcF/p_results.db",
+]
+
+
+def write_counters(fetch_db: str, write_db: str, copy_fetch_db: str, copy_write_db: str, command=None) -> dict:
     """profiles/counters.json from four rocprofv3 --pmc databases: FETCH_SIZE
     (with the SQ counters) and WRITE_SIZE passes of the benchmark, and the same
     two counters over plain device copies of a known size, which scale them to
@@ -128,7 +143,7 @@ def write_counters(fetch_db: str, write_db: str, copy_fetch_db: str, copy_write_
     copy_bytes = 268435456
     fs = copy_bytes / (ca["copy"]["FETCH_SIZE"] * 1024)
     ws = copy_bytes / (cb["copy"]["WRITE_SIZE"] * 1024)
-    out = {"command": command,
+    out = {"command": command or PMC_COMMANDS,
            "calibration": {"copy_bytes": copy_bytes, "fetch_scale": fs, "write_scale": ws,
                            "copy_fetch_kib": ca["copy"]["FETCH_SIZE"], "copy_write_kib": cb["copy"]["WRITE_SIZE"]},
            "kernels": {}}
@@ -841,7 +856,7 @@ def main(argv=None):
                          "and exit")
     a = ap.parse_args(argv)
     if a.write_counters:
-        out = write_counters(*a.write_counters, command=os.environ.get("NUASM_COUNTERS_COMMAND", ""))
+        out = write_counters(*a.write_counters, command=os.environ.get("NUASM_COUNTERS_COMMAND") or None)
         print(json.dumps({"kernels": sorted(out["kernels"]), "calibration": out["calibration"]}))
         return 0
     if a.gpus != 1:
